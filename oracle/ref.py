@@ -1,0 +1,118 @@
+"""ctypes front end of the CPU oracle (libmpref.so).  TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg import this
+module.  Arrays follow the multi-component layout of the paper (Sec. 3): a
+K-component array of length L is a C-contiguous (K, L) float64 array.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.build(force=False)
+        L = ctypes.CDLL(path)
+        P = ctypes.c_void_p
+        i64 = ctypes.c_int64
+        L.oracle_eft.argtypes = [ctypes.c_int, i64, P, P, P, P]
+        L.oracle_elementwise.argtypes = [ctypes.c_int, ctypes.c_int, i64, P, P, P]
+        L.oracle_renorm5.argtypes = [i64, P, P]
+        L.oracle_spmv.argtypes = [ctypes.c_int, i64, i64, i64, P, P, P, P, P, P, P, P, P, i64, P, ctypes.c_int]
+        L.oracle_canonical_log2w.argtypes = [i64]
+        L.oracle_num_threads.argtypes = []
+        for name in ("oracle_eft", "oracle_elementwise", "oracle_renorm5", "oracle_spmv",
+                     "oracle_canonical_log2w", "oracle_num_threads"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def eft(which, a, b):
+    """which: 'two_sum' | 'quick_two_sum' | 'two_prod' -> (s, e) arrays."""
+    code = {"two_sum": 0, "quick_two_sum": 1, "two_prod": 2}[which]
+    a, b = _f64(a), _f64(b)
+    s = np.empty_like(a)
+    e = np.empty_like(a)
+    assert lib().oracle_eft(code, a.size, _p(a), _p(b), _p(s), _p(e)) == 0
+    return s, e
+
+
+def elementwise(K, op, x, y):
+    """op: 'add' | 'mul' | 'mul_d' (DD times binary64).  x (K, n); y (K, n) or (n,)."""
+    code = {"add": 0, "mul": 1, "mul_d": 2}[op]
+    x, y = _f64(x), _f64(y)
+    n = x.shape[1]
+    r = np.zeros((K, n))
+    assert lib().oracle_elementwise(K, code, n, _p(x), _p(y), _p(r)) == 0
+    return r
+
+
+def renorm5(c):
+    c = _f64(c)
+    n = c.shape[1]
+    r = np.zeros((4, n))
+    lib().oracle_renorm5(n, _p(c), _p(r))
+    return r
+
+
+def canonical_log2w(lengths):
+    lengths = np.asarray(lengths, dtype=np.int64)
+    out = np.zeros(lengths.size, dtype=np.uint8)
+    L = np.maximum(lengths, 1)
+    # largest l <= 6 with 2^l <= len
+    lw = np.floor(np.log2(L)).astype(np.int64)
+    lw = np.where((1 << (lw + 1)) <= L, lw + 1, lw)
+    lw = np.where((1 << lw) > L, lw - 1, lw)
+    out[:] = np.minimum(6, lw)
+    return out
+
+
+def spmv(K, row_ptr, col_idx, a_re, x_re, a_im=None, x_im=None, log2w=None, rows=None,
+         n_cols=None, nthreads=0):
+    """y = A x in K-component arithmetic (Sec. 3).  Returns y_re or (y_re, y_im).
+
+    log2w: per-row lane-width exponents (None = canonical order).  rows: subset of rows
+    to compute (others are returned as NaN).  nthreads: OpenMP threads (0 = default).
+    """
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
+    n = row_ptr.size - 1
+    nnz = col_idx.size
+    if n_cols is None:
+        n_cols = x_re.shape[1]
+    a_re, a_im, x_re, x_im = _f64(a_re), _f64(a_im), _f64(x_re), _f64(x_im)
+    assert a_re.shape == (K, nnz) and x_re.shape == (K, n_cols)
+    cplx = a_im is not None
+    y_re = np.full((K, n), np.nan)
+    y_im = np.full((K, n), np.nan) if cplx else None
+    lw = None if log2w is None else np.ascontiguousarray(log2w, dtype=np.uint8)
+    sel = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    rc = lib().oracle_spmv(K, n, n_cols, nnz, _p(row_ptr), _p(col_idx), _p(lw),
+                           _p(a_re), _p(a_im), _p(x_re), _p(x_im), _p(y_re), _p(y_im),
+                           0 if sel is None else sel.size, _p(sel), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle_spmv: invalid argument (lane width larger than the row?)")
+    return (y_re, y_im) if cplx else y_re
+
+
+def num_threads():
+    return lib().oracle_num_threads()
+
+
+def loaded_path():
+    return os.path.abspath(_build.LIB)
