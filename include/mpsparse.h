@@ -1,0 +1,160 @@
+/*
+ * mpsparse.h -- C ABI of the MI355X (gfx950) multi-component-precision sparse library.
+ *
+ * What it computes: CSR sparse matrix-vector products y = A x in double-double (DD,
+ * K = 2 binary64 components), triple-double (TD, K = 3) and quad-double (QD, K = 4)
+ * arithmetic, real and complex (Kouya, arXiv 2412.17510, Sec. 2 and Sec. 3), and the
+ * DD Krylov solvers that call them (Sec. 4.2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory.  Every array argument is a DEVICE pointer (memory of the current HIP
+ *   device), unless the comment says "host".  The caller owns all of them; the library
+ *   never frees caller memory.  Plans (mp_plan) are library-owned: create and destroy
+ *   them with the calls below.
+ * Multi-component layout (Sec. 3: one binary64 array per component).  An array of
+ *   length L with K components is ONE block of K*L doubles; component c (0 = leading)
+ *   of element i is at base[c*L + i].  Components are non-overlapping with the leading
+ *   one first (each at most half an ulp of the one above).
+ * Complex data (Sec. 3, Eq. 2): separate real and imaginary multi-component blocks
+ *   over one shared sparsity pattern.
+ * CSR (Sec. 3): row_ptr int32[n_rows+1], col_idx int32[nnz], 0-based, row_ptr[0] = 0,
+ *   non-decreasing, columns in [0, n_cols).  Values follow the col_idx order.
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *   SpMV calls only enqueue work and return.  Calls documented as synchronising wait
+ *   for their stream before returning.
+ * Errors.  Every call returns an mp_status; nothing aborts and no C++ exception
+ *   crosses the ABI.  Host-side O(1) checks run on every call (null pointers, sizes,
+ *   K, aliasing of outputs with inputs); a failed HIP call returns MP_ERR_HIP.  The
+ *   message of the last failure of the calling thread is in mp_last_error().
+ *   O(nnz) structural checks of a CSR matrix are done only by mp_csr_validate.
+ *
+ * Summation order (the reading of Sec. 3, Fig. 1 this library fixes).  For row i with
+ *   len elements and lane width W = 2^log2w[i] (W <= len, W <= 1024): lane l < W
+ *   accumulates the products of elements l, l+W, l+2W, ... in that order, starting
+ *   from its first product; the W lane sums are folded as acc[l] = add(acc[l],
+ *   acc[l+off]) for off = W/2, ..., 1; y_i = acc[0].  Products are mul(a, x) with the
+ *   matrix operand first.  An empty row gives +0.  The canonical order uses the
+ *   largest power of two W <= min(len, 64).  Two calls with the same lane widths give
+ *   bitwise identical results, whatever kernel mapping a plan uses.
+ */
+#ifndef MPSPARSE_H
+#define MPSPARSE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MP_OK = 0,
+    MP_ERR_INVALID_ARG = -1,   /* null pointer, bad size, bad K, malformed CSR (validate) */
+    MP_ERR_ALIAS = -2,         /* an output overlaps an input */
+    MP_ERR_HIP = -3,           /* a HIP runtime call or kernel launch failed */
+    MP_ERR_NO_MEMORY = -4,     /* library allocation failed / workspace too small */
+    MP_ERR_NOT_CONVERGED = -5, /* solver hit max_iter; best iterate written back */
+    MP_ERR_BREAKDOWN = -6,     /* solver breakdown (zero or non-finite scalar) */
+    MP_ERR_UNSUPPORTED = -7    /* option combination not provided */
+} mp_status;
+
+/* A CSR sparsity pattern (device pointers; see the conventions above). */
+typedef struct {
+    int32_t n_rows;
+    int32_t n_cols;
+    int64_t nnz;
+    const int32_t *row_ptr;
+    const int32_t *col_idx;
+} mp_csr;
+
+/* Opaque execution plan: per-row lane widths (the summation order), rows binned by
+ * lane width, and the tile list one fused kernel launch walks.  Immutable after
+ * creation; usable from several streams at once; owned by the library. */
+typedef struct mp_plan mp_plan;
+
+/* Width policy of a plan: log2w(len) = clamp(floor(log2(len)) - shift, 0, max_log2w)
+ * (len >= 1; empty rows get 0).  shift = 0, max_log2w = 6 is the canonical order. */
+typedef struct {
+    int32_t shift;      /* 0..12: aim at >= 2^shift elements per lane */
+    int32_t max_log2w;  /* 0..10: widest lane group (1024 lanes) */
+} mp_width_policy;
+
+/* Last error message of the calling thread ("" if none).  Static storage. */
+const char *mp_last_error(void);
+
+/* Library version string. */
+const char *mp_version(void);
+
+/* O(nnz) structural check of a CSR pattern on the device (row_ptr[0] == 0,
+ * non-decreasing, row_ptr[n_rows] == nnz, col_idx in range).  Synchronises `stream`.
+ * Returns MP_OK or MP_ERR_INVALID_ARG (with the first problem in mp_last_error()). */
+mp_status mp_csr_validate(const mp_csr *A, void *stream);
+
+/* Build a plan for pattern A with the given width policy (NULL = canonical).
+ * Reads row_ptr back to the host once, bins rows by lane width and uploads the row
+ * permutation and tile list.  Synchronises `stream`.  *out receives the plan. */
+mp_status mp_plan_create(const mp_csr *A, const mp_width_policy *policy, void *stream, mp_plan **out);
+
+/* Build a plan whose lane widths are given explicitly: host array log2w[n_rows],
+ * each entry <= 10 and with 2^log2w[i] <= len_i for non-empty rows (0 for empty rows).
+ * Synchronises `stream`. */
+mp_status mp_plan_create_explicit(const mp_csr *A, const uint8_t *log2w_host, void *stream, mp_plan **out);
+
+/* Autotuned plan (Sec. 4.1 observes that SpMV speed depends on the matrix size and
+ * structure): times every width policy of a fixed candidate list with the K-component
+ * kernel (complex if is_complex) on the caller's operands, which are only read
+ * (y is overwritten), and keeps the fastest.  The winning policy is returned in
+ * *chosen (may be NULL).  Synchronises `stream`. */
+mp_status mp_plan_autotune(const mp_csr *A, int32_t ncomp, int32_t is_complex,
+                           const double *a_re, const double *a_im, const double *x_re, const double *x_im,
+                           double *y_re, double *y_im, int32_t reps, void *stream,
+                           mp_plan **out, mp_width_policy *chosen);
+
+mp_status mp_plan_destroy(mp_plan *plan);
+
+/* Copy the plan's per-row lane-width exponents to host array log2w_host[n_rows]
+ * (the summation order of every row, for reproducing a result elsewhere). */
+mp_status mp_plan_row_log2w(const mp_plan *plan, uint8_t *log2w_host);
+
+/* Number of rows and of workgroup tiles of a plan (host ints; either may be NULL). */
+mp_status mp_plan_info(const mp_plan *plan, int32_t *n_rows, int32_t *n_tiles);
+
+/*
+ * Real SpMV y = A x (Sec. 3, Fig. 1) in DD (Algs 1-2), TD and QD (Sec. 2).
+ *   a: K*nnz values, x: K*n_cols, y: K*n_rows (multi-component layout above).
+ *   plan: NULL = canonical order with a one-row-per-wavefront kernel that needs no
+ *   plan; otherwise the plan's order and binned kernel (the plan must have been made
+ *   for a pattern with the same n_rows).
+ *   y must not overlap a or x (MP_ERR_ALIAS).  Enqueues on `stream` and returns.
+ */
+mp_status mpspmv_csr_dd(const mp_csr *A, const double *a, const double *x, double *y,
+                        const mp_plan *plan, void *stream);
+mp_status mpspmv_csr_td(const mp_csr *A, const double *a, const double *x, double *y,
+                        const mp_plan *plan, void *stream);
+mp_status mpspmv_csr_qd(const mp_csr *A, const double *a, const double *x, double *y,
+                        const mp_plan *plan, void *stream);
+
+/*
+ * Complex SpMV (Sec. 3, Eq. 3): with A = A_re + i A_im and x = x_re + i x_im,
+ *   y_re = A_re x_re - A_im x_im and y_im = A_re x_im + A_im x_re, formed as four
+ *   accumulator sets in one pass over the pattern (each in the order above) and
+ *   combined at the end of the row: y_re = add(rr, -ii), y_im = add(ri, ir).
+ *   Same layouts and rules as the real calls; y_re / y_im must not overlap any input
+ *   or each other.
+ */
+mp_status mpspmv_csr_dd_complex(const mp_csr *A, const double *a_re, const double *a_im,
+                                const double *x_re, const double *x_im, double *y_re, double *y_im,
+                                const mp_plan *plan, void *stream);
+mp_status mpspmv_csr_td_complex(const mp_csr *A, const double *a_re, const double *a_im,
+                                const double *x_re, const double *x_im, double *y_re, double *y_im,
+                                const mp_plan *plan, void *stream);
+mp_status mpspmv_csr_qd_complex(const mp_csr *A, const double *a_re, const double *a_im,
+                                const double *x_re, const double *x_im, double *y_re, double *y_im,
+                                const mp_plan *plan, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPSPARSE_H */

@@ -156,11 +156,13 @@ static void three_sum2(double a, double b, double c, double *s, double *e1)
 /* Renormalisation of five roughly ordered terms into four non-overlapping
  * components.  First sweep, bottom-up: a chain of QuickTwoSums from the
  * smallest term to the largest leaves t0 (the rounded total) and the errors
- * t1..t4.  Second sweep, top-down: carry s = t0 and for i = 1..4 form
- * (s, e) = QuickTwoSum(s, t_i); a non-zero e closes the current component (it
- * is emitted and e becomes the new carry), a zero e lets the carry absorb t_i.
- * Once three components are closed the fourth only absorbs (its errors are
- * dropped).  Tests against zero are exact comparisons with 0.0. */
+ * t1..t4.  Second sweep, top-down: (t0, t1) is already a QuickTwoSum pair, so a
+ * non-zero t1 closes t0 as the first component and t1 becomes the carry s (else
+ * s = t0); then for i = 2..4 form (s, e) = QuickTwoSum(s, t_i): a non-zero e
+ * closes the current component (s is emitted and e becomes the new carry), a zero
+ * e lets the carry absorb t_i.  Once three components are closed the fourth only
+ * absorbs (its errors are dropped); the final carry is the last component.  Tests
+ * against zero are exact comparisons with 0.0. */
 static mpv renorm5(double c0, double c1, double c2, double c3, double c4)
 {
     double s, t[5], e;
@@ -171,7 +173,12 @@ static mpv renorm5(double c0, double c1, double c2, double c3, double c4)
     quick_two_sum(c1, s, &s, &t[2]);
     quick_two_sum(c0, s, &t[0], &t[1]);
     s = t[0];
-    for (i = 1; i <= 4; ++i) {
+    if (t[1] != 0.0) {
+        r.c[0] = t[0];
+        k = 1;
+        s = t[1];
+    }
+    for (i = 2; i <= 4; ++i) {
         double sn;
         quick_two_sum(s, t[i], &sn, &e);
         s = sn;

@@ -1,0 +1,237 @@
+"""Thin ctypes binding of libmpsparse.so (the C ABI declared in include/mpsparse.h).
+
+Argument marshalling only: tensors are torch CUDA tensors (device memory), streams
+are torch CUDA streams, and every computation runs in the library's HIP kernels.
+Multi-component arrays are C-contiguous float64 tensors of shape (K, L) (component
+0 leading), exactly the K*L block layout of the C ABI.
+
+Importing this module fails loudly if the library has not been built; there is no
+fallback implementation.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmpsparse.so")
+
+MP_OK = 0
+STATUS_NAMES = {0: "MP_OK", -1: "MP_ERR_INVALID_ARG", -2: "MP_ERR_ALIAS", -3: "MP_ERR_HIP",
+                -4: "MP_ERR_NO_MEMORY", -5: "MP_ERR_NOT_CONVERGED", -6: "MP_ERR_BREAKDOWN",
+                -7: "MP_ERR_UNSUPPORTED"}
+
+
+class MpError(RuntimeError):
+    def __init__(self, status, func, message):
+        self.status = status
+        super().__init__("%s returned %s: %s" % (func, STATUS_NAMES.get(status, status), message))
+
+
+class mp_csr(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int32), ("n_cols", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p)]
+
+
+class mp_width_policy(ctypes.Structure):
+    _fields_ = [("shift", ctypes.c_int32), ("max_log2w", ctypes.c_int32)]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libmpsparse.so is not built (expected at %s); run __graft_entry__.build()" % LIB_PATH)
+
+_lib = ctypes.CDLL(LIB_PATH)
+_P = ctypes.c_void_p
+_I = ctypes.c_int32
+_CSR = ctypes.POINTER(mp_csr)
+
+_SIGS = {
+    "mp_last_error": ([], ctypes.c_char_p),
+    "mp_version": ([], ctypes.c_char_p),
+    "mp_csr_validate": ([_CSR, _P], ctypes.c_int),
+    "mp_plan_create": ([_CSR, ctypes.POINTER(mp_width_policy), _P, ctypes.POINTER(_P)], ctypes.c_int),
+    "mp_plan_create_explicit": ([_CSR, _P, _P, ctypes.POINTER(_P)], ctypes.c_int),
+    "mp_plan_autotune": ([_CSR, _I, _I, _P, _P, _P, _P, _P, _P, _I, _P, ctypes.POINTER(_P),
+                          ctypes.POINTER(mp_width_policy)], ctypes.c_int),
+    "mp_plan_destroy": ([_P], ctypes.c_int),
+    "mp_plan_row_log2w": ([_P, _P], ctypes.c_int),
+    "mp_plan_info": ([_P, ctypes.POINTER(_I), ctypes.POINTER(_I)], ctypes.c_int),
+}
+for _name in ("mpspmv_csr_dd", "mpspmv_csr_td", "mpspmv_csr_qd"):
+    _SIGS[_name] = ([_CSR, _P, _P, _P, _P, _P], ctypes.c_int)
+for _name in ("mpspmv_csr_dd_complex", "mpspmv_csr_td_complex", "mpspmv_csr_qd_complex"):
+    _SIGS[_name] = ([_CSR, _P, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int)
+
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+
+def _check(status, func):
+    if status != MP_OK:
+        raise MpError(status, func, _lib.mp_last_error().decode())
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check_mp(t, K, L, name):
+    import torch
+    if t is None:
+        raise ValueError("%s is required" % name)
+    if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape) != (K, L):
+        raise ValueError("%s must be a contiguous CUDA float64 tensor of shape (%d, %d); got %s %s %s"
+                         % (name, K, L, tuple(t.shape), t.dtype, t.device))
+
+
+def version():
+    return _lib.mp_version().decode()
+
+
+def library_path():
+    return LIB_PATH
+
+
+class Csr:
+    """A CSR pattern in device memory (int32 row_ptr / col_idx tensors, 0-based)."""
+
+    def __init__(self, row_ptr, col_idx, n_cols=None):
+        import torch
+        for t, nm in ((row_ptr, "row_ptr"), (col_idx, "col_idx")):
+            if not t.is_cuda or t.dtype != torch.int32 or not t.is_contiguous() or t.dim() != 1:
+                raise ValueError("%s must be a contiguous 1-D CUDA int32 tensor" % nm)
+        self.row_ptr = row_ptr
+        self.col_idx = col_idx
+        self.n_rows = row_ptr.numel() - 1
+        self.n_cols = self.n_rows if n_cols is None else int(n_cols)
+        self.nnz = col_idx.numel()
+        self.c = mp_csr(self.n_rows, self.n_cols, self.nnz, row_ptr.data_ptr(),
+                        col_idx.data_ptr() if self.nnz else None)
+
+    @classmethod
+    def from_numpy(cls, row_ptr, col_idx, n_cols=None, device="cuda"):
+        import torch
+        rp = torch.from_numpy(np.ascontiguousarray(row_ptr, dtype=np.int32)).to(device)
+        ci = torch.from_numpy(np.ascontiguousarray(col_idx, dtype=np.int32)).to(device)
+        return cls(rp, ci, n_cols)
+
+
+class Plan:
+    """Owns an mp_plan* (destroyed with the object)."""
+
+    def __init__(self, handle, n_rows):
+        self._h = handle
+        self.n_rows = n_rows
+
+    @property
+    def handle(self):
+        return self._h
+
+    def destroy(self):
+        if self._h:
+            _lib.mp_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def row_log2w(self):
+        out = np.zeros(self.n_rows, dtype=np.uint8)
+        _check(_lib.mp_plan_row_log2w(self._h, out.ctypes.data_as(ctypes.c_void_p)), "mp_plan_row_log2w")
+        return out
+
+    def info(self):
+        n = ctypes.c_int32()
+        t = ctypes.c_int32()
+        _check(_lib.mp_plan_info(self._h, ctypes.byref(n), ctypes.byref(t)), "mp_plan_info")
+        return {"n_rows": n.value, "n_tiles": t.value}
+
+
+def _plan_handle(plan):
+    return None if plan is None else plan.handle
+
+
+def mp_csr_validate(A, stream=None):
+    _check(_lib.mp_csr_validate(ctypes.byref(A.c), _stream_ptr(stream)), "mp_csr_validate")
+
+
+def mp_plan_create(A, shift=0, max_log2w=6, stream=None):
+    h = ctypes.c_void_p()
+    pol = mp_width_policy(shift, max_log2w)
+    _check(_lib.mp_plan_create(ctypes.byref(A.c), ctypes.byref(pol), _stream_ptr(stream), ctypes.byref(h)),
+           "mp_plan_create")
+    return Plan(h.value, A.n_rows)
+
+
+def mp_plan_create_explicit(A, log2w, stream=None):
+    lw = np.ascontiguousarray(log2w, dtype=np.uint8)
+    if lw.size != A.n_rows:
+        raise ValueError("log2w must have n_rows entries")
+    h = ctypes.c_void_p()
+    _check(_lib.mp_plan_create_explicit(ctypes.byref(A.c), lw.ctypes.data_as(ctypes.c_void_p),
+                                        _stream_ptr(stream), ctypes.byref(h)), "mp_plan_create_explicit")
+    return Plan(h.value, A.n_rows)
+
+
+def mp_plan_autotune(A, ncomp, a_re, x_re, y_re, a_im=None, x_im=None, y_im=None, reps=3, stream=None):
+    cplx = a_im is not None
+    h = ctypes.c_void_p()
+    pol = mp_width_policy()
+    _check(_lib.mp_plan_autotune(ctypes.byref(A.c), ncomp, int(cplx), _ptr(a_re), _ptr(a_im), _ptr(x_re),
+                                 _ptr(x_im), _ptr(y_re), _ptr(y_im), reps, _stream_ptr(stream), ctypes.byref(h),
+                                 ctypes.byref(pol)), "mp_plan_autotune")
+    return Plan(h.value, A.n_rows), (pol.shift, pol.max_log2w)
+
+
+def _spmv_real(name, K):
+    fn = getattr(_lib, name)
+
+    def call(A, a, x, y, plan=None, stream=None):
+        _check_mp(a, K, A.nnz, "a")
+        _check_mp(x, K, A.n_cols, "x")
+        _check_mp(y, K, A.n_rows, "y")
+        _check(fn(ctypes.byref(A.c), _ptr(a), _ptr(x), _ptr(y), _plan_handle(plan), _stream_ptr(stream)), name)
+        return y
+
+    call.__name__ = name
+    call.__doc__ = "y = A x in %d-component arithmetic (C ABI %s); tensors of shape (K, len)." % (K, name)
+    return call
+
+
+def _spmv_complex(name, K):
+    fn = getattr(_lib, name)
+
+    def call(A, a_re, a_im, x_re, x_im, y_re, y_im, plan=None, stream=None):
+        for t, nm, L in ((a_re, "a_re", A.nnz), (a_im, "a_im", A.nnz), (x_re, "x_re", A.n_cols),
+                         (x_im, "x_im", A.n_cols), (y_re, "y_re", A.n_rows), (y_im, "y_im", A.n_rows)):
+            _check_mp(t, K, L, nm)
+        _check(fn(ctypes.byref(A.c), _ptr(a_re), _ptr(a_im), _ptr(x_re), _ptr(x_im), _ptr(y_re), _ptr(y_im),
+                  _plan_handle(plan), _stream_ptr(stream)), name)
+        return y_re, y_im
+
+    call.__name__ = name
+    call.__doc__ = "complex y = A x in %d-component arithmetic (C ABI %s)." % (K, name)
+    return call
+
+
+mpspmv_csr_dd = _spmv_real("mpspmv_csr_dd", 2)
+mpspmv_csr_td = _spmv_real("mpspmv_csr_td", 3)
+mpspmv_csr_qd = _spmv_real("mpspmv_csr_qd", 4)
+mpspmv_csr_dd_complex = _spmv_complex("mpspmv_csr_dd_complex", 2)
+mpspmv_csr_td_complex = _spmv_complex("mpspmv_csr_td_complex", 3)
+mpspmv_csr_qd_complex = _spmv_complex("mpspmv_csr_qd_complex", 4)
+
+SPMV = {(2, False): mpspmv_csr_dd, (3, False): mpspmv_csr_td, (4, False): mpspmv_csr_qd,
+        (2, True): mpspmv_csr_dd_complex, (3, True): mpspmv_csr_td_complex, (4, True): mpspmv_csr_qd_complex}

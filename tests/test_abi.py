@@ -1,0 +1,63 @@
+"""The C-ABI library builds for gfx950, loads, and exports every entry point the header
+declares (CPU only: no compute call is made)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mpsparse.h")
+LIB = os.path.join(ROOT, "paper_2412_17510_amd", "libmpsparse.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:mp_status|const char \*)\s*(\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2412_17510_amd import build
+        build.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_north_star_calls():
+    names = declared_functions()
+    for n in ("mpspmv_csr_dd", "mpspmv_csr_td", "mpspmv_csr_qd", "mpspmv_csr_dd_complex",
+              "mpspmv_csr_td_complex", "mpspmv_csr_qd_complex", "mp_last_error"):
+        assert n in names
+
+
+def test_every_declared_symbol_exported(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True, check=True).stdout
+    exported = set(line.split()[-1] for line in out.splitlines() if " T " in line)
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    for n in declared_functions():
+        assert hasattr(lib, n)
+
+
+def test_library_is_gfx950(lib):
+    """The embedded device code object targets gfx950 (target id string in our own build)."""
+    data = open(LIB, "rb").read()
+    assert b"amdgcn-amd-amdhsa--gfx950" in data
+
+
+def test_version_and_error_calls_are_host_only(lib):
+    lib.mp_version.restype = ctypes.c_char_p
+    lib.mp_last_error.restype = ctypes.c_char_p
+    assert b"gfx950" in lib.mp_version()
+    assert isinstance(lib.mp_last_error(), bytes)
+
+
+def test_null_arguments_rejected_without_gpu(lib):
+    """O(1) host checks fire before any HIP call."""
+    lib.mpspmv_csr_dd.restype = ctypes.c_int
+    lib.mp_last_error.restype = ctypes.c_char_p
+    assert lib.mpspmv_csr_dd(None, None, None, None, None, None) == -1
+    assert b"NULL" in lib.mp_last_error()

@@ -1,0 +1,256 @@
+"""GPU parity of the multi-component CSR SpMV (C ABI) with the CPU oracle.
+
+Bar: bitwise equality of every component (+0 == -0, no NaN) when the GPU plan's
+lane widths (the summation order, exported with mp_plan_row_log2w) are given to the
+oracle.  Cases: the 2D 5-point workload (n = 10,000, 49,600 nnz), ragged random
+matrices spanning several tiles and every lane width 1..1024, the paper's 5x5
+example, empty rows / empty matrices / a single 5,000-element row, every plan kind
+(plan-free kernel, canonical plan, width policies, explicit orders, autotuned), run
+to run determinism, argument errors, and the full n = 1e6 power-law workload on
+sampled rows (including every 4,096-element row).
+"""
+import numpy as np
+import pytest
+
+from oracle import ref
+from tests.helpers import assert_same_values, dev, host
+from workloads import (laplace2d_5pt, random_csr, random_mp, sqrt2_vector, csr_from_dense,
+                       paper_example_5x5, powerlaw_pattern, mp_from_leads)
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = [(2, False), (3, False), (4, False), (2, True), (3, True), (4, True)]
+
+
+@pytest.fixture(scope="module")
+def mp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2412_17510_amd import mp as binding
+    return binding
+
+
+def run_gpu(mp, K, cplx, A, a_re, x_re, a_im=None, x_im=None, plan=None):
+    import torch
+    n = A.n_rows
+    y_re = torch.full((K, n), float("nan"), dtype=torch.float64, device="cuda")
+    if not cplx:
+        mp.SPMV[(K, False)](A, dev(a_re), dev(x_re), y_re, plan=plan)
+        torch.cuda.synchronize()
+        return host(y_re), None
+    y_im = torch.full((K, n), float("nan"), dtype=torch.float64, device="cuda")
+    mp.SPMV[(K, True)](A, dev(a_re), dev(a_im), dev(x_re), dev(x_im), y_re, y_im, plan=plan)
+    torch.cuda.synchronize()
+    return host(y_re), host(y_im)
+
+
+def check(mp, K, cplx, row_ptr, col_idx, a_re, x_re, a_im=None, x_im=None, plan=None, A=None, what=""):
+    if A is None:
+        A = mp.Csr.from_numpy(row_ptr, col_idx, n_cols=x_re.shape[1])
+    y_re, y_im = run_gpu(mp, K, cplx, A, a_re, x_re, a_im, x_im, plan)
+    lw = None if plan is None else plan.row_log2w()
+    want = ref.spmv(K, row_ptr, col_idx, a_re, x_re, a_im=a_im, x_im=x_im, log2w=lw)
+    if cplx:
+        assert_same_values(y_re, want[0], what + " re")
+        assert_same_values(y_im, want[1], what + " im")
+    else:
+        assert_same_values(y_re, want, what)
+    return y_re, y_im
+
+
+def test_laplace2d_dd_all_plans(mp):
+    row_ptr, col_idx, a = laplace2d_5pt(100, K=2, seed=0)
+    rng = np.random.default_rng(0)
+    x = random_mp(10000, 2, rng)
+    A = mp.Csr.from_numpy(row_ptr, col_idx)
+    mp.mp_csr_validate(A)
+    check(mp, 2, False, row_ptr, col_idx, a, x, A=A, what="plan-free")
+    canon = mp.mp_plan_create(A)
+    assert np.array_equal(canon.row_log2w(), ref.canonical_log2w(np.diff(row_ptr)))
+    y1, _ = check(mp, 2, False, row_ptr, col_idx, a, x, plan=canon, A=A, what="canonical plan")
+    y0, _ = run_gpu(mp, 2, False, A, a, x)
+    assert_same_values(y0, y1, "plan-free vs canonical plan")
+    for shift, mx in ((0, 1), (2, 6), (1, 0)):
+        check(mp, 2, False, row_ptr, col_idx, a, x, plan=mp.mp_plan_create(A, shift, mx), A=A,
+              what="policy %d,%d" % (shift, mx))
+
+
+@pytest.mark.parametrize("K,cplx", VARIANTS)
+def test_ragged_random_every_width(mp, K, cplx):
+    rng = np.random.default_rng(1000 + 10 * K + cplx)
+    # every length class: empty, short, around wavefront and tile sizes, long
+    lengths = np.concatenate([[0, 1, 2, 3, 5, 63, 64, 65, 127, 128, 255, 256, 511, 512, 1023, 1024, 2049, 0],
+                              rng.integers(0, 40, 700), rng.integers(40, 300, 60)])
+    n_cols = 3000
+    row_ptr, col_idx, a_re, a_im = random_csr(lengths.size, n_cols, lengths, K, rng, cplx)
+    x_re = random_mp(n_cols, K, rng)
+    x_im = random_mp(n_cols, K, rng) if cplx else None
+    A = mp.Csr.from_numpy(row_ptr, col_idx, n_cols=n_cols)
+    check(mp, K, cplx, row_ptr, col_idx, a_re, x_re, a_im, x_im, A=A, what="plan-free")
+    check(mp, K, cplx, row_ptr, col_idx, a_re, x_re, a_im, x_im, plan=mp.mp_plan_create(A), A=A,
+          what="canonical")
+    check(mp, K, cplx, row_ptr, col_idx, a_re, x_re, a_im, x_im, plan=mp.mp_plan_create(A, 2, 4), A=A,
+          what="policy 2,4")
+    # explicit random orders, including every wide (multi-wavefront) width
+    fl = np.array([0 if L == 0 else int(np.floor(np.log2(L))) for L in lengths])
+    lw = np.array([rng.integers(0, min(10, f) + 1) for f in fl], dtype=np.uint8)
+    lw[lengths >= 1024] = 10
+    lw[(lengths >= 512) & (lengths < 1024)] = 9
+    lw[(lengths >= 256) & (lengths < 512)] = 8
+    lw[(lengths >= 128) & (lengths < 256)] = 7
+    check(mp, K, cplx, row_ptr, col_idx, a_re, x_re, a_im, x_im, plan=mp.mp_plan_create_explicit(A, lw), A=A,
+          what="explicit wide")
+    lw2 = np.array([rng.integers(0, min(10, f) + 1) for f in fl], dtype=np.uint8)
+    check(mp, K, cplx, row_ptr, col_idx, a_re, x_re, a_im, x_im, plan=mp.mp_plan_create_explicit(A, lw2), A=A,
+          what="explicit random")
+
+
+@pytest.mark.parametrize("K", [2, 3, 4])
+def test_paper_5x5_example(mp, K):
+    row_ptr, col_idx, vals = csr_from_dense(paper_example_5x5())
+    a = np.zeros((K, vals.size))
+    a[0] = vals
+    v = sqrt2_vector(5, K)
+    check(mp, K, False, row_ptr, col_idx, a, v, what="5x5 plan-free")
+    A = mp.Csr.from_numpy(row_ptr, col_idx)
+    check(mp, K, False, row_ptr, col_idx, a, v, plan=mp.mp_plan_create(A), A=A, what="5x5 canonical")
+
+
+@pytest.mark.parametrize("K,cplx", [(2, False), (4, True)])
+def test_edge_cases(mp, K, cplx):
+    import torch
+    rng = np.random.default_rng(7)
+    # all rows empty
+    row_ptr = np.zeros(9, dtype=np.int32)
+    col_idx = np.zeros(0, dtype=np.int32)
+    a = np.zeros((K, 0))
+    x = random_mp(4, K, rng)
+    xi = random_mp(4, K, rng) if cplx else None
+    check(mp, K, cplx, row_ptr, col_idx, a, x, a if cplx else None, xi, what="all empty")
+    A = mp.Csr.from_numpy(row_ptr, col_idx, n_cols=4)
+    check(mp, K, cplx, row_ptr, col_idx, a, x, a if cplx else None, xi, plan=mp.mp_plan_create(A), A=A,
+          what="all empty, plan")
+    # no rows at all
+    A0 = mp.Csr.from_numpy(np.zeros(1, dtype=np.int32), col_idx, n_cols=4)
+    y0 = torch.zeros((K, 0), dtype=torch.float64, device="cuda")
+    if cplx:
+        mp.SPMV[(K, True)](A0, dev(a), dev(a), dev(x), dev(xi), y0, y0.clone())
+    else:
+        mp.SPMV[(K, False)](A0, dev(a), dev(x), y0)
+    torch.cuda.synchronize()
+    # one long row and a 1-element row
+    lengths = np.array([5000, 1])
+    row_ptr, col_idx, a_re, a_im = random_csr(2, 6000, lengths, K, rng, cplx)
+    x = random_mp(6000, K, rng)
+    xi = random_mp(6000, K, rng) if cplx else None
+    A = mp.Csr.from_numpy(row_ptr, col_idx, n_cols=6000)
+    for plan in (None, mp.mp_plan_create(A), mp.mp_plan_create(A, 0, 10),
+                 mp.mp_plan_create_explicit(A, np.array([10, 0], dtype=np.uint8))):
+        check(mp, K, cplx, row_ptr, col_idx, a_re, x, a_im, xi, plan=plan, A=A, what="long row")
+
+
+def test_zero_tail_inputs_take_general_renorm_path(mp):
+    """Integer-valued inputs give exact zero errors inside the QD renormalisation (the
+    select-based path); results must still match the oracle and be exact."""
+    rng = np.random.default_rng(9)
+    lengths = rng.integers(0, 90, 300)
+    row_ptr, col_idx, _, _ = random_csr(300, 500, lengths, 4, rng)
+    for K in (3, 4):
+        a = np.zeros((K, col_idx.size))
+        a[0] = rng.integers(-2 ** 20, 2 ** 20, col_idx.size)
+        x = np.zeros((K, 500))
+        x[0] = rng.integers(-2 ** 20, 2 ** 20, 500)
+        y, _ = check(mp, K, False, row_ptr, col_idx, a, x, what="integers K=%d" % K)
+        assert np.all(y[1:] == 0)
+
+
+def test_determinism_and_errors(mp):
+    import torch
+    rng = np.random.default_rng(3)
+    lengths = rng.integers(0, 200, 2000)
+    row_ptr, col_idx, a, _ = random_csr(2000, 2500, lengths, 2, rng)
+    x = random_mp(2500, 2, rng)
+    A = mp.Csr.from_numpy(row_ptr, col_idx, n_cols=2500)
+    plan = mp.mp_plan_create(A, 1, 5)
+    ad, xd = dev(a), dev(x)
+    y = torch.empty((2, 2000), dtype=torch.float64, device="cuda")
+    mp.mpspmv_csr_dd(A, ad, xd, y, plan=plan)
+    first = host(y).copy()
+    for _ in range(10):
+        y.fill_(float("nan"))
+        mp.mpspmv_csr_dd(A, ad, xd, y, plan=plan)
+        assert np.array_equal(host(y), first)
+    # aliasing: y is x (square 5x5 example)
+    rp5, ci5, v5 = csr_from_dense(paper_example_5x5())
+    A5 = mp.Csr.from_numpy(rp5, ci5)
+    a5 = np.zeros((2, v5.size))
+    a5[0] = v5
+    x5 = dev(random_mp(5, 2, rng))
+    with pytest.raises(mp.MpError) as ei:
+        mp.mpspmv_csr_dd(A5, dev(a5), x5, x5)
+    assert ei.value.status == -2
+    # a plan built for another pattern is rejected
+    with pytest.raises(mp.MpError):
+        mp.mpspmv_csr_dd(A5, dev(a5), x5, torch.empty((2, 5), dtype=torch.float64, device="cuda"), plan=plan)
+    # malformed patterns are reported by validate
+    bad_cols = col_idx.copy()
+    bad_cols[5] = 2500
+    with pytest.raises(mp.MpError):
+        mp.mp_csr_validate(mp.Csr.from_numpy(row_ptr, bad_cols, n_cols=2500))
+    bad_rp = row_ptr.copy()
+    bad_rp[10] = bad_rp[11] + 1
+    with pytest.raises(mp.MpError):
+        mp.mp_csr_validate(mp.Csr.from_numpy(bad_rp, col_idx, n_cols=2500))
+    with pytest.raises(mp.MpError):
+        mp.mp_plan_create(mp.Csr.from_numpy(bad_rp, col_idx, n_cols=2500))
+    with pytest.raises(mp.MpError):
+        mp.mp_plan_create_explicit(A, np.full(2000, 10, dtype=np.uint8))
+
+
+# ---------------------------------------------------------------------------------------
+# full-size power-law workload (n = 1e6, mean 27 nnz/row), sampled rows
+# ---------------------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def powerlaw():
+    row_ptr, col_idx = powerlaw_pattern(n=1_000_000, seed=1)
+    return row_ptr, col_idx
+
+
+@pytest.mark.parametrize("K,cplx", VARIANTS)
+def test_powerlaw_full_size_sampled(mp, powerlaw, K, cplx):
+    import torch
+    row_ptr, col_idx = powerlaw
+    n = row_ptr.size - 1
+    nnz = col_idx.size
+    rng = np.random.default_rng([5, K, int(cplx)])
+    a_re = mp_from_leads(rng.uniform(-1, 1, nnz), K, rng)
+    a_im = mp_from_leads(rng.uniform(-1, 1, nnz), K, rng) if cplx else None
+    x_re = random_mp(n, K, rng)
+    x_im = random_mp(n, K, rng) if cplx else None
+    A = mp.Csr.from_numpy(row_ptr, col_idx)
+    ad_re, xd_re = dev(a_re), dev(x_re)
+    ad_im = dev(a_im) if cplx else None
+    xd_im = dev(x_im) if cplx else None
+    y_re = torch.empty((K, n), dtype=torch.float64, device="cuda")
+    y_im = torch.empty((K, n), dtype=torch.float64, device="cuda") if cplx else None
+    args = (ad_re, ad_im, xd_re, xd_im, y_re, y_im) if cplx else (ad_re, xd_re, y_re)
+    plan, pol = mp.mp_plan_autotune(A, K, ad_re, xd_re, y_re, ad_im, xd_im, y_im, reps=2)
+    lengths = np.diff(row_ptr)
+    rows = np.unique(np.concatenate([rng.choice(n, 3000, replace=False), np.nonzero(lengths >= 2048)[0],
+                                     [0, n - 1]]))
+    for p in (plan, None):
+        if cplx:
+            y_im.fill_(float("nan"))
+        y_re.fill_(float("nan"))
+        mp.SPMV[(K, cplx)](A, *args, plan=p)
+        torch.cuda.synchronize()
+        lw = None if p is None else p.row_log2w()
+        want = ref.spmv(K, row_ptr, col_idx, a_re, x_re, a_im=a_im, x_im=x_im, log2w=lw, rows=rows)
+        got_re = host(y_re)
+        if cplx:
+            assert_same_values(got_re[:, rows], want[0][:, rows], "powerlaw re %s" % (pol,))
+            assert_same_values(host(y_im)[:, rows], want[1][:, rows], "powerlaw im %s" % (pol,))
+        else:
+            assert_same_values(got_re[:, rows], want[:, rows], "powerlaw %s" % (pol,))
+        assert not np.isnan(got_re).any()
