@@ -1,0 +1,220 @@
+"""Benchmark: multi-component CSR SpMV throughput on one MI355X.
+
+Workload: the power-law CSR matrix (n = 1,000,000, row lengths with density ~ L^-2.1,
+mean 27 nnz/row, at most 4,096; 70% of the entries in a 2,000-wide band, 30%
+uniform; values U(-1,1) with K-component tails; seed 1), y = A x.
+
+One step = one y = A x in double-double (the headline variant) with the autotuned
+plan; `value` = nnz / (ms_per_step) in GNNZ/s.  The other variants (TD, QD, and the
+three complex ones) are timed the same way after the headline loop and reported in
+`variants`, each with its roofline.  Inputs are resident in HBM before timing starts.
+
+Roofline (algorithmic traffic and work only):
+  bytes/launch = 4(n+1) + nnz(4 + 8Kc) + 2*8Kc*n     (c = 2 for complex)
+  FP64 ops/launch = ops_per_nnz(K, complex) * nnz
+peaks: HBM 8.0 TB/s; FP64 VALU 256 CUs x 64 lanes x 2.4 GHz = 39.3e12 instructions/s
+(add, mul and fma each issue once; 78.6 TFLOP/s counts an fma as two flops).
+
+The CPU baseline is the oracle (plain scalar C, OpenMP over rows) timed on the host
+cores on the same matrix.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_INSTR_PEAK = 256 * 64 * 2.4e9      # 39.3e12 FP64 VALU instructions / s
+# FP64 instructions per nnz of the element operations (one mul + one add per nnz; the
+# counts follow the operation sequences of the library's arithmetic header)
+OPS_MUL = {2: 9, 3: 118, 4: 118}
+OPS_ADD = {2: 11, 3: 82, 4: 82}
+
+VARIANTS = [(2, False, "dd"), (3, False, "td"), (4, False, "qd"),
+            (2, True, "dd_complex"), (3, True, "td_complex"), (4, True, "qd_complex")]
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def ops_per_nnz(K, cplx):
+    per = OPS_MUL[K] + OPS_ADD[K]
+    return per * (4 if cplx else 1)
+
+
+def algo_bytes(n, nnz, K, cplx):
+    c = 2 if cplx else 1
+    return 4 * (n + 1) + nnz * (4 + 8 * K * c) + 2 * 8 * K * c * n
+
+
+def roofline(n, nnz, K, cplx, ms):
+    t = ms * 1e-3
+    gbs = algo_bytes(n, nnz, K, cplx) / t / 1e9
+    tops = ops_per_nnz(K, cplx) * nnz / t / 1e12
+    t_hbm = algo_bytes(n, nnz, K, cplx) / (HBM_PEAK_GBS * 1e9)
+    t_alu = ops_per_nnz(K, cplx) * nnz / FP64_INSTR_PEAK
+    if t_hbm >= t_alu:
+        return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    peak = FP64_INSTR_PEAK / 1e12
+    return {"bound": "alu", "achieved": round(tops, 2), "peak": round(peak, 2), "unit": "T FP64-instr/s",
+            "frac": round(tops / peak, 4)}
+
+
+def time_loop(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def copy_bandwidth(torch):
+    """Achievable HBM bandwidth of a plain device copy (1 GiB read + 1 GiB write)."""
+    n = (1 << 30) // 8
+    src = torch.empty(n, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    ms, _ = time_loop(lambda: dst.copy_(src), 10, 3, torch)
+    del src, dst
+    return 2 * n * 8 / (ms * 1e-3) / 1e9
+
+
+def cpu_baseline(row_ptr, col_idx, a, x, min_seconds):
+    from oracle import ref
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        ref.spmv(2, row_ptr, col_idx, a, x)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= min_seconds:
+            break
+    nnz = col_idx.size
+    return {"value": round(reps * nnz / el / 1e9, 4), "unit": "GNNZ/s", "cores": ref.num_threads(),
+            "kind": "oracle",
+            "sample": "DD real y=Ax on the full n=1e6 power-law matrix (%d nnz), %d repetitions in %.1f s"
+                      % (nnz, reps, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--variants", default="all", help="comma list of dd,td,qd,dd_complex,... or all")
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=6.0)
+    ap.add_argument("--plan", default="autotune", help="autotune | canonical | shift,max_log2w,tile_nnz")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (multi-GPU sharding is a design note, not a "
+              "measured path); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2412_17510_amd import mp
+    from workloads import powerlaw_pattern, random_mp, mp_from_leads
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    row_ptr, col_idx = powerlaw_pattern(n=args.n, seed=1)
+    n = row_ptr.size - 1
+    nnz = col_idx.size
+    log("pattern n=%d nnz=%d in %.1f s" % (n, nnz, time.perf_counter() - t0))
+    A = mp.Csr.from_numpy(row_ptr, col_idx)
+    wanted = [v for v in VARIANTS if args.variants == "all" or v[2] in args.variants.split(",")]
+    if wanted[0][2] != "dd":
+        raise SystemExit("the headline variant dd must be included")
+
+    results = {}
+    headline = None
+    host_dd = None
+    for K, cplx, name in wanted:
+        rng = np.random.default_rng([1, K, int(cplx)])
+        a_re = mp_from_leads(rng.uniform(-1, 1, nnz), K, rng)
+        a_im = mp_from_leads(rng.uniform(-1, 1, nnz), K, rng) if cplx else None
+        x_re = random_mp(n, K, rng)
+        x_im = random_mp(n, K, rng) if cplx else None
+        d = lambda v: None if v is None else torch.from_numpy(v).cuda()  # noqa: E731
+        ad_re, ad_im, xd_re, xd_im = d(a_re), d(a_im), d(x_re), d(x_im)
+        y_re = torch.empty((K, n), dtype=torch.float64, device="cuda")
+        y_im = torch.empty((K, n), dtype=torch.float64, device="cuda") if cplx else None
+        if name == "dd":
+            host_dd = (a_re, x_re)
+        del a_re, a_im, x_re, x_im
+        if args.plan == "autotune":
+            plan, pol = mp.mp_plan_autotune(A, K, ad_re, xd_re, y_re, ad_im, xd_im, y_im, reps=5)
+        elif args.plan == "canonical":
+            plan = mp.mp_plan_create(A, K, cplx)
+            pol = {"shift": 0, "max_log2w": 6, "tile_nnz": plan.info()["tile_nnz"]}
+        else:
+            s, m, c = (int(v) for v in args.plan.split(","))
+            plan = mp.mp_plan_create(A, K, cplx, s, m, c)
+            pol = {"shift": s, "max_log2w": m, "tile_nnz": plan.info()["tile_nnz"]}
+        fn = mp.SPMV[(K, cplx)]
+        if cplx:
+            step = lambda: fn(A, ad_re, ad_im, xd_re, xd_im, y_re, y_im, plan=plan)  # noqa: E731
+        else:
+            step = lambda: fn(A, ad_re, xd_re, y_re, plan=plan)  # noqa: E731
+        ms, wall = time_loop(step, args.steps, args.warmup, torch)
+        rf = roofline(n, nnz, K, cplx, ms)
+        results[name] = {"gnnz_s": round(nnz / (ms * 1e-3) / 1e9, 3), "ms": round(ms, 4),
+                         "plan": pol, "roofline": rf}
+        log("%-10s policy=%s %.4f ms  %.2f GNNZ/s  %s %.1f %s (%.1f%%)" % (
+            name, pol, ms, nnz / (ms * 1e-3) / 1e9, rf["bound"], rf["achieved"], rf["unit"], 100 * rf["frac"]))
+        if name == "dd":
+            headline = (ms, wall, rf, pol)
+        del ad_re, ad_im, xd_re, xd_im, y_re, y_im, plan
+        torch.cuda.empty_cache()
+
+    copy_gbs = copy_bandwidth(torch)
+    log("device copy bandwidth %.0f GB/s" % copy_gbs)
+    ms, wall, rf, pol = headline
+    rf = dict(rf)
+    rf["traffic"] = None
+    rf["measured_copy_GBs"] = round(copy_gbs, 1)
+    out = {
+        "metric": "DD SpMV GNNZ/s (power-law n=1e6, autotuned plan) and % of the binding roofline",
+        "value": round(nnz / (ms * 1e-3) / 1e9, 3),
+        "unit": "GNNZ/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "powerlaw-csr n=%d nnz=%d mean-row 27 max-row 4096 band70%%/2000 uniform30%%" % (n, nnz),
+                   "precision": "double-double (K=2 binary64 components), real",
+                   "plan": pol, "parallelism": "single-gpu"},
+        "roofline": rf,
+        "variants": results,
+    }
+    if not args.no_cpu_baseline and host_dd is not None:
+        log("timing the CPU oracle ...")
+        out["cpu_baseline"] = cpu_baseline(row_ptr, col_idx, host_dd[0], host_dd[1], args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -68,17 +68,27 @@ typedef struct {
     const int32_t *col_idx;
 } mp_csr;
 
-/* Opaque execution plan: per-row lane widths (the summation order), rows binned by
- * lane width, and the tile list one fused kernel launch walks.  Immutable after
- * creation; usable from several streams at once; owned by the library. */
+/* Opaque execution plan of one pattern for one variant (K components, real or
+ * complex): the per-row lane widths (the summation order), the work decomposition
+ * one SpMV launch walks -- contiguous row tiles of at most tile_nnz elements whose
+ * products are staged in LDS, and single-row tiles for longer rows -- and a device
+ * buffer into which every planned SpMV first copies x with its components side by
+ * side (so that one gather fetches all of them).  Owned by the library.  Because of
+ * that buffer, SpMV calls that use the same plan must not run concurrently: issue
+ * them on one stream or order them with events. */
 typedef struct mp_plan mp_plan;
 
-/* Width policy of a plan: log2w(len) = clamp(floor(log2(len)) - shift, 0, max_log2w)
- * (len >= 1; empty rows get 0).  shift = 0, max_log2w = 6 is the canonical order. */
+/* Plan options.  Lane widths: log2w(len) = clamp(floor(log2(len)) - shift, 0,
+ * max_log2w) for len >= 1 (empty rows get 0); shift = 0, max_log2w = 6 is the
+ * canonical order.  tile_nnz: elements staged per workgroup tile, one of 256, 512,
+ * 1024, 2048 and at most what the variant's LDS budget allows (DD real 2048, TD/QD
+ * real 1024, DD/TD complex 512, QD complex 256); 0 = the largest allowed, capped at
+ * 1024. */
 typedef struct {
     int32_t shift;      /* 0..12: aim at >= 2^shift elements per lane */
     int32_t max_log2w;  /* 0..10: widest lane group (1024 lanes) */
-} mp_width_policy;
+    int32_t tile_nnz;   /* 0 or 256..2048 (power of two) */
+} mp_plan_opts;
 
 /* Last error message of the calling thread ("" if none).  Static storage. */
 const char *mp_last_error(void);
@@ -91,25 +101,27 @@ const char *mp_version(void);
  * Returns MP_OK or MP_ERR_INVALID_ARG (with the first problem in mp_last_error()). */
 mp_status mp_csr_validate(const mp_csr *A, void *stream);
 
-/* Build a plan for pattern A with the given width policy (NULL = canonical).
- * Reads row_ptr back to the host once, bins rows by lane width and uploads the row
- * permutation and tile list.  Synchronises `stream`.  *out receives the plan. */
-mp_status mp_plan_create(const mp_csr *A, const mp_width_policy *policy, void *stream, mp_plan **out);
+/* Build a plan for pattern A and variant (ncomp in {2,3,4}, is_complex in {0,1}) with
+ * the given options (NULL = canonical order, default tile size).  Reads row_ptr back
+ * to the host once and uploads the tile list.  Synchronises `stream`. */
+mp_status mp_plan_create(const mp_csr *A, int32_t ncomp, int32_t is_complex, const mp_plan_opts *opts,
+                         void *stream, mp_plan **out);
 
 /* Build a plan whose lane widths are given explicitly: host array log2w[n_rows],
  * each entry <= 10 and with 2^log2w[i] <= len_i for non-empty rows (0 for empty rows).
- * Synchronises `stream`. */
-mp_status mp_plan_create_explicit(const mp_csr *A, const uint8_t *log2w_host, void *stream, mp_plan **out);
+ * tile_nnz as in mp_plan_opts.  Synchronises `stream`. */
+mp_status mp_plan_create_explicit(const mp_csr *A, int32_t ncomp, int32_t is_complex, const uint8_t *log2w_host,
+                                  int32_t tile_nnz, void *stream, mp_plan **out);
 
 /* Autotuned plan (Sec. 4.1 observes that SpMV speed depends on the matrix size and
- * structure): times every width policy of a fixed candidate list with the K-component
- * kernel (complex if is_complex) on the caller's operands, which are only read
- * (y is overwritten), and keeps the fastest.  The winning policy is returned in
+ * structure): times the K-component kernel (complex if is_complex) on the caller's
+ * operands (only read; y is overwritten) for a fixed list of tile sizes and then of
+ * width policies, and keeps the fastest.  The winning options are returned in
  * *chosen (may be NULL).  Synchronises `stream`. */
 mp_status mp_plan_autotune(const mp_csr *A, int32_t ncomp, int32_t is_complex,
                            const double *a_re, const double *a_im, const double *x_re, const double *x_im,
                            double *y_re, double *y_im, int32_t reps, void *stream,
-                           mp_plan **out, mp_width_policy *chosen);
+                           mp_plan **out, mp_plan_opts *chosen);
 
 mp_status mp_plan_destroy(mp_plan *plan);
 
@@ -117,15 +129,17 @@ mp_status mp_plan_destroy(mp_plan *plan);
  * (the summation order of every row, for reproducing a result elsewhere). */
 mp_status mp_plan_row_log2w(const mp_plan *plan, uint8_t *log2w_host);
 
-/* Number of rows and of workgroup tiles of a plan (host ints; either may be NULL). */
-mp_status mp_plan_info(const mp_plan *plan, int32_t *n_rows, int32_t *n_tiles);
+/* Plan facts (host ints; any pointer may be NULL): rows, tiles, staged elements per
+ * tile, variant. */
+mp_status mp_plan_info(const mp_plan *plan, int32_t *n_rows, int32_t *n_tiles, int32_t *tile_nnz,
+                       int32_t *ncomp, int32_t *is_complex);
 
 /*
  * Real SpMV y = A x (Sec. 3, Fig. 1) in DD (Algs 1-2), TD and QD (Sec. 2).
  *   a: K*nnz values, x: K*n_cols, y: K*n_rows (multi-component layout above).
  *   plan: NULL = canonical order with a one-row-per-wavefront kernel that needs no
- *   plan; otherwise the plan's order and binned kernel (the plan must have been made
- *   for a pattern with the same n_rows).
+ *   plan; otherwise the plan's order and tiles (the plan must have been made for
+ *   this variant and for a pattern with the same n_rows and nnz).
  *   y must not overlap a or x (MP_ERR_ALIAS).  Enqueues on `stream` and returns.
  */
 mp_status mpspmv_csr_dd(const mp_csr *A, const double *a, const double *x, double *y,
@@ -152,6 +166,70 @@ mp_status mpspmv_csr_td_complex(const mp_csr *A, const double *a_re, const doubl
 mp_status mpspmv_csr_qd_complex(const mp_csr *A, const double *a_re, const double *a_im,
                                 const double *x_re, const double *x_im, double *y_re, double *y_im,
                                 const mp_plan *plan, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Krylov solvers in double-double (Sec. 4.2: CG for symmetric positive-definite A,
+ * BiCGSTAB for non-symmetric A; x0 given, stop on the residual norm).
+ *
+ * The solve runs on the device: one SpMV (in the plan's order, or the canonical
+ * order when plan is NULL) and fused DD vector kernels per step; every dot product
+ * uses one fixed reduction tree (chunks of 4096 elements summed in the W = 256 lane
+ * order, chunk sums combined pairwise), so iterates are reproducible bit for bit.
+ * The iteration stops when the recurrence residual satisfies ||r||^2 <= rtol^2
+ * ||b||^2 (DD comparison) and the true residual b - A x confirms it; a failed
+ * confirmation restarts the recurrence from the true residual.  Scalars (alpha,
+ * beta, omega) are DD, divisions use Dekker's DD long division.  The host reads the
+ * device state back every `check_every` iterations (the only device-to-host
+ * traffic of a solve).
+ * ------------------------------------------------------------------------- */
+
+enum { MP_PRECOND_NONE = 0, MP_PRECOND_JACOBI = 1 };
+enum { MP_INNER_FP64 = 0, MP_INNER_FP32 = 1 };
+
+typedef struct {
+    int32_t precond;        /* MP_PRECOND_NONE or MP_PRECOND_JACOBI (z_i = r_i * fl(1/hi(a_ii)), Alg. 3) */
+    int32_t max_iter;       /* Krylov iterations (for refinement: per inner solve) */
+    double rtol;            /* target ||b - A x||_2 <= rtol ||b||_2 */
+    int32_t check_every;    /* iterations between host reads of the device state (0 = 32) */
+    int32_t inner;          /* refinement only: MP_INNER_FP64 or MP_INNER_FP32 */
+    double inner_rtol;      /* refinement only: residual reduction asked of each inner solve */
+    int32_t inner_max_iter; /* refinement only (0 = max_iter) */
+    int32_t max_outer;      /* refinement only: refinement steps */
+} mp_solve_opts;
+
+typedef struct {
+    int32_t status;      /* MP_OK, MP_ERR_NOT_CONVERGED or MP_ERR_BREAKDOWN */
+    int32_t iters;       /* Krylov iterations (refinement: total inner iterations) */
+    int32_t outer_iters; /* refinement steps (0 for the plain solvers) */
+    int32_t restarts;    /* failed true-residual confirmations */
+    double rr_true[2];   /* DD ||b - A x||^2 of the returned x */
+    double bb[2];        /* DD ||b||^2 */
+    double relres;       /* sqrt(rr_true / bb) in binary64 */
+    double seconds;      /* wall time of the call */
+} mp_solve_info;
+
+/* Bytes of device workspace a solver needs for A and opts (host size_t out). */
+mp_status mpkrylov_workspace_bytes(const mp_csr *A, const mp_solve_opts *opts, size_t *bytes);
+
+/*
+ * DD preconditioned CG.  a: 2*nnz DD values of an SPD matrix (n_rows == n_cols);
+ * b: 2*n right-hand side; x: 2*n, in = x0, out = solution (the best iterate on
+ * non-convergence).  ws: device workspace of ws_bytes >= mpkrylov_workspace_bytes.
+ * plan: NULL or a DD real plan of A.  info: host struct, filled on return.
+ * Synchronises `stream`.  Returns MP_OK, MP_ERR_NOT_CONVERGED or MP_ERR_BREAKDOWN
+ * (pAp <= 0 or a non-finite scalar), or an argument / HIP error.
+ */
+mp_status mpkrylov_cg(const mp_csr *A, const double *a, const double *b, double *x, const mp_solve_opts *opts,
+                      const mp_plan *plan, void *ws, size_t ws_bytes, mp_solve_info *info, void *stream);
+
+/*
+ * DD BiCGSTAB (van der Vorst) with right Jacobi preconditioning (or none), shadow
+ * residual r0.  Arguments as mpkrylov_cg; A need not be symmetric.  Breakdown when
+ * (r0, r), (r0, v) or (t, t) vanishes or omega = 0.
+ */
+mp_status mpkrylov_bicgstab(const mp_csr *A, const double *a, const double *b, double *x,
+                            const mp_solve_opts *opts, const mp_plan *plan, void *ws, size_t ws_bytes,
+                            mp_solve_info *info, void *stream);
 
 #ifdef __cplusplus
 }

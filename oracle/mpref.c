@@ -384,11 +384,11 @@ int oracle_spmv(int K, int64_t n_rows, int64_t n_cols, int64_t nnz,
     const int cplx = (a_im != NULL);
     if (K < 2 || K > 4) return -1;
 #ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
+    const int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
 #else
     (void)nthreads;
 #endif
-#pragma omp parallel
+#pragma omp parallel num_threads(nt)
     {
         mpv *lanes = (mpv *)malloc(sizeof(mpv) * 1024);
 #pragma omp for schedule(dynamic, 256)
@@ -432,4 +432,311 @@ int oracle_num_threads(void)
 #else
     return 1;
 #endif
+}
+
+/* ------------------------------------------------------------------------- */
+/* DD vector kernels and scalars for the Krylov solvers (Sec. 4.2).           */
+/* ------------------------------------------------------------------------- */
+
+#define DOT_LANES 256
+#define DOT_CHUNK 4096
+
+/* DD comparison a <= b on (leading, trailing) pairs of non-overlapping values. */
+static int dd_le(mpv a, mpv b)
+{
+    return (a.c[0] < b.c[0]) || (a.c[0] == b.c[0] && a.c[1] <= b.c[1]);
+}
+
+/* DD division a / b (Dekker's long division): q1 = a0/b0, the remainder
+ * a - q1*b formed with TwoProd/TwoSum and the trailing parts, q2 = remainder/b0,
+ * result QuickTwoSum(q1, q2). */
+static mpv dd_div(mpv a, mpv b)
+{
+    double q1, p, e, w, s, f, q2;
+    mpv r = {{0.0, 0.0, 0.0, 0.0}};
+    q1 = a.c[0] / b.c[0];
+    two_prod(q1, b.c[0], &p, &e);
+    w = q1 * b.c[1];
+    e = e + w;
+    two_sum(a.c[0], -p, &s, &f);
+    f = f - e;
+    f = f + a.c[1];
+    q2 = (s + f) / b.c[0];
+    quick_two_sum(q1, q2, &r.c[0], &r.c[1]);
+    return r;
+}
+
+/* Dot product order: the vector is cut into chunks of 4096 elements; inside a
+ * chunk, lane l < 256 accumulates elements l, l+256, ... (the SpMV row order with
+ * W = 256), the lanes holding elements are folded acc[l] += acc[l+off], off =
+ * 128..1, a lane without elements being skipped; the chunk sums are then combined
+ * by a pairwise tree, P[i] = add(P[2i], P[2i+1]) level by level, an unpaired last
+ * element passing up unchanged.  n = 0 gives 0. */
+static mpv dd_dot_vec(int64_t n, const double *x, const double *y)
+{
+    int64_t nch = (n + DOT_CHUNK - 1) / DOT_CHUNK, c, m;
+    mpv zero = {{0.0, 0.0, 0.0, 0.0}};
+    mpv *P, lanes[DOT_LANES], out;
+    if (n == 0) return zero;
+    P = (mpv *)malloc(sizeof(mpv) * (size_t)nch);
+    for (c = 0; c < nch; ++c) {
+        int64_t base = c * DOT_CHUNK, cnt = n - base < DOT_CHUNK ? n - base : DOT_CHUNK;
+        int l, off, used = cnt < DOT_LANES ? (int)cnt : DOT_LANES;
+        for (l = 0; l < used; ++l) {
+            int64_t k = base + l;
+            lanes[l] = dd_mul(load_mp(2, x, n, k), load_mp(2, y, n, k));
+            for (k = k + DOT_LANES; k < base + cnt; k += DOT_LANES)
+                lanes[l] = dd_add(lanes[l], dd_mul(load_mp(2, x, n, k), load_mp(2, y, n, k)));
+        }
+        for (off = DOT_LANES / 2; off >= 1; off /= 2)
+            for (l = 0; l < off; ++l)
+                if (l + off < used) lanes[l] = dd_add(lanes[l], lanes[l + off]);
+        P[c] = lanes[0];
+    }
+    for (m = nch; m > 1; m = (m + 1) / 2) {
+        int64_t i;
+        for (i = 0; i < m / 2; ++i) P[i] = dd_add(P[2 * i], P[2 * i + 1]);
+        if (m % 2) P[m / 2] = P[m - 1];
+    }
+    out = P[0];
+    free(P);
+    return out;
+}
+
+int oracle_dd_dot(int64_t n, const double *x, const double *y, double *out2)
+{
+    mpv d = dd_dot_vec(n, x, y);
+    out2[0] = d.c[0];
+    out2[1] = d.c[1];
+    return 0;
+}
+
+int oracle_dd_div(const double *a2, const double *b2, double *out2)
+{
+    mpv a = {{a2[0], a2[1], 0.0, 0.0}}, b = {{b2[0], b2[1], 0.0, 0.0}}, r = dd_div(a, b);
+    out2[0] = r.c[0];
+    out2[1] = r.c[1];
+    return 0;
+}
+
+/* Krylov result record (matches the solver info of the GPU library). */
+typedef struct {
+    int32_t status;      /* 0 converged, -5 not converged, -6 breakdown */
+    int32_t iters;
+    int32_t restarts;    /* true-residual confirmations that failed */
+    int32_t reserved;
+    double rr_true[2];   /* DD ||b - A x||^2 at exit */
+    double bb[2];        /* DD ||b||^2 */
+} oracle_solve_info;
+
+typedef struct {
+    int64_t n, nnz;
+    const int32_t *row_ptr, *col_idx;
+    const uint8_t *log2w;
+    const double *a;
+} dd_mat;
+
+static void dd_spmv(const dd_mat *M, const double *x, double *y)
+{
+    oracle_spmv(2, M->n, M->n, M->nnz, M->row_ptr, M->col_idx, M->log2w, M->a, NULL, x, NULL, y, NULL,
+                0, NULL, 0);
+}
+
+static mpv ld2(const double *v, int64_t n, int64_t i) { return load_mp(2, v, n, i); }
+static void st2(double *v, int64_t n, int64_t i, mpv x) { store_mp(2, v, n, i, x); }
+
+/* r = b - A x  (q is scratch) */
+static void dd_residual(const dd_mat *M, const double *b, const double *x, double *q, double *r)
+{
+    int64_t i, n = M->n;
+    dd_spmv(M, x, q);
+    for (i = 0; i < n; ++i) st2(r, n, i, dd_add(ld2(b, n, i), mp_neg(ld2(q, n, i))));
+}
+
+/* z = M^-1 r: Jacobi (z_i = DDmulD(r_i, minv_i), Alg. 3) or copy when minv is NULL */
+static void dd_precond(int64_t n, const double *minv, const double *r, double *z)
+{
+    int64_t i;
+    for (i = 0; i < n; ++i) st2(z, n, i, minv ? dd_mul_d(ld2(r, n, i), minv[i]) : ld2(r, n, i));
+}
+
+/* Jacobi inverse diagonal: fl(1 / leading component of a_ii) (1 where the row has no
+ * diagonal entry). */
+int oracle_jacobi_minv(int64_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *a_hi,
+                       double *minv)
+{
+    int64_t i, k;
+    for (i = 0; i < n; ++i) {
+        minv[i] = 1.0;
+        for (k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+            if (col_idx[k] == i) minv[i] = 1.0 / a_hi[k];
+    }
+    return 0;
+}
+
+/*
+ * Preconditioned CG in DD (Hestenes-Stiefel form; x0 given, stop on the recurrence
+ * residual ||r_k||^2 <= rtol^2 ||b||^2, confirmed with the true residual b - A x;
+ * a failed confirmation restarts from the true residual).
+ *   minv: Jacobi inverse diagonal (NULL = no preconditioner).  hist (optional,
+ *   2*(max_iter+1) doubles): DD ||r_k||^2 of the recurrence at iteration k.
+ */
+int oracle_cg(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx, const uint8_t *log2w,
+              const double *a, const double *b, double *x, const double *minv, double rtol, int32_t max_iter,
+              oracle_solve_info *info, double *hist)
+{
+    dd_mat M = {n, nnz, row_ptr, col_idx, log2w, a};
+    double *r = (double *)malloc(sizeof(double) * 2 * (size_t)n);
+    double *z = (double *)malloc(sizeof(double) * 2 * (size_t)n);
+    double *p = (double *)malloc(sizeof(double) * 2 * (size_t)n);
+    double *q = (double *)malloc(sizeof(double) * 2 * (size_t)n);
+    mpv rho, rr, bb, tol2, pq, alpha, beta, rho_new;
+    int64_t i;
+    int32_t k = 0;
+    int status = -5;
+    memset(info, 0, sizeof(*info));
+    bb = dd_dot_vec(n, b, b);
+    tol2 = dd_mul_d(bb, rtol * rtol);
+    dd_residual(&M, b, x, q, r);
+    dd_precond(n, minv, r, z);
+    memcpy(p, z, sizeof(double) * 2 * (size_t)n);
+    rho = dd_dot_vec(n, r, z);
+    rr = dd_dot_vec(n, r, r);
+    if (hist) { hist[0] = rr.c[0]; hist[1] = rr.c[1]; }
+    for (;;) {
+        if (dd_le(rr, tol2)) {
+            /* confirm with the true residual */
+            dd_residual(&M, b, x, q, r);
+            rr = dd_dot_vec(n, r, r);
+            if (dd_le(rr, tol2)) { status = 0; break; }
+            info->restarts++;
+            dd_precond(n, minv, r, z);
+            memcpy(p, z, sizeof(double) * 2 * (size_t)n);
+            rho = dd_dot_vec(n, r, z);
+        }
+        if (k >= max_iter) break;
+        dd_spmv(&M, p, q);
+        pq = dd_dot_vec(n, p, q);
+        if (!(pq.c[0] > 0.0) || !isfinite(pq.c[0])) { status = -6; break; }
+        alpha = dd_div(rho, pq);
+        for (i = 0; i < n; ++i) {
+            st2(x, n, i, dd_add(ld2(x, n, i), dd_mul(alpha, ld2(p, n, i))));
+            st2(r, n, i, dd_add(ld2(r, n, i), mp_neg(dd_mul(alpha, ld2(q, n, i)))));
+        }
+        dd_precond(n, minv, r, z);
+        rho_new = dd_dot_vec(n, r, z);
+        rr = dd_dot_vec(n, r, r);
+        k++;
+        if (hist) { hist[2 * k] = rr.c[0]; hist[2 * k + 1] = rr.c[1]; }
+        if (!isfinite(rr.c[0]) || !isfinite(rho_new.c[0])) { status = -6; break; }
+        beta = dd_div(rho_new, rho);
+        rho = rho_new;
+        for (i = 0; i < n; ++i) st2(p, n, i, dd_add(ld2(z, n, i), dd_mul(beta, ld2(p, n, i))));
+    }
+    /* exit record: the true residual of the returned x */
+    dd_residual(&M, b, x, q, r);
+    rr = dd_dot_vec(n, r, r);
+    info->status = status;
+    info->iters = k;
+    info->rr_true[0] = rr.c[0]; info->rr_true[1] = rr.c[1];
+    info->bb[0] = bb.c[0]; info->bb[1] = bb.c[1];
+    free(r); free(z); free(p); free(q);
+    return status;
+}
+
+/*
+ * BiCGSTAB (van der Vorst) in DD with right preconditioning by minv (NULL = none);
+ * shadow residual = the initial residual.  Same stopping rule and restart-on-failed-
+ * confirmation as oracle_cg; the convergence test is made on ||s||^2 after the
+ * half step and on ||r||^2 after the full step.
+ */
+int oracle_bicgstab(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx, const uint8_t *log2w,
+                    const double *a, const double *b, double *x, const double *minv, double rtol,
+                    int32_t max_iter, oracle_solve_info *info, double *hist)
+{
+    dd_mat M = {n, nnz, row_ptr, col_idx, log2w, a};
+    size_t bytes = sizeof(double) * 2 * (size_t)n;
+    double *r = (double *)malloc(bytes), *rh = (double *)malloc(bytes), *p = (double *)malloc(bytes);
+    double *v = (double *)malloc(bytes), *ph = (double *)malloc(bytes), *s = (double *)malloc(bytes);
+    double *sh = (double *)malloc(bytes), *t = (double *)malloc(bytes), *q = (double *)malloc(bytes);
+    mpv one = {{1.0, 0.0, 0.0, 0.0}}, zero = {{0.0, 0.0, 0.0, 0.0}};
+    mpv rho_old = one, alpha = one, omega = one, rho, beta, rv, ts, tt, rr, ss, bb, tol2;
+    int64_t i;
+    int32_t k = 0;
+    int status = -5, fresh = 1;
+    memset(info, 0, sizeof(*info));
+    bb = dd_dot_vec(n, b, b);
+    tol2 = dd_mul_d(bb, rtol * rtol);
+    dd_residual(&M, b, x, q, r);
+    memcpy(rh, r, bytes);
+    memset(v, 0, bytes);
+    memset(p, 0, bytes);
+    rr = dd_dot_vec(n, r, r);
+    if (hist) { hist[0] = rr.c[0]; hist[1] = rr.c[1]; }
+    for (;;) {
+        if (dd_le(rr, tol2)) {
+            dd_residual(&M, b, x, q, r);
+            rr = dd_dot_vec(n, r, r);
+            if (dd_le(rr, tol2)) { status = 0; break; }
+            info->restarts++;
+            memcpy(rh, r, bytes);
+            fresh = 1;
+        }
+        if (k >= max_iter) break;
+        rho = dd_dot_vec(n, rh, r);
+        if (rho.c[0] == 0.0 || !isfinite(rho.c[0])) { status = -6; break; }
+        if (fresh) {
+            memcpy(p, r, bytes);
+            fresh = 0;
+        } else {
+            beta = dd_mul(dd_div(rho, rho_old), dd_div(alpha, omega));
+            for (i = 0; i < n; ++i) {
+                mpv pv = dd_add(ld2(p, n, i), mp_neg(dd_mul(omega, ld2(v, n, i))));
+                st2(p, n, i, dd_add(ld2(r, n, i), dd_mul(beta, pv)));
+            }
+        }
+        dd_precond(n, minv, p, ph);
+        dd_spmv(&M, ph, v);
+        rv = dd_dot_vec(n, rh, v);
+        if (rv.c[0] == 0.0 || !isfinite(rv.c[0])) { status = -6; break; }
+        alpha = dd_div(rho, rv);
+        for (i = 0; i < n; ++i) st2(s, n, i, dd_add(ld2(r, n, i), mp_neg(dd_mul(alpha, ld2(v, n, i)))));
+        ss = dd_dot_vec(n, s, s);
+        k++;
+        if (dd_le(ss, tol2)) {
+            for (i = 0; i < n; ++i) st2(x, n, i, dd_add(ld2(x, n, i), dd_mul(alpha, ld2(ph, n, i))));
+            memcpy(r, s, bytes);
+            rr = ss;
+            if (hist) { hist[2 * k] = rr.c[0]; hist[2 * k + 1] = rr.c[1]; }
+            rho_old = rho;
+            omega = one;
+            fresh = 1;
+            continue;
+        }
+        dd_precond(n, minv, s, sh);
+        dd_spmv(&M, sh, t);
+        ts = dd_dot_vec(n, t, s);
+        tt = dd_dot_vec(n, t, t);
+        if (tt.c[0] == 0.0 || !isfinite(tt.c[0])) { status = -6; break; }
+        omega = dd_div(ts, tt);
+        for (i = 0; i < n; ++i) {
+            mpv xv = dd_add(ld2(x, n, i), dd_mul(alpha, ld2(ph, n, i)));
+            st2(x, n, i, dd_add(xv, dd_mul(omega, ld2(sh, n, i))));
+            st2(r, n, i, dd_add(ld2(s, n, i), mp_neg(dd_mul(omega, ld2(t, n, i)))));
+        }
+        rr = dd_dot_vec(n, r, r);
+        if (hist) { hist[2 * k] = rr.c[0]; hist[2 * k + 1] = rr.c[1]; }
+        if (!isfinite(rr.c[0])) { status = -6; break; }
+        if (omega.c[0] == 0.0) { status = -6; break; }
+        rho_old = rho;
+    }
+    (void)zero;
+    dd_residual(&M, b, x, q, r);
+    rr = dd_dot_vec(n, r, r);
+    info->status = status;
+    info->iters = k;
+    info->rr_true[0] = rr.c[0]; info->rr_true[1] = rr.c[1];
+    info->bb[0] = bb.c[0]; info->bb[1] = bb.c[1];
+    free(r); free(rh); free(p); free(v); free(ph); free(s); free(sh); free(t); free(q);
+    return status;
 }

@@ -116,3 +116,87 @@ def num_threads():
 
 def loaded_path():
     return os.path.abspath(_build.LIB)
+
+
+# ---------------------------------------------------------------------------------------
+# Krylov layer (DD): dot, division, Jacobi inverse diagonal, CG, BiCGSTAB
+# ---------------------------------------------------------------------------------------
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("rr_true", ctypes.c_double * 2), ("bb", ctypes.c_double * 2)]
+
+
+def _krylov_sigs():
+    L = lib()
+    if getattr(L, "_krylov_ready", False):
+        return L
+    P = ctypes.c_void_p
+    i64 = ctypes.c_int64
+    L.oracle_dd_dot.argtypes = [i64, P, P, P]
+    L.oracle_dd_div.argtypes = [P, P, P]
+    L.oracle_jacobi_minv.argtypes = [i64, P, P, P, P]
+    for f in (L.oracle_cg, L.oracle_bicgstab):
+        f.argtypes = [i64, i64, P, P, P, P, P, P, P, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(SolveInfo), P]
+        f.restype = ctypes.c_int
+    L._krylov_ready = True
+    return L
+
+
+def dd_dot(x, y):
+    L = _krylov_sigs()
+    x, y = _f64(x), _f64(y)
+    out = np.zeros(2)
+    L.oracle_dd_dot(x.shape[1], _p(x), _p(y), _p(out))
+    return out
+
+
+def dd_div(a, b):
+    L = _krylov_sigs()
+    a, b = _f64(a), _f64(b)
+    out = np.zeros(2)
+    L.oracle_dd_div(_p(a), _p(b), _p(out))
+    return out
+
+
+def jacobi_minv(row_ptr, col_idx, a_hi):
+    L = _krylov_sigs()
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
+    a_hi = _f64(a_hi)
+    n = row_ptr.size - 1
+    out = np.zeros(n)
+    L.oracle_jacobi_minv(n, _p(row_ptr), _p(col_idx), _p(a_hi), _p(out))
+    return out
+
+
+def _solve(fn, row_ptr, col_idx, a, b, x0, precond, rtol, max_iter, log2w, history):
+    L = _krylov_sigs()
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
+    a, b = _f64(a), _f64(b)
+    n = row_ptr.size - 1
+    x = np.array(x0, dtype=np.float64, order="C", copy=True) if x0 is not None else np.zeros((2, n))
+    minv = jacobi_minv(row_ptr, col_idx, a[0]) if precond == "jacobi" else None
+    lw = None if log2w is None else np.ascontiguousarray(log2w, dtype=np.uint8)
+    hist = np.zeros(2 * (max_iter + 1)) if history else None
+    info = SolveInfo()
+    getattr(L, fn)(n, col_idx.size, _p(row_ptr), _p(col_idx), _p(lw), _p(a), _p(b), _p(x), _p(minv),
+                   float(rtol), int(max_iter), ctypes.byref(info), _p(hist))
+    out = {"status": info.status, "iters": info.iters, "restarts": info.restarts,
+           "rr_true": np.array(info.rr_true[:]), "bb": np.array(info.bb[:])}
+    if history:
+        out["history"] = hist[:2 * (info.iters + 1)].reshape(-1, 2)
+    return x, out
+
+
+def cg(row_ptr, col_idx, a, b, x0=None, precond="jacobi", rtol=1e-28, max_iter=10000, log2w=None,
+       history=False):
+    """DD preconditioned CG (oracle).  Returns (x, info dict)."""
+    return _solve("oracle_cg", row_ptr, col_idx, a, b, x0, precond, rtol, max_iter, log2w, history)
+
+
+def bicgstab(row_ptr, col_idx, a, b, x0=None, precond="jacobi", rtol=1e-28, max_iter=10000, log2w=None,
+             history=False):
+    """DD BiCGSTAB (oracle).  Returns (x, info dict)."""
+    return _solve("oracle_bicgstab", row_ptr, col_idx, a, b, x0, precond, rtol, max_iter, log2w, history)

@@ -33,9 +33,24 @@ class mp_csr(ctypes.Structure):
                 ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p)]
 
 
-class mp_width_policy(ctypes.Structure):
-    _fields_ = [("shift", ctypes.c_int32), ("max_log2w", ctypes.c_int32)]
+class mp_plan_opts(ctypes.Structure):
+    _fields_ = [("shift", ctypes.c_int32), ("max_log2w", ctypes.c_int32), ("tile_nnz", ctypes.c_int32)]
 
+
+class mp_solve_opts(ctypes.Structure):
+    _fields_ = [("precond", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("rtol", ctypes.c_double),
+                ("check_every", ctypes.c_int32), ("inner", ctypes.c_int32), ("inner_rtol", ctypes.c_double),
+                ("inner_max_iter", ctypes.c_int32), ("max_outer", ctypes.c_int32)]
+
+
+class mp_solve_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("outer_iters", ctypes.c_int32),
+                ("restarts", ctypes.c_int32), ("rr_true", ctypes.c_double * 2), ("bb", ctypes.c_double * 2),
+                ("relres", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
+PRECOND = {"none": 0, "jacobi": 1}
+INNER = {"fp64": 0, "fp32": 1}
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libmpsparse.so is not built (expected at %s); run __graft_entry__.build()" % LIB_PATH)
@@ -49,18 +64,24 @@ _SIGS = {
     "mp_last_error": ([], ctypes.c_char_p),
     "mp_version": ([], ctypes.c_char_p),
     "mp_csr_validate": ([_CSR, _P], ctypes.c_int),
-    "mp_plan_create": ([_CSR, ctypes.POINTER(mp_width_policy), _P, ctypes.POINTER(_P)], ctypes.c_int),
-    "mp_plan_create_explicit": ([_CSR, _P, _P, ctypes.POINTER(_P)], ctypes.c_int),
+    "mp_plan_create": ([_CSR, _I, _I, ctypes.POINTER(mp_plan_opts), _P, ctypes.POINTER(_P)], ctypes.c_int),
+    "mp_plan_create_explicit": ([_CSR, _I, _I, _P, _I, _P, ctypes.POINTER(_P)], ctypes.c_int),
     "mp_plan_autotune": ([_CSR, _I, _I, _P, _P, _P, _P, _P, _P, _I, _P, ctypes.POINTER(_P),
-                          ctypes.POINTER(mp_width_policy)], ctypes.c_int),
+                          ctypes.POINTER(mp_plan_opts)], ctypes.c_int),
     "mp_plan_destroy": ([_P], ctypes.c_int),
     "mp_plan_row_log2w": ([_P, _P], ctypes.c_int),
-    "mp_plan_info": ([_P, ctypes.POINTER(_I), ctypes.POINTER(_I)], ctypes.c_int),
+    "mp_plan_info": ([_P] + [ctypes.POINTER(_I)] * 5, ctypes.c_int),
 }
 for _name in ("mpspmv_csr_dd", "mpspmv_csr_td", "mpspmv_csr_qd"):
     _SIGS[_name] = ([_CSR, _P, _P, _P, _P, _P], ctypes.c_int)
 for _name in ("mpspmv_csr_dd_complex", "mpspmv_csr_td_complex", "mpspmv_csr_qd_complex"):
     _SIGS[_name] = ([_CSR, _P, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int)
+
+_SIGS["mpkrylov_workspace_bytes"] = ([_CSR, ctypes.POINTER(mp_solve_opts), ctypes.POINTER(ctypes.c_size_t)],
+                                     ctypes.c_int)
+for _name in ("mpkrylov_cg", "mpkrylov_bicgstab"):
+    _SIGS[_name] = ([_CSR, _P, _P, _P, ctypes.POINTER(mp_solve_opts), _P, _P, ctypes.c_size_t,
+                     ctypes.POINTER(mp_solve_info), _P], ctypes.c_int)
 
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -153,10 +174,9 @@ class Plan:
         return out
 
     def info(self):
-        n = ctypes.c_int32()
-        t = ctypes.c_int32()
-        _check(_lib.mp_plan_info(self._h, ctypes.byref(n), ctypes.byref(t)), "mp_plan_info")
-        return {"n_rows": n.value, "n_tiles": t.value}
+        v = [ctypes.c_int32() for _ in range(5)]
+        _check(_lib.mp_plan_info(self._h, *[ctypes.byref(x) for x in v]), "mp_plan_info")
+        return dict(zip(("n_rows", "n_tiles", "tile_nnz", "ncomp", "is_complex"), (x.value for x in v)))
 
 
 def _plan_handle(plan):
@@ -167,32 +187,35 @@ def mp_csr_validate(A, stream=None):
     _check(_lib.mp_csr_validate(ctypes.byref(A.c), _stream_ptr(stream)), "mp_csr_validate")
 
 
-def mp_plan_create(A, shift=0, max_log2w=6, stream=None):
+def mp_plan_create(A, ncomp, is_complex=False, shift=0, max_log2w=6, tile_nnz=0, stream=None):
+    """Plan for pattern A and variant (ncomp, is_complex); canonical order by default."""
     h = ctypes.c_void_p()
-    pol = mp_width_policy(shift, max_log2w)
-    _check(_lib.mp_plan_create(ctypes.byref(A.c), ctypes.byref(pol), _stream_ptr(stream), ctypes.byref(h)),
-           "mp_plan_create")
+    opts = mp_plan_opts(shift, max_log2w, tile_nnz)
+    _check(_lib.mp_plan_create(ctypes.byref(A.c), ncomp, int(bool(is_complex)), ctypes.byref(opts),
+                               _stream_ptr(stream), ctypes.byref(h)), "mp_plan_create")
     return Plan(h.value, A.n_rows)
 
 
-def mp_plan_create_explicit(A, log2w, stream=None):
+def mp_plan_create_explicit(A, ncomp, is_complex, log2w, tile_nnz=0, stream=None):
     lw = np.ascontiguousarray(log2w, dtype=np.uint8)
     if lw.size != A.n_rows:
         raise ValueError("log2w must have n_rows entries")
     h = ctypes.c_void_p()
-    _check(_lib.mp_plan_create_explicit(ctypes.byref(A.c), lw.ctypes.data_as(ctypes.c_void_p),
-                                        _stream_ptr(stream), ctypes.byref(h)), "mp_plan_create_explicit")
+    _check(_lib.mp_plan_create_explicit(ctypes.byref(A.c), ncomp, int(bool(is_complex)),
+                                        lw.ctypes.data_as(ctypes.c_void_p), tile_nnz, _stream_ptr(stream),
+                                        ctypes.byref(h)), "mp_plan_create_explicit")
     return Plan(h.value, A.n_rows)
 
 
 def mp_plan_autotune(A, ncomp, a_re, x_re, y_re, a_im=None, x_im=None, y_im=None, reps=3, stream=None):
+    """Autotuned plan; returns (Plan, {"shift", "max_log2w", "tile_nnz"})."""
     cplx = a_im is not None
     h = ctypes.c_void_p()
-    pol = mp_width_policy()
+    opts = mp_plan_opts()
     _check(_lib.mp_plan_autotune(ctypes.byref(A.c), ncomp, int(cplx), _ptr(a_re), _ptr(a_im), _ptr(x_re),
                                  _ptr(x_im), _ptr(y_re), _ptr(y_im), reps, _stream_ptr(stream), ctypes.byref(h),
-                                 ctypes.byref(pol)), "mp_plan_autotune")
-    return Plan(h.value, A.n_rows), (pol.shift, pol.max_log2w)
+                                 ctypes.byref(opts)), "mp_plan_autotune")
+    return Plan(h.value, A.n_rows), {"shift": opts.shift, "max_log2w": opts.max_log2w, "tile_nnz": opts.tile_nnz}
 
 
 def _spmv_real(name, K):
@@ -235,3 +258,60 @@ mpspmv_csr_qd_complex = _spmv_complex("mpspmv_csr_qd_complex", 4)
 
 SPMV = {(2, False): mpspmv_csr_dd, (3, False): mpspmv_csr_td, (4, False): mpspmv_csr_qd,
         (2, True): mpspmv_csr_dd_complex, (3, True): mpspmv_csr_td_complex, (4, True): mpspmv_csr_qd_complex}
+
+
+# ---------------------------------------------------------------------------------------
+# Krylov solvers
+# ---------------------------------------------------------------------------------------
+
+def _opts(precond="jacobi", rtol=1e-28, max_iter=10000, check_every=32, inner="fp64", inner_rtol=1e-8,
+          inner_max_iter=0, max_outer=50):
+    return mp_solve_opts(PRECOND[precond], int(max_iter), float(rtol), int(check_every), INNER[inner],
+                         float(inner_rtol), int(inner_max_iter), int(max_outer))
+
+
+def _info_dict(info):
+    return {"status": info.status, "iters": info.iters, "outer_iters": info.outer_iters,
+            "restarts": info.restarts, "rr_true": np.array(info.rr_true[:]), "bb": np.array(info.bb[:]),
+            "relres": info.relres, "seconds": info.seconds}
+
+
+def mpkrylov_workspace_bytes(A, **opts):
+    o = _opts(**opts)
+    nb = ctypes.c_size_t()
+    _check(_lib.mpkrylov_workspace_bytes(ctypes.byref(A.c), ctypes.byref(o), ctypes.byref(nb)),
+           "mpkrylov_workspace_bytes")
+    return nb.value
+
+
+def _workspace(A, ws, **opts):
+    import torch
+    need = mpkrylov_workspace_bytes(A, **opts)
+    if ws is None:
+        ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    return ws
+
+
+def _solver(name):
+    fn = getattr(_lib, name)
+
+    def call(A, a, b, x, plan=None, ws=None, stream=None, raise_on_failure=False, **opts):
+        _check_mp(a, 2, A.nnz, "a")
+        _check_mp(b, 2, A.n_rows, "b")
+        _check_mp(x, 2, A.n_rows, "x")
+        o = _opts(**opts)
+        ws = _workspace(A, ws, **opts)
+        info = mp_solve_info()
+        st = fn(ctypes.byref(A.c), _ptr(a), _ptr(b), _ptr(x), ctypes.byref(o), _plan_handle(plan), _ptr(ws),
+                ws.numel() * ws.element_size(), ctypes.byref(info), _stream_ptr(stream))
+        if st not in (MP_OK, -5, -6) or (raise_on_failure and st != MP_OK):
+            _check(st, name)
+        return _info_dict(info)
+
+    call.__name__ = name
+    call.__doc__ = "DD Krylov solve (C ABI %s); x is updated in place; returns the info record." % name
+    return call
+
+
+mpkrylov_cg = _solver("mpkrylov_cg")
+mpkrylov_bicgstab = _solver("mpkrylov_bicgstab")

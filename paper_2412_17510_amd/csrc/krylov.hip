@@ -1,0 +1,887 @@
+// krylov.hip -- double-double CG and BiCGSTAB on the device (Sec. 4.2 of Kouya,
+// arXiv 2412.17510: Krylov subspace methods built on the multi-component SpMV).
+//
+// Every step is a kernel on the caller's stream: the DD SpMV of spmv.hip, and fused
+// DD vector kernels that update the iterate vectors and form the partial sums of the
+// dot products in the same pass.  Dot products follow one fixed tree -- chunks of
+// 4096 elements, each summed by 256 lanes in the lane order of the SpMV (lane l takes
+// elements l, l+256, ...; halving fold), chunk sums combined pairwise -- so every
+// iterate is reproducible bit for bit.  Scalars live in a device state block; the
+// single-workgroup "final" kernels fold the chunk sums, form alpha / beta / omega with
+// DD division and raise a `done` flag (converged on the recurrence, breakdown, or
+// iteration limit) that makes every later kernel of the step a no-op.  The host reads
+// the state back every `check_every` iterations, confirms convergence with the true
+// residual b - A x, and restarts the recurrence from it when the confirmation fails.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "common.hpp"
+#include "mp_arith.hpp"
+#include "plan.hpp"
+
+namespace mpk {
+
+constexpr int kDotLanes = 256;
+constexpr int kDotChunk = 4096;
+constexpr int kMaxChunks = 2048;   // n <= 8,388,608
+
+enum : int32_t { RUN = 0, RECURRENCE_MET = 1, BROKE_DOWN = 2, ITER_LIMIT = 3, CONFIRMED = 4, RESTART = 5 };
+
+struct KState {
+    dd_t rho, rho_old, rr, bb, tol2, pq, alpha, beta, omega, rv, ss, ts, tt, rr_true;
+    int32_t done;
+    int32_t iters;
+    int32_t max_iter;
+    int32_t fresh;      // BiCGSTAB: the next step starts with p = r
+    int32_t half;       // BiCGSTAB: the half step met the tolerance
+    int32_t restarts;
+    int32_t pad[2];
+};
+
+__device__ __forceinline__ dd_t ldd(const double *__restrict__ v, int64_t n, int64_t i)
+{
+    dd_t r;
+    r.c[0] = v[i];
+    r.c[1] = v[n + i];
+    return r;
+}
+
+__device__ __forceinline__ void sdd(double *__restrict__ v, int64_t n, int64_t i, const dd_t &x)
+{
+    v[i] = x.c[0];
+    v[n + i] = x.c[1];
+}
+
+__device__ __forceinline__ dd_t dd_zero()
+{
+    dd_t r;
+    r.c[0] = 0.0;
+    r.c[1] = 0.0;
+    return r;
+}
+
+__device__ __forceinline__ dd_t dd_sub(const dd_t &a, const dd_t &b) { return dd_add(a, mp_neg(b)); }
+
+__device__ __forceinline__ bool dd_finite(const dd_t &a) { return isfinite(a.c[0]); }
+
+// Fold the lane sums of one chunk: lanes [0, used) hold values; acc[l] += acc[l+off]
+// for off = 128..1 when lane l+off holds a value.
+__device__ __forceinline__ dd_t chunk_fold(const dd_t &v, int used, dd_t *lds)
+{
+    const int t = threadIdx.x;
+    lds[t] = v;
+    __syncthreads();
+    for (int off = kDotLanes / 2; off >= 1; off >>= 1) {
+        if (t < off && t + off < used) lds[t] = dd_add(lds[t], lds[t + off]);
+        __syncthreads();
+    }
+    const dd_t r = lds[0];
+    __syncthreads();
+    return r;
+}
+
+// Pairwise tree over m chunk sums (single workgroup): level s combines node i*2s
+// with node i*2s + s when that node exists; an unpaired node passes up unchanged.
+__device__ __forceinline__ dd_t pair_tree(const dd_t *__restrict__ part, int m, dd_t *P)
+{
+    const int t = threadIdx.x;
+    for (int i = t; i < m; i += kDotLanes) P[i] = part[i];
+    __syncthreads();
+    for (int s = 1; s < m; s <<= 1) {
+        for (int i = t; (int64_t)i * 2 * s + s < m; i += kDotLanes) P[i * 2 * s] = dd_add(P[i * 2 * s], P[i * 2 * s + s]);
+        __syncthreads();
+    }
+    const dd_t r = m > 0 ? P[0] : dd_zero();
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ int chunk_used(int64_t n, int c)
+{
+    const int64_t left = n - (int64_t)c * kDotChunk;
+    return left < kDotLanes ? (int)left : kDotLanes;
+}
+
+// ---------------------------------------------------------------------------
+// generic kernels
+// ---------------------------------------------------------------------------
+
+// chunk sums of dot(x1, y1) and (optionally) dot(x2, y2); one workgroup per chunk
+__global__ __launch_bounds__(256) void k_dot2(int64_t n, const double *__restrict__ x1, const double *__restrict__ y1,
+                                              const double *__restrict__ x2, const double *__restrict__ y2,
+                                              dd_t *__restrict__ part1, dd_t *__restrict__ part2,
+                                              const KState *__restrict__ st)
+{
+    __shared__ dd_t lds[kDotLanes];
+    if (st && st->done != RUN) return;
+    const int c = blockIdx.x;
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)c * kDotChunk;
+    const int64_t end = (n - base) < kDotChunk ? n : base + kDotChunk;
+    const int used = chunk_used(n, c);
+    dd_t a1 = dd_zero(), a2 = dd_zero();
+    if (t < used) {
+        int64_t k = base + t;
+        a1 = dd_mul(ldd(x1, n, k), ldd(y1, n, k));
+        if (x2) a2 = dd_mul(ldd(x2, n, k), ldd(y2, n, k));
+        for (k += kDotLanes; k < end; k += kDotLanes) {
+            a1 = dd_add(a1, dd_mul(ldd(x1, n, k), ldd(y1, n, k)));
+            if (x2) a2 = dd_add(a2, dd_mul(ldd(x2, n, k), ldd(y2, n, k)));
+        }
+    }
+    const dd_t s1 = chunk_fold(a1, used, lds);
+    if (t == 0) part1[c] = s1;
+    if (x2) {
+        const dd_t s2 = chunk_fold(a2, used, lds);
+        if (t == 0) part2[c] = s2;
+    }
+}
+
+// r = b - q
+__global__ __launch_bounds__(256) void k_residual(int64_t n, const double *__restrict__ b,
+                                                  const double *__restrict__ q, double *__restrict__ r)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        sdd(r, n, i, dd_sub(ldd(b, n, i), ldd(q, n, i)));
+}
+
+// z = M^-1 r (Jacobi: DD times the binary64 inverse diagonal, Alg. 3; or a copy)
+__global__ __launch_bounds__(256) void k_precond(int64_t n, const double *__restrict__ minv,
+                                                 const double *__restrict__ r, double *__restrict__ z,
+                                                 const KState *__restrict__ st)
+{
+    if (st && st->done != RUN) return;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        sdd(z, n, i, minv ? dd_mul_d(ldd(r, n, i), minv[i]) : ldd(r, n, i));
+}
+
+__global__ __launch_bounds__(256) void k_copy(int64_t n2, const double *__restrict__ src, double *__restrict__ dst)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n2; i += (int64_t)gridDim.x * 256) dst[i] = src[i];
+}
+
+// Jacobi inverse diagonal fl(1 / hi(a_ii)); 1 where the row has no diagonal entry
+__global__ __launch_bounds__(256) void k_jacobi_minv(int64_t n, const int32_t *__restrict__ rp,
+                                                     const int32_t *__restrict__ ci, const double *__restrict__ a_hi,
+                                                     double *__restrict__ minv)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        double m = 1.0;
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+            if (ci[k] == i) m = 1.0 / a_hi[k];
+        minv[i] = m;
+    }
+}
+
+// confirmation of a recurrence convergence: rr_true from chunk sums
+__global__ __launch_bounds__(256) void k_confirm(const dd_t *__restrict__ part, int m, KState *__restrict__ st)
+{
+    __shared__ dd_t P[kMaxChunks];
+    const dd_t rr = pair_tree(part, m, P);
+    if (threadIdx.x == 0) {
+        st->rr_true = rr;
+        if (dd_le(rr, st->tol2)) {
+            st->done = CONFIRMED;
+        } else {
+            st->rr = rr;
+            st->restarts += 1;
+            st->done = RESTART;
+        }
+    }
+}
+
+// exit record: rr_true of the returned x
+__global__ __launch_bounds__(256) void k_exit_rr(const dd_t *__restrict__ part, int m, KState *__restrict__ st)
+{
+    __shared__ dd_t P[kMaxChunks];
+    const dd_t rr = pair_tree(part, m, P);
+    if (threadIdx.x == 0) st->rr_true = rr;
+}
+
+// ---------------------------------------------------------------------------
+// CG
+// ---------------------------------------------------------------------------
+
+// bb, rho = (r, z), rr = (r, r) of the start vectors; tolerance; first test
+__global__ __launch_bounds__(256) void k_cg_init(const dd_t *__restrict__ pbb, const dd_t *__restrict__ prz,
+                                                 const dd_t *__restrict__ prr, int m, double rtol2, int32_t max_iter,
+                                                 KState *__restrict__ st)
+{
+    __shared__ dd_t P[kMaxChunks];
+    const dd_t bb = pair_tree(pbb, m, P);
+    const dd_t rz = pair_tree(prz, m, P);
+    const dd_t rr = pair_tree(prr, m, P);
+    if (threadIdx.x == 0) {
+        st->bb = bb;
+        st->tol2 = dd_mul_d(bb, rtol2);
+        st->rho = rz;
+        st->rr = rr;
+        st->iters = 0;
+        st->max_iter = max_iter;
+        st->restarts = 0;
+        st->done = dd_le(rr, st->tol2) ? RECURRENCE_MET : (max_iter <= 0 ? ITER_LIMIT : RUN);
+    }
+}
+
+// after a restart from the true residual: rho = (r, z)
+__global__ __launch_bounds__(256) void k_cg_restart(const dd_t *__restrict__ prz, int m, KState *__restrict__ st)
+{
+    __shared__ dd_t P[kMaxChunks];
+    const dd_t rz = pair_tree(prz, m, P);
+    if (threadIdx.x == 0) {
+        st->rho = rz;
+        st->done = st->iters >= st->max_iter ? ITER_LIMIT : RUN;
+    }
+}
+
+// alpha = rho / (p, q); breakdown unless (p, q) > 0
+__global__ __launch_bounds__(256) void k_cg_alpha(const dd_t *__restrict__ ppq, int m, KState *__restrict__ st)
+{
+    __shared__ dd_t P[kMaxChunks];
+    if (st->done != RUN) return;
+    const dd_t pq = pair_tree(ppq, m, P);
+    if (threadIdx.x == 0) {
+        st->pq = pq;
+        if (!(pq.c[0] > 0.0) || !dd_finite(pq))
+            st->done = BROKE_DOWN;
+        else
+            st->alpha = dd_div(st->rho, pq);
+    }
+}
+
+// x += alpha p; r -= alpha q; z = M^-1 r; chunk sums of (r, z) and (r, r)
+__global__ __launch_bounds__(256) void k_cg_update(int64_t n, double *__restrict__ x, double *__restrict__ r,
+                                                   double *__restrict__ z, const double *__restrict__ p,
+                                                   const double *__restrict__ q, const double *__restrict__ minv,
+                                                   dd_t *__restrict__ prz, dd_t *__restrict__ prr,
+                                                   const KState *__restrict__ st)
+{
+    __shared__ dd_t lds[kDotLanes];
+    if (st->done != RUN) return;
+    const dd_t alpha = st->alpha;
+    const int c = blockIdx.x;
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)c * kDotChunk;
+    const int64_t end = (n - base) < kDotChunk ? n : base + kDotChunk;
+    const int used = chunk_used(n, c);
+    dd_t arz = dd_zero(), arr = dd_zero();
+    bool first = true;
+    for (int64_t k = base + t; k < end; k += kDotLanes) {
+        sdd(x, n, k, dd_add(ldd(x, n, k), dd_mul(alpha, ldd(p, n, k))));
+        const dd_t rk = dd_sub(ldd(r, n, k), dd_mul(alpha, ldd(q, n, k)));
+        sdd(r, n, k, rk);
+        const dd_t zk = minv ? dd_mul_d(rk, minv[k]) : rk;
+        sdd(z, n, k, zk);
+        if (first) {
+            arz = dd_mul(rk, zk);
+            arr = dd_mul(rk, rk);
+            first = false;
+        } else {
+            arz = dd_add(arz, dd_mul(rk, zk));
+            arr = dd_add(arr, dd_mul(rk, rk));
+        }
+    }
+    const dd_t s1 = chunk_fold(arz, used, lds);
+    const dd_t s2 = chunk_fold(arr, used, lds);
+    if (t == 0) {
+        prz[c] = s1;
+        prr[c] = s2;
+    }
+}
+
+// rho_new = (r, z), rr = (r, r); beta = rho_new / rho; convergence / limit tests
+__global__ __launch_bounds__(256) void k_cg_beta(const dd_t *__restrict__ prz, const dd_t *__restrict__ prr, int m,
+                                                 KState *__restrict__ st)
+{
+    __shared__ dd_t P[kMaxChunks];
+    if (st->done != RUN) return;
+    const dd_t rz = pair_tree(prz, m, P);
+    const dd_t rr = pair_tree(prr, m, P);
+    if (threadIdx.x == 0) {
+        st->iters += 1;
+        st->rr = rr;
+        if (!dd_finite(rr) || !dd_finite(rz)) {
+            st->done = BROKE_DOWN;
+            return;
+        }
+        st->beta = dd_div(rz, st->rho);
+        st->rho = rz;
+        if (dd_le(rr, st->tol2))
+            st->done = RECURRENCE_MET;
+        else if (st->iters >= st->max_iter)
+            st->done = ITER_LIMIT;
+    }
+}
+
+// p = z + beta p
+__global__ __launch_bounds__(256) void k_cg_p(int64_t n, const double *__restrict__ z, double *__restrict__ p,
+                                              const KState *__restrict__ st)
+{
+    if (st->done != RUN) return;
+    const dd_t beta = st->beta;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        sdd(p, n, i, dd_add(ldd(z, n, i), dd_mul(beta, ldd(p, n, i))));
+}
+
+// ---------------------------------------------------------------------------
+// BiCGSTAB
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_bi_init(const dd_t *__restrict__ pbb, const dd_t *__restrict__ prr, int m,
+                                                 double rtol2, int32_t max_iter, KState *__restrict__ st)
+{
+    __shared__ dd_t P[kMaxChunks];
+    const dd_t bb = pair_tree(pbb, m, P);
+    const dd_t rr = pair_tree(prr, m, P);
+    if (threadIdx.x == 0) {
+        dd_t one;
+        one.c[0] = 1.0;
+        one.c[1] = 0.0;
+        st->bb = bb;
+        st->tol2 = dd_mul_d(bb, rtol2);
+        st->rr = rr;
+        st->rho_old = one;
+        st->alpha = one;
+        st->omega = one;
+        st->iters = 0;
+        st->max_iter = max_iter;
+        st->restarts = 0;
+        st->fresh = 1;
+        st->half = 0;
+        st->done = dd_le(rr, st->tol2) ? RECURRENCE_MET : (max_iter <= 0 ? ITER_LIMIT : RUN);
+    }
+}
+
+// after a restart: the shadow residual is the new residual, next step starts fresh
+__global__ __launch_bounds__(256) void k_bi_restart(KState *__restrict__ st)
+{
+    if (threadIdx.x == 0) {
+        st->fresh = 1;
+        st->done = st->iters >= st->max_iter ? ITER_LIMIT : RUN;
+    }
+}
+
+// rho = (rh, r); beta = (rho / rho_old)(alpha / omega) unless the step is fresh
+__global__ __launch_bounds__(256) void k_bi_rho(const dd_t *__restrict__ part, int m, KState *__restrict__ st)
+{
+    __shared__ dd_t P[kMaxChunks];
+    if (st->done != RUN) return;
+    const dd_t rho = pair_tree(part, m, P);
+    if (threadIdx.x == 0) {
+        st->rho = rho;
+        if (rho.c[0] == 0.0 || !dd_finite(rho)) {
+            st->done = BROKE_DOWN;
+            return;
+        }
+        if (!st->fresh) st->beta = dd_mul(dd_div(rho, st->rho_old), dd_div(st->alpha, st->omega));
+    }
+}
+
+// p = r (fresh) or p = r + beta (p - omega v)
+__global__ __launch_bounds__(256) void k_bi_p(int64_t n, const double *__restrict__ r, double *__restrict__ p,
+                                              const double *__restrict__ v, const KState *__restrict__ st)
+{
+    if (st->done != RUN) return;
+    const bool fresh = st->fresh != 0;
+    const dd_t beta = st->beta, omega = st->omega;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        if (fresh) {
+            sdd(p, n, i, ldd(r, n, i));
+        } else {
+            const dd_t pv = dd_sub(ldd(p, n, i), dd_mul(omega, ldd(v, n, i)));
+            sdd(p, n, i, dd_add(ldd(r, n, i), dd_mul(beta, pv)));
+        }
+    }
+}
+
+// alpha = rho / (rh, v)
+__global__ __launch_bounds__(256) void k_bi_alpha(const dd_t *__restrict__ part, int m, KState *__restrict__ st)
+{
+    __shared__ dd_t P[kMaxChunks];
+    if (st->done != RUN) return;
+    const dd_t rv = pair_tree(part, m, P);
+    if (threadIdx.x == 0) {
+        st->fresh = 0;
+        st->rv = rv;
+        if (rv.c[0] == 0.0 || !dd_finite(rv)) {
+            st->done = BROKE_DOWN;
+            return;
+        }
+        st->alpha = dd_div(st->rho, rv);
+    }
+}
+
+// s = r - alpha v; chunk sums of (s, s)
+__global__ __launch_bounds__(256) void k_bi_s(int64_t n, const double *__restrict__ r, const double *__restrict__ v,
+                                              double *__restrict__ s, dd_t *__restrict__ pss,
+                                              const KState *__restrict__ st)
+{
+    __shared__ dd_t lds[kDotLanes];
+    if (st->done != RUN) return;
+    const dd_t alpha = st->alpha;
+    const int c = blockIdx.x;
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)c * kDotChunk;
+    const int64_t end = (n - base) < kDotChunk ? n : base + kDotChunk;
+    const int used = chunk_used(n, c);
+    dd_t acc = dd_zero();
+    bool first = true;
+    for (int64_t k = base + t; k < end; k += kDotLanes) {
+        const dd_t sk = dd_sub(ldd(r, n, k), dd_mul(alpha, ldd(v, n, k)));
+        sdd(s, n, k, sk);
+        acc = first ? dd_mul(sk, sk) : dd_add(acc, dd_mul(sk, sk));
+        first = false;
+    }
+    const dd_t sum = chunk_fold(acc, used, lds);
+    if (t == 0) pss[c] = sum;
+}
+
+// ss = (s, s); one step counted; half-step test
+__global__ __launch_bounds__(256) void k_bi_ss(const dd_t *__restrict__ part, int m, KState *__restrict__ st)
+{
+    __shared__ dd_t P[kMaxChunks];
+    if (st->done != RUN) return;
+    const dd_t ss = pair_tree(part, m, P);
+    if (threadIdx.x == 0) {
+        st->ss = ss;
+        st->iters += 1;
+        st->half = dd_le(ss, st->tol2) ? 1 : 0;
+    }
+}
+
+// half step met the tolerance: x += alpha ph; r = s
+__global__ __launch_bounds__(256) void k_bi_half(int64_t n, double *__restrict__ x, double *__restrict__ r,
+                                                 const double *__restrict__ ph, const double *__restrict__ s,
+                                                 const KState *__restrict__ st)
+{
+    if (st->done != RUN || !st->half) return;
+    const dd_t alpha = st->alpha;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        sdd(x, n, i, dd_add(ldd(x, n, i), dd_mul(alpha, ldd(ph, n, i))));
+        sdd(r, n, i, ldd(s, n, i));
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bi_half_final(KState *__restrict__ st)
+{
+    if (threadIdx.x != 0 || st->done != RUN || !st->half) return;
+    dd_t one;
+    one.c[0] = 1.0;
+    one.c[1] = 0.0;
+    st->rr = st->ss;
+    st->rho_old = st->rho;
+    st->omega = one;
+    st->fresh = 1;
+    st->half = 0;
+    st->done = RECURRENCE_MET;
+}
+
+// omega = (t, s) / (t, t)
+__global__ __launch_bounds__(256) void k_bi_omega(const dd_t *__restrict__ pts, const dd_t *__restrict__ ptt, int m,
+                                                  KState *__restrict__ st)
+{
+    __shared__ dd_t P[kMaxChunks];
+    if (st->done != RUN) return;
+    const dd_t ts = pair_tree(pts, m, P);
+    const dd_t tt = pair_tree(ptt, m, P);
+    if (threadIdx.x == 0) {
+        st->ts = ts;
+        st->tt = tt;
+        if (tt.c[0] == 0.0 || !dd_finite(tt)) {
+            st->done = BROKE_DOWN;
+            return;
+        }
+        st->omega = dd_div(ts, tt);
+    }
+}
+
+// x = (x + alpha ph) + omega sh; r = s - omega t; chunk sums of (r, r)
+__global__ __launch_bounds__(256) void k_bi_xr(int64_t n, double *__restrict__ x, double *__restrict__ r,
+                                               const double *__restrict__ ph, const double *__restrict__ sh,
+                                               const double *__restrict__ s, const double *__restrict__ tv,
+                                               dd_t *__restrict__ prr, const KState *__restrict__ st)
+{
+    __shared__ dd_t lds[kDotLanes];
+    if (st->done != RUN) return;
+    const dd_t alpha = st->alpha, omega = st->omega;
+    const int c = blockIdx.x;
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)c * kDotChunk;
+    const int64_t end = (n - base) < kDotChunk ? n : base + kDotChunk;
+    const int used = chunk_used(n, c);
+    dd_t acc = dd_zero();
+    bool first = true;
+    for (int64_t k = base + t; k < end; k += kDotLanes) {
+        const dd_t xv = dd_add(ldd(x, n, k), dd_mul(alpha, ldd(ph, n, k)));
+        sdd(x, n, k, dd_add(xv, dd_mul(omega, ldd(sh, n, k))));
+        const dd_t rk = dd_sub(ldd(s, n, k), dd_mul(omega, ldd(tv, n, k)));
+        sdd(r, n, k, rk);
+        acc = first ? dd_mul(rk, rk) : dd_add(acc, dd_mul(rk, rk));
+        first = false;
+    }
+    const dd_t sum = chunk_fold(acc, used, lds);
+    if (t == 0) prr[c] = sum;
+}
+
+// rr = (r, r); breakdown on omega = 0; convergence / limit tests
+__global__ __launch_bounds__(256) void k_bi_rr(const dd_t *__restrict__ part, int m, KState *__restrict__ st)
+{
+    __shared__ dd_t P[kMaxChunks];
+    if (st->done != RUN) return;
+    const dd_t rr = pair_tree(part, m, P);
+    if (threadIdx.x == 0) {
+        st->rr = rr;
+        if (!dd_finite(rr) || st->omega.c[0] == 0.0) {
+            st->done = BROKE_DOWN;
+            return;
+        }
+        st->rho_old = st->rho;
+        if (dd_le(rr, st->tol2))
+            st->done = RECURRENCE_MET;
+        else if (st->iters >= st->max_iter)
+            st->done = ITER_LIMIT;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host driver
+// ---------------------------------------------------------------------------
+
+struct Workspace {
+    KState *st;
+    double *minv;
+    double *v[9];
+    dd_t *part[3];
+};
+
+inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t workspace_bytes(int64_t n)
+{
+    size_t b = align256(sizeof(KState));
+    b += align256(sizeof(double) * (size_t)n);
+    b += 9 * align256(sizeof(double) * 2 * (size_t)n);
+    b += 3 * align256(sizeof(dd_t) * kMaxChunks);
+    return b;
+}
+
+Workspace carve(void *ws, int64_t n)
+{
+    Workspace w;
+    char *p = static_cast<char *>(ws);
+    w.st = reinterpret_cast<KState *>(p);
+    p += align256(sizeof(KState));
+    w.minv = reinterpret_cast<double *>(p);
+    p += align256(sizeof(double) * (size_t)n);
+    for (int i = 0; i < 9; ++i) {
+        w.v[i] = reinterpret_cast<double *>(p);
+        p += align256(sizeof(double) * 2 * (size_t)n);
+    }
+    for (int i = 0; i < 3; ++i) {
+        w.part[i] = reinterpret_cast<dd_t *>(p);
+        p += align256(sizeof(dd_t) * kMaxChunks);
+    }
+    return w;
+}
+
+bool host_dd_le(const double *a, const double *b) { return (a[0] < b[0]) || (a[0] == b[0] && a[1] <= b[1]); }
+
+mp_status spmv_dispatch(int K, bool cplx, const mp_csr *A, const double *a_re, const double *a_im,
+                        const double *x_re, const double *x_im, double *y_re, double *y_im, const mp_plan *plan,
+                        hipStream_t s);
+
+struct Solver {
+    const mp_csr *A;
+    const double *a;
+    const mp_plan *plan;
+    hipStream_t s;
+    int64_t n;
+    int m;            // chunks
+    unsigned vblocks;  // blocks of the element-wise kernels
+    Workspace w;
+
+    mp_status spmv(const double *xin, double *yout)
+    {
+        return spmv_dispatch(2, false, A, a, nullptr, xin, nullptr, yout, nullptr, plan, s);
+    }
+    mp_status launched()
+    {
+        MP_HIP_TRY(hipGetLastError());
+        return MP_OK;
+    }
+    mp_status dot2(const double *x1, const double *y1, const double *x2, const double *y2, dd_t *p1, dd_t *p2,
+                   const KState *guard)
+    {
+        hipLaunchKernelGGL(k_dot2, dim3(m), dim3(256), 0, s, n, x1, y1, x2, y2, p1, p2, guard);
+        return launched();
+    }
+    // r = b - A x (q scratch)
+    mp_status residual(const double *b, const double *x, double *q, double *r)
+    {
+        mp_status st = spmv(x, q);
+        if (st != MP_OK) return st;
+        hipLaunchKernelGGL(k_residual, dim3(vblocks), dim3(256), 0, s, n, b, q, r);
+        return launched();
+    }
+    mp_status read_state(KState *h)
+    {
+        MP_HIP_TRY(hipMemcpyAsync(h, w.st, sizeof(KState), hipMemcpyDeviceToHost, s));
+        MP_HIP_TRY(hipStreamSynchronize(s));
+        return MP_OK;
+    }
+    // true residual of x into r, rr_true into the state (confirm = test against tol2)
+    mp_status true_residual(const double *b, const double *x, double *q, double *r, bool confirm)
+    {
+        mp_status st = residual(b, x, q, r);
+        if (st == MP_OK) st = dot2(r, r, nullptr, nullptr, w.part[0], nullptr, nullptr);
+        if (st != MP_OK) return st;
+        if (confirm)
+            hipLaunchKernelGGL(k_confirm, dim3(1), dim3(256), 0, s, w.part[0], m, w.st);
+        else
+            hipLaunchKernelGGL(k_exit_rr, dim3(1), dim3(256), 0, s, w.part[0], m, w.st);
+        return launched();
+    }
+};
+
+mp_status check_solver_args(const char *name, const mp_csr *A, const double *a, const double *b, const double *x,
+                            const mp_solve_opts *opts, const mp_plan *plan, void *ws, size_t ws_bytes,
+                            mp_solve_info *info)
+{
+    mp_status st = check_csr(A);
+    if (st != MP_OK) return st;
+    if (!opts || !info) return fail(MP_ERR_INVALID_ARG, "%s: opts or info is NULL", name);
+    if (A->n_rows != A->n_cols) return fail(MP_ERR_INVALID_ARG, "%s: matrix must be square", name);
+    if (A->n_rows > 0 && (!b || !x || !ws)) return fail(MP_ERR_INVALID_ARG, "%s: b, x or workspace is NULL", name);
+    if (A->nnz > 0 && !a) return fail(MP_ERR_INVALID_ARG, "%s: a is NULL", name);
+    if ((int64_t)A->n_rows > (int64_t)kMaxChunks * kDotChunk)
+        return fail(MP_ERR_UNSUPPORTED, "%s: n = %d exceeds the solver limit %d", name, A->n_rows,
+                    kMaxChunks * kDotChunk);
+    if (ws_bytes < workspace_bytes(A->n_rows))
+        return fail(MP_ERR_NO_MEMORY, "%s: workspace of %zu bytes, %zu needed", name, ws_bytes,
+                    workspace_bytes(A->n_rows));
+    if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(MP_ERR_INVALID_ARG, "%s: workspace must be 256-byte aligned", name);
+    if (opts->precond != MP_PRECOND_NONE && opts->precond != MP_PRECOND_JACOBI)
+        return fail(MP_ERR_INVALID_ARG, "%s: unknown preconditioner %d", name, opts->precond);
+    if (!(opts->rtol >= 0.0)) return fail(MP_ERR_INVALID_ARG, "%s: rtol must be >= 0", name);
+    if (plan && (plan->ncomp != 2 || plan->cplx || plan->n_rows != A->n_rows || plan->nnz != A->nnz))
+        return fail(MP_ERR_INVALID_ARG, "%s: plan is not a DD real plan of this matrix", name);
+    const size_t vb = sizeof(double) * 2 * (size_t)A->n_rows;
+    if (overlaps(x, vb, b, vb) || overlaps(x, vb, a, sizeof(double) * 2 * (size_t)A->nnz) ||
+        overlaps(x, vb, ws, ws_bytes) || overlaps(b, vb, ws, ws_bytes))
+        return fail(MP_ERR_ALIAS, "%s: x overlaps b, a or the workspace", name);
+    return MP_OK;
+}
+
+void fill_info(const KState &h, int status, double secs, mp_solve_info *info)
+{
+    std::memset(info, 0, sizeof(*info));
+    info->status = status;
+    info->iters = h.iters;
+    info->restarts = h.restarts;
+    info->rr_true[0] = h.rr_true.c[0];
+    info->rr_true[1] = h.rr_true.c[1];
+    info->bb[0] = h.bb.c[0];
+    info->bb[1] = h.bb.c[1];
+    info->relres = h.bb.c[0] > 0 ? std::sqrt(h.rr_true.c[0] / h.bb.c[0]) : std::sqrt(h.rr_true.c[0]);
+    info->seconds = secs;
+}
+
+mp_status run_cg(Solver &S, const double *b, double *x, const mp_solve_opts *o, mp_solve_info *info)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    const int64_t n = S.n;
+    const int m = S.m;
+    double *r = S.w.v[0], *z = S.w.v[1], *p = S.w.v[2], *q = S.w.v[3];
+    const double *minv = o->precond == MP_PRECOND_JACOBI ? S.w.minv : nullptr;
+    const int every = o->check_every > 0 ? o->check_every : 32;
+    mp_status st = MP_OK;
+    KState h;
+    std::memset(&h, 0, sizeof(h));
+    MP_HIP_TRY(hipMemsetAsync(S.w.st, 0, sizeof(KState), S.s));
+    if (minv) {
+        hipLaunchKernelGGL(k_jacobi_minv, dim3(S.vblocks), dim3(256), 0, S.s, n, S.A->row_ptr, S.A->col_idx, S.a,
+                           S.w.minv);
+        if ((st = S.launched()) != MP_OK) return st;
+    }
+    // start: r = b - A x, z = M^-1 r, p = z, bb, rho, rr
+    if ((st = S.residual(b, x, q, r)) != MP_OK) return st;
+    hipLaunchKernelGGL(k_precond, dim3(S.vblocks), dim3(256), 0, S.s, n, minv, r, z, nullptr);
+    hipLaunchKernelGGL(k_copy, dim3(S.vblocks), dim3(256), 0, S.s, 2 * n, z, p);
+    if ((st = S.launched()) != MP_OK) return st;
+    if ((st = S.dot2(b, b, r, z, S.w.part[0], S.w.part[1], nullptr)) != MP_OK) return st;
+    if ((st = S.dot2(r, r, nullptr, nullptr, S.w.part[2], nullptr, nullptr)) != MP_OK) return st;
+    hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(256), 0, S.s, S.w.part[0], S.w.part[1], S.w.part[2], m,
+                       o->rtol * o->rtol, o->max_iter, S.w.st);
+    if ((st = S.launched()) != MP_OK) return st;
+    int status = MP_ERR_NOT_CONVERGED;
+    for (;;) {
+        if ((st = S.read_state(&h)) != MP_OK) return st;
+        if (h.done == RUN) {
+            for (int it = 0; it < every; ++it) {
+                if ((st = S.spmv(p, q)) != MP_OK) return st;
+                if ((st = S.dot2(p, q, nullptr, nullptr, S.w.part[0], nullptr, S.w.st)) != MP_OK) return st;
+                hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(256), 0, S.s, S.w.part[0], m, S.w.st);
+                hipLaunchKernelGGL(k_cg_update, dim3(m), dim3(256), 0, S.s, n, x, r, z, p, q, minv, S.w.part[1],
+                                   S.w.part[2], S.w.st);
+                hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(256), 0, S.s, S.w.part[1], S.w.part[2], m, S.w.st);
+                hipLaunchKernelGGL(k_cg_p, dim3(S.vblocks), dim3(256), 0, S.s, n, z, p, S.w.st);
+                if ((st = S.launched()) != MP_OK) return st;
+            }
+            continue;
+        }
+        if (h.done == RECURRENCE_MET) {
+            if ((st = S.true_residual(b, x, q, r, true)) != MP_OK) return st;
+            continue;
+        }
+        if (h.done == RESTART) {
+            hipLaunchKernelGGL(k_precond, dim3(S.vblocks), dim3(256), 0, S.s, n, minv, r, z, nullptr);
+            hipLaunchKernelGGL(k_copy, dim3(S.vblocks), dim3(256), 0, S.s, 2 * n, z, p);
+            if ((st = S.launched()) != MP_OK) return st;
+            if ((st = S.dot2(r, z, nullptr, nullptr, S.w.part[1], nullptr, nullptr)) != MP_OK) return st;
+            hipLaunchKernelGGL(k_cg_restart, dim3(1), dim3(256), 0, S.s, S.w.part[1], m, S.w.st);
+            if ((st = S.launched()) != MP_OK) return st;
+            continue;
+        }
+        status = h.done == CONFIRMED ? MP_OK : (h.done == BROKE_DOWN ? MP_ERR_BREAKDOWN : MP_ERR_NOT_CONVERGED);
+        break;
+    }
+    if ((st = S.true_residual(b, x, q, r, false)) != MP_OK) return st;
+    if ((st = S.read_state(&h)) != MP_OK) return st;
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    fill_info(h, status, secs, info);
+    if (status == MP_ERR_NOT_CONVERGED) return fail(MP_ERR_NOT_CONVERGED, "mpkrylov_cg: no convergence in %d iterations", h.iters);
+    if (status == MP_ERR_BREAKDOWN) return fail(MP_ERR_BREAKDOWN, "mpkrylov_cg: breakdown at iteration %d", h.iters);
+    return MP_OK;
+}
+
+mp_status run_bicgstab(Solver &S, const double *b, double *x, const mp_solve_opts *o, mp_solve_info *info)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    const int64_t n = S.n;
+    const int m = S.m;
+    double *r = S.w.v[0], *rh = S.w.v[1], *p = S.w.v[2], *v = S.w.v[3], *ph = S.w.v[4], *s = S.w.v[5];
+    double *sh = S.w.v[6], *tv = S.w.v[7], *q = S.w.v[8];
+    const double *minv = o->precond == MP_PRECOND_JACOBI ? S.w.minv : nullptr;
+    const int every = o->check_every > 0 ? o->check_every : 32;
+    mp_status st = MP_OK;
+    KState h;
+    std::memset(&h, 0, sizeof(h));
+    MP_HIP_TRY(hipMemsetAsync(S.w.st, 0, sizeof(KState), S.s));
+    if (minv) {
+        hipLaunchKernelGGL(k_jacobi_minv, dim3(S.vblocks), dim3(256), 0, S.s, n, S.A->row_ptr, S.A->col_idx, S.a,
+                           S.w.minv);
+        if ((st = S.launched()) != MP_OK) return st;
+    }
+    if ((st = S.residual(b, x, q, r)) != MP_OK) return st;
+    hipLaunchKernelGGL(k_copy, dim3(S.vblocks), dim3(256), 0, S.s, 2 * n, r, rh);
+    if ((st = S.launched()) != MP_OK) return st;
+    if ((st = S.dot2(b, b, r, r, S.w.part[0], S.w.part[1], nullptr)) != MP_OK) return st;
+    hipLaunchKernelGGL(k_bi_init, dim3(1), dim3(256), 0, S.s, S.w.part[0], S.w.part[1], m, o->rtol * o->rtol,
+                       o->max_iter, S.w.st);
+    if ((st = S.launched()) != MP_OK) return st;
+    int status = MP_ERR_NOT_CONVERGED;
+    for (;;) {
+        if ((st = S.read_state(&h)) != MP_OK) return st;
+        if (h.done == RUN) {
+            for (int it = 0; it < every; ++it) {
+                if ((st = S.dot2(rh, r, nullptr, nullptr, S.w.part[0], nullptr, S.w.st)) != MP_OK) return st;
+                hipLaunchKernelGGL(k_bi_rho, dim3(1), dim3(256), 0, S.s, S.w.part[0], m, S.w.st);
+                hipLaunchKernelGGL(k_bi_p, dim3(S.vblocks), dim3(256), 0, S.s, n, r, p, v, S.w.st);
+                hipLaunchKernelGGL(k_precond, dim3(S.vblocks), dim3(256), 0, S.s, n, minv, p, ph, S.w.st);
+                if ((st = S.launched()) != MP_OK) return st;
+                if ((st = S.spmv(ph, v)) != MP_OK) return st;
+                if ((st = S.dot2(rh, v, nullptr, nullptr, S.w.part[0], nullptr, S.w.st)) != MP_OK) return st;
+                hipLaunchKernelGGL(k_bi_alpha, dim3(1), dim3(256), 0, S.s, S.w.part[0], m, S.w.st);
+                hipLaunchKernelGGL(k_bi_s, dim3(m), dim3(256), 0, S.s, n, r, v, s, S.w.part[0], S.w.st);
+                hipLaunchKernelGGL(k_bi_ss, dim3(1), dim3(256), 0, S.s, S.w.part[0], m, S.w.st);
+                hipLaunchKernelGGL(k_bi_half, dim3(S.vblocks), dim3(256), 0, S.s, n, x, r, ph, s, S.w.st);
+                hipLaunchKernelGGL(k_bi_half_final, dim3(1), dim3(64), 0, S.s, S.w.st);
+                hipLaunchKernelGGL(k_precond, dim3(S.vblocks), dim3(256), 0, S.s, n, minv, s, sh, S.w.st);
+                if ((st = S.launched()) != MP_OK) return st;
+                if ((st = S.spmv(sh, tv)) != MP_OK) return st;
+                if ((st = S.dot2(tv, s, tv, tv, S.w.part[0], S.w.part[1], S.w.st)) != MP_OK) return st;
+                hipLaunchKernelGGL(k_bi_omega, dim3(1), dim3(256), 0, S.s, S.w.part[0], S.w.part[1], m, S.w.st);
+                hipLaunchKernelGGL(k_bi_xr, dim3(m), dim3(256), 0, S.s, n, x, r, ph, sh, s, tv, S.w.part[2], S.w.st);
+                hipLaunchKernelGGL(k_bi_rr, dim3(1), dim3(256), 0, S.s, S.w.part[2], m, S.w.st);
+                if ((st = S.launched()) != MP_OK) return st;
+            }
+            continue;
+        }
+        if (h.done == RECURRENCE_MET) {
+            if ((st = S.true_residual(b, x, q, r, true)) != MP_OK) return st;
+            continue;
+        }
+        if (h.done == RESTART) {
+            hipLaunchKernelGGL(k_copy, dim3(S.vblocks), dim3(256), 0, S.s, 2 * n, r, rh);
+            hipLaunchKernelGGL(k_bi_restart, dim3(1), dim3(64), 0, S.s, S.w.st);
+            if ((st = S.launched()) != MP_OK) return st;
+            continue;
+        }
+        status = h.done == CONFIRMED ? MP_OK : (h.done == BROKE_DOWN ? MP_ERR_BREAKDOWN : MP_ERR_NOT_CONVERGED);
+        break;
+    }
+    if ((st = S.true_residual(b, x, q, r, false)) != MP_OK) return st;
+    if ((st = S.read_state(&h)) != MP_OK) return st;
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    fill_info(h, status, secs, info);
+    if (status == MP_ERR_NOT_CONVERGED)
+        return fail(MP_ERR_NOT_CONVERGED, "mpkrylov_bicgstab: no convergence in %d iterations", h.iters);
+    if (status == MP_ERR_BREAKDOWN) return fail(MP_ERR_BREAKDOWN, "mpkrylov_bicgstab: breakdown at iteration %d", h.iters);
+    return MP_OK;
+}
+
+mp_status solve_entry(const char *name, bool bicg, const mp_csr *A, const double *a, const double *b, double *x,
+                      const mp_solve_opts *opts, const mp_plan *plan, void *ws, size_t ws_bytes, mp_solve_info *info,
+                      void *stream)
+{
+    clear_error();
+    mp_status st = check_solver_args(name, A, a, b, x, opts, plan, ws, ws_bytes, info);
+    if (st != MP_OK) return st;
+    if (A->n_rows == 0) {
+        std::memset(info, 0, sizeof(*info));
+        return MP_OK;
+    }
+    Solver S;
+    S.A = A;
+    S.a = a;
+    S.plan = plan;
+    S.s = static_cast<hipStream_t>(stream);
+    S.n = A->n_rows;
+    S.m = (int)((S.n + kDotChunk - 1) / kDotChunk);
+    const int64_t vb = (S.n + 255) / 256;
+    S.vblocks = (unsigned)(vb < 8192 ? vb : 8192);
+    S.w = carve(ws, S.n);
+    return bicg ? run_bicgstab(S, b, x, opts, info) : run_cg(S, b, x, opts, info);
+}
+
+}  // namespace mpk
+
+extern "C" {
+
+mp_status mpkrylov_workspace_bytes(const mp_csr *A, const mp_solve_opts *opts, size_t *bytes)
+{
+    mpk::clear_error();
+    (void)opts;
+    mp_status st = mpk::check_csr(A);
+    if (st != MP_OK) return st;
+    if (!bytes) return mpk::fail(MP_ERR_INVALID_ARG, "bytes is NULL");
+    *bytes = mpk::workspace_bytes(A->n_rows);
+    return MP_OK;
+}
+
+mp_status mpkrylov_cg(const mp_csr *A, const double *a, const double *b, double *x, const mp_solve_opts *opts,
+                      const mp_plan *plan, void *ws, size_t ws_bytes, mp_solve_info *info, void *stream)
+{
+    return mpk::solve_entry("mpkrylov_cg", false, A, a, b, x, opts, plan, ws, ws_bytes, info, stream);
+}
+
+mp_status mpkrylov_bicgstab(const mp_csr *A, const double *a, const double *b, double *x, const mp_solve_opts *opts,
+                            const mp_plan *plan, void *ws, size_t ws_bytes, mp_solve_info *info, void *stream)
+{
+    return mpk::solve_entry("mpkrylov_bicgstab", true, A, a, b, x, opts, plan, ws, ws_bytes, info, stream);
+}
+
+}  // extern "C"

@@ -96,6 +96,33 @@ __device__ __forceinline__ dd_t dd_mul_d(const dd_t &x, double y)
     return r;
 }
 
+// DD comparison a <= b (non-overlapping pairs: compare leading, then trailing parts)
+__device__ __forceinline__ bool dd_le(const dd_t &a, const dd_t &b)
+{
+    return (a.c[0] < b.c[0]) || (a.c[0] == b.c[0] && a.c[1] <= b.c[1]);
+}
+
+// DD division a / b (Dekker's long division): q1 = a0 / b0; the remainder a - q1 b
+// from an exact product q1*b0, the trailing products and an exact difference;
+// q2 = remainder / b0; result QuickTwoSum(q1, q2).  Binary64 division is the
+// correctly rounded IEEE operation.
+__device__ __forceinline__ dd_t dd_div(const dd_t &a, const dd_t &b)
+{
+    const double q1 = a.c[0] / b.c[0];
+    double p, e;
+    two_prod(q1, b.c[0], p, e);
+    const double w = q1 * b.c[1];
+    e = e + w;
+    double s, f;
+    two_sum(a.c[0], -p, s, f);
+    f = f - e;
+    f = f + a.c[1];
+    const double q2 = (s + f) / b.c[0];
+    dd_t r;
+    quick_two_sum(q1, q2, r.c[0], r.c[1]);
+    return r;
+}
+
 // ---------------------------------------------------------------------------
 // quad-double building blocks
 // ---------------------------------------------------------------------------

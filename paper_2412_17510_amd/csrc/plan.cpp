@@ -1,6 +1,6 @@
-// plan.cpp -- plan construction (row binning by lane width), explicit orders and the
-// autotuner.  Host C++; the per-row work is O(n) integer bookkeeping done once per
-// pattern, after which SpMV calls only read the uploaded permutation and tile lists.
+// plan.cpp -- plan construction (row tiling), explicit orders and the autotuner.
+// Host C++; the per-row work is O(n) integer bookkeeping done once per pattern and
+// variant, after which SpMV calls only read the uploaded tile list and lane widths.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -13,20 +13,18 @@
 
 namespace mpk {
 
-mp_status spmv_dispatch(int K, bool cplx, const mp_csr *A, const double *a_re, const double *a_im,
-                        const double *x_re, const double *x_im, double *y_re, double *y_im, const mp_plan *plan,
-                        hipStream_t s);
-
-namespace {
-
-void free_plan(mp_plan *p)
+void plan_free(mp_plan *p)
 {
     if (!p) return;
-    if (p->d_perm) (void)hipFree(p->d_perm);
-    if (p->d_small) (void)hipFree(p->d_small);
-    if (p->d_big) (void)hipFree(p->d_big);
+    if (p->d_stream) (void)hipFree(p->d_stream);
+    if (p->d_xstage) (void)hipFree(p->d_xstage);
+    if (p->d_log2w) (void)hipFree(p->d_log2w);
+    if (p->d_wide_rows) (void)hipFree(p->d_wide_rows);
+    if (p->d_wide) (void)hipFree(p->d_wide);
     delete p;
 }
+
+namespace {
 
 template <typename T>
 mp_status upload(const std::vector<T> &h, T **d, hipStream_t s)
@@ -50,54 +48,92 @@ mp_status read_row_ptr(const mp_csr *A, hipStream_t s, std::vector<int32_t> &h)
     return MP_OK;
 }
 
+mp_status check_variant(int32_t ncomp, int32_t is_complex)
+{
+    if (ncomp < 2 || ncomp > 4) return fail(MP_ERR_INVALID_ARG, "ncomp must be 2, 3 or 4 (got %d)", ncomp);
+    if (is_complex != 0 && is_complex != 1) return fail(MP_ERR_INVALID_ARG, "is_complex must be 0 or 1");
+    return MP_OK;
+}
+
+mp_status resolve_tile(int32_t ncomp, int32_t is_complex, int32_t requested, int *tile)
+{
+    const int mx = max_tile_nnz(ncomp, is_complex != 0);
+    if (requested == 0) {
+        *tile = default_tile_nnz(ncomp, is_complex != 0);
+        return MP_OK;
+    }
+    if (requested < 256 || requested > 2048 || (requested & (requested - 1)))
+        return fail(MP_ERR_INVALID_ARG, "tile_nnz must be 0 or a power of two in 256..2048 (got %d)", requested);
+    if (requested > mx)
+        return fail(MP_ERR_UNSUPPORTED, "tile_nnz %d exceeds the LDS budget of this variant (max %d)", requested, mx);
+    *tile = requested;
+    return MP_OK;
+}
+
 }  // namespace
 
-mp_status plan_build(const std::vector<int32_t> &rp, std::vector<uint8_t> &&log2w, int64_t nnz, hipStream_t s,
-                     mp_plan **out)
+mp_status plan_build(const std::vector<int32_t> &rp, std::vector<uint8_t> &&log2w, int64_t nnz, int32_t n_cols,
+                     int K, bool cplx, int C, hipStream_t s, mp_plan **out)
 {
     const int32_t n = (int32_t)rp.size() - 1;
     mp_plan *p = new (std::nothrow) mp_plan;
     if (!p) return fail(MP_ERR_NO_MEMORY, "plan allocation failed");
     p->n_rows = n;
     p->nnz = nnz;
+    p->ncomp = K;
+    p->cplx = cplx ? 1 : 0;
+    p->tile_nnz = C;
+    p->n_cols = n_cols;
     p->log2w = std::move(log2w);
-    // stable counting sort of the rows by lane width
-    int64_t count[kMaxLog2W + 2] = {0};
-    for (int32_t i = 0; i < n; ++i) count[p->log2w[i] + 1]++;
-    for (int w = 0; w <= kMaxLog2W; ++w) count[w + 1] += count[w];
-    std::vector<int32_t> perm((size_t)n);
-    {
-        int64_t pos[kMaxLog2W + 1];
-        for (int w = 0; w <= kMaxLog2W; ++w) pos[w] = count[w];
-        for (int32_t i = 0; i < n; ++i) perm[(size_t)pos[p->log2w[i]]++] = i;
-    }
-    std::vector<mp_tile> small, big;
-    int maxw = 0;
-    for (int w = 0; w <= kMaxLog2W; ++w) {
-        const int64_t b = count[w], e = count[w + 1];
-        if (e > b) maxw = w;
-        const int64_t per = w <= 8 ? (kTileLanes >> w) : 1;
-        for (int64_t f = b; f < e; f += per) {
-            const int64_t cnt = std::min<int64_t>(per, e - f);
-            mp_tile t{(int32_t)f, (int32_t)((w << 16) | (int32_t)cnt)};
-            (w <= 6 ? small : big).push_back(t);
+    std::vector<mp_stream_tile> tiles;
+    std::vector<int32_t> wide_rows;
+    std::vector<mp_tile> wide;
+    tiles.reserve((size_t)(nnz / C + 16));
+    int32_t i = 0;
+    while (i < n) {
+        const int64_t len = (int64_t)rp[i + 1] - rp[i];
+        if (len > C) {
+            const int lw = p->log2w[i];
+            if (lw > kMaxLongLog2W) {
+                wide.push_back(mp_tile{(int32_t)wide_rows.size(), (int32_t)((lw << 16) | 1)});
+                wide_rows.push_back(i);
+            } else {
+                tiles.push_back(mp_stream_tile{i, 1, rp[i], tile_info(lw, 1, 0)});
+            }
+            ++i;
+            continue;
         }
+        const int32_t start = i;
+        int64_t acc = 0;
+        int32_t cnt = 0;
+        int maxlw = 0;
+        while (i < n && cnt < C) {
+            const int64_t l = (int64_t)rp[i + 1] - rp[i];
+            if (l > C || acc + l > C) break;
+            acc += l;
+            if (l > 0 && p->log2w[i] > maxlw) maxlw = p->log2w[i];
+            ++cnt;
+            ++i;
+        }
+        tiles.push_back(mp_stream_tile{start, cnt, rp[start], tile_info(maxlw, 0, (int)acc)});
     }
-    auto by_first_row = [&](const mp_tile &a, const mp_tile &b) { return perm[a.first] < perm[b.first]; };
-    std::stable_sort(small.begin(), small.end(), by_first_row);
-    std::stable_sort(big.begin(), big.end(), by_first_row);
-    p->n_small = (int32_t)small.size();
-    p->n_big = (int32_t)big.size();
-    p->max_log2w = maxw;
-    mp_status st = upload(perm, &p->d_perm, s);
-    if (st == MP_OK) st = upload(small, &p->d_small, s);
-    if (st == MP_OK) st = upload(big, &p->d_big, s);
+    p->n_stream = (int32_t)tiles.size();
+    p->n_wide = (int32_t)wide.size();
+    mp_status st = upload(tiles, &p->d_stream, s);
+    if (st == MP_OK) st = upload(p->log2w, &p->d_log2w, s);
+    if (st == MP_OK) st = upload(wide_rows, &p->d_wide_rows, s);
+    if (st == MP_OK) st = upload(wide, &p->d_wide, s);
+    if (st == MP_OK && n_cols > 0) {
+        hipError_t e = hipMalloc(reinterpret_cast<void **>(&p->d_xstage),
+                                 sizeof(double) * (size_t)xstage_doubles(K, cplx) * (size_t)n_cols);
+        if (e != hipSuccess) st = hip_fail(e, "hipMalloc(x staging)");
+    }
     if (st == MP_OK) {
         hipError_t e = hipStreamSynchronize(s);
         if (e != hipSuccess) st = hip_fail(e, "hipStreamSynchronize");
     }
     if (st != MP_OK) {
-        free_plan(p);
+        plan_free(p);
         return st;
     }
     *out = p;
@@ -106,23 +142,25 @@ mp_status plan_build(const std::vector<int32_t> &rp, std::vector<uint8_t> &&log2
 
 namespace {
 
-mp_status create_with_policy(const mp_csr *A, const mp_width_policy &pol, hipStream_t s,
-                             const std::vector<int32_t> &rp, mp_plan **out)
+mp_status create_with_opts(const mp_csr *A, int K, bool cplx, const mp_plan_opts &o, int C, hipStream_t s,
+                           const std::vector<int32_t> &rp, mp_plan **out)
 {
     std::vector<uint8_t> lw((size_t)A->n_rows);
-    for (int32_t i = 0; i < A->n_rows; ++i) lw[i] = (uint8_t)policy_log2w((int64_t)rp[i + 1] - rp[i], pol);
-    mp_status st = plan_build(rp, std::move(lw), A->nnz, s, out);
+    for (int32_t i = 0; i < A->n_rows; ++i)
+        lw[i] = (uint8_t)policy_log2w((int64_t)rp[i + 1] - rp[i], o.shift, o.max_log2w);
+    mp_status st = plan_build(rp, std::move(lw), A->nnz, A->n_cols, K, cplx, C, s, out);
     if (st == MP_OK) {
-        (*out)->policy = pol;
+        (*out)->opts = o;
+        (*out)->opts.tile_nnz = C;
         (*out)->explicit_order = false;
     }
     return st;
 }
 
-mp_status check_policy(const mp_width_policy &pol)
+mp_status check_opts(const mp_plan_opts &o)
 {
-    if (pol.shift < 0 || pol.shift > 12 || pol.max_log2w < 0 || pol.max_log2w > kMaxLog2W)
-        return fail(MP_ERR_INVALID_ARG, "width policy out of range (shift=%d max_log2w=%d)", pol.shift, pol.max_log2w);
+    if (o.shift < 0 || o.shift > 12 || o.max_log2w < 0 || o.max_log2w > kMaxLog2W)
+        return fail(MP_ERR_INVALID_ARG, "plan options out of range (shift=%d max_log2w=%d)", o.shift, o.max_log2w);
     return MP_OK;
 }
 
@@ -132,29 +170,37 @@ mp_status check_policy(const mp_width_policy &pol)
 
 extern "C" {
 
-mp_status mp_plan_create(const mp_csr *A, const mp_width_policy *policy, void *stream, mp_plan **out)
+mp_status mp_plan_create(const mp_csr *A, int32_t ncomp, int32_t is_complex, const mp_plan_opts *opts, void *stream,
+                         mp_plan **out)
 {
     mpk::clear_error();
     if (!out) return mpk::fail(MP_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     mp_status st = mpk::check_csr(A);
+    if (st == MP_OK) st = mpk::check_variant(ncomp, is_complex);
     if (st != MP_OK) return st;
-    const mp_width_policy pol = policy ? *policy : mp_width_policy{0, 6};
-    st = mpk::check_policy(pol);
+    const mp_plan_opts o = opts ? *opts : mp_plan_opts{0, 6, 0};
+    st = mpk::check_opts(o);
+    int C = 0;
+    if (st == MP_OK) st = mpk::resolve_tile(ncomp, is_complex, o.tile_nnz, &C);
     if (st != MP_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::vector<int32_t> rp;
     st = mpk::read_row_ptr(A, s, rp);
     if (st != MP_OK) return st;
-    return mpk::create_with_policy(A, pol, s, rp, out);
+    return mpk::create_with_opts(A, ncomp, is_complex != 0, o, C, s, rp, out);
 }
 
-mp_status mp_plan_create_explicit(const mp_csr *A, const uint8_t *log2w_host, void *stream, mp_plan **out)
+mp_status mp_plan_create_explicit(const mp_csr *A, int32_t ncomp, int32_t is_complex, const uint8_t *log2w_host,
+                                  int32_t tile_nnz, void *stream, mp_plan **out)
 {
     mpk::clear_error();
     if (!out) return mpk::fail(MP_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     mp_status st = mpk::check_csr(A);
+    if (st == MP_OK) st = mpk::check_variant(ncomp, is_complex);
+    int C = 0;
+    if (st == MP_OK) st = mpk::resolve_tile(ncomp, is_complex, tile_nnz, &C);
     if (st != MP_OK) return st;
     if (A->n_rows > 0 && !log2w_host) return mpk::fail(MP_ERR_INVALID_ARG, "log2w is NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -168,15 +214,18 @@ mp_status mp_plan_create_explicit(const mp_csr *A, const uint8_t *log2w_host, vo
             return mpk::fail(MP_ERR_INVALID_ARG, "log2w[%d] = %d is not valid for a row of %lld elements", i,
                              (int)lw[i], (long long)len);
     }
-    st = mpk::plan_build(rp, std::move(lw), A->nnz, s, out);
-    if (st == MP_OK) (*out)->explicit_order = true;
+    st = mpk::plan_build(rp, std::move(lw), A->nnz, A->n_cols, ncomp, is_complex != 0, C, s, out);
+    if (st == MP_OK) {
+        (*out)->explicit_order = true;
+        (*out)->opts.tile_nnz = C;
+    }
     return st;
 }
 
 mp_status mp_plan_destroy(mp_plan *plan)
 {
     mpk::clear_error();
-    mpk::free_plan(plan);
+    mpk::plan_free(plan);
     return MP_OK;
 }
 
@@ -188,77 +237,92 @@ mp_status mp_plan_row_log2w(const mp_plan *plan, uint8_t *log2w_host)
     return MP_OK;
 }
 
-mp_status mp_plan_info(const mp_plan *plan, int32_t *n_rows, int32_t *n_tiles)
+mp_status mp_plan_info(const mp_plan *plan, int32_t *n_rows, int32_t *n_tiles, int32_t *tile_nnz, int32_t *ncomp,
+                       int32_t *is_complex)
 {
     mpk::clear_error();
     if (!plan) return mpk::fail(MP_ERR_INVALID_ARG, "plan is NULL");
     if (n_rows) *n_rows = plan->n_rows;
-    if (n_tiles) *n_tiles = plan->n_small + plan->n_big;
+    if (n_tiles) *n_tiles = plan->n_stream + plan->n_wide;
+    if (tile_nnz) *tile_nnz = plan->tile_nnz;
+    if (ncomp) *ncomp = plan->ncomp;
+    if (is_complex) *is_complex = plan->cplx;
     return MP_OK;
 }
 
 mp_status mp_plan_autotune(const mp_csr *A, int32_t ncomp, int32_t is_complex, const double *a_re,
                            const double *a_im, const double *x_re, const double *x_im, double *y_re, double *y_im,
-                           int32_t reps, void *stream, mp_plan **out, mp_width_policy *chosen)
+                           int32_t reps, void *stream, mp_plan **out, mp_plan_opts *chosen)
 {
     mpk::clear_error();
     if (!out) return mpk::fail(MP_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     mp_status st = mpk::check_csr(A);
+    if (st == MP_OK) st = mpk::check_variant(ncomp, is_complex);
     if (st != MP_OK) return st;
-    if (ncomp < 2 || ncomp > 4) return mpk::fail(MP_ERR_INVALID_ARG, "ncomp must be 2, 3 or 4");
     if (A->nnz > 0 && (!a_re || !x_re || !y_re || (is_complex && (!a_im || !x_im || !y_im))))
         return mpk::fail(MP_ERR_INVALID_ARG, "operand is NULL");
     if (reps < 1) reps = 1;
+    const bool cplx = is_complex != 0;
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::vector<int32_t> rp;
     st = mpk::read_row_ptr(A, s, rp);
     if (st != MP_OK) return st;
-    // candidate width policies: lane widths from "as wide as the row" (shift 0) to
-    // "several elements per lane" (shift 3), capped at 16..1024 lanes
-    static const mp_width_policy cands[] = {{0, 6}, {1, 6}, {2, 6}, {3, 6}, {0, 5}, {1, 5}, {2, 5}, {0, 4},
-                                            {1, 4}, {2, 4}, {1, 3}, {0, 8}, {1, 8}, {0, 10}};
     hipEvent_t e0, e1;
     MP_HIP_TRY(hipEventCreate(&e0));
     MP_HIP_TRY(hipEventCreate(&e1));
     mp_plan *best = nullptr;
     float best_ms = 0.f;
-    mp_width_policy best_pol{0, 6};
-    for (const mp_width_policy &pol : cands) {
+    mp_plan_opts best_o{0, 6, 0};
+    auto trial = [&](const mp_plan_opts &o) -> mp_status {
+        int C = 0;
+        mp_status t = mpk::resolve_tile(ncomp, is_complex, o.tile_nnz, &C);
+        if (t != MP_OK) return t;
         mp_plan *p = nullptr;
-        st = mpk::create_with_policy(A, pol, s, rp, &p);
-        if (st != MP_OK) break;
-        st = mpk::spmv_dispatch(ncomp, is_complex != 0, A, a_re, a_im, x_re, x_im, y_re, y_im, p, s);
+        t = mpk::create_with_opts(A, ncomp, cplx, o, C, s, rp, &p);
+        if (t != MP_OK) return t;
+        t = mpk::spmv_dispatch(ncomp, cplx, A, a_re, a_im, x_re, x_im, y_re, y_im, p, s);
         hipError_t err = hipSuccess;
-        if (st == MP_OK) err = hipEventRecord(e0, s);
-        for (int r = 0; st == MP_OK && err == hipSuccess && r < reps; ++r)
-            st = mpk::spmv_dispatch(ncomp, is_complex != 0, A, a_re, a_im, x_re, x_im, y_re, y_im, p, s);
-        if (st == MP_OK && err == hipSuccess) err = hipEventRecord(e1, s);
-        if (st == MP_OK && err == hipSuccess) err = hipEventSynchronize(e1);
+        if (t == MP_OK) err = hipEventRecord(e0, s);
+        for (int r = 0; t == MP_OK && err == hipSuccess && r < reps; ++r)
+            t = mpk::spmv_dispatch(ncomp, cplx, A, a_re, a_im, x_re, x_im, y_re, y_im, p, s);
+        if (t == MP_OK && err == hipSuccess) err = hipEventRecord(e1, s);
+        if (t == MP_OK && err == hipSuccess) err = hipEventSynchronize(e1);
         float ms = 0.f;
-        if (st == MP_OK && err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-        if (st == MP_OK && err != hipSuccess) st = mpk::hip_fail(err, "autotune timing");
-        if (st != MP_OK) {
-            mpk::free_plan(p);
-            break;
+        if (t == MP_OK && err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        if (t == MP_OK && err != hipSuccess) t = mpk::hip_fail(err, "autotune timing");
+        if (t != MP_OK) {
+            mpk::plan_free(p);
+            return t;
         }
         if (!best || ms < best_ms) {
-            mpk::free_plan(best);
+            mpk::plan_free(best);
             best = p;
             best_ms = ms;
-            best_pol = pol;
+            best_o = p->opts;
         } else {
-            mpk::free_plan(p);
+            mpk::plan_free(p);
         }
+        return MP_OK;
+    };
+    // stage 1: tile sizes under a middle-of-the-road order; stage 2: lane-width policies
+    const int mx = mpk::max_tile_nnz(ncomp, cplx);
+    for (int C = 256; st == MP_OK && C <= mx; C <<= 1) st = trial(mp_plan_opts{1, 6, C});
+    const int bestC = best ? best->tile_nnz : mpk::default_tile_nnz(ncomp, cplx);
+    static const int pols[][2] = {{0, 6}, {2, 6}, {3, 6}, {0, 5}, {1, 5}, {2, 5}, {0, 4}, {1, 4},
+                                  {2, 4}, {1, 3}, {0, 8}, {1, 8}, {2, 8}};
+    for (const auto &pp : pols) {
+        if (st != MP_OK) break;
+        st = trial(mp_plan_opts{pp[0], pp[1], bestC});
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != MP_OK) {
-        mpk::free_plan(best);
+        mpk::plan_free(best);
         return st;
     }
     *out = best;
-    if (chosen) *chosen = best_pol;
+    if (chosen) *chosen = best_o;
     return MP_OK;
 }
 

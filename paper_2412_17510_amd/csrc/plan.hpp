@@ -1,16 +1,21 @@
 // plan.hpp -- the execution plan of a CSR pattern (library-internal layout).
 //
-// A plan fixes the summation order of every row (its lane width W = 2^log2w) and
-// the work decomposition of one SpMV:
-//   * rows are binned by log2w (stable, so each bin keeps ascending row order) into
-//     a permutation `perm`;
-//   * each bin is cut into workgroup tiles of 256 lanes: a tile of bin w holds
-//     256 >> w rows for w <= 8 and one row for w >= 8;
-//   * "small" tiles (w <= 6: whole rows inside one wavefront) and "big" tiles (w >= 7:
-//     rows spanning several wavefronts) go to two kernels;
-//   * inside each list tiles are ordered by their first row, so the XCD-aware
-//     block mapping hands each XCD a contiguous range of rows (its L2 then holds the
-//     banded part of x those rows gather).
+// A plan fixes, for one variant (K components, real or complex):
+//   * the summation order of every row, i.e. its lane width W = 2^log2w (host and
+//     device copies);
+//   * the tiles one SpMV launch walks, in row order:
+//       SHORT  a contiguous range of rows holding at most tile_nnz elements (and at
+//              most tile_nnz rows): the workgroup stages all their products in LDS,
+//              then applies the lane/fold order from LDS;
+//       LONG   one row longer than tile_nnz with W <= 256: processed in chunks of
+//              tile_nnz staged products, W lane accumulators carried in registers;
+//   * rows longer than tile_nnz with W >= 512 go to a separate list handled by the
+//     register-only wide-row kernel (one row per workgroup);
+//   * a staging buffer for an interleaved copy of x (the K components of x_j, and for
+//     complex data then the K imaginary ones, side by side), written at the start
+//     of every planned SpMV so that one gather fetches all components of x_j.
+// Tiles are in ascending row order, so the XCD-aware block mapping hands each XCD a
+// contiguous range of rows (its L2 then holds the banded part of x those rows gather).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -20,7 +25,19 @@
 
 #include "mpsparse.h"
 
-// A tile: first position in perm, and (log2w << 16) | number of rows.
+struct mp_stream_tile {
+    int32_t row_start;
+    int32_t row_count;
+    int32_t elem_start;  // first element (row_ptr[row_start])
+    int32_t info;        // max_log2w | kind << 4 | elem_count << 8 (SHORT tiles; 0 count for LONG)
+};
+
+inline int32_t tile_info(int max_log2w, int kind, int elem_count)
+{
+    return max_log2w | (kind << 4) | (elem_count << 8);
+}
+
+// wide-row tile: position in the wide-row permutation and (log2w << 16) | row count
 struct mp_tile {
     int32_t first;
     int32_t lw_count;
@@ -29,36 +46,74 @@ struct mp_tile {
 struct mp_plan {
     int32_t n_rows = 0;
     int64_t nnz = 0;
-    int32_t n_small = 0;          // tiles with log2w <= 6
-    int32_t n_big = 0;            // tiles with log2w >= 7
-    int32_t max_log2w = 0;
-    int32_t *d_perm = nullptr;    // device, n_rows
-    mp_tile *d_small = nullptr;   // device, n_small
-    mp_tile *d_big = nullptr;     // device, n_big
-    std::vector<uint8_t> log2w;   // host copy of the order
-    mp_width_policy policy{0, 6};
+    int32_t ncomp = 2;
+    int32_t cplx = 0;
+    int32_t tile_nnz = 1024;
+    int32_t n_stream = 0;
+    int32_t n_wide = 0;
+    mp_stream_tile *d_stream = nullptr;   // device, n_stream
+    double *d_xstage = nullptr;           // device, interleaved copy of x (K or 2K doubles per column)
+    int32_t n_cols = 0;
+    uint8_t *d_log2w = nullptr;           // device, n_rows
+    int32_t *d_wide_rows = nullptr;       // device, n_wide
+    mp_tile *d_wide = nullptr;            // device, n_wide
+    std::vector<uint8_t> log2w;           // host copy of the order
+    mp_plan_opts opts{0, 6, 0};
     bool explicit_order = false;
 };
 
 namespace mpk {
 
-constexpr int kTileLanes = 256;
 constexpr int kMaxLog2W = 10;
+constexpr int kMaxLongLog2W = 8;   // LONG tiles: W <= 256
 
-// lane-width exponent of a row of `len` elements under a width policy
-inline int policy_log2w(int64_t len, const mp_width_policy &p)
+// doubles per staged product: K, times 4 accumulator sets for complex
+inline int prod_doubles(int K, bool cplx) { return K * (cplx ? 4 : 1); }
+
+// doubles per column of the interleaved x copy
+inline int xstage_doubles(int K, bool cplx) { return K * (cplx ? 2 : 1); }
+
+// LDS bytes of a SHORT/LONG tile kernel staging C elements
+inline int64_t stream_lds_bytes(int K, bool cplx, int C)
+{
+    return (int64_t)C * (8 * prod_doubles(K, cplx) + 4 + 4 + 2) + 16;
+}
+
+// largest tile size (power of two in 256..2048) that fits 64 KiB of LDS
+inline int max_tile_nnz(int K, bool cplx)
+{
+    int c = 2048;
+    while (c > 256 && stream_lds_bytes(K, cplx, c) > 65536) c >>= 1;
+    return c;
+}
+
+inline int default_tile_nnz(int K, bool cplx)
+{
+    const int m = max_tile_nnz(K, cplx);
+    return m < 1024 ? m : 1024;
+}
+
+// lane-width exponent of a row of `len` elements under the plan options
+inline int policy_log2w(int64_t len, int shift, int max_log2w)
 {
     if (len <= 0) return 0;
     int fl = 0;
     while (fl < 62 && ((int64_t)2 << fl) <= len) ++fl;
-    int w = fl - p.shift;
+    int w = fl - shift;
     if (w < 0) w = 0;
-    if (w > p.max_log2w) w = p.max_log2w;
+    if (w > max_log2w) w = max_log2w;
     return w;
 }
 
-// Build a plan from host row lengths and per-row log2w (validated by the caller).
+// Build a plan from host row_ptr and per-row log2w (validated by the caller).
 mp_status plan_build(const std::vector<int32_t> &row_ptr_host, std::vector<uint8_t> &&log2w, int64_t nnz,
-                     hipStream_t stream, mp_plan **out);
+                     int32_t n_cols, int K, bool cplx, int tile_nnz, hipStream_t stream, mp_plan **out);
+
+void plan_free(mp_plan *p);
+
+// launch one SpMV of variant (K, cplx) with an optional plan (used by the autotuner)
+mp_status spmv_dispatch(int K, bool cplx, const mp_csr *A, const double *a_re, const double *a_im,
+                        const double *x_re, const double *x_im, double *y_re, double *y_im, const mp_plan *plan,
+                        hipStream_t s);
 
 }  // namespace mpk

@@ -15,11 +15,16 @@
 // once (coalesced along a row's lanes) and gathers K (or 2K) doubles of x.
 //
 // Kernels
-//   spmv_small_kernel  tiles of rows with W <= 64: 256/W rows per 256-thread group,
-//                      each row inside one wavefront, fold by shuffles;
-//   spmv_big_kernel    rows with W in 128..1024: one (or two, W = 128) rows per
-//                      group, 256 lanes per thread-sweep, fold in-thread, then LDS,
-//                      then shuffles;
+//   spmv_stream_kernel  planned path.  SHORT tiles (a contiguous range of rows with at
+//                       most C = tile_nnz elements): phase 1 streams the tile's
+//                       col_idx / value runs coalesced, gathers x and writes every
+//                       product to LDS (all threads busy, many loads in flight);
+//                       phase 2 runs the lane/fold order of each row out of LDS.
+//                       LONG tiles (one row longer than C, W <= 256): the same two
+//                       phases per chunk of C elements, lane sums carried in registers.
+//   spmv_wide_kernel    rows longer than C with W = 512 or 1024: lanes strided over
+//                       the row in registers, folded in-thread, through LDS, then by
+//                       shuffles.
 //   spmv_rowwave_kernel no plan: one row per wavefront, canonical W chosen in-kernel.
 // Block indices are remapped so that consecutive tiles land on the same XCD.
 #include <hip/hip_runtime.h>
@@ -47,6 +52,7 @@ struct SpmvArgs {
     const int32_t *__restrict__ perm;
     const mp_tile *__restrict__ tiles;
     int32_t n_tiles;
+    const double *__restrict__ xs;   // interleaved copy of x (planned path)
 };
 
 // ---------------------------------------------------------------------------
@@ -201,76 +207,283 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks)
 }
 
 // ---------------------------------------------------------------------------
-// small tiles: W <= 64
+// stream tiles (planned path)
 // ---------------------------------------------------------------------------
 
-template <int K, bool CPLX, int LW>
-__device__ __forceinline__ void small_tile(const SpmvArgs &A, int first, int nrows)
+// Exclusive prefix sum of one int per thread over a 256-thread block.
+__device__ __forceinline__ int block_exclusive_scan(int v, int *s_wave)
 {
-    constexpr int W = 1 << LW;
-    const int t = threadIdx.x;
-    const int g = t >> LW;
-    const int l = t & (W - 1);
-    const bool active = g < nrows;
-    int32_t row = 0, beg = 0, end = 0;
-    if (active) {
-        row = A.perm[first + g];
-        beg = A.row_ptr[row];
-        end = A.row_ptr[row + 1];
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
     }
-    Acc<K, CPLX> acc;
-    acc_zero(acc);
-    if (beg + l < end) {
-        first_product(A, beg + l, acc);
-        for (int64_t k = (int64_t)beg + l + W; k < end; k += W) add_product(A, k, acc);
-    }
-    wave_fold<K, CPLX, W>(acc);
-    if (active && l == 0) acc_store(A, row, acc, end > beg);
+    if (lane == 63) s_wave[wid] = x;
+    __syncthreads();
+    int pre = 0;
+    for (int w = 0; w < wid; ++w) pre += s_wave[w];
+    return pre + x - v;
 }
+
+// Interleaved copy of x: column j holds its K real components, then (complex) its K
+// imaginary ones, so one gather brings every component of x_j.
+template <int K, bool CPLX>
+__global__ __launch_bounds__(256) void k_stage_x(const double *__restrict__ x_re, const double *__restrict__ x_im,
+                                                 int32_t n_cols, double *__restrict__ xs)
+{
+    constexpr int D = K * (CPLX ? 2 : 1);
+    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n_cols; j += (int64_t)gridDim.x * 256) {
+        double v[D];
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            v[c] = x_re[c * (int64_t)n_cols + j];
+            if constexpr (CPLX) v[K + c] = x_im[c * (int64_t)n_cols + j];
+        }
+#pragma unroll
+        for (int c = 0; c < D; ++c) xs[j * D + c] = v[c];
+    }
+}
+
+// matrix operands of one element, loaded with the non-temporal hint (streamed once)
+template <int K, bool CPLX>
+struct AElem {
+    int32_t col;
+    mpn<K> re;
+    mpn<K> im;
+};
 
 template <int K, bool CPLX>
-__global__ __launch_bounds__(256) void spmv_small_kernel(SpmvArgs A)
+__device__ __forceinline__ void load_aelem(const SpmvArgs &A, int64_t k, AElem<K, CPLX> &e)
 {
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const mp_tile d = A.tiles[tile];
-    const int lw = d.lw_count >> 16;
-    const int nrows = d.lw_count & 0xffff;
-    switch (lw) {
-        case 0: small_tile<K, CPLX, 0>(A, d.first, nrows); break;
-        case 1: small_tile<K, CPLX, 1>(A, d.first, nrows); break;
-        case 2: small_tile<K, CPLX, 2>(A, d.first, nrows); break;
-        case 3: small_tile<K, CPLX, 3>(A, d.first, nrows); break;
-        case 4: small_tile<K, CPLX, 4>(A, d.first, nrows); break;
-        case 5: small_tile<K, CPLX, 5>(A, d.first, nrows); break;
-        default: small_tile<K, CPLX, 6>(A, d.first, nrows); break;
+    e.col = __builtin_nontemporal_load(A.col + k);
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        e.re.c[c] = __builtin_nontemporal_load(A.a_re + c * A.nnz + k);
+        if constexpr (CPLX) e.im.c[c] = __builtin_nontemporal_load(A.a_im + c * A.nnz + k);
     }
 }
 
+// product(s) of one element with the staged x (matrix operand first)
+template <int K, bool CPLX>
+__device__ __forceinline__ Acc<K, CPLX> staged_product(const SpmvArgs &A, const AElem<K, CPLX> &e)
+{
+    constexpr int D = K * (CPLX ? 2 : 1);
+    const double *xp = A.xs + (int64_t)e.col * D;
+    mpn<K> xr;
+#pragma unroll
+    for (int c = 0; c < K; ++c) xr.c[c] = xp[c];
+    Acc<K, CPLX> p;
+    if constexpr (CPLX) {
+        mpn<K> xi;
+#pragma unroll
+        for (int c = 0; c < K; ++c) xi.c[c] = xp[K + c];
+        p.rr = mp_mul(e.re, xr);
+        p.ii = mp_mul(e.im, xi);
+        p.ri = mp_mul(e.re, xi);
+        p.ir = mp_mul(e.im, xr);
+    } else {
+        p.v = mp_mul(e.re, xr);
+    }
+    return p;
+}
+
+// LDS of one stream-tile workgroup staging C elements
+template <int K, bool CPLX, int C>
+struct StreamLds {
+    Acc<K, CPLX> prod[C];      // staged products, later lane sums
+    int32_t beg[C + 1];        // row starts relative to the tile's first element
+    int32_t off[C + 1];        // first lane of each row
+    uint16_t lane_row[C];      // row of each lane
+    int32_t wave_tmp[4];
+};
+
+// SHORT tile: rows [r0, r0+nr), ne <= C elements starting at e0, at most C rows.
+// The element loads are issued first (their addresses need only the descriptor), the
+// row bookkeeping overlaps them, and the products go to LDS once x has arrived.
+template <int K, bool CPLX, int J>
+__device__ __forceinline__ void short_tile(const SpmvArgs &A, const uint8_t *__restrict__ log2w,
+                                           const mp_stream_tile &T, StreamLds<K, CPLX, 256 * J> &L)
+{
+    const int t = threadIdx.x;
+    const int r0 = T.row_start;
+    const int nr = T.row_count;
+    const int32_t e0 = T.elem_start;
+    const int ne = T.info >> 8;
+    // phase 1a: matrix operands of elements t, t+256, ...
+    AElem<K, CPLX> el[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int p = t + 256 * j;
+        if (p < ne) load_aelem<K, CPLX>(A, (int64_t)e0 + p, el[j]);
+    }
+    // rows t*J .. t*J+J-1: starts, lane counts (W, or 0 for an empty row)
+    int wl[J];
+    int sum = 0;
+#pragma unroll
+    for (int q = 0; q < J; ++q) {
+        const int i = t * J + q;
+        wl[q] = 0;
+        if (i < nr) {
+            const int32_t b = A.row_ptr[r0 + i], e = A.row_ptr[r0 + i + 1];
+            L.beg[i] = b - e0;
+            wl[q] = e > b ? (1 << log2w[r0 + i]) : 0;
+            sum += wl[q];
+        }
+    }
+    if (t == 0) L.beg[nr] = ne;
+    // phase 1b: gather x, products into LDS
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int p = t + 256 * j;
+        if (p < ne) L.prod[p] = staged_product<K, CPLX>(A, el[j]);
+    }
+    int run = block_exclusive_scan(sum, L.wave_tmp);
+#pragma unroll
+    for (int q = 0; q < J; ++q) {
+        const int i = t * J + q;
+        if (i < nr) L.off[i] = run;
+        run += wl[q];
+    }
+    if (t == 255) L.off[nr] = run;
+    __syncthreads();
+    // lane -> row map
+#pragma unroll
+    for (int q = 0; q < J; ++q) {
+        const int i = t * J + q;
+        if (i < nr) {
+            const int o = L.off[i];
+            for (int l = 0; l < wl[q]; ++l) L.lane_row[o + l] = (uint16_t)i;
+        }
+    }
+    __syncthreads();
+    // phase 2: lane l of row i sums its products l, l+W, ... and leaves the sum in the
+    // slot of its first product (a slot no other lane reads)
+    const int nl = L.off[nr];
+    int li[J], ll[J], lw[J], lb[J];
+#pragma unroll
+    for (int q = 0; q < J; ++q) {
+        const int lane = t + 256 * q;
+        li[q] = -1;
+        if (lane < nl) {
+            const int i = L.lane_row[lane];
+            const int o = L.off[i];
+            li[q] = i;
+            ll[q] = lane - o;
+            lw[q] = L.off[i + 1] - o;
+            lb[q] = L.beg[i];
+            const int e = L.beg[i + 1];
+            Acc<K, CPLX> acc = L.prod[lb[q] + ll[q]];
+            for (int p = lb[q] + ll[q] + lw[q]; p < e; p += lw[q]) acc_add(acc, L.prod[p]);
+            L.prod[lb[q] + ll[q]] = acc;
+        }
+    }
+    __syncthreads();
+    // fold: acc[l] += acc[l + off] for off = W/2 .. 1
+    for (int off = (1 << (T.info & 15)) >> 1; off >= 1; off >>= 1) {
+#pragma unroll
+        for (int q = 0; q < J; ++q) {
+            if (li[q] >= 0 && ll[q] < off && off < lw[q]) {
+                Acc<K, CPLX> v = L.prod[lb[q] + ll[q]];
+                acc_add(v, L.prod[lb[q] + ll[q] + off]);
+                L.prod[lb[q] + ll[q]] = v;
+            }
+        }
+        __syncthreads();
+    }
+    for (int i = t; i < nr; i += 256) {
+        const int b = L.beg[i];
+        const bool nonempty = L.beg[i + 1] > b;
+        Acc<K, CPLX> v;
+        if (nonempty) v = L.prod[b];
+        else acc_zero(v);
+        acc_store(A, r0 + i, v, nonempty);
+    }
+}
+
+// LONG tile: one row of len > C with W <= 256 lanes (lane l on thread l).
+template <int K, bool CPLX, int J>
+__device__ __forceinline__ void long_tile(const SpmvArgs &A, const uint8_t *__restrict__ log2w,
+                                          const mp_stream_tile &T, StreamLds<K, CPLX, 256 * J> &L)
+{
+    constexpr int C = 256 * J;
+    const int t = threadIdx.x;
+    const int row = T.row_start;
+    const int32_t b0 = A.row_ptr[row], end = A.row_ptr[row + 1];
+    const int W = 1 << log2w[row];
+    Acc<K, CPLX> acc;
+    acc_zero(acc);
+    for (int32_t c0 = b0; c0 < end; c0 += C) {
+        const int cl = (end - c0) < C ? (end - c0) : C;
+        AElem<K, CPLX> el[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int p = t + 256 * j;
+            if (p < cl) load_aelem<K, CPLX>(A, (int64_t)c0 + p, el[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int p = t + 256 * j;
+            if (p < cl) L.prod[p] = staged_product<K, CPLX>(A, el[j]);
+        }
+        __syncthreads();
+        if (t < W) {
+            // first local index p with (c0 - b0 + p) == t (mod W)
+            const int rel = (c0 - b0) & (W - 1);
+            int p = (t - rel) & (W - 1);
+            if (c0 == b0) {
+                acc = L.prod[p];   // the lane's first product (p = t < W <= C)
+                p += W;
+            }
+            for (; p < cl; p += W) acc_add(acc, L.prod[p]);
+        }
+        __syncthreads();
+    }
+    if (t < W) L.prod[t] = acc;
+    __syncthreads();
+    for (int off = W >> 1; off >= 1; off >>= 1) {
+        if (t < off) {
+            Acc<K, CPLX> v = L.prod[t];
+            acc_add(v, L.prod[t + off]);
+            L.prod[t] = v;
+        }
+        __syncthreads();
+    }
+    if (t == 0) acc_store(A, row, L.prod[0], true);
+}
+
+template <int K, bool CPLX, int J>
+__global__ __launch_bounds__(256) void spmv_stream_kernel(SpmvArgs A, const mp_stream_tile *__restrict__ tiles,
+                                                          const uint8_t *__restrict__ log2w)
+{
+    __shared__ StreamLds<K, CPLX, 256 * J> L;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const mp_stream_tile T = tiles[tile];
+    if (((T.info >> 4) & 15) == 0)
+        short_tile<K, CPLX, J>(A, log2w, T, L);
+    else
+        long_tile<K, CPLX, J>(A, log2w, T, L);
+}
+
 // ---------------------------------------------------------------------------
-// big tiles: W = 128..1024
+// wide rows: W = 512 or 1024 (one row per workgroup, lanes in registers)
 // ---------------------------------------------------------------------------
 
 template <int K, bool CPLX, int LW>
-__device__ __forceinline__ void big_tile(const SpmvArgs &A, int first, int nrows, Acc<K, CPLX> *lds)
+__device__ __forceinline__ void wide_row(const SpmvArgs &A, int first, Acc<K, CPLX> *lds)
 {
     constexpr int W = 1 << LW;
-    constexpr int J = W > 256 ? W / 256 : 1;        // lanes per thread
-    constexpr int SPAN = W >= 256 ? 256 : W;        // threads per row
+    constexpr int J = W / 256;   // lanes per thread
     const int t = threadIdx.x;
-    const int g = t / SPAN;
-    const int l0 = t % SPAN;
-    const bool active = g < nrows;
-    int32_t row = 0, beg = 0, end = 0;
-    if (active) {
-        row = A.perm[first + g];
-        beg = A.row_ptr[row];
-        end = A.row_ptr[row + 1];
-    }
+    const int32_t row = A.perm[first];
+    const int32_t beg = A.row_ptr[row], end = A.row_ptr[row + 1];
     Acc<K, CPLX> acc[J];
 #pragma unroll
     for (int j = 0; j < J; ++j) {
         acc_zero(acc[j]);
-        const int l = l0 + 256 * j;
+        const int l = t + 256 * j;
         if (beg + l < end) {
             first_product(A, beg + l, acc[j]);
             for (int64_t k = (int64_t)beg + l + W; k < end; k += W) add_product(A, k, acc[j]);
@@ -284,31 +497,27 @@ __device__ __forceinline__ void big_tile(const SpmvArgs &A, int first, int nrows
     }
     // steps across wavefronts (off = 128, 64) through LDS
 #pragma unroll
-    for (int off = SPAN / 2; off >= 64; off >>= 1) {
+    for (int off = 128; off >= 64; off >>= 1) {
         __syncthreads();
         lds[t] = acc[0];
         __syncthreads();
-        if (l0 < off) acc_add(acc[0], lds[t + off]);
+        if (t < off) acc_add(acc[0], lds[t + off]);
     }
     // steps inside a wavefront
     wave_fold<K, CPLX, 64>(acc[0]);
-    if (active && l0 == 0) acc_store(A, row, acc[0], end > beg);
+    if (t == 0) acc_store(A, row, acc[0], end > beg);
 }
 
 template <int K, bool CPLX>
-__global__ __launch_bounds__(256) void spmv_big_kernel(SpmvArgs A)
+__global__ __launch_bounds__(256) void spmv_wide_kernel(SpmvArgs A)
 {
     __shared__ Acc<K, CPLX> lds[256];
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const mp_tile d = A.tiles[tile];
-    const int lw = d.lw_count >> 16;
-    const int nrows = d.lw_count & 0xffff;
-    switch (lw) {
-        case 7: big_tile<K, CPLX, 7>(A, d.first, nrows, lds); break;
-        case 8: big_tile<K, CPLX, 8>(A, d.first, nrows, lds); break;
-        case 9: big_tile<K, CPLX, 9>(A, d.first, nrows, lds); break;
-        default: big_tile<K, CPLX, 10>(A, d.first, nrows, lds); break;
-    }
+    if ((d.lw_count >> 16) == 9)
+        wide_row<K, CPLX, 9>(A, d.first, lds);
+    else
+        wide_row<K, CPLX, 10>(A, d.first, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -342,6 +551,19 @@ __global__ __launch_bounds__(256) void spmv_rowwave_kernel(SpmvArgs A)
 // launch
 // ---------------------------------------------------------------------------
 
+template <int K, bool CPLX, int J>
+mp_status launch_stream(const SpmvArgs &A, const mp_plan *plan, hipStream_t s)
+{
+    if constexpr (sizeof(StreamLds<K, CPLX, 256 * J>) > 65536) {
+        return fail(MP_ERR_UNSUPPORTED, "tile size %d exceeds the LDS budget of this variant", 256 * J);
+    } else {
+        hipLaunchKernelGGL((spmv_stream_kernel<K, CPLX, J>), dim3(plan->n_stream), dim3(256), 0, s, A,
+                           plan->d_stream, plan->d_log2w);
+        MP_HIP_TRY(hipGetLastError());
+        return MP_OK;
+    }
+}
+
 template <int K, bool CPLX>
 mp_status launch_spmv(const mp_csr *Acsr, const double *a_re, const double *a_im, const double *x_re,
                       const double *x_im, double *y_re, double *y_im, const mp_plan *plan, hipStream_t s)
@@ -361,6 +583,7 @@ mp_status launch_spmv(const mp_csr *Acsr, const double *a_re, const double *a_im
     A.perm = nullptr;
     A.tiles = nullptr;
     A.n_tiles = 0;
+    A.xs = nullptr;
     if (Acsr->n_rows == 0) return MP_OK;
     if (!plan) {
         const int64_t blocks = ((int64_t)Acsr->n_rows + 3) / 4;
@@ -369,17 +592,31 @@ mp_status launch_spmv(const mp_csr *Acsr, const double *a_re, const double *a_im
         MP_HIP_TRY(hipGetLastError());
         return MP_OK;
     }
-    A.perm = plan->d_perm;
-    if (plan->n_small > 0) {
-        A.tiles = plan->d_small;
-        A.n_tiles = plan->n_small;
-        hipLaunchKernelGGL((spmv_small_kernel<K, CPLX>), dim3(plan->n_small), dim3(256), 0, s, A);
-        MP_HIP_TRY(hipGetLastError());
+    if (plan->n_stream > 0) {
+        if (plan->n_cols != Acsr->n_cols)
+            return fail(MP_ERR_INVALID_ARG, "plan was built for n_cols=%d, matrix has %d", plan->n_cols, Acsr->n_cols);
+        A.xs = plan->d_xstage;
+        if (Acsr->n_cols > 0) {
+            const int64_t sb = ((int64_t)Acsr->n_cols + 255) / 256;
+            hipLaunchKernelGGL((k_stage_x<K, CPLX>), dim3((unsigned)(sb < 4096 ? sb : 4096)), dim3(256), 0, s, x_re,
+                               x_im, Acsr->n_cols, plan->d_xstage);
+            MP_HIP_TRY(hipGetLastError());
+        }
+        mp_status st;
+        switch (plan->tile_nnz) {
+            case 256: st = launch_stream<K, CPLX, 1>(A, plan, s); break;
+            case 512: st = launch_stream<K, CPLX, 2>(A, plan, s); break;
+            case 1024: st = launch_stream<K, CPLX, 4>(A, plan, s); break;
+            case 2048: st = launch_stream<K, CPLX, 8>(A, plan, s); break;
+            default: st = fail(MP_ERR_INVALID_ARG, "plan has an invalid tile size %d", plan->tile_nnz);
+        }
+        if (st != MP_OK) return st;
     }
-    if (plan->n_big > 0) {
-        A.tiles = plan->d_big;
-        A.n_tiles = plan->n_big;
-        hipLaunchKernelGGL((spmv_big_kernel<K, CPLX>), dim3(plan->n_big), dim3(256), 0, s, A);
+    if (plan->n_wide > 0) {
+        A.perm = plan->d_wide_rows;
+        A.tiles = plan->d_wide;
+        A.n_tiles = plan->n_wide;
+        hipLaunchKernelGGL((spmv_wide_kernel<K, CPLX>), dim3(plan->n_wide), dim3(256), 0, s, A);
         MP_HIP_TRY(hipGetLastError());
     }
     return MP_OK;
@@ -398,6 +635,9 @@ mp_status spmv_entry(const char *name, const mp_csr *A, const double *a_re, cons
     if (plan && (plan->n_rows != A->n_rows || plan->nnz != A->nnz))
         return fail(MP_ERR_INVALID_ARG, "%s: plan was built for n_rows=%d nnz=%lld, matrix has n_rows=%d nnz=%lld",
                     name, plan->n_rows, (long long)plan->nnz, A->n_rows, (long long)A->nnz);
+    if (plan && (plan->ncomp != K || plan->cplx != (CPLX ? 1 : 0)))
+        return fail(MP_ERR_INVALID_ARG, "%s: plan was built for ncomp=%d is_complex=%d", name, plan->ncomp,
+                    plan->cplx);
     const size_t yb = sizeof(double) * K * (size_t)A->n_rows;
     const size_t ab = sizeof(double) * K * (size_t)A->nnz;
     const size_t xb = sizeof(double) * K * (size_t)A->n_cols;
@@ -413,7 +653,6 @@ mp_status spmv_entry(const char *name, const mp_csr *A, const double *a_re, cons
     return launch_spmv<K, CPLX>(A, a_re, a_im, x_re, x_im, y_re, y_im, plan, static_cast<hipStream_t>(stream));
 }
 
-// used by the autotuner
 mp_status spmv_dispatch(int K, bool cplx, const mp_csr *A, const double *a_re, const double *a_im,
                         const double *x_re, const double *x_im, double *y_re, double *y_im, const mp_plan *plan,
                         hipStream_t s)

@@ -20,6 +20,9 @@ from workloads import (laplace2d_5pt, random_csr, random_mp, sqrt2_vector, csr_f
 pytestmark = pytest.mark.gpu
 
 VARIANTS = [(2, False), (3, False), (4, False), (2, True), (3, True), (4, True)]
+# tile sizes (elements staged in LDS per workgroup) each variant supports
+TILES = {(2, False): (256, 512, 1024, 2048), (3, False): (256, 512, 1024), (4, False): (256, 512, 1024),
+         (2, True): (256, 512), (3, True): (256, 512), (4, True): (256,)}
 
 
 @pytest.fixture(scope="module")
@@ -65,14 +68,17 @@ def test_laplace2d_dd_all_plans(mp):
     A = mp.Csr.from_numpy(row_ptr, col_idx)
     mp.mp_csr_validate(A)
     check(mp, 2, False, row_ptr, col_idx, a, x, A=A, what="plan-free")
-    canon = mp.mp_plan_create(A)
+    canon = mp.mp_plan_create(A, 2)
     assert np.array_equal(canon.row_log2w(), ref.canonical_log2w(np.diff(row_ptr)))
     y1, _ = check(mp, 2, False, row_ptr, col_idx, a, x, plan=canon, A=A, what="canonical plan")
     y0, _ = run_gpu(mp, 2, False, A, a, x)
     assert_same_values(y0, y1, "plan-free vs canonical plan")
     for shift, mx in ((0, 1), (2, 6), (1, 0)):
-        check(mp, 2, False, row_ptr, col_idx, a, x, plan=mp.mp_plan_create(A, shift, mx), A=A,
+        check(mp, 2, False, row_ptr, col_idx, a, x, plan=mp.mp_plan_create(A, 2, False, shift, mx), A=A,
               what="policy %d,%d" % (shift, mx))
+    for tile in (256, 512, 1024, 2048):
+        check(mp, 2, False, row_ptr, col_idx, a, x, plan=mp.mp_plan_create(A, 2, False, 0, 6, tile), A=A,
+              what="tile %d" % tile)
 
 
 @pytest.mark.parametrize("K,cplx", VARIANTS)
@@ -87,10 +93,13 @@ def test_ragged_random_every_width(mp, K, cplx):
     x_im = random_mp(n_cols, K, rng) if cplx else None
     A = mp.Csr.from_numpy(row_ptr, col_idx, n_cols=n_cols)
     check(mp, K, cplx, row_ptr, col_idx, a_re, x_re, a_im, x_im, A=A, what="plan-free")
-    check(mp, K, cplx, row_ptr, col_idx, a_re, x_re, a_im, x_im, plan=mp.mp_plan_create(A), A=A,
-          what="canonical")
-    check(mp, K, cplx, row_ptr, col_idx, a_re, x_re, a_im, x_im, plan=mp.mp_plan_create(A, 2, 4), A=A,
+    for tile in TILES[(K, cplx)]:
+        check(mp, K, cplx, row_ptr, col_idx, a_re, x_re, a_im, x_im, plan=mp.mp_plan_create(A, K, cplx, tile_nnz=tile),
+              A=A, what="canonical tile %d" % tile)
+    check(mp, K, cplx, row_ptr, col_idx, a_re, x_re, a_im, x_im, plan=mp.mp_plan_create(A, K, cplx, 2, 4), A=A,
           what="policy 2,4")
+    check(mp, K, cplx, row_ptr, col_idx, a_re, x_re, a_im, x_im, plan=mp.mp_plan_create(A, K, cplx, 0, 8), A=A,
+          what="policy 0,8")
     # explicit random orders, including every wide (multi-wavefront) width
     fl = np.array([0 if L == 0 else int(np.floor(np.log2(L))) for L in lengths])
     lw = np.array([rng.integers(0, min(10, f) + 1) for f in fl], dtype=np.uint8)
@@ -98,11 +107,12 @@ def test_ragged_random_every_width(mp, K, cplx):
     lw[(lengths >= 512) & (lengths < 1024)] = 9
     lw[(lengths >= 256) & (lengths < 512)] = 8
     lw[(lengths >= 128) & (lengths < 256)] = 7
-    check(mp, K, cplx, row_ptr, col_idx, a_re, x_re, a_im, x_im, plan=mp.mp_plan_create_explicit(A, lw), A=A,
-          what="explicit wide")
+    for tile in TILES[(K, cplx)]:
+        check(mp, K, cplx, row_ptr, col_idx, a_re, x_re, a_im, x_im,
+              plan=mp.mp_plan_create_explicit(A, K, cplx, lw, tile), A=A, what="explicit wide tile %d" % tile)
     lw2 = np.array([rng.integers(0, min(10, f) + 1) for f in fl], dtype=np.uint8)
-    check(mp, K, cplx, row_ptr, col_idx, a_re, x_re, a_im, x_im, plan=mp.mp_plan_create_explicit(A, lw2), A=A,
-          what="explicit random")
+    check(mp, K, cplx, row_ptr, col_idx, a_re, x_re, a_im, x_im, plan=mp.mp_plan_create_explicit(A, K, cplx, lw2),
+          A=A, what="explicit random")
 
 
 @pytest.mark.parametrize("K", [2, 3, 4])
@@ -113,7 +123,7 @@ def test_paper_5x5_example(mp, K):
     v = sqrt2_vector(5, K)
     check(mp, K, False, row_ptr, col_idx, a, v, what="5x5 plan-free")
     A = mp.Csr.from_numpy(row_ptr, col_idx)
-    check(mp, K, False, row_ptr, col_idx, a, v, plan=mp.mp_plan_create(A), A=A, what="5x5 canonical")
+    check(mp, K, False, row_ptr, col_idx, a, v, plan=mp.mp_plan_create(A, K), A=A, what="5x5 canonical")
 
 
 @pytest.mark.parametrize("K,cplx", [(2, False), (4, True)])
@@ -128,7 +138,7 @@ def test_edge_cases(mp, K, cplx):
     xi = random_mp(4, K, rng) if cplx else None
     check(mp, K, cplx, row_ptr, col_idx, a, x, a if cplx else None, xi, what="all empty")
     A = mp.Csr.from_numpy(row_ptr, col_idx, n_cols=4)
-    check(mp, K, cplx, row_ptr, col_idx, a, x, a if cplx else None, xi, plan=mp.mp_plan_create(A), A=A,
+    check(mp, K, cplx, row_ptr, col_idx, a, x, a if cplx else None, xi, plan=mp.mp_plan_create(A, K, cplx), A=A,
           what="all empty, plan")
     # no rows at all
     A0 = mp.Csr.from_numpy(np.zeros(1, dtype=np.int32), col_idx, n_cols=4)
@@ -144,8 +154,10 @@ def test_edge_cases(mp, K, cplx):
     x = random_mp(6000, K, rng)
     xi = random_mp(6000, K, rng) if cplx else None
     A = mp.Csr.from_numpy(row_ptr, col_idx, n_cols=6000)
-    for plan in (None, mp.mp_plan_create(A), mp.mp_plan_create(A, 0, 10),
-                 mp.mp_plan_create_explicit(A, np.array([10, 0], dtype=np.uint8))):
+    for plan in (None, mp.mp_plan_create(A, K, cplx), mp.mp_plan_create(A, K, cplx, 0, 10),
+                 mp.mp_plan_create(A, K, cplx, 0, 8), mp.mp_plan_create(A, K, cplx, 3, 4),
+                 mp.mp_plan_create_explicit(A, K, cplx, np.array([10, 0], dtype=np.uint8)),
+                 mp.mp_plan_create_explicit(A, K, cplx, np.array([9, 0], dtype=np.uint8))):
         check(mp, K, cplx, row_ptr, col_idx, a_re, x, a_im, xi, plan=plan, A=A, what="long row")
 
 
@@ -171,7 +183,7 @@ def test_determinism_and_errors(mp):
     row_ptr, col_idx, a, _ = random_csr(2000, 2500, lengths, 2, rng)
     x = random_mp(2500, 2, rng)
     A = mp.Csr.from_numpy(row_ptr, col_idx, n_cols=2500)
-    plan = mp.mp_plan_create(A, 1, 5)
+    plan = mp.mp_plan_create(A, 2, False, 1, 5)
     ad, xd = dev(a), dev(x)
     y = torch.empty((2, 2000), dtype=torch.float64, device="cuda")
     mp.mpspmv_csr_dd(A, ad, xd, y, plan=plan)
@@ -202,9 +214,17 @@ def test_determinism_and_errors(mp):
     with pytest.raises(mp.MpError):
         mp.mp_csr_validate(mp.Csr.from_numpy(bad_rp, col_idx, n_cols=2500))
     with pytest.raises(mp.MpError):
-        mp.mp_plan_create(mp.Csr.from_numpy(bad_rp, col_idx, n_cols=2500))
+        mp.mp_plan_create(mp.Csr.from_numpy(bad_rp, col_idx, n_cols=2500), 2)
     with pytest.raises(mp.MpError):
-        mp.mp_plan_create_explicit(A, np.full(2000, 10, dtype=np.uint8))
+        mp.mp_plan_create_explicit(A, 2, False, np.full(2000, 10, dtype=np.uint8))
+    # a plan made for another variant is rejected
+    with pytest.raises(mp.MpError):
+        mp.mpspmv_csr_qd(A, dev(np.zeros((4, a.shape[1]))), dev(np.zeros((4, 2500))),
+                         torch.empty((4, 2000), dtype=torch.float64, device="cuda"), plan=plan)
+    # tile sizes beyond the variant's LDS budget are refused
+    with pytest.raises(mp.MpError) as ei:
+        mp.mp_plan_create(A, 4, True, tile_nnz=2048)
+    assert ei.value.status == -7
 
 
 # ---------------------------------------------------------------------------------------
@@ -254,3 +274,4 @@ def test_powerlaw_full_size_sampled(mp, powerlaw, K, cplx):
         else:
             assert_same_values(got_re[:, rows], want[:, rows], "powerlaw %s" % (pol,))
         assert not np.isnan(got_re).any()
+    assert plan.info()["tile_nnz"] == pol["tile_nnz"]

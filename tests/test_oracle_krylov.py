@@ -1,0 +1,135 @@
+"""Pins of the oracle's DD Krylov layer (CPU only).
+
+* The DD dot product (fixed tree) is within n 2^-100 sum|x||y| of the exact value
+  (Fractions), and exact on small integers; DD division is within 2^-100 of the exact
+  quotient and exact where the quotient is representable.
+* CG on a diagonal matrix with k distinct eigenvalues, unpreconditioned, converges in
+  at most k iterations (a property of exact-arithmetic CG that DD keeps).
+* CG / BiCGSTAB solve b = A v with the paper's v = sqrt(2)[1..n] (Sec. 4.2) on an SPD
+  diffusion matrix and on a non-symmetric narrow-band matrix to relative residual
+  1e-28; the returned x's residual is certified with exact rational arithmetic.
+* Breakdown (NaN right-hand side) and iteration limit are reported; a warm start
+  at the solution stops at once.
+"""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import ref, exact
+from workloads import random_mp, diffusion3d_7pt, banded_nonsymmetric, sqrt2_vector, random_csr
+
+
+def _fr(v):
+    return Fraction(float(v[0])) + Fraction(float(v[1]))
+
+
+@pytest.mark.parametrize("n", [0, 1, 255, 256, 4096, 4097, 9000])
+def test_dd_dot_bound(n):
+    rng = np.random.default_rng(n)
+    x = random_mp(n, 2, rng)
+    y = random_mp(n, 2, rng)
+    d = ref.dd_dot(x, y)
+    ex = sum((_fr(x[:, i]) * _fr(y[:, i]) for i in range(n)), Fraction(0))
+    s = sum((abs(_fr(x[:, i]) * _fr(y[:, i])) for i in range(n)), Fraction(0))
+    assert abs(_fr(d) - ex) <= max(n, 1) * s / 2 ** 100
+    if n == 0:
+        assert d[0] == 0 and d[1] == 0
+
+
+def test_dd_dot_integers_exact():
+    rng = np.random.default_rng(1)
+    n = 10000
+    x = np.zeros((2, n))
+    y = np.zeros((2, n))
+    x[0] = rng.integers(-2 ** 20, 2 ** 20, n)
+    y[0] = rng.integers(-2 ** 20, 2 ** 20, n)
+    d = ref.dd_dot(x, y)
+    assert _fr(d) == int(np.dot(x[0].astype(object), y[0].astype(object)))
+
+
+def test_dd_div():
+    rng = np.random.default_rng(2)
+    for _ in range(2000):
+        a = random_mp(1, 2, rng)[:, 0] * 2.0 ** rng.integers(-30, 30)
+        b = random_mp(1, 2, rng)[:, 0] * 2.0 ** rng.integers(-30, 30)
+        q = ref.dd_div(a, b)
+        ex = _fr(a) / _fr(b)
+        assert abs(_fr(q) - ex) <= abs(ex) / 2 ** 100
+    assert list(ref.dd_div(np.array([6.0, 0.0]), np.array([3.0, 0.0]))) == [2.0, 0.0]
+    assert list(ref.dd_div(np.array([1.0, 0.0]), np.array([4.0, 0.0]))) == [0.25, 0.0]
+
+
+def test_cg_k_distinct_eigenvalues():
+    n = 400
+    eig = np.array([1.0, 2.0, 3.0, 5.0, 8.0])
+    diag = eig[np.arange(n) % eig.size]
+    row_ptr = np.arange(n + 1, dtype=np.int32)
+    col_idx = np.arange(n, dtype=np.int32)
+    a = np.zeros((2, n))
+    a[0] = diag
+    rng = np.random.default_rng(3)
+    b = random_mp(n, 2, rng)
+    x, info = ref.cg(row_ptr, col_idx, a, b, precond="none", rtol=1e-28, max_iter=50)
+    assert info["status"] == 0
+    assert info["iters"] <= eig.size
+
+
+def _certify(row_ptr, col_idx, a, b, x, rtol):
+    """Exact ||b - A x||^2 <= rtol^2 ||b||^2 (rationals)."""
+    n = row_ptr.size - 1
+    ys, _ = exact.exact_row_products(row_ptr, col_idx, a, x)
+    scale = Fraction(1, 2 ** (-exact.E_SCALE))
+    rr = Fraction(0)
+    bb = Fraction(0)
+    for i in range(n):
+        bi = _fr(b[:, i])
+        ri = bi - ys[i] * scale
+        rr += ri * ri
+        bb += bi * bi
+    return rr <= Fraction(rtol) ** 2 * bb * Fraction(101, 100), float(rr / bb) ** 0.5
+
+
+@pytest.mark.parametrize("precond", ["none", "jacobi"])
+def test_cg_known_solution_certified(precond):
+    row_ptr, col_idx, a = diffusion3d_7pt(m=8, sigma=1.0, seed=4)
+    n = row_ptr.size - 1
+    v = sqrt2_vector(n, 2)
+    b = ref.spmv(2, row_ptr, col_idx, a, v)
+    x, info = ref.cg(row_ptr, col_idx, a, b, precond=precond, rtol=1e-28, max_iter=5000)
+    assert info["status"] == 0
+    ok, rel = _certify(row_ptr, col_idx, a, b, x, 1e-28)
+    assert ok, rel
+    # forward error against the known v: within cond(A) times the residual level
+    err = np.max(np.abs((x[0] - v[0]) + (x[1] - v[1]))) / np.max(np.abs(v[0]))
+    assert err < 1e-24
+
+
+def test_bicgstab_nonsymmetric_certified():
+    row_ptr, col_idx, a = banded_nonsymmetric(n=200, seed=5)
+    v = sqrt2_vector(200, 2)
+    b = ref.spmv(2, row_ptr, col_idx, a, v)
+    for precond in ("none", "jacobi"):
+        x, info = ref.bicgstab(row_ptr, col_idx, a, b, precond=precond, rtol=1e-28, max_iter=20000)
+        assert info["status"] == 0
+        ok, rel = _certify(row_ptr, col_idx, a, b, x, 1e-28)
+        assert ok, rel
+
+
+def test_failure_modes():
+    row_ptr, col_idx, a = diffusion3d_7pt(m=6, sigma=1.0, seed=6)
+    n = row_ptr.size - 1
+    rng = np.random.default_rng(7)
+    b = random_mp(n, 2, rng)
+    bad = b.copy()
+    bad[0, 5] = np.nan
+    for solve in (ref.cg, ref.bicgstab):
+        _, info = solve(row_ptr, col_idx, a, bad, rtol=1e-28, max_iter=50)
+        assert info["status"] == -6
+        _, info = solve(row_ptr, col_idx, a, b, rtol=1e-28, max_iter=3)
+        assert info["status"] == -5 and info["iters"] == 3
+    # warm start at the solution: converged without iterating
+    x, info = ref.cg(row_ptr, col_idx, a, b, rtol=1e-20, max_iter=5000)
+    assert info["status"] == 0
+    x2, info2 = ref.cg(row_ptr, col_idx, a, b, x0=x, rtol=1e-20, max_iter=5000)
+    assert info2["status"] == 0 and info2["iters"] == 0 and np.array_equal(x, x2)

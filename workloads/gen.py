@@ -357,3 +357,28 @@ def diffusion3d_7pt(m=64, sigma=2.5, az=1.0, K=2, seed=2):
     row_ptr = np.cumsum(row_ptr)
     assert nface * 2 + n == c.size
     return row_ptr.astype(np.int32), c.astype(np.int32), np.ascontiguousarray(v)
+
+
+def banded_nonsymmetric(n=1000, K=2, seed=3, diag=2.0, lower=-1.015, upper=-0.985, upper2=-0.0009):
+    """Narrow-band non-symmetric matrix shaped like the paper's tub1000 (n = 1000, 3,996
+    nonzeros): bands at offsets -1, 0, +1, +2 (4n - 4 entries), leads
+    diag(1 + 0.01u), lower(1 + 0.01u), upper(1 + 0.01u), upper2(1 + 0.01u) with
+    u ~ U(-1,1) per entry, then K-component tails.  Returns (row_ptr, col_idx, a)."""
+    rng = np.random.default_rng(seed)
+    rows, cols, vals = [], [], []
+    for off, v in ((-1, lower), (0, diag), (1, upper), (2, upper2)):
+        i = np.arange(max(0, -off), min(n, n - off))
+        rows.append(i)
+        cols.append(i + off)
+        vals.append(np.full(i.size, v))
+    r = np.concatenate(rows)
+    c = np.concatenate(cols)
+    v = np.concatenate(vals)
+    order = np.lexsort((c, r))
+    r, c, v = r[order], c[order], v[order]
+    lead = v * (1.0 + 0.01 * rng.uniform(-1.0, 1.0, size=v.size))
+    a = mp_from_leads(lead, K, rng)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(row_ptr, r + 1, 1)
+    row_ptr = np.cumsum(row_ptr)
+    return row_ptr.astype(np.int32), c.astype(np.int32), a
