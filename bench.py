@@ -123,6 +123,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=6.0)
     ap.add_argument("--plan", default="autotune", help="autotune | canonical | shift,max_log2w,tile_nnz")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy 5 times (counter calibration for the traffic figure)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (multi-GPU sharding is a design note, not a "
@@ -130,10 +132,21 @@ def main():
         sys.exit(2)
 
     import torch
+    torch.cuda.set_device(0)
+    if args.calib_copy:
+        n = (1 << 30) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes": n * 8, "copies": 5}))
+        return
+
     from paper_2412_17510_amd import mp
+    from paper_2412_17510_amd.profiling import source_hash
     from workloads import powerlaw_pattern, random_mp, mp_from_leads
 
-    torch.cuda.set_device(0)
     t0 = time.perf_counter()
     row_ptr, col_idx = powerlaw_pattern(n=args.n, seed=1)
     n = row_ptr.size - 1
@@ -189,7 +202,16 @@ def main():
     log("device copy bandwidth %.0f GB/s" % copy_gbs)
     ms, wall, rf, pol = headline
     rf = dict(rf)
+    rf["kernels"] = "one mpspmv_csr_dd call = x staging kernel + tile kernel (timed together)"
     rf["traffic"] = None
+    tfile = os.path.join(ROOT, "profiles", "spmv_dd_powerlaw_traffic.json")
+    if os.path.exists(tfile):
+        with open(tfile) as f:
+            tr = json.load(f)
+        if tr.get("source_hash") == source_hash() and tr.get("plan") == pol and tr.get("n") == n:
+            rf["traffic"] = round(tr["traffic_bytes"])
+            rf["traffic_note"] = "FETCH_SIZE+WRITE_SIZE of the tile kernel per launch, copy-calibrated"
+    rf["algorithmic_bytes"] = algo_bytes(n, nnz, 2, False)
     rf["measured_copy_GBs"] = round(copy_gbs, 1)
     out = {
         "metric": "DD SpMV GNNZ/s (power-law n=1e6, autotuned plan) and % of the binding roofline",
