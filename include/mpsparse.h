@@ -206,6 +206,8 @@ typedef struct {
     double bb[2];        /* DD ||b||^2 */
     double relres;       /* sqrt(rr_true / bb) in binary64 */
     double seconds;      /* wall time of the call */
+    int32_t fell_back;   /* refinement only: 1 if it switched to DD Jacobi-CG (stall or max_outer) */
+    int32_t reserved;
 } mp_solve_info;
 
 /* Bytes of device workspace a solver needs for A and opts (host size_t out). */
@@ -230,6 +232,25 @@ mp_status mpkrylov_cg(const mp_csr *A, const double *a, const double *b, double 
 mp_status mpkrylov_bicgstab(const mp_csr *A, const double *a, const double *b, double *x,
                             const mp_solve_opts *opts, const mp_plan *plan, void *ws, size_t ws_bytes,
                             mp_solve_info *info, void *stream);
+
+/*
+ * Mixed-precision iterative refinement (layer on the paper's method; the paper lists
+ * mixed-precision Krylov methods as future work, Sec. 5).  Outer loop in DD: r = b - A x
+ * with the DD SpMV (plan order) and a DD subtraction; stop when ||r||^2 <= rtol^2
+ * ||b||^2.  Otherwise the inner right-hand side is hi(r) scaled by 2^-e (e = exponent of
+ * max |hi(r)|, an exact scaling) and rounded to the inner precision; the inner solve is
+ * Jacobi-PCG (opts.precond) on hi(A) in binary64 (MP_INNER_FP64) or on fl32(hi(A)) in
+ * binary32 (MP_INNER_FP32), to a residual reduction of opts.inner_rtol or
+ * opts.inner_max_iter iterations, each row of its SpMV summed sequentially and its dot
+ * products in the DD solver's tree shape; then x_i = DDadd(x_i, (d_i 2^e, 0)).  If two
+ * consecutive refinement steps each reduce ||r||^2 by less than 4x, or max_outer steps
+ * pass, the solve continues as DD Jacobi-CG from the current x (opts.max_iter
+ * iterations) and info.fell_back = 1.  Arguments as mpkrylov_cg; A must be SPD for the
+ * inner CG.  Workspace: mpkrylov_workspace_bytes with the same opts (binary32 adds a
+ * copy of hi(A)).
+ */
+mp_status mpkrylov_ir(const mp_csr *A, const double *a, const double *b, double *x, const mp_solve_opts *opts,
+                      const mp_plan *plan, void *ws, size_t ws_bytes, mp_solve_info *info, void *stream);
 
 #ifdef __cplusplus
 }

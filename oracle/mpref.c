@@ -740,3 +740,203 @@ int oracle_bicgstab(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_
     free(r); free(rh); free(p); free(v); free(ph); free(s); free(sh); free(t); free(q);
     return status;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Mixed-precision iterative refinement (DD residual and update, binary64 or  */
+/* binary32 inner Jacobi-PCG on the leading component of A).                   */
+/* ------------------------------------------------------------------------- */
+
+/* Inner plain-precision PCG, written once per type.  SpMV order: each row summed
+ * sequentially in element order (first product, then one add per element).  Dot
+ * products: the DD dot tree's shape (chunks of 4096, W = 256 lanes, halving fold,
+ * pairwise chunk tree) in the inner type.  d starts at 0; stop when ||r||^2 <=
+ * inner_rtol^2 ||r0||^2, or at max_iter, or on breakdown (pq <= 0, non-finite). */
+#define DEFINE_INNER(T, SUF)                                                                        \
+    static T dot_##SUF(int64_t n, const T *x, const T *y)                                          \
+    {                                                                                              \
+        int64_t nch = (n + DOT_CHUNK - 1) / DOT_CHUNK, c, m;                                       \
+        T *P, lanes[DOT_LANES], out;                                                               \
+        if (n == 0) return (T)0;                                                                   \
+        P = (T *)malloc(sizeof(T) * (size_t)nch);                                                  \
+        for (c = 0; c < nch; ++c) {                                                                \
+            int64_t base = c * DOT_CHUNK, cnt = n - base < DOT_CHUNK ? n - base : DOT_CHUNK;      \
+            int l, off, used = cnt < DOT_LANES ? (int)cnt : DOT_LANES;                             \
+            for (l = 0; l < used; ++l) {                                                           \
+                int64_t k = base + l;                                                              \
+                T prod = x[k] * y[k];                                                              \
+                lanes[l] = prod;                                                                   \
+                for (k = k + DOT_LANES; k < base + cnt; k += DOT_LANES) {                          \
+                    prod = x[k] * y[k];                                                            \
+                    lanes[l] = lanes[l] + prod;                                                    \
+                }                                                                                  \
+            }                                                                                      \
+            for (off = DOT_LANES / 2; off >= 1; off /= 2)                                          \
+                for (l = 0; l < off; ++l)                                                          \
+                    if (l + off < used) lanes[l] = lanes[l] + lanes[l + off];                      \
+            P[c] = lanes[0];                                                                       \
+        }                                                                                          \
+        for (m = nch; m > 1; m = (m + 1) / 2) {                                                    \
+            int64_t i;                                                                             \
+            for (i = 0; i < m / 2; ++i) P[i] = P[2 * i] + P[2 * i + 1];                            \
+            if (m % 2) P[m / 2] = P[m - 1];                                                        \
+        }                                                                                          \
+        out = P[0];                                                                                \
+        free(P);                                                                                   \
+        return out;                                                                                \
+    }                                                                                              \
+    static void spmv_##SUF(int64_t n, const int32_t *rp, const int32_t *ci, const T *a, const T *x, T *y) \
+    {                                                                                              \
+        int64_t i;                                                                                 \
+        _Pragma("omp parallel for schedule(static)")                                               \
+        for (i = 0; i < n; ++i) {                                                                  \
+            int64_t k;                                                                             \
+            T s = (T)0;                                                                            \
+            for (k = rp[i]; k < rp[i + 1]; ++k) {                                                  \
+                T prod = a[k] * x[ci[k]];                                                          \
+                s = (k == rp[i]) ? prod : s + prod;                                                \
+            }                                                                                      \
+            y[i] = s;                                                                              \
+        }                                                                                          \
+    }                                                                                              \
+    /* returns iterations; *status: 0 converged, -5 limit, -6 breakdown */                        \
+    static int inner_pcg_##SUF(int64_t n, const int32_t *rp, const int32_t *ci, const T *a,       \
+                               const T *minv, const T *r0, T *d, double inner_rtol, int max_iter,  \
+                               int *status)                                                        \
+    {                                                                                              \
+        size_t bytes = sizeof(T) * (size_t)n;                                                      \
+        T *r = (T *)malloc(bytes), *z = (T *)malloc(bytes), *p = (T *)malloc(bytes),               \
+          *q = (T *)malloc(bytes);                                                                 \
+        T rho, rr, rr0, tol, pq, alpha, beta, rho_new;                                             \
+        int64_t i;                                                                                 \
+        int k = 0;                                                                                 \
+        *status = -5;                                                                              \
+        for (i = 0; i < n; ++i) {                                                                  \
+            d[i] = (T)0;                                                                           \
+            r[i] = r0[i];                                                                          \
+            z[i] = minv ? r[i] * minv[i] : r[i];                                                   \
+            p[i] = z[i];                                                                           \
+        }                                                                                          \
+        rho = dot_##SUF(n, r, z);                                                                  \
+        rr0 = dot_##SUF(n, r, r);                                                                  \
+        tol = (T)(inner_rtol * inner_rtol) * rr0;                                                  \
+        if (rr0 <= tol) *status = 0;                                                               \
+        while (*status == -5 && k < max_iter) {                                                    \
+            spmv_##SUF(n, rp, ci, a, p, q);                                                        \
+            pq = dot_##SUF(n, p, q);                                                               \
+            if (!(pq > (T)0) || !isfinite((double)pq)) { *status = -6; break; }                   \
+            alpha = rho / pq;                                                                      \
+            for (i = 0; i < n; ++i) {                                                              \
+                T ap = alpha * p[i], aq = alpha * q[i];                                            \
+                d[i] = d[i] + ap;                                                                  \
+                r[i] = r[i] - aq;                                                                  \
+                z[i] = minv ? r[i] * minv[i] : r[i];                                               \
+            }                                                                                      \
+            rho_new = dot_##SUF(n, r, z);                                                          \
+            rr = dot_##SUF(n, r, r);                                                               \
+            k++;                                                                                   \
+            if (!isfinite((double)rr) || !isfinite((double)rho_new)) { *status = -6; break; }      \
+            beta = rho_new / rho;                                                                  \
+            rho = rho_new;                                                                         \
+            if (rr <= tol) { *status = 0; break; }                                                 \
+            for (i = 0; i < n; ++i) {                                                              \
+                T bp = beta * p[i];                                                                \
+                p[i] = z[i] + bp;                                                                  \
+            }                                                                                      \
+        }                                                                                          \
+        free(r); free(z); free(p); free(q);                                                        \
+        return k;                                                                                  \
+    }
+
+DEFINE_INNER(double, f64)
+DEFINE_INNER(float, f32)
+
+typedef struct {
+    int32_t status;
+    int32_t iters;        /* inner iterations (+ fallback DD CG iterations) */
+    int32_t outer_iters;
+    int32_t fell_back;
+    double rr_true[2];
+    double bb[2];
+} oracle_ir_info;
+
+/*
+ * Iterative refinement: r = b - A x in DD (DD SpMV in the given order + DD subtract),
+ * stop when ||r||^2 <= rtol^2 ||b||^2 (DD); otherwise e = exponent of max|hi(r)|
+ * (frexp), inner right-hand side hi(r) * 2^-e rounded to the inner type, inner PCG
+ * on hi(A) (binary64) or fl32(hi(A)) (binary32) with Jacobi fl(1/hi(a_ii)) (rounded
+ * to binary32 for the binary32 inner), then x_i = DDadd(x_i, (d_i * 2^e, 0)).
+ * Stall: two consecutive outer steps that each fail to reduce ||r||^2 below a quarter
+ * of the previous value switch to DD Jacobi-CG from the current x (max_iter
+ * iterations); so does reaching max_outer.
+ */
+int oracle_ir(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx, const uint8_t *log2w,
+              const double *a, const double *b, double *x, int inner_fp32, int jacobi, double rtol,
+              double inner_rtol, int32_t inner_max_iter, int32_t max_outer, int32_t max_iter,
+              oracle_ir_info *info)
+{
+    dd_mat M = {n, nnz, row_ptr, col_idx, log2w, a};
+    size_t vb = sizeof(double) * 2 * (size_t)n;
+    double *r = (double *)malloc(vb), *q = (double *)malloc(vb);
+    double *minv = (double *)malloc(sizeof(double) * (size_t)n);
+    double *r64 = (double *)malloc(sizeof(double) * (size_t)n), *d64 = (double *)malloc(sizeof(double) * (size_t)n);
+    float *a32 = NULL, *m32 = NULL, *r32 = NULL, *d32 = NULL;
+    mpv bb, tol2, rr;
+    double prev = 0.0, prev2 = 0.0;
+    int64_t i, k;
+    int outer = 0, stalled = 0, status = -5;
+    memset(info, 0, sizeof(*info));
+    oracle_jacobi_minv(n, row_ptr, col_idx, a, minv);
+    if (inner_fp32) {
+        a32 = (float *)malloc(sizeof(float) * (size_t)(nnz > 0 ? nnz : 1));
+        m32 = (float *)malloc(sizeof(float) * (size_t)n);
+        r32 = (float *)malloc(sizeof(float) * (size_t)n);
+        d32 = (float *)malloc(sizeof(float) * (size_t)n);
+        for (k = 0; k < nnz; ++k) a32[k] = (float)a[k];
+        for (i = 0; i < n; ++i) m32[i] = (float)minv[i];
+    }
+    bb = dd_dot_vec(n, b, b);
+    tol2 = dd_mul_d(bb, rtol * rtol);
+    for (;;) {
+        double mx = 0.0;
+        int e, st, it;
+        dd_residual(&M, b, x, q, r);
+        rr = dd_dot_vec(n, r, r);
+        if (dd_le(rr, tol2)) { status = 0; break; }
+        if (!isfinite(rr.c[0])) { status = -6; break; }
+        if (outer >= 2 && rr.c[0] > 0.25 * prev && prev > 0.25 * prev2) { stalled = 1; break; }
+        if (outer >= max_outer) { stalled = 1; break; }
+        prev2 = prev;
+        prev = rr.c[0];
+        for (i = 0; i < n; ++i) if (fabs(r[i]) > mx) mx = fabs(r[i]);
+        (void)frexp(mx, &e);
+        if (inner_fp32) {
+            for (i = 0; i < n; ++i) r32[i] = (float)ldexp(r[i], -e);
+            it = inner_pcg_f32(n, row_ptr, col_idx, a32, jacobi ? m32 : NULL, r32, d32, inner_rtol, inner_max_iter, &st);
+            for (i = 0; i < n; ++i) d64[i] = (double)d32[i];
+        } else {
+            for (i = 0; i < n; ++i) r64[i] = ldexp(r[i], -e);
+            it = inner_pcg_f64(n, row_ptr, col_idx, a, jacobi ? minv : NULL, r64, d64, inner_rtol, inner_max_iter, &st);
+        }
+        info->iters += it;
+        for (i = 0; i < n; ++i) {
+            mpv dv = {{ldexp(d64[i], e), 0.0, 0.0, 0.0}};
+            st2(x, n, i, dd_add(ld2(x, n, i), dv));
+        }
+        outer++;
+    }
+    info->outer_iters = outer;
+    if (stalled) {
+        oracle_solve_info ci;
+        info->fell_back = 1;
+        status = oracle_cg(n, nnz, row_ptr, col_idx, log2w, a, b, x, jacobi ? minv : NULL, rtol, max_iter, &ci, NULL);
+        info->iters += ci.iters;
+    }
+    dd_residual(&M, b, x, q, r);
+    rr = dd_dot_vec(n, r, r);
+    info->status = status;
+    info->rr_true[0] = rr.c[0]; info->rr_true[1] = rr.c[1];
+    info->bb[0] = bb.c[0]; info->bb[1] = bb.c[1];
+    free(r); free(q); free(minv); free(r64); free(d64);
+    free(a32); free(m32); free(r32); free(d32);
+    return status;
+}

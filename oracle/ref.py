@@ -200,3 +200,34 @@ def bicgstab(row_ptr, col_idx, a, b, x0=None, precond="jacobi", rtol=1e-28, max_
              history=False):
     """DD BiCGSTAB (oracle).  Returns (x, info dict)."""
     return _solve("oracle_bicgstab", row_ptr, col_idx, a, b, x0, precond, rtol, max_iter, log2w, history)
+
+
+class IrInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("outer_iters", ctypes.c_int32),
+                ("fell_back", ctypes.c_int32), ("rr_true", ctypes.c_double * 2), ("bb", ctypes.c_double * 2)]
+
+
+def ir(row_ptr, col_idx, a, b, x0=None, inner="fp64", precond="jacobi", rtol=1e-28, inner_rtol=1e-8,
+       inner_max_iter=1000, max_outer=50, max_iter=10000, log2w=None):
+    """Mixed-precision iterative refinement (oracle).  Returns (x, info dict)."""
+    L = _krylov_sigs()
+    if not getattr(L, "_ir_ready", False):
+        P = ctypes.c_void_p
+        i64 = ctypes.c_int64
+        L.oracle_ir.argtypes = [i64, i64, P, P, P, P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                ctypes.POINTER(IrInfo)]
+        L.oracle_ir.restype = ctypes.c_int
+        L._ir_ready = True
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
+    a, b = _f64(a), _f64(b)
+    n = row_ptr.size - 1
+    x = np.array(x0, dtype=np.float64, order="C", copy=True) if x0 is not None else np.zeros((2, n))
+    lw = None if log2w is None else np.ascontiguousarray(log2w, dtype=np.uint8)
+    info = IrInfo()
+    L.oracle_ir(n, col_idx.size, _p(row_ptr), _p(col_idx), _p(lw), _p(a), _p(b), _p(x), int(inner == "fp32"),
+                int(precond == "jacobi"), float(rtol), float(inner_rtol), int(inner_max_iter), int(max_outer),
+                int(max_iter), ctypes.byref(info))
+    return x, {"status": info.status, "iters": info.iters, "outer_iters": info.outer_iters,
+               "fell_back": info.fell_back, "rr_true": np.array(info.rr_true[:]), "bb": np.array(info.bb[:])}

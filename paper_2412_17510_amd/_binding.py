@@ -46,7 +46,8 @@ class mp_solve_opts(ctypes.Structure):
 class mp_solve_info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("outer_iters", ctypes.c_int32),
                 ("restarts", ctypes.c_int32), ("rr_true", ctypes.c_double * 2), ("bb", ctypes.c_double * 2),
-                ("relres", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("relres", ctypes.c_double), ("seconds", ctypes.c_double), ("fell_back", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 PRECOND = {"none": 0, "jacobi": 1}
@@ -79,7 +80,7 @@ for _name in ("mpspmv_csr_dd_complex", "mpspmv_csr_td_complex", "mpspmv_csr_qd_c
 
 _SIGS["mpkrylov_workspace_bytes"] = ([_CSR, ctypes.POINTER(mp_solve_opts), ctypes.POINTER(ctypes.c_size_t)],
                                      ctypes.c_int)
-for _name in ("mpkrylov_cg", "mpkrylov_bicgstab"):
+for _name in ("mpkrylov_cg", "mpkrylov_bicgstab", "mpkrylov_ir"):
     _SIGS[_name] = ([_CSR, _P, _P, _P, ctypes.POINTER(mp_solve_opts), _P, _P, ctypes.c_size_t,
                      ctypes.POINTER(mp_solve_info), _P], ctypes.c_int)
 
@@ -273,7 +274,7 @@ def _opts(precond="jacobi", rtol=1e-28, max_iter=10000, check_every=32, inner="f
 def _info_dict(info):
     return {"status": info.status, "iters": info.iters, "outer_iters": info.outer_iters,
             "restarts": info.restarts, "rr_true": np.array(info.rr_true[:]), "bb": np.array(info.bb[:]),
-            "relres": info.relres, "seconds": info.seconds}
+            "relres": info.relres, "seconds": info.seconds, "fell_back": info.fell_back}
 
 
 def mpkrylov_workspace_bytes(A, **opts):
@@ -315,3 +316,4 @@ def _solver(name):
 
 mpkrylov_cg = _solver("mpkrylov_cg")
 mpkrylov_bicgstab = _solver("mpkrylov_bicgstab")
+mpkrylov_ir = _solver("mpkrylov_ir")

@@ -547,6 +547,314 @@ __global__ __launch_bounds__(256) void k_bi_rr(const dd_t *__restrict__ part, in
 }
 
 // ---------------------------------------------------------------------------
+// mixed-precision iterative refinement: plain-precision inner PCG (T = double or
+// float) on hi(A), in the same reduction shapes as the DD solver
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct InState {
+    T rho, rr, rr0, tol, pq, alpha, beta;
+    int32_t done;
+    int32_t iters;
+    int32_t max_iter;
+    int32_t pad;
+    double maxabs;   // max |hi(r)| of the current DD residual (outer loop)
+};
+
+template <typename T>
+__device__ __forceinline__ T chunk_fold_t(T v, int used, T *lds)
+{
+    const int t = threadIdx.x;
+    lds[t] = v;
+    __syncthreads();
+    for (int off = kDotLanes / 2; off >= 1; off >>= 1) {
+        if (t < off && t + off < used) lds[t] = lds[t] + lds[t + off];
+        __syncthreads();
+    }
+    const T r = lds[0];
+    __syncthreads();
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ T pair_tree_t(const T *__restrict__ part, int m, T *P)
+{
+    const int t = threadIdx.x;
+    for (int i = t; i < m; i += kDotLanes) P[i] = part[i];
+    __syncthreads();
+    for (int s = 1; s < m; s <<= 1) {
+        for (int i = t; (int64_t)i * 2 * s + s < m; i += kDotLanes) P[i * 2 * s] = P[i * 2 * s] + P[i * 2 * s + s];
+        __syncthreads();
+    }
+    const T r = m > 0 ? P[0] : T(0);
+    __syncthreads();
+    return r;
+}
+
+// inner right-hand side: hi(r) * 2^-e rounded to T
+template <typename T>
+__global__ __launch_bounds__(256) void k_in_stage(int64_t n, const double *__restrict__ r_dd, int e,
+                                                  T *__restrict__ r0)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        r0[i] = (T)ldexp(r_dd[i], -e);
+}
+
+// d = 0, r = r0, z = M^-1 r, p = z
+template <typename T>
+__global__ __launch_bounds__(256) void k_in_init(int64_t n, const T *__restrict__ r0, const T *__restrict__ minv,
+                                                 T *__restrict__ d, T *__restrict__ r, T *__restrict__ z,
+                                                 T *__restrict__ p)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const T ri = r0[i];
+        const T zi = minv ? ri * minv[i] : ri;
+        d[i] = T(0);
+        r[i] = ri;
+        z[i] = zi;
+        p[i] = zi;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_in_dot2(int64_t n, const T *__restrict__ x1, const T *__restrict__ y1,
+                                                 const T *__restrict__ x2, const T *__restrict__ y2,
+                                                 T *__restrict__ part1, T *__restrict__ part2,
+                                                 const InState<T> *__restrict__ st)
+{
+    __shared__ T lds[kDotLanes];
+    if (st && st->done != RUN) return;
+    const int c = blockIdx.x;
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)c * kDotChunk;
+    const int64_t end = (n - base) < kDotChunk ? n : base + kDotChunk;
+    const int used = chunk_used(n, c);
+    T a1 = T(0), a2 = T(0);
+    if (t < used) {
+        int64_t k = base + t;
+        a1 = x1[k] * y1[k];
+        if (x2) a2 = x2[k] * y2[k];
+        for (k += kDotLanes; k < end; k += kDotLanes) {
+            const T p1 = x1[k] * y1[k];
+            a1 = a1 + p1;
+            if (x2) {
+                const T p2 = x2[k] * y2[k];
+                a2 = a2 + p2;
+            }
+        }
+    }
+    const T s1 = chunk_fold_t(a1, used, lds);
+    if (t == 0) part1[c] = s1;
+    if (x2) {
+        const T s2 = chunk_fold_t(a2, used, lds);
+        if (t == 0) part2[c] = s2;
+    }
+}
+
+// rho = (r, z), rr0 = (r, r), tolerance
+template <typename T>
+__global__ __launch_bounds__(256) void k_in_start(const T *__restrict__ prz, const T *__restrict__ prr, int m,
+                                                  T irt2, int32_t max_iter, InState<T> *__restrict__ st)
+{
+    __shared__ T P[kMaxChunks];
+    const T rz = pair_tree_t(prz, m, P);
+    const T rr = pair_tree_t(prr, m, P);
+    if (threadIdx.x == 0) {
+        st->rho = rz;
+        st->rr0 = rr;
+        st->rr = rr;
+        st->tol = irt2 * rr;
+        st->iters = 0;
+        st->max_iter = max_iter;
+        st->done = rr <= st->tol ? CONFIRMED : (max_iter <= 0 ? ITER_LIMIT : RUN);
+    }
+}
+
+// y = A x with each row summed sequentially (one thread per row)
+template <typename T>
+__global__ __launch_bounds__(256) void k_in_spmv(int64_t n, const int32_t *__restrict__ rp,
+                                                 const int32_t *__restrict__ ci, const T *__restrict__ a,
+                                                 const T *__restrict__ x, T *__restrict__ y,
+                                                 const InState<T> *__restrict__ st)
+{
+    if (st->done != RUN) return;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const int32_t b = rp[i], e = rp[i + 1];
+        T s = T(0);
+        for (int32_t k = b; k < e; ++k) {
+            const T prod = a[k] * x[ci[k]];
+            s = (k == b) ? prod : s + prod;
+        }
+        y[i] = s;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_in_alpha(const T *__restrict__ ppq, int m, InState<T> *__restrict__ st)
+{
+    __shared__ T P[kMaxChunks];
+    if (st->done != RUN) return;
+    const T pq = pair_tree_t(ppq, m, P);
+    if (threadIdx.x == 0) {
+        st->pq = pq;
+        if (!(pq > T(0)) || !isfinite((double)pq))
+            st->done = BROKE_DOWN;
+        else
+            st->alpha = st->rho / pq;
+    }
+}
+
+// d += alpha p; r -= alpha q; z = M^-1 r; chunk sums of (r, z), (r, r)
+template <typename T>
+__global__ __launch_bounds__(256) void k_in_update(int64_t n, T *__restrict__ d, T *__restrict__ r,
+                                                   T *__restrict__ z, const T *__restrict__ p,
+                                                   const T *__restrict__ q, const T *__restrict__ minv,
+                                                   T *__restrict__ prz, T *__restrict__ prr,
+                                                   const InState<T> *__restrict__ st)
+{
+    __shared__ T lds[kDotLanes];
+    if (st->done != RUN) return;
+    const T alpha = st->alpha;
+    const int c = blockIdx.x;
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)c * kDotChunk;
+    const int64_t end = (n - base) < kDotChunk ? n : base + kDotChunk;
+    const int used = chunk_used(n, c);
+    T arz = T(0), arr = T(0);
+    bool first = true;
+    for (int64_t k = base + t; k < end; k += kDotLanes) {
+        const T ap = alpha * p[k];
+        const T aq = alpha * q[k];
+        d[k] = d[k] + ap;
+        const T rk = r[k] - aq;
+        r[k] = rk;
+        const T zk = minv ? rk * minv[k] : rk;
+        z[k] = zk;
+        const T p1 = rk * zk;
+        const T p2 = rk * rk;
+        if (first) {
+            arz = p1;
+            arr = p2;
+            first = false;
+        } else {
+            arz = arz + p1;
+            arr = arr + p2;
+        }
+    }
+    const T s1 = chunk_fold_t(arz, used, lds);
+    const T s2 = chunk_fold_t(arr, used, lds);
+    if (t == 0) {
+        prz[c] = s1;
+        prr[c] = s2;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_in_beta(const T *__restrict__ prz, const T *__restrict__ prr, int m,
+                                                 InState<T> *__restrict__ st)
+{
+    __shared__ T P[kMaxChunks];
+    if (st->done != RUN) return;
+    const T rz = pair_tree_t(prz, m, P);
+    const T rr = pair_tree_t(prr, m, P);
+    if (threadIdx.x == 0) {
+        st->iters += 1;
+        st->rr = rr;
+        if (!isfinite((double)rr) || !isfinite((double)rz)) {
+            st->done = BROKE_DOWN;
+            return;
+        }
+        st->beta = rz / st->rho;
+        st->rho = rz;
+        if (rr <= st->tol)
+            st->done = CONFIRMED;
+        else if (st->iters >= st->max_iter)
+            st->done = ITER_LIMIT;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_in_p(int64_t n, const T *__restrict__ z, T *__restrict__ p,
+                                              const InState<T> *__restrict__ st)
+{
+    if (st->done != RUN) return;
+    const T beta = st->beta;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const T bp = beta * p[i];
+        p[i] = z[i] + bp;
+    }
+}
+
+// x_i = DDadd(x_i, (d_i * 2^e, 0))
+template <typename T>
+__global__ __launch_bounds__(256) void k_ir_update(int64_t n, double *__restrict__ x, const T *__restrict__ d, int e)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        dd_t dv;
+        dv.c[0] = ldexp((double)d[i], e);
+        dv.c[1] = 0.0;
+        sdd(x, n, i, dd_add(ldd(x, n, i), dv));
+    }
+}
+
+// max |v_i| per chunk of 4096 (exact, order-free)
+__global__ __launch_bounds__(256) void k_maxabs(int64_t n, const double *__restrict__ v, double *__restrict__ part)
+{
+    __shared__ double lds[kDotLanes];
+    const int c = blockIdx.x;
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)c * kDotChunk;
+    const int64_t end = (n - base) < kDotChunk ? n : base + kDotChunk;
+    double m = 0.0;
+    for (int64_t k = base + t; k < end; k += kDotLanes) m = fmax(m, fabs(v[k]));
+    lds[t] = m;
+    __syncthreads();
+    for (int off = kDotLanes / 2; off >= 1; off >>= 1) {
+        if (t < off) lds[t] = fmax(lds[t], lds[t + off]);
+        __syncthreads();
+    }
+    if (t == 0) part[c] = lds[0];
+}
+
+__global__ __launch_bounds__(256) void k_maxabs_final(const double *__restrict__ part, int m, double *__restrict__ out)
+{
+    __shared__ double lds[kDotLanes];
+    const int t = threadIdx.x;
+    double v = 0.0;
+    for (int i = t; i < m; i += kDotLanes) v = fmax(v, part[i]);
+    lds[t] = v;
+    __syncthreads();
+    for (int off = kDotLanes / 2; off >= 1; off >>= 1) {
+        if (t < off) lds[t] = fmax(lds[t], lds[t + off]);
+        __syncthreads();
+    }
+    if (t == 0) *out = lds[0];
+}
+
+__global__ __launch_bounds__(256) void k_to_f32(int64_t n, const double *__restrict__ src, float *__restrict__ dst)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) dst[i] = (float)src[i];
+}
+
+// bb and tolerance of the refinement, rr of the current residual
+__global__ __launch_bounds__(256) void k_ir_norms(const dd_t *__restrict__ pbb, const dd_t *__restrict__ prr, int m,
+                                                  double rtol2, int first, KState *__restrict__ st)
+{
+    __shared__ dd_t P[kMaxChunks];
+    const dd_t rr = pair_tree(prr, m, P);
+    dd_t bb = dd_zero();
+    if (first) bb = pair_tree(pbb, m, P);
+    if (threadIdx.x == 0) {
+        if (first) {
+            st->bb = bb;
+            st->tol2 = dd_mul_d(bb, rtol2);
+        }
+        st->rr = rr;
+        st->rr_true = rr;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // host driver
 // ---------------------------------------------------------------------------
 
@@ -555,16 +863,20 @@ struct Workspace {
     double *minv;
     double *v[9];
     dd_t *part[3];
+    void *inner;   // InState<T>
+    float *a32;
 };
 
 inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-size_t workspace_bytes(int64_t n)
+size_t workspace_bytes(int64_t n, int64_t nnz_f32 = 0)
 {
     size_t b = align256(sizeof(KState));
     b += align256(sizeof(double) * (size_t)n);
     b += 9 * align256(sizeof(double) * 2 * (size_t)n);
     b += 3 * align256(sizeof(dd_t) * kMaxChunks);
+    b += 256;                                         // inner-solver state
+    b += align256(sizeof(float) * (size_t)nnz_f32);   // binary32 copy of hi(A)
     return b;
 }
 
@@ -584,6 +896,9 @@ Workspace carve(void *ws, int64_t n)
         w.part[i] = reinterpret_cast<dd_t *>(p);
         p += align256(sizeof(dd_t) * kMaxChunks);
     }
+    w.inner = p;
+    p += 256;
+    w.a32 = reinterpret_cast<float *>(p);
     return w;
 }
 
@@ -647,7 +962,7 @@ struct Solver {
 };
 
 mp_status check_solver_args(const char *name, const mp_csr *A, const double *a, const double *b, const double *x,
-                            const mp_solve_opts *opts, const mp_plan *plan, void *ws, size_t ws_bytes,
+                            const mp_solve_opts *opts, const mp_plan *plan, void *ws, size_t ws_bytes, size_t need,
                             mp_solve_info *info)
 {
     mp_status st = check_csr(A);
@@ -659,9 +974,8 @@ mp_status check_solver_args(const char *name, const mp_csr *A, const double *a, 
     if ((int64_t)A->n_rows > (int64_t)kMaxChunks * kDotChunk)
         return fail(MP_ERR_UNSUPPORTED, "%s: n = %d exceeds the solver limit %d", name, A->n_rows,
                     kMaxChunks * kDotChunk);
-    if (ws_bytes < workspace_bytes(A->n_rows))
-        return fail(MP_ERR_NO_MEMORY, "%s: workspace of %zu bytes, %zu needed", name, ws_bytes,
-                    workspace_bytes(A->n_rows));
+    if (ws_bytes < need)
+        return fail(MP_ERR_NO_MEMORY, "%s: workspace of %zu bytes, %zu needed", name, ws_bytes, need);
     if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(MP_ERR_INVALID_ARG, "%s: workspace must be 256-byte aligned", name);
     if (opts->precond != MP_PRECOND_NONE && opts->precond != MP_PRECOND_JACOBI)
         return fail(MP_ERR_INVALID_ARG, "%s: unknown preconditioner %d", name, opts->precond);
@@ -687,6 +1001,7 @@ void fill_info(const KState &h, int status, double secs, mp_solve_info *info)
     info->bb[1] = h.bb.c[1];
     info->relres = h.bb.c[0] > 0 ? std::sqrt(h.rr_true.c[0] / h.bb.c[0]) : std::sqrt(h.rr_true.c[0]);
     info->seconds = secs;
+    info->fell_back = 0;
 }
 
 mp_status run_cg(Solver &S, const double *b, double *x, const mp_solve_opts *o, mp_solve_info *info)
@@ -833,12 +1148,155 @@ mp_status run_bicgstab(Solver &S, const double *b, double *x, const mp_solve_opt
     return MP_OK;
 }
 
-mp_status solve_entry(const char *name, bool bicg, const mp_csr *A, const double *a, const double *b, double *x,
+template <typename T>
+mp_status inner_solve(Solver &S, const double *r_dd, int e, const T *a_in, const T *minv, T *d, double inner_rtol,
+                      int max_iter, int every, int *iters, int *status)
+{
+    const int64_t n = S.n;
+    const int m = S.m;
+    InState<T> *ist = static_cast<InState<T> *>(S.w.inner);
+    T *r0 = reinterpret_cast<T *>(S.w.v[5]);
+    T *r = r0 + n, *z = reinterpret_cast<T *>(S.w.v[6]), *p = z + n, *q = reinterpret_cast<T *>(S.w.v[7]);
+    T *part0 = reinterpret_cast<T *>(S.w.part[0]), *part1 = reinterpret_cast<T *>(S.w.part[1]);
+    T *part2 = reinterpret_cast<T *>(S.w.part[2]);
+    mp_status st;
+    hipLaunchKernelGGL(k_in_stage<T>, dim3(S.vblocks), dim3(256), 0, S.s, n, r_dd, e, r0);
+    hipLaunchKernelGGL(k_in_init<T>, dim3(S.vblocks), dim3(256), 0, S.s, n, r0, minv, d, r, z, p);
+    hipLaunchKernelGGL(k_in_dot2<T>, dim3(m), dim3(256), 0, S.s, n, r, z, r, r, part1, part2, nullptr);
+    hipLaunchKernelGGL(k_in_start<T>, dim3(1), dim3(256), 0, S.s, part1, part2, m, (T)(inner_rtol * inner_rtol),
+                       max_iter, ist);
+    if ((st = S.launched()) != MP_OK) return st;
+    InState<T> h;
+    for (;;) {
+        MP_HIP_TRY(hipMemcpyAsync(&h, ist, sizeof(h), hipMemcpyDeviceToHost, S.s));
+        MP_HIP_TRY(hipStreamSynchronize(S.s));
+        if (h.done != RUN) break;
+        for (int it = 0; it < every; ++it) {
+            hipLaunchKernelGGL(k_in_spmv<T>, dim3(S.vblocks), dim3(256), 0, S.s, n, S.A->row_ptr, S.A->col_idx,
+                               a_in, p, q, ist);
+            hipLaunchKernelGGL(k_in_dot2<T>, dim3(m), dim3(256), 0, S.s, n, p, q, nullptr, nullptr, part0, nullptr,
+                               ist);
+            hipLaunchKernelGGL(k_in_alpha<T>, dim3(1), dim3(256), 0, S.s, part0, m, ist);
+            hipLaunchKernelGGL(k_in_update<T>, dim3(m), dim3(256), 0, S.s, n, d, r, z, p, q, minv, part1, part2, ist);
+            hipLaunchKernelGGL(k_in_beta<T>, dim3(1), dim3(256), 0, S.s, part1, part2, m, ist);
+            hipLaunchKernelGGL(k_in_p<T>, dim3(S.vblocks), dim3(256), 0, S.s, n, z, p, ist);
+            if ((st = S.launched()) != MP_OK) return st;
+        }
+    }
+    *iters = h.iters;
+    *status = h.done == CONFIRMED ? MP_OK : (h.done == BROKE_DOWN ? MP_ERR_BREAKDOWN : MP_ERR_NOT_CONVERGED);
+    return MP_OK;
+}
+
+template <typename T>
+mp_status run_ir_t(Solver &S, const double *b, double *x, const mp_solve_opts *o, mp_solve_info *info)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    const int64_t n = S.n;
+    const int m = S.m;
+    const bool jacobi = o->precond == MP_PRECOND_JACOBI;
+    const int every = o->check_every > 0 ? o->check_every : 32;
+    const int inner_max = o->inner_max_iter > 0 ? o->inner_max_iter : o->max_iter;
+    double *r = S.w.v[0], *q = S.w.v[3];
+    T *d = reinterpret_cast<T *>(S.w.v[4]);
+    T *minvT = reinterpret_cast<T *>(S.w.v[8]);
+    double *maxpart = reinterpret_cast<double *>(S.w.v[8]) + n;   // after the inner inverse diagonal
+    double *maxabs = &static_cast<InState<T> *>(S.w.inner)->maxabs;
+    const T *a_in;
+    mp_status st;
+    MP_HIP_TRY(hipMemsetAsync(S.w.st, 0, sizeof(KState), S.s));
+    hipLaunchKernelGGL(k_jacobi_minv, dim3(S.vblocks), dim3(256), 0, S.s, n, S.A->row_ptr, S.A->col_idx, S.a,
+                       S.w.minv);
+    if constexpr (sizeof(T) == 4) {
+        hipLaunchKernelGGL(k_to_f32, dim3(S.vblocks), dim3(256), 0, S.s, n, S.w.minv, reinterpret_cast<float *>(minvT));
+        const int64_t ab = (S.A->nnz + 255) / 256;
+        if (S.A->nnz > 0)
+            hipLaunchKernelGGL(k_to_f32, dim3((unsigned)(ab < 8192 ? ab : 8192)), dim3(256), 0, S.s, S.A->nnz, S.a,
+                               S.w.a32);
+        a_in = reinterpret_cast<const T *>(S.w.a32);
+    } else {
+        hipLaunchKernelGGL(k_copy, dim3(S.vblocks), dim3(256), 0, S.s, n, S.w.minv, reinterpret_cast<double *>(minvT));
+        a_in = reinterpret_cast<const T *>(S.a);
+    }
+    if ((st = S.launched()) != MP_OK) return st;
+    const T *minv_in = jacobi ? minvT : nullptr;
+    KState h;
+    std::memset(&h, 0, sizeof(h));
+    int outer = 0, status = MP_ERR_NOT_CONVERGED, total_inner = 0;
+    bool stalled = false;
+    double prev = 0.0, prev2 = 0.0;
+    for (;;) {
+        if ((st = S.residual(b, x, q, r)) != MP_OK) return st;
+        if ((st = S.dot2(r, r, b, b, S.w.part[1], S.w.part[0], nullptr)) != MP_OK) return st;
+        hipLaunchKernelGGL(k_ir_norms, dim3(1), dim3(256), 0, S.s, S.w.part[0], S.w.part[1], m, o->rtol * o->rtol,
+                           outer == 0 ? 1 : 0, S.w.st);
+        hipLaunchKernelGGL(k_maxabs, dim3(m), dim3(256), 0, S.s, n, r, maxpart);
+        hipLaunchKernelGGL(k_maxabs_final, dim3(1), dim3(256), 0, S.s, maxpart, m, maxabs);
+        if ((st = S.launched()) != MP_OK) return st;
+        if ((st = S.read_state(&h)) != MP_OK) return st;
+        double mx = 0.0;
+        MP_HIP_TRY(hipMemcpyAsync(&mx, maxabs, sizeof(double), hipMemcpyDeviceToHost, S.s));
+        MP_HIP_TRY(hipStreamSynchronize(S.s));
+        const double rr[2] = {h.rr.c[0], h.rr.c[1]}, tol2[2] = {h.tol2.c[0], h.tol2.c[1]};
+        if (host_dd_le(rr, tol2)) {
+            status = MP_OK;
+            break;
+        }
+        if (!std::isfinite(rr[0])) {
+            status = MP_ERR_BREAKDOWN;
+            break;
+        }
+        if ((outer >= 2 && rr[0] > 0.25 * prev && prev > 0.25 * prev2) || outer >= o->max_outer) {
+            stalled = true;
+            break;
+        }
+        prev2 = prev;
+        prev = rr[0];
+        int e = 0;
+        (void)std::frexp(mx, &e);
+        int it = 0, ist = 0;
+        if ((st = inner_solve<T>(S, r, e, a_in, minv_in, d, o->inner_rtol, inner_max, every, &it, &ist)) != MP_OK)
+            return st;
+        total_inner += it;
+        hipLaunchKernelGGL(k_ir_update<T>, dim3(S.vblocks), dim3(256), 0, S.s, n, x, d, e);
+        if ((st = S.launched()) != MP_OK) return st;
+        outer++;
+    }
+    int fell_back = 0, restarts = 0;
+    if (stalled) {
+        mp_solve_opts co = *o;
+        mp_solve_info ci;
+        fell_back = 1;
+        st = run_cg(S, b, x, &co, &ci);
+        if (st != MP_OK && st != MP_ERR_NOT_CONVERGED && st != MP_ERR_BREAKDOWN) return st;
+        status = ci.status;
+        total_inner += ci.iters;
+        restarts = ci.restarts;
+    }
+    if ((st = S.true_residual(b, x, q, r, false)) != MP_OK) return st;
+    if ((st = S.read_state(&h)) != MP_OK) return st;
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    fill_info(h, status, secs, info);
+    info->iters = total_inner;
+    info->outer_iters = outer;
+    info->restarts = restarts;
+    info->fell_back = fell_back;
+    clear_error();
+    if (status == MP_ERR_NOT_CONVERGED) return fail(MP_ERR_NOT_CONVERGED, "mpkrylov_ir: not converged");
+    if (status == MP_ERR_BREAKDOWN) return fail(MP_ERR_BREAKDOWN, "mpkrylov_ir: breakdown");
+    return MP_OK;
+}
+
+mp_status solve_entry(const char *name, int kind, const mp_csr *A, const double *a, const double *b, double *x,
                       const mp_solve_opts *opts, const mp_plan *plan, void *ws, size_t ws_bytes, mp_solve_info *info,
                       void *stream)
 {
     clear_error();
-    mp_status st = check_solver_args(name, A, a, b, x, opts, plan, ws, ws_bytes, info);
+    if (kind == 2 && opts && opts->inner != MP_INNER_FP64 && opts->inner != MP_INNER_FP32)
+        return fail(MP_ERR_INVALID_ARG, "%s: unknown inner precision %d", name, opts->inner);
+    const size_t need = (A && opts && kind == 2 && opts->inner == MP_INNER_FP32) ? workspace_bytes(A->n_rows, A->nnz)
+                                                                                  : (A ? workspace_bytes(A->n_rows) : 0);
+    mp_status st = check_solver_args(name, A, a, b, x, opts, plan, ws, ws_bytes, need, info);
     if (st != MP_OK) return st;
     if (A->n_rows == 0) {
         std::memset(info, 0, sizeof(*info));
@@ -854,7 +1312,9 @@ mp_status solve_entry(const char *name, bool bicg, const mp_csr *A, const double
     const int64_t vb = (S.n + 255) / 256;
     S.vblocks = (unsigned)(vb < 8192 ? vb : 8192);
     S.w = carve(ws, S.n);
-    return bicg ? run_bicgstab(S, b, x, opts, info) : run_cg(S, b, x, opts, info);
+    if (kind == 0) return run_cg(S, b, x, opts, info);
+    if (kind == 1) return run_bicgstab(S, b, x, opts, info);
+    return opts->inner == MP_INNER_FP32 ? run_ir_t<float>(S, b, x, opts, info) : run_ir_t<double>(S, b, x, opts, info);
 }
 
 }  // namespace mpk
@@ -864,24 +1324,30 @@ extern "C" {
 mp_status mpkrylov_workspace_bytes(const mp_csr *A, const mp_solve_opts *opts, size_t *bytes)
 {
     mpk::clear_error();
-    (void)opts;
     mp_status st = mpk::check_csr(A);
     if (st != MP_OK) return st;
     if (!bytes) return mpk::fail(MP_ERR_INVALID_ARG, "bytes is NULL");
-    *bytes = mpk::workspace_bytes(A->n_rows);
+    *bytes = (opts && opts->inner == MP_INNER_FP32) ? mpk::workspace_bytes(A->n_rows, A->nnz)
+                                                    : mpk::workspace_bytes(A->n_rows);
     return MP_OK;
 }
 
 mp_status mpkrylov_cg(const mp_csr *A, const double *a, const double *b, double *x, const mp_solve_opts *opts,
                       const mp_plan *plan, void *ws, size_t ws_bytes, mp_solve_info *info, void *stream)
 {
-    return mpk::solve_entry("mpkrylov_cg", false, A, a, b, x, opts, plan, ws, ws_bytes, info, stream);
+    return mpk::solve_entry("mpkrylov_cg", 0, A, a, b, x, opts, plan, ws, ws_bytes, info, stream);
 }
 
 mp_status mpkrylov_bicgstab(const mp_csr *A, const double *a, const double *b, double *x, const mp_solve_opts *opts,
                             const mp_plan *plan, void *ws, size_t ws_bytes, mp_solve_info *info, void *stream)
 {
-    return mpk::solve_entry("mpkrylov_bicgstab", true, A, a, b, x, opts, plan, ws, ws_bytes, info, stream);
+    return mpk::solve_entry("mpkrylov_bicgstab", 1, A, a, b, x, opts, plan, ws, ws_bytes, info, stream);
+}
+
+mp_status mpkrylov_ir(const mp_csr *A, const double *a, const double *b, double *x, const mp_solve_opts *opts,
+                      const mp_plan *plan, void *ws, size_t ws_bytes, mp_solve_info *info, void *stream)
+{
+    return mpk::solve_entry("mpkrylov_ir", 2, A, a, b, x, opts, plan, ws, ws_bytes, info, stream);
 }
 
 }  // extern "C"
