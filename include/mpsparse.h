@@ -252,6 +252,60 @@ mp_status mpkrylov_bicgstab(const mp_csr *A, const double *a, const double *b, d
 mp_status mpkrylov_ir(const mp_csr *A, const double *a, const double *b, double *x, const mp_solve_opts *opts,
                       const mp_plan *plan, void *ws, size_t ws_bytes, mp_solve_info *info, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Batched systems (layer on the paper's method): nsys independent square systems
+ * stored as the diagonal blocks of ONE block-diagonal CSR matrix A (system s owns rows
+ * and columns [sys_ptr[s], sys_ptr[s+1]); no entry outside its block), each with nrhs
+ * right-hand sides (nrhs in {1, 2, 4, 8}).  Multi-RHS arrays are DD, component-major,
+ * right-hand sides fastest: V[c*N*nrhs + row*nrhs + r] (N = n_rows, c in {0, 1}).
+ * Every row of the batched SpMM is summed sequentially in element order (the SpMV
+ * order with W = 1), so results equal separate mpspmv_csr_dd calls with a plan whose
+ * lane widths are all 1, and the batched CG equals separate mpkrylov_cg calls (one per
+ * system and right-hand side) with such a plan, bit for bit.
+ * ------------------------------------------------------------------------- */
+
+/* Opaque batch schedule: the system table, the per-system chunks of the dot products
+ * and the SpMM thread mapping (threads per row).  Owned by the library. */
+typedef struct mp_batch_plan mp_batch_plan;
+
+/* Build a batch plan.  sys_ptr_host: host int32[nsys+1], sys_ptr[0] = 0, strictly
+ * increasing, sys_ptr[nsys] = n_rows.  threads_per_row: power of two <= nrhs (each
+ * thread computes nrhs/threads_per_row right-hand sides of one row).  Checks on the
+ * device that A is block-diagonal (MP_ERR_INVALID_ARG otherwise).  Synchronises. */
+mp_status mp_batch_plan_create(const mp_csr *A, const int32_t *sys_ptr_host, int32_t nsys, int32_t nrhs,
+                               int32_t threads_per_row, void *stream, mp_batch_plan **out);
+
+/* Time the SpMM for every threads-per-row choice on the caller's operands (X read,
+ * Y overwritten) and keep the fastest in the plan (*threads_per_row, host, may be
+ * NULL).  Synchronises. */
+mp_status mp_batch_plan_autotune(mp_batch_plan *plan, const mp_csr *A, const double *a, const double *X, double *Y,
+                                 int32_t reps, void *stream, int32_t *threads_per_row);
+
+mp_status mp_batch_plan_destroy(mp_batch_plan *plan);
+
+/* Y = A X for every right-hand side (DD).  a: 2*nnz; X, Y: 2*N*nrhs.  plan may be NULL
+ * (one thread per row).  Enqueues and returns. */
+mp_status mpspmm_csr_dd_batched(const mp_csr *A, const double *a, const double *X, double *Y, int32_t nrhs,
+                                const mp_batch_plan *plan, void *stream);
+
+/* Device workspace bytes of mpkrylov_cg_batched for a plan (host size_t out). */
+mp_status mpkrylov_batched_workspace_bytes(const mp_batch_plan *plan, size_t *bytes);
+
+/*
+ * DD Jacobi-PCG (opts.precond) for every (system, right-hand side) pair at once.
+ * B: right-hand sides, X: in = starting vectors, out = solutions (2*N*nrhs each).
+ * Each pair keeps its own DD scalars, stop test (rtol), true-residual confirmation,
+ * restarts and iteration limit, exactly as mpkrylov_cg.  One step runs six kernels
+ * over all pairs; with use_graph = 1 a chunk of opts.check_every steps is captured
+ * once into a hipGraph and replayed (on a private stream ordered after `stream`)
+ * until every pair has finished.  info: host array of nsys*nrhs records, pair (s, r)
+ * at index s*nrhs + r.  Synchronises `stream`.  Returns MP_OK when every pair
+ * converged, else the worst pair status.
+ */
+mp_status mpkrylov_cg_batched(const mp_csr *A, const double *a, const double *B, double *X, int32_t nrhs,
+                              const mp_solve_opts *opts, const mp_batch_plan *plan, int32_t use_graph, void *ws,
+                              size_t ws_bytes, mp_solve_info *info, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

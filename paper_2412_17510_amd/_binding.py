@@ -84,6 +84,14 @@ for _name in ("mpkrylov_cg", "mpkrylov_bicgstab", "mpkrylov_ir"):
     _SIGS[_name] = ([_CSR, _P, _P, _P, ctypes.POINTER(mp_solve_opts), _P, _P, ctypes.c_size_t,
                      ctypes.POINTER(mp_solve_info), _P], ctypes.c_int)
 
+_SIGS["mp_batch_plan_create"] = ([_CSR, _P, _I, _I, _I, _P, ctypes.POINTER(_P)], ctypes.c_int)
+_SIGS["mp_batch_plan_autotune"] = ([_P, _CSR, _P, _P, _P, _I, _P, ctypes.POINTER(_I)], ctypes.c_int)
+_SIGS["mp_batch_plan_destroy"] = ([_P], ctypes.c_int)
+_SIGS["mpspmm_csr_dd_batched"] = ([_CSR, _P, _P, _P, _I, _P, _P], ctypes.c_int)
+_SIGS["mpkrylov_batched_workspace_bytes"] = ([_P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int)
+_SIGS["mpkrylov_cg_batched"] = ([_CSR, _P, _P, _P, _I, ctypes.POINTER(mp_solve_opts), _P, _I, _P, ctypes.c_size_t,
+                                 _P, _P], ctypes.c_int)
+
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
     _f.argtypes = _args
@@ -317,3 +325,86 @@ def _solver(name):
 mpkrylov_cg = _solver("mpkrylov_cg")
 mpkrylov_bicgstab = _solver("mpkrylov_bicgstab")
 mpkrylov_ir = _solver("mpkrylov_ir")
+
+
+# ---------------------------------------------------------------------------------------
+# batched block-diagonal systems
+# ---------------------------------------------------------------------------------------
+
+class BatchPlan:
+    """Owns an mp_batch_plan* (destroyed with the object)."""
+
+    def __init__(self, handle, nsys, nrhs):
+        self._h = handle
+        self.nsys = nsys
+        self.nrhs = nrhs
+
+    @property
+    def handle(self):
+        return self._h
+
+    def destroy(self):
+        if self._h:
+            _lib.mp_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def _check_multi(t, N, R, name):
+    import torch
+    if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape) != (2, N, R):
+        raise ValueError("%s must be a contiguous CUDA float64 tensor of shape (2, %d, %d)" % (name, N, R))
+
+
+def mp_batch_plan_create(A, sys_ptr, nrhs, threads_per_row=1, stream=None):
+    sp = np.ascontiguousarray(sys_ptr, dtype=np.int32)
+    h = ctypes.c_void_p()
+    _check(_lib.mp_batch_plan_create(ctypes.byref(A.c), sp.ctypes.data_as(ctypes.c_void_p), sp.size - 1, nrhs,
+                                     threads_per_row, _stream_ptr(stream), ctypes.byref(h)), "mp_batch_plan_create")
+    return BatchPlan(h.value, sp.size - 1, nrhs)
+
+
+def mp_batch_plan_autotune(plan, A, a, X, Y, reps=3, stream=None):
+    tpr = ctypes.c_int32()
+    _check(_lib.mp_batch_plan_autotune(plan.handle, ctypes.byref(A.c), _ptr(a), _ptr(X), _ptr(Y), reps,
+                                       _stream_ptr(stream), ctypes.byref(tpr)), "mp_batch_plan_autotune")
+    return tpr.value
+
+
+def mpspmm_csr_dd_batched(A, a, X, Y, nrhs, plan=None, stream=None):
+    _check_mp(a, 2, A.nnz, "a")
+    _check_multi(X, A.n_cols, nrhs, "X")
+    _check_multi(Y, A.n_rows, nrhs, "Y")
+    _check(_lib.mpspmm_csr_dd_batched(ctypes.byref(A.c), _ptr(a), _ptr(X), _ptr(Y), nrhs,
+                                      None if plan is None else plan.handle, _stream_ptr(stream)),
+           "mpspmm_csr_dd_batched")
+    return Y
+
+
+def mpkrylov_batched_workspace_bytes(plan):
+    nb = ctypes.c_size_t()
+    _check(_lib.mpkrylov_batched_workspace_bytes(plan.handle, ctypes.byref(nb)), "mpkrylov_batched_workspace_bytes")
+    return nb.value
+
+
+def mpkrylov_cg_batched(A, a, B, X, nrhs, plan, use_graph=True, ws=None, stream=None, raise_on_failure=False, **opts):
+    """Batched DD Jacobi-CG; X updated in place; returns a list of nsys*nrhs info dicts."""
+    import torch
+    _check_mp(a, 2, A.nnz, "a")
+    _check_multi(B, A.n_rows, nrhs, "B")
+    _check_multi(X, A.n_rows, nrhs, "X")
+    o = _opts(**opts)
+    if ws is None:
+        ws = torch.empty(mpkrylov_batched_workspace_bytes(plan), dtype=torch.uint8, device="cuda")
+    npairs = plan.nsys * nrhs
+    infos = (mp_solve_info * npairs)()
+    st = _lib.mpkrylov_cg_batched(ctypes.byref(A.c), _ptr(a), _ptr(B), _ptr(X), nrhs, ctypes.byref(o), plan.handle,
+                                  int(bool(use_graph)), _ptr(ws), ws.numel(), infos, _stream_ptr(stream))
+    if st not in (MP_OK, -5, -6) or (raise_on_failure and st != MP_OK):
+        _check(st, "mpkrylov_cg_batched")
+    return [_info_dict(i) for i in infos]

@@ -1,0 +1,111 @@
+"""GPU checks of the batched block-diagonal layer (C ABI mpspmm_csr_dd_batched,
+mpkrylov_cg_batched).
+
+* SpMM: every right-hand side equals the oracle's single-vector SpMV with W = 1 order,
+  bitwise, for every threads-per-row mapping (the autotuner's search space).
+* Batched CG: every (system, rhs) pair equals a separate oracle DD CG solve with the
+  same order (status, iterations, restarts, bitwise x and true residual); the hipGraph
+  replay path equals the eager path bitwise; a pair equals the GPU's own single-system
+  mpkrylov_cg with a W = 1 plan.
+* A matrix with an entry outside its system's block is refused.
+"""
+import numpy as np
+import pytest
+
+from oracle import ref
+from tests.helpers import assert_same_values, dev, host
+from workloads import batched_diffusion, random_mp
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mp():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2412_17510_amd import mp as binding
+    return binding
+
+
+def multi(rng, N, R):
+    """(2, N, R) DD multi-vector with random leads and tails."""
+    v = random_mp(N * R, 2, rng)
+    return np.ascontiguousarray(v.reshape(2, N, R))
+
+
+@pytest.mark.parametrize("R", [1, 4, 8])
+def test_batched_spmm_matches_single_spmv(mp, R):
+    import torch
+    rp, ci, a, sp = batched_diffusion([5, 7, 4, 9], sigma=2.0, seed=41)
+    N = rp.size - 1
+    rng = np.random.default_rng(41 + R)
+    X = multi(rng, N, R)
+    A = mp.Csr.from_numpy(rp, ci)
+    want = [ref.spmv(2, rp, ci, a, np.ascontiguousarray(X[:, :, r]), log2w=np.zeros(N, np.uint8)) for r in range(R)]
+    for tpr in [t for t in (1, 2, 4, 8) if t <= R]:
+        plan = mp.mp_batch_plan_create(A, sp, R, tpr)
+        Y = torch.full((2, N, R), float("nan"), dtype=torch.float64, device="cuda")
+        mp.mpspmm_csr_dd_batched(A, dev(a), dev(X), Y, R, plan=plan)
+        torch.cuda.synchronize()
+        Yh = host(Y)
+        for r in range(R):
+            assert_same_values(Yh[:, :, r], want[r], "spmm tpr=%d rhs %d" % (tpr, r))
+    plan = mp.mp_batch_plan_create(A, sp, R, 1)
+    Y = torch.empty((2, N, R), dtype=torch.float64, device="cuda")
+    tpr = mp.mp_batch_plan_autotune(plan, A, dev(a), dev(X), Y)
+    assert tpr in (1, 2, 4, 8) and tpr <= R
+
+
+@pytest.mark.parametrize("precond", ["jacobi", "none"])
+def test_batched_cg_matches_single_solves(mp, precond):
+    import torch
+    edges = [4, 6, 5, 7, 3, 6]
+    rp, ci, a, sp = batched_diffusion(edges, sigma=2.0, seed=42)
+    N = rp.size - 1
+    R = 4
+    rng = np.random.default_rng(42)
+    B = multi(rng, N, R)
+    A = mp.Csr.from_numpy(rp, ci)
+    plan = mp.mp_batch_plan_create(A, sp, R, 2)
+    results = {}
+    for use_graph in (True, False):
+        X = torch.zeros((2, N, R), dtype=torch.float64, device="cuda")
+        infos = mp.mpkrylov_cg_batched(A, dev(a), dev(B), X, R, plan, use_graph=use_graph, precond=precond,
+                                       rtol=1e-28, max_iter=3000, check_every=8)
+        results[use_graph] = (host(X), infos)
+    assert_same_values(results[True][0], results[False][0], "graph vs eager")
+    Xg, infos = results[True]
+    for s in range(len(edges)):
+        r0, r1 = sp[s], sp[s + 1]
+        rps = (rp[r0:r1 + 1] - rp[r0]).astype(np.int32)
+        cis = (ci[rp[r0]:rp[r1]] - r0).astype(np.int32)
+        a_s = np.ascontiguousarray(a[:, rp[r0]:rp[r1]])
+        for r in range(R):
+            b_s = np.ascontiguousarray(B[:, r0:r1, r])
+            xo, io = ref.cg(rps, cis, a_s, b_s, precond=precond, rtol=1e-28, max_iter=3000,
+                            log2w=np.zeros(r1 - r0, np.uint8))
+            ig = infos[s * R + r]
+            assert (ig["status"], ig["iters"], ig["restarts"]) == (io["status"], io["iters"], io["restarts"]), (s, r)
+            assert_same_values(Xg[:, r0:r1, r], xo, "pair (%d, %d) x" % (s, r))
+            assert_same_values(ig["rr_true"], io["rr_true"], "pair (%d, %d) rr" % (s, r))
+            assert ig["status"] == 0
+    # one pair against the GPU's own single-system solver with a W = 1 plan
+    s, r = 3, 2
+    r0, r1 = sp[s], sp[s + 1]
+    rps = (rp[r0:r1 + 1] - rp[r0]).astype(np.int32)
+    cis = (ci[rp[r0]:rp[r1]] - r0).astype(np.int32)
+    As = mp.Csr.from_numpy(rps, cis)
+    p1 = mp.mp_plan_create(As, 2, False, 0, 0)
+    xs = torch.zeros((2, r1 - r0), dtype=torch.float64, device="cuda")
+    mp.mpkrylov_cg(As, dev(np.ascontiguousarray(a[:, rp[r0]:rp[r1]])), dev(np.ascontiguousarray(B[:, r0:r1, r])),
+                   xs, plan=p1, precond=precond, rtol=1e-28, max_iter=3000)
+    assert_same_values(host(xs), Xg[:, r0:r1, r], "batched vs single GPU solve")
+
+
+def test_batched_rejects_off_block_entries(mp):
+    rp, ci, a, sp = batched_diffusion([4, 4], sigma=1.0, seed=43)
+    bad = ci.copy()
+    bad[3] = sp[1] + 2   # row 0 of system 0 pointing into system 1
+    A = mp.Csr.from_numpy(rp, bad)
+    with pytest.raises(mp.MpError):
+        mp.mp_batch_plan_create(A, sp, 2, 1)

@@ -382,3 +382,22 @@ def banded_nonsymmetric(n=1000, K=2, seed=3, diag=2.0, lower=-1.015, upper=-0.98
     np.add.at(row_ptr, r + 1, 1)
     row_ptr = np.cumsum(row_ptr)
     return row_ptr.astype(np.int32), c.astype(np.int32), a
+
+
+def batched_diffusion(edges, sigma=2.5, seed=3, K=2, az=1.0):
+    """Block-diagonal CSR of independent 3D diffusion systems (one per grid edge in
+    `edges`, system s generated by diffusion3d_7pt with seed (seed, s)).  Returns
+    (row_ptr, col_idx, a (K, nnz), sys_ptr)."""
+    rps, cis, avs, sys_ptr = [], [], [], [0]
+    row_off = 0
+    nnz_off = 0
+    for s, m in enumerate(edges):
+        rp, ci, a = diffusion3d_7pt(m=int(m), sigma=sigma, az=az, K=K, seed=int(seed) * 100003 + s)
+        rps.append(rp[:-1].astype(np.int64) + nnz_off)
+        cis.append(ci.astype(np.int64) + row_off)
+        avs.append(a)
+        row_off += rp.size - 1
+        nnz_off += ci.size
+        sys_ptr.append(row_off)
+    row_ptr = np.concatenate(rps + [np.array([nnz_off])]).astype(np.int32)
+    return row_ptr, np.concatenate(cis).astype(np.int32), np.concatenate(avs, axis=1), np.array(sys_ptr, np.int32)
