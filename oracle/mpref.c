@@ -746,7 +746,9 @@ int oracle_bicgstab(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_
 /* binary32 inner Jacobi-PCG on the leading component of A).                   */
 /* ------------------------------------------------------------------------- */
 
-/* Inner plain-precision PCG, written once per type.  SpMV order: each row summed
+/* Inner plain-precision PCG, written once per type.  The preconditioner is z = M r
+ * with M given by its values on A's pattern (mv, applied as an SpMV), else
+ * z_i = r_i minv_i (Jacobi), else z = r.  SpMV order: each row summed
  * sequentially in element order (first product, then one add per element).  Dot
  * products: the DD dot tree's shape (chunks of 4096, W = 256 lanes, halving fold,
  * pairwise chunk tree) in the inner type.  d starts at 0; stop when ||r||^2 <=
@@ -800,8 +802,8 @@ int oracle_bicgstab(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_
     }                                                                                              \
     /* returns iterations; *status: 0 converged, -5 limit, -6 breakdown */                        \
     static int inner_pcg_##SUF(int64_t n, const int32_t *rp, const int32_t *ci, const T *a,       \
-                               const T *minv, const T *r0, T *d, double inner_rtol, int max_iter,  \
-                               int *status)                                                        \
+                               const T *minv, const T *mv, const T *r0, T *d, double inner_rtol,   \
+                               int max_iter, int *status)                                          \
     {                                                                                              \
         size_t bytes = sizeof(T) * (size_t)n;                                                      \
         T *r = (T *)malloc(bytes), *z = (T *)malloc(bytes), *p = (T *)malloc(bytes),               \
@@ -814,8 +816,9 @@ int oracle_bicgstab(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_
             d[i] = (T)0;                                                                           \
             r[i] = r0[i];                                                                          \
             z[i] = minv ? r[i] * minv[i] : r[i];                                                   \
-            p[i] = z[i];                                                                           \
         }                                                                                          \
+        if (mv) spmv_##SUF(n, rp, ci, mv, r, z);                                                   \
+        for (i = 0; i < n; ++i) p[i] = z[i];                                                       \
         rho = dot_##SUF(n, r, z);                                                                  \
         rr0 = dot_##SUF(n, r, r);                                                                  \
         tol = (T)(inner_rtol * inner_rtol) * rr0;                                                  \
@@ -831,6 +834,7 @@ int oracle_bicgstab(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_
                 r[i] = r[i] - aq;                                                                  \
                 z[i] = minv ? r[i] * minv[i] : r[i];                                               \
             }                                                                                      \
+            if (mv) spmv_##SUF(n, rp, ci, mv, r, z);                                               \
             rho_new = dot_##SUF(n, r, z);                                                          \
             rr = dot_##SUF(n, r, r);                                                               \
             k++;                                                                                   \
@@ -865,13 +869,15 @@ typedef struct {
  * (frexp), inner right-hand side hi(r) * 2^-e rounded to the inner type, inner PCG
  * on hi(A) (binary64) or fl32(hi(A)) (binary32) with Jacobi fl(1/hi(a_ii)) (rounded
  * to binary32 for the binary32 inner), then x_i = DDadd(x_i, (d_i * 2^e, 0)).
+ * With mvals (a learned approximate inverse on A's pattern, rounded to binary32 for
+ * the binary32 inner) the inner PCG uses z = M r instead of the Jacobi step.
  * Stall: two consecutive outer steps that each fail to reduce ||r||^2 below a quarter
  * of the previous value switch to DD Jacobi-CG from the current x (max_iter
  * iterations); so does reaching max_outer.
  */
 int oracle_ir(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx, const uint8_t *log2w,
-              const double *a, const double *b, double *x, int inner_fp32, int jacobi, double rtol,
-              double inner_rtol, int32_t inner_max_iter, int32_t max_outer, int32_t max_iter,
+              const double *a, const double *b, double *x, int inner_fp32, int jacobi, const double *mvals,
+              double rtol, double inner_rtol, int32_t inner_max_iter, int32_t max_outer, int32_t max_iter,
               oracle_ir_info *info)
 {
     dd_mat M = {n, nnz, row_ptr, col_idx, log2w, a};
@@ -879,7 +885,7 @@ int oracle_ir(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col
     double *r = (double *)malloc(vb), *q = (double *)malloc(vb);
     double *minv = (double *)malloc(sizeof(double) * (size_t)n);
     double *r64 = (double *)malloc(sizeof(double) * (size_t)n), *d64 = (double *)malloc(sizeof(double) * (size_t)n);
-    float *a32 = NULL, *m32 = NULL, *r32 = NULL, *d32 = NULL;
+    float *a32 = NULL, *m32 = NULL, *r32 = NULL, *d32 = NULL, *mv32 = NULL;
     mpv bb, tol2, rr;
     double prev = 0.0, prev2 = 0.0;
     int64_t i, k;
@@ -893,6 +899,10 @@ int oracle_ir(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col
         d32 = (float *)malloc(sizeof(float) * (size_t)n);
         for (k = 0; k < nnz; ++k) a32[k] = (float)a[k];
         for (i = 0; i < n; ++i) m32[i] = (float)minv[i];
+        if (mvals) {
+            mv32 = (float *)malloc(sizeof(float) * (size_t)(nnz > 0 ? nnz : 1));
+            for (k = 0; k < nnz; ++k) mv32[k] = (float)mvals[k];
+        }
     }
     bb = dd_dot_vec(n, b, b);
     tol2 = dd_mul_d(bb, rtol * rtol);
@@ -911,11 +921,13 @@ int oracle_ir(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col
         (void)frexp(mx, &e);
         if (inner_fp32) {
             for (i = 0; i < n; ++i) r32[i] = (float)ldexp(r[i], -e);
-            it = inner_pcg_f32(n, row_ptr, col_idx, a32, jacobi ? m32 : NULL, r32, d32, inner_rtol, inner_max_iter, &st);
+            it = inner_pcg_f32(n, row_ptr, col_idx, a32, (jacobi && !mvals) ? m32 : NULL, mv32, r32, d32, inner_rtol,
+                               inner_max_iter, &st);
             for (i = 0; i < n; ++i) d64[i] = (double)d32[i];
         } else {
             for (i = 0; i < n; ++i) r64[i] = ldexp(r[i], -e);
-            it = inner_pcg_f64(n, row_ptr, col_idx, a, jacobi ? minv : NULL, r64, d64, inner_rtol, inner_max_iter, &st);
+            it = inner_pcg_f64(n, row_ptr, col_idx, a, (jacobi && !mvals) ? minv : NULL, mvals, r64, d64, inner_rtol,
+                               inner_max_iter, &st);
         }
         info->iters += it;
         for (i = 0; i < n; ++i) {
@@ -928,7 +940,9 @@ int oracle_ir(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col
     if (stalled) {
         oracle_solve_info ci;
         info->fell_back = 1;
-        status = oracle_cg(n, nnz, row_ptr, col_idx, log2w, a, b, x, jacobi ? minv : NULL, rtol, max_iter, &ci, NULL);
+        /* a learned inner preconditioner falls back to plain Jacobi DD CG */
+        status = oracle_cg(n, nnz, row_ptr, col_idx, log2w, a, b, x, (jacobi || mvals) ? minv : NULL, rtol, max_iter,
+                           &ci, NULL);
         info->iters += ci.iters;
     }
     dd_residual(&M, b, x, q, r);
@@ -937,6 +951,6 @@ int oracle_ir(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col
     info->rr_true[0] = rr.c[0]; info->rr_true[1] = rr.c[1];
     info->bb[0] = bb.c[0]; info->bb[1] = bb.c[1];
     free(r); free(q); free(minv); free(r64); free(d64);
-    free(a32); free(m32); free(r32); free(d32);
+    free(a32); free(m32); free(r32); free(d32); free(mv32);
     return status;
 }

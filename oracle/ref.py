@@ -208,13 +208,16 @@ class IrInfo(ctypes.Structure):
 
 
 def ir(row_ptr, col_idx, a, b, x0=None, inner="fp64", precond="jacobi", rtol=1e-28, inner_rtol=1e-8,
-       inner_max_iter=1000, max_outer=50, max_iter=10000, log2w=None):
-    """Mixed-precision iterative refinement (oracle).  Returns (x, info dict)."""
+       inner_max_iter=1000, max_outer=50, max_iter=10000, log2w=None, m_values=None):
+    """Mixed-precision iterative refinement (oracle).  Returns (x, info dict).
+
+    ``m_values``: optional inner preconditioner M given by its binary64 values on A's
+    pattern (z = M r); the stall fallback is then Jacobi DD CG."""
     L = _krylov_sigs()
     if not getattr(L, "_ir_ready", False):
         P = ctypes.c_void_p
         i64 = ctypes.c_int64
-        L.oracle_ir.argtypes = [i64, i64, P, P, P, P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+        L.oracle_ir.argtypes = [i64, i64, P, P, P, P, P, P, ctypes.c_int, ctypes.c_int, P, ctypes.c_double,
                                 ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                 ctypes.POINTER(IrInfo)]
         L.oracle_ir.restype = ctypes.c_int
@@ -225,9 +228,12 @@ def ir(row_ptr, col_idx, a, b, x0=None, inner="fp64", precond="jacobi", rtol=1e-
     n = row_ptr.size - 1
     x = np.array(x0, dtype=np.float64, order="C", copy=True) if x0 is not None else np.zeros((2, n))
     lw = None if log2w is None else np.ascontiguousarray(log2w, dtype=np.uint8)
+    mv = None if m_values is None else _f64(m_values)
+    if mv is not None and mv.shape != (col_idx.size,):
+        raise ValueError("m_values must hold one value per stored element")
     info = IrInfo()
     L.oracle_ir(n, col_idx.size, _p(row_ptr), _p(col_idx), _p(lw), _p(a), _p(b), _p(x), int(inner == "fp32"),
-                int(precond == "jacobi"), float(rtol), float(inner_rtol), int(inner_max_iter), int(max_outer),
+                int(precond == "jacobi"), _p(mv), float(rtol), float(inner_rtol), int(inner_max_iter), int(max_outer),
                 int(max_iter), ctypes.byref(info))
     return x, {"status": info.status, "iters": info.iters, "outer_iters": info.outer_iters,
                "fell_back": info.fell_back, "rr_true": np.array(info.rr_true[:]), "bb": np.array(info.bb[:])}

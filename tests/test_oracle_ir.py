@@ -41,3 +41,52 @@ def test_ir_stall_falls_back_to_dd_cg():
     assert ok, rel
     x0, info0 = ref.ir(row_ptr, col_idx, a, b, max_outer=0, rtol=1e-28)
     assert info0["fell_back"] == 1 and info0["outer_iters"] == 0 and info0["status"] == 0
+
+
+def _jacobi_on_pattern(row_ptr, col_idx, a):
+    rows = np.repeat(np.arange(row_ptr.size - 1), np.diff(row_ptr))
+    return np.where(rows == col_idx, 1.0 / np.where(rows == col_idx, a[0], 1.0), 0.0)
+
+
+@pytest.mark.parametrize("inner", ["fp64", "fp32"])
+def test_ir_learned_m_equal_to_jacobi_reproduces_jacobi(inner):
+    """M = D^-1 stored on A's pattern (zero off-diagonal values) gives the same iterates."""
+    row_ptr, col_idx, a = diffusion3d_7pt(m=7, sigma=2.0, seed=23)
+    n = row_ptr.size - 1
+    b = random_mp(n, 2, np.random.default_rng(23))
+    mv = _jacobi_on_pattern(row_ptr, col_idx, a)
+    kw = dict(inner=inner, inner_rtol=1e-5, inner_max_iter=500, rtol=1e-28)
+    xj, ij = ref.ir(row_ptr, col_idx, a, b, **kw)
+    xm, im = ref.ir(row_ptr, col_idx, a, b, m_values=mv, **kw)
+    assert ij["status"] == 0 and (ij["iters"], ij["outer_iters"]) == (im["iters"], im["outer_iters"])
+    assert np.array_equal(xj, xm)
+
+
+def test_ir_learned_exact_inverse_of_diagonal_matrix():
+    """For a diagonal A and M = A^-1 every inner PCG converges in one iteration."""
+    n = 300
+    rng = np.random.default_rng(24)
+    row_ptr = np.arange(n + 1, dtype=np.int32)
+    col_idx = np.arange(n, dtype=np.int32)
+    a = np.zeros((2, n))
+    a[0] = 2.0 ** rng.integers(0, 6, n)   # exact reciprocals
+    b = random_mp(n, 2, rng)
+    x, info = ref.ir(row_ptr, col_idx, a, b, inner="fp64", m_values=1.0 / a[0], inner_rtol=1e-12, rtol=1e-28)
+    assert info["status"] == 0 and info["fell_back"] == 0
+    assert info["iters"] == info["outer_iters"]
+    ok, rel = _certify(row_ptr, col_idx, a, b, x, 1e-28)
+    assert ok, rel
+
+
+def test_ir_with_network_preconditioner_converges():
+    from oracle import mpnn
+    row_ptr, col_idx, a = diffusion3d_7pt(m=6, sigma=2.0, seed=25)
+    n = row_ptr.size - 1
+    b = random_mp(n, 2, np.random.default_rng(25))
+    g = mpnn.Graph(row_ptr, col_idx, a[0])
+    mv, _ = mpnn.forward(g, mpnn.init_params(2, scale=2.0), bf=True)
+    for inner in ("fp64", "fp32"):
+        x, info = ref.ir(row_ptr, col_idx, a, b, inner=inner, m_values=mv, inner_rtol=1e-5, rtol=1e-28)
+        assert info["status"] == 0 and info["fell_back"] == 0
+        ok, rel = _certify(row_ptr, col_idx, a, b, x, 1e-28)
+        assert ok, rel
