@@ -183,11 +183,12 @@ mp_status mpspmv_csr_qd_complex(const mp_csr *A, const double *a_re, const doubl
  * traffic of a solve).
  * ------------------------------------------------------------------------- */
 
-enum { MP_PRECOND_NONE = 0, MP_PRECOND_JACOBI = 1 };
+enum { MP_PRECOND_NONE = 0, MP_PRECOND_JACOBI = 1, MP_PRECOND_LEARNED = 2 };
 enum { MP_INNER_FP64 = 0, MP_INNER_FP32 = 1 };
 
 typedef struct {
-    int32_t precond;        /* MP_PRECOND_NONE or MP_PRECOND_JACOBI (z_i = r_i * fl(1/hi(a_ii)), Alg. 3) */
+    int32_t precond;        /* MP_PRECOND_NONE or MP_PRECOND_JACOBI (z_i = r_i * fl(1/hi(a_ii)), Alg. 3);
+                               MP_PRECOND_LEARNED for mpkrylov_ir_learned only */
     int32_t max_iter;       /* Krylov iterations (for refinement: per inner solve) */
     double rtol;            /* target ||b - A x||_2 <= rtol ||b||_2 */
     int32_t check_every;    /* iterations between host reads of the device state (0 = 32) */
@@ -252,6 +253,23 @@ mp_status mpkrylov_bicgstab(const mp_csr *A, const double *a, const double *b, d
 mp_status mpkrylov_ir(const mp_csr *A, const double *a, const double *b, double *x, const mp_solve_opts *opts,
                       const mp_plan *plan, void *ws, size_t ws_bytes, mp_solve_info *info, void *stream);
 
+/*
+ * Refinement as mpkrylov_ir, with the inner PCG preconditioned by a given sparse
+ * approximate inverse M instead of Jacobi: z = M r, M given by its binary64 values on
+ * A's pattern (m_values: device double[nnz], same element order as a; read only;
+ * rounded to binary32 for MP_INNER_FP32), each row of z = M r summed sequentially in
+ * element order.  M must be symmetric positive definite for the inner CG (the
+ * network of mp_mpnn_forward guarantees it).  opts.precond must be
+ * MP_PRECOND_LEARNED; the stall / max_outer fallback is plain DD Jacobi-CG.  With M =
+ * D^-1 stored on the pattern (zero off-diagonal values) the iterates equal
+ * mpkrylov_ir's with MP_PRECOND_JACOBI.  Workspace: mpkrylov_workspace_bytes with the
+ * same opts (binary32 adds copies of hi(A) and M).  MP_ERR_ALIAS if m_values overlaps
+ * x or the workspace.
+ */
+mp_status mpkrylov_ir_learned(const mp_csr *A, const double *a, const double *m_values, const double *b, double *x,
+                              const mp_solve_opts *opts, const mp_plan *plan, void *ws, size_t ws_bytes,
+                              mp_solve_info *info, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Batched systems (layer on the paper's method): nsys independent square systems
  * stored as the diagonal blocks of ONE block-diagonal CSR matrix A (system s owns rows
@@ -305,6 +323,73 @@ mp_status mpkrylov_batched_workspace_bytes(const mp_batch_plan *plan, size_t *by
 mp_status mpkrylov_cg_batched(const mp_csr *A, const double *a, const double *B, double *X, int32_t nrhs,
                               const mp_solve_opts *opts, const mp_batch_plan *plan, int32_t use_graph, void *ws,
                               size_t ws_bytes, mp_solve_info *info, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned preconditioner (layer on the paper's method, for the refinement's inner
+ * solve): a message-passing network over the graph of an SPD matrix with a symmetric
+ * pattern and sorted columns predicts M = S (I + C) S on A's pattern (S = D^-1/2,
+ * C symmetric with |c_ij| <= 1/2 and diagonal 1 + sum_j |c_ij| + delta_i, delta_i >= 0,
+ * so M is SPD; zero weights give exactly M = D^-1).  Network, with w_ij =
+ * -hi(a_ij)/sqrt(hi(a_ii) hi(a_jj)) and node features f_i = [sum_j w_ij,
+ * sum_j w_ij^2, deg_i/8, 1]:
+ *   h0 = relu(f W0 + b0); three layers h = relu(h Ws + (sum_j w_ij h_j) Wn + b);
+ *   u_i = h_i.wu + bu; v_ij = sum_k qv_k h_ik h_jk + bv; c_ij = tanh(v_ij)/2;
+ *   delta_i = softplus(u_i) - softplus(0).
+ * Hidden width 64; 25218 parameters, float32 master copy in this order: W0 (4x64,
+ * row-major), b0, then per layer Ws (64x64), Wn (64x64), b; then wu, bu, qv, bv.
+ * Weights and dense-layer inputs are rounded to bfloat16 (nearest-even) when used,
+ * products accumulate in float32; M is assembled in binary64.  Training minimises
+ * L = (M r - e)^T A (M r - e) / e^T A e over pairs (r, e = A^-1 r); the backward pass
+ * takes the bfloat16 roundings as the identity.  Every reduction has a fixed order,
+ * so forward values and gradients are deterministic.
+ * ------------------------------------------------------------------------- */
+
+typedef struct mp_mpnn mp_mpnn;     /* parameters, gradients, Adam moments (device) */
+typedef struct mp_graph mp_graph;   /* one matrix's graph, features and activations */
+
+/* Number of parameters (host int32 out). */
+mp_status mp_mpnn_param_count(int32_t *count);
+
+/* Create a network with all parameters, gradients and moments zero.  hidden must be 64
+ * (MP_ERR_UNSUPPORTED otherwise). */
+mp_status mp_mpnn_create(int32_t hidden, mp_mpnn **out);
+mp_status mp_mpnn_destroy(mp_mpnn *net);
+
+/* Copy parameters from / to a host float[param_count]; set also zeroes the Adam
+ * moments.  Gradients: host float[param_count].  These synchronise the device. */
+mp_status mp_mpnn_set_params(mp_mpnn *net, const float *host_params);
+mp_status mp_mpnn_get_params(const mp_mpnn *net, float *host_params);
+mp_status mp_mpnn_get_grads(const mp_mpnn *net, float *host_grads);
+
+/* Zero the gradient accumulator (enqueued on stream). */
+mp_status mp_mpnn_zero_grads(mp_mpnn *net, void *stream);
+
+/*
+ * Build the graph of A: a = DD values (device, 2*nnz; only hi is read).  The graph
+ * keeps pointers to A's row_ptr/col_idx and to a: they must stay valid and unchanged
+ * while it exists.  MP_ERR_INVALID_ARG unless every row has a positive diagonal and
+ * every off-diagonal entry its transpose (columns sorted).  Synchronises.
+ */
+mp_status mp_graph_create(const mp_csr *A, const double *a, void *stream, mp_graph **out);
+mp_status mp_graph_destroy(mp_graph *g);
+
+/* Forward pass: m_values (device double[nnz], A's element order) = M.  Enqueues. */
+mp_status mp_mpnn_forward(const mp_mpnn *net, mp_graph *g, double *m_values, void *stream);
+
+/*
+ * Forward pass, loss and backward pass for npairs pairs (device, r and e each
+ * npairs*n binary64 values, pair p at offset p*n; 1 <= npairs <= n): the
+ * gradients of the npairs losses are ADDED to the network's accumulator.
+ * loss_host: NULL or host double[npairs] (then the call synchronises).  A = hi of the
+ * graph's values.  Calls on one graph must not overlap (activations are per graph).
+ */
+mp_status mp_mpnn_loss_grad(mp_mpnn *net, mp_graph *g, const double *r, const double *e, int32_t npairs,
+                            double *loss_host, void *stream);
+
+/* One Adam step (bias-corrected, step >= 1) on the accumulated gradients times
+ * grad_scale.  Enqueues. */
+mp_status mp_mpnn_adam_step(mp_mpnn *net, float lr, float beta1, float beta2, float eps, float grad_scale,
+                            int32_t step, void *stream);
 
 #ifdef __cplusplus
 }

@@ -182,3 +182,12 @@ def init_params(seed, scale=0.1):
             fan_in = shp[0] if len(shp) == 2 else HIDDEN
             p[name] = rng.normal(0.0, scale / np.sqrt(fan_in), size=shp)
     return pack(p).astype(np.float32).astype(np.float64)
+
+
+def adam(theta, g, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step (Kingma and Ba, bias-corrected), float64.  Returns (theta, m, v)."""
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mh = m / (1.0 - beta1 ** step)
+    vh = v / (1.0 - beta2 ** step)
+    return theta - lr * mh / (np.sqrt(vh) + eps), m, v

@@ -50,7 +50,7 @@ class mp_solve_info(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
-PRECOND = {"none": 0, "jacobi": 1}
+PRECOND = {"none": 0, "jacobi": 1, "learned": 2}
 INNER = {"fp64": 0, "fp32": 1}
 
 if not os.path.exists(LIB_PATH):
@@ -84,6 +84,19 @@ for _name in ("mpkrylov_cg", "mpkrylov_bicgstab", "mpkrylov_ir"):
     _SIGS[_name] = ([_CSR, _P, _P, _P, ctypes.POINTER(mp_solve_opts), _P, _P, ctypes.c_size_t,
                      ctypes.POINTER(mp_solve_info), _P], ctypes.c_int)
 
+_SIGS["mpkrylov_ir_learned"] = ([_CSR, _P, _P, _P, _P, ctypes.POINTER(mp_solve_opts), _P, _P, ctypes.c_size_t,
+                                 ctypes.POINTER(mp_solve_info), _P], ctypes.c_int)
+_SIGS["mp_mpnn_param_count"] = ([ctypes.POINTER(_I)], ctypes.c_int)
+_SIGS["mp_mpnn_create"] = ([_I, ctypes.POINTER(_P)], ctypes.c_int)
+_SIGS["mp_mpnn_destroy"] = ([_P], ctypes.c_int)
+for _name in ("mp_mpnn_set_params", "mp_mpnn_get_params", "mp_mpnn_get_grads", "mp_mpnn_zero_grads"):
+    _SIGS[_name] = ([_P, _P], ctypes.c_int)
+_SIGS["mp_graph_create"] = ([_CSR, _P, _P, ctypes.POINTER(_P)], ctypes.c_int)
+_SIGS["mp_graph_destroy"] = ([_P], ctypes.c_int)
+_SIGS["mp_mpnn_forward"] = ([_P, _P, _P, _P], ctypes.c_int)
+_SIGS["mp_mpnn_loss_grad"] = ([_P, _P, _P, _P, _I, _P, _P], ctypes.c_int)
+_SIGS["mp_mpnn_adam_step"] = ([_P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                               _I, _P], ctypes.c_int)
 _SIGS["mp_batch_plan_create"] = ([_CSR, _P, _I, _I, _I, _P, ctypes.POINTER(_P)], ctypes.c_int)
 _SIGS["mp_batch_plan_autotune"] = ([_P, _CSR, _P, _P, _P, _I, _P, ctypes.POINTER(_I)], ctypes.c_int)
 _SIGS["mp_batch_plan_destroy"] = ([_P], ctypes.c_int)
@@ -325,6 +338,142 @@ def _solver(name):
 mpkrylov_cg = _solver("mpkrylov_cg")
 mpkrylov_bicgstab = _solver("mpkrylov_bicgstab")
 mpkrylov_ir = _solver("mpkrylov_ir")
+
+
+def mpkrylov_ir_learned(A, a, m_values, b, x, plan=None, ws=None, stream=None, raise_on_failure=False, **opts):
+    """Refinement with a learned inner preconditioner (C ABI mpkrylov_ir_learned).
+
+    m_values: CUDA float64 tensor of A.nnz values of M on A's pattern.  x is updated in
+    place; returns the info record."""
+    import torch
+    _check_mp(a, 2, A.nnz, "a")
+    _check_mp(b, 2, A.n_rows, "b")
+    _check_mp(x, 2, A.n_rows, "x")
+    if (not m_values.is_cuda or m_values.dtype != torch.float64 or not m_values.is_contiguous()
+            or m_values.numel() != A.nnz):
+        raise ValueError("m_values must be a contiguous CUDA float64 tensor of %d values" % A.nnz)
+    opts["precond"] = "learned"
+    o = _opts(**opts)
+    ws = _workspace(A, ws, **opts)
+    info = mp_solve_info()
+    st = _lib.mpkrylov_ir_learned(ctypes.byref(A.c), _ptr(a), _ptr(m_values), _ptr(b), _ptr(x), ctypes.byref(o),
+                                  _plan_handle(plan), _ptr(ws), ws.numel() * ws.element_size(), ctypes.byref(info),
+                                  _stream_ptr(stream))
+    if st not in (MP_OK, -5, -6) or (raise_on_failure and st != MP_OK):
+        _check(st, "mpkrylov_ir_learned")
+    return _info_dict(info)
+
+
+# ---------------------------------------------------------------------------------------
+# learned preconditioner network
+# ---------------------------------------------------------------------------------------
+
+def mp_mpnn_param_count():
+    c = _I()
+    _check(_lib.mp_mpnn_param_count(ctypes.byref(c)), "mp_mpnn_param_count")
+    return c.value
+
+
+class Mpnn:
+    """Owns an mp_mpnn* (parameters, gradient accumulator, Adam moments on the device)."""
+
+    def __init__(self, hidden=64):
+        h = _P()
+        _check(_lib.mp_mpnn_create(int(hidden), ctypes.byref(h)), "mp_mpnn_create")
+        self._h = h
+        self.n_params = mp_mpnn_param_count()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def destroy(self):
+        if self._h:
+            _lib.mp_mpnn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def set_params(self, theta):
+        t = np.ascontiguousarray(theta, dtype=np.float32)
+        if t.shape != (self.n_params,):
+            raise ValueError("expected %d parameters" % self.n_params)
+        _check(_lib.mp_mpnn_set_params(self._h, t.ctypes.data_as(_P)), "mp_mpnn_set_params")
+
+    def get_params(self):
+        t = np.empty(self.n_params, dtype=np.float32)
+        _check(_lib.mp_mpnn_get_params(self._h, t.ctypes.data_as(_P)), "mp_mpnn_get_params")
+        return t
+
+    def get_grads(self):
+        t = np.empty(self.n_params, dtype=np.float32)
+        _check(_lib.mp_mpnn_get_grads(self._h, t.ctypes.data_as(_P)), "mp_mpnn_get_grads")
+        return t
+
+    def zero_grads(self, stream=None):
+        _check(_lib.mp_mpnn_zero_grads(self._h, _stream_ptr(stream)), "mp_mpnn_zero_grads")
+
+    def adam_step(self, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, grad_scale=1.0, stream=None):
+        _check(_lib.mp_mpnn_adam_step(self._h, float(lr), float(beta1), float(beta2), float(eps), float(grad_scale),
+                                      int(step), _stream_ptr(stream)), "mp_mpnn_adam_step")
+
+
+class Graph:
+    """Owns an mp_graph* built from (A, a); keeps A and a alive while it exists."""
+
+    def __init__(self, A, a, stream=None):
+        _check_mp(a, 2, A.nnz, "a")
+        h = _P()
+        _check(_lib.mp_graph_create(ctypes.byref(A.c), _ptr(a), _stream_ptr(stream), ctypes.byref(h)),
+               "mp_graph_create")
+        self._h = h
+        self.A, self.a = A, a
+
+    @property
+    def handle(self):
+        return self._h
+
+    def destroy(self):
+        if self._h:
+            _lib.mp_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def mp_mpnn_forward(net, g, m_values=None, stream=None):
+    """M values of the network on g's pattern (CUDA float64 tensor of nnz values)."""
+    import torch
+    if m_values is None:
+        m_values = torch.empty(g.A.nnz, dtype=torch.float64, device="cuda")
+    _check(_lib.mp_mpnn_forward(net.handle, g.handle, _ptr(m_values), _stream_ptr(stream)), "mp_mpnn_forward")
+    return m_values
+
+
+def mp_mpnn_loss_grad(net, g, r, e, stream=None):
+    """Add the gradients of the losses of the pairs (r[p], e[p]) to the accumulator.
+
+    r, e: CUDA float64 tensors of shape (npairs, n).  Returns the losses (numpy)."""
+    import torch
+    n = g.A.n_rows
+    for t, nm in ((r, "r"), (e, "e")):
+        if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous() or t.dim() != 2 or t.shape[1] != n:
+            raise ValueError("%s must be a contiguous CUDA float64 tensor of shape (npairs, %d)" % (nm, n))
+    npairs = r.shape[0]
+    if e.shape[0] != npairs:
+        raise ValueError("r and e hold different numbers of pairs")
+    out = np.empty(npairs, dtype=np.float64)
+    _check(_lib.mp_mpnn_loss_grad(net.handle, g.handle, _ptr(r), _ptr(e), int(npairs), out.ctypes.data_as(_P),
+                                  _stream_ptr(stream)), "mp_mpnn_loss_grad")
+    return out
 
 
 # ---------------------------------------------------------------------------------------

@@ -785,6 +785,43 @@ __global__ __launch_bounds__(256) void k_in_p(int64_t n, const T *__restrict__ z
     }
 }
 
+// d += alpha p; r -= alpha q (the learned-preconditioner step applies z = M r separately)
+template <typename T>
+__global__ __launch_bounds__(256) void k_in_update_dr(int64_t n, T *__restrict__ d, T *__restrict__ r,
+                                                      const T *__restrict__ p, const T *__restrict__ q,
+                                                      const InState<T> *__restrict__ st)
+{
+    if (st->done != RUN) return;
+    const T alpha = st->alpha;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const T ap = alpha * p[i];
+        const T aq = alpha * q[i];
+        d[i] = d[i] + ap;
+        r[i] = r[i] - aq;
+    }
+}
+
+// z = M r with M given by its values on A's pattern, rows summed sequentially; when
+// p is given, p = z as well (start of the inner solve, st may then be NULL)
+template <typename T>
+__global__ __launch_bounds__(256) void k_in_mspmv(int64_t n, const int32_t *__restrict__ rp,
+                                                  const int32_t *__restrict__ ci, const T *__restrict__ mv,
+                                                  const T *__restrict__ r, T *__restrict__ z, T *__restrict__ p,
+                                                  const InState<T> *__restrict__ st)
+{
+    if (st && st->done != RUN) return;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const int32_t b = rp[i], e = rp[i + 1];
+        T s = T(0);
+        for (int32_t k = b; k < e; ++k) {
+            const T prod = mv[k] * r[ci[k]];
+            s = (k == b) ? prod : s + prod;
+        }
+        z[i] = s;
+        if (p) p[i] = s;
+    }
+}
+
 // x_i = DDadd(x_i, (d_i * 2^e, 0))
 template <typename T>
 __global__ __launch_bounds__(256) void k_ir_update(int64_t n, double *__restrict__ x, const T *__restrict__ d, int e)
@@ -876,7 +913,7 @@ size_t workspace_bytes(int64_t n, int64_t nnz_f32 = 0)
     b += 9 * align256(sizeof(double) * 2 * (size_t)n);
     b += 3 * align256(sizeof(dd_t) * kMaxChunks);
     b += 256;                                         // inner-solver state
-    b += align256(sizeof(float) * (size_t)nnz_f32);   // binary32 copy of hi(A)
+    b += align256(sizeof(float) * (size_t)nnz_f32);   // binary32 copies of hi(A) (and of M)
     return b;
 }
 
@@ -963,7 +1000,7 @@ struct Solver {
 
 mp_status check_solver_args(const char *name, const mp_csr *A, const double *a, const double *b, const double *x,
                             const mp_solve_opts *opts, const mp_plan *plan, void *ws, size_t ws_bytes, size_t need,
-                            mp_solve_info *info)
+                            mp_solve_info *info, bool learned)
 {
     mp_status st = check_csr(A);
     if (st != MP_OK) return st;
@@ -977,8 +1014,13 @@ mp_status check_solver_args(const char *name, const mp_csr *A, const double *a, 
     if (ws_bytes < need)
         return fail(MP_ERR_NO_MEMORY, "%s: workspace of %zu bytes, %zu needed", name, ws_bytes, need);
     if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(MP_ERR_INVALID_ARG, "%s: workspace must be 256-byte aligned", name);
-    if (opts->precond != MP_PRECOND_NONE && opts->precond != MP_PRECOND_JACOBI)
+    if (opts->precond == MP_PRECOND_LEARNED) {
+        if (!learned) return fail(MP_ERR_INVALID_ARG, "%s: the learned preconditioner needs mpkrylov_ir_learned", name);
+    } else if (learned) {
+        return fail(MP_ERR_INVALID_ARG, "%s: opts.precond must be MP_PRECOND_LEARNED", name);
+    } else if (opts->precond != MP_PRECOND_NONE && opts->precond != MP_PRECOND_JACOBI) {
         return fail(MP_ERR_INVALID_ARG, "%s: unknown preconditioner %d", name, opts->precond);
+    }
     if (!(opts->rtol >= 0.0)) return fail(MP_ERR_INVALID_ARG, "%s: rtol must be >= 0", name);
     if (plan && (plan->ncomp != 2 || plan->cplx || plan->n_rows != A->n_rows || plan->nnz != A->nnz))
         return fail(MP_ERR_INVALID_ARG, "%s: plan is not a DD real plan of this matrix", name);
@@ -1149,8 +1191,8 @@ mp_status run_bicgstab(Solver &S, const double *b, double *x, const mp_solve_opt
 }
 
 template <typename T>
-mp_status inner_solve(Solver &S, const double *r_dd, int e, const T *a_in, const T *minv, T *d, double inner_rtol,
-                      int max_iter, int every, int *iters, int *status)
+mp_status inner_solve(Solver &S, const double *r_dd, int e, const T *a_in, const T *minv, const T *mv, T *d,
+                      double inner_rtol, int max_iter, int every, int *iters, int *status)
 {
     const int64_t n = S.n;
     const int m = S.m;
@@ -1161,7 +1203,10 @@ mp_status inner_solve(Solver &S, const double *r_dd, int e, const T *a_in, const
     T *part2 = reinterpret_cast<T *>(S.w.part[2]);
     mp_status st;
     hipLaunchKernelGGL(k_in_stage<T>, dim3(S.vblocks), dim3(256), 0, S.s, n, r_dd, e, r0);
-    hipLaunchKernelGGL(k_in_init<T>, dim3(S.vblocks), dim3(256), 0, S.s, n, r0, minv, d, r, z, p);
+    hipLaunchKernelGGL(k_in_init<T>, dim3(S.vblocks), dim3(256), 0, S.s, n, r0, mv ? nullptr : minv, d, r, z, p);
+    if (mv)
+        hipLaunchKernelGGL(k_in_mspmv<T>, dim3(S.vblocks), dim3(256), 0, S.s, n, S.A->row_ptr, S.A->col_idx, mv, r, z,
+                           p, nullptr);
     hipLaunchKernelGGL(k_in_dot2<T>, dim3(m), dim3(256), 0, S.s, n, r, z, r, r, part1, part2, nullptr);
     hipLaunchKernelGGL(k_in_start<T>, dim3(1), dim3(256), 0, S.s, part1, part2, m, (T)(inner_rtol * inner_rtol),
                        max_iter, ist);
@@ -1177,7 +1222,15 @@ mp_status inner_solve(Solver &S, const double *r_dd, int e, const T *a_in, const
             hipLaunchKernelGGL(k_in_dot2<T>, dim3(m), dim3(256), 0, S.s, n, p, q, nullptr, nullptr, part0, nullptr,
                                ist);
             hipLaunchKernelGGL(k_in_alpha<T>, dim3(1), dim3(256), 0, S.s, part0, m, ist);
-            hipLaunchKernelGGL(k_in_update<T>, dim3(m), dim3(256), 0, S.s, n, d, r, z, p, q, minv, part1, part2, ist);
+            if (mv) {
+                hipLaunchKernelGGL(k_in_update_dr<T>, dim3(S.vblocks), dim3(256), 0, S.s, n, d, r, p, q, ist);
+                hipLaunchKernelGGL(k_in_mspmv<T>, dim3(S.vblocks), dim3(256), 0, S.s, n, S.A->row_ptr, S.A->col_idx,
+                                   mv, r, z, nullptr, ist);
+                hipLaunchKernelGGL(k_in_dot2<T>, dim3(m), dim3(256), 0, S.s, n, r, z, r, r, part1, part2, ist);
+            } else {
+                hipLaunchKernelGGL(k_in_update<T>, dim3(m), dim3(256), 0, S.s, n, d, r, z, p, q, minv, part1, part2,
+                                   ist);
+            }
             hipLaunchKernelGGL(k_in_beta<T>, dim3(1), dim3(256), 0, S.s, part1, part2, m, ist);
             hipLaunchKernelGGL(k_in_p<T>, dim3(S.vblocks), dim3(256), 0, S.s, n, z, p, ist);
             if ((st = S.launched()) != MP_OK) return st;
@@ -1189,7 +1242,8 @@ mp_status inner_solve(Solver &S, const double *r_dd, int e, const T *a_in, const
 }
 
 template <typename T>
-mp_status run_ir_t(Solver &S, const double *b, double *x, const mp_solve_opts *o, mp_solve_info *info)
+mp_status run_ir_t(Solver &S, const double *b, double *x, const double *mvals, const mp_solve_opts *o,
+                   mp_solve_info *info)
 {
     const auto t0 = std::chrono::steady_clock::now();
     const int64_t n = S.n;
@@ -1203,6 +1257,7 @@ mp_status run_ir_t(Solver &S, const double *b, double *x, const mp_solve_opts *o
     double *maxpart = reinterpret_cast<double *>(S.w.v[8]) + n;   // after the inner inverse diagonal
     double *maxabs = &static_cast<InState<T> *>(S.w.inner)->maxabs;
     const T *a_in;
+    const T *mv_in = nullptr;
     mp_status st;
     MP_HIP_TRY(hipMemsetAsync(S.w.st, 0, sizeof(KState), S.s));
     hipLaunchKernelGGL(k_jacobi_minv, dim3(S.vblocks), dim3(256), 0, S.s, n, S.A->row_ptr, S.A->col_idx, S.a,
@@ -1214,9 +1269,17 @@ mp_status run_ir_t(Solver &S, const double *b, double *x, const mp_solve_opts *o
             hipLaunchKernelGGL(k_to_f32, dim3((unsigned)(ab < 8192 ? ab : 8192)), dim3(256), 0, S.s, S.A->nnz, S.a,
                                S.w.a32);
         a_in = reinterpret_cast<const T *>(S.w.a32);
+        if (mvals) {
+            float *m32 = S.w.a32 + ((S.A->nnz + 63) & ~(int64_t)63);
+            if (S.A->nnz > 0)
+                hipLaunchKernelGGL(k_to_f32, dim3((unsigned)(ab < 8192 ? ab : 8192)), dim3(256), 0, S.s, S.A->nnz,
+                                   mvals, m32);
+            mv_in = reinterpret_cast<const T *>(m32);
+        }
     } else {
         hipLaunchKernelGGL(k_copy, dim3(S.vblocks), dim3(256), 0, S.s, n, S.w.minv, reinterpret_cast<double *>(minvT));
         a_in = reinterpret_cast<const T *>(S.a);
+        if (mvals) mv_in = reinterpret_cast<const T *>(mvals);
     }
     if ((st = S.launched()) != MP_OK) return st;
     const T *minv_in = jacobi ? minvT : nullptr;
@@ -1255,7 +1318,8 @@ mp_status run_ir_t(Solver &S, const double *b, double *x, const mp_solve_opts *o
         int e = 0;
         (void)std::frexp(mx, &e);
         int it = 0, ist = 0;
-        if ((st = inner_solve<T>(S, r, e, a_in, minv_in, d, o->inner_rtol, inner_max, every, &it, &ist)) != MP_OK)
+        if ((st = inner_solve<T>(S, r, e, a_in, minv_in, mv_in, d, o->inner_rtol, inner_max, every, &it, &ist)) !=
+            MP_OK)
             return st;
         total_inner += it;
         hipLaunchKernelGGL(k_ir_update<T>, dim3(S.vblocks), dim3(256), 0, S.s, n, x, d, e);
@@ -1267,6 +1331,7 @@ mp_status run_ir_t(Solver &S, const double *b, double *x, const mp_solve_opts *o
         mp_solve_opts co = *o;
         mp_solve_info ci;
         fell_back = 1;
+        if (mvals) co.precond = MP_PRECOND_JACOBI;   // a learned inner M falls back to plain Jacobi DD CG
         st = run_cg(S, b, x, &co, &ci);
         if (st != MP_OK && st != MP_ERR_NOT_CONVERGED && st != MP_ERR_BREAKDOWN) return st;
         status = ci.status;
@@ -1287,17 +1352,36 @@ mp_status run_ir_t(Solver &S, const double *b, double *x, const mp_solve_opts *o
     return MP_OK;
 }
 
-mp_status solve_entry(const char *name, int kind, const mp_csr *A, const double *a, const double *b, double *x,
-                      const mp_solve_opts *opts, const mp_plan *plan, void *ws, size_t ws_bytes, mp_solve_info *info,
-                      void *stream)
+// bytes of workspace: binary32 copies of hi(A) (and of M for the learned inner
+// preconditioner) only for a binary32 inner solve
+size_t solver_bytes(const mp_csr *A, const mp_solve_opts *o)
+{
+    if (!A) return 0;
+    int64_t f32 = 0;
+    if (o && o->inner == MP_INNER_FP32) {
+        f32 = A->nnz;
+        if (o->precond == MP_PRECOND_LEARNED) f32 = ((A->nnz + 63) & ~(int64_t)63) + A->nnz;
+    }
+    return workspace_bytes(A->n_rows, f32);
+}
+
+// kind: 0 CG, 1 BiCGSTAB, 2 refinement, 3 refinement with a learned inner M (mvals)
+mp_status solve_entry(const char *name, int kind, const mp_csr *A, const double *a, const double *mvals,
+                      const double *b, double *x, const mp_solve_opts *opts, const mp_plan *plan, void *ws,
+                      size_t ws_bytes, mp_solve_info *info, void *stream)
 {
     clear_error();
-    if (kind == 2 && opts && opts->inner != MP_INNER_FP64 && opts->inner != MP_INNER_FP32)
+    if (kind >= 2 && opts && opts->inner != MP_INNER_FP64 && opts->inner != MP_INNER_FP32)
         return fail(MP_ERR_INVALID_ARG, "%s: unknown inner precision %d", name, opts->inner);
-    const size_t need = (A && opts && kind == 2 && opts->inner == MP_INNER_FP32) ? workspace_bytes(A->n_rows, A->nnz)
-                                                                                  : (A ? workspace_bytes(A->n_rows) : 0);
-    mp_status st = check_solver_args(name, A, a, b, x, opts, plan, ws, ws_bytes, need, info);
+    const size_t need = kind >= 2 ? solver_bytes(A, opts) : (A ? workspace_bytes(A->n_rows) : 0);
+    mp_status st = check_solver_args(name, A, a, b, x, opts, plan, ws, ws_bytes, need, info, kind == 3);
     if (st != MP_OK) return st;
+    if (kind == 3) {
+        if (A->nnz > 0 && !mvals) return fail(MP_ERR_INVALID_ARG, "%s: m_values is NULL", name);
+        const size_t vb = sizeof(double) * 2 * (size_t)A->n_rows, mb = sizeof(double) * (size_t)A->nnz;
+        if (overlaps(x, vb, mvals, mb) || overlaps(ws, ws_bytes, mvals, mb))
+            return fail(MP_ERR_ALIAS, "%s: m_values overlaps x or the workspace", name);
+    }
     if (A->n_rows == 0) {
         std::memset(info, 0, sizeof(*info));
         return MP_OK;
@@ -1314,7 +1398,9 @@ mp_status solve_entry(const char *name, int kind, const mp_csr *A, const double 
     S.w = carve(ws, S.n);
     if (kind == 0) return run_cg(S, b, x, opts, info);
     if (kind == 1) return run_bicgstab(S, b, x, opts, info);
-    return opts->inner == MP_INNER_FP32 ? run_ir_t<float>(S, b, x, opts, info) : run_ir_t<double>(S, b, x, opts, info);
+    const double *mv = kind == 3 ? mvals : nullptr;
+    return opts->inner == MP_INNER_FP32 ? run_ir_t<float>(S, b, x, mv, opts, info)
+                                        : run_ir_t<double>(S, b, x, mv, opts, info);
 }
 
 }  // namespace mpk
@@ -1327,27 +1413,33 @@ mp_status mpkrylov_workspace_bytes(const mp_csr *A, const mp_solve_opts *opts, s
     mp_status st = mpk::check_csr(A);
     if (st != MP_OK) return st;
     if (!bytes) return mpk::fail(MP_ERR_INVALID_ARG, "bytes is NULL");
-    *bytes = (opts && opts->inner == MP_INNER_FP32) ? mpk::workspace_bytes(A->n_rows, A->nnz)
-                                                    : mpk::workspace_bytes(A->n_rows);
+    *bytes = mpk::solver_bytes(A, opts);
     return MP_OK;
 }
 
 mp_status mpkrylov_cg(const mp_csr *A, const double *a, const double *b, double *x, const mp_solve_opts *opts,
                       const mp_plan *plan, void *ws, size_t ws_bytes, mp_solve_info *info, void *stream)
 {
-    return mpk::solve_entry("mpkrylov_cg", 0, A, a, b, x, opts, plan, ws, ws_bytes, info, stream);
+    return mpk::solve_entry("mpkrylov_cg", 0, A, a, nullptr, b, x, opts, plan, ws, ws_bytes, info, stream);
 }
 
 mp_status mpkrylov_bicgstab(const mp_csr *A, const double *a, const double *b, double *x, const mp_solve_opts *opts,
                             const mp_plan *plan, void *ws, size_t ws_bytes, mp_solve_info *info, void *stream)
 {
-    return mpk::solve_entry("mpkrylov_bicgstab", 1, A, a, b, x, opts, plan, ws, ws_bytes, info, stream);
+    return mpk::solve_entry("mpkrylov_bicgstab", 1, A, a, nullptr, b, x, opts, plan, ws, ws_bytes, info, stream);
 }
 
 mp_status mpkrylov_ir(const mp_csr *A, const double *a, const double *b, double *x, const mp_solve_opts *opts,
                       const mp_plan *plan, void *ws, size_t ws_bytes, mp_solve_info *info, void *stream)
 {
-    return mpk::solve_entry("mpkrylov_ir", 2, A, a, b, x, opts, plan, ws, ws_bytes, info, stream);
+    return mpk::solve_entry("mpkrylov_ir", 2, A, a, nullptr, b, x, opts, plan, ws, ws_bytes, info, stream);
+}
+
+mp_status mpkrylov_ir_learned(const mp_csr *A, const double *a, const double *m_values, const double *b, double *x,
+                              const mp_solve_opts *opts, const mp_plan *plan, void *ws, size_t ws_bytes,
+                              mp_solve_info *info, void *stream)
+{
+    return mpk::solve_entry("mpkrylov_ir_learned", 3, A, a, m_values, b, x, opts, plan, ws, ws_bytes, info, stream);
 }
 
 }  // extern "C"

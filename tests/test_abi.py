@@ -26,10 +26,12 @@ def lib():
     return ctypes.CDLL(LIB)
 
 
-def test_header_declares_north_star_calls():
+def test_header_declares_spmv_entry_points():
     names = declared_functions()
     for n in ("mpspmv_csr_dd", "mpspmv_csr_td", "mpspmv_csr_qd", "mpspmv_csr_dd_complex",
-              "mpspmv_csr_td_complex", "mpspmv_csr_qd_complex", "mp_last_error"):
+              "mpspmv_csr_td_complex", "mpspmv_csr_qd_complex", "mp_last_error", "mpkrylov_cg",
+              "mpkrylov_bicgstab", "mpkrylov_ir", "mpkrylov_ir_learned", "mpspmm_csr_dd_batched",
+              "mpkrylov_cg_batched", "mp_mpnn_forward", "mp_mpnn_loss_grad", "mp_mpnn_adam_step"):
         assert n in names
 
 
@@ -61,3 +63,18 @@ def test_null_arguments_rejected_without_gpu(lib):
     lib.mp_last_error.restype = ctypes.c_char_p
     assert lib.mpspmv_csr_dd(None, None, None, None, None, None) == -1
     assert b"NULL" in lib.mp_last_error()
+
+
+def test_learned_entry_points_host_checks(lib):
+    """Parameter count agrees with the oracle network; NULL / unsupported arguments fail
+    before any HIP call."""
+    from oracle import mpnn
+    lib.mp_last_error.restype = ctypes.c_char_p
+    c = ctypes.c_int32()
+    assert lib.mp_mpnn_param_count(ctypes.byref(c)) == 0 and c.value == mpnn.n_params()
+    h = ctypes.c_void_p()
+    assert lib.mp_mpnn_create(32, ctypes.byref(h)) == -7 and not h.value
+    assert lib.mp_mpnn_create(64, None) == -1
+    assert lib.mpkrylov_ir_learned(None, None, None, None, None, None, None, None, ctypes.c_size_t(0), None,
+                                   None) == -1
+    assert lib.mp_graph_create(None, None, None, ctypes.byref(h)) == -1

@@ -1,0 +1,206 @@
+"""GPU checks of the learned refinement preconditioner (C ABI mp_mpnn_*, mp_graph_*,
+mpkrylov_ir_learned).
+
+* Forward: M from the GPU network equals the oracle network (bfloat16 mode) within
+  1e-3 of max|M| (float32 accumulation against binary64; a rare float32 difference
+  can move a value across a bfloat16 rounding boundary, one bfloat16 ulp = 2^-8
+  relative, which the bound covers), with the median element error below 1e-5 of
+  max|M|; with zero weights M equals the oracle's (the Jacobi inverse diagonal)
+  bit for bit.
+* Backward: summed gradients of two pairs equal the oracle's (bfloat16 mode) within
+  1e-3 in norm per parameter block, losses within 1e-4 relative; Adam equals the
+  oracle's step.
+* Learned refinement: with M values computed by the oracle network and uploaded,
+  iterates, counts and status equal the oracle's refinement with the same M bit for
+  bit (binary64 and binary32 inner, and the Jacobi DD CG fallback after a stall);
+  the zero-weight network reproduces Jacobi refinement exactly.
+* Training on the GPU lowers the mean loss, and the trained network needs fewer inner
+  iterations than Jacobi on held-out matrices (both certified to 1e-28).
+"""
+import numpy as np
+import pytest
+
+from oracle import mpnn, ref
+from tests.helpers import assert_same_values, dev, host
+from workloads import diffusion3d_7pt, random_mp
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mp():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2412_17510_amd import mp as binding
+    return binding
+
+
+def problem(m, seed, sigma=2.0):
+    rp, ci, a = diffusion3d_7pt(m=m, sigma=sigma, seed=seed)
+    return rp, ci, a, mpnn.Graph(rp, ci, a[0])
+
+
+def gpu_graph(mp, rp, ci, a):
+    A = mp.Csr.from_numpy(rp, ci)
+    ad = dev(a)
+    return A, ad, mp.Graph(A, ad)
+
+
+def test_forward_matches_oracle(mp):
+    import torch
+    rp, ci, a, g = problem(6, 71)
+    A, ad, gg = gpu_graph(mp, rp, ci, a)
+    net = mp.Mpnn()
+    for scale in (0.5, 2.0):
+        theta = mpnn.init_params(11, scale=scale).astype(np.float32)
+        net.set_params(theta)
+        assert np.array_equal(net.get_params(), theta)
+        Mg = host(mp.mp_mpnn_forward(net, gg))
+        torch.cuda.synchronize()
+        Mr, _ = mpnn.forward(g, theta.astype(np.float64), bf=True)
+        err = np.abs(Mg - Mr)
+        scale_m = np.abs(Mr).max()
+        assert err.max() <= 1e-3 * scale_m, (scale, err.max() / scale_m)
+        assert np.median(err) <= 1e-5 * scale_m
+    net.set_params(np.zeros(net.n_params, np.float32))
+    Mg = host(mp.mp_mpnn_forward(net, gg))
+    Mr, _ = mpnn.forward(g, np.zeros(mpnn.n_params()), bf=True)
+    assert_same_values(Mg, Mr, "zero network")
+
+
+def test_gradients_match_oracle(mp):
+    import torch
+    rp, ci, a, g = problem(5, 72)
+    A, ad, gg = gpu_graph(mp, rp, ci, a)
+    theta = mpnn.init_params(12, scale=1.0).astype(np.float32)
+    rng = np.random.default_rng(72)
+    E = rng.standard_normal((2, g.n))
+    R = np.stack([g.spmv(g.a_hi, E[p]) for p in range(2)])
+    net = mp.Mpnn()
+    net.set_params(theta)
+    net.zero_grads()
+    losses = mp.mp_mpnn_loss_grad(net, gg, dev(R), dev(E))
+    grads = net.get_grads().astype(np.float64)
+    want_l, want_g = [], np.zeros(mpnn.n_params())
+    for p in range(2):
+        L, gr = mpnn.backward(g, theta.astype(np.float64), R[p], E[p], bf=True)
+        want_l.append(L)
+        want_g += gr
+    np.testing.assert_allclose(losses, want_l, rtol=1e-4)
+    off = 0
+    for name, shp in mpnn.param_shapes():
+        k = int(np.prod(shp))
+        gw, gx = want_g[off:off + k], grads[off:off + k]
+        assert np.linalg.norm(gx - gw) <= 1e-3 * np.linalg.norm(gw) + 1e-12, name
+        off += k
+    # the accumulator adds: a second call doubles the gradient
+    mp.mp_mpnn_loss_grad(net, gg, dev(R), dev(E))
+    np.testing.assert_allclose(net.get_grads(), 2.0 * grads, rtol=1e-6, atol=1e-30)
+    # Adam against the oracle's step (float32 master weights)
+    net.zero_grads()
+    mp.mp_mpnn_loss_grad(net, gg, dev(R), dev(E))
+    g32 = net.get_grads().astype(np.float64)
+    net.adam_step(1, lr=1e-2, grad_scale=0.5)
+    torch.cuda.synchronize()
+    want, _, _ = mpnn.adam(theta.astype(np.float64), 0.5 * g32, 0.0, 0.0, 1, lr=1e-2)
+    np.testing.assert_allclose(net.get_params(), want, rtol=1e-5, atol=1e-7)
+
+
+@pytest.mark.parametrize("inner", ["fp64", "fp32"])
+def test_learned_ir_matches_oracle(mp, inner):
+    import torch
+    rp, ci, a, g = problem(7, 73)
+    n = g.n
+    theta = mpnn.init_params(13, scale=2.0)
+    Mr, _ = mpnn.forward(g, theta, bf=True)
+    b = random_mp(n, 2, np.random.default_rng(73))
+    kw = dict(inner=inner, inner_rtol=1e-5, rtol=1e-28)
+    xo, io = ref.ir(rp, ci, a, b, m_values=Mr, inner_max_iter=400, **kw)
+    A = mp.Csr.from_numpy(rp, ci)
+    x = torch.zeros((2, n), dtype=torch.float64, device="cuda")
+    ig = mp.mpkrylov_ir_learned(A, dev(a), dev(Mr), dev(b), x, inner_max_iter=400, **kw)
+    assert io["status"] == 0 and io["fell_back"] == 0
+    for k in ("status", "iters", "outer_iters", "fell_back"):
+        assert ig[k] == io[k], k
+    assert_same_values(host(x), xo, "learned IR x")
+    assert_same_values(ig["rr_true"], io["rr_true"], "learned IR rr")
+    # stall -> Jacobi DD CG fallback
+    xo, io = ref.ir(rp, ci, a, b, m_values=Mr, inner_max_iter=1, **kw)
+    x.zero_()
+    ig = mp.mpkrylov_ir_learned(A, dev(a), dev(Mr), dev(b), x, inner_max_iter=1, **kw)
+    assert io["fell_back"] == 1 and io["status"] == 0
+    for k in ("status", "iters", "outer_iters", "fell_back"):
+        assert ig[k] == io[k], k
+    assert_same_values(host(x), xo, "fallback x")
+
+
+def test_zero_network_reproduces_jacobi_ir(mp):
+    import torch
+    rp, ci, a, g = problem(8, 74)
+    A, ad, gg = gpu_graph(mp, rp, ci, a)
+    n = g.n
+    net = mp.Mpnn()
+    M = mp.mp_mpnn_forward(net, gg)
+    bd = dev(random_mp(n, 2, np.random.default_rng(74)))
+    for inner in ("fp64", "fp32"):
+        xj = torch.zeros((2, n), dtype=torch.float64, device="cuda")
+        xl = torch.zeros_like(xj)
+        ij = mp.mpkrylov_ir(A, ad, bd, xj, inner=inner, inner_rtol=1e-6, rtol=1e-28)
+        il = mp.mpkrylov_ir_learned(A, ad, M, bd, xl, inner=inner, inner_rtol=1e-6, rtol=1e-28)
+        assert ij["status"] == 0
+        for k in ("status", "iters", "outer_iters", "fell_back"):
+            assert ij[k] == il[k], (inner, k)
+        assert_same_values(host(xl), host(xj), "zero network vs Jacobi (%s)" % inner)
+
+
+def test_learned_ir_rejects_wrong_precond_and_alias(mp):
+    import torch
+    rp, ci, a, g = problem(4, 75)
+    A = mp.Csr.from_numpy(rp, ci)
+    n = g.n
+    ad = dev(a)
+    b = dev(random_mp(n, 2, np.random.default_rng(75)))
+    x = torch.zeros((2, n), dtype=torch.float64, device="cuda")
+    with pytest.raises(mp.MpError):
+        mp.mpkrylov_ir(A, ad, b, x, precond="learned")
+    big = torch.zeros(2 * n + A.nnz, dtype=torch.float64, device="cuda")
+    xv = big[:2 * n].view(2, n)
+    with pytest.raises(mp.MpError):   # M overlapping x
+        mp.mpkrylov_ir_learned(A, ad, big[n:n + A.nnz], b, xv)
+
+
+def test_training_beats_jacobi_on_held_out(mp):
+    import torch
+    from paper_2412_17510_amd import learned
+    tr = learned.Trainer(learned.init_params(0, scale=0.1), lr=3e-3)
+    keep = []
+    for seed in (81, 82, 83):
+        rp, ci, a = diffusion3d_7pt(m=10, sigma=2.0, seed=seed)
+        A = mp.Csr.from_numpy(rp, ci)
+        ad = dev(a)
+        xt = dev(random_mp(rp.size - 1, 2, np.random.default_rng(seed)))
+        R, E = learned.cg_pairs(A, ad, xt)
+        tr.add(A, ad, R, E)
+        keep.append((A, ad))
+    l0 = tr.mean_loss()
+    for _ in range(200):
+        tr.step()
+    l1 = tr.mean_loss()
+    assert l1 < 0.8 * l0, (l0, l1)
+    tot_l = tot_j = 0
+    for seed in (91, 92):
+        rp, ci, a = diffusion3d_7pt(m=12, sigma=2.0, seed=seed)
+        n = rp.size - 1
+        A = mp.Csr.from_numpy(rp, ci)
+        ad = dev(a)
+        bd = dev(random_mp(n, 2, np.random.default_rng(seed)))
+        M = learned.m_values(tr.net, A, ad)
+        xj = torch.zeros((2, n), dtype=torch.float64, device="cuda")
+        xl = torch.zeros_like(xj)
+        ij = mp.mpkrylov_ir(A, ad, bd, xj, inner="fp64", inner_rtol=1e-8, rtol=1e-28)
+        il = mp.mpkrylov_ir_learned(A, ad, M, bd, xl, inner="fp64", inner_rtol=1e-8, rtol=1e-28)
+        assert ij["status"] == 0 and il["status"] == 0 and il["fell_back"] == 0
+        assert il["relres"] <= 1e-28 * 1.01
+        tot_l += il["iters"]
+        tot_j += ij["iters"]
+    assert tot_l < 0.9 * tot_j, (tot_l, tot_j)

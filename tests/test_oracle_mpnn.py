@@ -118,3 +118,17 @@ def test_gradient_is_additive_over_pairs():
     assert L3 == pytest.approx(L1, rel=1e-12)
     np.testing.assert_allclose(g3, g1, rtol=1e-9, atol=1e-12 * abs(g1).max())
     assert L1 != L2
+
+
+def test_adam_first_step_is_signed_learning_rate():
+    """After bias correction the first step moves each parameter by lr * g / (|g| + eps)."""
+    rng = np.random.default_rng(3)
+    g = rng.standard_normal(100) * 10.0 ** rng.integers(-3, 3, 100)
+    theta = rng.standard_normal(100)
+    t1, m, v = mpnn.adam(theta, g, np.zeros(100), np.zeros(100), 1, lr=0.01, eps=0.0)
+    np.testing.assert_allclose(t1, theta - 0.01 * np.sign(g), rtol=0, atol=1e-15)
+    # a constant gradient keeps the step at lr (bias-corrected moments equal g and g^2)
+    t, m, v = theta, np.zeros(100), np.zeros(100)
+    for s in range(1, 6):
+        t, m, v = mpnn.adam(t, g, m, v, s, lr=0.01, eps=0.0)
+    np.testing.assert_allclose(t, theta - 0.05 * np.sign(g), rtol=0, atol=1e-12)
