@@ -27,6 +27,8 @@ namespace mpk {
 constexpr int kDotLanes = 256;
 constexpr int kDotChunk = 4096;
 constexpr int kMaxChunks = 2048;   // n <= 8,388,608
+constexpr int kPerLane = kDotChunk / kDotLanes;   // elements per lane and chunk
+constexpr int kBatch = 8;                          // loads issued ahead of the arithmetic
 
 enum : int32_t { RUN = 0, RECURRENCE_MET = 1, BROKE_DOWN = 2, ITER_LIMIT = 3, CONFIRMED = 4, RESTART = 5 };
 
@@ -109,7 +111,9 @@ __device__ __forceinline__ int chunk_used(int64_t n, int c)
 // generic kernels
 // ---------------------------------------------------------------------------
 
-// chunk sums of dot(x1, y1) and (optionally) dot(x2, y2); one workgroup per chunk
+// chunk sums of dot(x1, y1) and (optionally) dot(x2, y2); one workgroup per chunk.
+// Lane t holds elements t + j*256 (j = 0..15) of its chunk; its loads are issued in
+// batches of kBatch before the products are accumulated in j order.
 __global__ __launch_bounds__(256) void k_dot2(int64_t n, const double *__restrict__ x1, const double *__restrict__ y1,
                                               const double *__restrict__ x2, const double *__restrict__ y2,
                                               dd_t *__restrict__ part1, dd_t *__restrict__ part2,
@@ -119,17 +123,37 @@ __global__ __launch_bounds__(256) void k_dot2(int64_t n, const double *__restric
     if (st && st->done != RUN) return;
     const int c = blockIdx.x;
     const int t = threadIdx.x;
-    const int64_t base = (int64_t)c * kDotChunk;
-    const int64_t end = (n - base) < kDotChunk ? n : base + kDotChunk;
+    const int64_t base = (int64_t)c * kDotChunk + t;
+    const int64_t end = (n - (int64_t)c * kDotChunk) < kDotChunk ? n : (int64_t)c * kDotChunk + kDotChunk;
     const int used = chunk_used(n, c);
     dd_t a1 = dd_zero(), a2 = dd_zero();
     if (t < used) {
-        int64_t k = base + t;
-        a1 = dd_mul(ldd(x1, n, k), ldd(y1, n, k));
-        if (x2) a2 = dd_mul(ldd(x2, n, k), ldd(y2, n, k));
-        for (k += kDotLanes; k < end; k += kDotLanes) {
-            a1 = dd_add(a1, dd_mul(ldd(x1, n, k), ldd(y1, n, k)));
-            if (x2) a2 = dd_add(a2, dd_mul(ldd(x2, n, k), ldd(y2, n, k)));
+        for (int j0 = 0; j0 < kPerLane; j0 += kBatch) {
+            dd_t u1[kBatch], v1[kBatch], u2[kBatch], v2[kBatch];
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j) {
+                const int64_t k = base + (int64_t)(j0 + j) * kDotLanes;
+                if (k < end) {
+                    u1[j] = ldd(x1, n, k);
+                    v1[j] = ldd(y1, n, k);
+                    if (x2) {
+                        u2[j] = ldd(x2, n, k);
+                        v2[j] = ldd(y2, n, k);
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j) {
+                const int64_t k = base + (int64_t)(j0 + j) * kDotLanes;
+                if (k < end) {
+                    const dd_t p1 = dd_mul(u1[j], v1[j]);
+                    a1 = (j0 + j == 0) ? p1 : dd_add(a1, p1);
+                    if (x2) {
+                        const dd_t p2 = dd_mul(u2[j], v2[j]);
+                        a2 = (j0 + j == 0) ? p2 : dd_add(a2, p2);
+                    }
+                }
+            }
         }
     }
     const dd_t s1 = chunk_fold(a1, used, lds);
@@ -237,51 +261,88 @@ __global__ __launch_bounds__(256) void k_cg_restart(const dd_t *__restrict__ prz
     }
 }
 
-// alpha = rho / (p, q); breakdown unless (p, q) > 0
-__global__ __launch_bounds__(256) void k_cg_alpha(const dd_t *__restrict__ ppq, int m, KState *__restrict__ st)
+// One CG step after q = A p and the chunk sums of (p, q) is two kernels:
+//   k_cg_update: alpha = rho / (p, q) (breakdown unless (p, q) > 0), then
+//                x += alpha p; r -= alpha q; z = M^-1 r; chunk sums of (r, z), (r, r)
+//   k_cg_p:      rho_new = (r, z), rr = (r, r); beta = rho_new / rho; stop tests;
+//                p = z + beta p (also into the SpMV's staged copy of x)
+// Every workgroup reduces the chunk sums itself (the same tree, so the same values),
+// which needs no separate scalar kernel.  The state is double-buffered across the two
+// kernels of a step: k_cg_p reads state `sr` and workgroup 0 writes the next state to
+// `sw`, so no workgroup reads a field that another workgroup of the same kernel is
+// writing.  A step with state sr = S[j & 1] writes S[(j + 1) & 1].
+
+__device__ __forceinline__ int32_t block_state(const KState *st)
 {
-    __shared__ dd_t P[kMaxChunks];
-    if (st->done != RUN) return;
-    const dd_t pq = pair_tree(ppq, m, P);
-    if (threadIdx.x == 0) {
-        st->pq = pq;
-        if (!(pq.c[0] > 0.0) || !dd_finite(pq))
-            st->done = BROKE_DOWN;
-        else
-            st->alpha = dd_div(st->rho, pq);
-    }
+    __shared__ int32_t s_done;
+    if (threadIdx.x == 0) s_done = st->done;
+    __syncthreads();
+    return s_done;
 }
 
-// x += alpha p; r -= alpha q; z = M^-1 r; chunk sums of (r, z) and (r, r)
 __global__ __launch_bounds__(256) void k_cg_update(int64_t n, double *__restrict__ x, double *__restrict__ r,
                                                    double *__restrict__ z, const double *__restrict__ p,
                                                    const double *__restrict__ q, const double *__restrict__ minv,
-                                                   dd_t *__restrict__ prz, dd_t *__restrict__ prr,
-                                                   const KState *__restrict__ st)
+                                                   const dd_t *__restrict__ ppq, int m, dd_t *__restrict__ prz,
+                                                   dd_t *__restrict__ prr, KState *__restrict__ st)
 {
     __shared__ dd_t lds[kDotLanes];
-    if (st->done != RUN) return;
-    const dd_t alpha = st->alpha;
+    __shared__ dd_t P[kMaxChunks];
+    if (block_state(st) != RUN) return;
+    const dd_t pq = pair_tree(ppq, m, P);
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (!(pq.c[0] > 0.0) || !dd_finite(pq)) {
+        if (lead) {
+            st->pq = pq;
+            st->done = BROKE_DOWN;
+        }
+        return;
+    }
+    const dd_t alpha = dd_div(st->rho, pq);
+    if (lead) {
+        st->pq = pq;
+        st->alpha = alpha;
+    }
     const int c = blockIdx.x;
     const int t = threadIdx.x;
-    const int64_t base = (int64_t)c * kDotChunk;
-    const int64_t end = (n - base) < kDotChunk ? n : base + kDotChunk;
+    const int64_t base = (int64_t)c * kDotChunk + t;
+    const int64_t end = (n - (int64_t)c * kDotChunk) < kDotChunk ? n : (int64_t)c * kDotChunk + kDotChunk;
     const int used = chunk_used(n, c);
     dd_t arz = dd_zero(), arr = dd_zero();
-    bool first = true;
-    for (int64_t k = base + t; k < end; k += kDotLanes) {
-        sdd(x, n, k, dd_add(ldd(x, n, k), dd_mul(alpha, ldd(p, n, k))));
-        const dd_t rk = dd_sub(ldd(r, n, k), dd_mul(alpha, ldd(q, n, k)));
-        sdd(r, n, k, rk);
-        const dd_t zk = minv ? dd_mul_d(rk, minv[k]) : rk;
-        sdd(z, n, k, zk);
-        if (first) {
-            arz = dd_mul(rk, zk);
-            arr = dd_mul(rk, rk);
-            first = false;
-        } else {
-            arz = dd_add(arz, dd_mul(rk, zk));
-            arr = dd_add(arr, dd_mul(rk, rk));
+    if (t < used) {
+        for (int j0 = 0; j0 < kPerLane; j0 += kBatch) {
+            dd_t xv[kBatch], pv[kBatch], rv[kBatch], qv[kBatch];
+            double mv[kBatch];
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j) {
+                const int64_t k = base + (int64_t)(j0 + j) * kDotLanes;
+                if (k < end) {
+                    xv[j] = ldd(x, n, k);
+                    pv[j] = ldd(p, n, k);
+                    rv[j] = ldd(r, n, k);
+                    qv[j] = ldd(q, n, k);
+                    mv[j] = minv ? minv[k] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j) {
+                const int64_t k = base + (int64_t)(j0 + j) * kDotLanes;
+                if (k < end) {
+                    sdd(x, n, k, dd_add(xv[j], dd_mul(alpha, pv[j])));
+                    const dd_t rk = dd_sub(rv[j], dd_mul(alpha, qv[j]));
+                    sdd(r, n, k, rk);
+                    const dd_t zk = minv ? dd_mul_d(rk, mv[j]) : rk;
+                    sdd(z, n, k, zk);
+                    const dd_t p1 = dd_mul(rk, zk), p2 = dd_mul(rk, rk);
+                    if (j0 + j == 0) {
+                        arz = p1;
+                        arr = p2;
+                    } else {
+                        arz = dd_add(arz, p1);
+                        arr = dd_add(arr, p2);
+                    }
+                }
+            }
         }
     }
     const dd_t s1 = chunk_fold(arz, used, lds);
@@ -292,38 +353,52 @@ __global__ __launch_bounds__(256) void k_cg_update(int64_t n, double *__restrict
     }
 }
 
-// rho_new = (r, z), rr = (r, r); beta = rho_new / rho; convergence / limit tests
-__global__ __launch_bounds__(256) void k_cg_beta(const dd_t *__restrict__ prz, const dd_t *__restrict__ prr, int m,
-                                                 KState *__restrict__ st)
+// xs: NULL, or the plan's staged copy of x (interleaved hi, lo) that the next SpMV reads
+__global__ __launch_bounds__(256) void k_cg_p(int64_t n, const double *__restrict__ z, double *__restrict__ p,
+                                              double *__restrict__ xs, const dd_t *__restrict__ prz,
+                                              const dd_t *__restrict__ prr, int m, const KState *__restrict__ sr,
+                                              KState *__restrict__ sw)
 {
     __shared__ dd_t P[kMaxChunks];
-    if (st->done != RUN) return;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (block_state(sr) != RUN) {
+        if (lead) *sw = *sr;
+        return;
+    }
     const dd_t rz = pair_tree(prz, m, P);
     const dd_t rr = pair_tree(prr, m, P);
-    if (threadIdx.x == 0) {
-        st->iters += 1;
-        st->rr = rr;
-        if (!dd_finite(rr) || !dd_finite(rz)) {
-            st->done = BROKE_DOWN;
-            return;
-        }
-        st->beta = dd_div(rz, st->rho);
-        st->rho = rz;
-        if (dd_le(rr, st->tol2))
-            st->done = RECURRENCE_MET;
-        else if (st->iters >= st->max_iter)
-            st->done = ITER_LIMIT;
+    const int32_t iters = sr->iters + 1;
+    int32_t done = RUN;
+    dd_t beta = dd_zero();
+    if (!dd_finite(rr) || !dd_finite(rz)) {
+        done = BROKE_DOWN;
+    } else {
+        beta = dd_div(rz, sr->rho);
+        if (dd_le(rr, sr->tol2))
+            done = RECURRENCE_MET;
+        else if (iters >= sr->max_iter)
+            done = ITER_LIMIT;
     }
-}
-
-// p = z + beta p
-__global__ __launch_bounds__(256) void k_cg_p(int64_t n, const double *__restrict__ z, double *__restrict__ p,
-                                              const KState *__restrict__ st)
-{
-    if (st->done != RUN) return;
-    const dd_t beta = st->beta;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-        sdd(p, n, i, dd_add(ldd(z, n, i), dd_mul(beta, ldd(p, n, i))));
+    if (lead) {
+        KState o = *sr;
+        o.iters = iters;
+        o.rr = rr;
+        if (done != BROKE_DOWN) {
+            o.beta = beta;
+            o.rho = rz;
+        }
+        o.done = done;
+        *sw = o;
+    }
+    if (done != RUN) return;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const dd_t pi = dd_add(ldd(z, n, i), dd_mul(beta, ldd(p, n, i)));
+        sdd(p, n, i, pi);
+        if (xs) {
+            xs[2 * i] = pi.c[0];
+            xs[2 * i + 1] = pi.c[1];
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -626,20 +701,36 @@ __global__ __launch_bounds__(256) void k_in_dot2(int64_t n, const T *__restrict_
     if (st && st->done != RUN) return;
     const int c = blockIdx.x;
     const int t = threadIdx.x;
-    const int64_t base = (int64_t)c * kDotChunk;
-    const int64_t end = (n - base) < kDotChunk ? n : base + kDotChunk;
+    const int64_t base = (int64_t)c * kDotChunk + t;
+    const int64_t end = (n - (int64_t)c * kDotChunk) < kDotChunk ? n : (int64_t)c * kDotChunk + kDotChunk;
     const int used = chunk_used(n, c);
     T a1 = T(0), a2 = T(0);
     if (t < used) {
-        int64_t k = base + t;
-        a1 = x1[k] * y1[k];
-        if (x2) a2 = x2[k] * y2[k];
-        for (k += kDotLanes; k < end; k += kDotLanes) {
-            const T p1 = x1[k] * y1[k];
-            a1 = a1 + p1;
-            if (x2) {
-                const T p2 = x2[k] * y2[k];
-                a2 = a2 + p2;
+        for (int j0 = 0; j0 < kPerLane; j0 += kBatch) {
+            T u1[kBatch], v1[kBatch], u2[kBatch], v2[kBatch];
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j) {
+                const int64_t k = base + (int64_t)(j0 + j) * kDotLanes;
+                if (k < end) {
+                    u1[j] = x1[k];
+                    v1[j] = y1[k];
+                    if (x2) {
+                        u2[j] = x2[k];
+                        v2[j] = y2[k];
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j) {
+                const int64_t k = base + (int64_t)(j0 + j) * kDotLanes;
+                if (k < end) {
+                    const T p1 = u1[j] * v1[j];
+                    a1 = (j0 + j == 0) ? p1 : a1 + p1;
+                    if (x2) {
+                        const T p2 = u2[j] * v2[j];
+                        a2 = (j0 + j == 0) ? p2 : a2 + p2;
+                    }
+                }
             }
         }
     }
@@ -670,77 +761,138 @@ __global__ __launch_bounds__(256) void k_in_start(const T *__restrict__ prz, con
     }
 }
 
-// y = A x with each row summed sequentially (one thread per row)
+// y = A x with each row summed sequentially (one thread per row; the loads of up to
+// eight elements are issued before their products are added)
 template <typename T>
 __global__ __launch_bounds__(256) void k_in_spmv(int64_t n, const int32_t *__restrict__ rp,
                                                  const int32_t *__restrict__ ci, const T *__restrict__ a,
                                                  const T *__restrict__ x, T *__restrict__ y,
                                                  const InState<T> *__restrict__ st)
 {
-    if (st->done != RUN) return;
+    if (st && st->done != RUN) return;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         const int32_t b = rp[i], e = rp[i + 1];
         T s = T(0);
-        for (int32_t k = b; k < e; ++k) {
-            const T prod = a[k] * x[ci[k]];
-            s = (k == b) ? prod : s + prod;
+        for (int32_t k0 = b; k0 < e; k0 += 8) {
+            T av[8], xv[8];
+            int32_t cv[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (k0 + j < e) {
+                    av[j] = a[k0 + j];
+                    cv[j] = ci[k0 + j];
+                }
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (k0 + j < e) xv[j] = x[cv[j]];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (k0 + j < e) {
+                    const T prod = av[j] * xv[j];
+                    s = (k0 + j == b) ? prod : s + prod;
+                }
         }
         y[i] = s;
     }
 }
 
+// An inner step after q = A p and the chunk sums of (p, q) is, as in the DD CG, an
+// update kernel that forms alpha itself and a p kernel that forms beta itself, with
+// the inner state double-buffered across the p kernel (st[j & 1] -> st[(j + 1) & 1]).
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_in_alpha(const T *__restrict__ ppq, int m, InState<T> *__restrict__ st)
+__device__ __forceinline__ int32_t in_block_state(const InState<T> *st)
 {
-    __shared__ T P[kMaxChunks];
-    if (st->done != RUN) return;
-    const T pq = pair_tree_t(ppq, m, P);
-    if (threadIdx.x == 0) {
-        st->pq = pq;
-        if (!(pq > T(0)) || !isfinite((double)pq))
-            st->done = BROKE_DOWN;
-        else
-            st->alpha = st->rho / pq;
-    }
+    __shared__ int32_t s_done;
+    if (threadIdx.x == 0) s_done = st->done;
+    __syncthreads();
+    return s_done;
 }
 
-// d += alpha p; r -= alpha q; z = M^-1 r; chunk sums of (r, z), (r, r)
+// alpha = rho / (p, q) (breakdown unless (p, q) > 0 and finite); false when not running
+template <typename T>
+__device__ __forceinline__ bool in_alpha(const T *__restrict__ ppq, int m, InState<T> *__restrict__ st, T *P,
+                                         T *alpha)
+{
+    if (in_block_state(st) != RUN) return false;
+    const T pq = pair_tree_t(ppq, m, P);
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (!(pq > T(0)) || !isfinite((double)pq)) {
+        if (lead) {
+            st->pq = pq;
+            st->done = BROKE_DOWN;
+        }
+        return false;
+    }
+    *alpha = st->rho / pq;
+    if (lead) {
+        st->pq = pq;
+        st->alpha = *alpha;
+    }
+    return true;
+}
+
+// d += alpha p; r -= alpha q; z = M^-1 r (Jacobi or none); chunk sums of (r, z), (r, r).
+// With z == NULL only d and r are updated (the learned preconditioner applies z = M r
+// in a kernel of its own) and no sums are written.
 template <typename T>
 __global__ __launch_bounds__(256) void k_in_update(int64_t n, T *__restrict__ d, T *__restrict__ r,
                                                    T *__restrict__ z, const T *__restrict__ p,
                                                    const T *__restrict__ q, const T *__restrict__ minv,
-                                                   T *__restrict__ prz, T *__restrict__ prr,
-                                                   const InState<T> *__restrict__ st)
+                                                   const T *__restrict__ ppq, int m, T *__restrict__ prz,
+                                                   T *__restrict__ prr, InState<T> *__restrict__ st)
 {
     __shared__ T lds[kDotLanes];
-    if (st->done != RUN) return;
-    const T alpha = st->alpha;
+    __shared__ T P[kMaxChunks];
+    T alpha;
+    if (!in_alpha(ppq, m, st, P, &alpha)) return;
     const int c = blockIdx.x;
     const int t = threadIdx.x;
-    const int64_t base = (int64_t)c * kDotChunk;
-    const int64_t end = (n - base) < kDotChunk ? n : base + kDotChunk;
+    const int64_t base = (int64_t)c * kDotChunk + t;
+    const int64_t end = (n - (int64_t)c * kDotChunk) < kDotChunk ? n : (int64_t)c * kDotChunk + kDotChunk;
     const int used = chunk_used(n, c);
     T arz = T(0), arr = T(0);
-    bool first = true;
-    for (int64_t k = base + t; k < end; k += kDotLanes) {
-        const T ap = alpha * p[k];
-        const T aq = alpha * q[k];
-        d[k] = d[k] + ap;
-        const T rk = r[k] - aq;
-        r[k] = rk;
-        const T zk = minv ? rk * minv[k] : rk;
-        z[k] = zk;
-        const T p1 = rk * zk;
-        const T p2 = rk * rk;
-        if (first) {
-            arz = p1;
-            arr = p2;
-            first = false;
-        } else {
-            arz = arz + p1;
-            arr = arr + p2;
+    if (t < used) {
+        for (int j0 = 0; j0 < kPerLane; j0 += kBatch) {
+            T dv[kBatch], rv[kBatch], pv[kBatch], qv[kBatch], mv[kBatch];
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j) {
+                const int64_t k = base + (int64_t)(j0 + j) * kDotLanes;
+                if (k < end) {
+                    dv[j] = d[k];
+                    rv[j] = r[k];
+                    pv[j] = p[k];
+                    qv[j] = q[k];
+                    mv[j] = minv ? minv[k] : T(0);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j) {
+                const int64_t k = base + (int64_t)(j0 + j) * kDotLanes;
+                if (k < end) {
+                    const T ap = alpha * pv[j];
+                    const T aq = alpha * qv[j];
+                    d[k] = dv[j] + ap;
+                    const T rk = rv[j] - aq;
+                    r[k] = rk;
+                    if (z) {
+                        const T zk = minv ? rk * mv[j] : rk;
+                        z[k] = zk;
+                        const T p1 = rk * zk;
+                        const T p2 = rk * rk;
+                        if (j0 + j == 0) {
+                            arz = p1;
+                            arr = p2;
+                        } else {
+                            arz = arz + p1;
+                            arr = arr + p2;
+                        }
+                    }
+                }
+            }
         }
     }
+    if (!z) return;
     const T s1 = chunk_fold_t(arz, used, lds);
     const T s2 = chunk_fold_t(arr, used, lds);
     if (t == 0) {
@@ -749,55 +901,47 @@ __global__ __launch_bounds__(256) void k_in_update(int64_t n, T *__restrict__ d,
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_in_beta(const T *__restrict__ prz, const T *__restrict__ prr, int m,
-                                                 InState<T> *__restrict__ st)
-{
-    __shared__ T P[kMaxChunks];
-    if (st->done != RUN) return;
-    const T rz = pair_tree_t(prz, m, P);
-    const T rr = pair_tree_t(prr, m, P);
-    if (threadIdx.x == 0) {
-        st->iters += 1;
-        st->rr = rr;
-        if (!isfinite((double)rr) || !isfinite((double)rz)) {
-            st->done = BROKE_DOWN;
-            return;
-        }
-        st->beta = rz / st->rho;
-        st->rho = rz;
-        if (rr <= st->tol)
-            st->done = CONFIRMED;
-        else if (st->iters >= st->max_iter)
-            st->done = ITER_LIMIT;
-    }
-}
-
+// rho_new = (r, z), rr = (r, r); beta = rho_new / rho; stop tests; p = z + beta p
 template <typename T>
 __global__ __launch_bounds__(256) void k_in_p(int64_t n, const T *__restrict__ z, T *__restrict__ p,
-                                              const InState<T> *__restrict__ st)
+                                              const T *__restrict__ prz, const T *__restrict__ prr, int m,
+                                              const InState<T> *__restrict__ sr, InState<T> *__restrict__ sw)
 {
-    if (st->done != RUN) return;
-    const T beta = st->beta;
+    __shared__ T P[kMaxChunks];
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (in_block_state(sr) != RUN) {
+        if (lead) *sw = *sr;
+        return;
+    }
+    const T rz = pair_tree_t(prz, m, P);
+    const T rr = pair_tree_t(prr, m, P);
+    const int32_t iters = sr->iters + 1;
+    int32_t done = RUN;
+    T beta = T(0);
+    if (!isfinite((double)rr) || !isfinite((double)rz)) {
+        done = BROKE_DOWN;
+    } else {
+        beta = rz / sr->rho;
+        if (rr <= sr->tol)
+            done = CONFIRMED;
+        else if (iters >= sr->max_iter)
+            done = ITER_LIMIT;
+    }
+    if (lead) {
+        InState<T> o = *sr;
+        o.iters = iters;
+        o.rr = rr;
+        if (done != BROKE_DOWN) {
+            o.beta = beta;
+            o.rho = rz;
+        }
+        o.done = done;
+        *sw = o;
+    }
+    if (done != RUN) return;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         const T bp = beta * p[i];
         p[i] = z[i] + bp;
-    }
-}
-
-// d += alpha p; r -= alpha q (the learned-preconditioner step applies z = M r separately)
-template <typename T>
-__global__ __launch_bounds__(256) void k_in_update_dr(int64_t n, T *__restrict__ d, T *__restrict__ r,
-                                                      const T *__restrict__ p, const T *__restrict__ q,
-                                                      const InState<T> *__restrict__ st)
-{
-    if (st->done != RUN) return;
-    const T alpha = st->alpha;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        const T ap = alpha * p[i];
-        const T aq = alpha * q[i];
-        d[i] = d[i] + ap;
-        r[i] = r[i] - aq;
     }
 }
 
@@ -813,9 +957,24 @@ __global__ __launch_bounds__(256) void k_in_mspmv(int64_t n, const int32_t *__re
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         const int32_t b = rp[i], e = rp[i + 1];
         T s = T(0);
-        for (int32_t k = b; k < e; ++k) {
-            const T prod = mv[k] * r[ci[k]];
-            s = (k == b) ? prod : s + prod;
+        for (int32_t k0 = b; k0 < e; k0 += 8) {
+            T av[8], xv[8];
+            int32_t cv[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (k0 + j < e) {
+                    av[j] = mv[k0 + j];
+                    cv[j] = ci[k0 + j];
+                }
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (k0 + j < e) xv[j] = r[cv[j]];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (k0 + j < e) {
+                    const T prod = av[j] * xv[j];
+                    s = (k0 + j == b) ? prod : s + prod;
+                }
         }
         z[i] = s;
         if (p) p[i] = s;
@@ -897,6 +1056,7 @@ __global__ __launch_bounds__(256) void k_ir_norms(const dd_t *__restrict__ pbb, 
 
 struct Workspace {
     KState *st;
+    KState *st2;   // second state buffer of the CG step (double-buffered)
     double *minv;
     double *v[9];
     dd_t *part[3];
@@ -908,7 +1068,7 @@ inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 size_t workspace_bytes(int64_t n, int64_t nnz_f32 = 0)
 {
-    size_t b = align256(sizeof(KState));
+    size_t b = 2 * align256(sizeof(KState));
     b += align256(sizeof(double) * (size_t)n);
     b += 9 * align256(sizeof(double) * 2 * (size_t)n);
     b += 3 * align256(sizeof(dd_t) * kMaxChunks);
@@ -922,6 +1082,8 @@ Workspace carve(void *ws, int64_t n)
     Workspace w;
     char *p = static_cast<char *>(ws);
     w.st = reinterpret_cast<KState *>(p);
+    p += align256(sizeof(KState));
+    w.st2 = reinterpret_cast<KState *>(p);
     p += align256(sizeof(KState));
     w.minv = reinterpret_cast<double *>(p);
     p += align256(sizeof(double) * (size_t)n);
@@ -1068,23 +1230,27 @@ mp_status run_cg(Solver &S, const double *b, double *x, const mp_solve_opts *o, 
     hipLaunchKernelGGL(k_precond, dim3(S.vblocks), dim3(256), 0, S.s, n, minv, r, z, nullptr);
     hipLaunchKernelGGL(k_copy, dim3(S.vblocks), dim3(256), 0, S.s, 2 * n, z, p);
     if ((st = S.launched()) != MP_OK) return st;
+    if ((st = spmv_stage_x(2, false, S.A, p, nullptr, S.plan, S.s)) != MP_OK) return st;
     if ((st = S.dot2(b, b, r, z, S.w.part[0], S.w.part[1], nullptr)) != MP_OK) return st;
     if ((st = S.dot2(r, r, nullptr, nullptr, S.w.part[2], nullptr, nullptr)) != MP_OK) return st;
     hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(256), 0, S.s, S.w.part[0], S.w.part[1], S.w.part[2], m,
                        o->rtol * o->rtol, o->max_iter, S.w.st);
     if ((st = S.launched()) != MP_OK) return st;
     int status = MP_ERR_NOT_CONVERGED;
+    double *xs = plan_staged_x(S.plan);
+    KState *sb[2] = {S.w.st, S.w.st2};
+    const int steps = (every + 1) & ~1;   // even: a chunk ends with the state in sb[0]
     for (;;) {
         if ((st = S.read_state(&h)) != MP_OK) return st;
         if (h.done == RUN) {
-            for (int it = 0; it < every; ++it) {
-                if ((st = S.spmv(p, q)) != MP_OK) return st;
-                if ((st = S.dot2(p, q, nullptr, nullptr, S.w.part[0], nullptr, S.w.st)) != MP_OK) return st;
-                hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(256), 0, S.s, S.w.part[0], m, S.w.st);
-                hipLaunchKernelGGL(k_cg_update, dim3(m), dim3(256), 0, S.s, n, x, r, z, p, q, minv, S.w.part[1],
-                                   S.w.part[2], S.w.st);
-                hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(256), 0, S.s, S.w.part[1], S.w.part[2], m, S.w.st);
-                hipLaunchKernelGGL(k_cg_p, dim3(S.vblocks), dim3(256), 0, S.s, n, z, p, S.w.st);
+            for (int it = 0; it < steps; ++it) {
+                KState *sr = sb[it & 1], *sw = sb[(it + 1) & 1];
+                if ((st = spmv_dd_prestaged(S.A, S.a, p, q, S.plan, S.s)) != MP_OK) return st;
+                if ((st = S.dot2(p, q, nullptr, nullptr, S.w.part[0], nullptr, sr)) != MP_OK) return st;
+                hipLaunchKernelGGL(k_cg_update, dim3(m), dim3(256), 0, S.s, n, x, r, z, p, q, minv, S.w.part[0], m,
+                                   S.w.part[1], S.w.part[2], sr);
+                hipLaunchKernelGGL(k_cg_p, dim3(S.vblocks), dim3(256), 0, S.s, n, z, p, xs, S.w.part[1], S.w.part[2],
+                                   m, sr, sw);
                 if ((st = S.launched()) != MP_OK) return st;
             }
             continue;
@@ -1097,6 +1263,7 @@ mp_status run_cg(Solver &S, const double *b, double *x, const mp_solve_opts *o, 
             hipLaunchKernelGGL(k_precond, dim3(S.vblocks), dim3(256), 0, S.s, n, minv, r, z, nullptr);
             hipLaunchKernelGGL(k_copy, dim3(S.vblocks), dim3(256), 0, S.s, 2 * n, z, p);
             if ((st = S.launched()) != MP_OK) return st;
+            if ((st = spmv_stage_x(2, false, S.A, p, nullptr, S.plan, S.s)) != MP_OK) return st;
             if ((st = S.dot2(r, z, nullptr, nullptr, S.w.part[1], nullptr, nullptr)) != MP_OK) return st;
             hipLaunchKernelGGL(k_cg_restart, dim3(1), dim3(256), 0, S.s, S.w.part[1], m, S.w.st);
             if ((st = S.launched()) != MP_OK) return st;
@@ -1212,27 +1379,29 @@ mp_status inner_solve(Solver &S, const double *r_dd, int e, const T *a_in, const
                        max_iter, ist);
     if ((st = S.launched()) != MP_OK) return st;
     InState<T> h;
+    InState<T> *sb[2] = {ist, ist + 1};
+    const int steps = (every + 1) & ~1;   // even: a chunk ends with the state in sb[0]
     for (;;) {
         MP_HIP_TRY(hipMemcpyAsync(&h, ist, sizeof(h), hipMemcpyDeviceToHost, S.s));
         MP_HIP_TRY(hipStreamSynchronize(S.s));
         if (h.done != RUN) break;
-        for (int it = 0; it < every; ++it) {
+        for (int it = 0; it < steps; ++it) {
+            InState<T> *sr = sb[it & 1], *sw = sb[(it + 1) & 1];
             hipLaunchKernelGGL(k_in_spmv<T>, dim3(S.vblocks), dim3(256), 0, S.s, n, S.A->row_ptr, S.A->col_idx,
-                               a_in, p, q, ist);
+                               a_in, p, q, sr);
             hipLaunchKernelGGL(k_in_dot2<T>, dim3(m), dim3(256), 0, S.s, n, p, q, nullptr, nullptr, part0, nullptr,
-                               ist);
-            hipLaunchKernelGGL(k_in_alpha<T>, dim3(1), dim3(256), 0, S.s, part0, m, ist);
+                               sr);
             if (mv) {
-                hipLaunchKernelGGL(k_in_update_dr<T>, dim3(S.vblocks), dim3(256), 0, S.s, n, d, r, p, q, ist);
+                hipLaunchKernelGGL(k_in_update<T>, dim3(m), dim3(256), 0, S.s, n, d, r, nullptr, p, q, nullptr, part0,
+                                   m, nullptr, nullptr, sr);
                 hipLaunchKernelGGL(k_in_mspmv<T>, dim3(S.vblocks), dim3(256), 0, S.s, n, S.A->row_ptr, S.A->col_idx,
-                                   mv, r, z, nullptr, ist);
-                hipLaunchKernelGGL(k_in_dot2<T>, dim3(m), dim3(256), 0, S.s, n, r, z, r, r, part1, part2, ist);
+                                   mv, r, z, nullptr, sr);
+                hipLaunchKernelGGL(k_in_dot2<T>, dim3(m), dim3(256), 0, S.s, n, r, z, r, r, part1, part2, sr);
             } else {
-                hipLaunchKernelGGL(k_in_update<T>, dim3(m), dim3(256), 0, S.s, n, d, r, z, p, q, minv, part1, part2,
-                                   ist);
+                hipLaunchKernelGGL(k_in_update<T>, dim3(m), dim3(256), 0, S.s, n, d, r, z, p, q, minv, part0, m,
+                                   part1, part2, sr);
             }
-            hipLaunchKernelGGL(k_in_beta<T>, dim3(1), dim3(256), 0, S.s, part1, part2, m, ist);
-            hipLaunchKernelGGL(k_in_p<T>, dim3(S.vblocks), dim3(256), 0, S.s, n, z, p, ist);
+            hipLaunchKernelGGL(k_in_p<T>, dim3(S.vblocks), dim3(256), 0, S.s, n, z, p, part1, part2, m, sr, sw);
             if ((st = S.launched()) != MP_OK) return st;
         }
     }

@@ -111,6 +111,19 @@ mp_status plan_build(const std::vector<int32_t> &row_ptr_host, std::vector<uint8
 
 void plan_free(mp_plan *p);
 
+// the plan's staged (interleaved) copy of x that its tile kernel gathers from, or NULL
+// when the plan has no tile kernel
+double *plan_staged_x(const mp_plan *plan);
+
+// write x into the plan's staged copy (no-op without one); DD real only
+mp_status spmv_stage_x(int K, bool cplx, const mp_csr *A, const double *x_re, const double *x_im,
+                       const mp_plan *plan, hipStream_t s);
+
+// DD real SpMV whose x has already been staged into the plan's copy (same x planar:
+// the wide-row kernel reads it)
+mp_status spmv_dd_prestaged(const mp_csr *A, const double *a, const double *x, double *y, const mp_plan *plan,
+                            hipStream_t s);
+
 // launch one SpMV of variant (K, cplx) with an optional plan (used by the autotuner)
 mp_status spmv_dispatch(int K, bool cplx, const mp_csr *A, const double *a_re, const double *a_im,
                         const double *x_re, const double *x_im, double *y_re, double *y_im, const mp_plan *plan,

@@ -564,9 +564,11 @@ mp_status launch_stream(const SpmvArgs &A, const mp_plan *plan, hipStream_t s)
     }
 }
 
+// stage = false: the caller has already written x into the plan's staged copy
 template <int K, bool CPLX>
 mp_status launch_spmv(const mp_csr *Acsr, const double *a_re, const double *a_im, const double *x_re,
-                      const double *x_im, double *y_re, double *y_im, const mp_plan *plan, hipStream_t s)
+                      const double *x_im, double *y_re, double *y_im, const mp_plan *plan, hipStream_t s,
+                      bool stage = true)
 {
     SpmvArgs A;
     A.row_ptr = Acsr->row_ptr;
@@ -596,7 +598,7 @@ mp_status launch_spmv(const mp_csr *Acsr, const double *a_re, const double *a_im
         if (plan->n_cols != Acsr->n_cols)
             return fail(MP_ERR_INVALID_ARG, "plan was built for n_cols=%d, matrix has %d", plan->n_cols, Acsr->n_cols);
         A.xs = plan->d_xstage;
-        if (Acsr->n_cols > 0) {
+        if (stage && Acsr->n_cols > 0) {
             const int64_t sb = ((int64_t)Acsr->n_cols + 255) / 256;
             hipLaunchKernelGGL((k_stage_x<K, CPLX>), dim3((unsigned)(sb < 4096 ? sb : 4096)), dim3(256), 0, s, x_re,
                                x_im, Acsr->n_cols, plan->d_xstage);
@@ -651,6 +653,29 @@ mp_status spmv_entry(const char *name, const mp_csr *A, const double *a_re, cons
     }
     if (CPLX && overlaps(y_re, yb, y_im, yb)) return fail(MP_ERR_ALIAS, "%s: y_re overlaps y_im", name);
     return launch_spmv<K, CPLX>(A, a_re, a_im, x_re, x_im, y_re, y_im, plan, static_cast<hipStream_t>(stream));
+}
+
+double *plan_staged_x(const mp_plan *plan)
+{
+    return (plan && plan->n_stream > 0 && plan->n_cols > 0) ? plan->d_xstage : nullptr;
+}
+
+mp_status spmv_stage_x(int K, bool cplx, const mp_csr *A, const double *x_re, const double *x_im,
+                       const mp_plan *plan, hipStream_t s)
+{
+    if (!plan_staged_x(plan)) return MP_OK;
+    if (K != 2 || cplx) return fail(MP_ERR_UNSUPPORTED, "staging is only exported for the DD real variant");
+    const int64_t sb = ((int64_t)A->n_cols + 255) / 256;
+    hipLaunchKernelGGL((k_stage_x<2, false>), dim3((unsigned)(sb < 4096 ? sb : 4096)), dim3(256), 0, s, x_re, x_im,
+                       A->n_cols, plan->d_xstage);
+    MP_HIP_TRY(hipGetLastError());
+    return MP_OK;
+}
+
+mp_status spmv_dd_prestaged(const mp_csr *A, const double *a, const double *x, double *y, const mp_plan *plan,
+                            hipStream_t s)
+{
+    return launch_spmv<2, false>(A, a, nullptr, x, nullptr, y, nullptr, plan, s, false);
 }
 
 mp_status spmv_dispatch(int K, bool cplx, const mp_csr *A, const double *a_re, const double *a_im,
