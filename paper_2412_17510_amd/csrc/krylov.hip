@@ -29,6 +29,9 @@ constexpr int kDotChunk = 4096;
 constexpr int kMaxChunks = 2048;   // n <= 8,388,608
 constexpr int kPerLane = kDotChunk / kDotLanes;   // elements per lane and chunk
 constexpr int kBatch = 8;                          // loads issued ahead of the arithmetic
+constexpr int kGroups = 4;                         // thread groups of a chunk workgroup
+constexpr int kChunkThreads = kDotLanes * kGroups; // threads of a chunk workgroup
+constexpr int kPerThread = kPerLane / kGroups;     // elements of a lane per thread
 
 enum : int32_t { RUN = 0, RECURRENCE_MET = 1, BROKE_DOWN = 2, ITER_LIMIT = 3, CONFIRMED = 4, RESTART = 5 };
 
@@ -74,7 +77,7 @@ __device__ __forceinline__ bool dd_finite(const dd_t &a) { return isfinite(a.c[0
 __device__ __forceinline__ dd_t chunk_fold(const dd_t &v, int used, dd_t *lds)
 {
     const int t = threadIdx.x;
-    lds[t] = v;
+    if (t < kDotLanes) lds[t] = v;
     __syncthreads();
     for (int off = kDotLanes / 2; off >= 1; off >>= 1) {
         if (t < off && t + off < used) lds[t] = dd_add(lds[t], lds[t + off]);
@@ -90,10 +93,11 @@ __device__ __forceinline__ dd_t chunk_fold(const dd_t &v, int used, dd_t *lds)
 __device__ __forceinline__ dd_t pair_tree(const dd_t *__restrict__ part, int m, dd_t *P)
 {
     const int t = threadIdx.x;
-    for (int i = t; i < m; i += kDotLanes) P[i] = part[i];
+    const int nt = blockDim.x;
+    for (int i = t; i < m; i += nt) P[i] = part[i];
     __syncthreads();
     for (int s = 1; s < m; s <<= 1) {
-        for (int i = t; (int64_t)i * 2 * s + s < m; i += kDotLanes) P[i * 2 * s] = dd_add(P[i * 2 * s], P[i * 2 * s + s]);
+        for (int i = t; (int64_t)i * 2 * s + s < m; i += nt) P[i * 2 * s] = dd_add(P[i * 2 * s], P[i * 2 * s + s]);
         __syncthreads();
     }
     const dd_t r = m > 0 ? P[0] : dd_zero();
@@ -107,60 +111,104 @@ __device__ __forceinline__ int chunk_used(int64_t n, int c)
     return left < kDotLanes ? (int)left : kDotLanes;
 }
 
+// Chunk workgroups of kChunkThreads threads: thread (g, t) = (tid / 256, tid % 256)
+// holds elements j = g*kPerThread .. g*kPerThread + kPerThread - 1 of lane t (element
+// c*4096 + t + 256 j).  Their loads and element-wise work run in parallel; the lane's
+// sums are then carried from group to group through LDS, so each lane still adds its
+// products one at a time in j order, starting from its first product.
+__device__ __forceinline__ dd_t vadd(const dd_t &a, const dd_t &b) { return dd_add(a, b); }
+__device__ __forceinline__ double vadd(double a, double b) { return a + b; }
+__device__ __forceinline__ float vadd(float a, float b) { return a + b; }
+
+// prod[q][jj]: product jj of sum q of this thread (valid for jj < nvalid); chain[q]:
+// LDS of kDotLanes values.  Leaves lane t's sum q in chain[q][t] for lanes holding
+// at least one element.
+template <typename V, int NS>
+__device__ __forceinline__ void lane_chain(const V (&prod)[NS][kPerThread], int nvalid, V (*chain)[kDotLanes])
+{
+    const int g = threadIdx.x / kDotLanes, t = threadIdx.x % kDotLanes;
+    for (int st = 0; st < kGroups; ++st) {
+        if (g == st && nvalid > 0) {
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
+                V a = st == 0 ? prod[q][0] : vadd(chain[q][t], prod[q][0]);
+#pragma unroll
+                for (int jj = 1; jj < kPerThread; ++jj)
+                    if (jj < nvalid) a = vadd(a, prod[q][jj]);
+                chain[q][t] = a;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// fold of the lane sums left by lane_chain: lds[l] += lds[l + off] for off = 128..1
+// where lane l + off holds a value; returns lds[0] (to every thread)
+template <typename V>
+__device__ __forceinline__ V chain_fold(V *lds, int used)
+{
+    const int t = threadIdx.x;
+    for (int off = kDotLanes / 2; off >= 1; off >>= 1) {
+        if (t < off && t + off < used) lds[t] = vadd(lds[t], lds[t + off]);
+        __syncthreads();
+    }
+    const V r = lds[0];
+    __syncthreads();
+    return r;
+}
+
+// valid elements of this thread in chunk c (a prefix of its kPerThread elements)
+__device__ __forceinline__ int thread_valid(int64_t n, int c)
+{
+    const int g = threadIdx.x / kDotLanes, t = threadIdx.x % kDotLanes;
+    const int64_t first = (int64_t)c * kDotChunk + t + (int64_t)g * kPerThread * kDotLanes;
+    if (first >= n) return 0;
+    const int64_t left = (n - 1 - first) / kDotLanes + 1;
+    return left < kPerThread ? (int)left : kPerThread;
+}
+
+__device__ __forceinline__ int64_t thread_elem(int c, int jj)
+{
+    const int g = threadIdx.x / kDotLanes, t = threadIdx.x % kDotLanes;
+    return (int64_t)c * kDotChunk + t + (int64_t)(g * kPerThread + jj) * kDotLanes;
+}
+
 // ---------------------------------------------------------------------------
 // generic kernels
 // ---------------------------------------------------------------------------
 
-// chunk sums of dot(x1, y1) and (optionally) dot(x2, y2); one workgroup per chunk.
-// Lane t holds elements t + j*256 (j = 0..15) of its chunk; its loads are issued in
-// batches of kBatch before the products are accumulated in j order.
-__global__ __launch_bounds__(256) void k_dot2(int64_t n, const double *__restrict__ x1, const double *__restrict__ y1,
-                                              const double *__restrict__ x2, const double *__restrict__ y2,
-                                              dd_t *__restrict__ part1, dd_t *__restrict__ part2,
-                                              const KState *__restrict__ st)
+// chunk sums of dot(x1, y1) and (optionally) dot(x2, y2); one workgroup per chunk
+__global__ __launch_bounds__(kChunkThreads) void k_dot2(int64_t n, const double *__restrict__ x1,
+                                                        const double *__restrict__ y1, const double *__restrict__ x2,
+                                                        const double *__restrict__ y2, dd_t *__restrict__ part1,
+                                                        dd_t *__restrict__ part2, const KState *__restrict__ st)
 {
-    __shared__ dd_t lds[kDotLanes];
+    __shared__ dd_t chain[2][kDotLanes];
     if (st && st->done != RUN) return;
     const int c = blockIdx.x;
-    const int t = threadIdx.x;
-    const int64_t base = (int64_t)c * kDotChunk + t;
-    const int64_t end = (n - (int64_t)c * kDotChunk) < kDotChunk ? n : (int64_t)c * kDotChunk + kDotChunk;
-    const int used = chunk_used(n, c);
-    dd_t a1 = dd_zero(), a2 = dd_zero();
-    if (t < used) {
-        for (int j0 = 0; j0 < kPerLane; j0 += kBatch) {
-            dd_t u1[kBatch], v1[kBatch], u2[kBatch], v2[kBatch];
+    const int nv = thread_valid(n, c);
+    dd_t pr[2][kPerThread];
 #pragma unroll
-            for (int j = 0; j < kBatch; ++j) {
-                const int64_t k = base + (int64_t)(j0 + j) * kDotLanes;
-                if (k < end) {
-                    u1[j] = ldd(x1, n, k);
-                    v1[j] = ldd(y1, n, k);
-                    if (x2) {
-                        u2[j] = ldd(x2, n, k);
-                        v2[j] = ldd(y2, n, k);
-                    }
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < kBatch; ++j) {
-                const int64_t k = base + (int64_t)(j0 + j) * kDotLanes;
-                if (k < end) {
-                    const dd_t p1 = dd_mul(u1[j], v1[j]);
-                    a1 = (j0 + j == 0) ? p1 : dd_add(a1, p1);
-                    if (x2) {
-                        const dd_t p2 = dd_mul(u2[j], v2[j]);
-                        a2 = (j0 + j == 0) ? p2 : dd_add(a2, p2);
-                    }
-                }
-            }
+    for (int jj = 0; jj < kPerThread; ++jj) {
+        if (jj < nv) {
+            const int64_t k = thread_elem(c, jj);
+            pr[0][jj] = dd_mul(ldd(x1, n, k), ldd(y1, n, k));
+            if (x2) pr[1][jj] = dd_mul(ldd(x2, n, k), ldd(y2, n, k));
         }
     }
-    const dd_t s1 = chunk_fold(a1, used, lds);
-    if (t == 0) part1[c] = s1;
+    const int used = chunk_used(n, c);
     if (x2) {
-        const dd_t s2 = chunk_fold(a2, used, lds);
-        if (t == 0) part2[c] = s2;
+        lane_chain<dd_t, 2>(pr, nv, chain);
+        const dd_t s1 = chain_fold(chain[0], used);
+        const dd_t s2 = chain_fold(chain[1], used);
+        if (threadIdx.x == 0) {
+            part1[c] = s1;
+            part2[c] = s2;
+        }
+    } else {
+        lane_chain<dd_t, 1>(reinterpret_cast<const dd_t(&)[1][kPerThread]>(pr[0]), nv, chain);
+        const dd_t s1 = chain_fold(chain[0], used);
+        if (threadIdx.x == 0) part1[c] = s1;
     }
 }
 
@@ -280,14 +328,35 @@ __device__ __forceinline__ int32_t block_state(const KState *st)
     return s_done;
 }
 
-__global__ __launch_bounds__(256) void k_cg_update(int64_t n, double *__restrict__ x, double *__restrict__ r,
-                                                   double *__restrict__ z, const double *__restrict__ p,
-                                                   const double *__restrict__ q, const double *__restrict__ minv,
-                                                   const dd_t *__restrict__ ppq, int m, dd_t *__restrict__ prz,
-                                                   dd_t *__restrict__ prr, KState *__restrict__ st)
+__global__ __launch_bounds__(kChunkThreads) void k_cg_update(int64_t n, double *__restrict__ x,
+                                                             double *__restrict__ r, double *__restrict__ z,
+                                                             const double *__restrict__ p,
+                                                             const double *__restrict__ q,
+                                                             const double *__restrict__ minv,
+                                                             const dd_t *__restrict__ ppq, int m,
+                                                             dd_t *__restrict__ prz, dd_t *__restrict__ prr,
+                                                             KState *__restrict__ st)
 {
-    __shared__ dd_t lds[kDotLanes];
+    __shared__ dd_t chain[2][kDotLanes];
     __shared__ dd_t P[kMaxChunks];
+    __shared__ dd_t s_rho;
+    // the element loads do not depend on the scalars: issue them first
+    const int c = blockIdx.x;
+    const int nv = thread_valid(n, c);
+    dd_t xv[kPerThread], pv[kPerThread], rv[kPerThread], qv[kPerThread];
+    double mv[kPerThread];
+#pragma unroll
+    for (int jj = 0; jj < kPerThread; ++jj) {
+        if (jj < nv) {
+            const int64_t k = thread_elem(c, jj);
+            xv[jj] = ldd(x, n, k);
+            pv[jj] = ldd(p, n, k);
+            rv[jj] = ldd(r, n, k);
+            qv[jj] = ldd(q, n, k);
+            mv[jj] = minv ? minv[k] : 0.0;
+        }
+    }
+    if (threadIdx.x == 0) s_rho = st->rho;
     if (block_state(st) != RUN) return;
     const dd_t pq = pair_tree(ppq, m, P);
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
@@ -298,56 +367,30 @@ __global__ __launch_bounds__(256) void k_cg_update(int64_t n, double *__restrict
         }
         return;
     }
-    const dd_t alpha = dd_div(st->rho, pq);
+    const dd_t alpha = dd_div(s_rho, pq);
     if (lead) {
         st->pq = pq;
         st->alpha = alpha;
     }
-    const int c = blockIdx.x;
-    const int t = threadIdx.x;
-    const int64_t base = (int64_t)c * kDotChunk + t;
-    const int64_t end = (n - (int64_t)c * kDotChunk) < kDotChunk ? n : (int64_t)c * kDotChunk + kDotChunk;
-    const int used = chunk_used(n, c);
-    dd_t arz = dd_zero(), arr = dd_zero();
-    if (t < used) {
-        for (int j0 = 0; j0 < kPerLane; j0 += kBatch) {
-            dd_t xv[kBatch], pv[kBatch], rv[kBatch], qv[kBatch];
-            double mv[kBatch];
+    dd_t pr[2][kPerThread];
 #pragma unroll
-            for (int j = 0; j < kBatch; ++j) {
-                const int64_t k = base + (int64_t)(j0 + j) * kDotLanes;
-                if (k < end) {
-                    xv[j] = ldd(x, n, k);
-                    pv[j] = ldd(p, n, k);
-                    rv[j] = ldd(r, n, k);
-                    qv[j] = ldd(q, n, k);
-                    mv[j] = minv ? minv[k] : 0.0;
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < kBatch; ++j) {
-                const int64_t k = base + (int64_t)(j0 + j) * kDotLanes;
-                if (k < end) {
-                    sdd(x, n, k, dd_add(xv[j], dd_mul(alpha, pv[j])));
-                    const dd_t rk = dd_sub(rv[j], dd_mul(alpha, qv[j]));
-                    sdd(r, n, k, rk);
-                    const dd_t zk = minv ? dd_mul_d(rk, mv[j]) : rk;
-                    sdd(z, n, k, zk);
-                    const dd_t p1 = dd_mul(rk, zk), p2 = dd_mul(rk, rk);
-                    if (j0 + j == 0) {
-                        arz = p1;
-                        arr = p2;
-                    } else {
-                        arz = dd_add(arz, p1);
-                        arr = dd_add(arr, p2);
-                    }
-                }
-            }
+    for (int jj = 0; jj < kPerThread; ++jj) {
+        if (jj < nv) {
+            const int64_t k = thread_elem(c, jj);
+            sdd(x, n, k, dd_add(xv[jj], dd_mul(alpha, pv[jj])));
+            const dd_t rk = dd_sub(rv[jj], dd_mul(alpha, qv[jj]));
+            sdd(r, n, k, rk);
+            const dd_t zk = minv ? dd_mul_d(rk, mv[jj]) : rk;
+            sdd(z, n, k, zk);
+            pr[0][jj] = dd_mul(rk, zk);
+            pr[1][jj] = dd_mul(rk, rk);
         }
     }
-    const dd_t s1 = chunk_fold(arz, used, lds);
-    const dd_t s2 = chunk_fold(arr, used, lds);
-    if (t == 0) {
+    lane_chain<dd_t, 2>(pr, nv, chain);
+    const int used = chunk_used(n, c);
+    const dd_t s1 = chain_fold(chain[0], used);
+    const dd_t s2 = chain_fold(chain[1], used);
+    if (threadIdx.x == 0) {
         prz[c] = s1;
         prr[c] = s2;
     }
@@ -360,23 +403,38 @@ __global__ __launch_bounds__(256) void k_cg_p(int64_t n, const double *__restric
                                               KState *__restrict__ sw)
 {
     __shared__ dd_t P[kMaxChunks];
+    __shared__ dd_t s_rho, s_tol2;
+    __shared__ int32_t s_iters, s_max;
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    // this thread's first element, loaded ahead of the scalars
+    const int64_t i0 = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    dd_t z0 = dd_zero(), p0 = dd_zero();
+    if (i0 < n) {
+        z0 = ldd(z, n, i0);
+        p0 = ldd(p, n, i0);
+    }
+    if (threadIdx.x == 0) {
+        s_rho = sr->rho;
+        s_tol2 = sr->tol2;
+        s_iters = sr->iters;
+        s_max = sr->max_iter;
+    }
     if (block_state(sr) != RUN) {
         if (lead) *sw = *sr;
         return;
     }
     const dd_t rz = pair_tree(prz, m, P);
     const dd_t rr = pair_tree(prr, m, P);
-    const int32_t iters = sr->iters + 1;
+    const int32_t iters = s_iters + 1;
     int32_t done = RUN;
     dd_t beta = dd_zero();
     if (!dd_finite(rr) || !dd_finite(rz)) {
         done = BROKE_DOWN;
     } else {
-        beta = dd_div(rz, sr->rho);
-        if (dd_le(rr, sr->tol2))
+        beta = dd_div(rz, s_rho);
+        if (dd_le(rr, s_tol2))
             done = RECURRENCE_MET;
-        else if (iters >= sr->max_iter)
+        else if (iters >= s_max)
             done = ITER_LIMIT;
     }
     if (lead) {
@@ -391,8 +449,9 @@ __global__ __launch_bounds__(256) void k_cg_p(int64_t n, const double *__restric
         *sw = o;
     }
     if (done != RUN) return;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        const dd_t pi = dd_add(ldd(z, n, i), dd_mul(beta, ldd(p, n, i)));
+    for (int64_t i = i0; i < n; i += (int64_t)gridDim.x * 256) {
+        const dd_t zi = i == i0 ? z0 : ldd(z, n, i);
+        const dd_t pi = dd_add(zi, dd_mul(beta, i == i0 ? p0 : ldd(p, n, i)));
         sdd(p, n, i, pi);
         if (xs) {
             xs[2 * i] = pi.c[0];
@@ -640,7 +699,7 @@ template <typename T>
 __device__ __forceinline__ T chunk_fold_t(T v, int used, T *lds)
 {
     const int t = threadIdx.x;
-    lds[t] = v;
+    if (t < kDotLanes) lds[t] = v;
     __syncthreads();
     for (int off = kDotLanes / 2; off >= 1; off >>= 1) {
         if (t < off && t + off < used) lds[t] = lds[t] + lds[t + off];
@@ -655,10 +714,11 @@ template <typename T>
 __device__ __forceinline__ T pair_tree_t(const T *__restrict__ part, int m, T *P)
 {
     const int t = threadIdx.x;
-    for (int i = t; i < m; i += kDotLanes) P[i] = part[i];
+    const int nt = blockDim.x;
+    for (int i = t; i < m; i += nt) P[i] = part[i];
     __syncthreads();
     for (int s = 1; s < m; s <<= 1) {
-        for (int i = t; (int64_t)i * 2 * s + s < m; i += kDotLanes) P[i * 2 * s] = P[i * 2 * s] + P[i * 2 * s + s];
+        for (int i = t; (int64_t)i * 2 * s + s < m; i += nt) P[i * 2 * s] = P[i * 2 * s] + P[i * 2 * s + s];
         __syncthreads();
     }
     const T r = m > 0 ? P[0] : T(0);
@@ -692,53 +752,37 @@ __global__ __launch_bounds__(256) void k_in_init(int64_t n, const T *__restrict_
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_in_dot2(int64_t n, const T *__restrict__ x1, const T *__restrict__ y1,
-                                                 const T *__restrict__ x2, const T *__restrict__ y2,
-                                                 T *__restrict__ part1, T *__restrict__ part2,
-                                                 const InState<T> *__restrict__ st)
+__global__ __launch_bounds__(kChunkThreads) void k_in_dot2(int64_t n, const T *__restrict__ x1,
+                                                           const T *__restrict__ y1, const T *__restrict__ x2,
+                                                           const T *__restrict__ y2, T *__restrict__ part1,
+                                                           T *__restrict__ part2, const InState<T> *__restrict__ st)
 {
-    __shared__ T lds[kDotLanes];
+    __shared__ T chain[2][kDotLanes];
     if (st && st->done != RUN) return;
     const int c = blockIdx.x;
-    const int t = threadIdx.x;
-    const int64_t base = (int64_t)c * kDotChunk + t;
-    const int64_t end = (n - (int64_t)c * kDotChunk) < kDotChunk ? n : (int64_t)c * kDotChunk + kDotChunk;
-    const int used = chunk_used(n, c);
-    T a1 = T(0), a2 = T(0);
-    if (t < used) {
-        for (int j0 = 0; j0 < kPerLane; j0 += kBatch) {
-            T u1[kBatch], v1[kBatch], u2[kBatch], v2[kBatch];
+    const int nv = thread_valid(n, c);
+    T pr[2][kPerThread];
 #pragma unroll
-            for (int j = 0; j < kBatch; ++j) {
-                const int64_t k = base + (int64_t)(j0 + j) * kDotLanes;
-                if (k < end) {
-                    u1[j] = x1[k];
-                    v1[j] = y1[k];
-                    if (x2) {
-                        u2[j] = x2[k];
-                        v2[j] = y2[k];
-                    }
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < kBatch; ++j) {
-                const int64_t k = base + (int64_t)(j0 + j) * kDotLanes;
-                if (k < end) {
-                    const T p1 = u1[j] * v1[j];
-                    a1 = (j0 + j == 0) ? p1 : a1 + p1;
-                    if (x2) {
-                        const T p2 = u2[j] * v2[j];
-                        a2 = (j0 + j == 0) ? p2 : a2 + p2;
-                    }
-                }
-            }
+    for (int jj = 0; jj < kPerThread; ++jj) {
+        if (jj < nv) {
+            const int64_t k = thread_elem(c, jj);
+            pr[0][jj] = x1[k] * y1[k];
+            if (x2) pr[1][jj] = x2[k] * y2[k];
         }
     }
-    const T s1 = chunk_fold_t(a1, used, lds);
-    if (t == 0) part1[c] = s1;
+    const int used = chunk_used(n, c);
     if (x2) {
-        const T s2 = chunk_fold_t(a2, used, lds);
-        if (t == 0) part2[c] = s2;
+        lane_chain<T, 2>(pr, nv, chain);
+        const T s1 = chain_fold(chain[0], used);
+        const T s2 = chain_fold(chain[1], used);
+        if (threadIdx.x == 0) {
+            part1[c] = s1;
+            part2[c] = s2;
+        }
+    } else {
+        lane_chain<T, 1>(reinterpret_cast<const T(&)[1][kPerThread]>(pr[0]), nv, chain);
+        const T s1 = chain_fold(chain[0], used);
+        if (threadIdx.x == 0) part1[c] = s1;
     }
 }
 
@@ -814,6 +858,8 @@ template <typename T>
 __device__ __forceinline__ bool in_alpha(const T *__restrict__ ppq, int m, InState<T> *__restrict__ st, T *P,
                                          T *alpha)
 {
+    __shared__ T s_rho;
+    if (threadIdx.x == 0) s_rho = st->rho;
     if (in_block_state(st) != RUN) return false;
     const T pq = pair_tree_t(ppq, m, P);
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
@@ -824,7 +870,7 @@ __device__ __forceinline__ bool in_alpha(const T *__restrict__ ppq, int m, InSta
         }
         return false;
     }
-    *alpha = st->rho / pq;
+    *alpha = s_rho / pq;
     if (lead) {
         st->pq = pq;
         st->alpha = *alpha;
@@ -836,66 +882,54 @@ __device__ __forceinline__ bool in_alpha(const T *__restrict__ ppq, int m, InSta
 // With z == NULL only d and r are updated (the learned preconditioner applies z = M r
 // in a kernel of its own) and no sums are written.
 template <typename T>
-__global__ __launch_bounds__(256) void k_in_update(int64_t n, T *__restrict__ d, T *__restrict__ r,
-                                                   T *__restrict__ z, const T *__restrict__ p,
-                                                   const T *__restrict__ q, const T *__restrict__ minv,
-                                                   const T *__restrict__ ppq, int m, T *__restrict__ prz,
-                                                   T *__restrict__ prr, InState<T> *__restrict__ st)
+__global__ __launch_bounds__(kChunkThreads) void k_in_update(int64_t n, T *__restrict__ d, T *__restrict__ r,
+                                                             T *__restrict__ z, const T *__restrict__ p,
+                                                             const T *__restrict__ q, const T *__restrict__ minv,
+                                                             const T *__restrict__ ppq, int m, T *__restrict__ prz,
+                                                             T *__restrict__ prr, InState<T> *__restrict__ st)
 {
-    __shared__ T lds[kDotLanes];
+    __shared__ T chain[2][kDotLanes];
     __shared__ T P[kMaxChunks];
+    const int c = blockIdx.x;
+    const int nv = thread_valid(n, c);
+    T dv[kPerThread], rv[kPerThread], pv[kPerThread], qv[kPerThread], mv[kPerThread];
+#pragma unroll
+    for (int jj = 0; jj < kPerThread; ++jj) {
+        if (jj < nv) {
+            const int64_t k = thread_elem(c, jj);
+            dv[jj] = d[k];
+            rv[jj] = r[k];
+            pv[jj] = p[k];
+            qv[jj] = q[k];
+            mv[jj] = minv ? minv[k] : T(0);
+        }
+    }
     T alpha;
     if (!in_alpha(ppq, m, st, P, &alpha)) return;
-    const int c = blockIdx.x;
-    const int t = threadIdx.x;
-    const int64_t base = (int64_t)c * kDotChunk + t;
-    const int64_t end = (n - (int64_t)c * kDotChunk) < kDotChunk ? n : (int64_t)c * kDotChunk + kDotChunk;
-    const int used = chunk_used(n, c);
-    T arz = T(0), arr = T(0);
-    if (t < used) {
-        for (int j0 = 0; j0 < kPerLane; j0 += kBatch) {
-            T dv[kBatch], rv[kBatch], pv[kBatch], qv[kBatch], mv[kBatch];
+    T pr[2][kPerThread];
 #pragma unroll
-            for (int j = 0; j < kBatch; ++j) {
-                const int64_t k = base + (int64_t)(j0 + j) * kDotLanes;
-                if (k < end) {
-                    dv[j] = d[k];
-                    rv[j] = r[k];
-                    pv[j] = p[k];
-                    qv[j] = q[k];
-                    mv[j] = minv ? minv[k] : T(0);
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < kBatch; ++j) {
-                const int64_t k = base + (int64_t)(j0 + j) * kDotLanes;
-                if (k < end) {
-                    const T ap = alpha * pv[j];
-                    const T aq = alpha * qv[j];
-                    d[k] = dv[j] + ap;
-                    const T rk = rv[j] - aq;
-                    r[k] = rk;
-                    if (z) {
-                        const T zk = minv ? rk * mv[j] : rk;
-                        z[k] = zk;
-                        const T p1 = rk * zk;
-                        const T p2 = rk * rk;
-                        if (j0 + j == 0) {
-                            arz = p1;
-                            arr = p2;
-                        } else {
-                            arz = arz + p1;
-                            arr = arr + p2;
-                        }
-                    }
-                }
+    for (int jj = 0; jj < kPerThread; ++jj) {
+        if (jj < nv) {
+            const int64_t k = thread_elem(c, jj);
+            const T ap = alpha * pv[jj];
+            const T aq = alpha * qv[jj];
+            d[k] = dv[jj] + ap;
+            const T rk = rv[jj] - aq;
+            r[k] = rk;
+            if (z) {
+                const T zk = minv ? rk * mv[jj] : rk;
+                z[k] = zk;
+                pr[0][jj] = rk * zk;
+                pr[1][jj] = rk * rk;
             }
         }
     }
     if (!z) return;
-    const T s1 = chunk_fold_t(arz, used, lds);
-    const T s2 = chunk_fold_t(arr, used, lds);
-    if (t == 0) {
+    lane_chain<T, 2>(pr, nv, chain);
+    const int used = chunk_used(n, c);
+    const T s1 = chain_fold(chain[0], used);
+    const T s2 = chain_fold(chain[1], used);
+    if (threadIdx.x == 0) {
         prz[c] = s1;
         prr[c] = s2;
     }
@@ -908,23 +942,37 @@ __global__ __launch_bounds__(256) void k_in_p(int64_t n, const T *__restrict__ z
                                               const InState<T> *__restrict__ sr, InState<T> *__restrict__ sw)
 {
     __shared__ T P[kMaxChunks];
+    __shared__ T s_rho, s_tol;
+    __shared__ int32_t s_iters, s_max;
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    const int64_t i0 = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    T z0 = T(0), p0 = T(0);
+    if (i0 < n) {
+        z0 = z[i0];
+        p0 = p[i0];
+    }
+    if (threadIdx.x == 0) {
+        s_rho = sr->rho;
+        s_tol = sr->tol;
+        s_iters = sr->iters;
+        s_max = sr->max_iter;
+    }
     if (in_block_state(sr) != RUN) {
         if (lead) *sw = *sr;
         return;
     }
     const T rz = pair_tree_t(prz, m, P);
     const T rr = pair_tree_t(prr, m, P);
-    const int32_t iters = sr->iters + 1;
+    const int32_t iters = s_iters + 1;
     int32_t done = RUN;
     T beta = T(0);
     if (!isfinite((double)rr) || !isfinite((double)rz)) {
         done = BROKE_DOWN;
     } else {
-        beta = rz / sr->rho;
-        if (rr <= sr->tol)
+        beta = rz / s_rho;
+        if (rr <= s_tol)
             done = CONFIRMED;
-        else if (iters >= sr->max_iter)
+        else if (iters >= s_max)
             done = ITER_LIMIT;
     }
     if (lead) {
@@ -939,9 +987,9 @@ __global__ __launch_bounds__(256) void k_in_p(int64_t n, const T *__restrict__ z
         *sw = o;
     }
     if (done != RUN) return;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        const T bp = beta * p[i];
-        p[i] = z[i] + bp;
+    for (int64_t i = i0; i < n; i += (int64_t)gridDim.x * 256) {
+        const T bp = beta * (i == i0 ? p0 : p[i]);
+        p[i] = (i == i0 ? z0 : z[i]) + bp;
     }
 }
 
@@ -1129,7 +1177,7 @@ struct Solver {
     mp_status dot2(const double *x1, const double *y1, const double *x2, const double *y2, dd_t *p1, dd_t *p2,
                    const KState *guard)
     {
-        hipLaunchKernelGGL(k_dot2, dim3(m), dim3(256), 0, s, n, x1, y1, x2, y2, p1, p2, guard);
+        hipLaunchKernelGGL(k_dot2, dim3(m), dim3(kChunkThreads), 0, s, n, x1, y1, x2, y2, p1, p2, guard);
         return launched();
     }
     // r = b - A x (q scratch)
@@ -1247,7 +1295,7 @@ mp_status run_cg(Solver &S, const double *b, double *x, const mp_solve_opts *o, 
                 KState *sr = sb[it & 1], *sw = sb[(it + 1) & 1];
                 if ((st = spmv_dd_prestaged(S.A, S.a, p, q, S.plan, S.s)) != MP_OK) return st;
                 if ((st = S.dot2(p, q, nullptr, nullptr, S.w.part[0], nullptr, sr)) != MP_OK) return st;
-                hipLaunchKernelGGL(k_cg_update, dim3(m), dim3(256), 0, S.s, n, x, r, z, p, q, minv, S.w.part[0], m,
+                hipLaunchKernelGGL(k_cg_update, dim3(m), dim3(kChunkThreads), 0, S.s, n, x, r, z, p, q, minv, S.w.part[0], m,
                                    S.w.part[1], S.w.part[2], sr);
                 hipLaunchKernelGGL(k_cg_p, dim3(S.vblocks), dim3(256), 0, S.s, n, z, p, xs, S.w.part[1], S.w.part[2],
                                    m, sr, sw);
@@ -1374,7 +1422,7 @@ mp_status inner_solve(Solver &S, const double *r_dd, int e, const T *a_in, const
     if (mv)
         hipLaunchKernelGGL(k_in_mspmv<T>, dim3(S.vblocks), dim3(256), 0, S.s, n, S.A->row_ptr, S.A->col_idx, mv, r, z,
                            p, nullptr);
-    hipLaunchKernelGGL(k_in_dot2<T>, dim3(m), dim3(256), 0, S.s, n, r, z, r, r, part1, part2, nullptr);
+    hipLaunchKernelGGL(k_in_dot2<T>, dim3(m), dim3(kChunkThreads), 0, S.s, n, r, z, r, r, part1, part2, nullptr);
     hipLaunchKernelGGL(k_in_start<T>, dim3(1), dim3(256), 0, S.s, part1, part2, m, (T)(inner_rtol * inner_rtol),
                        max_iter, ist);
     if ((st = S.launched()) != MP_OK) return st;
@@ -1389,16 +1437,16 @@ mp_status inner_solve(Solver &S, const double *r_dd, int e, const T *a_in, const
             InState<T> *sr = sb[it & 1], *sw = sb[(it + 1) & 1];
             hipLaunchKernelGGL(k_in_spmv<T>, dim3(S.vblocks), dim3(256), 0, S.s, n, S.A->row_ptr, S.A->col_idx,
                                a_in, p, q, sr);
-            hipLaunchKernelGGL(k_in_dot2<T>, dim3(m), dim3(256), 0, S.s, n, p, q, nullptr, nullptr, part0, nullptr,
+            hipLaunchKernelGGL(k_in_dot2<T>, dim3(m), dim3(kChunkThreads), 0, S.s, n, p, q, nullptr, nullptr, part0, nullptr,
                                sr);
             if (mv) {
-                hipLaunchKernelGGL(k_in_update<T>, dim3(m), dim3(256), 0, S.s, n, d, r, nullptr, p, q, nullptr, part0,
+                hipLaunchKernelGGL(k_in_update<T>, dim3(m), dim3(kChunkThreads), 0, S.s, n, d, r, nullptr, p, q, nullptr, part0,
                                    m, nullptr, nullptr, sr);
                 hipLaunchKernelGGL(k_in_mspmv<T>, dim3(S.vblocks), dim3(256), 0, S.s, n, S.A->row_ptr, S.A->col_idx,
                                    mv, r, z, nullptr, sr);
-                hipLaunchKernelGGL(k_in_dot2<T>, dim3(m), dim3(256), 0, S.s, n, r, z, r, r, part1, part2, sr);
+                hipLaunchKernelGGL(k_in_dot2<T>, dim3(m), dim3(kChunkThreads), 0, S.s, n, r, z, r, r, part1, part2, sr);
             } else {
-                hipLaunchKernelGGL(k_in_update<T>, dim3(m), dim3(256), 0, S.s, n, d, r, z, p, q, minv, part0, m,
+                hipLaunchKernelGGL(k_in_update<T>, dim3(m), dim3(kChunkThreads), 0, S.s, n, d, r, z, p, q, minv, part0, m,
                                    part1, part2, sr);
             }
             hipLaunchKernelGGL(k_in_p<T>, dim3(S.vblocks), dim3(256), 0, S.s, n, z, p, part1, part2, m, sr, sw);
