@@ -121,7 +121,8 @@ def dd_rel_diff(x, ref):
 
 def solves_section(mp, torch, repeats=2):
     """DD-accurate solves of the 64^3 sigma = 2.5 diffusion system (relative residual 1e-28):
-    plain DD Jacobi-CG against mixed-precision refinement with binary64 / binary32 inner CG."""
+    plain DD Jacobi-CG against mixed-precision refinement with binary64 / binary32 inner CG,
+    preconditioned by Jacobi or by the trained network (when its checkpoint is present)."""
     from workloads import diffusion3d_7pt, random_mp
     t0 = time.perf_counter()
     rp, ci, a = diffusion3d_7pt(m=64, sigma=2.5, seed=2)
@@ -142,12 +143,41 @@ def solves_section(mp, torch, repeats=2):
                                                             max_iter=100000))}
     out = {"workload": "3D 7-point diffusion 64^3, lognormal sigma 2.5 (seed 2), random DD b, x0 = 0",
            "plan": pol, "target_relres": 1e-28}
+    # learned preconditioner: M from the trained network (forward pass timed and added)
+    ckpt = os.path.join(ROOT, "paper_2412_17510_amd", "data", "mpnn_diffusion.npz")
+    t_fwd = None
+    if os.path.exists(ckpt):
+        from paper_2412_17510_amd import learned
+        net = mp.Mpnn()
+        with np.load(ckpt, allow_pickle=False) as f:
+            net.set_params(f["theta"])
+            meta = {k: f[k].item() for k in f.files if k != "theta"}
+        fwd = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g = mp.Graph(A, ad)
+            M = mp.mp_mpnn_forward(net, g)
+            torch.cuda.synchronize()
+            fwd.append(time.perf_counter() - t0)
+            g.destroy()
+        t_fwd = min(fwd)
+        out["learned"] = {"checkpoint": os.path.relpath(ckpt, ROOT), "trained_on": meta,
+                          "forward_s": round(t_fwd, 5),
+                          "note": "M = network forward pass on this matrix (graph set-up + 5 dense layers + "
+                                  "readouts); its time is added to the learned solves"}
+        for inn, irt in (("fp64", 1e-8), ("fp32", 1e-5)):
+            runs["ir_%s_learned" % inn] = dict(
+                fn=lambda A_, a_, b_, x_, M=M, **kw: mp.mpkrylov_ir_learned(A_, a_, M, b_, x_, **kw),
+                kw=dict(rtol=1e-28, inner=inn, inner_rtol=irt, inner_max_iter=50000, max_outer=60, max_iter=100000),
+                extra=t_fwd)
     ref = None
     for name, r in runs.items():
         best = None
         for _ in range(repeats):
             x = torch.zeros((2, n), dtype=torch.float64, device="cuda")
             info = r["fn"](A, ad, bd, x, plan=plan, check_every=32, **r["kw"])
+            info["seconds"] += r.get("extra", 0.0)
             if best is None or info["seconds"] < best[1]["seconds"]:
                 best = (x.cpu().numpy(), info)
         xh, info = best

@@ -118,16 +118,35 @@ __global__ __launch_bounds__(256) void k_bspmm(int32_t n, const int32_t *__restr
     dd_t acc[RPT];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) acc[q] = bz();
-    for (int32_t k = b; k < e; ++k) {
-        const int64_t j = __builtin_nontemporal_load(ci + k);
-        dd_t av;
-        av.c[0] = __builtin_nontemporal_load(a + k);
-        av.c[1] = __builtin_nontemporal_load(a + nnz + k);
+    // elements in groups of kG: matrix operands first, then the x gathers, then the
+    // products in element order
+    constexpr int kG = 4;
+    for (int32_t k0 = b; k0 < e; k0 += kG) {
+        int64_t jv[kG];
+        dd_t av[kG];
 #pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-            const dd_t p = dd_mul(av, bld(X, NR, j, R, r0 + q));
-            acc[q] = (k == b) ? p : dd_add(acc[q], p);
-        }
+        for (int u = 0; u < kG; ++u)
+            if (k0 + u < e) {
+                jv[u] = __builtin_nontemporal_load(ci + k0 + u);
+                av[u].c[0] = __builtin_nontemporal_load(a + k0 + u);
+                av[u].c[1] = __builtin_nontemporal_load(a + nnz + k0 + u);
+            }
+        dd_t xv[kG][RPT];
+#pragma unroll
+        for (int u = 0; u < kG; ++u)
+            if (k0 + u < e) {
+#pragma unroll
+                for (int q = 0; q < RPT; ++q) xv[u][q] = bld(X, NR, jv[u], R, r0 + q);
+            }
+#pragma unroll
+        for (int u = 0; u < kG; ++u)
+            if (k0 + u < e) {
+#pragma unroll
+                for (int q = 0; q < RPT; ++q) {
+                    const dd_t p = dd_mul(av[u], xv[u][q]);
+                    acc[q] = (k0 + u == b) ? p : dd_add(acc[q], p);
+                }
+            }
     }
 #pragma unroll
     for (int q = 0; q < RPT; ++q) bst(Y, NR, row, R, r0 + q, acc[q]);
@@ -137,22 +156,37 @@ __global__ __launch_bounds__(256) void k_bspmm(int32_t n, const int32_t *__restr
 // reductions over the rows of one system
 // ---------------------------------------------------------------------------
 
-// fold the 256 lane sums (lanes [0, used) hold values) of R right-hand sides at once
+// Chunk workgroups: kBLanes lanes x tpl(R) threads per lane.  Thread t serves lane
+// t / tpl and right-hand sides r = t % tpl + tpl*i (i < R / tpl), so the threads of a
+// wavefront read the R adjacent values of consecutive rows together (coalesced), while
+// every (lane, right-hand side) still accumulates its rows in order.
 template <int R>
-__device__ __forceinline__ void bfold(dd_t (&acc)[R], int used, dd_t (*lds)[R], dd_t *out)
+struct BMap {
+    static constexpr int TPL = R < 4 ? R : 4;   // threads per lane
+    static constexpr int RPT = R / TPL;         // right-hand sides per thread
+    static constexpr int THREADS = kBLanes * TPL;
+    __device__ static int lane() { return threadIdx.x / TPL; }
+    __device__ static int rhs(int i) { return threadIdx.x % TPL + TPL * i; }
+};
+
+// fold the lane sums (lanes [0, used) hold values): lds[l][r] += lds[l + off][r] for
+// off = 128 .. 1; out[r] = lds[0][r]
+template <int R>
+__device__ __forceinline__ void bfold(const dd_t (&acc)[BMap<R>::RPT], int used, dd_t (*lds)[R], dd_t *out)
 {
-    const int t = threadIdx.x;
+    using M = BMap<R>;
+    const int l = M::lane();
 #pragma unroll
-    for (int r = 0; r < R; ++r) lds[t][r] = acc[r];
+    for (int i = 0; i < M::RPT; ++i) lds[l][M::rhs(i)] = acc[i];
     __syncthreads();
     for (int off = kBLanes / 2; off >= 1; off >>= 1) {
-        if (t < off && t + off < used) {
+        if (l < off && l + off < used) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) lds[t][r] = dd_add(lds[t][r], lds[t + off][r]);
+            for (int i = 0; i < M::RPT; ++i) lds[l][M::rhs(i)] = dd_add(lds[l][M::rhs(i)], lds[l + off][M::rhs(i)]);
         }
         __syncthreads();
     }
-    if (t < R) out[t] = lds[0][t];
+    if (threadIdx.x < R) out[threadIdx.x] = lds[0][threadIdx.x];
     __syncthreads();
 }
 
@@ -178,30 +212,33 @@ __device__ __forceinline__ ChunkInfo chunk_info(int c, const int32_t *__restrict
 
 // chunk sums of (X1, Y1) and optionally (X2, Y2), every right-hand side
 template <int R>
-__global__ __launch_bounds__(256) void k_bdot2(int32_t n, const double *__restrict__ X1, const double *__restrict__ Y1,
-                                               const double *__restrict__ X2, const double *__restrict__ Y2,
-                                               dd_t *__restrict__ part1, dd_t *__restrict__ part2,
-                                               const int32_t *__restrict__ chunk_row,
-                                               const int32_t *__restrict__ chunk_sys,
-                                               const int32_t *__restrict__ sys_ptr)
+__global__ __launch_bounds__(BMap<R>::THREADS) void k_bdot2(int32_t n, const double *__restrict__ X1,
+                                                            const double *__restrict__ Y1,
+                                                            const double *__restrict__ X2,
+                                                            const double *__restrict__ Y2, dd_t *__restrict__ part1,
+                                                            dd_t *__restrict__ part2,
+                                                            const int32_t *__restrict__ chunk_row,
+                                                            const int32_t *__restrict__ chunk_sys,
+                                                            const int32_t *__restrict__ sys_ptr)
 {
+    using M = BMap<R>;
     __shared__ dd_t lds[kBLanes][R];
     const int c = blockIdx.x;
-    const int t = threadIdx.x;
     const ChunkInfo ch = chunk_info(c, chunk_row, chunk_sys, sys_ptr);
     const int64_t NR = (int64_t)n * R;
-    dd_t a1[R], a2[R];
+    dd_t a1[M::RPT], a2[M::RPT];
 #pragma unroll
-    for (int r = 0; r < R; ++r) a1[r] = a2[r] = bz();
+    for (int i = 0; i < M::RPT; ++i) a1[i] = a2[i] = bz();
     bool first = true;
-    for (int64_t k = ch.row0 + t; k < ch.end; k += kBLanes) {
+    for (int64_t k = ch.row0 + M::lane(); k < ch.end; k += kBLanes) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
+        for (int i = 0; i < M::RPT; ++i) {
+            const int r = M::rhs(i);
             const dd_t p1 = dd_mul(bld(X1, NR, k, R, r), bld(Y1, NR, k, R, r));
-            a1[r] = first ? p1 : dd_add(a1[r], p1);
+            a1[i] = first ? p1 : dd_add(a1[i], p1);
             if (X2) {
                 const dd_t p2 = dd_mul(bld(X2, NR, k, R, r), bld(Y2, NR, k, R, r));
-                a2[r] = first ? p2 : dd_add(a2[r], p2);
+                a2[i] = first ? p2 : dd_add(a2[i], p2);
             }
         }
         first = false;
@@ -241,20 +278,19 @@ __device__ __forceinline__ int32_t row_system(const int32_t *__restrict__ sys_pt
     return lo;
 }
 
-// R = B - Q for pairs in state `want` (all pairs when want < 0)
+// R = B - Q for pairs in state `want` (all pairs when want < 0); one thread per
+// (row, right-hand side), right-hand sides fastest (coalesced)
 template <int R>
 __global__ __launch_bounds__(256) void k_bresidual(int32_t n, const double *__restrict__ B, const double *__restrict__ Q,
                                                    double *__restrict__ Rv, const int32_t *__restrict__ sys_ptr, int nsys,
                                                    const BState *__restrict__ st, int want)
 {
     const int64_t NR = (int64_t)n * R;
-    for (int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x; row < n; row += (int64_t)gridDim.x * 256) {
-        const int s = want < 0 ? 0 : row_system(sys_ptr, nsys, row);
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            if (want >= 0 && st[s * R + r].done != want) continue;
-            bst(Rv, NR, row, R, r, dd_add(bld(B, NR, row, R, r), mp_neg(bld(Q, NR, row, R, r))));
-        }
+    for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < NR; g += (int64_t)gridDim.x * 256) {
+        const int64_t row = g / R;
+        const int r = (int)(g % R);
+        if (want >= 0 && st[row_system(sys_ptr, nsys, row) * R + r].done != want) continue;
+        bst(Rv, NR, row, R, r, dd_add(bld(B, NR, row, R, r), mp_neg(bld(Q, NR, row, R, r))));
     }
 }
 
@@ -266,16 +302,14 @@ __global__ __launch_bounds__(256) void k_bprecond_copy(int32_t n, const double *
                                                        int nsys, const BState *__restrict__ st, int want)
 {
     const int64_t NR = (int64_t)n * R;
-    for (int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x; row < n; row += (int64_t)gridDim.x * 256) {
-        const int s = want < 0 ? 0 : row_system(sys_ptr, nsys, row);
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            if (want >= 0 && st[s * R + r].done != want) continue;
-            const dd_t rv = bld(Rv, NR, row, R, r);
-            const dd_t z = minv ? dd_mul_d(rv, minv[row]) : rv;
-            bst(Z, NR, row, R, r, z);
-            bst(P, NR, row, R, r, z);
-        }
+    for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < NR; g += (int64_t)gridDim.x * 256) {
+        const int64_t row = g / R;
+        const int r = (int)(g % R);
+        if (want >= 0 && st[row_system(sys_ptr, nsys, row) * R + r].done != want) continue;
+        const dd_t rv = bld(Rv, NR, row, R, r);
+        const dd_t z = minv ? dd_mul_d(rv, minv[row]) : rv;
+        bst(Z, NR, row, R, r, z);
+        bst(P, NR, row, R, r, z);
     }
 }
 
@@ -436,44 +470,55 @@ __global__ __launch_bounds__(256) void k_bexit(const dd_t *__restrict__ prr, con
 
 // x += alpha p; r -= alpha q; z = M^-1 r; chunk sums of (r, z), (r, r) -- running pairs
 template <int R>
-__global__ __launch_bounds__(256) void k_bupdate(int32_t n, double *__restrict__ X, double *__restrict__ Rv,
-                                                 double *__restrict__ Z, const double *__restrict__ P,
-                                                 const double *__restrict__ Q, const double *__restrict__ minv,
-                                                 dd_t *__restrict__ prz, dd_t *__restrict__ prr,
-                                                 const int32_t *__restrict__ chunk_row,
-                                                 const int32_t *__restrict__ chunk_sys,
-                                                 const int32_t *__restrict__ sys_ptr, const BState *__restrict__ st)
+__global__ __launch_bounds__(BMap<R>::THREADS) void k_bupdate(int32_t n, double *__restrict__ X,
+                                                              double *__restrict__ Rv, double *__restrict__ Z,
+                                                              const double *__restrict__ P,
+                                                              const double *__restrict__ Q,
+                                                              const double *__restrict__ minv,
+                                                              dd_t *__restrict__ prz, dd_t *__restrict__ prr,
+                                                              const int32_t *__restrict__ chunk_row,
+                                                              const int32_t *__restrict__ chunk_sys,
+                                                              const int32_t *__restrict__ sys_ptr,
+                                                              const BState *__restrict__ st)
 {
+    using M = BMap<R>;
     __shared__ dd_t lds[kBLanes][R];
+    __shared__ int s_any;
     const int c = blockIdx.x;
-    const int t = threadIdx.x;
     const ChunkInfo ch = chunk_info(c, chunk_row, chunk_sys, sys_ptr);
     const int64_t NR = (int64_t)n * R;
-    bool run[R];
-    dd_t alpha[R], arz[R], arr[R];
-    bool any = false;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        run[r] = st[ch.sys * R + r].done == B_RUN;
-        alpha[r] = st[ch.sys * R + r].alpha;
-        arz[r] = arr[r] = bz();
-        any |= run[r];
+    if (threadIdx.x == 0) {
+        int any = 0;
+        for (int r = 0; r < R; ++r) any |= st[ch.sys * R + r].done == B_RUN;
+        s_any = any;
     }
-    if (!any) return;   // uniform in the workgroup
+    __syncthreads();
+    if (!s_any) return;   // uniform in the workgroup
+    bool run[M::RPT];
+    dd_t alpha[M::RPT], arz[M::RPT], arr[M::RPT];
+#pragma unroll
+    for (int i = 0; i < M::RPT; ++i) {
+        run[i] = st[ch.sys * R + M::rhs(i)].done == B_RUN;
+        alpha[i] = st[ch.sys * R + M::rhs(i)].alpha;
+        arz[i] = arr[i] = bz();
+    }
     bool first = true;
-    for (int64_t k = ch.row0 + t; k < ch.end; k += kBLanes) {
+    for (int64_t k = ch.row0 + M::lane(); k < ch.end; k += kBLanes) {
         const double mi = minv ? minv[k] : 1.0;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            if (!run[r]) continue;
-            bst(X, NR, k, R, r, dd_add(bld(X, NR, k, R, r), dd_mul(alpha[r], bld(P, NR, k, R, r))));
-            const dd_t rk = dd_add(bld(Rv, NR, k, R, r), mp_neg(dd_mul(alpha[r], bld(Q, NR, k, R, r))));
+        for (int i = 0; i < M::RPT; ++i) {
+            if (!run[i]) continue;
+            const int r = M::rhs(i);
+            const dd_t xk = bld(X, NR, k, R, r), pk = bld(P, NR, k, R, r);
+            const dd_t rk0 = bld(Rv, NR, k, R, r), qk = bld(Q, NR, k, R, r);
+            bst(X, NR, k, R, r, dd_add(xk, dd_mul(alpha[i], pk)));
+            const dd_t rk = dd_add(rk0, mp_neg(dd_mul(alpha[i], qk)));
             bst(Rv, NR, k, R, r, rk);
             const dd_t zk = minv ? dd_mul_d(rk, mi) : rk;
             bst(Z, NR, k, R, r, zk);
             const dd_t p1 = dd_mul(rk, zk), p2 = dd_mul(rk, rk);
-            arz[r] = first ? p1 : dd_add(arz[r], p1);
-            arr[r] = first ? p2 : dd_add(arr[r], p2);
+            arz[i] = first ? p1 : dd_add(arz[i], p1);
+            arr[i] = first ? p2 : dd_add(arr[i], p2);
         }
         first = false;
     }
@@ -483,24 +528,30 @@ __global__ __launch_bounds__(256) void k_bupdate(int32_t n, double *__restrict__
 
 // p = z + beta p -- running pairs
 template <int R>
-__global__ __launch_bounds__(256) void k_bp(int32_t n, const double *__restrict__ Z, double *__restrict__ P,
-                                            const int32_t *__restrict__ chunk_row, const int32_t *__restrict__ chunk_sys,
-                                            const int32_t *__restrict__ sys_ptr, const BState *__restrict__ st)
+__global__ __launch_bounds__(BMap<R>::THREADS) void k_bp(int32_t n, const double *__restrict__ Z,
+                                                         double *__restrict__ P,
+                                                         const int32_t *__restrict__ chunk_row,
+                                                         const int32_t *__restrict__ chunk_sys,
+                                                         const int32_t *__restrict__ sys_ptr,
+                                                         const BState *__restrict__ st)
 {
+    using M = BMap<R>;
     const int c = blockIdx.x;
     const ChunkInfo ch = chunk_info(c, chunk_row, chunk_sys, sys_ptr);
     const int64_t NR = (int64_t)n * R;
-    bool run[R];
-    dd_t beta[R];
+    bool run[M::RPT];
+    dd_t beta[M::RPT];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        run[r] = st[ch.sys * R + r].done == B_RUN;
-        beta[r] = st[ch.sys * R + r].beta;
+    for (int i = 0; i < M::RPT; ++i) {
+        run[i] = st[ch.sys * R + M::rhs(i)].done == B_RUN;
+        beta[i] = st[ch.sys * R + M::rhs(i)].beta;
     }
-    for (int64_t k = ch.row0 + threadIdx.x; k < ch.end; k += kBLanes) {
+    for (int64_t k = ch.row0 + M::lane(); k < ch.end; k += kBLanes) {
 #pragma unroll
-        for (int r = 0; r < R; ++r)
-            if (run[r]) bst(P, NR, k, R, r, dd_add(bld(Z, NR, k, R, r), dd_mul(beta[r], bld(P, NR, k, R, r))));
+        for (int i = 0; i < M::RPT; ++i) {
+            const int r = M::rhs(i);
+            if (run[i]) bst(P, NR, k, R, r, dd_add(bld(Z, NR, k, R, r), dd_mul(beta[i], bld(P, NR, k, R, r))));
+        }
     }
 }
 
@@ -606,7 +657,8 @@ struct BatchCG {
     mp_status spmm(const double *X, double *Y) { return launch_bspmm_r<R>(p->tpr, A, a, X, Y, s); }
     void dot2(const double *X1, const double *Y1, const double *X2, const double *Y2, dd_t *p1, dd_t *p2)
     {
-        hipLaunchKernelGGL(k_bdot2<R>, dim3(p->n_chunks), dim3(256), 0, s, A->n_rows, X1, Y1, X2, Y2, p1, p2,
+        hipLaunchKernelGGL(k_bdot2<R>, dim3(p->n_chunks), dim3(BMap<R>::THREADS), 0, s, A->n_rows, X1, Y1, X2, Y2, p1,
+                           p2,
                            p->d_chunk_row, p->d_chunk_sys, p->d_sys_ptr);
     }
     // one CG step for every running pair
@@ -616,10 +668,11 @@ struct BatchCG {
         if (stt != MP_OK) return stt;
         dot2(P, Q, nullptr, nullptr, part[0], nullptr);
         hipLaunchKernelGGL(k_balpha<R>, dim3(p->nsys), dim3(256), 0, s, part[0], p->d_sys_chunk, st);
-        hipLaunchKernelGGL(k_bupdate<R>, dim3(p->n_chunks), dim3(256), 0, s, A->n_rows, X, Rv, Z, P, Q, minv, part[1],
+        hipLaunchKernelGGL(k_bupdate<R>, dim3(p->n_chunks), dim3(BMap<R>::THREADS), 0, s, A->n_rows, X, Rv, Z, P, Q, minv,
+                           part[1],
                            part[2], p->d_chunk_row, p->d_chunk_sys, p->d_sys_ptr, st);
         hipLaunchKernelGGL(k_bbeta<R>, dim3(p->nsys), dim3(256), 0, s, part[1], part[2], p->d_sys_chunk, max_iter, st);
-        hipLaunchKernelGGL(k_bp<R>, dim3(p->n_chunks), dim3(256), 0, s, A->n_rows, Z, P, p->d_chunk_row,
+        hipLaunchKernelGGL(k_bp<R>, dim3(p->n_chunks), dim3(BMap<R>::THREADS), 0, s, A->n_rows, Z, P, p->d_chunk_row,
                            p->d_chunk_sys, p->d_sys_ptr, st);
         return launched();
     }
