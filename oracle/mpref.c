@@ -252,7 +252,38 @@ static mpv qd_mul(mpv x, mpv y)
 
 /* Triple-double (Sec. 2): the QD operations applied with the fourth component
  * of both operands set to zero; the result keeps its first three components. */
+/* Algorithm 4 (QD times binary64), with the garbled steps read after Hida, Li and
+ * Bailey's product of a quad-double by a double: the three leading partial products
+ * exactly (TwoProd), the fourth plainly (the listing adds x[3] and y where the
+ * product is meant); the order-eps terms merged by a TwoSum (the listing prints
+ * TwoProd, but errors of sums are summed); the order-eps^2 terms by ThreeSum; the
+ * first order-eps^2 error, the second product error and the fourth product by
+ * ThreeSum2 (the listing's operand list repeats an already consumed term); the two
+ * remaining errors by one plain add; then the 5 -> 4 renormalisation. */
+static mpv qd_mul_d(mpv x, double y)
+{
+    double p0, q0, p1, q1, p2, q2, p3, s1, s2;
+    two_prod(x.c[0], y, &p0, &q0);
+    two_prod(x.c[1], y, &p1, &q1);
+    two_prod(x.c[2], y, &p2, &q2);
+    p3 = x.c[3] * y;
+    two_sum(q0, p1, &s1, &s2);
+    three_sum(s2, q1, p2, &s2, &q1, &p2);
+    three_sum2(q1, q2, p3, &q1, &q2);
+    return renorm5(p0, s1, s2, q1, q2 + p2);
+}
+
 static mpv td_trunc(mpv r) { r.c[3] = 0.0; return r; }
+
+/* Algorithm 5 (TD times binary64): the QD product of the zero-padded value, first
+ * three components kept -- TD operations are the QD ones with x[3] = 0 (Sec. 2). */
+static mpv td_mul_d(mpv x, double y) { x.c[3] = 0.0; return td_trunc(qd_mul_d(x, y)); }
+
+/* K-component value times a binary64 value (Algs 3-5) */
+static mpv mp_mul_d(int K, mpv x, double y)
+{
+    return K == 2 ? dd_mul_d(x, y) : (K == 3 ? td_mul_d(x, y) : qd_mul_d(x, y));
+}
 static mpv td_add(mpv x, mpv y) { x.c[3] = 0.0; y.c[3] = 0.0; return td_trunc(qd_add(x, y)); }
 static mpv td_mul(mpv x, mpv y) { x.c[3] = 0.0; y.c[3] = 0.0; return td_trunc(qd_mul(x, y)); }
 
@@ -287,7 +318,7 @@ static void store_mp(int K, double *base, int64_t len, int64_t i, mpv v)
 
 /* ------------------------------------------------------------------------- */
 /* Exported element-wise operations (for the tests of the arithmetic itself). */
-/* op: 0 = add, 1 = mul, 2 = mul by binary64 (DD only, y holds n doubles).     */
+/* op: 0 = add, 1 = mul, 2 = mul by binary64 (Algs 3-5; y holds n doubles).     */
 /* ------------------------------------------------------------------------- */
 int oracle_eft(int which, int64_t n, const double *a, const double *b, double *s, double *e)
 {
@@ -308,8 +339,7 @@ int oracle_elementwise(int K, int op, int64_t n, const double *x, const double *
     for (i = 0; i < n; ++i) {
         mpv a = load_mp(K, x, n, i), out;
         if (op == 2) {
-            if (K != 2) return -1;
-            out = dd_mul_d(a, y[i]);
+            out = mp_mul_d(K, a, y[i]);
         } else {
             mpv b = load_mp(K, y, n, i);
             out = op == 0 ? mp_add(K, a, b) : mp_mul(K, a, b);
@@ -359,6 +389,24 @@ static mpv row_sum(int K, int64_t start, int64_t len, int W, const int32_t *col,
         lanes[l] = mp_mul(K, load_mp(K, A, nnz, k), load_mp(K, X, n, col[k]));
         for (k = k + W; k < start + len; k += W)
             lanes[l] = mp_add(K, lanes[l], mp_mul(K, load_mp(K, A, nnz, k), load_mp(K, X, n, col[k])));
+    }
+    for (off = W / 2; off >= 1; off /= 2)
+        for (l = 0; l < off; ++l)
+            lanes[l] = mp_add(K, lanes[l], lanes[l + off]);
+    return lanes[0];
+}
+
+/* One accumulator set with a binary64 matrix: sum_k mul_d(X[col[k]], A[k]) in the
+ * lane/fold order of row_sum. */
+static mpv row_sum_d(int K, int64_t start, int64_t len, int W, const int32_t *col, const double *A,
+                     const double *X, int64_t n, mpv *lanes)
+{
+    int l, off;
+    for (l = 0; l < W; ++l) {
+        int64_t k = start + l;
+        lanes[l] = mp_mul_d(K, load_mp(K, X, n, col[k]), A[k]);
+        for (k = k + W; k < start + len; k += W)
+            lanes[l] = mp_add(K, lanes[l], mp_mul_d(K, load_mp(K, X, n, col[k]), A[k]));
     }
     for (off = W / 2; off >= 1; off /= 2)
         for (l = 0; l < off; ++l)
@@ -953,4 +1001,47 @@ int oracle_ir(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col
     free(r); free(q); free(minv); free(r64); free(d64);
     free(a32); free(m32); free(r32); free(d32); free(mv32);
     return status;
+}
+
+/*
+ * y = A x with a binary64 matrix (one value per element) and a K-component x
+ * (the paper's SpMV of binary64 SuiteSparse matrices, Sec. 2 with Algs 3-5): each
+ * product is mul_d(x_col, a_k); the summation order is oracle_spmv's.  Real only.
+ */
+int oracle_spmv_dmat(int K, int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_t *row_ptr,
+                     const int32_t *col_idx, const uint8_t *log2w, const double *a, const double *x, double *y,
+                     int nthreads)
+{
+    int64_t i;
+    int bad = 0;
+    if (K < 2 || K > 4) return -1;
+    (void)nnz;
+#ifdef _OPENMP
+    const int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel num_threads(nt)
+    {
+        mpv *lanes = (mpv *)malloc(sizeof(mpv) * 1024);
+#pragma omp for schedule(dynamic, 256)
+        for (i = 0; i < n_rows; ++i) {
+            int64_t start = row_ptr[i], len = (int64_t)row_ptr[i + 1] - row_ptr[i];
+            int lw = log2w ? log2w[i] : oracle_canonical_log2w(len);
+            int W = 1 << lw;
+            mpv zero = {{0.0, 0.0, 0.0, 0.0}};
+            if (len == 0) {
+                store_mp(K, y, n_rows, i, zero);
+                continue;
+            }
+            if (lw > 10 || W > len) {
+#pragma omp atomic write
+                bad = 1;
+                continue;
+            }
+            store_mp(K, y, n_rows, i, row_sum_d(K, start, len, W, col_idx, a, x, n_cols, lanes));
+        }
+        free(lanes);
+    }
+    return bad ? -1 : 0;
 }

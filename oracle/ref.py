@@ -25,9 +25,10 @@ def lib():
         L.oracle_elementwise.argtypes = [ctypes.c_int, ctypes.c_int, i64, P, P, P]
         L.oracle_renorm5.argtypes = [i64, P, P]
         L.oracle_spmv.argtypes = [ctypes.c_int, i64, i64, i64, P, P, P, P, P, P, P, P, P, i64, P, ctypes.c_int]
+        L.oracle_spmv_dmat.argtypes = [ctypes.c_int, i64, i64, i64, P, P, P, P, P, P, ctypes.c_int]
         L.oracle_canonical_log2w.argtypes = [i64]
         L.oracle_num_threads.argtypes = []
-        for name in ("oracle_eft", "oracle_elementwise", "oracle_renorm5", "oracle_spmv",
+        for name in ("oracle_eft", "oracle_elementwise", "oracle_renorm5", "oracle_spmv", "oracle_spmv_dmat",
                      "oracle_canonical_log2w", "oracle_num_threads"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -53,7 +54,8 @@ def eft(which, a, b):
 
 
 def elementwise(K, op, x, y):
-    """op: 'add' | 'mul' | 'mul_d' (DD times binary64).  x (K, n); y (K, n) or (n,)."""
+    """op: 'add' | 'mul' | 'mul_d' (K-component times binary64, Algs 3-5).  x (K, n);
+    y (K, n), or (n,) for mul_d."""
     code = {"add": 0, "mul": 1, "mul_d": 2}[op]
     x, y = _f64(x), _f64(y)
     n = x.shape[1]
@@ -108,6 +110,26 @@ def spmv(K, row_ptr, col_idx, a_re, x_re, a_im=None, x_im=None, log2w=None, rows
     if rc != 0:
         raise ValueError("oracle_spmv: invalid argument (lane width larger than the row?)")
     return (y_re, y_im) if cplx else y_re
+
+
+def spmv_dmat(K, row_ptr, col_idx, a, x, log2w=None, n_cols=None, nthreads=0):
+    """y = A x with a binary64 matrix a (nnz values) and a K-component x (Algs 3-5 for
+    the products, the order of spmv).  Returns y (K, n)."""
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
+    n = row_ptr.size - 1
+    nnz = col_idx.size
+    a, x = _f64(a), _f64(x)
+    if n_cols is None:
+        n_cols = x.shape[1]
+    assert a.shape == (nnz,) and x.shape == (K, n_cols)
+    y = np.full((K, n), np.nan)
+    lw = None if log2w is None else np.ascontiguousarray(log2w, dtype=np.uint8)
+    rc = lib().oracle_spmv_dmat(K, n, n_cols, nnz, _p(row_ptr), _p(col_idx), _p(lw), _p(a), _p(x), _p(y),
+                                int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle_spmv_dmat: invalid argument")
+    return y
 
 
 def num_threads():
