@@ -36,6 +36,7 @@ FP64_INSTR_PEAK = 256 * 64 * 2.4e9      # 39.3e12 FP64 VALU instructions / s
 # counts follow the operation sequences of the library's arithmetic header)
 OPS_MUL = {2: 9, 3: 118, 4: 118}
 OPS_ADD = {2: 11, 3: 82, 4: 82}
+OPS_MUL_D = {2: 7, 3: 66, 4: 66}    # K-component times binary64 (Algs 3-5)
 
 VARIANTS = [(2, False, "dd"), (3, False, "td"), (4, False, "qd"),
             (2, True, "dd_complex"), (3, True, "td_complex"), (4, True, "qd_complex")]
@@ -45,22 +46,25 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def ops_per_nnz(K, cplx):
+def ops_per_nnz(K, cplx, dmat=False):
+    if dmat:
+        return OPS_MUL_D[K] + OPS_ADD[K]
     per = OPS_MUL[K] + OPS_ADD[K]
     return per * (4 if cplx else 1)
 
 
-def algo_bytes(n, nnz, K, cplx):
+def algo_bytes(n, nnz, K, cplx, dmat=False):
     c = 2 if cplx else 1
-    return 4 * (n + 1) + nnz * (4 + 8 * K * c) + 2 * 8 * K * c * n
+    per_nnz = 4 + (8 if dmat else 8 * K * c)
+    return 4 * (n + 1) + nnz * per_nnz + 2 * 8 * K * c * n
 
 
-def roofline(n, nnz, K, cplx, ms):
+def roofline(n, nnz, K, cplx, ms, dmat=False):
     t = ms * 1e-3
-    gbs = algo_bytes(n, nnz, K, cplx) / t / 1e9
-    tops = ops_per_nnz(K, cplx) * nnz / t / 1e12
-    t_hbm = algo_bytes(n, nnz, K, cplx) / (HBM_PEAK_GBS * 1e9)
-    t_alu = ops_per_nnz(K, cplx) * nnz / FP64_INSTR_PEAK
+    gbs = algo_bytes(n, nnz, K, cplx, dmat) / t / 1e9
+    tops = ops_per_nnz(K, cplx, dmat) * nnz / t / 1e12
+    t_hbm = algo_bytes(n, nnz, K, cplx, dmat) / (HBM_PEAK_GBS * 1e9)
+    t_alu = ops_per_nnz(K, cplx, dmat) * nnz / FP64_INSTR_PEAK
     if t_hbm >= t_alu:
         return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(gbs / HBM_PEAK_GBS, 4)}
@@ -356,6 +360,19 @@ def main():
             name, pol, ms, nnz / (ms * 1e-3) / 1e9, rf["bound"], rf["achieved"], rf["unit"], 100 * rf["frac"]))
         if name == "dd":
             headline = (ms, wall, rf, pol)
+        if not cplx:
+            # binary64 matrix (its leading components) times the same K-component x, same plan
+            a64 = ad_re[0].contiguous()
+            fd = mp.SPMV_D[K]
+            msd, _ = time_loop(lambda: fd(A, a64, xd_re, y_re, plan=plan), args.steps, args.warmup, torch)
+            rfd = roofline(n, nnz, K, False, msd, dmat=True)
+            results[name + "_d"] = {"gnnz_s": round(nnz / (msd * 1e-3) / 1e9, 3), "ms": round(msd, 4),
+                                    "plan": pol, "roofline": rfd,
+                                    "matrix": "binary64 (Algs 3-5 products)"}
+            log("%-10s policy=%s %.4f ms  %.2f GNNZ/s  %s %.1f %s (%.1f%%)" % (
+                name + "_d", pol, msd, nnz / (msd * 1e-3) / 1e9, rfd["bound"], rfd["achieved"], rfd["unit"],
+                100 * rfd["frac"]))
+            del a64
         del ad_re, ad_im, xd_re, xd_im, y_re, y_im, plan
         torch.cuda.empty_cache()
 

@@ -167,6 +167,26 @@ mp_status mpspmv_csr_qd_complex(const mp_csr *A, const double *a_re, const doubl
                                 const double *x_re, const double *x_im, double *y_re, double *y_im,
                                 const mp_plan *plan, void *stream);
 
+/*
+ * y = A x with a binary64 matrix and a K-component vector (Sec. 2: the SuiteSparse
+ * matrices are binary64, multiplied by DD/QD/TD vectors with the mixed products of
+ * Algs 3, 4 and 5).  a: nnz binary64 values (ONE component, element order of A);
+ * x, y: K-component planar arrays as in mpspmv_csr_dd.  Each product is
+ * mul_d(x_col, a_k) -- DD: TwoProd of the leading part plus the trailing part times
+ * a, QuickTwoSum (Alg. 3); QD: Alg. 4 read after Hida, Li and Bailey; TD: the QD
+ * product of the zero-padded value, three components kept (Alg. 5 per Sec. 2) --
+ * and the row sums follow the plan's order exactly as in mpspmv_csr_dd, so a plan
+ * made for (K, real) serves both.  For DD the result equals mpspmv_csr_dd on the
+ * same matrix stored with zero trailing components.  Errors and aliasing rules as
+ * mpspmv_csr_dd (a is nnz doubles).
+ */
+mp_status mpspmv_csr_dd_d(const mp_csr *A, const double *a, const double *x, double *y, const mp_plan *plan,
+                          void *stream);
+mp_status mpspmv_csr_td_d(const mp_csr *A, const double *a, const double *x, double *y, const mp_plan *plan,
+                          void *stream);
+mp_status mpspmv_csr_qd_d(const mp_csr *A, const double *a, const double *x, double *y, const mp_plan *plan,
+                          void *stream);
+
 /* ---------------------------------------------------------------------------
  * Krylov solvers in double-double (Sec. 4.2: CG for symmetric positive-definite A,
  * BiCGSTAB for non-symmetric A; x0 given, stop on the residual norm).

@@ -1010,9 +1010,9 @@ int oracle_ir(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col
  */
 int oracle_spmv_dmat(int K, int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_t *row_ptr,
                      const int32_t *col_idx, const uint8_t *log2w, const double *a, const double *x, double *y,
-                     int nthreads)
+                     int64_t nsel, const int64_t *rows, int nthreads)
 {
-    int64_t i;
+    int64_t t, count = rows ? nsel : n_rows;
     int bad = 0;
     if (K < 2 || K > 4) return -1;
     (void)nnz;
@@ -1025,7 +1025,8 @@ int oracle_spmv_dmat(int K, int64_t n_rows, int64_t n_cols, int64_t nnz, const i
     {
         mpv *lanes = (mpv *)malloc(sizeof(mpv) * 1024);
 #pragma omp for schedule(dynamic, 256)
-        for (i = 0; i < n_rows; ++i) {
+        for (t = 0; t < count; ++t) {
+            int64_t i = rows ? rows[t] : t;
             int64_t start = row_ptr[i], len = (int64_t)row_ptr[i + 1] - row_ptr[i];
             int lw = log2w ? log2w[i] : oracle_canonical_log2w(len);
             int W = 1 << lw;

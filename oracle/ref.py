@@ -25,7 +25,7 @@ def lib():
         L.oracle_elementwise.argtypes = [ctypes.c_int, ctypes.c_int, i64, P, P, P]
         L.oracle_renorm5.argtypes = [i64, P, P]
         L.oracle_spmv.argtypes = [ctypes.c_int, i64, i64, i64, P, P, P, P, P, P, P, P, P, i64, P, ctypes.c_int]
-        L.oracle_spmv_dmat.argtypes = [ctypes.c_int, i64, i64, i64, P, P, P, P, P, P, ctypes.c_int]
+        L.oracle_spmv_dmat.argtypes = [ctypes.c_int, i64, i64, i64, P, P, P, P, P, P, i64, P, ctypes.c_int]
         L.oracle_canonical_log2w.argtypes = [i64]
         L.oracle_num_threads.argtypes = []
         for name in ("oracle_eft", "oracle_elementwise", "oracle_renorm5", "oracle_spmv", "oracle_spmv_dmat",
@@ -112,9 +112,10 @@ def spmv(K, row_ptr, col_idx, a_re, x_re, a_im=None, x_im=None, log2w=None, rows
     return (y_re, y_im) if cplx else y_re
 
 
-def spmv_dmat(K, row_ptr, col_idx, a, x, log2w=None, n_cols=None, nthreads=0):
+def spmv_dmat(K, row_ptr, col_idx, a, x, log2w=None, n_cols=None, rows=None, nthreads=0):
     """y = A x with a binary64 matrix a (nnz values) and a K-component x (Algs 3-5 for
-    the products, the order of spmv).  Returns y (K, n)."""
+    the products, the order of spmv).  Returns y (K, n); rows: optional subset (the
+    other rows are NaN)."""
     row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
     col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
     n = row_ptr.size - 1
@@ -125,8 +126,9 @@ def spmv_dmat(K, row_ptr, col_idx, a, x, log2w=None, n_cols=None, nthreads=0):
     assert a.shape == (nnz,) and x.shape == (K, n_cols)
     y = np.full((K, n), np.nan)
     lw = None if log2w is None else np.ascontiguousarray(log2w, dtype=np.uint8)
+    sel = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
     rc = lib().oracle_spmv_dmat(K, n, n_cols, nnz, _p(row_ptr), _p(col_idx), _p(lw), _p(a), _p(x), _p(y),
-                                int(nthreads))
+                                0 if sel is None else sel.size, _p(sel), int(nthreads))
     if rc != 0:
         raise ValueError("oracle_spmv_dmat: invalid argument")
     return y

@@ -73,7 +73,8 @@ _SIGS = {
     "mp_plan_row_log2w": ([_P, _P], ctypes.c_int),
     "mp_plan_info": ([_P] + [ctypes.POINTER(_I)] * 5, ctypes.c_int),
 }
-for _name in ("mpspmv_csr_dd", "mpspmv_csr_td", "mpspmv_csr_qd"):
+for _name in ("mpspmv_csr_dd", "mpspmv_csr_td", "mpspmv_csr_qd", "mpspmv_csr_dd_d", "mpspmv_csr_td_d",
+              "mpspmv_csr_qd_d"):
     _SIGS[_name] = ([_CSR, _P, _P, _P, _P, _P], ctypes.c_int)
 for _name in ("mpspmv_csr_dd_complex", "mpspmv_csr_td_complex", "mpspmv_csr_qd_complex"):
     _SIGS[_name] = ([_CSR, _P, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int)
@@ -255,6 +256,23 @@ def _spmv_real(name, K):
     return call
 
 
+def _spmv_dmat(name, K):
+    fn = getattr(_lib, name)
+
+    def call(A, a, x, y, plan=None, stream=None):
+        import torch
+        if not a.is_cuda or a.dtype != torch.float64 or not a.is_contiguous() or a.numel() != A.nnz:
+            raise ValueError("a must be a contiguous CUDA float64 tensor of %d binary64 values" % A.nnz)
+        _check_mp(x, K, A.n_cols, "x")
+        _check_mp(y, K, A.n_rows, "y")
+        _check(fn(ctypes.byref(A.c), _ptr(a), _ptr(x), _ptr(y), _plan_handle(plan), _stream_ptr(stream)), name)
+        return y
+
+    call.__name__ = name
+    call.__doc__ = ("y = A x with a binary64 matrix and a %d-component vector (C ABI %s)." % (K, name))
+    return call
+
+
 def _spmv_complex(name, K):
     fn = getattr(_lib, name)
 
@@ -277,6 +295,11 @@ mpspmv_csr_qd = _spmv_real("mpspmv_csr_qd", 4)
 mpspmv_csr_dd_complex = _spmv_complex("mpspmv_csr_dd_complex", 2)
 mpspmv_csr_td_complex = _spmv_complex("mpspmv_csr_td_complex", 3)
 mpspmv_csr_qd_complex = _spmv_complex("mpspmv_csr_qd_complex", 4)
+
+mpspmv_csr_dd_d = _spmv_dmat("mpspmv_csr_dd_d", 2)
+mpspmv_csr_td_d = _spmv_dmat("mpspmv_csr_td_d", 3)
+mpspmv_csr_qd_d = _spmv_dmat("mpspmv_csr_qd_d", 4)
+SPMV_D = {2: mpspmv_csr_dd_d, 3: mpspmv_csr_td_d, 4: mpspmv_csr_qd_d}
 
 SPMV = {(2, False): mpspmv_csr_dd, (3, False): mpspmv_csr_td, (4, False): mpspmv_csr_qd,
         (2, True): mpspmv_csr_dd_complex, (3, True): mpspmv_csr_td_complex, (4, True): mpspmv_csr_qd_complex}

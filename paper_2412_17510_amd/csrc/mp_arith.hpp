@@ -254,6 +254,27 @@ __device__ __forceinline__ qd_t qd_mul(const qd_t &x, const qd_t &y)
     return renorm5(p0, h1, s0, s1, s2);
 }
 
+// QD times binary64 (Alg. 4; its garbled steps read after Hida, Li and Bailey's
+// product of a quad-double by a double): the three leading partial products exact,
+// the fourth plain; the order-eps pair merged by TwoSum, the order-eps^2 terms by
+// ThreeSum, the first order-eps^2 error with the second product error and the
+// fourth product by ThreeSum2, the last two errors by one add; renormalised.
+__device__ __forceinline__ qd_t qd_mul_d(const qd_t &x, double y)
+{
+    double p0, q0, p1, q1, p2, q2;
+    two_prod(x.c[0], y, p0, q0);
+    two_prod(x.c[1], y, p1, q1);
+    two_prod(x.c[2], y, p2, q2);
+    const double p3 = x.c[3] * y;
+    double s1, s2;
+    two_sum(q0, p1, s1, s2);
+    double t0, t1, t2;
+    three_sum(s2, q1, p2, t0, t1, t2);
+    double u0, u1;
+    three_sum2(t1, q2, p3, u0, u1);
+    return renorm5(p0, s1, t0, u0, u1 + t2);
+}
+
 // ---------------------------------------------------------------------------
 // triple-double: QD with zero fourth components, three components kept
 // ---------------------------------------------------------------------------
@@ -274,9 +295,22 @@ __device__ __forceinline__ td_t td_mul(const td_t &x, const td_t &y)
     return td_t{{r.c[0], r.c[1], r.c[2]}};
 }
 
+// TD times binary64 (Alg. 5): the QD product of the zero-padded value, three
+// components kept
+__device__ __forceinline__ td_t td_mul_d(const td_t &x, double y)
+{
+    const qd_t a = {{x.c[0], x.c[1], x.c[2], 0.0}};
+    const qd_t r = qd_mul_d(a, y);
+    return td_t{{r.c[0], r.c[1], r.c[2]}};
+}
+
 // ---------------------------------------------------------------------------
 // K-generic dispatch
 // ---------------------------------------------------------------------------
+
+__device__ __forceinline__ dd_t mp_mul_d(const dd_t &x, double y) { return dd_mul_d(x, y); }
+__device__ __forceinline__ td_t mp_mul_d(const td_t &x, double y) { return td_mul_d(x, y); }
+__device__ __forceinline__ qd_t mp_mul_d(const qd_t &x, double y) { return qd_mul_d(x, y); }
 
 __device__ __forceinline__ dd_t mp_add(const dd_t &x, const dd_t &y) { return dd_add(x, y); }
 __device__ __forceinline__ td_t mp_add(const td_t &x, const td_t &y) { return td_add(x, y); }

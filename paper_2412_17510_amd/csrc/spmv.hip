@@ -98,21 +98,31 @@ __device__ __forceinline__ mpn<K> shfl_xor_mp(const mpn<K> &v, int mask)
 }
 
 // products of element k (matrix operand first)
-template <int K>
+// DM: the matrix holds one binary64 value per element and the product is the
+// K-component x times that value (Algs 3-5)
+template <int K, bool DM>
+__device__ __forceinline__ mpn<K> elem_product(const SpmvArgs &A, int64_t k)
+{
+    const int32_t j = A.col[k];
+    if constexpr (DM)
+        return mp_mul_d(load_mp<K>(A.x_re, A.n_cols, j), A.a_re[k]);
+    else
+        return mp_mul(load_mp<K>(A.a_re, A.nnz, k), load_mp<K>(A.x_re, A.n_cols, j));
+}
+
+template <int K, bool DM>
 __device__ __forceinline__ void first_product(const SpmvArgs &A, int64_t k, Acc<K, false> &acc)
 {
-    const int32_t j = A.col[k];
-    acc.v = mp_mul(load_mp<K>(A.a_re, A.nnz, k), load_mp<K>(A.x_re, A.n_cols, j));
+    acc.v = elem_product<K, DM>(A, k);
 }
 
-template <int K>
+template <int K, bool DM>
 __device__ __forceinline__ void add_product(const SpmvArgs &A, int64_t k, Acc<K, false> &acc)
 {
-    const int32_t j = A.col[k];
-    acc.v = mp_add(acc.v, mp_mul(load_mp<K>(A.a_re, A.nnz, k), load_mp<K>(A.x_re, A.n_cols, j)));
+    acc.v = mp_add(acc.v, elem_product<K, DM>(A, k));
 }
 
-template <int K>
+template <int K, bool DM>
 __device__ __forceinline__ void first_product(const SpmvArgs &A, int64_t k, Acc<K, true> &acc)
 {
     const int32_t j = A.col[k];
@@ -124,7 +134,7 @@ __device__ __forceinline__ void first_product(const SpmvArgs &A, int64_t k, Acc<
     acc.ir = mp_mul(ai, xr);
 }
 
-template <int K>
+template <int K, bool DM>
 __device__ __forceinline__ void add_product(const SpmvArgs &A, int64_t k, Acc<K, true> &acc)
 {
     const int32_t j = A.col[k];
@@ -255,10 +265,14 @@ struct AElem {
     mpn<K> im;
 };
 
-template <int K, bool CPLX>
+template <int K, bool CPLX, bool DM>
 __device__ __forceinline__ void load_aelem(const SpmvArgs &A, int64_t k, AElem<K, CPLX> &e)
 {
     e.col = __builtin_nontemporal_load(A.col + k);
+    if constexpr (DM) {
+        e.re.c[0] = __builtin_nontemporal_load(A.a_re + k);
+        return;
+    }
 #pragma unroll
     for (int c = 0; c < K; ++c) {
         e.re.c[c] = __builtin_nontemporal_load(A.a_re + c * A.nnz + k);
@@ -267,7 +281,7 @@ __device__ __forceinline__ void load_aelem(const SpmvArgs &A, int64_t k, AElem<K
 }
 
 // product(s) of one element with the staged x (matrix operand first)
-template <int K, bool CPLX>
+template <int K, bool CPLX, bool DM>
 __device__ __forceinline__ Acc<K, CPLX> staged_product(const SpmvArgs &A, const AElem<K, CPLX> &e)
 {
     constexpr int D = K * (CPLX ? 2 : 1);
@@ -284,6 +298,8 @@ __device__ __forceinline__ Acc<K, CPLX> staged_product(const SpmvArgs &A, const 
         p.ii = mp_mul(e.im, xi);
         p.ri = mp_mul(e.re, xi);
         p.ir = mp_mul(e.im, xr);
+    } else if constexpr (DM) {
+        p.v = mp_mul_d(xr, e.re.c[0]);
     } else {
         p.v = mp_mul(e.re, xr);
     }
@@ -303,7 +319,7 @@ struct StreamLds {
 // SHORT tile: rows [r0, r0+nr), ne <= C elements starting at e0, at most C rows.
 // The element loads are issued first (their addresses need only the descriptor), the
 // row bookkeeping overlaps them, and the products go to LDS once x has arrived.
-template <int K, bool CPLX, int J>
+template <int K, bool CPLX, int J, bool DM>
 __device__ __forceinline__ void short_tile(const SpmvArgs &A, const uint8_t *__restrict__ log2w,
                                            const mp_stream_tile &T, StreamLds<K, CPLX, 256 * J> &L)
 {
@@ -317,7 +333,7 @@ __device__ __forceinline__ void short_tile(const SpmvArgs &A, const uint8_t *__r
 #pragma unroll
     for (int j = 0; j < J; ++j) {
         const int p = t + 256 * j;
-        if (p < ne) load_aelem<K, CPLX>(A, (int64_t)e0 + p, el[j]);
+        if (p < ne) load_aelem<K, CPLX, DM>(A, (int64_t)e0 + p, el[j]);
     }
     // rows t*J .. t*J+J-1: starts, lane counts (W, or 0 for an empty row)
     int wl[J];
@@ -338,7 +354,7 @@ __device__ __forceinline__ void short_tile(const SpmvArgs &A, const uint8_t *__r
 #pragma unroll
     for (int j = 0; j < J; ++j) {
         const int p = t + 256 * j;
-        if (p < ne) L.prod[p] = staged_product<K, CPLX>(A, el[j]);
+        if (p < ne) L.prod[p] = staged_product<K, CPLX, DM>(A, el[j]);
     }
     int run = block_exclusive_scan(sum, L.wave_tmp);
 #pragma unroll
@@ -404,7 +420,7 @@ __device__ __forceinline__ void short_tile(const SpmvArgs &A, const uint8_t *__r
 }
 
 // LONG tile: one row of len > C with W <= 256 lanes (lane l on thread l).
-template <int K, bool CPLX, int J>
+template <int K, bool CPLX, int J, bool DM>
 __device__ __forceinline__ void long_tile(const SpmvArgs &A, const uint8_t *__restrict__ log2w,
                                           const mp_stream_tile &T, StreamLds<K, CPLX, 256 * J> &L)
 {
@@ -421,12 +437,12 @@ __device__ __forceinline__ void long_tile(const SpmvArgs &A, const uint8_t *__re
 #pragma unroll
         for (int j = 0; j < J; ++j) {
             const int p = t + 256 * j;
-            if (p < cl) load_aelem<K, CPLX>(A, (int64_t)c0 + p, el[j]);
+            if (p < cl) load_aelem<K, CPLX, DM>(A, (int64_t)c0 + p, el[j]);
         }
 #pragma unroll
         for (int j = 0; j < J; ++j) {
             const int p = t + 256 * j;
-            if (p < cl) L.prod[p] = staged_product<K, CPLX>(A, el[j]);
+            if (p < cl) L.prod[p] = staged_product<K, CPLX, DM>(A, el[j]);
         }
         __syncthreads();
         if (t < W) {
@@ -454,7 +470,7 @@ __device__ __forceinline__ void long_tile(const SpmvArgs &A, const uint8_t *__re
     if (t == 0) acc_store(A, row, L.prod[0], true);
 }
 
-template <int K, bool CPLX, int J>
+template <int K, bool CPLX, int J, bool DM>
 __global__ __launch_bounds__(256) void spmv_stream_kernel(SpmvArgs A, const mp_stream_tile *__restrict__ tiles,
                                                           const uint8_t *__restrict__ log2w)
 {
@@ -462,16 +478,16 @@ __global__ __launch_bounds__(256) void spmv_stream_kernel(SpmvArgs A, const mp_s
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const mp_stream_tile T = tiles[tile];
     if (((T.info >> 4) & 15) == 0)
-        short_tile<K, CPLX, J>(A, log2w, T, L);
+        short_tile<K, CPLX, J, DM>(A, log2w, T, L);
     else
-        long_tile<K, CPLX, J>(A, log2w, T, L);
+        long_tile<K, CPLX, J, DM>(A, log2w, T, L);
 }
 
 // ---------------------------------------------------------------------------
 // wide rows: W = 512 or 1024 (one row per workgroup, lanes in registers)
 // ---------------------------------------------------------------------------
 
-template <int K, bool CPLX, int LW>
+template <int K, bool CPLX, int LW, bool DM>
 __device__ __forceinline__ void wide_row(const SpmvArgs &A, int first, Acc<K, CPLX> *lds)
 {
     constexpr int W = 1 << LW;
@@ -485,8 +501,8 @@ __device__ __forceinline__ void wide_row(const SpmvArgs &A, int first, Acc<K, CP
         acc_zero(acc[j]);
         const int l = t + 256 * j;
         if (beg + l < end) {
-            first_product(A, beg + l, acc[j]);
-            for (int64_t k = (int64_t)beg + l + W; k < end; k += W) add_product(A, k, acc[j]);
+            first_product<K, DM>(A, beg + l, acc[j]);
+            for (int64_t k = (int64_t)beg + l + W; k < end; k += W) add_product<K, DM>(A, k, acc[j]);
         }
     }
     // fold steps whose partner lane lives in the same thread (off >= 256)
@@ -508,23 +524,23 @@ __device__ __forceinline__ void wide_row(const SpmvArgs &A, int first, Acc<K, CP
     if (t == 0) acc_store(A, row, acc[0], end > beg);
 }
 
-template <int K, bool CPLX>
+template <int K, bool CPLX, bool DM>
 __global__ __launch_bounds__(256) void spmv_wide_kernel(SpmvArgs A)
 {
     __shared__ Acc<K, CPLX> lds[256];
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const mp_tile d = A.tiles[tile];
     if ((d.lw_count >> 16) == 9)
-        wide_row<K, CPLX, 9>(A, d.first, lds);
+        wide_row<K, CPLX, 9, DM>(A, d.first, lds);
     else
-        wide_row<K, CPLX, 10>(A, d.first, lds);
+        wide_row<K, CPLX, 10, DM>(A, d.first, lds);
 }
 
 // ---------------------------------------------------------------------------
 // no plan: one row per wavefront, canonical W = largest power of two <= min(len, 64)
 // ---------------------------------------------------------------------------
 
-template <int K, bool CPLX>
+template <int K, bool CPLX, bool DM>
 __global__ __launch_bounds__(256) void spmv_rowwave_kernel(SpmvArgs A)
 {
     const int64_t wave = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
@@ -538,8 +554,8 @@ __global__ __launch_bounds__(256) void spmv_rowwave_kernel(SpmvArgs A)
     Acc<K, CPLX> acc;
     acc_zero(acc);
     if (lane < W && lane < len) {
-        first_product(A, beg + lane, acc);
-        for (int64_t k = (int64_t)beg + lane + W; k < end; k += W) add_product(A, k, acc);
+        first_product<K, DM>(A, beg + lane, acc);
+        for (int64_t k = (int64_t)beg + lane + W; k < end; k += W) add_product<K, DM>(A, k, acc);
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1)
@@ -551,13 +567,13 @@ __global__ __launch_bounds__(256) void spmv_rowwave_kernel(SpmvArgs A)
 // launch
 // ---------------------------------------------------------------------------
 
-template <int K, bool CPLX, int J>
+template <int K, bool CPLX, int J, bool DM>
 mp_status launch_stream(const SpmvArgs &A, const mp_plan *plan, hipStream_t s)
 {
     if constexpr (sizeof(StreamLds<K, CPLX, 256 * J>) > 65536) {
         return fail(MP_ERR_UNSUPPORTED, "tile size %d exceeds the LDS budget of this variant", 256 * J);
     } else {
-        hipLaunchKernelGGL((spmv_stream_kernel<K, CPLX, J>), dim3(plan->n_stream), dim3(256), 0, s, A,
+        hipLaunchKernelGGL((spmv_stream_kernel<K, CPLX, J, DM>), dim3(plan->n_stream), dim3(256), 0, s, A,
                            plan->d_stream, plan->d_log2w);
         MP_HIP_TRY(hipGetLastError());
         return MP_OK;
@@ -565,7 +581,7 @@ mp_status launch_stream(const SpmvArgs &A, const mp_plan *plan, hipStream_t s)
 }
 
 // stage = false: the caller has already written x into the plan's staged copy
-template <int K, bool CPLX>
+template <int K, bool CPLX, bool DM = false>
 mp_status launch_spmv(const mp_csr *Acsr, const double *a_re, const double *a_im, const double *x_re,
                       const double *x_im, double *y_re, double *y_im, const mp_plan *plan, hipStream_t s,
                       bool stage = true)
@@ -590,7 +606,7 @@ mp_status launch_spmv(const mp_csr *Acsr, const double *a_re, const double *a_im
     if (!plan) {
         const int64_t blocks = ((int64_t)Acsr->n_rows + 3) / 4;
         if (blocks > INT32_MAX) return fail(MP_ERR_INVALID_ARG, "too many rows for the plan-free kernel");
-        hipLaunchKernelGGL((spmv_rowwave_kernel<K, CPLX>), dim3((unsigned)blocks), dim3(256), 0, s, A);
+        hipLaunchKernelGGL((spmv_rowwave_kernel<K, CPLX, DM>), dim3((unsigned)blocks), dim3(256), 0, s, A);
         MP_HIP_TRY(hipGetLastError());
         return MP_OK;
     }
@@ -606,10 +622,10 @@ mp_status launch_spmv(const mp_csr *Acsr, const double *a_re, const double *a_im
         }
         mp_status st;
         switch (plan->tile_nnz) {
-            case 256: st = launch_stream<K, CPLX, 1>(A, plan, s); break;
-            case 512: st = launch_stream<K, CPLX, 2>(A, plan, s); break;
-            case 1024: st = launch_stream<K, CPLX, 4>(A, plan, s); break;
-            case 2048: st = launch_stream<K, CPLX, 8>(A, plan, s); break;
+            case 256: st = launch_stream<K, CPLX, 1, DM>(A, plan, s); break;
+            case 512: st = launch_stream<K, CPLX, 2, DM>(A, plan, s); break;
+            case 1024: st = launch_stream<K, CPLX, 4, DM>(A, plan, s); break;
+            case 2048: st = launch_stream<K, CPLX, 8, DM>(A, plan, s); break;
             default: st = fail(MP_ERR_INVALID_ARG, "plan has an invalid tile size %d", plan->tile_nnz);
         }
         if (st != MP_OK) return st;
@@ -618,13 +634,13 @@ mp_status launch_spmv(const mp_csr *Acsr, const double *a_re, const double *a_im
         A.perm = plan->d_wide_rows;
         A.tiles = plan->d_wide;
         A.n_tiles = plan->n_wide;
-        hipLaunchKernelGGL((spmv_wide_kernel<K, CPLX>), dim3(plan->n_wide), dim3(256), 0, s, A);
+        hipLaunchKernelGGL((spmv_wide_kernel<K, CPLX, DM>), dim3(plan->n_wide), dim3(256), 0, s, A);
         MP_HIP_TRY(hipGetLastError());
     }
     return MP_OK;
 }
 
-template <int K, bool CPLX>
+template <int K, bool CPLX, bool DM = false>
 mp_status spmv_entry(const char *name, const mp_csr *A, const double *a_re, const double *a_im, const double *x_re,
                      const double *x_im, double *y_re, double *y_im, const mp_plan *plan, void *stream)
 {
@@ -641,7 +657,7 @@ mp_status spmv_entry(const char *name, const mp_csr *A, const double *a_re, cons
         return fail(MP_ERR_INVALID_ARG, "%s: plan was built for ncomp=%d is_complex=%d", name, plan->ncomp,
                     plan->cplx);
     const size_t yb = sizeof(double) * K * (size_t)A->n_rows;
-    const size_t ab = sizeof(double) * K * (size_t)A->nnz;
+    const size_t ab = sizeof(double) * (DM ? 1 : K) * (size_t)A->nnz;
     const size_t xb = sizeof(double) * K * (size_t)A->n_cols;
     const double *ins[4] = {a_re, a_im, x_re, x_im};
     const size_t insz[4] = {ab, CPLX ? ab : 0, xb, CPLX ? xb : 0};
@@ -652,7 +668,7 @@ mp_status spmv_entry(const char *name, const mp_csr *A, const double *a_re, cons
                 return fail(MP_ERR_ALIAS, "%s: an output overlaps an input", name);
     }
     if (CPLX && overlaps(y_re, yb, y_im, yb)) return fail(MP_ERR_ALIAS, "%s: y_re overlaps y_im", name);
-    return launch_spmv<K, CPLX>(A, a_re, a_im, x_re, x_im, y_re, y_im, plan, static_cast<hipStream_t>(stream));
+    return launch_spmv<K, CPLX, DM>(A, a_re, a_im, x_re, x_im, y_re, y_im, plan, static_cast<hipStream_t>(stream));
 }
 
 double *plan_staged_x(const mp_plan *plan)
@@ -731,6 +747,24 @@ mp_status mpspmv_csr_qd_complex(const mp_csr *A, const double *a_re, const doubl
                                 const double *x_im, double *y_re, double *y_im, const mp_plan *plan, void *stream)
 {
     return mpk::spmv_entry<4, true>("mpspmv_csr_qd_complex", A, a_re, a_im, x_re, x_im, y_re, y_im, plan, stream);
+}
+
+mp_status mpspmv_csr_dd_d(const mp_csr *A, const double *a, const double *x, double *y, const mp_plan *plan,
+                          void *stream)
+{
+    return mpk::spmv_entry<2, false, true>("mpspmv_csr_dd_d", A, a, nullptr, x, nullptr, y, nullptr, plan, stream);
+}
+
+mp_status mpspmv_csr_td_d(const mp_csr *A, const double *a, const double *x, double *y, const mp_plan *plan,
+                          void *stream)
+{
+    return mpk::spmv_entry<3, false, true>("mpspmv_csr_td_d", A, a, nullptr, x, nullptr, y, nullptr, plan, stream);
+}
+
+mp_status mpspmv_csr_qd_d(const mp_csr *A, const double *a, const double *x, double *y, const mp_plan *plan,
+                          void *stream)
+{
+    return mpk::spmv_entry<4, false, true>("mpspmv_csr_qd_d", A, a, nullptr, x, nullptr, y, nullptr, plan, stream);
 }
 
 }  // extern "C"

@@ -1,0 +1,115 @@
+"""GPU parity of the binary64-matrix SpMV (C ABI mpspmv_csr_{dd,td,qd}_d) with the
+oracle: bitwise equality of every component under the plan's exported order, on
+ragged random matrices spanning several tiles and every lane width 1..1024 (plan-free
+kernel, canonical plans of every tile size, width policies, explicit orders), the
+paper's 5x5 example, and sampled rows of the full n = 1e6 power-law workload; for DD
+the result equals the DD SpMV of the zero-tail matrix on the GPU too; argument
+checks."""
+import numpy as np
+import pytest
+
+from oracle import ref
+from tests.helpers import assert_same_values, dev, host
+from workloads import (random_csr, random_mp, sqrt2_vector, csr_from_dense, paper_example_5x5, powerlaw_pattern)
+
+pytestmark = pytest.mark.gpu
+
+TILES = {2: (256, 512, 1024, 2048), 3: (256, 512, 1024), 4: (256, 512, 1024)}
+
+
+@pytest.fixture(scope="module")
+def mp():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2412_17510_amd import mp as binding
+    return binding
+
+
+def run(mp, K, A, a, x, plan=None):
+    import torch
+    y = torch.full((K, A.n_rows), float("nan"), dtype=torch.float64, device="cuda")
+    mp.SPMV_D[K](A, dev(a), dev(x), y, plan=plan)
+    torch.cuda.synchronize()
+    return host(y)
+
+
+def check(mp, K, row_ptr, col_idx, a, x, A, plan=None, what=""):
+    got = run(mp, K, A, a, x, plan)
+    lw = None if plan is None else plan.row_log2w()
+    assert_same_values(got, ref.spmv_dmat(K, row_ptr, col_idx, a, x, log2w=lw), what)
+    return got
+
+
+@pytest.mark.parametrize("K", [2, 3, 4])
+def test_ragged_random_every_width(mp, K):
+    rng = np.random.default_rng(2000 + K)
+    lengths = np.concatenate([[0, 1, 2, 3, 5, 63, 64, 65, 127, 128, 255, 256, 511, 512, 1023, 1024, 2049, 0],
+                              rng.integers(0, 40, 700), rng.integers(40, 300, 60)])
+    n_cols = 3000
+    row_ptr, col_idx, _, _ = random_csr(lengths.size, n_cols, lengths, K, rng)
+    a = rng.uniform(-1, 1, col_idx.size) * 2.0 ** rng.integers(-20, 20, col_idx.size)
+    x = random_mp(n_cols, K, rng)
+    A = mp.Csr.from_numpy(row_ptr, col_idx, n_cols=n_cols)
+    check(mp, K, row_ptr, col_idx, a, x, A, what="plan-free")
+    for tile in TILES[K]:
+        check(mp, K, row_ptr, col_idx, a, x, A, plan=mp.mp_plan_create(A, K, False, tile_nnz=tile),
+              what="canonical tile %d" % tile)
+    for sh, mx in ((2, 4), (0, 8), (2, 8)):
+        check(mp, K, row_ptr, col_idx, a, x, A, plan=mp.mp_plan_create(A, K, False, sh, mx), what="policy")
+    fl = np.array([0 if L == 0 else int(np.floor(np.log2(L))) for L in lengths])
+    lw = np.array([rng.integers(0, min(10, f) + 1) for f in fl], dtype=np.uint8)
+    lw[lengths >= 1024] = 10
+    lw[(lengths >= 512) & (lengths < 1024)] = 9
+    for tile in TILES[K]:
+        check(mp, K, row_ptr, col_idx, a, x, A, plan=mp.mp_plan_create_explicit(A, K, False, lw, tile),
+              what="explicit wide tile %d" % tile)
+    if K == 2:
+        # equal to the DD SpMV of the same matrix with zero trailing components
+        import torch
+        padded = np.zeros((2, a.size))
+        padded[0] = a
+        plan = mp.mp_plan_create(A, 2, False, 2, 8)
+        yd = torch.empty((2, A.n_rows), dtype=torch.float64, device="cuda")
+        mp.mpspmv_csr_dd(A, dev(padded), dev(x), yd, plan=plan)
+        assert_same_values(run(mp, 2, A, a, x, plan), host(yd), "dmat vs zero-tail DD")
+
+
+@pytest.mark.parametrize("K", [2, 3, 4])
+def test_paper_5x5(mp, K):
+    row_ptr, col_idx, vals = csr_from_dense(paper_example_5x5())
+    A = mp.Csr.from_numpy(row_ptr, col_idx)
+    v = sqrt2_vector(5, K)
+    check(mp, K, row_ptr, col_idx, vals, v, A, what="5x5 plan-free")
+    check(mp, K, row_ptr, col_idx, vals, v, A, plan=mp.mp_plan_create(A, K), what="5x5 canonical")
+
+
+@pytest.mark.parametrize("K", [2, 4])
+def test_powerlaw_full_size_sampled(mp, K):
+    import torch
+    row_ptr, col_idx = powerlaw_pattern(n=1_000_000, seed=1)
+    n = row_ptr.size - 1
+    rng = np.random.default_rng([7, K])
+    a = rng.uniform(-1, 1, col_idx.size)
+    x = random_mp(n, K, rng)
+    A = mp.Csr.from_numpy(row_ptr, col_idx)
+    y = torch.empty((K, n), dtype=torch.float64, device="cuda")
+    plan = mp.mp_plan_create(A, K, False, 2, 8, 512)
+    mp.SPMV_D[K](A, dev(a), dev(x), y, plan=plan)
+    torch.cuda.synchronize()
+    lengths = np.diff(row_ptr)
+    rows = np.unique(np.concatenate([rng.choice(n, 3000, replace=False), np.nonzero(lengths >= 2048)[0], [0, n - 1]]))
+    want = ref.spmv_dmat(K, row_ptr, col_idx, a, x, log2w=plan.row_log2w(), rows=rows)
+    assert_same_values(host(y)[:, rows], want[:, rows], "powerlaw dmat K=%d" % K)
+
+
+def test_argument_checks(mp):
+    import torch
+    row_ptr, col_idx, vals = csr_from_dense(paper_example_5x5())
+    A = mp.Csr.from_numpy(row_ptr, col_idx)
+    x = dev(sqrt2_vector(5, 2))
+    y = torch.empty((2, 5), dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        mp.mpspmv_csr_dd_d(A, dev(np.zeros((2, vals.size))), x, y)
+    buf = torch.zeros(16, dtype=torch.float64, device="cuda")
+    with pytest.raises(mp.MpError):   # y overlapping a
+        mp.mpspmv_csr_dd_d(A, buf[:8], x, buf[6:16].view(2, 5))
