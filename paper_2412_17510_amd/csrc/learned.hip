@@ -194,6 +194,137 @@ __global__ __launch_bounds__(256) void k_dense(int32_t n, const float *__restric
     H[node * kH + o] = acc > 0.f ? acc : 0.f;
 }
 
+// ---------------------------------------------------------------------------
+// hidden dense layers on the matrix cores (bf16 operands, fp32 accumulation)
+// ---------------------------------------------------------------------------
+
+typedef short v4bf __attribute__((ext_vector_type(4)));   // four bfloat16 bit patterns
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short bf16_bits(float x) { return (short)(__float_as_uint(bfr(x)) >> 16); }
+
+// One wavefront computes a 16-node x 64-output block as 4 column blocks of the
+// 16x16x16 bf16 MFMA.  Operand layout of that instruction (lane l, element v):
+// A[i][k] with i = l % 16, k = 4 (l / 16) + v; B[k][j] with k = 4 (l / 16) + v,
+// j = l % 16; D[i][j] with i = 4 (l / 16) + v, j = l % 16.
+//   out = X1 W1 + X2 W2 (64 inputs each), W given in LDS as bf16 [k][o] (or, with
+//   TRANS, as [o][k] so that the product is X W^T)
+// SPLIT: X is not a bfloat16 quantity (a gradient); it is split exactly enough as
+// hi + lo with hi = bf(X), lo = bf(X - hi) and both parts are multiplied (about 16
+// significant bits, far below the float32 accumulation's own error budget here).
+template <bool TRANS, bool SPLIT>
+__device__ __forceinline__ void mfma_rows16(const float *__restrict__ X, int64_t node0, int32_t n,
+                                            const short *__restrict__ sW, v4f (&acc)[4], bool relu_mask,
+                                            const float *__restrict__ Hmask)
+{
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15, g = lane >> 4;
+    const int64_t node = node0 + r;
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+        v4bf a, alo;
+        const int k0 = 16 * kb + 4 * g;
+        if (node < n) {
+            const float4 xv = *reinterpret_cast<const float4 *>(X + node * kH + k0);
+            float x4[4] = {xv.x, xv.y, xv.z, xv.w};
+            if (relu_mask) {
+                const float4 hv = *reinterpret_cast<const float4 *>(Hmask + node * kH + k0);
+                x4[0] = hv.x > 0.f ? x4[0] : 0.f;
+                x4[1] = hv.y > 0.f ? x4[1] : 0.f;
+                x4[2] = hv.z > 0.f ? x4[2] : 0.f;
+                x4[3] = hv.w > 0.f ? x4[3] : 0.f;
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                a[v] = bf16_bits(x4[v]);
+                if constexpr (SPLIT) alo[v] = bf16_bits(x4[v] - bfr(x4[v]));
+            }
+        } else {
+            a = v4bf{0, 0, 0, 0};
+            alo = a;
+        }
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            v4bf bm;
+            const int o = 16 * cb + r;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) bm[v] = TRANS ? sW[o * kH + k0 + v] : sW[(k0 + v) * kH + o];
+            acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bm, acc[cb], 0, 0, 0);
+            if constexpr (SPLIT) acc[cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, bm, acc[cb], 0, 0, 0);
+        }
+    }
+}
+
+// H = relu(bf(X1) bf(W1) + bf(X2) bf(W2) + b) for the hidden layers; 64 nodes per block
+__global__ __launch_bounds__(256) void k_dense_mfma(int32_t n, const float *__restrict__ X1,
+                                                    const float *__restrict__ W1, const float *__restrict__ X2,
+                                                    const float *__restrict__ W2, const float *__restrict__ b,
+                                                    float *__restrict__ H)
+{
+    __shared__ short sW[2][kH * kH];
+    const int t = threadIdx.x;
+    for (int i = t; i < kH * kH; i += 256) {
+        sW[0][i] = bf16_bits(W1[i]);
+        sW[1][i] = bf16_bits(W2[i]);
+    }
+    __syncthreads();
+    const int64_t node0 = (int64_t)blockIdx.x * 64 + (t >> 6) * 16;
+    v4f acc[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) acc[cb] = v4f{0.f, 0.f, 0.f, 0.f};
+    mfma_rows16<false, false>(X1, node0, n, sW[0], acc, false, nullptr);
+    mfma_rows16<false, false>(X2, node0, n, sW[1], acc, false, nullptr);
+    const int lane = t & 63;
+    const int r = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+        const int o = 16 * cb + r;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t node = node0 + 4 * g + v;
+            if (node < n) {
+                const float z = acc[cb][v] + b[o];
+                H[node * kH + o] = z > 0.f ? z : 0.f;
+            }
+        }
+    }
+}
+
+// dX1 = dZ bf(W1)^T, dX2 = dZ bf(W2)^T with dZ = dH o [Hout > 0] (split in two bf16
+// parts); 64 nodes per block
+__global__ __launch_bounds__(256) void k_dense_bwd_x_mfma(int32_t n, const float *__restrict__ dH,
+                                                          const float *__restrict__ Hout,
+                                                          const float *__restrict__ W1, float *__restrict__ dX1,
+                                                          const float *__restrict__ W2, float *__restrict__ dX2)
+{
+    __shared__ short sW[2][kH * kH];
+    const int t = threadIdx.x;
+    for (int i = t; i < kH * kH; i += 256) {
+        sW[0][i] = bf16_bits(W1[i]);
+        sW[1][i] = bf16_bits(W2[i]);
+    }
+    __syncthreads();
+    const int64_t node0 = (int64_t)blockIdx.x * 64 + (t >> 6) * 16;
+    const int lane = t & 63;
+    const int r = lane & 15, g = lane >> 4;
+    for (int w = 0; w < 2; ++w) {
+        v4f acc[4];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) acc[cb] = v4f{0.f, 0.f, 0.f, 0.f};
+        mfma_rows16<true, true>(dH, node0, n, sW[w], acc, true, Hout);
+        float *out = w ? dX2 : dX1;
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            const int k = 16 * cb + r;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t node = node0 + 4 * g + v;
+                if (node < n) out[node * kH + k] = acc[cb][v];
+            }
+        }
+    }
+}
+
 // Out_i = base_i + sum_j w_ij X_j (row order); thread per (node, feature)
 __global__ __launch_bounds__(256) void k_aggregate(int32_t n, const int32_t *__restrict__ rp,
                                                    const int32_t *__restrict__ ci, const float *__restrict__ w,
@@ -361,55 +492,37 @@ __global__ __launch_bounds__(256) void k_readout_bwd(int32_t n, const int32_t *_
     dH[node * kH + f] = acc;
 }
 
-// dX = (dH o [Hout > 0]) W^T for a K x 64 weight (thread per (node, k)); optional second
-// weight gives dX2
-__global__ __launch_bounds__(256) void k_dense_bwd_x(int32_t n, const float *__restrict__ dH,
-                                                     const float *__restrict__ Hout, const float *__restrict__ W1,
-                                                     float *__restrict__ dX1, const float *__restrict__ W2,
-                                                     float *__restrict__ dX2)
-{
-    __shared__ float sW1[kH * kH];
-    __shared__ float sW2[kH * kH];
-    __shared__ float sdz[4][kH];
-    const int t = threadIdx.x;
-    for (int i = t; i < kH * kH; i += 256) {
-        sW1[i] = bfr(W1[i]);
-        sW2[i] = bfr(W2[i]);
-    }
-    const int local = t >> 6, k = t & 63;
-    const int64_t node = (int64_t)blockIdx.x * 4 + local;
-    if (node < n) sdz[local][k] = Hout[node * kH + k] > 0.f ? dH[node * kH + k] : 0.f;
-    __syncthreads();
-    if (node >= n) return;
-    float a1 = 0.f, a2 = 0.f;
-    for (int o = 0; o < kH; ++o) {
-        a1 = fmaf(sdz[local][o], sW1[k * kH + o], a1);
-        a2 = fmaf(sdz[local][o], sW2[k * kH + o], a2);
-    }
-    dX1[node * kH + k] = a1;
-    dX2[node * kH + k] = a2;
-}
-
 // per block of 256 nodes: partial dW[k][o] = sum_i bf(X_ik) dZ_io (dZ = dH o [Hout > 0]),
-// and (row K of the partial) db[o] = sum_i dZ_io; thread per o, loop over k
+// and (row K of the partial) db[o] = sum_i dZ_io.  Thread (q, o) = (tid / 64, tid % 64)
+// holds the sums of k = q, q + 4, ...; every sum runs over the block's nodes in order.
 template <int K>
-__global__ __launch_bounds__(64) void k_wgrad_part(int32_t n, const float *__restrict__ X, const float *__restrict__ dH,
-                                                   const float *__restrict__ Hout, float *__restrict__ part)
+__global__ __launch_bounds__(256) void k_wgrad_part(int32_t n, const float *__restrict__ X, const float *__restrict__ dH,
+                                                    const float *__restrict__ Hout, float *__restrict__ part)
 {
-    const int o = threadIdx.x;
+    constexpr int NK = (K + 3) / 4;
+    const int o = threadIdx.x & 63;
+    const int q = threadIdx.x >> 6;
     const int64_t i0 = (int64_t)blockIdx.x * kNodeBlock;
     const int64_t i1 = (i0 + kNodeBlock) < n ? i0 + kNodeBlock : n;
     float *out = part + (int64_t)blockIdx.x * (K + 1) * kH;
+    float acc[NK];
+#pragma unroll
+    for (int m = 0; m < NK; ++m) acc[m] = 0.f;
     float db = 0.f;
-    for (int64_t i = i0; i < i1; ++i) db += Hout[i * kH + o] > 0.f ? dH[i * kH + o] : 0.f;
-    out[K * kH + o] = db;
-    for (int k = 0; k < K; ++k) {
-        float acc = 0.f;
-        for (int64_t i = i0; i < i1; ++i) {
-            const float dz = Hout[i * kH + o] > 0.f ? dH[i * kH + o] : 0.f;
-            acc = fmaf(bfr(X[i * K + k]), dz, acc);
+    for (int64_t i = i0; i < i1; ++i) {
+        const float dz = Hout[i * kH + o] > 0.f ? dH[i * kH + o] : 0.f;
+        db += dz;
+#pragma unroll
+        for (int m = 0; m < NK; ++m) {
+            const int k = q + 4 * m;
+            if (k < K) acc[m] = fmaf(bfr(X[i * K + k]), dz, acc[m]);
         }
-        out[k * kH + o] = acc;
+    }
+    if (q == 0) out[K * kH + o] = db;
+#pragma unroll
+    for (int m = 0; m < NK; ++m) {
+        const int k = q + 4 * m;
+        if (k < K) out[k * kH + o] = acc[m];
     }
 }
 
@@ -532,7 +645,7 @@ mp_status mpnn_forward(const mp_mpnn *net, mp_graph *g, hipStream_t s)
     for (int l = 1; l <= 3; ++l) {
         hipLaunchKernelGGL(k_aggregate, dim3((unsigned)(((int64_t)n * kH + 255) / 256)), dim3(256), 0, s, n, g->row_ptr,
                            g->col_idx, g->d_w, g->d_H[l - 1], nullptr, g->d_Mg[l]);
-        hipLaunchKernelGGL((k_dense<kH, true>), dim3(nodes4), dim3(256), 0, s, n, g->d_H[l - 1], th + off_ws(l),
+        hipLaunchKernelGGL(k_dense_mfma, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, s, n, g->d_H[l - 1], th + off_ws(l),
                            g->d_Mg[l], th + off_wn(l), th + off_b(l), g->d_H[l]);
     }
     hipLaunchKernelGGL(k_readout, dim3(nb256(g->nnz > n ? g->nnz : n)), dim3(256), 0, s, n, g->nnz, g->d_rows,
@@ -769,20 +882,21 @@ mp_status mp_mpnn_loss_grad(mp_mpnn *net, mp_graph *g, const double *r, const do
     float *dH = g->d_dH, *dH2 = g->d_dH2;
     for (int l = 3; l >= 1; --l) {
         // weight gradients of layer l (Ws with X = H[l-1], Wn with X = Mg[l]); bias with the first
-        hipLaunchKernelGGL((k_wgrad_part<kH>), dim3(g->nblk), dim3(64), 0, s, n, g->d_H[l - 1], dH, g->d_H[l],
+        hipLaunchKernelGGL((k_wgrad_part<kH>), dim3(g->nblk), dim3(256), 0, s, n, g->d_H[l - 1], dH, g->d_H[l],
                            g->d_wpart);
         hipLaunchKernelGGL((k_wgrad_reduce<kH>), dim3((unsigned)(((kH + 1) * kH + 255) / 256)), dim3(256), 0, s,
                            g->nblk, g->d_wpart, grad, off_ws(l), off_b(l));
-        hipLaunchKernelGGL((k_wgrad_part<kH>), dim3(g->nblk), dim3(64), 0, s, n, g->d_Mg[l], dH, g->d_H[l],
+        hipLaunchKernelGGL((k_wgrad_part<kH>), dim3(g->nblk), dim3(256), 0, s, n, g->d_Mg[l], dH, g->d_H[l],
                            g->d_wpart);
         hipLaunchKernelGGL((k_wgrad_reduce<kH>), dim3((unsigned)(((kH + 1) * kH + 255) / 256)), dim3(256), 0, s,
                            g->nblk, g->d_wpart, grad, off_wn(l), -1);
         // input gradients: dH[l-1] = dZ Ws^T + aggregate(dZ Wn^T)
-        hipLaunchKernelGGL(k_dense_bwd_x, dim3(nodes4), dim3(256), 0, s, n, dH, g->d_H[l], th + off_ws(l), dH2,
+        hipLaunchKernelGGL(k_dense_bwd_x_mfma, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, s, n, dH, g->d_H[l],
+                           th + off_ws(l), dH2,
                            th + off_wn(l), g->d_dMg);
         hipLaunchKernelGGL(k_aggregate, dim3(nh), dim3(256), 0, s, n, g->row_ptr, g->col_idx, g->d_w, g->d_dMg, dH2, dH);
     }
-    hipLaunchKernelGGL((k_wgrad_part<kF>), dim3(g->nblk), dim3(64), 0, s, n, g->d_f, dH, g->d_H[0], g->d_wpart);
+    hipLaunchKernelGGL((k_wgrad_part<kF>), dim3(g->nblk), dim3(256), 0, s, n, g->d_f, dH, g->d_H[0], g->d_wpart);
     hipLaunchKernelGGL((k_wgrad_reduce<kF>), dim3((unsigned)(((kF + 1) * kH + 255) / 256)), dim3(256), 0, s, g->nblk,
                        g->d_wpart, grad, OFF_W0, OFF_B0);
     MP_HIP_TRY(hipGetLastError());
