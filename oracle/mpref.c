@@ -1046,3 +1046,28 @@ int oracle_spmv_dmat(int K, int64_t n_rows, int64_t n_cols, int64_t nnz, const i
     }
     return bad ? -1 : 0;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Transpose (for A^T v, Sec. 3): a stable counting sort by column, so row j   */
+/* of A^T holds column j of A in increasing row order.  a: ncomp planar value  */
+/* arrays of nnz (permuted together with the pattern).                         */
+/* ------------------------------------------------------------------------- */
+int oracle_transpose(int64_t n_rows, int64_t n_cols, int64_t nnz, int ncomp, const int32_t *row_ptr,
+                     const int32_t *col_idx, const double *a, int32_t *row_ptr_t, int32_t *col_idx_t, double *a_t)
+{
+    int64_t i, k, j;
+    int c;
+    int64_t *next = (int64_t *)calloc((size_t)n_cols + 1, sizeof(int64_t));
+    if (!next) return -1;
+    for (k = 0; k < nnz; ++k) next[col_idx[k] + 1]++;
+    for (j = 0; j < n_cols; ++j) next[j + 1] += next[j];
+    for (j = 0; j <= n_cols; ++j) row_ptr_t[j] = (int32_t)next[j];
+    for (i = 0; i < n_rows; ++i)
+        for (k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+            int64_t dst = next[col_idx[k]]++;
+            col_idx_t[dst] = (int32_t)i;
+            for (c = 0; c < ncomp; ++c) a_t[(int64_t)c * nnz + dst] = a[(int64_t)c * nnz + k];
+        }
+    free(next);
+    return 0;
+}

@@ -26,9 +26,11 @@ def lib():
         L.oracle_renorm5.argtypes = [i64, P, P]
         L.oracle_spmv.argtypes = [ctypes.c_int, i64, i64, i64, P, P, P, P, P, P, P, P, P, i64, P, ctypes.c_int]
         L.oracle_spmv_dmat.argtypes = [ctypes.c_int, i64, i64, i64, P, P, P, P, P, P, i64, P, ctypes.c_int]
+        L.oracle_transpose.argtypes = [i64, i64, i64, ctypes.c_int, P, P, P, P, P, P]
         L.oracle_canonical_log2w.argtypes = [i64]
         L.oracle_num_threads.argtypes = []
         for name in ("oracle_eft", "oracle_elementwise", "oracle_renorm5", "oracle_spmv", "oracle_spmv_dmat",
+                     "oracle_transpose",
                      "oracle_canonical_log2w", "oracle_num_threads"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -132,6 +134,26 @@ def spmv_dmat(K, row_ptr, col_idx, a, x, log2w=None, n_cols=None, rows=None, nth
     if rc != 0:
         raise ValueError("oracle_spmv_dmat: invalid argument")
     return y
+
+
+def transpose(row_ptr, col_idx, a, n_cols=None):
+    """CSR of A^T (stable: row j of A^T lists column j of A in increasing row order) and
+    the values permuted with it.  a: (ncomp, nnz) or (nnz,).  Returns (row_ptr_t,
+    col_idx_t, a_t) with a_t shaped like a."""
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
+    n = row_ptr.size - 1
+    nnz = col_idx.size
+    if n_cols is None:
+        n_cols = int(col_idx.max()) + 1 if nnz else n
+    a = _f64(a)
+    a2 = a.reshape(-1, nnz)
+    rpt = np.empty(n_cols + 1, dtype=np.int32)
+    cit = np.empty(nnz, dtype=np.int32)
+    at = np.empty_like(a2)
+    assert lib().oracle_transpose(n, n_cols, nnz, a2.shape[0], _p(row_ptr), _p(col_idx), _p(a2), _p(rpt), _p(cit),
+                                  _p(at)) == 0
+    return rpt, cit, at.reshape(a.shape)
 
 
 def num_threads():
