@@ -187,6 +187,22 @@ mp_status mpspmv_csr_td_d(const mp_csr *A, const double *a, const double *x, dou
 mp_status mpspmv_csr_qd_d(const mp_csr *A, const double *a, const double *x, double *y, const mp_plan *plan,
                           void *stream);
 
+/*
+ * A^T in CSR, for A^T v (Sec. 3's SpTMV, which the paper computes by splitting A
+ * across threads and combining the partial results in a critical section, and
+ * suggests transposing first).  Row j of A^T lists column j of A in increasing row
+ * order (a stable sort of the elements by column), the values permuted with the
+ * pattern, so A^T v = an ordinary SpMV of A^T (with a plan of A^T) and is
+ * deterministic.  ncomp: value components per array (1 for a binary64 matrix, 2..4
+ * for DD/TD/QD); a_im/at_im both NULL (real) or both given.  Outputs (device,
+ * caller-owned): row_ptr_t int32[n_cols+1], col_idx_t int32[nnz], at_re (and at_im)
+ * double[ncomp*nnz] planar like a.  Allocates temporary device memory (about 16
+ * bytes per element plus the sort workspace) and synchronises `stream`.  nnz must be
+ * below 2^31.  MP_ERR_ALIAS if an output overlaps an input or another output.
+ */
+mp_status mp_csr_transpose(const mp_csr *A, int32_t ncomp, const double *a_re, const double *a_im,
+                           int32_t *row_ptr_t, int32_t *col_idx_t, double *at_re, double *at_im, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Krylov solvers in double-double (Sec. 4.2: CG for symmetric positive-definite A,
  * BiCGSTAB for non-symmetric A; x0 given, stop on the residual norm).

@@ -85,6 +85,7 @@ for _name in ("mpkrylov_cg", "mpkrylov_bicgstab", "mpkrylov_ir"):
     _SIGS[_name] = ([_CSR, _P, _P, _P, ctypes.POINTER(mp_solve_opts), _P, _P, ctypes.c_size_t,
                      ctypes.POINTER(mp_solve_info), _P], ctypes.c_int)
 
+_SIGS["mp_csr_transpose"] = ([_CSR, _I, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int)
 _SIGS["mpkrylov_ir_learned"] = ([_CSR, _P, _P, _P, _P, ctypes.POINTER(mp_solve_opts), _P, _P, ctypes.c_size_t,
                                  ctypes.POINTER(mp_solve_info), _P], ctypes.c_int)
 _SIGS["mp_mpnn_param_count"] = ([ctypes.POINTER(_I)], ctypes.c_int)
@@ -254,6 +255,25 @@ def _spmv_real(name, K):
     call.__name__ = name
     call.__doc__ = "y = A x in %d-component arithmetic (C ABI %s); tensors of shape (K, len)." % (K, name)
     return call
+
+
+def mp_csr_transpose(A, a_re, a_im=None, stream=None):
+    """A^T (C ABI mp_csr_transpose): returns (Csr of A^T, at_re, at_im or None), values
+    shaped like a_re ((ncomp, nnz), or (nnz,) for a binary64 matrix)."""
+    import torch
+    for t, nm in ((a_re, "a_re"), (a_im, "a_im")):
+        if t is None:
+            continue
+        if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous() or t.numel() % max(A.nnz, 1):
+            raise ValueError("%s must be a contiguous CUDA float64 tensor of ncomp * nnz values" % nm)
+    ncomp = a_re.numel() // A.nnz if A.nnz else (a_re.shape[0] if a_re.dim() == 2 else 1)
+    rpt = torch.empty(A.n_cols + 1, dtype=torch.int32, device="cuda")
+    cit = torch.empty(A.nnz, dtype=torch.int32, device="cuda")
+    at_re = torch.empty_like(a_re)
+    at_im = torch.empty_like(a_im) if a_im is not None else None
+    _check(_lib.mp_csr_transpose(ctypes.byref(A.c), int(ncomp), _ptr(a_re), _ptr(a_im), _ptr(rpt), _ptr(cit),
+                                 _ptr(at_re), _ptr(at_im), _stream_ptr(stream)), "mp_csr_transpose")
+    return Csr(rpt, cit, n_cols=A.n_rows), at_re, at_im
 
 
 def _spmv_dmat(name, K):
