@@ -1071,3 +1071,89 @@ int oracle_transpose(int64_t n_rows, int64_t n_cols, int64_t nnz, int ncomp, con
     free(next);
     return 0;
 }
+
+/*
+ * Preconditioned BiCG in DD (Fletcher's biconjugate gradients, Sec. 4.2's list of
+ * Krylov methods), Jacobi preconditioning (symmetric, so the shadow system uses the
+ * same M).  A^T is given explicitly (row_ptr_t, col_idx_t, a_t: the stable transpose,
+ * log2w_t its lane widths).  r~ = r at the start; per step q = A p, q~ = A^T p~,
+ * sigma = (p~, q), alpha = rho / sigma, x += alpha p, r -= alpha q, r~ -= alpha q~,
+ * z = M r, z~ = M r~, rho' = (r~, z), beta = rho' / rho, p = z + beta p,
+ * p~ = z~ + beta p~.  Stop test, confirmation and restart as oracle_cg (a restart
+ * also resets r~ to the true residual).  Breakdown: sigma = 0 or non-finite, rho' = 0
+ * while not converged, or a non-finite rho' or ||r||^2.
+ */
+int oracle_bicg(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx, const uint8_t *log2w,
+                const double *a, const int32_t *row_ptr_t, const int32_t *col_idx_t, const uint8_t *log2w_t,
+                const double *a_t, const double *b, double *x, const double *minv, double rtol, int32_t max_iter,
+                oracle_solve_info *info, double *hist)
+{
+    dd_mat M = {n, nnz, row_ptr, col_idx, log2w, a};
+    dd_mat Mt = {n, nnz, row_ptr_t, col_idx_t, log2w_t, a_t};
+    size_t vb = sizeof(double) * 2 * (size_t)n;
+    double *r = (double *)malloc(vb), *z = (double *)malloc(vb), *p = (double *)malloc(vb), *q = (double *)malloc(vb);
+    double *rt = (double *)malloc(vb), *zt = (double *)malloc(vb), *pt = (double *)malloc(vb), *qt = (double *)malloc(vb);
+    mpv rho, rr, bb, tol2, sigma, alpha, beta, rho_new;
+    int64_t i;
+    int32_t k = 0;
+    int status = -5;
+    memset(info, 0, sizeof(*info));
+    bb = dd_dot_vec(n, b, b);
+    tol2 = dd_mul_d(bb, rtol * rtol);
+    dd_residual(&M, b, x, q, r);
+    memcpy(rt, r, vb);
+    dd_precond(n, minv, r, z);
+    memcpy(zt, z, vb);
+    memcpy(p, z, vb);
+    memcpy(pt, z, vb);
+    rho = dd_dot_vec(n, rt, z);
+    rr = dd_dot_vec(n, r, r);
+    if (hist) { hist[0] = rr.c[0]; hist[1] = rr.c[1]; }
+    for (;;) {
+        if (dd_le(rr, tol2)) {
+            dd_residual(&M, b, x, q, r);
+            rr = dd_dot_vec(n, r, r);
+            if (dd_le(rr, tol2)) { status = 0; break; }
+            info->restarts++;
+            memcpy(rt, r, vb);
+            dd_precond(n, minv, r, z);
+            memcpy(zt, z, vb);
+            memcpy(p, z, vb);
+            memcpy(pt, z, vb);
+            rho = dd_dot_vec(n, rt, z);
+        }
+        if (k >= max_iter) break;
+        dd_spmv(&M, p, q);
+        dd_spmv(&Mt, pt, qt);
+        sigma = dd_dot_vec(n, pt, q);
+        if (sigma.c[0] == 0.0 || !isfinite(sigma.c[0])) { status = -6; break; }
+        alpha = dd_div(rho, sigma);
+        for (i = 0; i < n; ++i) {
+            st2(x, n, i, dd_add(ld2(x, n, i), dd_mul(alpha, ld2(p, n, i))));
+            st2(r, n, i, dd_add(ld2(r, n, i), mp_neg(dd_mul(alpha, ld2(q, n, i)))));
+            st2(rt, n, i, dd_add(ld2(rt, n, i), mp_neg(dd_mul(alpha, ld2(qt, n, i)))));
+        }
+        dd_precond(n, minv, r, z);
+        dd_precond(n, minv, rt, zt);
+        rho_new = dd_dot_vec(n, rt, z);
+        rr = dd_dot_vec(n, r, r);
+        k++;
+        if (hist) { hist[2 * k] = rr.c[0]; hist[2 * k + 1] = rr.c[1]; }
+        if (!isfinite(rr.c[0]) || !isfinite(rho_new.c[0])) { status = -6; break; }
+        if (rho_new.c[0] == 0.0 && !dd_le(rr, tol2)) { status = -6; break; }
+        beta = dd_div(rho_new, rho);
+        rho = rho_new;
+        for (i = 0; i < n; ++i) {
+            st2(p, n, i, dd_add(ld2(z, n, i), dd_mul(beta, ld2(p, n, i))));
+            st2(pt, n, i, dd_add(ld2(zt, n, i), dd_mul(beta, ld2(pt, n, i))));
+        }
+    }
+    dd_residual(&M, b, x, q, r);
+    rr = dd_dot_vec(n, r, r);
+    info->status = status;
+    info->iters = k;
+    info->rr_true[0] = rr.c[0]; info->rr_true[1] = rr.c[1];
+    info->bb[0] = bb.c[0]; info->bb[1] = bb.c[1];
+    free(r); free(z); free(p); free(q); free(rt); free(zt); free(pt); free(qt);
+    return status;
+}

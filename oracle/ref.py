@@ -185,6 +185,9 @@ def _krylov_sigs():
     for f in (L.oracle_cg, L.oracle_bicgstab):
         f.argtypes = [i64, i64, P, P, P, P, P, P, P, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(SolveInfo), P]
         f.restype = ctypes.c_int
+    L.oracle_bicg.argtypes = [i64, i64, P, P, P, P, P, P, P, P, P, P, P, ctypes.c_double, ctypes.c_int32,
+                              ctypes.POINTER(SolveInfo), P]
+    L.oracle_bicg.restype = ctypes.c_int
     L._krylov_ready = True
     return L
 
@@ -246,6 +249,30 @@ def bicgstab(row_ptr, col_idx, a, b, x0=None, precond="jacobi", rtol=1e-28, max_
              history=False):
     """DD BiCGSTAB (oracle).  Returns (x, info dict)."""
     return _solve("oracle_bicgstab", row_ptr, col_idx, a, b, x0, precond, rtol, max_iter, log2w, history)
+
+
+def bicg(row_ptr, col_idx, a, b, x0=None, precond="jacobi", rtol=1e-28, max_iter=10000, log2w=None,
+         log2w_t=None, history=False):
+    """DD BiCG (oracle); A^T from the oracle's stable transpose.  Returns (x, info dict)."""
+    L = _krylov_sigs()
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
+    a, b = _f64(a), _f64(b)
+    n = row_ptr.size - 1
+    rpt, cit, at = transpose(row_ptr, col_idx, a, n_cols=n)
+    x = np.array(x0, dtype=np.float64, order="C", copy=True) if x0 is not None else np.zeros((2, n))
+    minv = jacobi_minv(row_ptr, col_idx, a[0]) if precond == "jacobi" else None
+    lw = None if log2w is None else np.ascontiguousarray(log2w, dtype=np.uint8)
+    lwt = None if log2w_t is None else np.ascontiguousarray(log2w_t, dtype=np.uint8)
+    hist = np.zeros(2 * (max_iter + 1)) if history else None
+    info = SolveInfo()
+    L.oracle_bicg(n, col_idx.size, _p(row_ptr), _p(col_idx), _p(lw), _p(a), _p(rpt), _p(cit), _p(lwt), _p(at),
+                  _p(b), _p(x), _p(minv), float(rtol), int(max_iter), ctypes.byref(info), _p(hist))
+    out = {"status": info.status, "iters": info.iters, "restarts": info.restarts,
+           "rr_true": np.array(info.rr_true[:]), "bb": np.array(info.bb[:])}
+    if history:
+        out["history"] = hist[:2 * (info.iters + 1)].reshape(-1, 2)
+    return x, out
 
 
 class IrInfo(ctypes.Structure):

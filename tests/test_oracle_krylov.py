@@ -133,3 +133,34 @@ def test_failure_modes():
     assert info["status"] == 0
     x2, info2 = ref.cg(row_ptr, col_idx, a, b, x0=x, rtol=1e-20, max_iter=5000)
     assert info2["status"] == 0 and info2["iters"] == 0 and np.array_equal(x, x2)
+
+
+def test_bicg_equals_cg_on_symmetric_matrices():
+    """With A = A^T exactly (values too) and a symmetric preconditioner the shadow
+    recursion of BiCG repeats the primal one, so BiCG is CG step for step: same
+    iterates bit for bit, same counts."""
+    row_ptr, col_idx, a = diffusion3d_7pt(m=7, sigma=1.5, seed=8)
+    n = row_ptr.size - 1
+    b = random_mp(n, 2, np.random.default_rng(8))
+    for precond in ("none", "jacobi"):
+        xc, ic = ref.cg(row_ptr, col_idx, a, b, precond=precond, rtol=1e-28, max_iter=5000, history=True)
+        xb, ib = ref.bicg(row_ptr, col_idx, a, b, precond=precond, rtol=1e-28, max_iter=5000, history=True)
+        assert ic["status"] == 0 and (ib["status"], ib["iters"], ib["restarts"]) == (0, ic["iters"], ic["restarts"])
+        assert np.array_equal(xb, xc)
+        assert np.array_equal(ib["history"], ic["history"])
+
+
+def test_bicg_nonsymmetric_certified():
+    row_ptr, col_idx, a = banded_nonsymmetric(n=200, seed=5)
+    v = sqrt2_vector(200, 2)
+    b = ref.spmv(2, row_ptr, col_idx, a, v)
+    for precond in ("none", "jacobi"):
+        x, info = ref.bicg(row_ptr, col_idx, a, b, precond=precond, rtol=1e-28, max_iter=20000)
+        assert info["status"] == 0
+        ok, rel = _certify(row_ptr, col_idx, a, b, x, 1e-28)
+        assert ok, rel
+    bad = b.copy()
+    bad[0, 5] = np.nan
+    assert ref.bicg(row_ptr, col_idx, a, bad, rtol=1e-28, max_iter=50)[1]["status"] == -6
+    _, info = ref.bicg(row_ptr, col_idx, a, b, rtol=1e-28, max_iter=3)
+    assert info["status"] == -5 and info["iters"] == 3
