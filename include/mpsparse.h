@@ -271,6 +271,24 @@ mp_status mpkrylov_bicgstab(const mp_csr *A, const double *a, const double *b, d
                             mp_solve_info *info, void *stream);
 
 /*
+ * DD BiCG (Fletcher's biconjugate gradients; Sec. 4.2 lists BiCG among the product-
+ * type Krylov methods, and its SpTMV is what slows it down there).  A^T is passed
+ * explicitly (At, at: e.g. from mp_csr_transpose, 2*nnz DD values) with an optional
+ * DD real plan of At (plan_t), so both products are ordinary planned SpMVs.  Jacobi
+ * (opts.precond) is symmetric, so the shadow system uses the same M.  r~ = r at the
+ * start and after every restart.  Step: q = A p, q~ = A^T p~, sigma = (p~, q),
+ * alpha = rho / sigma, x += alpha p, r -= alpha q, r~ -= alpha q~, z = M r,
+ * z~ = M r~, rho' = (r~, z), beta = rho' / rho, p = z + beta p, p~ = z~ + beta p~.
+ * Stop test, true-residual confirmation and restarts as mpkrylov_cg.  Breakdown:
+ * sigma = 0, rho' = 0 before convergence, or a non-finite scalar.  On an exactly
+ * symmetric A (pattern and values) with At its stable transpose the iterates equal
+ * mpkrylov_cg's bit for bit.  Other arguments as mpkrylov_cg.
+ */
+mp_status mpkrylov_bicg(const mp_csr *A, const double *a, const mp_csr *At, const double *at, const double *b,
+                        double *x, const mp_solve_opts *opts, const mp_plan *plan, const mp_plan *plan_t, void *ws,
+                        size_t ws_bytes, mp_solve_info *info, void *stream);
+
+/*
  * Mixed-precision iterative refinement (layer on the paper's method; the paper lists
  * mixed-precision Krylov methods as future work, Sec. 5).  Outer loop in DD: r = b - A x
  * with the DD SpMV (plan order) and a DD subtraction; stop when ||r||^2 <= rtol^2

@@ -85,6 +85,8 @@ for _name in ("mpkrylov_cg", "mpkrylov_bicgstab", "mpkrylov_ir"):
     _SIGS[_name] = ([_CSR, _P, _P, _P, ctypes.POINTER(mp_solve_opts), _P, _P, ctypes.c_size_t,
                      ctypes.POINTER(mp_solve_info), _P], ctypes.c_int)
 
+_SIGS["mpkrylov_bicg"] = ([_CSR, _P, _CSR, _P, _P, _P, ctypes.POINTER(mp_solve_opts), _P, _P, _P, ctypes.c_size_t,
+                           ctypes.POINTER(mp_solve_info), _P], ctypes.c_int)
 _SIGS["mp_csr_transpose"] = ([_CSR, _I, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int)
 _SIGS["mpkrylov_ir_learned"] = ([_CSR, _P, _P, _P, _P, ctypes.POINTER(mp_solve_opts), _P, _P, ctypes.c_size_t,
                                  ctypes.POINTER(mp_solve_info), _P], ctypes.c_int)
@@ -381,6 +383,24 @@ def _solver(name):
 mpkrylov_cg = _solver("mpkrylov_cg")
 mpkrylov_bicgstab = _solver("mpkrylov_bicgstab")
 mpkrylov_ir = _solver("mpkrylov_ir")
+
+
+def mpkrylov_bicg(A, a, At, at, b, x, plan=None, plan_t=None, ws=None, stream=None, raise_on_failure=False, **opts):
+    """DD BiCG (C ABI mpkrylov_bicg) with A^T given as (At, at), e.g. from
+    mp_csr_transpose.  x is updated in place; returns the info record."""
+    _check_mp(a, 2, A.nnz, "a")
+    _check_mp(at, 2, At.nnz, "at")
+    _check_mp(b, 2, A.n_rows, "b")
+    _check_mp(x, 2, A.n_rows, "x")
+    o = _opts(**opts)
+    ws = _workspace(A, ws, **opts)
+    info = mp_solve_info()
+    st = _lib.mpkrylov_bicg(ctypes.byref(A.c), _ptr(a), ctypes.byref(At.c), _ptr(at), _ptr(b), _ptr(x),
+                            ctypes.byref(o), _plan_handle(plan), _plan_handle(plan_t), _ptr(ws),
+                            ws.numel() * ws.element_size(), ctypes.byref(info), _stream_ptr(stream))
+    if st not in (MP_OK, -5, -6) or (raise_on_failure and st != MP_OK):
+        _check(st, "mpkrylov_bicg")
+    return _info_dict(info)
 
 
 def mpkrylov_ir_learned(A, a, m_values, b, x, plan=None, ws=None, stream=None, raise_on_failure=False, **opts):

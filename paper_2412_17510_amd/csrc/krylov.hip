@@ -461,6 +461,104 @@ __global__ __launch_bounds__(256) void k_cg_p(int64_t n, const double *__restric
 }
 
 // ---------------------------------------------------------------------------
+// BiCG (Fletcher), with A^T given explicitly
+// ---------------------------------------------------------------------------
+
+// sigma = (p~, q); alpha = rho / sigma; breakdown when sigma is 0 or not finite
+__global__ __launch_bounds__(256) void k_bicg_alpha(const dd_t *__restrict__ ppq, int m, KState *__restrict__ st)
+{
+    __shared__ dd_t P[kMaxChunks];
+    if (st->done != RUN) return;
+    const dd_t pq = pair_tree(ppq, m, P);
+    if (threadIdx.x == 0) {
+        st->pq = pq;
+        if (pq.c[0] == 0.0 || !dd_finite(pq))
+            st->done = BROKE_DOWN;
+        else
+            st->alpha = dd_div(st->rho, pq);
+    }
+}
+
+// x += alpha p; r -= alpha q; r~ -= alpha q~; z = M^-1 r; z~ = M^-1 r~;
+// chunk sums of (r~, z) and (r, r)
+__global__ __launch_bounds__(256) void k_bicg_update(int64_t n, double *__restrict__ x, double *__restrict__ r,
+                                                     double *__restrict__ z, const double *__restrict__ p,
+                                                     const double *__restrict__ q, double *__restrict__ rt,
+                                                     double *__restrict__ zt, const double *__restrict__ qt,
+                                                     const double *__restrict__ minv, dd_t *__restrict__ prz,
+                                                     dd_t *__restrict__ prr, const KState *__restrict__ st)
+{
+    __shared__ dd_t lds[kDotLanes];
+    if (st->done != RUN) return;
+    const dd_t alpha = st->alpha;
+    const int c = blockIdx.x;
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)c * kDotChunk;
+    const int64_t end = (n - base) < kDotChunk ? n : base + kDotChunk;
+    const int used = chunk_used(n, c);
+    dd_t arz = dd_zero(), arr = dd_zero();
+    bool first = true;
+    for (int64_t k = base + t; k < end; k += kDotLanes) {
+        sdd(x, n, k, dd_add(ldd(x, n, k), dd_mul(alpha, ldd(p, n, k))));
+        const dd_t rk = dd_sub(ldd(r, n, k), dd_mul(alpha, ldd(q, n, k)));
+        const dd_t rtk = dd_sub(ldd(rt, n, k), dd_mul(alpha, ldd(qt, n, k)));
+        sdd(r, n, k, rk);
+        sdd(rt, n, k, rtk);
+        const dd_t zk = minv ? dd_mul_d(rk, minv[k]) : rk;
+        const dd_t ztk = minv ? dd_mul_d(rtk, minv[k]) : rtk;
+        sdd(z, n, k, zk);
+        sdd(zt, n, k, ztk);
+        const dd_t p1 = dd_mul(rtk, zk), p2 = dd_mul(rk, rk);
+        arz = first ? p1 : dd_add(arz, p1);
+        arr = first ? p2 : dd_add(arr, p2);
+        first = false;
+    }
+    const dd_t s1 = chunk_fold(arz, used, lds);
+    const dd_t s2 = chunk_fold(arr, used, lds);
+    if (t == 0) {
+        prz[c] = s1;
+        prr[c] = s2;
+    }
+}
+
+// rho' = (r~, z), rr = (r, r); beta = rho' / rho; stop tests
+__global__ __launch_bounds__(256) void k_bicg_beta(const dd_t *__restrict__ prz, const dd_t *__restrict__ prr, int m,
+                                                   KState *__restrict__ st)
+{
+    __shared__ dd_t P[kMaxChunks];
+    if (st->done != RUN) return;
+    const dd_t rz = pair_tree(prz, m, P);
+    const dd_t rr = pair_tree(prr, m, P);
+    if (threadIdx.x == 0) {
+        st->iters += 1;
+        st->rr = rr;
+        if (!dd_finite(rr) || !dd_finite(rz) || (rz.c[0] == 0.0 && !dd_le(rr, st->tol2))) {
+            st->done = BROKE_DOWN;
+            return;
+        }
+        st->beta = dd_div(rz, st->rho);
+        st->rho = rz;
+        if (dd_le(rr, st->tol2))
+            st->done = RECURRENCE_MET;
+        else if (st->iters >= st->max_iter)
+            st->done = ITER_LIMIT;
+    }
+}
+
+// p = z + beta p; p~ = z~ + beta p~
+__global__ __launch_bounds__(256) void k_bicg_p(int64_t n, const double *__restrict__ z, double *__restrict__ p,
+                                                const double *__restrict__ zt, double *__restrict__ pt,
+                                                const KState *__restrict__ st)
+{
+    if (st->done != RUN) return;
+    const dd_t beta = st->beta;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        sdd(p, n, i, dd_add(ldd(z, n, i), dd_mul(beta, ldd(p, n, i))));
+        sdd(pt, n, i, dd_add(ldd(zt, n, i), dd_mul(beta, ldd(pt, n, i))));
+    }
+}
+
+// ---------------------------------------------------------------------------
 // BiCGSTAB
 // ---------------------------------------------------------------------------
 
@@ -1329,6 +1427,84 @@ mp_status run_cg(Solver &S, const double *b, double *x, const mp_solve_opts *o, 
     return MP_OK;
 }
 
+// BiCG driver: A^T (At, at) with an optional plan of its own
+mp_status run_bicg(Solver &S, const mp_csr *At, const double *at, const mp_plan *plan_t, const double *b, double *x,
+                   const mp_solve_opts *o, mp_solve_info *info)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    const int64_t n = S.n;
+    const int m = S.m;
+    double *r = S.w.v[0], *z = S.w.v[1], *p = S.w.v[2], *q = S.w.v[3];
+    double *rt = S.w.v[4], *zt = S.w.v[5], *pt = S.w.v[6], *qt = S.w.v[7];
+    const double *minv = o->precond == MP_PRECOND_JACOBI ? S.w.minv : nullptr;
+    const int every = o->check_every > 0 ? o->check_every : 32;
+    mp_status st = MP_OK;
+    KState h;
+    std::memset(&h, 0, sizeof(h));
+    MP_HIP_TRY(hipMemsetAsync(S.w.st, 0, sizeof(KState), S.s));
+    if (minv) {
+        hipLaunchKernelGGL(k_jacobi_minv, dim3(S.vblocks), dim3(256), 0, S.s, n, S.A->row_ptr, S.A->col_idx, S.a,
+                           S.w.minv);
+        if ((st = S.launched()) != MP_OK) return st;
+    }
+    // shadow start r~ = r; z = M^-1 r; z~ = p = p~ = z
+    auto reset = [&]() -> mp_status {
+        hipLaunchKernelGGL(k_copy, dim3(S.vblocks), dim3(256), 0, S.s, 2 * n, r, rt);
+        hipLaunchKernelGGL(k_precond, dim3(S.vblocks), dim3(256), 0, S.s, n, minv, r, z, nullptr);
+        hipLaunchKernelGGL(k_copy, dim3(S.vblocks), dim3(256), 0, S.s, 2 * n, z, zt);
+        hipLaunchKernelGGL(k_copy, dim3(S.vblocks), dim3(256), 0, S.s, 2 * n, z, p);
+        hipLaunchKernelGGL(k_copy, dim3(S.vblocks), dim3(256), 0, S.s, 2 * n, z, pt);
+        return S.launched();
+    };
+    if ((st = S.residual(b, x, q, r)) != MP_OK) return st;
+    if ((st = reset()) != MP_OK) return st;
+    if ((st = S.dot2(b, b, rt, z, S.w.part[0], S.w.part[1], nullptr)) != MP_OK) return st;
+    if ((st = S.dot2(r, r, nullptr, nullptr, S.w.part[2], nullptr, nullptr)) != MP_OK) return st;
+    hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(256), 0, S.s, S.w.part[0], S.w.part[1], S.w.part[2], m,
+                       o->rtol * o->rtol, o->max_iter, S.w.st);
+    if ((st = S.launched()) != MP_OK) return st;
+    int status = MP_ERR_NOT_CONVERGED;
+    for (;;) {
+        if ((st = S.read_state(&h)) != MP_OK) return st;
+        if (h.done == RUN) {
+            for (int it = 0; it < every; ++it) {
+                if ((st = S.spmv(p, q)) != MP_OK) return st;
+                if ((st = spmv_dispatch(2, false, At, at, nullptr, pt, nullptr, qt, nullptr, plan_t, S.s)) != MP_OK)
+                    return st;
+                if ((st = S.dot2(pt, q, nullptr, nullptr, S.w.part[0], nullptr, S.w.st)) != MP_OK) return st;
+                hipLaunchKernelGGL(k_bicg_alpha, dim3(1), dim3(256), 0, S.s, S.w.part[0], m, S.w.st);
+                hipLaunchKernelGGL(k_bicg_update, dim3(m), dim3(256), 0, S.s, n, x, r, z, p, q, rt, zt, qt, minv,
+                                   S.w.part[1], S.w.part[2], S.w.st);
+                hipLaunchKernelGGL(k_bicg_beta, dim3(1), dim3(256), 0, S.s, S.w.part[1], S.w.part[2], m, S.w.st);
+                hipLaunchKernelGGL(k_bicg_p, dim3(S.vblocks), dim3(256), 0, S.s, n, z, p, zt, pt, S.w.st);
+                if ((st = S.launched()) != MP_OK) return st;
+            }
+            continue;
+        }
+        if (h.done == RECURRENCE_MET) {
+            if ((st = S.true_residual(b, x, q, r, true)) != MP_OK) return st;
+            continue;
+        }
+        if (h.done == RESTART) {
+            if ((st = reset()) != MP_OK) return st;
+            if ((st = S.dot2(rt, z, nullptr, nullptr, S.w.part[1], nullptr, nullptr)) != MP_OK) return st;
+            hipLaunchKernelGGL(k_cg_restart, dim3(1), dim3(256), 0, S.s, S.w.part[1], m, S.w.st);
+            if ((st = S.launched()) != MP_OK) return st;
+            continue;
+        }
+        status = h.done == CONFIRMED ? MP_OK : (h.done == BROKE_DOWN ? MP_ERR_BREAKDOWN : MP_ERR_NOT_CONVERGED);
+        break;
+    }
+    if ((st = S.true_residual(b, x, q, r, false)) != MP_OK) return st;
+    if ((st = S.read_state(&h)) != MP_OK) return st;
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    fill_info(h, status, secs, info);
+    if (status == MP_ERR_NOT_CONVERGED)
+        return fail(MP_ERR_NOT_CONVERGED, "mpkrylov_bicg: no convergence in %d iterations", h.iters);
+    if (status == MP_ERR_BREAKDOWN) return fail(MP_ERR_BREAKDOWN, "mpkrylov_bicg: breakdown at iteration %d", h.iters);
+    return MP_OK;
+}
+
 mp_status run_bicgstab(Solver &S, const double *b, double *x, const mp_solve_opts *o, mp_solve_info *info)
 {
     const auto t0 = std::chrono::steady_clock::now();
@@ -1650,6 +1826,41 @@ mp_status mpkrylov_ir(const mp_csr *A, const double *a, const double *b, double 
                       const mp_plan *plan, void *ws, size_t ws_bytes, mp_solve_info *info, void *stream)
 {
     return mpk::solve_entry("mpkrylov_ir", 2, A, a, nullptr, b, x, opts, plan, ws, ws_bytes, info, stream);
+}
+
+mp_status mpkrylov_bicg(const mp_csr *A, const double *a, const mp_csr *At, const double *at, const double *b,
+                        double *x, const mp_solve_opts *opts, const mp_plan *plan, const mp_plan *plan_t, void *ws,
+                        size_t ws_bytes, mp_solve_info *info, void *stream)
+{
+    using namespace mpk;
+    clear_error();
+    const size_t need = A ? workspace_bytes(A->n_rows) : 0;
+    mp_status st = check_solver_args("mpkrylov_bicg", A, a, b, x, opts, plan, ws, ws_bytes, need, info, false);
+    if (st != MP_OK) return st;
+    if ((st = check_csr(At)) != MP_OK) return st;
+    if (At->n_rows != A->n_cols || At->n_cols != A->n_rows || At->nnz != A->nnz)
+        return fail(MP_ERR_INVALID_ARG, "mpkrylov_bicg: At is not the transpose's shape");
+    if (At->nnz > 0 && !at) return fail(MP_ERR_INVALID_ARG, "mpkrylov_bicg: at is NULL");
+    if (plan_t && (plan_t->ncomp != 2 || plan_t->cplx || plan_t->n_rows != At->n_rows || plan_t->nnz != At->nnz))
+        return fail(MP_ERR_INVALID_ARG, "mpkrylov_bicg: plan_t is not a DD real plan of At");
+    const size_t vb = sizeof(double) * 2 * (size_t)A->n_rows;
+    if (overlaps(x, vb, at, sizeof(double) * 2 * (size_t)At->nnz))
+        return fail(MP_ERR_ALIAS, "mpkrylov_bicg: x overlaps at");
+    if (A->n_rows == 0) {
+        std::memset(info, 0, sizeof(*info));
+        return MP_OK;
+    }
+    Solver S;
+    S.A = A;
+    S.a = a;
+    S.plan = plan;
+    S.s = static_cast<hipStream_t>(stream);
+    S.n = A->n_rows;
+    S.m = (int)((S.n + kDotChunk - 1) / kDotChunk);
+    const int64_t vblk = (S.n + 255) / 256;
+    S.vblocks = (unsigned)(vblk < 8192 ? vblk : 8192);
+    S.w = carve(ws, S.n);
+    return run_bicg(S, At, at, plan_t, b, x, opts, info);
 }
 
 mp_status mpkrylov_ir_learned(const mp_csr *A, const double *a, const double *m_values, const double *b, double *x,

@@ -117,3 +117,35 @@ def test_breakdown_warm_start_and_errors(mp):
     with pytest.raises(mp.MpError):
         qplan = mp.mp_plan_create(A, 4)
         mp.mpkrylov_cg(A, ad, bd, x, plan=qplan)
+
+
+def test_bicg_matches_oracle_and_cg(mp):
+    """GPU BiCG (with the device transpose) equals the oracle's BiCG bit for bit on a
+    non-symmetric band and on a symmetric diffusion matrix, where it also equals CG."""
+    import torch
+    from workloads import banded_nonsymmetric, diffusion3d_7pt
+    for name, (row_ptr, col_idx, a) in (("band", banded_nonsymmetric(n=300, seed=5)),
+                                        ("diffusion", diffusion3d_7pt(m=7, sigma=1.5, seed=8))):
+        n = row_ptr.size - 1
+        b = random_mp(n, 2, np.random.default_rng(11))
+        A = mp.Csr.from_numpy(row_ptr, col_idx)
+        ad, bd = dev(a), dev(b)
+        At, at, _ = mp.mp_csr_transpose(A, ad)
+        for precond in ("none", "jacobi"):
+            for plans in ((None, None), (mp.mp_plan_create(A, 2, False, 2, 6), mp.mp_plan_create(At, 2, False, 1, 4))):
+                x = torch.zeros((2, n), dtype=torch.float64, device="cuda")
+                ig = mp.mpkrylov_bicg(A, ad, At, at, bd, x, plan=plans[0], plan_t=plans[1], precond=precond,
+                                      rtol=1e-28, max_iter=20000, check_every=16)
+                lw = None if plans[0] is None else plans[0].row_log2w()
+                lwt = None if plans[1] is None else plans[1].row_log2w()
+                xo, io = ref.bicg(row_ptr, col_idx, a, b, precond=precond, rtol=1e-28, max_iter=20000, log2w=lw,
+                                  log2w_t=lwt)
+                assert (ig["status"], ig["iters"], ig["restarts"]) == (io["status"], io["iters"], io["restarts"]), name
+                assert io["status"] == 0
+                assert_same_values(host(x), xo, "%s bicg x" % name)
+                assert_same_values(ig["rr_true"], io["rr_true"], "%s bicg rr" % name)
+                if name == "diffusion" and plans[0] is None:
+                    xc = torch.zeros_like(x)
+                    ic = mp.mpkrylov_cg(A, ad, bd, xc, precond=precond, rtol=1e-28, max_iter=20000, check_every=16)
+                    assert ic["iters"] == ig["iters"]
+                    assert_same_values(host(xc), host(x), "bicg = cg on a symmetric matrix")
