@@ -1157,3 +1157,91 @@ int oracle_bicg(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *c
     free(r); free(z); free(p); free(q); free(rt); free(zt); free(pt); free(qt);
     return status;
 }
+
+/*
+ * CGS in DD (Sonneveld's conjugate gradient squared, Sec. 4.2's list), with right
+ * Jacobi preconditioning as oracle_bicgstab (solve A M y = b, x = M y, so r stays
+ * the true recurrence residual of A x = b).  Shadow r~ = r at the start and after
+ * each restart.  Step: rho = (r~, r) (breakdown when 0 or not finite); the first
+ * step after a (re)start takes u = p = r, later steps beta = rho / rho_old,
+ * u = r + beta q, p = u + beta (q + beta p); p^ = M p, v = A p^, sigma = (r~, v)
+ * (breakdown when 0 or not finite), alpha = rho / sigma, q = u - alpha v,
+ * u^ = M (u + q), x += alpha u^, r -= alpha A u^.  Stop test, confirmation and
+ * restarts as oracle_cg.
+ */
+int oracle_cgs(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx, const uint8_t *log2w,
+               const double *a, const double *b, double *x, const double *minv, double rtol, int32_t max_iter,
+               oracle_solve_info *info, double *hist)
+{
+    dd_mat M = {n, nnz, row_ptr, col_idx, log2w, a};
+    size_t vb = sizeof(double) * 2 * (size_t)n;
+    double *r = (double *)malloc(vb), *rh = (double *)malloc(vb), *u = (double *)malloc(vb), *p = (double *)malloc(vb);
+    double *q = (double *)malloc(vb), *v = (double *)malloc(vb), *uh = (double *)malloc(vb), *t = (double *)malloc(vb);
+    double *ph = (double *)malloc(vb);
+    mpv rho, rho_old = {{1.0, 0.0, 0.0, 0.0}}, beta, sigma, alpha, rr, bb, tol2;
+    int64_t i;
+    int32_t k = 0;
+    int status = -5, fresh = 1;
+    memset(info, 0, sizeof(*info));
+    bb = dd_dot_vec(n, b, b);
+    tol2 = dd_mul_d(bb, rtol * rtol);
+    dd_residual(&M, b, x, t, r);
+    memcpy(rh, r, vb);
+    memset(q, 0, vb);
+    memset(p, 0, vb);
+    rr = dd_dot_vec(n, r, r);
+    if (hist) { hist[0] = rr.c[0]; hist[1] = rr.c[1]; }
+    for (;;) {
+        if (dd_le(rr, tol2)) {
+            dd_residual(&M, b, x, t, r);
+            rr = dd_dot_vec(n, r, r);
+            if (dd_le(rr, tol2)) { status = 0; break; }
+            info->restarts++;
+            memcpy(rh, r, vb);
+            fresh = 1;
+        }
+        if (k >= max_iter) break;
+        rho = dd_dot_vec(n, rh, r);
+        if (rho.c[0] == 0.0 || !isfinite(rho.c[0])) { status = -6; break; }
+        if (fresh) {
+            memcpy(u, r, vb);
+            memcpy(p, r, vb);
+            fresh = 0;
+        } else {
+            beta = dd_div(rho, rho_old);
+            for (i = 0; i < n; ++i) {
+                mpv ui = dd_add(ld2(r, n, i), dd_mul(beta, ld2(q, n, i)));
+                mpv w = dd_add(ld2(q, n, i), dd_mul(beta, ld2(p, n, i)));
+                st2(u, n, i, ui);
+                st2(p, n, i, dd_add(ui, dd_mul(beta, w)));
+            }
+        }
+        dd_precond(n, minv, p, ph);
+        dd_spmv(&M, ph, v);
+        sigma = dd_dot_vec(n, rh, v);
+        if (sigma.c[0] == 0.0 || !isfinite(sigma.c[0])) { status = -6; break; }
+        alpha = dd_div(rho, sigma);
+        for (i = 0; i < n; ++i) {
+            mpv qi = dd_add(ld2(u, n, i), mp_neg(dd_mul(alpha, ld2(v, n, i))));
+            mpv s = dd_add(ld2(u, n, i), qi);
+            st2(q, n, i, qi);
+            st2(uh, n, i, minv ? dd_mul_d(s, minv[i]) : s);
+        }
+        for (i = 0; i < n; ++i) st2(x, n, i, dd_add(ld2(x, n, i), dd_mul(alpha, ld2(uh, n, i))));
+        dd_spmv(&M, uh, t);
+        for (i = 0; i < n; ++i) st2(r, n, i, dd_add(ld2(r, n, i), mp_neg(dd_mul(alpha, ld2(t, n, i)))));
+        rr = dd_dot_vec(n, r, r);
+        k++;
+        if (hist) { hist[2 * k] = rr.c[0]; hist[2 * k + 1] = rr.c[1]; }
+        if (!isfinite(rr.c[0])) { status = -6; break; }
+        rho_old = rho;
+    }
+    dd_residual(&M, b, x, t, r);
+    rr = dd_dot_vec(n, r, r);
+    info->status = status;
+    info->iters = k;
+    info->rr_true[0] = rr.c[0]; info->rr_true[1] = rr.c[1];
+    info->bb[0] = bb.c[0]; info->bb[1] = bb.c[1];
+    free(r); free(rh); free(u); free(p); free(q); free(v); free(uh); free(t); free(ph);
+    return status;
+}

@@ -164,3 +164,31 @@ def test_bicg_nonsymmetric_certified():
     assert ref.bicg(row_ptr, col_idx, a, bad, rtol=1e-28, max_iter=50)[1]["status"] == -6
     _, info = ref.bicg(row_ptr, col_idx, a, b, rtol=1e-28, max_iter=3)
     assert info["status"] == -5 and info["iters"] == 3
+
+
+def test_cgs_k_distinct_eigenvalues_and_nonsymmetric_certified():
+    """CGS squares the BiCG polynomial, so on a diagonal matrix with k distinct
+    eigenvalues it also terminates within k steps; on the tub1000-shaped band it
+    reaches 1e-28, certified by an exact residual; failures are reported."""
+    n = 400
+    eig = np.array([1.0, 2.0, 3.0, 5.0, 8.0])
+    row_ptr = np.arange(n + 1, dtype=np.int32)
+    col_idx = np.arange(n, dtype=np.int32)
+    a = np.zeros((2, n))
+    a[0] = eig[np.arange(n) % eig.size]
+    b = random_mp(n, 2, np.random.default_rng(3))
+    _, info = ref.cgs(row_ptr, col_idx, a, b, precond="none", rtol=1e-28, max_iter=50)
+    assert info["status"] == 0 and info["iters"] <= eig.size
+    row_ptr, col_idx, a = banded_nonsymmetric(n=200, seed=5)
+    v = sqrt2_vector(200, 2)
+    b = ref.spmv(2, row_ptr, col_idx, a, v)
+    for precond in ("none", "jacobi"):
+        x, info = ref.cgs(row_ptr, col_idx, a, b, precond=precond, rtol=1e-28, max_iter=20000)
+        assert info["status"] == 0
+        ok, rel = _certify(row_ptr, col_idx, a, b, x, 1e-28)
+        assert ok, rel
+    bad = b.copy()
+    bad[0, 5] = np.nan
+    assert ref.cgs(row_ptr, col_idx, a, bad, rtol=1e-28, max_iter=50)[1]["status"] == -6
+    _, info = ref.cgs(row_ptr, col_idx, a, b, rtol=1e-28, max_iter=3)
+    assert info["status"] == -5 and info["iters"] == 3
