@@ -271,6 +271,20 @@ mp_status mpkrylov_bicgstab(const mp_csr *A, const double *a, const double *b, d
                             mp_solve_info *info, void *stream);
 
 /*
+ * DD CGS (Sonneveld's conjugate gradient squared; Sec. 4.2's list of product-type
+ * Krylov methods) with right Jacobi preconditioning (opts.precond; solves A M y = b,
+ * x = M y, so r is the residual of A x = b).  Shadow r~ = r at the start and after a
+ * restart.  Step: rho = (r~, r) (breakdown if 0 or not finite); the first step after
+ * a (re)start takes u = p = r, later ones beta = rho / rho_old, u = r + beta q,
+ * p = u + beta (q + beta p); p^ = M p, v = A p^, sigma = (r~, v) (breakdown if 0 or
+ * not finite), alpha = rho / sigma, q = u - alpha v, u^ = M (u + q), x += alpha u^,
+ * r -= alpha A u^.  Two SpMVs per step.  Stop test, confirmation, restarts and
+ * arguments as mpkrylov_cg (A need not be symmetric).
+ */
+mp_status mpkrylov_cgs(const mp_csr *A, const double *a, const double *b, double *x, const mp_solve_opts *opts,
+                       const mp_plan *plan, void *ws, size_t ws_bytes, mp_solve_info *info, void *stream);
+
+/*
  * DD BiCG (Fletcher's biconjugate gradients; Sec. 4.2 lists BiCG among the product-
  * type Krylov methods, and its SpTMV is what slows it down there).  A^T is passed
  * explicitly (At, at: e.g. from mp_csr_transpose, 2*nnz DD values) with an optional

@@ -559,6 +559,159 @@ __global__ __launch_bounds__(256) void k_bicg_p(int64_t n, const double *__restr
 }
 
 // ---------------------------------------------------------------------------
+// CGS (Sonneveld), right Jacobi preconditioning
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_cgs_init(const dd_t *__restrict__ pbb, const dd_t *__restrict__ prr, int m,
+                                                  double rtol2, int32_t max_iter, KState *__restrict__ st)
+{
+    __shared__ dd_t P[kMaxChunks];
+    const dd_t bb = pair_tree(pbb, m, P);
+    const dd_t rr = pair_tree(prr, m, P);
+    if (threadIdx.x == 0) {
+        st->bb = bb;
+        st->tol2 = dd_mul_d(bb, rtol2);
+        st->rr = rr;
+        st->iters = 0;
+        st->max_iter = max_iter;
+        st->restarts = 0;
+        st->fresh = 1;
+        st->done = dd_le(rr, st->tol2) ? RECURRENCE_MET : (max_iter <= 0 ? ITER_LIMIT : RUN);
+    }
+}
+
+// after a failed confirmation: the shadow is reset by the host, the next step is fresh
+__global__ __launch_bounds__(64) void k_cgs_restart(KState *__restrict__ st)
+{
+    if (threadIdx.x == 0) {
+        st->fresh = 1;
+        st->done = st->iters >= st->max_iter ? ITER_LIMIT : RUN;
+    }
+}
+
+// rho = (r~, r): breakdown when 0 or not finite; beta = rho / rho_old unless fresh
+__global__ __launch_bounds__(256) void k_cgs_rho(const dd_t *__restrict__ prho, int m, KState *__restrict__ st)
+{
+    __shared__ dd_t P[kMaxChunks];
+    if (st->done != RUN) return;
+    const dd_t rho = pair_tree(prho, m, P);
+    if (threadIdx.x == 0) {
+        if (rho.c[0] == 0.0 || !dd_finite(rho)) {
+            st->done = BROKE_DOWN;
+            return;
+        }
+        st->rho = rho;
+        if (!st->fresh) st->beta = dd_div(rho, st->rho_old);
+    }
+}
+
+// fresh: u = p = r; else u = r + beta q, p = u + beta (q + beta p); p^ = M^-1 p
+__global__ __launch_bounds__(256) void k_cgs_up(int64_t n, const double *__restrict__ r, const double *__restrict__ q,
+                                                double *__restrict__ u, double *__restrict__ p,
+                                                double *__restrict__ ph, const double *__restrict__ minv,
+                                                const KState *__restrict__ st)
+{
+    if (st->done != RUN) return;
+    const bool fresh = st->fresh != 0;
+    const dd_t beta = st->beta;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const dd_t ri = ldd(r, n, i);
+        dd_t pi;
+        if (fresh) {
+            sdd(u, n, i, ri);
+            pi = ri;
+        } else {
+            const dd_t qi = ldd(q, n, i);
+            const dd_t ui = dd_add(ri, dd_mul(beta, qi));
+            const dd_t w = dd_add(qi, dd_mul(beta, ldd(p, n, i)));
+            sdd(u, n, i, ui);
+            pi = dd_add(ui, dd_mul(beta, w));
+        }
+        sdd(p, n, i, pi);
+        sdd(ph, n, i, minv ? dd_mul_d(pi, minv[i]) : pi);
+    }
+}
+
+// sigma = (r~, v): breakdown when 0 or not finite; alpha = rho / sigma
+__global__ __launch_bounds__(256) void k_cgs_alpha(const dd_t *__restrict__ psig, int m, KState *__restrict__ st)
+{
+    __shared__ dd_t P[kMaxChunks];
+    if (st->done != RUN) return;
+    const dd_t sigma = pair_tree(psig, m, P);
+    if (threadIdx.x == 0) {
+        st->fresh = 0;
+        st->pq = sigma;
+        if (sigma.c[0] == 0.0 || !dd_finite(sigma))
+            st->done = BROKE_DOWN;
+        else
+            st->alpha = dd_div(st->rho, sigma);
+    }
+}
+
+// q = u - alpha v; u^ = M^-1 (u + q); x += alpha u^
+__global__ __launch_bounds__(256) void k_cgs_q(int64_t n, const double *__restrict__ u, const double *__restrict__ v,
+                                               double *__restrict__ q, double *__restrict__ uh, double *__restrict__ x,
+                                               const double *__restrict__ minv, const KState *__restrict__ st)
+{
+    if (st->done != RUN) return;
+    const dd_t alpha = st->alpha;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const dd_t ui = ldd(u, n, i);
+        const dd_t qi = dd_sub(ui, dd_mul(alpha, ldd(v, n, i)));
+        const dd_t s = dd_add(ui, qi);
+        const dd_t uhi = minv ? dd_mul_d(s, minv[i]) : s;
+        sdd(q, n, i, qi);
+        sdd(uh, n, i, uhi);
+        sdd(x, n, i, dd_add(ldd(x, n, i), dd_mul(alpha, uhi)));
+    }
+}
+
+// r -= alpha t; chunk sums of (r, r)
+__global__ __launch_bounds__(256) void k_cgs_r(int64_t n, double *__restrict__ r, const double *__restrict__ t,
+                                               dd_t *__restrict__ prr, const KState *__restrict__ st)
+{
+    __shared__ dd_t lds[kDotLanes];
+    if (st->done != RUN) return;
+    const dd_t alpha = st->alpha;
+    const int c = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int64_t base = (int64_t)c * kDotChunk;
+    const int64_t end = (n - base) < kDotChunk ? n : base + kDotChunk;
+    const int used = chunk_used(n, c);
+    dd_t arr = dd_zero();
+    bool first = true;
+    for (int64_t k = base + tid; k < end; k += kDotLanes) {
+        const dd_t rk = dd_sub(ldd(r, n, k), dd_mul(alpha, ldd(t, n, k)));
+        sdd(r, n, k, rk);
+        const dd_t p2 = dd_mul(rk, rk);
+        arr = first ? p2 : dd_add(arr, p2);
+        first = false;
+    }
+    const dd_t s = chunk_fold(arr, used, lds);
+    if (tid == 0) prr[c] = s;
+}
+
+__global__ __launch_bounds__(256) void k_cgs_rr(const dd_t *__restrict__ prr, int m, KState *__restrict__ st)
+{
+    __shared__ dd_t P[kMaxChunks];
+    if (st->done != RUN) return;
+    const dd_t rr = pair_tree(prr, m, P);
+    if (threadIdx.x == 0) {
+        st->iters += 1;
+        st->rr = rr;
+        if (!dd_finite(rr)) {
+            st->done = BROKE_DOWN;
+            return;
+        }
+        st->rho_old = st->rho;
+        if (dd_le(rr, st->tol2))
+            st->done = RECURRENCE_MET;
+        else if (st->iters >= st->max_iter)
+            st->done = ITER_LIMIT;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // BiCGSTAB
 // ---------------------------------------------------------------------------
 
@@ -1505,6 +1658,75 @@ mp_status run_bicg(Solver &S, const mp_csr *At, const double *at, const mp_plan 
     return MP_OK;
 }
 
+mp_status run_cgs(Solver &S, const double *b, double *x, const mp_solve_opts *o, mp_solve_info *info)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    const int64_t n = S.n;
+    const int m = S.m;
+    double *r = S.w.v[0], *rh = S.w.v[1], *u = S.w.v[2], *p = S.w.v[3], *q = S.w.v[4], *v = S.w.v[5];
+    double *uh = S.w.v[6], *t = S.w.v[7], *ph = S.w.v[8];
+    const double *minv = o->precond == MP_PRECOND_JACOBI ? S.w.minv : nullptr;
+    const int every = o->check_every > 0 ? o->check_every : 32;
+    mp_status st = MP_OK;
+    KState h;
+    std::memset(&h, 0, sizeof(h));
+    MP_HIP_TRY(hipMemsetAsync(S.w.st, 0, sizeof(KState), S.s));
+    if (minv) {
+        hipLaunchKernelGGL(k_jacobi_minv, dim3(S.vblocks), dim3(256), 0, S.s, n, S.A->row_ptr, S.A->col_idx, S.a,
+                           S.w.minv);
+        if ((st = S.launched()) != MP_OK) return st;
+    }
+    if ((st = S.residual(b, x, t, r)) != MP_OK) return st;
+    hipLaunchKernelGGL(k_copy, dim3(S.vblocks), dim3(256), 0, S.s, 2 * n, r, rh);
+    if ((st = S.launched()) != MP_OK) return st;
+    if ((st = S.dot2(b, b, r, r, S.w.part[0], S.w.part[1], nullptr)) != MP_OK) return st;
+    hipLaunchKernelGGL(k_cgs_init, dim3(1), dim3(256), 0, S.s, S.w.part[0], S.w.part[1], m, o->rtol * o->rtol,
+                       o->max_iter, S.w.st);
+    if ((st = S.launched()) != MP_OK) return st;
+    int status = MP_ERR_NOT_CONVERGED;
+    for (;;) {
+        if ((st = S.read_state(&h)) != MP_OK) return st;
+        if (h.done == RUN) {
+            for (int it = 0; it < every; ++it) {
+                if ((st = S.dot2(rh, r, nullptr, nullptr, S.w.part[0], nullptr, S.w.st)) != MP_OK) return st;
+                hipLaunchKernelGGL(k_cgs_rho, dim3(1), dim3(256), 0, S.s, S.w.part[0], m, S.w.st);
+                hipLaunchKernelGGL(k_cgs_up, dim3(S.vblocks), dim3(256), 0, S.s, n, r, q, u, p, ph, minv, S.w.st);
+                if ((st = S.launched()) != MP_OK) return st;
+                if ((st = S.spmv(ph, v)) != MP_OK) return st;
+                if ((st = S.dot2(rh, v, nullptr, nullptr, S.w.part[1], nullptr, S.w.st)) != MP_OK) return st;
+                hipLaunchKernelGGL(k_cgs_alpha, dim3(1), dim3(256), 0, S.s, S.w.part[1], m, S.w.st);
+                hipLaunchKernelGGL(k_cgs_q, dim3(S.vblocks), dim3(256), 0, S.s, n, u, v, q, uh, x, minv, S.w.st);
+                if ((st = S.launched()) != MP_OK) return st;
+                if ((st = S.spmv(uh, t)) != MP_OK) return st;
+                hipLaunchKernelGGL(k_cgs_r, dim3(m), dim3(256), 0, S.s, n, r, t, S.w.part[2], S.w.st);
+                hipLaunchKernelGGL(k_cgs_rr, dim3(1), dim3(256), 0, S.s, S.w.part[2], m, S.w.st);
+                if ((st = S.launched()) != MP_OK) return st;
+            }
+            continue;
+        }
+        if (h.done == RECURRENCE_MET) {
+            if ((st = S.true_residual(b, x, t, r, true)) != MP_OK) return st;
+            continue;
+        }
+        if (h.done == RESTART) {
+            hipLaunchKernelGGL(k_copy, dim3(S.vblocks), dim3(256), 0, S.s, 2 * n, r, rh);
+            hipLaunchKernelGGL(k_cgs_restart, dim3(1), dim3(64), 0, S.s, S.w.st);
+            if ((st = S.launched()) != MP_OK) return st;
+            continue;
+        }
+        status = h.done == CONFIRMED ? MP_OK : (h.done == BROKE_DOWN ? MP_ERR_BREAKDOWN : MP_ERR_NOT_CONVERGED);
+        break;
+    }
+    if ((st = S.true_residual(b, x, t, r, false)) != MP_OK) return st;
+    if ((st = S.read_state(&h)) != MP_OK) return st;
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    fill_info(h, status, secs, info);
+    if (status == MP_ERR_NOT_CONVERGED)
+        return fail(MP_ERR_NOT_CONVERGED, "mpkrylov_cgs: no convergence in %d iterations", h.iters);
+    if (status == MP_ERR_BREAKDOWN) return fail(MP_ERR_BREAKDOWN, "mpkrylov_cgs: breakdown at iteration %d", h.iters);
+    return MP_OK;
+}
+
 mp_status run_bicgstab(Solver &S, const double *b, double *x, const mp_solve_opts *o, mp_solve_info *info)
 {
     const auto t0 = std::chrono::steady_clock::now();
@@ -1758,15 +1980,16 @@ size_t solver_bytes(const mp_csr *A, const mp_solve_opts *o)
     return workspace_bytes(A->n_rows, f32);
 }
 
-// kind: 0 CG, 1 BiCGSTAB, 2 refinement, 3 refinement with a learned inner M (mvals)
+// kind: 0 CG, 1 BiCGSTAB, 2 refinement, 3 refinement with a learned inner M (mvals), 4 CGS
 mp_status solve_entry(const char *name, int kind, const mp_csr *A, const double *a, const double *mvals,
                       const double *b, double *x, const mp_solve_opts *opts, const mp_plan *plan, void *ws,
                       size_t ws_bytes, mp_solve_info *info, void *stream)
 {
     clear_error();
-    if (kind >= 2 && opts && opts->inner != MP_INNER_FP64 && opts->inner != MP_INNER_FP32)
+    const bool refine = kind == 2 || kind == 3;
+    if (refine && opts && opts->inner != MP_INNER_FP64 && opts->inner != MP_INNER_FP32)
         return fail(MP_ERR_INVALID_ARG, "%s: unknown inner precision %d", name, opts->inner);
-    const size_t need = kind >= 2 ? solver_bytes(A, opts) : (A ? workspace_bytes(A->n_rows) : 0);
+    const size_t need = refine ? solver_bytes(A, opts) : (A ? workspace_bytes(A->n_rows) : 0);
     mp_status st = check_solver_args(name, A, a, b, x, opts, plan, ws, ws_bytes, need, info, kind == 3);
     if (st != MP_OK) return st;
     if (kind == 3) {
@@ -1791,6 +2014,7 @@ mp_status solve_entry(const char *name, int kind, const mp_csr *A, const double 
     S.w = carve(ws, S.n);
     if (kind == 0) return run_cg(S, b, x, opts, info);
     if (kind == 1) return run_bicgstab(S, b, x, opts, info);
+    if (kind == 4) return run_cgs(S, b, x, opts, info);
     const double *mv = kind == 3 ? mvals : nullptr;
     return opts->inner == MP_INNER_FP32 ? run_ir_t<float>(S, b, x, mv, opts, info)
                                         : run_ir_t<double>(S, b, x, mv, opts, info);
@@ -1820,6 +2044,12 @@ mp_status mpkrylov_bicgstab(const mp_csr *A, const double *a, const double *b, d
                             const mp_plan *plan, void *ws, size_t ws_bytes, mp_solve_info *info, void *stream)
 {
     return mpk::solve_entry("mpkrylov_bicgstab", 1, A, a, nullptr, b, x, opts, plan, ws, ws_bytes, info, stream);
+}
+
+mp_status mpkrylov_cgs(const mp_csr *A, const double *a, const double *b, double *x, const mp_solve_opts *opts,
+                       const mp_plan *plan, void *ws, size_t ws_bytes, mp_solve_info *info, void *stream)
+{
+    return mpk::solve_entry("mpkrylov_cgs", 4, A, a, nullptr, b, x, opts, plan, ws, ws_bytes, info, stream);
 }
 
 mp_status mpkrylov_ir(const mp_csr *A, const double *a, const double *b, double *x, const mp_solve_opts *opts,
