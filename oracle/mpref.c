@@ -1245,3 +1245,151 @@ int oracle_cgs(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *co
     free(r); free(rh); free(u); free(p); free(q); free(v); free(uh); free(t); free(ph);
     return status;
 }
+
+/*
+ * GPBiCG in DD (Zhang's generalized product-type BiCG, Sec. 4.2's list), with right
+ * Jacobi preconditioning as oracle_bicgstab: every product with A is a product with
+ * A M, and x collects M times the y-space corrections.  Shadow r~ = r at the start and
+ * after each restart.  One step:
+ *   rho = (r~, r) (breakdown when 0 or not finite);
+ *   first step after a (re)start: p = r; later steps: beta = (alpha'/zeta')(rho/rho'),
+ *     p = r + beta (p - u), w = c' + beta q'  (primes: the previous step's values);
+ *   q = A M p; sigma = (r~, q) (breakdown when 0 or not finite); alpha = rho / sigma;
+ *   t = r - alpha q; later steps y = t' - t - alpha w;
+ *   half step: when (t, t) meets the tolerance, x += M (alpha p), r = t, and the
+ *     next step starts fresh (as BiCGSTAB's s test);
+ *   c = A M t;
+ *   first step: zeta = (c, t) / (c, c), eta = 0 (breakdown when (c, c) is 0);
+ *   later steps, with d = (c,c)(y,y) - (y,c)^2 (breakdown when 0):
+ *     zeta = ((y,y)(c,t) - (y,t)(y,c)) / d,  eta = ((c,c)(y,t) - (y,c)(c,t)) / d;
+ *   breakdown when zeta is 0 or zeta / eta are not finite;
+ *   u = zeta q + eta (t' - r + beta u)       [first step: u = zeta q]
+ *   z = zeta r + eta z - alpha u             [first step: z = zeta r - alpha u]
+ *   x += M (alpha p + z)
+ *   r = t - eta y - zeta c                   [first step: r = t - zeta c]
+ *   t' = t.
+ * Stop test, confirmation and restarts as oracle_cg; a step is counted when t is formed.
+ */
+int oracle_gpbicg(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx, const uint8_t *log2w,
+                  const double *a, const double *b, double *x, const double *minv, double rtol, int32_t max_iter,
+                  oracle_solve_info *info, double *hist)
+{
+    dd_mat M = {n, nnz, row_ptr, col_idx, log2w, a};
+    size_t vb = sizeof(double) * 2 * (size_t)n;
+    double *r = (double *)malloc(vb), *rh = (double *)malloc(vb), *p = (double *)malloc(vb);
+    double *q = (double *)malloc(vb), *t = (double *)malloc(vb), *c = (double *)malloc(vb);
+    double *y = (double *)malloc(vb), *u = (double *)malloc(vb), *z = (double *)malloc(vb);
+    double *w = (double *)malloc(vb), *tp = (double *)malloc(vb), *tmp = (double *)malloc(vb);
+    mpv zero = {{0.0, 0.0, 0.0, 0.0}};
+    mpv rho, rho_old = zero, beta = zero, sigma, alpha = zero, zeta = zero, eta = zero;
+    mpv rr, tt, cc, ct, yy, yc, yt, den, bb, tol2;
+    int64_t i;
+    int32_t k = 0;
+    int status = -5, fresh = 1;
+    memset(info, 0, sizeof(*info));
+    bb = dd_dot_vec(n, b, b);
+    tol2 = dd_mul_d(bb, rtol * rtol);
+    dd_residual(&M, b, x, tmp, r);
+    memcpy(rh, r, vb);
+    rr = dd_dot_vec(n, r, r);
+    if (hist) { hist[0] = rr.c[0]; hist[1] = rr.c[1]; }
+    for (;;) {
+        if (dd_le(rr, tol2)) {
+            dd_residual(&M, b, x, tmp, r);
+            rr = dd_dot_vec(n, r, r);
+            if (dd_le(rr, tol2)) { status = 0; break; }
+            info->restarts++;
+            memcpy(rh, r, vb);
+            fresh = 1;
+        }
+        if (k >= max_iter) break;
+        rho = dd_dot_vec(n, rh, r);
+        if (rho.c[0] == 0.0 || !isfinite(rho.c[0])) { status = -6; break; }
+        if (fresh) {
+            memcpy(p, r, vb);
+        } else {
+            beta = dd_mul(dd_div(alpha, zeta), dd_div(rho, rho_old));
+            for (i = 0; i < n; ++i) {
+                st2(p, n, i, dd_add(ld2(r, n, i), dd_mul(beta, dd_add(ld2(p, n, i), mp_neg(ld2(u, n, i))))));
+                st2(w, n, i, dd_add(ld2(c, n, i), dd_mul(beta, ld2(q, n, i))));
+            }
+        }
+        dd_precond(n, minv, p, tmp);
+        dd_spmv(&M, tmp, q);
+        sigma = dd_dot_vec(n, rh, q);
+        if (sigma.c[0] == 0.0 || !isfinite(sigma.c[0])) { status = -6; break; }
+        alpha = dd_div(rho, sigma);
+        for (i = 0; i < n; ++i) {
+            mpv ti = dd_add(ld2(r, n, i), mp_neg(dd_mul(alpha, ld2(q, n, i))));
+            st2(t, n, i, ti);
+            if (!fresh)
+                st2(y, n, i, dd_add(dd_add(ld2(tp, n, i), mp_neg(ti)), mp_neg(dd_mul(alpha, ld2(w, n, i)))));
+        }
+        tt = dd_dot_vec(n, t, t);
+        k++;
+        if (dd_le(tt, tol2)) {
+            for (i = 0; i < n; ++i) {
+                mpv d = dd_mul(alpha, ld2(p, n, i));
+                st2(x, n, i, dd_add(ld2(x, n, i), minv ? dd_mul_d(d, minv[i]) : d));
+            }
+            memcpy(r, t, vb);
+            rr = tt;
+            if (hist) { hist[2 * k] = rr.c[0]; hist[2 * k + 1] = rr.c[1]; }
+            rho_old = rho;
+            fresh = 1;
+            continue;
+        }
+        dd_precond(n, minv, t, tmp);
+        dd_spmv(&M, tmp, c);
+        cc = dd_dot_vec(n, c, c);
+        ct = dd_dot_vec(n, c, t);
+        if (fresh) {
+            if (cc.c[0] == 0.0 || !isfinite(cc.c[0])) { status = -6; break; }
+            zeta = dd_div(ct, cc);
+            eta = zero;
+        } else {
+            yy = dd_dot_vec(n, y, y);
+            yc = dd_dot_vec(n, y, c);
+            yt = dd_dot_vec(n, y, t);
+            den = dd_add(dd_mul(cc, yy), mp_neg(dd_mul(yc, yc)));
+            if (den.c[0] == 0.0 || !isfinite(den.c[0])) { status = -6; break; }
+            zeta = dd_div(dd_add(dd_mul(yy, ct), mp_neg(dd_mul(yt, yc))), den);
+            eta = dd_div(dd_add(dd_mul(cc, yt), mp_neg(dd_mul(yc, ct))), den);
+        }
+        if (zeta.c[0] == 0.0 || !isfinite(zeta.c[0]) || !isfinite(eta.c[0])) { status = -6; break; }
+        for (i = 0; i < n; ++i) {
+            mpv ri = ld2(r, n, i), ti = ld2(t, n, i), ui, zi, d;
+            if (fresh) {
+                ui = dd_mul(zeta, ld2(q, n, i));
+                zi = dd_add(dd_mul(zeta, ri), mp_neg(dd_mul(alpha, ui)));
+            } else {
+                mpv g = dd_add(dd_add(ld2(tp, n, i), mp_neg(ri)), dd_mul(beta, ld2(u, n, i)));
+                ui = dd_add(dd_mul(zeta, ld2(q, n, i)), dd_mul(eta, g));
+                zi = dd_add(dd_add(dd_mul(zeta, ri), dd_mul(eta, ld2(z, n, i))), mp_neg(dd_mul(alpha, ui)));
+            }
+            st2(u, n, i, ui);
+            st2(z, n, i, zi);
+            d = dd_add(dd_mul(alpha, ld2(p, n, i)), zi);
+            st2(x, n, i, dd_add(ld2(x, n, i), minv ? dd_mul_d(d, minv[i]) : d));
+            if (fresh)
+                ri = dd_add(ti, mp_neg(dd_mul(zeta, ld2(c, n, i))));
+            else
+                ri = dd_add(dd_add(ti, mp_neg(dd_mul(eta, ld2(y, n, i)))), mp_neg(dd_mul(zeta, ld2(c, n, i))));
+            st2(r, n, i, ri);
+            st2(tp, n, i, ti);
+        }
+        rr = dd_dot_vec(n, r, r);
+        if (hist) { hist[2 * k] = rr.c[0]; hist[2 * k + 1] = rr.c[1]; }
+        if (!isfinite(rr.c[0])) { status = -6; break; }
+        rho_old = rho;
+        fresh = 0;
+    }
+    dd_residual(&M, b, x, tmp, r);
+    rr = dd_dot_vec(n, r, r);
+    info->status = status;
+    info->iters = k;
+    info->rr_true[0] = rr.c[0]; info->rr_true[1] = rr.c[1];
+    info->bb[0] = bb.c[0]; info->bb[1] = bb.c[1];
+    free(r); free(rh); free(p); free(q); free(t); free(c); free(y); free(u); free(z); free(w); free(tp); free(tmp);
+    return status;
+}

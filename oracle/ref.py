@@ -182,7 +182,7 @@ def _krylov_sigs():
     L.oracle_dd_dot.argtypes = [i64, P, P, P]
     L.oracle_dd_div.argtypes = [P, P, P]
     L.oracle_jacobi_minv.argtypes = [i64, P, P, P, P]
-    for f in (L.oracle_cg, L.oracle_bicgstab, L.oracle_cgs):
+    for f in (L.oracle_cg, L.oracle_bicgstab, L.oracle_cgs, L.oracle_gpbicg):
         f.argtypes = [i64, i64, P, P, P, P, P, P, P, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(SolveInfo), P]
         f.restype = ctypes.c_int
     L.oracle_bicg.argtypes = [i64, i64, P, P, P, P, P, P, P, P, P, P, P, ctypes.c_double, ctypes.c_int32,
@@ -255,6 +255,12 @@ def cgs(row_ptr, col_idx, a, b, x0=None, precond="jacobi", rtol=1e-28, max_iter=
         history=False):
     """DD CGS (oracle).  Returns (x, info dict)."""
     return _solve("oracle_cgs", row_ptr, col_idx, a, b, x0, precond, rtol, max_iter, log2w, history)
+
+
+def gpbicg(row_ptr, col_idx, a, b, x0=None, precond="jacobi", rtol=1e-28, max_iter=10000, log2w=None,
+           history=False):
+    """DD GPBiCG (oracle).  Returns (x, info dict)."""
+    return _solve("oracle_gpbicg", row_ptr, col_idx, a, b, x0, precond, rtol, max_iter, log2w, history)
 
 
 def bicg(row_ptr, col_idx, a, b, x0=None, precond="jacobi", rtol=1e-28, max_iter=10000, log2w=None,

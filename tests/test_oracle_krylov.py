@@ -10,6 +10,13 @@
   1e-28; the returned x's residual is certified with exact rational arithmetic.
 * Breakdown (NaN right-hand side) and iteration limit are reported; a warm start
   at the solution stops at once.
+* GPBiCG: terminates within k steps on diagonal matrices with k distinct eigenvalues;
+  certified 1e-28 on the non-symmetric band; its first step equals BiCGSTAB's to DD
+  rounding (eta = 0); each step's recurrence residual equals the exact residual of
+  that step's iterate to DD rounding.  Each of eleven plausible mistakes in its
+  recursions (a dropped eta term in u, z or r, a sign in y, eta, w or p, beta without
+  alpha/zeta, swapped dots in zeta, x without the preconditioner) fails three or more
+  of these pins.
 """
 from fractions import Fraction
 
@@ -192,3 +199,83 @@ def test_cgs_k_distinct_eigenvalues_and_nonsymmetric_certified():
     assert ref.cgs(row_ptr, col_idx, a, bad, rtol=1e-28, max_iter=50)[1]["status"] == -6
     _, info = ref.cgs(row_ptr, col_idx, a, b, rtol=1e-28, max_iter=3)
     assert info["status"] == -5 and info["iters"] == 3
+
+
+def test_gpbicg_k_distinct_eigenvalues():
+    """GPBiCG's residual polynomial carries the BiCG polynomial as a factor, so on a
+    diagonal matrix with k distinct eigenvalues it terminates within k steps."""
+    n = 400
+    for eig in (np.array([1.0, 2.0, 3.0, 5.0, 8.0]), np.array([0.5, 4.0]), np.array([1.0, 1.5, 2.0, 7.0, 9.0, 12.0])):
+        row_ptr = np.arange(n + 1, dtype=np.int32)
+        col_idx = np.arange(n, dtype=np.int32)
+        a = np.zeros((2, n))
+        a[0] = eig[np.arange(n) % eig.size]
+        b = random_mp(n, 2, np.random.default_rng(eig.size))
+        _, info = ref.gpbicg(row_ptr, col_idx, a, b, precond="none", rtol=1e-28, max_iter=50)
+        assert info["status"] == 0 and info["iters"] <= eig.size, (eig, info)
+
+
+@pytest.mark.parametrize("precond", ["none", "jacobi"])
+def test_gpbicg_nonsymmetric_certified(precond):
+    row_ptr, col_idx, a = banded_nonsymmetric(n=200, seed=5)
+    v = sqrt2_vector(200, 2)
+    b = ref.spmv(2, row_ptr, col_idx, a, v)
+    x, info = ref.gpbicg(row_ptr, col_idx, a, b, precond=precond, rtol=1e-28, max_iter=20000)
+    assert info["status"] == 0
+    ok, rel = _certify(row_ptr, col_idx, a, b, x, 1e-28)
+    assert ok, rel
+
+
+def test_gpbicg_first_step_is_bicgstab():
+    """With eta = 0 (the first step) GPBiCG's step is BiCGSTAB's: zeta is BiCGSTAB's
+    omega and alpha p + z = alpha p + omega s, so the first iterates agree to DD
+    rounding."""
+    row_ptr, col_idx, a = banded_nonsymmetric(n=200, seed=6)
+    b = random_mp(200, 2, np.random.default_rng(6))
+    for precond in ("none", "jacobi"):
+        xg, ig = ref.gpbicg(row_ptr, col_idx, a, b, precond=precond, rtol=1e-28, max_iter=1, history=True)
+        xb, ib = ref.bicgstab(row_ptr, col_idx, a, b, precond=precond, rtol=1e-28, max_iter=1, history=True)
+        assert ig["iters"] == ib["iters"] == 1
+        xs = np.abs(xb[0]).max()
+        assert np.abs((xg[0] - xb[0]) + (xg[1] - xb[1])).max() <= 1e-28 * xs
+        rg, rb = _fr(ig["history"][1]), _fr(ib["history"][1])
+        assert abs(rg - rb) <= Fraction(1, 10 ** 26) * rb
+
+
+def test_gpbicg_recurrence_tracks_true_residual():
+    """Every step's recurrence residual equals the true residual of that step's iterate
+    (exact rational b - A x) to DD rounding: x (through u and z) and r (through y, w
+    and c) are updated consistently.  A dropped or mis-signed term in either
+    recursion separates the two by the size of the residual itself."""
+    row_ptr, col_idx, a = banded_nonsymmetric(n=120, seed=7)
+    n = 120
+    b = random_mp(n, 2, np.random.default_rng(7))
+    bb = sum(_fr(b[:, i]) ** 2 for i in range(n))
+    for precond in ("none", "jacobi"):
+        _, full = ref.gpbicg(row_ptr, col_idx, a, b, precond=precond, rtol=1e-28, max_iter=12, history=True)
+        hist = full["history"]
+        assert full["iters"] >= 8
+        for k in range(1, 9):
+            xk, ik = ref.gpbicg(row_ptr, col_idx, a, b, precond=precond, rtol=1e-28, max_iter=k)
+            assert ik["iters"] == k
+            ys, _ = exact.exact_row_products(row_ptr, col_idx, a, xk)
+            scale = Fraction(1, 2 ** (-exact.E_SCALE))
+            rr_true = sum((_fr(b[:, i]) - ys[i] * scale) ** 2 for i in range(n))
+            rr_rec = _fr(hist[k])
+            gap = abs(float(rr_true) ** 0.5 - float(rr_rec) ** 0.5)
+            assert gap <= 1e-24 * float(bb) ** 0.5, (precond, k, gap, float(rr_rec) ** 0.5)
+            assert rr_rec < Fraction(1, 4) * bb or k < 3
+
+
+def test_gpbicg_failures_and_warm_start():
+    row_ptr, col_idx, a = banded_nonsymmetric(n=200, seed=5)
+    b = random_mp(200, 2, np.random.default_rng(9))
+    bad = b.copy()
+    bad[0, 5] = np.nan
+    assert ref.gpbicg(row_ptr, col_idx, a, bad, rtol=1e-28, max_iter=50)[1]["status"] == -6
+    _, info = ref.gpbicg(row_ptr, col_idx, a, b, rtol=1e-28, max_iter=3)
+    assert info["status"] == -5 and info["iters"] == 3
+    x, info = ref.gpbicg(row_ptr, col_idx, a, b, rtol=1e-24, max_iter=5000)
+    assert info["status"] == 0
+    x2, info2 = ref.gpbicg(row_ptr, col_idx, a, b, x0=x, rtol=1e-24, max_iter=5000)
+    assert info2["iters"] == 0 and np.array_equal(x, x2)
