@@ -285,6 +285,29 @@ mp_status mpkrylov_cgs(const mp_csr *A, const double *a, const double *b, double
                        const mp_plan *plan, void *ws, size_t ws_bytes, mp_solve_info *info, void *stream);
 
 /*
+ * DD GPBiCG (Zhang's generalized product-type method based on BiCG; Sec. 4.2's list)
+ * with right Jacobi preconditioning (opts.precond; every product with A is one with
+ * A M and x collects M times the corrections, so r is the residual of A x = b).
+ * Shadow r~ = r at the start and after a restart.  Step: rho = (r~, r) (breakdown if
+ * 0 or not finite); the first step after a (re)start takes p = r, later ones
+ * beta = (alpha'/zeta')(rho/rho'), p = r + beta (p - u), w = c' + beta q' (primes:
+ * previous step); q = A M p, sigma = (r~, q) (breakdown if 0 or not finite),
+ * alpha = rho / sigma, t = r - alpha q, later steps y = t' - t - alpha w.  If
+ * (t, t) meets the tolerance: x += M (alpha p), r = t, confirm, and the next step is
+ * fresh.  Else c = A M t; first step zeta = (c,t)/(c,c), eta = 0; later steps
+ * d = (c,c)(y,y) - (y,c)^2, zeta = ((y,y)(c,t) - (y,t)(y,c))/d,
+ * eta = ((c,c)(y,t) - (y,c)(c,t))/d (breakdown if (c,c) or d is 0, zeta is 0, or zeta
+ * or eta is not finite); u = zeta q + eta (t' - r + beta u), z = zeta r + eta z -
+ * alpha u (first step: u = zeta q, z = zeta r - alpha u), x += M (alpha p + z),
+ * r = t - eta y - zeta c (first step: t - zeta c), t' = t.  Two SpMVs per step; a
+ * step is counted when t is formed.  Stop test, confirmation, restarts and arguments
+ * as mpkrylov_cg (A need not be symmetric).
+ */
+mp_status mpkrylov_gpbicg(const mp_csr *A, const double *a, const double *b, double *x,
+                          const mp_solve_opts *opts, const mp_plan *plan, void *ws, size_t ws_bytes,
+                          mp_solve_info *info, void *stream);
+
+/*
  * DD BiCG (Fletcher's biconjugate gradients; Sec. 4.2 lists BiCG among the product-
  * type Krylov methods, and its SpTMV is what slows it down there).  A^T is passed
  * explicitly (At, at: e.g. from mp_csr_transpose, 2*nnz DD values) with an optional

@@ -81,7 +81,7 @@ for _name in ("mpspmv_csr_dd_complex", "mpspmv_csr_td_complex", "mpspmv_csr_qd_c
 
 _SIGS["mpkrylov_workspace_bytes"] = ([_CSR, ctypes.POINTER(mp_solve_opts), ctypes.POINTER(ctypes.c_size_t)],
                                      ctypes.c_int)
-for _name in ("mpkrylov_cg", "mpkrylov_bicgstab", "mpkrylov_cgs", "mpkrylov_ir"):
+for _name in ("mpkrylov_cg", "mpkrylov_bicgstab", "mpkrylov_cgs", "mpkrylov_gpbicg", "mpkrylov_ir"):
     _SIGS[_name] = ([_CSR, _P, _P, _P, ctypes.POINTER(mp_solve_opts), _P, _P, ctypes.c_size_t,
                      ctypes.POINTER(mp_solve_info), _P], ctypes.c_int)
 
@@ -383,6 +383,7 @@ def _solver(name):
 mpkrylov_cg = _solver("mpkrylov_cg")
 mpkrylov_bicgstab = _solver("mpkrylov_bicgstab")
 mpkrylov_cgs = _solver("mpkrylov_cgs")
+mpkrylov_gpbicg = _solver("mpkrylov_gpbicg")
 mpkrylov_ir = _solver("mpkrylov_ir")
 
 

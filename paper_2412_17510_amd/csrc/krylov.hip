@@ -36,7 +36,7 @@ constexpr int kPerThread = kPerLane / kGroups;     // elements of a lane per thr
 enum : int32_t { RUN = 0, RECURRENCE_MET = 1, BROKE_DOWN = 2, ITER_LIMIT = 3, CONFIRMED = 4, RESTART = 5 };
 
 struct KState {
-    dd_t rho, rho_old, rr, bb, tol2, pq, alpha, beta, omega, rv, ss, ts, tt, rr_true;
+    dd_t rho, rho_old, rr, bb, tol2, pq, alpha, beta, omega, rv, ss, ts, tt, rr_true, zeta, eta;
     int32_t done;
     int32_t iters;
     int32_t max_iter;
@@ -712,6 +712,297 @@ __global__ __launch_bounds__(256) void k_cgs_rr(const dd_t *__restrict__ prr, in
 }
 
 // ---------------------------------------------------------------------------
+// GPBiCG (Zhang), right Jacobi preconditioning.  Vectors: r, r~, p, q = A M p,
+// t = r - alpha q, c = A M t, y, u, z, w, t' (the previous t), and one scratch for
+// M p / M t.  A step is counted when t is formed; a t that meets the tolerance ends
+// the step early (x += M alpha p, r = t) and the next step is fresh.
+// ---------------------------------------------------------------------------
+
+// rho = (r~, r): breakdown when 0 or not finite; later steps beta = (alpha/zeta)(rho/rho_old)
+__global__ __launch_bounds__(256) void k_gp_rho(const dd_t *__restrict__ prho, int m, KState *__restrict__ st)
+{
+    __shared__ dd_t P[kMaxChunks];
+    if (st->done != RUN) return;
+    const dd_t rho = pair_tree(prho, m, P);
+    if (threadIdx.x == 0) {
+        if (rho.c[0] == 0.0 || !dd_finite(rho)) {
+            st->done = BROKE_DOWN;
+            return;
+        }
+        st->rho = rho;
+        if (!st->fresh) st->beta = dd_mul(dd_div(st->alpha, st->zeta), dd_div(rho, st->rho_old));
+    }
+}
+
+// fresh: p = r; else p = r + beta (p - u), w = c + beta q; tmp = M p
+__global__ __launch_bounds__(256) void k_gp_p(int64_t n, const double *__restrict__ r, double *__restrict__ p,
+                                              const double *__restrict__ u, const double *__restrict__ c,
+                                              const double *__restrict__ q, double *__restrict__ w,
+                                              double *__restrict__ tmp, const double *__restrict__ minv,
+                                              const KState *__restrict__ st)
+{
+    if (st->done != RUN) return;
+    const bool fresh = st->fresh != 0;
+    const dd_t beta = st->beta;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const dd_t ri = ldd(r, n, i);
+        dd_t pi;
+        if (fresh) {
+            pi = ri;
+        } else {
+            const dd_t ui = ldd(u, n, i), ci = ldd(c, n, i), qi = ldd(q, n, i), po = ldd(p, n, i);
+            pi = dd_add(ri, dd_mul(beta, dd_sub(po, ui)));
+            sdd(w, n, i, dd_add(ci, dd_mul(beta, qi)));
+        }
+        sdd(p, n, i, pi);
+        sdd(tmp, n, i, minv ? dd_mul_d(pi, minv[i]) : pi);
+    }
+}
+
+// sigma = (r~, q): breakdown when 0 or not finite; alpha = rho / sigma
+__global__ __launch_bounds__(256) void k_gp_alpha(const dd_t *__restrict__ psig, int m, KState *__restrict__ st)
+{
+    __shared__ dd_t P[kMaxChunks];
+    if (st->done != RUN) return;
+    const dd_t sigma = pair_tree(psig, m, P);
+    if (threadIdx.x == 0) {
+        st->pq = sigma;
+        if (sigma.c[0] == 0.0 || !dd_finite(sigma))
+            st->done = BROKE_DOWN;
+        else
+            st->alpha = dd_div(st->rho, sigma);
+    }
+}
+
+// t = r - alpha q; later steps y = (t' - t) - alpha w; tmp = M t; chunk sums of (t, t)
+__global__ __launch_bounds__(256) void k_gp_t(int64_t n, const double *__restrict__ r, const double *__restrict__ q,
+                                              const double *__restrict__ tp, const double *__restrict__ w,
+                                              double *__restrict__ t, double *__restrict__ y,
+                                              double *__restrict__ tmp, const double *__restrict__ minv,
+                                              dd_t *__restrict__ ptt, const KState *__restrict__ st)
+{
+    __shared__ dd_t lds[kDotLanes];
+    if (st->done != RUN) return;
+    const bool fresh = st->fresh != 0;
+    const dd_t alpha = st->alpha;
+    const int c = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int64_t base = (int64_t)c * kDotChunk;
+    const int64_t end = (n - base) < kDotChunk ? n : base + kDotChunk;
+    const int used = chunk_used(n, c);
+    dd_t acc = dd_zero();
+    bool first = true;
+    for (int64_t k = base + tid; k < end; k += kDotLanes) {
+        const dd_t tk = dd_sub(ldd(r, n, k), dd_mul(alpha, ldd(q, n, k)));
+        sdd(t, n, k, tk);
+        if (!fresh) sdd(y, n, k, dd_sub(dd_sub(ldd(tp, n, k), tk), dd_mul(alpha, ldd(w, n, k))));
+        sdd(tmp, n, k, minv ? dd_mul_d(tk, minv[k]) : tk);
+        const dd_t p2 = dd_mul(tk, tk);
+        acc = first ? p2 : dd_add(acc, p2);
+        first = false;
+    }
+    const dd_t sum = chunk_fold(acc, used, lds);
+    if (tid == 0) ptt[c] = sum;
+}
+
+// tt = (t, t); the step is counted; half-step test
+__global__ __launch_bounds__(256) void k_gp_tt(const dd_t *__restrict__ ptt, int m, KState *__restrict__ st)
+{
+    __shared__ dd_t P[kMaxChunks];
+    if (st->done != RUN) return;
+    const dd_t tt = pair_tree(ptt, m, P);
+    if (threadIdx.x == 0) {
+        st->tt = tt;
+        st->iters += 1;
+        st->half = dd_le(tt, st->tol2) ? 1 : 0;
+    }
+}
+
+// half step met the tolerance: x += M (alpha p); r = t
+__global__ __launch_bounds__(256) void k_gp_half(int64_t n, double *__restrict__ x, double *__restrict__ r,
+                                                 const double *__restrict__ p, const double *__restrict__ t,
+                                                 const double *__restrict__ minv, const KState *__restrict__ st)
+{
+    if (st->done != RUN || !st->half) return;
+    const dd_t alpha = st->alpha;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const dd_t d = dd_mul(alpha, ldd(p, n, i));
+        sdd(x, n, i, dd_add(ldd(x, n, i), minv ? dd_mul_d(d, minv[i]) : d));
+        sdd(r, n, i, ldd(t, n, i));
+    }
+}
+
+__global__ __launch_bounds__(64) void k_gp_half_final(KState *__restrict__ st)
+{
+    if (threadIdx.x != 0 || st->done != RUN || !st->half) return;
+    st->rr = st->tt;
+    st->rho_old = st->rho;
+    st->fresh = 1;
+    st->half = 0;
+    st->done = RECURRENCE_MET;
+}
+
+// chunk sums of (c, c), (c, t) and, after the first step, (y, y), (y, c), (y, t)
+__global__ __launch_bounds__(kChunkThreads) void k_gp_dots(int64_t n, const double *__restrict__ cv,
+                                                           const double *__restrict__ t, const double *__restrict__ y,
+                                                           dd_t *__restrict__ pcc, dd_t *__restrict__ pct,
+                                                           dd_t *__restrict__ pyy, dd_t *__restrict__ pyc,
+                                                           dd_t *__restrict__ pyt, const KState *__restrict__ st)
+{
+    __shared__ dd_t chain[5][kDotLanes];
+    if (st->done != RUN) return;
+    const bool fresh = st->fresh != 0;
+    const int c = blockIdx.x;
+    const int nv = thread_valid(n, c);
+    dd_t pr[5][kPerThread];
+#pragma unroll
+    for (int jj = 0; jj < kPerThread; ++jj) {
+        if (jj < nv) {
+            const int64_t k = thread_elem(c, jj);
+            const dd_t ck = ldd(cv, n, k), tk = ldd(t, n, k);
+            pr[0][jj] = dd_mul(ck, ck);
+            pr[1][jj] = dd_mul(ck, tk);
+            if (!fresh) {
+                const dd_t yk = ldd(y, n, k);
+                pr[2][jj] = dd_mul(yk, yk);
+                pr[3][jj] = dd_mul(yk, ck);
+                pr[4][jj] = dd_mul(yk, tk);
+            }
+        }
+    }
+    const int used = chunk_used(n, c);
+    dd_t *outs[5] = {pcc, pct, pyy, pyc, pyt};
+    if (fresh) {
+        lane_chain<dd_t, 2>(reinterpret_cast<const dd_t(&)[2][kPerThread]>(pr[0]), nv, chain);
+        for (int q = 0; q < 2; ++q) {
+            const dd_t sq = chain_fold(chain[q], used);
+            if (threadIdx.x == 0) outs[q][c] = sq;
+        }
+    } else {
+        lane_chain<dd_t, 5>(pr, nv, chain);
+        for (int q = 0; q < 5; ++q) {
+            const dd_t sq = chain_fold(chain[q], used);
+            if (threadIdx.x == 0) outs[q][c] = sq;
+        }
+    }
+}
+
+// zeta and eta: first step zeta = (c,t)/(c,c), eta = 0; later steps from the 2x2
+// normal equations with d = (c,c)(y,y) - (y,c)^2; breakdown on a zero (c,c) or d, a
+// zero zeta or a non-finite zeta / eta
+__global__ __launch_bounds__(256) void k_gp_zeta(const dd_t *__restrict__ pcc, const dd_t *__restrict__ pct,
+                                                 const dd_t *__restrict__ pyy, const dd_t *__restrict__ pyc,
+                                                 const dd_t *__restrict__ pyt, int m, KState *__restrict__ st)
+{
+    __shared__ dd_t P[kMaxChunks];
+    if (st->done != RUN) return;
+    const bool fresh = st->fresh != 0;
+    const dd_t cc = pair_tree(pcc, m, P);
+    const dd_t ct = pair_tree(pct, m, P);
+    dd_t yy = dd_zero(), yc = dd_zero(), yt = dd_zero();
+    if (!fresh) {
+        yy = pair_tree(pyy, m, P);
+        yc = pair_tree(pyc, m, P);
+        yt = pair_tree(pyt, m, P);
+    }
+    if (threadIdx.x == 0) {
+        dd_t zeta, eta;
+        if (fresh) {
+            if (cc.c[0] == 0.0 || !dd_finite(cc)) {
+                st->done = BROKE_DOWN;
+                return;
+            }
+            zeta = dd_div(ct, cc);
+            eta = dd_zero();
+        } else {
+            const dd_t den = dd_sub(dd_mul(cc, yy), dd_mul(yc, yc));
+            if (den.c[0] == 0.0 || !dd_finite(den)) {
+                st->done = BROKE_DOWN;
+                return;
+            }
+            zeta = dd_div(dd_sub(dd_mul(yy, ct), dd_mul(yt, yc)), den);
+            eta = dd_div(dd_sub(dd_mul(cc, yt), dd_mul(yc, ct)), den);
+        }
+        if (zeta.c[0] == 0.0 || !dd_finite(zeta) || !dd_finite(eta)) {
+            st->done = BROKE_DOWN;
+            return;
+        }
+        st->zeta = zeta;
+        st->eta = eta;
+    }
+}
+
+// u = zeta q + eta (t' - r + beta u), z = zeta r + eta z - alpha u (first step:
+// u = zeta q, z = zeta r - alpha u); x += M (alpha p + z); r = t - eta y - zeta c
+// (first step: r = t - zeta c); t' = t; chunk sums of (r, r)
+__global__ __launch_bounds__(256) void k_gp_update(int64_t n, double *__restrict__ x, double *__restrict__ r,
+                                                   const double *__restrict__ p, const double *__restrict__ q,
+                                                   const double *__restrict__ t, const double *__restrict__ cv,
+                                                   const double *__restrict__ y, double *__restrict__ u,
+                                                   double *__restrict__ z, double *__restrict__ tp,
+                                                   const double *__restrict__ minv, dd_t *__restrict__ prr,
+                                                   const KState *__restrict__ st)
+{
+    __shared__ dd_t lds[kDotLanes];
+    if (st->done != RUN) return;
+    const bool fresh = st->fresh != 0;
+    const dd_t alpha = st->alpha, beta = st->beta, zeta = st->zeta, eta = st->eta;
+    const int c = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int64_t base = (int64_t)c * kDotChunk;
+    const int64_t end = (n - base) < kDotChunk ? n : base + kDotChunk;
+    const int used = chunk_used(n, c);
+    dd_t acc = dd_zero();
+    bool first = true;
+    for (int64_t k = base + tid; k < end; k += kDotLanes) {
+        const dd_t rk = ldd(r, n, k), tk = ldd(t, n, k), qk = ldd(q, n, k), ck = ldd(cv, n, k);
+        dd_t uk, zk, rn;
+        if (fresh) {
+            uk = dd_mul(zeta, qk);
+            zk = dd_sub(dd_mul(zeta, rk), dd_mul(alpha, uk));
+            rn = dd_sub(tk, dd_mul(zeta, ck));
+        } else {
+            const dd_t g = dd_add(dd_sub(ldd(tp, n, k), rk), dd_mul(beta, ldd(u, n, k)));
+            uk = dd_add(dd_mul(zeta, qk), dd_mul(eta, g));
+            zk = dd_sub(dd_add(dd_mul(zeta, rk), dd_mul(eta, ldd(z, n, k))), dd_mul(alpha, uk));
+            rn = dd_sub(dd_sub(tk, dd_mul(eta, ldd(y, n, k))), dd_mul(zeta, ck));
+        }
+        sdd(u, n, k, uk);
+        sdd(z, n, k, zk);
+        const dd_t d = dd_add(dd_mul(alpha, ldd(p, n, k)), zk);
+        sdd(x, n, k, dd_add(ldd(x, n, k), minv ? dd_mul_d(d, minv[k]) : d));
+        sdd(r, n, k, rn);
+        sdd(tp, n, k, tk);
+        const dd_t p2 = dd_mul(rn, rn);
+        acc = first ? p2 : dd_add(acc, p2);
+        first = false;
+    }
+    const dd_t sum = chunk_fold(acc, used, lds);
+    if (tid == 0) prr[c] = sum;
+}
+
+// rr = (r, r): breakdown when not finite; the next step is not fresh; stop tests
+__global__ __launch_bounds__(256) void k_gp_rr(const dd_t *__restrict__ prr, int m, KState *__restrict__ st)
+{
+    __shared__ dd_t P[kMaxChunks];
+    if (st->done != RUN) return;
+    const dd_t rr = pair_tree(prr, m, P);
+    if (threadIdx.x == 0) {
+        st->rr = rr;
+        if (!dd_finite(rr)) {
+            st->done = BROKE_DOWN;
+            return;
+        }
+        st->rho_old = st->rho;
+        st->fresh = 0;
+        if (dd_le(rr, st->tol2))
+            st->done = RECURRENCE_MET;
+        else if (st->iters >= st->max_iter)
+            st->done = ITER_LIMIT;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // BiCGSTAB
 // ---------------------------------------------------------------------------
 
@@ -1353,12 +1644,15 @@ __global__ __launch_bounds__(256) void k_ir_norms(const dd_t *__restrict__ pbb, 
 // host driver
 // ---------------------------------------------------------------------------
 
+constexpr int kVecs = 12;   // DD work vectors (GPBiCG uses all of them)
+constexpr int kParts = 6;   // chunk-sum arrays
+
 struct Workspace {
     KState *st;
     KState *st2;   // second state buffer of the CG step (double-buffered)
     double *minv;
-    double *v[9];
-    dd_t *part[3];
+    double *v[kVecs];
+    dd_t *part[kParts];
     void *inner;   // InState<T>
     float *a32;
 };
@@ -1369,8 +1663,8 @@ size_t workspace_bytes(int64_t n, int64_t nnz_f32 = 0)
 {
     size_t b = 2 * align256(sizeof(KState));
     b += align256(sizeof(double) * (size_t)n);
-    b += 9 * align256(sizeof(double) * 2 * (size_t)n);
-    b += 3 * align256(sizeof(dd_t) * kMaxChunks);
+    b += kVecs * align256(sizeof(double) * 2 * (size_t)n);
+    b += kParts * align256(sizeof(dd_t) * kMaxChunks);
     b += 256;                                         // inner-solver state
     b += align256(sizeof(float) * (size_t)nnz_f32);   // binary32 copies of hi(A) (and of M)
     return b;
@@ -1386,11 +1680,11 @@ Workspace carve(void *ws, int64_t n)
     p += align256(sizeof(KState));
     w.minv = reinterpret_cast<double *>(p);
     p += align256(sizeof(double) * (size_t)n);
-    for (int i = 0; i < 9; ++i) {
+    for (int i = 0; i < kVecs; ++i) {
         w.v[i] = reinterpret_cast<double *>(p);
         p += align256(sizeof(double) * 2 * (size_t)n);
     }
-    for (int i = 0; i < 3; ++i) {
+    for (int i = 0; i < kParts; ++i) {
         w.part[i] = reinterpret_cast<dd_t *>(p);
         p += align256(sizeof(dd_t) * kMaxChunks);
     }
@@ -1727,6 +2021,84 @@ mp_status run_cgs(Solver &S, const double *b, double *x, const mp_solve_opts *o,
     return MP_OK;
 }
 
+mp_status run_gpbicg(Solver &S, const double *b, double *x, const mp_solve_opts *o, mp_solve_info *info)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    const int64_t n = S.n;
+    const int m = S.m;
+    double *r = S.w.v[0], *rh = S.w.v[1], *p = S.w.v[2], *q = S.w.v[3], *t = S.w.v[4], *c = S.w.v[5];
+    double *y = S.w.v[6], *u = S.w.v[7], *z = S.w.v[8], *w = S.w.v[9], *tp = S.w.v[10], *tmp = S.w.v[11];
+    dd_t **P = S.w.part;
+    const double *minv = o->precond == MP_PRECOND_JACOBI ? S.w.minv : nullptr;
+    const int every = o->check_every > 0 ? o->check_every : 32;
+    mp_status st = MP_OK;
+    KState h;
+    std::memset(&h, 0, sizeof(h));
+    MP_HIP_TRY(hipMemsetAsync(S.w.st, 0, sizeof(KState), S.s));
+    if (minv) {
+        hipLaunchKernelGGL(k_jacobi_minv, dim3(S.vblocks), dim3(256), 0, S.s, n, S.A->row_ptr, S.A->col_idx, S.a,
+                           S.w.minv);
+        if ((st = S.launched()) != MP_OK) return st;
+    }
+    if ((st = S.residual(b, x, tmp, r)) != MP_OK) return st;
+    hipLaunchKernelGGL(k_copy, dim3(S.vblocks), dim3(256), 0, S.s, 2 * n, r, rh);
+    if ((st = S.launched()) != MP_OK) return st;
+    if ((st = S.dot2(b, b, r, r, P[0], P[1], nullptr)) != MP_OK) return st;
+    hipLaunchKernelGGL(k_cgs_init, dim3(1), dim3(256), 0, S.s, P[0], P[1], m, o->rtol * o->rtol, o->max_iter,
+                       S.w.st);
+    if ((st = S.launched()) != MP_OK) return st;
+    int status = MP_ERR_NOT_CONVERGED;
+    for (;;) {
+        if ((st = S.read_state(&h)) != MP_OK) return st;
+        if (h.done == RUN) {
+            for (int it = 0; it < every; ++it) {
+                if ((st = S.dot2(rh, r, nullptr, nullptr, P[0], nullptr, S.w.st)) != MP_OK) return st;
+                hipLaunchKernelGGL(k_gp_rho, dim3(1), dim3(256), 0, S.s, P[0], m, S.w.st);
+                hipLaunchKernelGGL(k_gp_p, dim3(S.vblocks), dim3(256), 0, S.s, n, r, p, u, c, q, w, tmp, minv, S.w.st);
+                if ((st = S.launched()) != MP_OK) return st;
+                if ((st = S.spmv(tmp, q)) != MP_OK) return st;
+                if ((st = S.dot2(rh, q, nullptr, nullptr, P[1], nullptr, S.w.st)) != MP_OK) return st;
+                hipLaunchKernelGGL(k_gp_alpha, dim3(1), dim3(256), 0, S.s, P[1], m, S.w.st);
+                hipLaunchKernelGGL(k_gp_t, dim3(m), dim3(256), 0, S.s, n, r, q, tp, w, t, y, tmp, minv, P[2], S.w.st);
+                hipLaunchKernelGGL(k_gp_tt, dim3(1), dim3(256), 0, S.s, P[2], m, S.w.st);
+                hipLaunchKernelGGL(k_gp_half, dim3(S.vblocks), dim3(256), 0, S.s, n, x, r, p, t, minv, S.w.st);
+                hipLaunchKernelGGL(k_gp_half_final, dim3(1), dim3(64), 0, S.s, S.w.st);
+                if ((st = S.launched()) != MP_OK) return st;
+                if ((st = S.spmv(tmp, c)) != MP_OK) return st;
+                hipLaunchKernelGGL(k_gp_dots, dim3(m), dim3(kChunkThreads), 0, S.s, n, c, t, y, P[0], P[1], P[2], P[3],
+                                   P[4], S.w.st);
+                hipLaunchKernelGGL(k_gp_zeta, dim3(1), dim3(256), 0, S.s, P[0], P[1], P[2], P[3], P[4], m, S.w.st);
+                hipLaunchKernelGGL(k_gp_update, dim3(m), dim3(256), 0, S.s, n, x, r, p, q, t, c, y, u, z, tp, minv,
+                                   P[5], S.w.st);
+                hipLaunchKernelGGL(k_gp_rr, dim3(1), dim3(256), 0, S.s, P[5], m, S.w.st);
+                if ((st = S.launched()) != MP_OK) return st;
+            }
+            continue;
+        }
+        if (h.done == RECURRENCE_MET) {
+            if ((st = S.true_residual(b, x, tmp, r, true)) != MP_OK) return st;
+            continue;
+        }
+        if (h.done == RESTART) {
+            hipLaunchKernelGGL(k_copy, dim3(S.vblocks), dim3(256), 0, S.s, 2 * n, r, rh);
+            hipLaunchKernelGGL(k_cgs_restart, dim3(1), dim3(64), 0, S.s, S.w.st);
+            if ((st = S.launched()) != MP_OK) return st;
+            continue;
+        }
+        status = h.done == CONFIRMED ? MP_OK : (h.done == BROKE_DOWN ? MP_ERR_BREAKDOWN : MP_ERR_NOT_CONVERGED);
+        break;
+    }
+    if ((st = S.true_residual(b, x, tmp, r, false)) != MP_OK) return st;
+    if ((st = S.read_state(&h)) != MP_OK) return st;
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    fill_info(h, status, secs, info);
+    if (status == MP_ERR_NOT_CONVERGED)
+        return fail(MP_ERR_NOT_CONVERGED, "mpkrylov_gpbicg: no convergence in %d iterations", h.iters);
+    if (status == MP_ERR_BREAKDOWN)
+        return fail(MP_ERR_BREAKDOWN, "mpkrylov_gpbicg: breakdown at iteration %d", h.iters);
+    return MP_OK;
+}
+
 mp_status run_bicgstab(Solver &S, const double *b, double *x, const mp_solve_opts *o, mp_solve_info *info)
 {
     const auto t0 = std::chrono::steady_clock::now();
@@ -1980,7 +2352,7 @@ size_t solver_bytes(const mp_csr *A, const mp_solve_opts *o)
     return workspace_bytes(A->n_rows, f32);
 }
 
-// kind: 0 CG, 1 BiCGSTAB, 2 refinement, 3 refinement with a learned inner M (mvals), 4 CGS
+// kind: 0 CG, 1 BiCGSTAB, 2 refinement, 3 refinement with a learned inner M (mvals), 4 CGS, 5 GPBiCG
 mp_status solve_entry(const char *name, int kind, const mp_csr *A, const double *a, const double *mvals,
                       const double *b, double *x, const mp_solve_opts *opts, const mp_plan *plan, void *ws,
                       size_t ws_bytes, mp_solve_info *info, void *stream)
@@ -2015,6 +2387,7 @@ mp_status solve_entry(const char *name, int kind, const mp_csr *A, const double 
     if (kind == 0) return run_cg(S, b, x, opts, info);
     if (kind == 1) return run_bicgstab(S, b, x, opts, info);
     if (kind == 4) return run_cgs(S, b, x, opts, info);
+    if (kind == 5) return run_gpbicg(S, b, x, opts, info);
     const double *mv = kind == 3 ? mvals : nullptr;
     return opts->inner == MP_INNER_FP32 ? run_ir_t<float>(S, b, x, mv, opts, info)
                                         : run_ir_t<double>(S, b, x, mv, opts, info);
@@ -2050,6 +2423,12 @@ mp_status mpkrylov_cgs(const mp_csr *A, const double *a, const double *b, double
                        const mp_plan *plan, void *ws, size_t ws_bytes, mp_solve_info *info, void *stream)
 {
     return mpk::solve_entry("mpkrylov_cgs", 4, A, a, nullptr, b, x, opts, plan, ws, ws_bytes, info, stream);
+}
+
+mp_status mpkrylov_gpbicg(const mp_csr *A, const double *a, const double *b, double *x, const mp_solve_opts *opts,
+                          const mp_plan *plan, void *ws, size_t ws_bytes, mp_solve_info *info, void *stream)
+{
+    return mpk::solve_entry("mpkrylov_gpbicg", 5, A, a, nullptr, b, x, opts, plan, ws, ws_bytes, info, stream);
 }
 
 mp_status mpkrylov_ir(const mp_csr *A, const double *a, const double *b, double *x, const mp_solve_opts *opts,

@@ -1,4 +1,4 @@
-"""GPU parity of the DD Krylov solvers (C ABI mpkrylov_cg / mpkrylov_bicgstab) with the
+"""GPU parity of the DD Krylov solvers (C ABI mpkrylov_cg / _bicgstab / _bicg / _cgs / _gpbicg) with the
 CPU oracle: same status, iteration count and restarts, bitwise identical x and
 identical DD true residual, with and without Jacobi preconditioning and with a
 non-canonical plan order.  Cases: SPD 3D diffusion (to 1e-28, and a 100-iteration
@@ -173,3 +173,79 @@ def test_cgs_matches_oracle(mp):
                 assert io["status"] == 0
                 assert_same_values(host(x), xo, "%s cgs x" % name)
                 assert_same_values(ig["rr_true"], io["rr_true"], "%s cgs rr" % name)
+
+
+def test_gpbicg_matches_oracle(mp):
+    """GPU GPBiCG equals the oracle's GPBiCG bit for bit (status, counts, x, residual)
+    on a non-symmetric band and a diffusion matrix, with and without plans, and over
+    several chunks of 4096 rows (a ragged last chunk)."""
+    import torch
+    from workloads import banded_nonsymmetric, diffusion3d_7pt
+    for name, (row_ptr, col_idx, a) in (("band", banded_nonsymmetric(n=300, seed=6)),
+                                        ("diffusion", diffusion3d_7pt(m=6, sigma=1.0, seed=9)),
+                                        ("diffusion-chunks", diffusion3d_7pt(m=21, sigma=1.0, seed=10))):
+        n = row_ptr.size - 1
+        b = random_mp(n, 2, np.random.default_rng(13))
+        A = mp.Csr.from_numpy(row_ptr, col_idx)
+        ad, bd = dev(a), dev(b)
+        for precond in ("none", "jacobi"):
+            for plan in (None, mp.mp_plan_create(A, 2, False, 2, 6)):
+                if name == "diffusion-chunks" and (precond == "none" or plan is None):
+                    continue
+                x = torch.zeros((2, n), dtype=torch.float64, device="cuda")
+                ig = mp.mpkrylov_gpbicg(A, ad, bd, x, plan=plan, precond=precond, rtol=1e-28, max_iter=20000,
+                                        check_every=8)
+                lw = None if plan is None else plan.row_log2w()
+                xo, io = ref.gpbicg(row_ptr, col_idx, a, b, precond=precond, rtol=1e-28, max_iter=20000, log2w=lw)
+                assert (ig["status"], ig["iters"], ig["restarts"]) == (io["status"], io["iters"], io["restarts"]), name
+                assert io["status"] == 0
+                assert_same_values(host(x), xo, "%s gpbicg x" % name)
+                assert_same_values(ig["rr_true"], io["rr_true"], "%s gpbicg rr" % name)
+
+
+def test_gpbicg_limits_half_step_and_breakdown(mp):
+    """Iteration limits (ending inside a check chunk), a half step that meets the
+    tolerance (a diagonal system with one distinct eigenvalue converges when t is
+    formed), a warm start at the solution, and a NaN right-hand side (breakdown)
+    report the oracle's status and counts."""
+    import torch
+    from workloads import banded_nonsymmetric
+    row_ptr, col_idx, a = banded_nonsymmetric(n=300, seed=6)
+    n = row_ptr.size - 1
+    A = mp.Csr.from_numpy(row_ptr, col_idx)
+    ad = dev(a)
+    b = random_mp(n, 2, np.random.default_rng(14))
+    for lim in (1, 2, 5, 11):
+        x = torch.zeros((2, n), dtype=torch.float64, device="cuda")
+        ig = mp.mpkrylov_gpbicg(A, ad, dev(b), x, rtol=1e-28, max_iter=lim, check_every=4)
+        xo, io = ref.gpbicg(row_ptr, col_idx, a, b, rtol=1e-28, max_iter=lim)
+        assert io["status"] == -5 and io["iters"] == lim
+        assert (ig["status"], ig["iters"], ig["restarts"]) == (io["status"], io["iters"], io["restarts"])
+        assert_same_values(ig["rr_true"], io["rr_true"], "limit %d rr" % lim)
+        assert_same_values(host(x), xo, "limit %d x" % lim)
+    # one distinct eigenvalue: t = 0 after the first alpha -> half step, then confirmed
+    nd = 5000
+    rp = np.arange(nd + 1, dtype=np.int32)
+    ci = np.arange(nd, dtype=np.int32)
+    ad_diag = np.zeros((2, nd))
+    ad_diag[0] = 3.0
+    bdg = random_mp(nd, 2, np.random.default_rng(15))
+    Ad = mp.Csr.from_numpy(rp, ci)
+    x = torch.zeros((2, nd), dtype=torch.float64, device="cuda")
+    ig = mp.mpkrylov_gpbicg(Ad, dev(ad_diag), dev(bdg), x, precond="none", rtol=1e-28, max_iter=50)
+    xo, io = ref.gpbicg(rp, ci, ad_diag, bdg, precond="none", rtol=1e-28, max_iter=50)
+    assert (ig["status"], ig["iters"], ig["restarts"]) == (io["status"], io["iters"], io["restarts"]) == (0, 1, 0)
+    assert_same_values(host(x), xo, "half step x")
+    # warm start at the solution: no step
+    xw = x.clone()
+    iw = mp.mpkrylov_gpbicg(Ad, dev(ad_diag), dev(bdg), xw, precond="none", rtol=1e-28, max_iter=50)
+    assert iw["iters"] == 0 and torch.equal(xw, x)
+    bad = b.copy()
+    bad[0, 7] = np.nan
+    x = torch.zeros((2, n), dtype=torch.float64, device="cuda")
+    ig = mp.mpkrylov_gpbicg(A, ad, dev(bad), x, rtol=1e-28, max_iter=50)
+    io = ref.gpbicg(row_ptr, col_idx, a, bad, rtol=1e-28, max_iter=50)[1]
+    assert ig["status"] == io["status"] == -6 and ig["iters"] == io["iters"]
+    with pytest.raises(mp.MpError) as ei:
+        mp.mpkrylov_gpbicg(A, ad, dev(bad), x, rtol=1e-28, max_iter=50, raise_on_failure=True)
+    assert ei.value.status == -6
