@@ -124,20 +124,21 @@ __global__ __launch_bounds__(256) void k_bspmm(int32_t n, const int32_t *__restr
     for (int32_t k0 = b; k0 < e; k0 += kG) {
         int64_t jv[kG];
         dd_t av[kG];
+        // branch-free (a slot past the row's end re-reads its first element), so all
+        // gathers of the group are in flight together
 #pragma unroll
-        for (int u = 0; u < kG; ++u)
-            if (k0 + u < e) {
-                jv[u] = __builtin_nontemporal_load(ci + k0 + u);
-                av[u].c[0] = __builtin_nontemporal_load(a + k0 + u);
-                av[u].c[1] = __builtin_nontemporal_load(a + nnz + k0 + u);
-            }
+        for (int u = 0; u < kG; ++u) {
+            const int32_t k = k0 + u < e ? k0 + u : b;
+            jv[u] = __builtin_nontemporal_load(ci + k);
+            av[u].c[0] = __builtin_nontemporal_load(a + k);
+            av[u].c[1] = __builtin_nontemporal_load(a + nnz + k);
+        }
         dd_t xv[kG][RPT];
 #pragma unroll
-        for (int u = 0; u < kG; ++u)
-            if (k0 + u < e) {
+        for (int u = 0; u < kG; ++u) {
 #pragma unroll
-                for (int q = 0; q < RPT; ++q) xv[u][q] = bld(X, NR, jv[u], R, r0 + q);
-            }
+            for (int q = 0; q < RPT; ++q) xv[u][q] = bld(X, NR, jv[u], R, r0 + q);
+        }
 #pragma unroll
         for (int u = 0; u < kG; ++u)
             if (k0 + u < e) {

@@ -1362,15 +1362,16 @@ __global__ __launch_bounds__(256) void k_in_spmv(int64_t n, const int32_t *__res
         for (int32_t k0 = b; k0 < e; k0 += 8) {
             T av[8], xv[8];
             int32_t cv[8];
+            // branch-free loads and gathers (a slot past the row's end re-reads its first
+            // element), so every gather of the group is in flight at once
 #pragma unroll
-            for (int j = 0; j < 8; ++j)
-                if (k0 + j < e) {
-                    av[j] = a[k0 + j];
-                    cv[j] = ci[k0 + j];
-                }
+            for (int j = 0; j < 8; ++j) {
+                const int32_t k = k0 + j < e ? k0 + j : b;
+                av[j] = a[k];
+                cv[j] = ci[k];
+            }
 #pragma unroll
-            for (int j = 0; j < 8; ++j)
-                if (k0 + j < e) xv[j] = x[cv[j]];
+            for (int j = 0; j < 8; ++j) xv[j] = x[cv[j]];
 #pragma unroll
             for (int j = 0; j < 8; ++j)
                 if (k0 + j < e) {
@@ -1550,15 +1551,16 @@ __global__ __launch_bounds__(256) void k_in_mspmv(int64_t n, const int32_t *__re
         for (int32_t k0 = b; k0 < e; k0 += 8) {
             T av[8], xv[8];
             int32_t cv[8];
+            // branch-free loads and gathers (a slot past the row's end re-reads its first
+            // element), so every gather of the group is in flight at once
 #pragma unroll
-            for (int j = 0; j < 8; ++j)
-                if (k0 + j < e) {
-                    av[j] = mv[k0 + j];
-                    cv[j] = ci[k0 + j];
-                }
+            for (int j = 0; j < 8; ++j) {
+                const int32_t k = k0 + j < e ? k0 + j : b;
+                av[j] = mv[k];
+                cv[j] = ci[k];
+            }
 #pragma unroll
-            for (int j = 0; j < 8; ++j)
-                if (k0 + j < e) xv[j] = r[cv[j]];
+            for (int j = 0; j < 8; ++j) xv[j] = r[cv[j]];
 #pragma unroll
             for (int j = 0; j < 8; ++j)
                 if (k0 + j < e) {

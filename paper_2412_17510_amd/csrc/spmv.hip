@@ -280,30 +280,49 @@ __device__ __forceinline__ void load_aelem(const SpmvArgs &A, int64_t k, AElem<K
     }
 }
 
-// product(s) of one element with the staged x (matrix operand first)
+// every component of x_j from the staged copy (one gather)
+template <int K, bool CPLX>
+struct XVal {
+    mpn<K> re;
+    mpn<K> im;
+};
+
+template <int K, bool CPLX>
+__device__ __forceinline__ XVal<K, CPLX> load_x(const SpmvArgs &A, int32_t col)
+{
+    constexpr int D = K * (CPLX ? 2 : 1);
+    const double *xp = A.xs + (int64_t)col * D;
+    XVal<K, CPLX> x;
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        x.re.c[c] = xp[c];
+        if constexpr (CPLX) x.im.c[c] = xp[K + c];
+    }
+    return x;
+}
+
+// product(s) of one element with its x (matrix operand first)
+template <int K, bool CPLX, bool DM>
+__device__ __forceinline__ Acc<K, CPLX> elem_times_x(const AElem<K, CPLX> &e, const XVal<K, CPLX> &x)
+{
+    Acc<K, CPLX> p;
+    if constexpr (CPLX) {
+        p.rr = mp_mul(e.re, x.re);
+        p.ii = mp_mul(e.im, x.im);
+        p.ri = mp_mul(e.re, x.im);
+        p.ir = mp_mul(e.im, x.re);
+    } else if constexpr (DM) {
+        p.v = mp_mul_d(x.re, e.re.c[0]);
+    } else {
+        p.v = mp_mul(e.re, x.re);
+    }
+    return p;
+}
+
 template <int K, bool CPLX, bool DM>
 __device__ __forceinline__ Acc<K, CPLX> staged_product(const SpmvArgs &A, const AElem<K, CPLX> &e)
 {
-    constexpr int D = K * (CPLX ? 2 : 1);
-    const double *xp = A.xs + (int64_t)e.col * D;
-    mpn<K> xr;
-#pragma unroll
-    for (int c = 0; c < K; ++c) xr.c[c] = xp[c];
-    Acc<K, CPLX> p;
-    if constexpr (CPLX) {
-        mpn<K> xi;
-#pragma unroll
-        for (int c = 0; c < K; ++c) xi.c[c] = xp[K + c];
-        p.rr = mp_mul(e.re, xr);
-        p.ii = mp_mul(e.im, xi);
-        p.ri = mp_mul(e.re, xi);
-        p.ir = mp_mul(e.im, xr);
-    } else if constexpr (DM) {
-        p.v = mp_mul_d(xr, e.re.c[0]);
-    } else {
-        p.v = mp_mul(e.re, xr);
-    }
-    return p;
+    return elem_times_x<K, CPLX, DM>(e, load_x<K, CPLX>(A, e.col));
 }
 
 // LDS of one stream-tile workgroup staging C elements
@@ -318,7 +337,10 @@ struct StreamLds {
 
 // SHORT tile: rows [r0, r0+nr), ne <= C elements starting at e0, at most C rows.
 // The element loads are issued first (their addresses need only the descriptor), the
-// row bookkeeping overlaps them, and the products go to LDS once x has arrived.
+// row bookkeeping overlaps them, then every gather of x is issued before the first
+// product is formed, and the products go to LDS.  Loads and gathers are branch-free
+// (a thread past the tile's end re-reads the tile's first element and discards it),
+// so a thread keeps all of its gathers in flight at once.
 template <int K, bool CPLX, int J, bool DM>
 __device__ __forceinline__ void short_tile(const SpmvArgs &A, const uint8_t *__restrict__ log2w,
                                            const mp_stream_tile &T, StreamLds<K, CPLX, 256 * J> &L)
@@ -330,10 +352,12 @@ __device__ __forceinline__ void short_tile(const SpmvArgs &A, const uint8_t *__r
     const int ne = T.info >> 8;
     // phase 1a: matrix operands of elements t, t+256, ...
     AElem<K, CPLX> el[J];
+    if (ne > 0) {
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
-        const int p = t + 256 * j;
-        if (p < ne) load_aelem<K, CPLX, DM>(A, (int64_t)e0 + p, el[j]);
+        for (int j = 0; j < J; ++j) {
+            const int p = t + 256 * j;
+            load_aelem<K, CPLX, DM>(A, (int64_t)e0 + (p < ne ? p : 0), el[j]);
+        }
     }
     // rows t*J .. t*J+J-1: starts, lane counts (W, or 0 for an empty row)
     int wl[J];
@@ -350,11 +374,16 @@ __device__ __forceinline__ void short_tile(const SpmvArgs &A, const uint8_t *__r
         }
     }
     if (t == 0) L.beg[nr] = ne;
-    // phase 1b: gather x, products into LDS
+    // phase 1b: gather x (all gathers first), products into LDS
+    if (ne > 0) {
+        XVal<K, CPLX> xv[J];
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
-        const int p = t + 256 * j;
-        if (p < ne) L.prod[p] = staged_product<K, CPLX, DM>(A, el[j]);
+        for (int j = 0; j < J; ++j) xv[j] = load_x<K, CPLX>(A, el[j].col);
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int p = t + 256 * j;
+            if (p < ne) L.prod[p] = elem_times_x<K, CPLX, DM>(el[j], xv[j]);
+        }
     }
     int run = block_exclusive_scan(sum, L.wave_tmp);
 #pragma unroll
@@ -420,8 +449,70 @@ __device__ __forceinline__ void short_tile(const SpmvArgs &A, const uint8_t *__r
 }
 
 // LONG tile: one row of len > C with W <= 256 lanes (lane l on thread l).
+//
+// Register form (DD real): lane l reads its own elements l, l+W, ... straight from
+// memory (consecutive lanes read consecutive elements, so every load is coalesced),
+// kLongBatch of them issued together, and adds their products in order in registers.
+// The fold steps whose partner lies in another wavefront (off >= 64) go through LDS,
+// the rest through cross-lane shuffles.  The wider TD / QD / complex values would
+// raise the register count of the whole kernel (and cut its occupancy), so they keep
+// the staged form below.
+constexpr int kLongBatch = 4;
+
 template <int K, bool CPLX, int J, bool DM>
-__device__ __forceinline__ void long_tile(const SpmvArgs &A, const uint8_t *__restrict__ log2w,
+__device__ __forceinline__ void long_tile_lanes(const SpmvArgs &A, const uint8_t *__restrict__ log2w,
+                                                const mp_stream_tile &T, StreamLds<K, CPLX, 256 * J> &L)
+{
+    const int t = threadIdx.x;
+    const int row = T.row_start;
+    const int32_t b0 = A.row_ptr[row], end = A.row_ptr[row + 1];
+    const int W = 1 << log2w[row];
+    Acc<K, CPLX> acc;
+    acc_zero(acc);
+    if (t < W) {
+        // W <= len, so every lane owns at least one element and starts from its first product
+        bool first = true;
+        for (int64_t k0 = (int64_t)b0 + t; k0 < end; k0 += (int64_t)kLongBatch * W) {
+            // branch-free batch: an element past the row's end re-reads the lane's first one
+            AElem<K, CPLX> el[kLongBatch];
+#pragma unroll
+            for (int q = 0; q < kLongBatch; ++q) {
+                const int64_t k = k0 + (int64_t)q * W;
+                load_aelem<K, CPLX, DM>(A, k < end ? k : k0, el[q]);
+            }
+            XVal<K, CPLX> xv[kLongBatch];
+#pragma unroll
+            for (int q = 0; q < kLongBatch; ++q) xv[q] = load_x<K, CPLX>(A, el[q].col);
+#pragma unroll
+            for (int q = 0; q < kLongBatch; ++q) {
+                if (k0 + (int64_t)q * W < end) {
+                    const Acc<K, CPLX> p = elem_times_x<K, CPLX, DM>(el[q], xv[q]);
+                    if (first)
+                        acc = p;
+                    else
+                        acc_add(acc, p);
+                    first = false;
+                }
+            }
+        }
+    }
+    // fold acc[l] += acc[l + off], off = W/2 .. 1
+    for (int off = W >> 1; off >= 64; off >>= 1) {
+        if (t >= off && t < 2 * off) L.prod[t] = acc;
+        __syncthreads();
+        if (t < off) acc_add(acc, L.prod[t + off]);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        if (off < W) acc_fold_xor(acc, off);
+    if (t == 0) acc_store(A, row, acc, true);
+}
+
+// LONG tile, staged form (TD / QD / complex): the row's elements pass through LDS in
+// chunks of C products, lane l (thread l) carrying its running sum in registers.
+template <int K, bool CPLX, int J, bool DM>
+__device__ __forceinline__ void long_tile_staged(const SpmvArgs &A, const uint8_t *__restrict__ log2w,
                                           const mp_stream_tile &T, StreamLds<K, CPLX, 256 * J> &L)
 {
     constexpr int C = 256 * J;
@@ -479,8 +570,10 @@ __global__ __launch_bounds__(256) void spmv_stream_kernel(SpmvArgs A, const mp_s
     const mp_stream_tile T = tiles[tile];
     if (((T.info >> 4) & 15) == 0)
         short_tile<K, CPLX, J, DM>(A, log2w, T, L);
+    else if constexpr (K == 2 && !CPLX)
+        long_tile_lanes<K, CPLX, J, DM>(A, log2w, T, L);
     else
-        long_tile<K, CPLX, J, DM>(A, log2w, T, L);
+        long_tile_staged<K, CPLX, J, DM>(A, log2w, T, L);
 }
 
 // ---------------------------------------------------------------------------
