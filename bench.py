@@ -307,6 +307,49 @@ def nonsymmetric_section(mp, torch, repeats=3):
     return out
 
 
+def locality_section(mp, torch, args):
+    """What the x gathers cost: the DD SpMV (autotuned plan) on three patterns with the
+    power-law workload's row lengths (same seed): the workload's columns (70 % within the
+    2,000-wide band, 30 % uniform), every column within the band, and each row reading one
+    contiguous run of x (row i: columns min(i, n - len) .. + len - 1, coalesced gathers).
+    The matrix streams and the algorithmic bytes are identical across the three."""
+    from workloads import powerlaw_pattern, random_mp, mp_from_leads
+    out = {}
+    base = None
+    for name, kw in (("workload 70% band / 30% uniform", {}), ("all within the band", {"p_band": 1.0}),
+                     ("contiguous run per row", None)):
+        t0 = time.perf_counter()
+        if kw is None:
+            rp, _ = base
+            n = rp.size - 1
+            lens = np.diff(rp).astype(np.int64)
+            start = np.minimum(np.arange(n, dtype=np.int64), n - lens)
+            row_of = np.repeat(np.arange(n, dtype=np.int64), lens)
+            ci = (start[row_of] + (np.arange(rp[-1], dtype=np.int64) - rp[:-1].astype(np.int64)[row_of])).astype(np.int32)
+        else:
+            rp, ci = powerlaw_pattern(n=args.n, seed=1, **kw)
+            if base is None:
+                base = (rp, ci)
+        n = rp.size - 1
+        nnz = ci.size
+        log("locality pattern '%s' nnz=%d in %.1f s" % (name, nnz, time.perf_counter() - t0))
+        A = mp.Csr.from_numpy(rp, ci)
+        rng = np.random.default_rng([1, 2, 0])
+        ad = torch.from_numpy(mp_from_leads(rng.uniform(-1, 1, nnz), 2, rng)).cuda()
+        xd = torch.from_numpy(random_mp(n, 2, rng)).cuda()
+        yd = torch.empty((2, n), dtype=torch.float64, device="cuda")
+        plan, pol = mp.mp_plan_autotune(A, 2, ad, xd, yd, reps=5)
+        ms, _ = time_loop(lambda: mp.mpspmv_csr_dd(A, ad, xd, yd, plan=plan), args.steps, args.warmup, torch)
+        rf = roofline(n, nnz, 2, False, ms)
+        out[name] = {"ms": round(ms, 4), "gnnz_s": round(nnz / (ms * 1e-3) / 1e9, 3), "plan": pol,
+                     "roofline_frac": rf["frac"], "achieved_GBs": rf["achieved"]}
+        log("%-34s %.4f ms  %.2f GNNZ/s  %.1f%% of 8 TB/s (algorithmic bytes)" % (
+            name, ms, nnz / (ms * 1e-3) / 1e9, 100 * rf["frac"]))
+        del A, ad, xd, yd, plan
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -317,8 +360,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=6.0)
     ap.add_argument("--plan", default="autotune", help="autotune | canonical | shift,max_log2w,tile_nnz")
-    ap.add_argument("--workload", default="spmv", choices=["spmv", "batched"],
-                    help="spmv (default: power-law SpMV line plus the 64^3 solves) or batched (256 systems x 8 rhs)")
+    ap.add_argument("--workload", default="spmv", choices=["spmv", "batched", "locality"],
+                    help="spmv (default: power-law SpMV line plus the 64^3 solves), batched (256 systems x 8 rhs) "
+                         "or locality (the DD SpMV on three column laws with the same row lengths)")
     ap.add_argument("--nsys", type=int, default=256)
     ap.add_argument("--loop-systems", type=int, default=6)
     ap.add_argument("--no-solves", action="store_true")
@@ -352,6 +396,16 @@ def main():
                           "value": res["cg"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
                           "higher_is_better": True, "dtype": "f64", "data": "synthetic",
                           "config": {"workload": res["workload"]}, "batched": res}), flush=True)
+        return
+
+    if args.workload == "locality":
+        res = locality_section(mp, torch, args)
+        first = next(iter(res.values()))
+        print(json.dumps({"metric": "DD SpMV GNNZ/s on the power-law row lengths under three column laws",
+                          "value": first["gnnz_s"], "unit": "GNNZ/s", "n_gpus": 1, "steps": args.steps,
+                          "warmup": args.warmup, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+                          "config": {"workload": "powerlaw row lengths n=%d, column laws: %s" % (args.n, list(res))},
+                          "locality": res}), flush=True)
         return
 
     t0 = time.perf_counter()
