@@ -203,6 +203,24 @@ mp_status mpspmv_csr_qd_d(const mp_csr *A, const double *a, const double *x, dou
 mp_status mp_csr_transpose(const mp_csr *A, int32_t ncomp, const double *a_re, const double *a_im,
                            int32_t *row_ptr_t, int32_t *col_idx_t, double *at_re, double *at_im, void *stream);
 
+/*
+ * COO -> CSR on the device (Sec. 3 describes both storage formats and the CSR
+ * arrays a COO matrix maps to).  row, col: nnz 0-based coordinates (device int32);
+ * v_re (and v_im for complex data, else NULL): ncomp planar value arrays of nnz
+ * doubles (ncomp 1..4: a binary64 matrix or K components).  Outputs (device,
+ * caller-allocated, not overlapping the inputs or each other): row_ptr int32[n_rows+1],
+ * col_idx int32[nnz], a_re / a_im (ncomp*nnz doubles, a_im NULL iff v_im is NULL).
+ * Elements are ordered by row, then column (a stable sort: elements with equal
+ * coordinates stay in input order and are kept as separate elements, which the SpMV
+ * then adds in that order).  Allocates temporaries and synchronises `stream`.
+ * MP_ERR_INVALID_ARG for a coordinate outside the matrix (nothing written), negative
+ * sizes, NULL pointers or ncomp out of range; MP_ERR_ALIAS for overlapping buffers;
+ * MP_ERR_UNSUPPORTED for nnz >= 2^31.
+ */
+mp_status mp_coo_to_csr(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row, const int32_t *col,
+                        int32_t ncomp, const double *v_re, const double *v_im, int32_t *row_ptr, int32_t *col_idx,
+                        double *a_re, double *a_im, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Krylov solvers in double-double (Sec. 4.2: CG for symmetric positive-definite A,
  * BiCGSTAB for non-symmetric A; x0 given, stop on the residual norm).

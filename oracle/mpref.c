@@ -1393,3 +1393,39 @@ int oracle_gpbicg(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t 
     free(r); free(rh); free(p); free(q); free(t); free(c); free(y); free(u); free(z); free(w); free(tp); free(tmp);
     return status;
 }
+
+/* ------------------------------------------------------------------------- */
+/* COO -> CSR (the storage conversion of Sec. 3): elements ordered by row, and */
+/* within a row by column; elements with the same (row, column) keep their    */
+/* input order (two stable counting sorts: by column, then by row).  Returns  */
+/* -2 when a coordinate is outside the matrix.  v: ncomp planar arrays of nnz. */
+/* ------------------------------------------------------------------------- */
+int oracle_coo_to_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_t *row, const int32_t *col, int ncomp,
+                      const double *v, int32_t *row_ptr, int32_t *col_idx, double *a)
+{
+    int64_t k, j;
+    int c;
+    int64_t *cnt, *by_col;
+    for (k = 0; k < nnz; ++k)
+        if (row[k] < 0 || row[k] >= n_rows || col[k] < 0 || col[k] >= n_cols) return -2;
+    cnt = (int64_t *)calloc((size_t)(n_cols > n_rows ? n_cols : n_rows) + 1, sizeof(int64_t));
+    by_col = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nnz > 0 ? nnz : 1));
+    if (!cnt || !by_col) { free(cnt); free(by_col); return -1; }
+    /* pass 1: stable order by column */
+    for (k = 0; k < nnz; ++k) cnt[col[k] + 1]++;
+    for (j = 0; j < n_cols; ++j) cnt[j + 1] += cnt[j];
+    for (k = 0; k < nnz; ++k) by_col[cnt[col[k]]++] = k;
+    /* pass 2: stable order by row of the column-ordered sequence */
+    memset(cnt, 0, sizeof(int64_t) * ((size_t)(n_cols > n_rows ? n_cols : n_rows) + 1));
+    for (k = 0; k < nnz; ++k) cnt[row[k] + 1]++;
+    for (j = 0; j < n_rows; ++j) cnt[j + 1] += cnt[j];
+    for (j = 0; j <= n_rows; ++j) row_ptr[j] = (int32_t)cnt[j];
+    for (k = 0; k < nnz; ++k) {
+        int64_t src = by_col[k], dst = cnt[row[src]]++;
+        col_idx[dst] = col[src];
+        for (c = 0; c < ncomp; ++c) a[(int64_t)c * nnz + dst] = v[(int64_t)c * nnz + src];
+    }
+    free(cnt);
+    free(by_col);
+    return 0;
+}

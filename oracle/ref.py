@@ -27,10 +27,11 @@ def lib():
         L.oracle_spmv.argtypes = [ctypes.c_int, i64, i64, i64, P, P, P, P, P, P, P, P, P, i64, P, ctypes.c_int]
         L.oracle_spmv_dmat.argtypes = [ctypes.c_int, i64, i64, i64, P, P, P, P, P, P, i64, P, ctypes.c_int]
         L.oracle_transpose.argtypes = [i64, i64, i64, ctypes.c_int, P, P, P, P, P, P]
+        L.oracle_coo_to_csr.argtypes = [i64, i64, i64, P, P, ctypes.c_int, P, P, P, P]
         L.oracle_canonical_log2w.argtypes = [i64]
         L.oracle_num_threads.argtypes = []
         for name in ("oracle_eft", "oracle_elementwise", "oracle_renorm5", "oracle_spmv", "oracle_spmv_dmat",
-                     "oracle_transpose",
+                     "oracle_transpose", "oracle_coo_to_csr",
                      "oracle_canonical_log2w", "oracle_num_threads"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -154,6 +155,26 @@ def transpose(row_ptr, col_idx, a, n_cols=None):
     assert lib().oracle_transpose(n, n_cols, nnz, a2.shape[0], _p(row_ptr), _p(col_idx), _p(a2), _p(rpt), _p(cit),
                                   _p(at)) == 0
     return rpt, cit, at.reshape(a.shape)
+
+
+def coo_to_csr(n_rows, n_cols, row, col, v):
+    """CSR of a COO matrix (0-based coordinates): elements ordered by row, then column;
+    equal coordinates keep their input order.  v: (ncomp, nnz) or (nnz,).  Returns
+    (row_ptr, col_idx, a) with a shaped like v; raises ValueError for a coordinate
+    outside the matrix."""
+    row = np.ascontiguousarray(row, dtype=np.int32)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    nnz = row.size
+    v = _f64(v)
+    v2 = v.reshape(-1, nnz) if nnz else v.reshape(1 if v.ndim < 2 else v.shape[0], 0)
+    rp = np.empty(n_rows + 1, dtype=np.int32)
+    ci = np.empty(nnz, dtype=np.int32)
+    a = np.empty_like(v2)
+    st = lib().oracle_coo_to_csr(n_rows, n_cols, nnz, _p(row), _p(col), v2.shape[0], _p(v2), _p(rp), _p(ci), _p(a))
+    if st == -2:
+        raise ValueError("coordinate outside the %d x %d matrix" % (n_rows, n_cols))
+    assert st == 0
+    return rp, ci, a.reshape(v.shape)
 
 
 def num_threads():

@@ -88,6 +88,7 @@ for _name in ("mpkrylov_cg", "mpkrylov_bicgstab", "mpkrylov_cgs", "mpkrylov_gpbi
 _SIGS["mpkrylov_bicg"] = ([_CSR, _P, _CSR, _P, _P, _P, ctypes.POINTER(mp_solve_opts), _P, _P, _P, ctypes.c_size_t,
                            ctypes.POINTER(mp_solve_info), _P], ctypes.c_int)
 _SIGS["mp_csr_transpose"] = ([_CSR, _I, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int)
+_SIGS["mp_coo_to_csr"] = ([_I, _I, ctypes.c_int64, _P, _P, _I, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int)
 _SIGS["mpkrylov_ir_learned"] = ([_CSR, _P, _P, _P, _P, ctypes.POINTER(mp_solve_opts), _P, _P, ctypes.c_size_t,
                                  ctypes.POINTER(mp_solve_info), _P], ctypes.c_int)
 _SIGS["mp_mpnn_param_count"] = ([ctypes.POINTER(_I)], ctypes.c_int)
@@ -276,6 +277,32 @@ def mp_csr_transpose(A, a_re, a_im=None, stream=None):
     _check(_lib.mp_csr_transpose(ctypes.byref(A.c), int(ncomp), _ptr(a_re), _ptr(a_im), _ptr(rpt), _ptr(cit),
                                  _ptr(at_re), _ptr(at_im), _stream_ptr(stream)), "mp_csr_transpose")
     return Csr(rpt, cit, n_cols=A.n_rows), at_re, at_im
+
+
+def mp_coo_to_csr(n_rows, n_cols, row, col, v_re, v_im=None, stream=None):
+    """CSR of a COO matrix (C ABI mp_coo_to_csr).  row, col: CUDA int32 tensors of nnz
+    0-based coordinates; v_re (v_im): CUDA float64 values, (ncomp, nnz) or (nnz,).
+    Returns (Csr, a_re, a_im or None), values shaped like v_re, ordered by row then
+    column (equal coordinates stay in input order)."""
+    import torch
+    nnz = row.numel()
+    for t, nm in ((row, "row"), (col, "col")):
+        if not t.is_cuda or t.dtype != torch.int32 or not t.is_contiguous() or t.numel() != nnz:
+            raise ValueError("%s must be a contiguous CUDA int32 tensor of %d coordinates" % (nm, nnz))
+    for t, nm in ((v_re, "v_re"), (v_im, "v_im")):
+        if t is None:
+            continue
+        if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous() or (nnz and t.numel() % nnz):
+            raise ValueError("%s must be a contiguous CUDA float64 tensor of ncomp * nnz values" % nm)
+    ncomp = v_re.numel() // nnz if nnz else (v_re.shape[0] if v_re.dim() == 2 else 1)
+    rp = torch.empty(n_rows + 1, dtype=torch.int32, device="cuda")
+    ci = torch.empty(nnz, dtype=torch.int32, device="cuda")
+    a_re = torch.empty_like(v_re)
+    a_im = torch.empty_like(v_im) if v_im is not None else None
+    _check(_lib.mp_coo_to_csr(int(n_rows), int(n_cols), int(nnz), _ptr(row), _ptr(col), int(ncomp), _ptr(v_re),
+                              _ptr(v_im), _ptr(rp), _ptr(ci), _ptr(a_re), _ptr(a_im), _stream_ptr(stream)),
+           "mp_coo_to_csr")
+    return Csr(rp, ci, n_cols=n_cols), a_re, a_im
 
 
 def _spmv_dmat(name, K):

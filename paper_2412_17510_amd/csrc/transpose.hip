@@ -1,4 +1,5 @@
-// transpose.hip -- CSR transpose on the device, for A^T v (Sec. 3).
+// transpose.hip -- CSR transpose (for A^T v) and COO -> CSR conversion on the device
+// (Sec. 3's storage formats).
 //
 // The paper forms A^T v by splitting A across threads and combining partial results
 // in a critical section (its order depends on the thread schedule) and suggests
@@ -60,6 +61,46 @@ __global__ __launch_bounds__(256) void k_t_gather(int64_t nnz, int ncomp, const 
         for (int c = 0; c < ncomp; ++c) {
             at_re[c * nnz + p] = a_re[c * nnz + k];
             if (a_im) at_im[c * nnz + p] = a_im[c * nnz + k];
+        }
+    }
+}
+
+// COO coordinates: count those outside the matrix; sort key row * n_cols + col
+__global__ __launch_bounds__(256) void k_c_keys(int64_t nnz, int32_t n_rows, int32_t n_cols,
+                                                const int32_t *__restrict__ row, const int32_t *__restrict__ col,
+                                                uint64_t *__restrict__ key, int32_t *__restrict__ vin,
+                                                unsigned int *__restrict__ bad)
+{
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * 256) {
+        const int32_t r = row[k], c = col[k];
+        const bool ok = r >= 0 && r < n_rows && c >= 0 && c < n_cols;
+        if (!ok) atomicAdd(bad, 1u);
+        key[k] = ok ? (uint64_t)r * (uint64_t)n_cols + (uint64_t)c : 0;
+        vin[k] = (int32_t)k;
+    }
+}
+
+// sorted keys -> row of each element and its column
+__global__ __launch_bounds__(256) void k_c_split(int64_t nnz, int32_t n_cols, const uint64_t *__restrict__ key,
+                                                 int32_t *__restrict__ srow, int32_t *__restrict__ cout)
+{
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * 256) {
+        const uint64_t q = key[p];
+        srow[p] = (int32_t)(q / (uint64_t)n_cols);
+        cout[p] = (int32_t)(q % (uint64_t)n_cols);
+    }
+}
+
+// values in sorted order: a[c][p] = v[c][perm[p]]
+__global__ __launch_bounds__(256) void k_c_gather(int64_t nnz, int ncomp, const int32_t *__restrict__ perm,
+                                                  const double *__restrict__ v_re, const double *__restrict__ v_im,
+                                                  double *__restrict__ a_re, double *__restrict__ a_im)
+{
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * 256) {
+        const int64_t k = perm[p];
+        for (int c = 0; c < ncomp; ++c) {
+            a_re[c * nnz + p] = v_re[c * nnz + k];
+            if (v_im) a_im[c * nnz + p] = v_im[c * nnz + k];
         }
     }
 }
@@ -140,5 +181,90 @@ extern "C" mp_status mp_csr_transpose(const mp_csr *A, int32_t ncomp, const doub
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(tmp);
     if (e != hipSuccess) return hip_fail(e, "mp_csr_transpose");
+    return MP_OK;
+}
+
+extern "C" mp_status mp_coo_to_csr(int32_t n_rows, int32_t n_cols, int64_t nnz, const int32_t *row,
+                                   const int32_t *col, int32_t ncomp, const double *v_re, const double *v_im,
+                                   int32_t *row_ptr, int32_t *col_idx, double *a_re, double *a_im, void *stream)
+{
+    using namespace mpk;
+    clear_error();
+    if (n_rows < 0 || n_cols < 0 || nnz < 0)
+        return fail(MP_ERR_INVALID_ARG, "mp_coo_to_csr: negative size (n_rows=%d n_cols=%d nnz=%lld)", n_rows, n_cols,
+                    (long long)nnz);
+    if (nnz >= INT32_MAX) return fail(MP_ERR_UNSUPPORTED, "mp_coo_to_csr: nnz must be below 2^31");
+    if (nnz > 0 && (n_rows == 0 || n_cols == 0))
+        return fail(MP_ERR_INVALID_ARG, "mp_coo_to_csr: %lld elements in an empty matrix", (long long)nnz);
+    if (ncomp < 1 || ncomp > 4) return fail(MP_ERR_INVALID_ARG, "mp_coo_to_csr: ncomp must be 1..4 (got %d)", ncomp);
+    if (!row_ptr) return fail(MP_ERR_INVALID_ARG, "mp_coo_to_csr: row_ptr is NULL");
+    if (nnz > 0 && (!row || !col || !v_re || !col_idx || !a_re))
+        return fail(MP_ERR_INVALID_ARG, "mp_coo_to_csr: row, col, v_re, col_idx or a_re is NULL");
+    if ((v_im == nullptr) != (a_im == nullptr))
+        return fail(MP_ERR_INVALID_ARG, "mp_coo_to_csr: v_im and a_im must both be given or both NULL");
+    const size_t vb = sizeof(double) * (size_t)ncomp * (size_t)nnz, ib = sizeof(int32_t) * (size_t)nnz;
+    const void *ins[4] = {row, col, v_re, v_im};
+    const size_t insz[4] = {ib, ib, vb, v_im ? vb : 0};
+    void *outs[4] = {row_ptr, col_idx, a_re, a_im};
+    const size_t outsz[4] = {sizeof(int32_t) * ((size_t)n_rows + 1), ib, vb, a_im ? vb : 0};
+    for (int o = 0; o < 4; ++o) {
+        for (int i = 0; i < 4; ++i)
+            if (overlaps(outs[o], outsz[o], ins[i], insz[i]))
+                return fail(MP_ERR_ALIAS, "mp_coo_to_csr: an output overlaps an input");
+        for (int p = o + 1; p < 4; ++p)
+            if (overlaps(outs[o], outsz[o], outs[p], outsz[p]))
+                return fail(MP_ERR_ALIAS, "mp_coo_to_csr: two outputs overlap");
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (nnz == 0) {
+        hipLaunchKernelGGL(k_t_empty, dim3(tgrid((int64_t)n_rows + 1)), dim3(256), 0, s, n_rows, row_ptr);
+        MP_HIP_TRY(hipGetLastError());
+        MP_HIP_TRY(hipStreamSynchronize(s));
+        return MP_OK;
+    }
+    // key bits: enough for n_rows * n_cols - 1
+    const uint64_t kmax = (uint64_t)n_rows * (uint64_t)n_cols;
+    int end_bit = 1;
+    while (end_bit < 64 && ((uint64_t)1 << end_bit) < kmax) ++end_bit;
+    size_t sort_bytes = 0;
+    hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (const uint64_t *)nullptr,
+                                                      (uint64_t *)nullptr, (const int32_t *)nullptr, (int32_t *)nullptr,
+                                                      (int)nnz, 0, end_bit, s);
+    if (e != hipSuccess) return hip_fail(e, "mp_coo_to_csr: sort size query");
+    const size_t n8 = ((size_t)nnz * sizeof(uint64_t) + 255) & ~(size_t)255;
+    const size_t n4 = ((size_t)nnz * sizeof(int32_t) + 255) & ~(size_t)255;
+    char *tmp = nullptr;
+    MP_HIP_TRY(hipMalloc(reinterpret_cast<void **>(&tmp), 2 * n8 + 3 * n4 + 256 + sort_bytes));
+    uint64_t *key = reinterpret_cast<uint64_t *>(tmp);
+    uint64_t *skey = reinterpret_cast<uint64_t *>(tmp + n8);
+    int32_t *vin = reinterpret_cast<int32_t *>(tmp + 2 * n8);
+    int32_t *perm = reinterpret_cast<int32_t *>(tmp + 2 * n8 + n4);
+    int32_t *srow = reinterpret_cast<int32_t *>(tmp + 2 * n8 + 2 * n4);
+    unsigned int *bad = reinterpret_cast<unsigned int *>(tmp + 2 * n8 + 3 * n4);
+    void *sort_ws = tmp + 2 * n8 + 3 * n4 + 256;
+    unsigned int nbad = 0;
+    e = hipMemsetAsync(bad, 0, sizeof(unsigned int), s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_c_keys, dim3(tgrid(nnz)), dim3(256), 0, s, nnz, n_rows, n_cols, row, col, key, vin, bad);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(&nbad, bad, sizeof(unsigned int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && nbad > 0) {
+        (void)hipFree(tmp);
+        return fail(MP_ERR_INVALID_ARG, "mp_coo_to_csr: %u coordinates outside the %d x %d matrix", nbad, n_rows,
+                    n_cols);
+    }
+    if (e == hipSuccess)
+        e = hipcub::DeviceRadixSort::SortPairs(sort_ws, sort_bytes, key, skey, vin, perm, (int)nnz, 0, end_bit, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_c_split, dim3(tgrid(nnz)), dim3(256), 0, s, nnz, n_cols, skey, srow, col_idx);
+        hipLaunchKernelGGL(k_t_bounds, dim3(tgrid(nnz)), dim3(256), 0, s, nnz, n_rows, srow, row_ptr);
+        hipLaunchKernelGGL(k_c_gather, dim3(tgrid(nnz)), dim3(256), 0, s, nnz, ncomp, perm, v_re, v_im, a_re, a_im);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return hip_fail(e, "mp_coo_to_csr");
     return MP_OK;
 }
