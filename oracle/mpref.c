@@ -514,13 +514,14 @@ static mpv dd_div(mpv a, mpv b)
     return r;
 }
 
-/* Dot product order: the vector is cut into chunks of 4096 elements; inside a
+/* Dot product order (K-component operations; the same tree for every K): the vector
+ * is cut into chunks of 4096 elements; inside a
  * chunk, lane l < 256 accumulates elements l, l+256, ... (the SpMV row order with
  * W = 256), the lanes holding elements are folded acc[l] += acc[l+off], off =
  * 128..1, a lane without elements being skipped; the chunk sums are then combined
  * by a pairwise tree, P[i] = add(P[2i], P[2i+1]) level by level, an unpaired last
  * element passing up unchanged.  n = 0 gives 0. */
-static mpv dd_dot_vec(int64_t n, const double *x, const double *y)
+static mpv dot_tree(int K, int64_t n, const double *x, const double *y)
 {
     int64_t nch = (n + DOT_CHUNK - 1) / DOT_CHUNK, c, m;
     mpv zero = {{0.0, 0.0, 0.0, 0.0}};
@@ -532,24 +533,26 @@ static mpv dd_dot_vec(int64_t n, const double *x, const double *y)
         int l, off, used = cnt < DOT_LANES ? (int)cnt : DOT_LANES;
         for (l = 0; l < used; ++l) {
             int64_t k = base + l;
-            lanes[l] = dd_mul(load_mp(2, x, n, k), load_mp(2, y, n, k));
+            lanes[l] = mp_mul(K, load_mp(K, x, n, k), load_mp(K, y, n, k));
             for (k = k + DOT_LANES; k < base + cnt; k += DOT_LANES)
-                lanes[l] = dd_add(lanes[l], dd_mul(load_mp(2, x, n, k), load_mp(2, y, n, k)));
+                lanes[l] = mp_add(K, lanes[l], mp_mul(K, load_mp(K, x, n, k), load_mp(K, y, n, k)));
         }
         for (off = DOT_LANES / 2; off >= 1; off /= 2)
             for (l = 0; l < off; ++l)
-                if (l + off < used) lanes[l] = dd_add(lanes[l], lanes[l + off]);
+                if (l + off < used) lanes[l] = mp_add(K, lanes[l], lanes[l + off]);
         P[c] = lanes[0];
     }
     for (m = nch; m > 1; m = (m + 1) / 2) {
         int64_t i;
-        for (i = 0; i < m / 2; ++i) P[i] = dd_add(P[2 * i], P[2 * i + 1]);
+        for (i = 0; i < m / 2; ++i) P[i] = mp_add(K, P[2 * i], P[2 * i + 1]);
         if (m % 2) P[m / 2] = P[m - 1];
     }
     out = P[0];
     free(P);
     return out;
 }
+
+static mpv dd_dot_vec(int64_t n, const double *x, const double *y) { return dot_tree(2, n, x, y); }
 
 int oracle_dd_dot(int64_t n, const double *x, const double *y, double *out2)
 {
@@ -1428,4 +1431,264 @@ int oracle_coo_to_csr(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_t
     free(cnt);
     free(by_col);
     return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* K-component Krylov layer (TD and QD solvers; K = 2 reproduces the DD one).  */
+/* ------------------------------------------------------------------------- */
+
+/* a <= b by lexicographic comparison of the components (both normalised): the first
+ * component that differs decides, and a comparison that is not an equality (greater,
+ * or a NaN) is false; for K = 2 this is dd_le. */
+static int mp_le(int K, mpv a, mpv b)
+{
+    int c;
+    for (c = 0; c < K; ++c) {
+        if (a.c[c] < b.c[c]) return 1;
+        if (!(a.c[c] == b.c[c])) return 0;
+    }
+    return 1;
+}
+
+/* K-component division a / b.  DD: Dekker's division (dd_div).  TD / QD: long
+ * division after Hida, Li and Bailey's quad-double division, written with the
+ * K-component operations: q0 = a0 / b0; three times r = r - b * q_i (a K-component
+ * times binary64 product and a K-component addition, starting from r = a) and
+ * q_{i+1} = r0 / b0; the quotient is the renormalisation of (q0, q1, q2, q3) (Renorm
+ * 5 -> 4 with a zero fifth term), truncated to three components for TD. */
+static mpv mp_div(int K, mpv a, mpv b)
+{
+    double q[4];
+    mpv r, out;
+    int i;
+    if (K == 2) return dd_div(a, b);
+    r = a;
+    for (i = 0; i < 4; ++i) {
+        q[i] = r.c[0] / b.c[0];
+        if (i < 3) r = mp_add(K, r, mp_neg(mp_mul_d(K, b, q[i])));
+    }
+    out = renorm5(q[0], q[1], q[2], q[3], 0.0);
+    return K == 3 ? td_trunc(out) : out;
+}
+
+/* The dot product tree of dd_dot_vec (one function for every K). */
+static mpv mp_dot_vec(int K, int64_t n, const double *x, const double *y) { return dot_tree(K, n, x, y); }
+
+int oracle_mp_div(int K, const double *a, const double *b, double *out)
+{
+    mpv x = {{0.0, 0.0, 0.0, 0.0}}, y = {{0.0, 0.0, 0.0, 0.0}}, r;
+    int c;
+    for (c = 0; c < K; ++c) { x.c[c] = a[c]; y.c[c] = b[c]; }
+    r = mp_div(K, x, y);
+    for (c = 0; c < K; ++c) out[c] = r.c[c];
+    return 0;
+}
+
+int oracle_mp_dot(int K, int64_t n, const double *x, const double *y, double *out)
+{
+    mpv d = mp_dot_vec(K, n, x, y);
+    int c;
+    for (c = 0; c < K; ++c) out[c] = d.c[c];
+    return 0;
+}
+
+typedef struct {
+    int K;
+    int64_t n, nnz;
+    const int32_t *row_ptr, *col_idx;
+    const uint8_t *log2w;
+    const double *a;
+} mp_mat;
+
+static void mpm_spmv(const mp_mat *M, const double *x, double *y)
+{
+    oracle_spmv(M->K, M->n, M->n, M->nnz, M->row_ptr, M->col_idx, M->log2w, M->a, NULL, x, NULL, y, NULL,
+                0, NULL, 0);
+}
+
+static mpv ldk(const mp_mat *M, const double *v, int64_t i) { return load_mp(M->K, v, M->n, i); }
+static void stk(const mp_mat *M, double *v, int64_t i, mpv x) { store_mp(M->K, v, M->n, i, x); }
+
+static void mpm_residual(const mp_mat *M, const double *b, const double *x, double *q, double *r)
+{
+    int64_t i;
+    mpm_spmv(M, x, q);
+    for (i = 0; i < M->n; ++i) stk(M, r, i, mp_add(M->K, ldk(M, b, i), mp_neg(ldk(M, q, i))));
+}
+
+static void mpm_precond(const mp_mat *M, const double *minv, const double *r, double *z)
+{
+    int64_t i;
+    for (i = 0; i < M->n; ++i) stk(M, z, i, minv ? mp_mul_d(M->K, ldk(M, r, i), minv[i]) : ldk(M, r, i));
+}
+
+static void mpm_info(const mp_mat *M, oracle_solve_info *info, int status, int32_t k, mpv rr, mpv bb)
+{
+    (void)M;
+    info->status = status;
+    info->iters = k;
+    info->rr_true[0] = rr.c[0]; info->rr_true[1] = rr.c[1];
+    info->bb[0] = bb.c[0]; info->bb[1] = bb.c[1];
+}
+
+/*
+ * Preconditioned CG in K-component arithmetic: the steps, stopping rule, confirmation
+ * and restarts of oracle_cg with mp_add / mp_mul / mp_mul_d / mp_div / mp_dot_vec /
+ * mp_le for K components (vectors K * n, planar).  For K = 2 it is oracle_cg.  The
+ * info record carries the two leading components of rr_true and bb.
+ */
+int oracle_cg_k(int K, int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx, const uint8_t *log2w,
+                const double *a, const double *b, double *x, const double *minv, double rtol, int32_t max_iter,
+                oracle_solve_info *info, double *hist)
+{
+    mp_mat M = {K, n, nnz, row_ptr, col_idx, log2w, a};
+    size_t vb = sizeof(double) * (size_t)K * (size_t)n;
+    double *r = (double *)malloc(vb), *z = (double *)malloc(vb), *p = (double *)malloc(vb), *q = (double *)malloc(vb);
+    mpv rho, rr, bb, tol2, pq, alpha, beta, rho_new;
+    int64_t i;
+    int32_t k = 0;
+    int status = -5;
+    memset(info, 0, sizeof(*info));
+    bb = mp_dot_vec(K, n, b, b);
+    tol2 = mp_mul_d(K, bb, rtol * rtol);
+    mpm_residual(&M, b, x, q, r);
+    mpm_precond(&M, minv, r, z);
+    memcpy(p, z, vb);
+    rho = mp_dot_vec(K, n, r, z);
+    rr = mp_dot_vec(K, n, r, r);
+    if (hist) { hist[0] = rr.c[0]; hist[1] = rr.c[1]; }
+    for (;;) {
+        if (mp_le(K, rr, tol2)) {
+            mpm_residual(&M, b, x, q, r);
+            rr = mp_dot_vec(K, n, r, r);
+            if (mp_le(K, rr, tol2)) { status = 0; break; }
+            info->restarts++;
+            mpm_precond(&M, minv, r, z);
+            memcpy(p, z, vb);
+            rho = mp_dot_vec(K, n, r, z);
+        }
+        if (k >= max_iter) break;
+        mpm_spmv(&M, p, q);
+        pq = mp_dot_vec(K, n, p, q);
+        if (!(pq.c[0] > 0.0) || !isfinite(pq.c[0])) { status = -6; break; }
+        alpha = mp_div(K, rho, pq);
+        for (i = 0; i < n; ++i) {
+            stk(&M, x, i, mp_add(K, ldk(&M, x, i), mp_mul(K, alpha, ldk(&M, p, i))));
+            stk(&M, r, i, mp_add(K, ldk(&M, r, i), mp_neg(mp_mul(K, alpha, ldk(&M, q, i)))));
+        }
+        mpm_precond(&M, minv, r, z);
+        rho_new = mp_dot_vec(K, n, r, z);
+        rr = mp_dot_vec(K, n, r, r);
+        k++;
+        if (hist) { hist[2 * k] = rr.c[0]; hist[2 * k + 1] = rr.c[1]; }
+        if (!isfinite(rr.c[0]) || !isfinite(rho_new.c[0])) { status = -6; break; }
+        beta = mp_div(K, rho_new, rho);
+        rho = rho_new;
+        for (i = 0; i < n; ++i) stk(&M, p, i, mp_add(K, ldk(&M, z, i), mp_mul(K, beta, ldk(&M, p, i))));
+    }
+    mpm_residual(&M, b, x, q, r);
+    rr = mp_dot_vec(K, n, r, r);
+    mpm_info(&M, info, status, k, rr, bb);
+    free(r); free(z); free(p); free(q);
+    return status;
+}
+
+/*
+ * BiCGSTAB in K-component arithmetic: the steps of oracle_bicgstab (right Jacobi
+ * preconditioning, shadow r0, half-step test on (s, s), restarts) with K-component
+ * operations.  For K = 2 it is oracle_bicgstab.
+ */
+int oracle_bicgstab_k(int K, int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                      const uint8_t *log2w, const double *a, const double *b, double *x, const double *minv,
+                      double rtol, int32_t max_iter, oracle_solve_info *info, double *hist)
+{
+    mp_mat M = {K, n, nnz, row_ptr, col_idx, log2w, a};
+    size_t vb = sizeof(double) * (size_t)K * (size_t)n;
+    double *r = (double *)malloc(vb), *rh = (double *)malloc(vb), *p = (double *)malloc(vb);
+    double *v = (double *)malloc(vb), *ph = (double *)malloc(vb), *s = (double *)malloc(vb);
+    double *sh = (double *)malloc(vb), *t = (double *)malloc(vb), *q = (double *)malloc(vb);
+    mpv one = {{1.0, 0.0, 0.0, 0.0}};
+    mpv rho_old = one, alpha = one, omega = one, rho, beta, rv, ts, tt, rr, ss, bb, tol2;
+    int64_t i;
+    int32_t k = 0;
+    int status = -5, fresh = 1;
+    memset(info, 0, sizeof(*info));
+    bb = mp_dot_vec(K, n, b, b);
+    tol2 = mp_mul_d(K, bb, rtol * rtol);
+    mpm_residual(&M, b, x, q, r);
+    memcpy(rh, r, vb);
+    memset(v, 0, vb);
+    memset(p, 0, vb);
+    rr = mp_dot_vec(K, n, r, r);
+    if (hist) { hist[0] = rr.c[0]; hist[1] = rr.c[1]; }
+    for (;;) {
+        if (mp_le(K, rr, tol2)) {
+            mpm_residual(&M, b, x, q, r);
+            rr = mp_dot_vec(K, n, r, r);
+            if (mp_le(K, rr, tol2)) { status = 0; break; }
+            info->restarts++;
+            memcpy(rh, r, vb);
+            fresh = 1;
+        }
+        if (k >= max_iter) break;
+        rho = mp_dot_vec(K, n, rh, r);
+        if (rho.c[0] == 0.0 || !isfinite(rho.c[0])) { status = -6; break; }
+        if (fresh) {
+            memcpy(p, r, vb);
+            fresh = 0;
+        } else {
+            beta = mp_mul(K, mp_div(K, rho, rho_old), mp_div(K, alpha, omega));
+            for (i = 0; i < n; ++i) {
+                mpv pv = mp_add(K, ldk(&M, p, i), mp_neg(mp_mul(K, omega, ldk(&M, v, i))));
+                stk(&M, p, i, mp_add(K, ldk(&M, r, i), mp_mul(K, beta, pv)));
+            }
+        }
+        mpm_precond(&M, minv, p, ph);
+        mpm_spmv(&M, ph, v);
+        rv = mp_dot_vec(K, n, rh, v);
+        if (rv.c[0] == 0.0 || !isfinite(rv.c[0])) { status = -6; break; }
+        alpha = mp_div(K, rho, rv);
+        for (i = 0; i < n; ++i) stk(&M, s, i, mp_add(K, ldk(&M, r, i), mp_neg(mp_mul(K, alpha, ldk(&M, v, i)))));
+        ss = mp_dot_vec(K, n, s, s);
+        k++;
+        if (mp_le(K, ss, tol2)) {
+            for (i = 0; i < n; ++i) stk(&M, x, i, mp_add(K, ldk(&M, x, i), mp_mul(K, alpha, ldk(&M, ph, i))));
+            memcpy(r, s, vb);
+            rr = ss;
+            if (hist) { hist[2 * k] = rr.c[0]; hist[2 * k + 1] = rr.c[1]; }
+            rho_old = rho;
+            omega = one;
+            fresh = 1;
+            continue;
+        }
+        mpm_precond(&M, minv, s, sh);
+        mpm_spmv(&M, sh, t);
+        ts = mp_dot_vec(K, n, t, s);
+        tt = mp_dot_vec(K, n, t, t);
+        if (tt.c[0] == 0.0 || !isfinite(tt.c[0])) { status = -6; break; }
+        omega = mp_div(K, ts, tt);
+        for (i = 0; i < n; ++i) {
+            mpv xv = mp_add(K, ldk(&M, x, i), mp_mul(K, alpha, ldk(&M, ph, i)));
+            stk(&M, x, i, mp_add(K, xv, mp_mul(K, omega, ldk(&M, sh, i))));
+            stk(&M, r, i, mp_add(K, ldk(&M, s, i), mp_neg(mp_mul(K, omega, ldk(&M, t, i)))));
+        }
+        rr = mp_dot_vec(K, n, r, r);
+        if (hist) { hist[2 * k] = rr.c[0]; hist[2 * k + 1] = rr.c[1]; }
+        if (!isfinite(rr.c[0])) { status = -6; break; }
+        if (omega.c[0] == 0.0) { status = -6; break; }
+        rho_old = rho;
+    }
+    mpm_residual(&M, b, x, q, r);
+    rr = mp_dot_vec(K, n, r, r);
+    mpm_info(&M, info, status, k, rr, bb);
+    free(r); free(rh); free(p); free(v); free(ph); free(s); free(sh); free(t); free(q);
+    return status;
+}
+
+int oracle_mp_le(int K, const double *a, const double *b)
+{
+    mpv x = {{0.0, 0.0, 0.0, 0.0}}, y = {{0.0, 0.0, 0.0, 0.0}};
+    int c;
+    for (c = 0; c < K; ++c) { x.c[c] = a[c]; y.c[c] = b[c]; }
+    return mp_le(K, x, y);
 }

@@ -209,6 +209,14 @@ def _krylov_sigs():
     L.oracle_bicg.argtypes = [i64, i64, P, P, P, P, P, P, P, P, P, P, P, ctypes.c_double, ctypes.c_int32,
                               ctypes.POINTER(SolveInfo), P]
     L.oracle_bicg.restype = ctypes.c_int
+    for f in (L.oracle_cg_k, L.oracle_bicgstab_k):
+        f.argtypes = [ctypes.c_int, i64, i64, P, P, P, P, P, P, P, ctypes.c_double, ctypes.c_int32,
+                      ctypes.POINTER(SolveInfo), P]
+        f.restype = ctypes.c_int
+    L.oracle_mp_div.argtypes = [ctypes.c_int, P, P, P]
+    L.oracle_mp_dot.argtypes = [ctypes.c_int, i64, P, P, P]
+    L.oracle_mp_le.argtypes = [ctypes.c_int, P, P]
+    L.oracle_mp_le.restype = ctypes.c_int
     L._krylov_ready = True
     return L
 
@@ -258,6 +266,63 @@ def _solve(fn, row_ptr, col_idx, a, b, x0, precond, rtol, max_iter, log2w, histo
     if history:
         out["history"] = hist[:2 * (info.iters + 1)].reshape(-1, 2)
     return x, out
+
+
+def mp_div(K, a, b):
+    """K-component a / b (DD: Dekker; TD/QD: long division).  Returns K components."""
+    L = _krylov_sigs()
+    a, b = _f64(a), _f64(b)
+    out = np.zeros(K)
+    L.oracle_mp_div(K, _p(a), _p(b), _p(out))
+    return out
+
+
+def mp_le(K, a, b):
+    """The solvers' stop comparison a <= b of K-component values (lexicographic)."""
+    L = _krylov_sigs()
+    return bool(L.oracle_mp_le(K, _p(_f64(a)), _p(_f64(b))))
+
+
+def mp_dot(K, x, y):
+    """K-component dot product of (K, n) vectors with the fixed tree."""
+    L = _krylov_sigs()
+    x, y = _f64(x), _f64(y)
+    out = np.zeros(K)
+    L.oracle_mp_dot(K, x.shape[1], _p(x), _p(y), _p(out))
+    return out
+
+
+def _solve_k(fn, K, row_ptr, col_idx, a, b, x0, precond, rtol, max_iter, log2w, history):
+    L = _krylov_sigs()
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
+    a, b = _f64(a), _f64(b)
+    n = row_ptr.size - 1
+    assert a.shape == (K, col_idx.size) and b.shape == (K, n)
+    x = np.array(x0, dtype=np.float64, order="C", copy=True) if x0 is not None else np.zeros((K, n))
+    minv = jacobi_minv(row_ptr, col_idx, a[0]) if precond == "jacobi" else None
+    lw = None if log2w is None else np.ascontiguousarray(log2w, dtype=np.uint8)
+    hist = np.zeros(2 * (max_iter + 1)) if history else None
+    info = SolveInfo()
+    getattr(L, fn)(K, n, col_idx.size, _p(row_ptr), _p(col_idx), _p(lw), _p(a), _p(b), _p(x), _p(minv),
+                   float(rtol), int(max_iter), ctypes.byref(info), _p(hist))
+    out = {"status": info.status, "iters": info.iters, "restarts": info.restarts,
+           "rr_true": np.array(info.rr_true[:]), "bb": np.array(info.bb[:])}
+    if history:
+        out["history"] = hist[:2 * (info.iters + 1)].reshape(-1, 2)
+    return x, out
+
+
+def cg_k(K, row_ptr, col_idx, a, b, x0=None, precond="jacobi", rtol=1e-28, max_iter=10000, log2w=None,
+         history=False):
+    """K-component preconditioned CG (oracle; K = 2 is cg).  a, b, x: (K, len)."""
+    return _solve_k("oracle_cg_k", K, row_ptr, col_idx, a, b, x0, precond, rtol, max_iter, log2w, history)
+
+
+def bicgstab_k(K, row_ptr, col_idx, a, b, x0=None, precond="jacobi", rtol=1e-28, max_iter=10000, log2w=None,
+               history=False):
+    """K-component BiCGSTAB (oracle; K = 2 is bicgstab).  a, b, x: (K, len)."""
+    return _solve_k("oracle_bicgstab_k", K, row_ptr, col_idx, a, b, x0, precond, rtol, max_iter, log2w, history)
 
 
 def cg(row_ptr, col_idx, a, b, x0=None, precond="jacobi", rtol=1e-28, max_iter=10000, log2w=None,
