@@ -303,6 +303,34 @@ mp_status mpkrylov_cgs(const mp_csr *A, const double *a, const double *b, double
                        const mp_plan *plan, void *ws, size_t ws_bytes, mp_solve_info *info, void *stream);
 
 /*
+ * CG and BiCGSTAB in triple-double (_td, K = 3) and quad-double (_qd, K = 4): Sec. 4.2
+ * runs the Krylov methods in every precision.  The steps, stopping rule, confirmation,
+ * restarts and breakdown rules are those of mpkrylov_cg / mpkrylov_bicgstab with
+ * K-component operations: add and mul (TD = the QD operation on zero-padded values,
+ * three components kept), K-component times binary64 (Jacobi, Algs 4-5), division by
+ * long division (q0 = a0/b0, three times r = r - b*q_i and q_{i+1} = r0/b0, the
+ * quotient the 5 -> 4 renormalisation of q0..q3, truncated to three components for
+ * TD), stop tests by lexicographic comparison of the components, and the dot
+ * product tree of the DD solvers.  a: K*nnz values (component-planar); b, x: K*n;
+ * plan: NULL or a K-component real plan of A; ws: device workspace of at least
+ * mpkrylov_mp_workspace_bytes(A, K) bytes, 256-byte aligned; n <= 4,194,304.  info
+ * carries the two leading components of rr_true and bb (relres from the leading
+ * ones).  Synchronises `stream`.  Returns MP_OK, MP_ERR_NOT_CONVERGED,
+ * MP_ERR_BREAKDOWN or an argument / HIP error (as mpkrylov_cg).
+ */
+mp_status mpkrylov_mp_workspace_bytes(const mp_csr *A, int32_t ncomp, size_t *bytes);
+mp_status mpkrylov_cg_td(const mp_csr *A, const double *a, const double *b, double *x, const mp_solve_opts *opts,
+                         const mp_plan *plan, void *ws, size_t ws_bytes, mp_solve_info *info, void *stream);
+mp_status mpkrylov_cg_qd(const mp_csr *A, const double *a, const double *b, double *x, const mp_solve_opts *opts,
+                         const mp_plan *plan, void *ws, size_t ws_bytes, mp_solve_info *info, void *stream);
+mp_status mpkrylov_bicgstab_td(const mp_csr *A, const double *a, const double *b, double *x,
+                               const mp_solve_opts *opts, const mp_plan *plan, void *ws, size_t ws_bytes,
+                               mp_solve_info *info, void *stream);
+mp_status mpkrylov_bicgstab_qd(const mp_csr *A, const double *a, const double *b, double *x,
+                               const mp_solve_opts *opts, const mp_plan *plan, void *ws, size_t ws_bytes,
+                               mp_solve_info *info, void *stream);
+
+/*
  * DD GPBiCG (Zhang's generalized product-type method based on BiCG; Sec. 4.2's list)
  * with right Jacobi preconditioning (opts.precond; every product with A is one with
  * A M and x collects M times the corrections, so r is the residual of A x = b).

@@ -17,7 +17,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmpsparse.so")
 
-SOURCES = ["common.cpp", "plan.cpp", "spmv.hip", "krylov.hip", "batched.hip", "learned.hip", "transpose.hip"]
+SOURCES = ["common.cpp", "plan.cpp", "spmv.hip", "krylov.hip", "krylov_mp.hip", "batched.hip", "learned.hip",
+           "transpose.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

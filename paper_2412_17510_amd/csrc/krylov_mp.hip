@@ -1,0 +1,900 @@
+// krylov_mp.hip -- CG and BiCGSTAB in triple-double and quad-double (Sec. 4.2 runs
+// the Krylov methods in DD, TD and QD on top of the multi-component SpMV).
+//
+// The steps, stopping rule, confirmation and restarts are those of the DD solvers
+// (krylov.hip) with K-component operations: additions, products and products with a
+// binary64 (TD = the QD operation on zero-padded values, three components kept),
+// a K-component division (long division: q0 = a0/b0, three times r = r - b*q_i and
+// q_{i+1} = r0/b0, then the renormalisation of q0..q3), a lexicographic comparison for
+// the stop tests, and the dot product tree of the DD solvers (chunks of 4096, 256
+// strided lanes, halving fold, pairwise tree over the chunk sums).  The kernels are
+// plain (one vector operation per launch): at these precisions the arithmetic, not the
+// launch sequence, dominates a step.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "common.hpp"
+#include "mp_arith.hpp"
+#include "plan.hpp"
+
+namespace mpk {
+namespace kmp {
+
+constexpr int kLanes = 256;
+constexpr int kChunk = 4096;
+constexpr int kMaxChunks = 1024;   // n <= 4,194,304 (the chunk sums of a QD dot fit 32 KiB of LDS)
+
+enum : int32_t { RUN = 0, RECURRENCE_MET = 1, BROKE_DOWN = 2, ITER_LIMIT = 3, CONFIRMED = 4, RESTART = 5 };
+
+template <int K>
+struct State {
+    mpn<K> rho, rho_old, rr, bb, tol2, pq, alpha, beta, omega, rv, ss, ts, tt, rr_true;
+    int32_t done;
+    int32_t iters;
+    int32_t max_iter;
+    int32_t fresh;
+    int32_t half;
+    int32_t restarts;
+};
+
+template <int K>
+__device__ __forceinline__ mpn<K> ldk(const double *__restrict__ v, int64_t n, int64_t i)
+{
+    mpn<K> r;
+#pragma unroll
+    for (int c = 0; c < K; ++c) r.c[c] = v[c * n + i];
+    return r;
+}
+
+template <int K>
+__device__ __forceinline__ void stk(double *__restrict__ v, int64_t n, int64_t i, const mpn<K> &x)
+{
+#pragma unroll
+    for (int c = 0; c < K; ++c) v[c * n + i] = x.c[c];
+}
+
+template <int K>
+__device__ __forceinline__ mpn<K> k_sub(const mpn<K> &a, const mpn<K> &b)
+{
+    return mp_add(a, mp_neg(b));
+}
+
+template <int K>
+__device__ __forceinline__ bool k_finite(const mpn<K> &a)
+{
+    return isfinite(a.c[0]);
+}
+
+// a <= b: the first component that differs decides; a comparison that is not an
+// equality (greater, or a NaN) is false
+template <int K>
+__device__ __forceinline__ bool k_le(const mpn<K> &a, const mpn<K> &b)
+{
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        if (a.c[c] < b.c[c]) return true;
+        if (!(a.c[c] == b.c[c])) return false;
+    }
+    return true;
+}
+
+// a / b by long division (TD: the QD division of the zero-padded values, three
+// components kept)
+template <int K>
+__device__ __forceinline__ mpn<K> k_div(const mpn<K> &a, const mpn<K> &b)
+{
+    double q[4];
+    mpn<K> r = a;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        q[i] = r.c[0] / b.c[0];
+        if (i < 3) r = mp_add(r, mp_neg(mp_mul_d(b, q[i])));
+    }
+    const qd_t o = renorm5(q[0], q[1], q[2], q[3], 0.0);
+    mpn<K> out;
+#pragma unroll
+    for (int c = 0; c < K; ++c) out.c[c] = o.c[c];
+    return out;
+}
+
+template <int K>
+__device__ __forceinline__ mpn<K> k_one()
+{
+    mpn<K> r = mp_zero<K>();
+    r.c[0] = 1.0;
+    return r;
+}
+
+// lane sums of one chunk -> fold acc[l] += acc[l+off] (off = 128..1) over the lanes
+// that hold elements; returns lds[0] to every thread
+template <int K>
+__device__ __forceinline__ mpn<K> chunk_fold(const mpn<K> &v, int used, mpn<K> *lds)
+{
+    const int t = threadIdx.x;
+    lds[t] = v;
+    __syncthreads();
+    for (int off = kLanes / 2; off >= 1; off >>= 1) {
+        if (t < off && t + off < used) lds[t] = mp_add(lds[t], lds[t + off]);
+        __syncthreads();
+    }
+    const mpn<K> r = lds[0];
+    __syncthreads();
+    return r;
+}
+
+// pairwise tree over m chunk sums (one workgroup of 256 threads)
+template <int K>
+__device__ __forceinline__ mpn<K> pair_tree(const mpn<K> *__restrict__ part, int m, mpn<K> *P)
+{
+    const int t = threadIdx.x;
+    for (int i = t; i < m; i += kLanes) P[i] = part[i];
+    __syncthreads();
+    for (int s = 1; s < m; s <<= 1) {
+        for (int i = t; (int64_t)i * 2 * s + s < m; i += kLanes) P[i * 2 * s] = mp_add(P[i * 2 * s], P[i * 2 * s + s]);
+        __syncthreads();
+    }
+    const mpn<K> r = m > 0 ? P[0] : mp_zero<K>();
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ int chunk_used(int64_t n, int c)
+{
+    const int64_t left = n - (int64_t)c * kChunk;
+    return left < kLanes ? (int)left : kLanes;
+}
+
+// chunk sums of (x1, y1) and optionally (x2, y2): lane l of chunk c adds the products of
+// elements c*4096 + l + 256 j in j order, starting from its first product
+template <int K>
+__global__ __launch_bounds__(256) void k_dot2(int64_t n, const double *__restrict__ x1, const double *__restrict__ y1,
+                                              const double *__restrict__ x2, const double *__restrict__ y2,
+                                              mpn<K> *__restrict__ p1, mpn<K> *__restrict__ p2,
+                                              const State<K> *__restrict__ st)
+{
+    __shared__ mpn<K> lds[kLanes];
+    if (st && st->done != RUN) return;
+    const int c = blockIdx.x;
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)c * kChunk;
+    const int64_t end = (n - base) < kChunk ? n : base + kChunk;
+    mpn<K> a1 = mp_zero<K>(), a2 = mp_zero<K>();
+    bool first = true;
+    for (int64_t k = base + t; k < end; k += kLanes) {
+        const mpn<K> q1 = mp_mul(ldk<K>(x1, n, k), ldk<K>(y1, n, k));
+        a1 = first ? q1 : mp_add(a1, q1);
+        if (x2) {
+            const mpn<K> q2 = mp_mul(ldk<K>(x2, n, k), ldk<K>(y2, n, k));
+            a2 = first ? q2 : mp_add(a2, q2);
+        }
+        first = false;
+    }
+    const int used = chunk_used(n, c);
+    const mpn<K> s1 = chunk_fold(a1, used, lds);
+    if (t == 0) p1[c] = s1;
+    if (x2) {
+        const mpn<K> s2 = chunk_fold(a2, used, lds);
+        if (t == 0) p2[c] = s2;
+    }
+}
+
+#define KMP_FOR(i, n) for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < (n); i += (int64_t)gridDim.x * 256)
+
+// r = b - q
+template <int K>
+__global__ __launch_bounds__(256) void k_residual(int64_t n, const double *__restrict__ b, const double *__restrict__ q,
+                                                  double *__restrict__ r)
+{
+    KMP_FOR(i, n) stk<K>(r, n, i, k_sub(ldk<K>(b, n, i), ldk<K>(q, n, i)));
+}
+
+// z = M^-1 r (Jacobi: K components times the binary64 inverse diagonal) or a copy
+template <int K>
+__global__ __launch_bounds__(256) void k_precond(int64_t n, const double *__restrict__ minv, const double *__restrict__ r,
+                                                 double *__restrict__ z, const State<K> *__restrict__ st)
+{
+    if (st && st->done != RUN) return;
+    KMP_FOR(i, n) stk<K>(z, n, i, minv ? mp_mul_d(ldk<K>(r, n, i), minv[i]) : ldk<K>(r, n, i));
+}
+
+__global__ __launch_bounds__(256) void k_copy(int64_t len, const double *__restrict__ src, double *__restrict__ dst)
+{
+    KMP_FOR(i, len) dst[i] = src[i];
+}
+
+// Jacobi inverse diagonal fl(1 / leading component of a_ii); 1 without a diagonal entry
+__global__ __launch_bounds__(256) void k_jacobi_minv(int64_t n, const int32_t *__restrict__ rp,
+                                                     const int32_t *__restrict__ ci, const double *__restrict__ a_hi,
+                                                     double *__restrict__ minv)
+{
+    KMP_FOR(i, n)
+    {
+        double m = 1.0;
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+            if (ci[k] == i) m = 1.0 / a_hi[k];
+        minv[i] = m;
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_confirm(const mpn<K> *__restrict__ part, int m, State<K> *__restrict__ st)
+{
+    __shared__ mpn<K> P[kMaxChunks];
+    const mpn<K> rr = pair_tree(part, m, P);
+    if (threadIdx.x == 0) {
+        st->rr_true = rr;
+        if (k_le(rr, st->tol2)) {
+            st->done = CONFIRMED;
+        } else {
+            st->rr = rr;
+            st->restarts += 1;
+            st->done = RESTART;
+        }
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_exit_rr(const mpn<K> *__restrict__ part, int m, State<K> *__restrict__ st)
+{
+    __shared__ mpn<K> P[kMaxChunks];
+    const mpn<K> rr = pair_tree(part, m, P);
+    if (threadIdx.x == 0) st->rr_true = rr;
+}
+
+// ---------------------------------------------------------------------------
+// CG
+// ---------------------------------------------------------------------------
+
+template <int K>
+__global__ __launch_bounds__(256) void k_cg_init(const mpn<K> *__restrict__ pbb, const mpn<K> *__restrict__ prz,
+                                                 const mpn<K> *__restrict__ prr, int m, double rtol2, int32_t max_iter,
+                                                 State<K> *__restrict__ st)
+{
+    __shared__ mpn<K> P[kMaxChunks];
+    const mpn<K> bb = pair_tree(pbb, m, P);
+    const mpn<K> rz = pair_tree(prz, m, P);
+    const mpn<K> rr = pair_tree(prr, m, P);
+    if (threadIdx.x == 0) {
+        st->bb = bb;
+        st->tol2 = mp_mul_d(bb, rtol2);
+        st->rho = rz;
+        st->rr = rr;
+        st->iters = 0;
+        st->max_iter = max_iter;
+        st->restarts = 0;
+        st->done = k_le(rr, st->tol2) ? RECURRENCE_MET : (max_iter <= 0 ? ITER_LIMIT : RUN);
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_cg_restart(const mpn<K> *__restrict__ prz, int m, State<K> *__restrict__ st)
+{
+    __shared__ mpn<K> P[kMaxChunks];
+    const mpn<K> rz = pair_tree(prz, m, P);
+    if (threadIdx.x == 0) {
+        st->rho = rz;
+        st->done = st->iters >= st->max_iter ? ITER_LIMIT : RUN;
+    }
+}
+
+// alpha = rho / (p, q); breakdown unless (p, q) > 0 and finite
+template <int K>
+__global__ __launch_bounds__(256) void k_cg_alpha(const mpn<K> *__restrict__ ppq, int m, State<K> *__restrict__ st)
+{
+    __shared__ mpn<K> P[kMaxChunks];
+    if (st->done != RUN) return;
+    const mpn<K> pq = pair_tree(ppq, m, P);
+    if (threadIdx.x == 0) {
+        st->pq = pq;
+        if (!(pq.c[0] > 0.0) || !k_finite(pq))
+            st->done = BROKE_DOWN;
+        else
+            st->alpha = k_div(st->rho, pq);
+    }
+}
+
+// x += alpha p; r -= alpha q
+template <int K>
+__global__ __launch_bounds__(256) void k_cg_xr(int64_t n, double *__restrict__ x, double *__restrict__ r,
+                                               const double *__restrict__ p, const double *__restrict__ q,
+                                               const State<K> *__restrict__ st)
+{
+    if (st->done != RUN) return;
+    const mpn<K> alpha = st->alpha;
+    KMP_FOR(i, n)
+    {
+        stk<K>(x, n, i, mp_add(ldk<K>(x, n, i), mp_mul(alpha, ldk<K>(p, n, i))));
+        stk<K>(r, n, i, k_sub(ldk<K>(r, n, i), mp_mul(alpha, ldk<K>(q, n, i))));
+    }
+}
+
+// rho_new = (r, z), rr = (r, r): one step counted; breakdown when not finite;
+// beta = rho_new / rho; stop tests
+template <int K>
+__global__ __launch_bounds__(256) void k_cg_beta(const mpn<K> *__restrict__ prz, const mpn<K> *__restrict__ prr, int m,
+                                                 State<K> *__restrict__ st)
+{
+    __shared__ mpn<K> P[kMaxChunks];
+    if (st->done != RUN) return;
+    const mpn<K> rz = pair_tree(prz, m, P);
+    const mpn<K> rr = pair_tree(prr, m, P);
+    if (threadIdx.x == 0) {
+        st->iters += 1;
+        st->rr = rr;
+        if (!k_finite(rr) || !k_finite(rz)) {
+            st->done = BROKE_DOWN;
+            return;
+        }
+        st->beta = k_div(rz, st->rho);
+        st->rho = rz;
+        st->half = 1;   // p is to be updated
+        if (k_le(rr, st->tol2))
+            st->done = RECURRENCE_MET;
+        else if (st->iters >= st->max_iter)
+            st->done = ITER_LIMIT;
+    }
+}
+
+// p = z + beta p (after a completed step, whatever the stop tests decided)
+template <int K>
+__global__ __launch_bounds__(256) void k_cg_p(int64_t n, const double *__restrict__ z, double *__restrict__ p,
+                                              State<K> *__restrict__ st)
+{
+    if (!st->half) return;
+    const mpn<K> beta = st->beta;
+    KMP_FOR(i, n) stk<K>(p, n, i, mp_add(ldk<K>(z, n, i), mp_mul(beta, ldk<K>(p, n, i))));
+}
+
+template <int K>
+__global__ __launch_bounds__(64) void k_cg_p_done(State<K> *__restrict__ st)
+{
+    if (threadIdx.x == 0) st->half = 0;
+}
+
+// ---------------------------------------------------------------------------
+// BiCGSTAB (right Jacobi preconditioning, shadow r0)
+// ---------------------------------------------------------------------------
+
+template <int K>
+__global__ __launch_bounds__(256) void k_bi_init(const mpn<K> *__restrict__ pbb, const mpn<K> *__restrict__ prr, int m,
+                                                 double rtol2, int32_t max_iter, State<K> *__restrict__ st)
+{
+    __shared__ mpn<K> P[kMaxChunks];
+    const mpn<K> bb = pair_tree(pbb, m, P);
+    const mpn<K> rr = pair_tree(prr, m, P);
+    if (threadIdx.x == 0) {
+        st->bb = bb;
+        st->tol2 = mp_mul_d(bb, rtol2);
+        st->rr = rr;
+        st->rho_old = k_one<K>();
+        st->alpha = k_one<K>();
+        st->omega = k_one<K>();
+        st->iters = 0;
+        st->max_iter = max_iter;
+        st->restarts = 0;
+        st->fresh = 1;
+        st->half = 0;
+        st->done = k_le(rr, st->tol2) ? RECURRENCE_MET : (max_iter <= 0 ? ITER_LIMIT : RUN);
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(64) void k_bi_restart(State<K> *__restrict__ st)
+{
+    if (threadIdx.x == 0) {
+        st->fresh = 1;
+        st->done = st->iters >= st->max_iter ? ITER_LIMIT : RUN;
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_bi_rho(const mpn<K> *__restrict__ part, int m, State<K> *__restrict__ st)
+{
+    __shared__ mpn<K> P[kMaxChunks];
+    if (st->done != RUN) return;
+    const mpn<K> rho = pair_tree(part, m, P);
+    if (threadIdx.x == 0) {
+        st->rho = rho;
+        if (rho.c[0] == 0.0 || !k_finite(rho)) {
+            st->done = BROKE_DOWN;
+            return;
+        }
+        if (!st->fresh) st->beta = mp_mul(k_div(rho, st->rho_old), k_div(st->alpha, st->omega));
+    }
+}
+
+// p = r (fresh) or p = r + beta (p - omega v); ph = M^-1 p
+template <int K>
+__global__ __launch_bounds__(256) void k_bi_p(int64_t n, const double *__restrict__ r, double *__restrict__ p,
+                                              const double *__restrict__ v, double *__restrict__ ph,
+                                              const double *__restrict__ minv, const State<K> *__restrict__ st)
+{
+    if (st->done != RUN) return;
+    const bool fresh = st->fresh != 0;
+    const mpn<K> beta = st->beta, omega = st->omega;
+    KMP_FOR(i, n)
+    {
+        mpn<K> pi;
+        if (fresh) {
+            pi = ldk<K>(r, n, i);
+        } else {
+            const mpn<K> pv = k_sub(ldk<K>(p, n, i), mp_mul(omega, ldk<K>(v, n, i)));
+            pi = mp_add(ldk<K>(r, n, i), mp_mul(beta, pv));
+        }
+        stk<K>(p, n, i, pi);
+        stk<K>(ph, n, i, minv ? mp_mul_d(pi, minv[i]) : pi);
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_bi_alpha(const mpn<K> *__restrict__ part, int m, State<K> *__restrict__ st)
+{
+    __shared__ mpn<K> P[kMaxChunks];
+    if (st->done != RUN) return;
+    const mpn<K> rv = pair_tree(part, m, P);
+    if (threadIdx.x == 0) {
+        st->fresh = 0;
+        st->rv = rv;
+        if (rv.c[0] == 0.0 || !k_finite(rv)) {
+            st->done = BROKE_DOWN;
+            return;
+        }
+        st->alpha = k_div(st->rho, rv);
+    }
+}
+
+// s = r - alpha v
+template <int K>
+__global__ __launch_bounds__(256) void k_bi_s(int64_t n, const double *__restrict__ r, const double *__restrict__ v,
+                                              double *__restrict__ s, const State<K> *__restrict__ st)
+{
+    if (st->done != RUN) return;
+    const mpn<K> alpha = st->alpha;
+    KMP_FOR(i, n) stk<K>(s, n, i, k_sub(ldk<K>(r, n, i), mp_mul(alpha, ldk<K>(v, n, i))));
+}
+
+// ss = (s, s); one step counted; half-step test
+template <int K>
+__global__ __launch_bounds__(256) void k_bi_ss(const mpn<K> *__restrict__ part, int m, State<K> *__restrict__ st)
+{
+    __shared__ mpn<K> P[kMaxChunks];
+    if (st->done != RUN) return;
+    const mpn<K> ss = pair_tree(part, m, P);
+    if (threadIdx.x == 0) {
+        st->ss = ss;
+        st->iters += 1;
+        st->half = k_le(ss, st->tol2) ? 1 : 0;
+    }
+}
+
+// half step met the tolerance: x += alpha ph; r = s
+template <int K>
+__global__ __launch_bounds__(256) void k_bi_half(int64_t n, double *__restrict__ x, double *__restrict__ r,
+                                                 const double *__restrict__ ph, const double *__restrict__ s,
+                                                 const State<K> *__restrict__ st)
+{
+    if (st->done != RUN || !st->half) return;
+    const mpn<K> alpha = st->alpha;
+    KMP_FOR(i, n)
+    {
+        stk<K>(x, n, i, mp_add(ldk<K>(x, n, i), mp_mul(alpha, ldk<K>(ph, n, i))));
+        stk<K>(r, n, i, ldk<K>(s, n, i));
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(64) void k_bi_half_final(State<K> *__restrict__ st)
+{
+    if (threadIdx.x != 0 || st->done != RUN || !st->half) return;
+    st->rr = st->ss;
+    st->rho_old = st->rho;
+    st->omega = k_one<K>();
+    st->fresh = 1;
+    st->half = 0;
+    st->done = RECURRENCE_MET;
+}
+
+// omega = (t, s) / (t, t)
+template <int K>
+__global__ __launch_bounds__(256) void k_bi_omega(const mpn<K> *__restrict__ pts, const mpn<K> *__restrict__ ptt, int m,
+                                                  State<K> *__restrict__ st)
+{
+    __shared__ mpn<K> P[kMaxChunks];
+    if (st->done != RUN) return;
+    const mpn<K> ts = pair_tree(pts, m, P);
+    const mpn<K> tt = pair_tree(ptt, m, P);
+    if (threadIdx.x == 0) {
+        st->ts = ts;
+        st->tt = tt;
+        if (tt.c[0] == 0.0 || !k_finite(tt)) {
+            st->done = BROKE_DOWN;
+            return;
+        }
+        st->omega = k_div(ts, tt);
+    }
+}
+
+// x = (x + alpha ph) + omega sh; r = s - omega t
+template <int K>
+__global__ __launch_bounds__(256) void k_bi_xr(int64_t n, double *__restrict__ x, double *__restrict__ r,
+                                               const double *__restrict__ ph, const double *__restrict__ sh,
+                                               const double *__restrict__ s, const double *__restrict__ tv,
+                                               const State<K> *__restrict__ st)
+{
+    if (st->done != RUN) return;
+    const mpn<K> alpha = st->alpha, omega = st->omega;
+    KMP_FOR(i, n)
+    {
+        const mpn<K> xv = mp_add(ldk<K>(x, n, i), mp_mul(alpha, ldk<K>(ph, n, i)));
+        stk<K>(x, n, i, mp_add(xv, mp_mul(omega, ldk<K>(sh, n, i))));
+        stk<K>(r, n, i, k_sub(ldk<K>(s, n, i), mp_mul(omega, ldk<K>(tv, n, i))));
+    }
+}
+
+// rr = (r, r); breakdown when not finite or omega = 0; stop tests
+template <int K>
+__global__ __launch_bounds__(256) void k_bi_rr(const mpn<K> *__restrict__ part, int m, State<K> *__restrict__ st)
+{
+    __shared__ mpn<K> P[kMaxChunks];
+    if (st->done != RUN) return;
+    const mpn<K> rr = pair_tree(part, m, P);
+    if (threadIdx.x == 0) {
+        st->rr = rr;
+        if (!k_finite(rr) || st->omega.c[0] == 0.0) {
+            st->done = BROKE_DOWN;
+            return;
+        }
+        st->rho_old = st->rho;
+        if (k_le(rr, st->tol2))
+            st->done = RECURRENCE_MET;
+        else if (st->iters >= st->max_iter)
+            st->done = ITER_LIMIT;
+    }
+}
+
+#undef KMP_FOR
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+inline size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+template <int K>
+size_t ws_bytes(int64_t n)
+{
+    return 2 * al256(sizeof(State<K>)) + al256(sizeof(double) * (size_t)n) +
+           9 * al256(sizeof(double) * K * (size_t)n) + 3 * al256(sizeof(mpn<K>) * kMaxChunks);
+}
+
+template <int K>
+struct Solver {
+    const mp_csr *A;
+    const double *a;
+    const mp_plan *plan;
+    hipStream_t s;
+    int64_t n;
+    int m;
+    unsigned vb;
+    State<K> *st;
+    double *minv;
+    double *v[9];
+    mpn<K> *part[3];
+
+    void carve(void *ws)
+    {
+        char *p = static_cast<char *>(ws);
+        st = reinterpret_cast<State<K> *>(p);
+        p += 2 * al256(sizeof(State<K>));
+        minv = reinterpret_cast<double *>(p);
+        p += al256(sizeof(double) * (size_t)n);
+        for (int i = 0; i < 9; ++i) {
+            v[i] = reinterpret_cast<double *>(p);
+            p += al256(sizeof(double) * K * (size_t)n);
+        }
+        for (int i = 0; i < 3; ++i) {
+            part[i] = reinterpret_cast<mpn<K> *>(p);
+            p += al256(sizeof(mpn<K>) * kMaxChunks);
+        }
+    }
+    mp_status launched()
+    {
+        MP_HIP_TRY(hipGetLastError());
+        return MP_OK;
+    }
+    mp_status spmv(const double *x, double *y)
+    {
+        return spmv_dispatch(K, false, A, a, nullptr, x, nullptr, y, nullptr, plan, s);
+    }
+    mp_status dot2(const double *x1, const double *y1, const double *x2, const double *y2, mpn<K> *p1, mpn<K> *p2,
+                   const State<K> *guard)
+    {
+        hipLaunchKernelGGL(k_dot2<K>, dim3(m), dim3(256), 0, s, n, x1, y1, x2, y2, p1, p2, guard);
+        return launched();
+    }
+    mp_status residual(const double *b, const double *x, double *q, double *r)
+    {
+        mp_status e = spmv(x, q);
+        if (e != MP_OK) return e;
+        hipLaunchKernelGGL(k_residual<K>, dim3(vb), dim3(256), 0, s, n, b, q, r);
+        return launched();
+    }
+    mp_status read_state(State<K> *h)
+    {
+        MP_HIP_TRY(hipMemcpyAsync(h, st, sizeof(State<K>), hipMemcpyDeviceToHost, s));
+        MP_HIP_TRY(hipStreamSynchronize(s));
+        return MP_OK;
+    }
+    mp_status true_residual(const double *b, const double *x, double *q, double *r, bool confirm)
+    {
+        mp_status e = residual(b, x, q, r);
+        if (e == MP_OK) e = dot2(r, r, nullptr, nullptr, part[0], nullptr, nullptr);
+        if (e != MP_OK) return e;
+        if (confirm)
+            hipLaunchKernelGGL(k_confirm<K>, dim3(1), dim3(256), 0, s, part[0], m, st);
+        else
+            hipLaunchKernelGGL(k_exit_rr<K>, dim3(1), dim3(256), 0, s, part[0], m, st);
+        return launched();
+    }
+    mp_status jacobi()
+    {
+        hipLaunchKernelGGL(k_jacobi_minv, dim3(vb), dim3(256), 0, s, n, A->row_ptr, A->col_idx, a, minv);
+        return launched();
+    }
+};
+
+template <int K>
+void fill(const State<K> &h, int status, double secs, mp_solve_info *info)
+{
+    std::memset(info, 0, sizeof(*info));
+    info->status = status;
+    info->iters = h.iters;
+    info->restarts = h.restarts;
+    info->rr_true[0] = h.rr_true.c[0];
+    info->rr_true[1] = h.rr_true.c[1];
+    info->bb[0] = h.bb.c[0];
+    info->bb[1] = h.bb.c[1];
+    info->relres = h.bb.c[0] > 0 ? std::sqrt(h.rr_true.c[0] / h.bb.c[0]) : std::sqrt(h.rr_true.c[0]);
+    info->seconds = secs;
+}
+
+template <int K>
+int finish_status(const State<K> &h)
+{
+    return h.done == CONFIRMED ? MP_OK : (h.done == BROKE_DOWN ? MP_ERR_BREAKDOWN : MP_ERR_NOT_CONVERGED);
+}
+
+template <int K>
+mp_status run_cg(Solver<K> &S, const double *b, double *x, const mp_solve_opts *o, mp_solve_info *info,
+                 const char *name)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    const int64_t n = S.n;
+    const int m = S.m;
+    double *r = S.v[0], *z = S.v[1], *p = S.v[2], *q = S.v[3];
+    const double *minv = o->precond == MP_PRECOND_JACOBI ? S.minv : nullptr;
+    const int every = o->check_every > 0 ? o->check_every : 32;
+    const int64_t len = (int64_t)K * n;
+    mp_status st;
+    State<K> h;
+    std::memset(&h, 0, sizeof(h));
+    MP_HIP_TRY(hipMemsetAsync(S.st, 0, sizeof(State<K>), S.s));
+    if (minv && (st = S.jacobi()) != MP_OK) return st;
+    if ((st = S.residual(b, x, q, r)) != MP_OK) return st;
+    hipLaunchKernelGGL(k_precond<K>, dim3(S.vb), dim3(256), 0, S.s, n, minv, r, z, nullptr);
+    hipLaunchKernelGGL(k_copy, dim3(S.vb), dim3(256), 0, S.s, len, z, p);
+    if ((st = S.launched()) != MP_OK) return st;
+    if ((st = S.dot2(b, b, r, z, S.part[0], S.part[1], nullptr)) != MP_OK) return st;
+    if ((st = S.dot2(r, r, nullptr, nullptr, S.part[2], nullptr, nullptr)) != MP_OK) return st;
+    hipLaunchKernelGGL(k_cg_init<K>, dim3(1), dim3(256), 0, S.s, S.part[0], S.part[1], S.part[2], m, o->rtol * o->rtol,
+                       o->max_iter, S.st);
+    if ((st = S.launched()) != MP_OK) return st;
+    for (;;) {
+        if ((st = S.read_state(&h)) != MP_OK) return st;
+        if (h.done == RUN) {
+            for (int it = 0; it < every; ++it) {
+                if ((st = S.spmv(p, q)) != MP_OK) return st;
+                if ((st = S.dot2(p, q, nullptr, nullptr, S.part[0], nullptr, S.st)) != MP_OK) return st;
+                hipLaunchKernelGGL(k_cg_alpha<K>, dim3(1), dim3(256), 0, S.s, S.part[0], m, S.st);
+                hipLaunchKernelGGL(k_cg_xr<K>, dim3(S.vb), dim3(256), 0, S.s, n, x, r, p, q, S.st);
+                hipLaunchKernelGGL(k_precond<K>, dim3(S.vb), dim3(256), 0, S.s, n, minv, r, z, S.st);
+                if ((st = S.launched()) != MP_OK) return st;
+                if ((st = S.dot2(r, z, r, r, S.part[1], S.part[2], S.st)) != MP_OK) return st;
+                hipLaunchKernelGGL(k_cg_beta<K>, dim3(1), dim3(256), 0, S.s, S.part[1], S.part[2], m, S.st);
+                hipLaunchKernelGGL(k_cg_p<K>, dim3(S.vb), dim3(256), 0, S.s, n, z, p, S.st);
+                hipLaunchKernelGGL(k_cg_p_done<K>, dim3(1), dim3(64), 0, S.s, S.st);
+                if ((st = S.launched()) != MP_OK) return st;
+            }
+            continue;
+        }
+        if (h.done == RECURRENCE_MET) {
+            if ((st = S.true_residual(b, x, q, r, true)) != MP_OK) return st;
+            continue;
+        }
+        if (h.done == RESTART) {
+            hipLaunchKernelGGL(k_precond<K>, dim3(S.vb), dim3(256), 0, S.s, n, minv, r, z, nullptr);
+            hipLaunchKernelGGL(k_copy, dim3(S.vb), dim3(256), 0, S.s, len, z, p);
+            if ((st = S.launched()) != MP_OK) return st;
+            if ((st = S.dot2(r, z, nullptr, nullptr, S.part[1], nullptr, nullptr)) != MP_OK) return st;
+            hipLaunchKernelGGL(k_cg_restart<K>, dim3(1), dim3(256), 0, S.s, S.part[1], m, S.st);
+            if ((st = S.launched()) != MP_OK) return st;
+            continue;
+        }
+        break;
+    }
+    const int status = finish_status(h);
+    if ((st = S.true_residual(b, x, q, r, false)) != MP_OK) return st;
+    if ((st = S.read_state(&h)) != MP_OK) return st;
+    fill(h, status, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(), info);
+    if (status == MP_ERR_NOT_CONVERGED) return fail(MP_ERR_NOT_CONVERGED, "%s: no convergence in %d iterations", name, h.iters);
+    if (status == MP_ERR_BREAKDOWN) return fail(MP_ERR_BREAKDOWN, "%s: breakdown at iteration %d", name, h.iters);
+    return MP_OK;
+}
+
+template <int K>
+mp_status run_bicgstab(Solver<K> &S, const double *b, double *x, const mp_solve_opts *o, mp_solve_info *info,
+                       const char *name)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    const int64_t n = S.n;
+    const int m = S.m;
+    double *r = S.v[0], *rh = S.v[1], *p = S.v[2], *v = S.v[3], *ph = S.v[4], *s = S.v[5];
+    double *sh = S.v[6], *tv = S.v[7], *q = S.v[8];
+    const double *minv = o->precond == MP_PRECOND_JACOBI ? S.minv : nullptr;
+    const int every = o->check_every > 0 ? o->check_every : 32;
+    const int64_t len = (int64_t)K * n;
+    mp_status st;
+    State<K> h;
+    std::memset(&h, 0, sizeof(h));
+    MP_HIP_TRY(hipMemsetAsync(S.st, 0, sizeof(State<K>), S.s));
+    if (minv && (st = S.jacobi()) != MP_OK) return st;
+    if ((st = S.residual(b, x, q, r)) != MP_OK) return st;
+    hipLaunchKernelGGL(k_copy, dim3(S.vb), dim3(256), 0, S.s, len, r, rh);
+    MP_HIP_TRY(hipMemsetAsync(v, 0, sizeof(double) * (size_t)len, S.s));
+    MP_HIP_TRY(hipMemsetAsync(p, 0, sizeof(double) * (size_t)len, S.s));
+    if ((st = S.launched()) != MP_OK) return st;
+    if ((st = S.dot2(b, b, r, r, S.part[0], S.part[1], nullptr)) != MP_OK) return st;
+    hipLaunchKernelGGL(k_bi_init<K>, dim3(1), dim3(256), 0, S.s, S.part[0], S.part[1], m, o->rtol * o->rtol,
+                       o->max_iter, S.st);
+    if ((st = S.launched()) != MP_OK) return st;
+    for (;;) {
+        if ((st = S.read_state(&h)) != MP_OK) return st;
+        if (h.done == RUN) {
+            for (int it = 0; it < every; ++it) {
+                if ((st = S.dot2(rh, r, nullptr, nullptr, S.part[0], nullptr, S.st)) != MP_OK) return st;
+                hipLaunchKernelGGL(k_bi_rho<K>, dim3(1), dim3(256), 0, S.s, S.part[0], m, S.st);
+                hipLaunchKernelGGL(k_bi_p<K>, dim3(S.vb), dim3(256), 0, S.s, n, r, p, v, ph, minv, S.st);
+                if ((st = S.launched()) != MP_OK) return st;
+                if ((st = S.spmv(ph, v)) != MP_OK) return st;
+                if ((st = S.dot2(rh, v, nullptr, nullptr, S.part[0], nullptr, S.st)) != MP_OK) return st;
+                hipLaunchKernelGGL(k_bi_alpha<K>, dim3(1), dim3(256), 0, S.s, S.part[0], m, S.st);
+                hipLaunchKernelGGL(k_bi_s<K>, dim3(S.vb), dim3(256), 0, S.s, n, r, v, s, S.st);
+                if ((st = S.launched()) != MP_OK) return st;
+                if ((st = S.dot2(s, s, nullptr, nullptr, S.part[0], nullptr, S.st)) != MP_OK) return st;
+                hipLaunchKernelGGL(k_bi_ss<K>, dim3(1), dim3(256), 0, S.s, S.part[0], m, S.st);
+                hipLaunchKernelGGL(k_bi_half<K>, dim3(S.vb), dim3(256), 0, S.s, n, x, r, ph, s, S.st);
+                hipLaunchKernelGGL(k_bi_half_final<K>, dim3(1), dim3(64), 0, S.s, S.st);
+                hipLaunchKernelGGL(k_precond<K>, dim3(S.vb), dim3(256), 0, S.s, n, minv, s, sh, S.st);
+                if ((st = S.launched()) != MP_OK) return st;
+                if ((st = S.spmv(sh, tv)) != MP_OK) return st;
+                if ((st = S.dot2(tv, s, tv, tv, S.part[0], S.part[1], S.st)) != MP_OK) return st;
+                hipLaunchKernelGGL(k_bi_omega<K>, dim3(1), dim3(256), 0, S.s, S.part[0], S.part[1], m, S.st);
+                hipLaunchKernelGGL(k_bi_xr<K>, dim3(S.vb), dim3(256), 0, S.s, n, x, r, ph, sh, s, tv, S.st);
+                if ((st = S.launched()) != MP_OK) return st;
+                if ((st = S.dot2(r, r, nullptr, nullptr, S.part[2], nullptr, S.st)) != MP_OK) return st;
+                hipLaunchKernelGGL(k_bi_rr<K>, dim3(1), dim3(256), 0, S.s, S.part[2], m, S.st);
+                if ((st = S.launched()) != MP_OK) return st;
+            }
+            continue;
+        }
+        if (h.done == RECURRENCE_MET) {
+            if ((st = S.true_residual(b, x, q, r, true)) != MP_OK) return st;
+            continue;
+        }
+        if (h.done == RESTART) {
+            hipLaunchKernelGGL(k_copy, dim3(S.vb), dim3(256), 0, S.s, len, r, rh);
+            hipLaunchKernelGGL(k_bi_restart<K>, dim3(1), dim3(64), 0, S.s, S.st);
+            if ((st = S.launched()) != MP_OK) return st;
+            continue;
+        }
+        break;
+    }
+    const int status = finish_status(h);
+    if ((st = S.true_residual(b, x, q, r, false)) != MP_OK) return st;
+    if ((st = S.read_state(&h)) != MP_OK) return st;
+    fill(h, status, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(), info);
+    if (status == MP_ERR_NOT_CONVERGED) return fail(MP_ERR_NOT_CONVERGED, "%s: no convergence in %d iterations", name, h.iters);
+    if (status == MP_ERR_BREAKDOWN) return fail(MP_ERR_BREAKDOWN, "%s: breakdown at iteration %d", name, h.iters);
+    return MP_OK;
+}
+
+// kind 0 CG, 1 BiCGSTAB
+template <int K>
+mp_status entry(const char *name, int kind, const mp_csr *A, const double *a, const double *b, double *x,
+                const mp_solve_opts *opts, const mp_plan *plan, void *ws, size_t wsb, mp_solve_info *info,
+                void *stream)
+{
+    clear_error();
+    mp_status st = check_csr(A);
+    if (st != MP_OK) return st;
+    if (!opts || !info) return fail(MP_ERR_INVALID_ARG, "%s: opts or info is NULL", name);
+    if (A->n_rows != A->n_cols) return fail(MP_ERR_INVALID_ARG, "%s: matrix must be square", name);
+    if (A->n_rows > 0 && (!b || !x || !ws)) return fail(MP_ERR_INVALID_ARG, "%s: b, x or workspace is NULL", name);
+    if (A->nnz > 0 && !a) return fail(MP_ERR_INVALID_ARG, "%s: a is NULL", name);
+    if ((int64_t)A->n_rows > (int64_t)kMaxChunks * kChunk)
+        return fail(MP_ERR_UNSUPPORTED, "%s: n = %d exceeds the solver limit %d", name, A->n_rows, kMaxChunks * kChunk);
+    const size_t need = ws_bytes<K>(A->n_rows);
+    if (wsb < need) return fail(MP_ERR_NO_MEMORY, "%s: workspace of %zu bytes, %zu needed", name, wsb, need);
+    if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(MP_ERR_INVALID_ARG, "%s: workspace must be 256-byte aligned", name);
+    if (opts->precond != MP_PRECOND_NONE && opts->precond != MP_PRECOND_JACOBI)
+        return fail(MP_ERR_INVALID_ARG, "%s: preconditioner must be none or Jacobi (got %d)", name, opts->precond);
+    if (!(opts->rtol >= 0.0)) return fail(MP_ERR_INVALID_ARG, "%s: rtol must be >= 0", name);
+    if (plan && (plan->ncomp != K || plan->cplx || plan->n_rows != A->n_rows || plan->nnz != A->nnz))
+        return fail(MP_ERR_INVALID_ARG, "%s: plan is not a %d-component real plan of this matrix", name, K);
+    const size_t vb = sizeof(double) * K * (size_t)A->n_rows;
+    if (overlaps(x, vb, b, vb) || overlaps(x, vb, a, sizeof(double) * K * (size_t)A->nnz) || overlaps(x, vb, ws, wsb) ||
+        overlaps(b, vb, ws, wsb))
+        return fail(MP_ERR_ALIAS, "%s: x overlaps b, a or the workspace", name);
+    if (A->n_rows == 0) {
+        std::memset(info, 0, sizeof(*info));
+        return MP_OK;
+    }
+    Solver<K> S;
+    S.A = A;
+    S.a = a;
+    S.plan = plan;
+    S.s = static_cast<hipStream_t>(stream);
+    S.n = A->n_rows;
+    S.m = (int)((S.n + kChunk - 1) / kChunk);
+    const int64_t blocks = (S.n + 255) / 256;
+    S.vb = (unsigned)(blocks < 8192 ? blocks : 8192);
+    S.carve(ws);
+    return kind == 0 ? run_cg<K>(S, b, x, opts, info, name) : run_bicgstab<K>(S, b, x, opts, info, name);
+}
+
+}  // namespace kmp
+}  // namespace mpk
+
+extern "C" {
+
+mp_status mpkrylov_mp_workspace_bytes(const mp_csr *A, int32_t ncomp, size_t *bytes)
+{
+    mpk::clear_error();
+    mp_status st = mpk::check_csr(A);
+    if (st != MP_OK) return st;
+    if (!bytes) return mpk::fail(MP_ERR_INVALID_ARG, "bytes is NULL");
+    if (ncomp != 3 && ncomp != 4) return mpk::fail(MP_ERR_INVALID_ARG, "ncomp must be 3 or 4 (got %d)", ncomp);
+    *bytes = ncomp == 3 ? mpk::kmp::ws_bytes<3>(A->n_rows) : mpk::kmp::ws_bytes<4>(A->n_rows);
+    return MP_OK;
+}
+
+mp_status mpkrylov_cg_td(const mp_csr *A, const double *a, const double *b, double *x, const mp_solve_opts *opts,
+                         const mp_plan *plan, void *ws, size_t ws_bytes, mp_solve_info *info, void *stream)
+{
+    return mpk::kmp::entry<3>("mpkrylov_cg_td", 0, A, a, b, x, opts, plan, ws, ws_bytes, info, stream);
+}
+
+mp_status mpkrylov_cg_qd(const mp_csr *A, const double *a, const double *b, double *x, const mp_solve_opts *opts,
+                         const mp_plan *plan, void *ws, size_t ws_bytes, mp_solve_info *info, void *stream)
+{
+    return mpk::kmp::entry<4>("mpkrylov_cg_qd", 0, A, a, b, x, opts, plan, ws, ws_bytes, info, stream);
+}
+
+mp_status mpkrylov_bicgstab_td(const mp_csr *A, const double *a, const double *b, double *x,
+                               const mp_solve_opts *opts, const mp_plan *plan, void *ws, size_t ws_bytes,
+                               mp_solve_info *info, void *stream)
+{
+    return mpk::kmp::entry<3>("mpkrylov_bicgstab_td", 1, A, a, b, x, opts, plan, ws, ws_bytes, info, stream);
+}
+
+mp_status mpkrylov_bicgstab_qd(const mp_csr *A, const double *a, const double *b, double *x,
+                               const mp_solve_opts *opts, const mp_plan *plan, void *ws, size_t ws_bytes,
+                               mp_solve_info *info, void *stream)
+{
+    return mpk::kmp::entry<4>("mpkrylov_bicgstab_qd", 1, A, a, b, x, opts, plan, ws, ws_bytes, info, stream);
+}
+
+}  // extern "C"
