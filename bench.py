@@ -270,7 +270,8 @@ def nonsymmetric_section(mp, torch, repeats=3):
     BiCGSTAB, GPBiCG; x0 = 0, unpreconditioned) in DD on the tub1000-shaped synthetic band
     (n = 1000, 3,996 nonzeros), b = A sqrt(2)[1..n], to the paper's criterion
     ||r|| <= 1e-13 ||b|| and to the DD-accurate 1e-28.  BiCG's A^T comes from the device
-    transpose (formed once, outside the timed solve)."""
+    transpose (formed once, outside the timed solve).  BiCGSTAB also runs in TD and QD
+    (the paper compares iteration counts across precisions)."""
     from workloads import banded_nonsymmetric, sqrt2_vector
     rp, ci, a = banded_nonsymmetric(n=1000, seed=3)
     n = rp.size - 1
@@ -304,6 +305,56 @@ def nonsymmetric_section(mp, torch, repeats=3):
             log("tub1000-like %-9s rtol %.0e: %.5f s  %d iters  relres %.3g  fwd err %.3g" % (
                 name, rtol, info["seconds"], info["iters"], info["relres"], rec[name]["forward_err"]))
         out["rtol_%.0e" % rtol] = rec
+    # BiCGSTAB in TD and QD on the same band (K-component data, same leading parts)
+    for K, fn in ((3, mp.mpkrylov_bicgstab_td), (4, mp.mpkrylov_bicgstab_qd)):
+        rpk, cik, ak = banded_nonsymmetric(n=1000, seed=3, K=K)
+        Ak = mp.Csr.from_numpy(rpk, cik)
+        akd = torch.from_numpy(ak).cuda()
+        vk = sqrt2_vector(n, K)
+        bk = torch.empty((K, n), dtype=torch.float64, device="cuda")
+        mp.SPMV[(K, False)](Ak, akd, torch.from_numpy(vk).cuda(), bk)
+        for rtol in (1e-13, 1e-28):
+            best = None
+            for _ in range(repeats):
+                x = torch.zeros((K, n), dtype=torch.float64, device="cuda")
+                info = fn(Ak, akd, bk, x, precond="none", rtol=rtol, max_iter=50000, check_every=16)
+                if best is None or info["seconds"] < best[1]["seconds"]:
+                    best = (x.cpu().numpy(), info)
+            xh, info = best
+            name = "bicgstab_%s" % ("td" if K == 3 else "qd")
+            out["rtol_%.0e" % rtol][name] = {"seconds": round(info["seconds"], 6), "status": info["status"],
+                                             "iters": info["iters"], "restarts": info["restarts"],
+                                             "relres": info["relres"], "forward_err": dd_rel_diff(xh[:2], vk[:2]),
+                                             "per_step": "2 SpMV"}
+            log("tub1000-like %-12s rtol %.0e: %.5f s  %d iters  relres %.3g" % (
+                name, rtol, info["seconds"], info["iters"], info["relres"]))
+    return out
+
+
+def precision_section(mp, torch):
+    """CG on the 64^3 sigma = 2.5 system in TD and QD (Jacobi, x0 = 0) to relative
+    residuals DD cannot reach (1e-44 and 1e-60), with K-component matrix and right-hand
+    side of the same law."""
+    from workloads import diffusion3d_7pt, random_mp
+    out = {}
+    for K, fn, rtol in ((3, mp.mpkrylov_cg_td, 1e-44), (4, mp.mpkrylov_cg_qd, 1e-60)):
+        rp, ci, a = diffusion3d_7pt(m=64, sigma=2.5, seed=2, K=K)
+        n = rp.size - 1
+        A = mp.Csr.from_numpy(rp, ci)
+        ad = torch.from_numpy(a).cuda()
+        bd = torch.from_numpy(random_mp(n, K, np.random.default_rng(2))).cuda()
+        ytmp = torch.empty((K, n), dtype=torch.float64, device="cuda")
+        plan, pol = mp.mp_plan_autotune(A, K, ad, bd, ytmp, reps=3)
+        x = torch.zeros((K, n), dtype=torch.float64, device="cuda")
+        info = fn(A, ad, bd, x, plan=plan, precond="jacobi", rtol=rtol, max_iter=100000, check_every=32)
+        name = "cg_%s" % ("td" if K == 3 else "qd")
+        out[name] = {"seconds": round(info["seconds"], 5), "solves_per_s": round(1.0 / info["seconds"], 3),
+                     "status": info["status"], "iters": info["iters"], "restarts": info["restarts"],
+                     "target_relres": rtol, "relres": info["relres"], "plan": pol}
+        log("%-8s 64^3 to %.0e: %.4f s  status %d  iters %d  relres %.3g" % (
+            name, rtol, info["seconds"], info["status"], info["iters"], info["relres"]))
+        del A, ad, bd, x, ytmp, plan
+        torch.cuda.empty_cache()
     return out
 
 
@@ -509,6 +560,7 @@ def main():
     if not args.no_solves:
         out["solves"] = solves_section(mp, torch)
         out["nonsymmetric_solves"] = nonsymmetric_section(mp, torch)
+        out["precision_solves"] = precision_section(mp, torch)
     if not args.no_cpu_baseline and host_dd is not None:
         log("timing the CPU oracle ...")
         out["cpu_baseline"] = cpu_baseline(row_ptr, col_idx, host_dd[0], host_dd[1], args.cpu_seconds)
