@@ -1075,327 +1075,8 @@ int oracle_transpose(int64_t n_rows, int64_t n_cols, int64_t nnz, int ncomp, con
     return 0;
 }
 
-/*
- * Preconditioned BiCG in DD (Fletcher's biconjugate gradients, Sec. 4.2's list of
- * Krylov methods), Jacobi preconditioning (symmetric, so the shadow system uses the
- * same M).  A^T is given explicitly (row_ptr_t, col_idx_t, a_t: the stable transpose,
- * log2w_t its lane widths).  r~ = r at the start; per step q = A p, q~ = A^T p~,
- * sigma = (p~, q), alpha = rho / sigma, x += alpha p, r -= alpha q, r~ -= alpha q~,
- * z = M r, z~ = M r~, rho' = (r~, z), beta = rho' / rho, p = z + beta p,
- * p~ = z~ + beta p~.  Stop test, confirmation and restart as oracle_cg (a restart
- * also resets r~ to the true residual).  Breakdown: sigma = 0 or non-finite, rho' = 0
- * while not converged, or a non-finite rho' or ||r||^2.
- */
-int oracle_bicg(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx, const uint8_t *log2w,
-                const double *a, const int32_t *row_ptr_t, const int32_t *col_idx_t, const uint8_t *log2w_t,
-                const double *a_t, const double *b, double *x, const double *minv, double rtol, int32_t max_iter,
-                oracle_solve_info *info, double *hist)
-{
-    dd_mat M = {n, nnz, row_ptr, col_idx, log2w, a};
-    dd_mat Mt = {n, nnz, row_ptr_t, col_idx_t, log2w_t, a_t};
-    size_t vb = sizeof(double) * 2 * (size_t)n;
-    double *r = (double *)malloc(vb), *z = (double *)malloc(vb), *p = (double *)malloc(vb), *q = (double *)malloc(vb);
-    double *rt = (double *)malloc(vb), *zt = (double *)malloc(vb), *pt = (double *)malloc(vb), *qt = (double *)malloc(vb);
-    mpv rho, rr, bb, tol2, sigma, alpha, beta, rho_new;
-    int64_t i;
-    int32_t k = 0;
-    int status = -5;
-    memset(info, 0, sizeof(*info));
-    bb = dd_dot_vec(n, b, b);
-    tol2 = dd_mul_d(bb, rtol * rtol);
-    dd_residual(&M, b, x, q, r);
-    memcpy(rt, r, vb);
-    dd_precond(n, minv, r, z);
-    memcpy(zt, z, vb);
-    memcpy(p, z, vb);
-    memcpy(pt, z, vb);
-    rho = dd_dot_vec(n, rt, z);
-    rr = dd_dot_vec(n, r, r);
-    if (hist) { hist[0] = rr.c[0]; hist[1] = rr.c[1]; }
-    for (;;) {
-        if (dd_le(rr, tol2)) {
-            dd_residual(&M, b, x, q, r);
-            rr = dd_dot_vec(n, r, r);
-            if (dd_le(rr, tol2)) { status = 0; break; }
-            info->restarts++;
-            memcpy(rt, r, vb);
-            dd_precond(n, minv, r, z);
-            memcpy(zt, z, vb);
-            memcpy(p, z, vb);
-            memcpy(pt, z, vb);
-            rho = dd_dot_vec(n, rt, z);
-        }
-        if (k >= max_iter) break;
-        dd_spmv(&M, p, q);
-        dd_spmv(&Mt, pt, qt);
-        sigma = dd_dot_vec(n, pt, q);
-        if (sigma.c[0] == 0.0 || !isfinite(sigma.c[0])) { status = -6; break; }
-        alpha = dd_div(rho, sigma);
-        for (i = 0; i < n; ++i) {
-            st2(x, n, i, dd_add(ld2(x, n, i), dd_mul(alpha, ld2(p, n, i))));
-            st2(r, n, i, dd_add(ld2(r, n, i), mp_neg(dd_mul(alpha, ld2(q, n, i)))));
-            st2(rt, n, i, dd_add(ld2(rt, n, i), mp_neg(dd_mul(alpha, ld2(qt, n, i)))));
-        }
-        dd_precond(n, minv, r, z);
-        dd_precond(n, minv, rt, zt);
-        rho_new = dd_dot_vec(n, rt, z);
-        rr = dd_dot_vec(n, r, r);
-        k++;
-        if (hist) { hist[2 * k] = rr.c[0]; hist[2 * k + 1] = rr.c[1]; }
-        if (!isfinite(rr.c[0]) || !isfinite(rho_new.c[0])) { status = -6; break; }
-        if (rho_new.c[0] == 0.0 && !dd_le(rr, tol2)) { status = -6; break; }
-        beta = dd_div(rho_new, rho);
-        rho = rho_new;
-        for (i = 0; i < n; ++i) {
-            st2(p, n, i, dd_add(ld2(z, n, i), dd_mul(beta, ld2(p, n, i))));
-            st2(pt, n, i, dd_add(ld2(zt, n, i), dd_mul(beta, ld2(pt, n, i))));
-        }
-    }
-    dd_residual(&M, b, x, q, r);
-    rr = dd_dot_vec(n, r, r);
-    info->status = status;
-    info->iters = k;
-    info->rr_true[0] = rr.c[0]; info->rr_true[1] = rr.c[1];
-    info->bb[0] = bb.c[0]; info->bb[1] = bb.c[1];
-    free(r); free(z); free(p); free(q); free(rt); free(zt); free(pt); free(qt);
-    return status;
-}
 
-/*
- * CGS in DD (Sonneveld's conjugate gradient squared, Sec. 4.2's list), with right
- * Jacobi preconditioning as oracle_bicgstab (solve A M y = b, x = M y, so r stays
- * the true recurrence residual of A x = b).  Shadow r~ = r at the start and after
- * each restart.  Step: rho = (r~, r) (breakdown when 0 or not finite); the first
- * step after a (re)start takes u = p = r, later steps beta = rho / rho_old,
- * u = r + beta q, p = u + beta (q + beta p); p^ = M p, v = A p^, sigma = (r~, v)
- * (breakdown when 0 or not finite), alpha = rho / sigma, q = u - alpha v,
- * u^ = M (u + q), x += alpha u^, r -= alpha A u^.  Stop test, confirmation and
- * restarts as oracle_cg.
- */
-int oracle_cgs(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx, const uint8_t *log2w,
-               const double *a, const double *b, double *x, const double *minv, double rtol, int32_t max_iter,
-               oracle_solve_info *info, double *hist)
-{
-    dd_mat M = {n, nnz, row_ptr, col_idx, log2w, a};
-    size_t vb = sizeof(double) * 2 * (size_t)n;
-    double *r = (double *)malloc(vb), *rh = (double *)malloc(vb), *u = (double *)malloc(vb), *p = (double *)malloc(vb);
-    double *q = (double *)malloc(vb), *v = (double *)malloc(vb), *uh = (double *)malloc(vb), *t = (double *)malloc(vb);
-    double *ph = (double *)malloc(vb);
-    mpv rho, rho_old = {{1.0, 0.0, 0.0, 0.0}}, beta, sigma, alpha, rr, bb, tol2;
-    int64_t i;
-    int32_t k = 0;
-    int status = -5, fresh = 1;
-    memset(info, 0, sizeof(*info));
-    bb = dd_dot_vec(n, b, b);
-    tol2 = dd_mul_d(bb, rtol * rtol);
-    dd_residual(&M, b, x, t, r);
-    memcpy(rh, r, vb);
-    memset(q, 0, vb);
-    memset(p, 0, vb);
-    rr = dd_dot_vec(n, r, r);
-    if (hist) { hist[0] = rr.c[0]; hist[1] = rr.c[1]; }
-    for (;;) {
-        if (dd_le(rr, tol2)) {
-            dd_residual(&M, b, x, t, r);
-            rr = dd_dot_vec(n, r, r);
-            if (dd_le(rr, tol2)) { status = 0; break; }
-            info->restarts++;
-            memcpy(rh, r, vb);
-            fresh = 1;
-        }
-        if (k >= max_iter) break;
-        rho = dd_dot_vec(n, rh, r);
-        if (rho.c[0] == 0.0 || !isfinite(rho.c[0])) { status = -6; break; }
-        if (fresh) {
-            memcpy(u, r, vb);
-            memcpy(p, r, vb);
-            fresh = 0;
-        } else {
-            beta = dd_div(rho, rho_old);
-            for (i = 0; i < n; ++i) {
-                mpv ui = dd_add(ld2(r, n, i), dd_mul(beta, ld2(q, n, i)));
-                mpv w = dd_add(ld2(q, n, i), dd_mul(beta, ld2(p, n, i)));
-                st2(u, n, i, ui);
-                st2(p, n, i, dd_add(ui, dd_mul(beta, w)));
-            }
-        }
-        dd_precond(n, minv, p, ph);
-        dd_spmv(&M, ph, v);
-        sigma = dd_dot_vec(n, rh, v);
-        if (sigma.c[0] == 0.0 || !isfinite(sigma.c[0])) { status = -6; break; }
-        alpha = dd_div(rho, sigma);
-        for (i = 0; i < n; ++i) {
-            mpv qi = dd_add(ld2(u, n, i), mp_neg(dd_mul(alpha, ld2(v, n, i))));
-            mpv s = dd_add(ld2(u, n, i), qi);
-            st2(q, n, i, qi);
-            st2(uh, n, i, minv ? dd_mul_d(s, minv[i]) : s);
-        }
-        for (i = 0; i < n; ++i) st2(x, n, i, dd_add(ld2(x, n, i), dd_mul(alpha, ld2(uh, n, i))));
-        dd_spmv(&M, uh, t);
-        for (i = 0; i < n; ++i) st2(r, n, i, dd_add(ld2(r, n, i), mp_neg(dd_mul(alpha, ld2(t, n, i)))));
-        rr = dd_dot_vec(n, r, r);
-        k++;
-        if (hist) { hist[2 * k] = rr.c[0]; hist[2 * k + 1] = rr.c[1]; }
-        if (!isfinite(rr.c[0])) { status = -6; break; }
-        rho_old = rho;
-    }
-    dd_residual(&M, b, x, t, r);
-    rr = dd_dot_vec(n, r, r);
-    info->status = status;
-    info->iters = k;
-    info->rr_true[0] = rr.c[0]; info->rr_true[1] = rr.c[1];
-    info->bb[0] = bb.c[0]; info->bb[1] = bb.c[1];
-    free(r); free(rh); free(u); free(p); free(q); free(v); free(uh); free(t); free(ph);
-    return status;
-}
 
-/*
- * GPBiCG in DD (Zhang's generalized product-type BiCG, Sec. 4.2's list), with right
- * Jacobi preconditioning as oracle_bicgstab: every product with A is a product with
- * A M, and x collects M times the y-space corrections.  Shadow r~ = r at the start and
- * after each restart.  One step:
- *   rho = (r~, r) (breakdown when 0 or not finite);
- *   first step after a (re)start: p = r; later steps: beta = (alpha'/zeta')(rho/rho'),
- *     p = r + beta (p - u), w = c' + beta q'  (primes: the previous step's values);
- *   q = A M p; sigma = (r~, q) (breakdown when 0 or not finite); alpha = rho / sigma;
- *   t = r - alpha q; later steps y = t' - t - alpha w;
- *   half step: when (t, t) meets the tolerance, x += M (alpha p), r = t, and the
- *     next step starts fresh (as BiCGSTAB's s test);
- *   c = A M t;
- *   first step: zeta = (c, t) / (c, c), eta = 0 (breakdown when (c, c) is 0);
- *   later steps, with d = (c,c)(y,y) - (y,c)^2 (breakdown when 0):
- *     zeta = ((y,y)(c,t) - (y,t)(y,c)) / d,  eta = ((c,c)(y,t) - (y,c)(c,t)) / d;
- *   breakdown when zeta is 0 or zeta / eta are not finite;
- *   u = zeta q + eta (t' - r + beta u)       [first step: u = zeta q]
- *   z = zeta r + eta z - alpha u             [first step: z = zeta r - alpha u]
- *   x += M (alpha p + z)
- *   r = t - eta y - zeta c                   [first step: r = t - zeta c]
- *   t' = t.
- * Stop test, confirmation and restarts as oracle_cg; a step is counted when t is formed.
- */
-int oracle_gpbicg(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx, const uint8_t *log2w,
-                  const double *a, const double *b, double *x, const double *minv, double rtol, int32_t max_iter,
-                  oracle_solve_info *info, double *hist)
-{
-    dd_mat M = {n, nnz, row_ptr, col_idx, log2w, a};
-    size_t vb = sizeof(double) * 2 * (size_t)n;
-    double *r = (double *)malloc(vb), *rh = (double *)malloc(vb), *p = (double *)malloc(vb);
-    double *q = (double *)malloc(vb), *t = (double *)malloc(vb), *c = (double *)malloc(vb);
-    double *y = (double *)malloc(vb), *u = (double *)malloc(vb), *z = (double *)malloc(vb);
-    double *w = (double *)malloc(vb), *tp = (double *)malloc(vb), *tmp = (double *)malloc(vb);
-    mpv zero = {{0.0, 0.0, 0.0, 0.0}};
-    mpv rho, rho_old = zero, beta = zero, sigma, alpha = zero, zeta = zero, eta = zero;
-    mpv rr, tt, cc, ct, yy, yc, yt, den, bb, tol2;
-    int64_t i;
-    int32_t k = 0;
-    int status = -5, fresh = 1;
-    memset(info, 0, sizeof(*info));
-    bb = dd_dot_vec(n, b, b);
-    tol2 = dd_mul_d(bb, rtol * rtol);
-    dd_residual(&M, b, x, tmp, r);
-    memcpy(rh, r, vb);
-    rr = dd_dot_vec(n, r, r);
-    if (hist) { hist[0] = rr.c[0]; hist[1] = rr.c[1]; }
-    for (;;) {
-        if (dd_le(rr, tol2)) {
-            dd_residual(&M, b, x, tmp, r);
-            rr = dd_dot_vec(n, r, r);
-            if (dd_le(rr, tol2)) { status = 0; break; }
-            info->restarts++;
-            memcpy(rh, r, vb);
-            fresh = 1;
-        }
-        if (k >= max_iter) break;
-        rho = dd_dot_vec(n, rh, r);
-        if (rho.c[0] == 0.0 || !isfinite(rho.c[0])) { status = -6; break; }
-        if (fresh) {
-            memcpy(p, r, vb);
-        } else {
-            beta = dd_mul(dd_div(alpha, zeta), dd_div(rho, rho_old));
-            for (i = 0; i < n; ++i) {
-                st2(p, n, i, dd_add(ld2(r, n, i), dd_mul(beta, dd_add(ld2(p, n, i), mp_neg(ld2(u, n, i))))));
-                st2(w, n, i, dd_add(ld2(c, n, i), dd_mul(beta, ld2(q, n, i))));
-            }
-        }
-        dd_precond(n, minv, p, tmp);
-        dd_spmv(&M, tmp, q);
-        sigma = dd_dot_vec(n, rh, q);
-        if (sigma.c[0] == 0.0 || !isfinite(sigma.c[0])) { status = -6; break; }
-        alpha = dd_div(rho, sigma);
-        for (i = 0; i < n; ++i) {
-            mpv ti = dd_add(ld2(r, n, i), mp_neg(dd_mul(alpha, ld2(q, n, i))));
-            st2(t, n, i, ti);
-            if (!fresh)
-                st2(y, n, i, dd_add(dd_add(ld2(tp, n, i), mp_neg(ti)), mp_neg(dd_mul(alpha, ld2(w, n, i)))));
-        }
-        tt = dd_dot_vec(n, t, t);
-        k++;
-        if (dd_le(tt, tol2)) {
-            for (i = 0; i < n; ++i) {
-                mpv d = dd_mul(alpha, ld2(p, n, i));
-                st2(x, n, i, dd_add(ld2(x, n, i), minv ? dd_mul_d(d, minv[i]) : d));
-            }
-            memcpy(r, t, vb);
-            rr = tt;
-            if (hist) { hist[2 * k] = rr.c[0]; hist[2 * k + 1] = rr.c[1]; }
-            rho_old = rho;
-            fresh = 1;
-            continue;
-        }
-        dd_precond(n, minv, t, tmp);
-        dd_spmv(&M, tmp, c);
-        cc = dd_dot_vec(n, c, c);
-        ct = dd_dot_vec(n, c, t);
-        if (fresh) {
-            if (cc.c[0] == 0.0 || !isfinite(cc.c[0])) { status = -6; break; }
-            zeta = dd_div(ct, cc);
-            eta = zero;
-        } else {
-            yy = dd_dot_vec(n, y, y);
-            yc = dd_dot_vec(n, y, c);
-            yt = dd_dot_vec(n, y, t);
-            den = dd_add(dd_mul(cc, yy), mp_neg(dd_mul(yc, yc)));
-            if (den.c[0] == 0.0 || !isfinite(den.c[0])) { status = -6; break; }
-            zeta = dd_div(dd_add(dd_mul(yy, ct), mp_neg(dd_mul(yt, yc))), den);
-            eta = dd_div(dd_add(dd_mul(cc, yt), mp_neg(dd_mul(yc, ct))), den);
-        }
-        if (zeta.c[0] == 0.0 || !isfinite(zeta.c[0]) || !isfinite(eta.c[0])) { status = -6; break; }
-        for (i = 0; i < n; ++i) {
-            mpv ri = ld2(r, n, i), ti = ld2(t, n, i), ui, zi, d;
-            if (fresh) {
-                ui = dd_mul(zeta, ld2(q, n, i));
-                zi = dd_add(dd_mul(zeta, ri), mp_neg(dd_mul(alpha, ui)));
-            } else {
-                mpv g = dd_add(dd_add(ld2(tp, n, i), mp_neg(ri)), dd_mul(beta, ld2(u, n, i)));
-                ui = dd_add(dd_mul(zeta, ld2(q, n, i)), dd_mul(eta, g));
-                zi = dd_add(dd_add(dd_mul(zeta, ri), dd_mul(eta, ld2(z, n, i))), mp_neg(dd_mul(alpha, ui)));
-            }
-            st2(u, n, i, ui);
-            st2(z, n, i, zi);
-            d = dd_add(dd_mul(alpha, ld2(p, n, i)), zi);
-            st2(x, n, i, dd_add(ld2(x, n, i), minv ? dd_mul_d(d, minv[i]) : d));
-            if (fresh)
-                ri = dd_add(ti, mp_neg(dd_mul(zeta, ld2(c, n, i))));
-            else
-                ri = dd_add(dd_add(ti, mp_neg(dd_mul(eta, ld2(y, n, i)))), mp_neg(dd_mul(zeta, ld2(c, n, i))));
-            st2(r, n, i, ri);
-            st2(tp, n, i, ti);
-        }
-        rr = dd_dot_vec(n, r, r);
-        if (hist) { hist[2 * k] = rr.c[0]; hist[2 * k + 1] = rr.c[1]; }
-        if (!isfinite(rr.c[0])) { status = -6; break; }
-        rho_old = rho;
-        fresh = 0;
-    }
-    dd_residual(&M, b, x, tmp, r);
-    rr = dd_dot_vec(n, r, r);
-    info->status = status;
-    info->iters = k;
-    info->rr_true[0] = rr.c[0]; info->rr_true[1] = rr.c[1];
-    info->bb[0] = bb.c[0]; info->bb[1] = bb.c[1];
-    free(r); free(rh); free(p); free(q); free(t); free(c); free(y); free(u); free(z); free(w); free(tp); free(tmp);
-    return status;
-}
 
 /* ------------------------------------------------------------------------- */
 /* COO -> CSR (the storage conversion of Sec. 3): elements ordered by row, and */
@@ -1691,4 +1372,356 @@ int oracle_mp_le(int K, const double *a, const double *b)
     int c;
     for (c = 0; c < K; ++c) { x.c[c] = a[c]; y.c[c] = b[c]; }
     return mp_le(K, x, y);
+}
+
+/*
+ * Preconditioned BiCG in K-component arithmetic (DD: K = 2) (Fletcher's biconjugate gradients, Sec. 4.2's list of
+ * Krylov methods), Jacobi preconditioning (symmetric, so the shadow system uses the
+ * same M).  A^T is given explicitly (row_ptr_t, col_idx_t, a_t: the stable transpose,
+ * log2w_t its lane widths).  r~ = r at the start; per step q = A p, q~ = A^T p~,
+ * sigma = (p~, q), alpha = rho / sigma, x += alpha p, r -= alpha q, r~ -= alpha q~,
+ * z = M r, z~ = M r~, rho' = (r~, z), beta = rho' / rho, p = z + beta p,
+ * p~ = z~ + beta p~.  Stop test, confirmation and restart as oracle_cg (a restart
+ * also resets r~ to the true residual).  Breakdown: sigma = 0 or non-finite, rho' = 0
+ * while not converged, or a non-finite rho' or ||r||^2.
+ */
+int oracle_bicg_k(int K, int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx, const uint8_t *log2w,
+                const double *a, const int32_t *row_ptr_t, const int32_t *col_idx_t, const uint8_t *log2w_t,
+                const double *a_t, const double *b, double *x, const double *minv, double rtol, int32_t max_iter,
+                oracle_solve_info *info, double *hist)
+{
+    mp_mat M = {K, n, nnz, row_ptr, col_idx, log2w, a};
+    mp_mat Mt = {K, n, nnz, row_ptr_t, col_idx_t, log2w_t, a_t};
+    size_t vb = sizeof(double) * (size_t)K * (size_t)n;
+    double *r = (double *)malloc(vb), *z = (double *)malloc(vb), *p = (double *)malloc(vb), *q = (double *)malloc(vb);
+    double *rt = (double *)malloc(vb), *zt = (double *)malloc(vb), *pt = (double *)malloc(vb);
+    double *qt = (double *)malloc(vb);
+    mpv rho, rr, bb, tol2, sigma, alpha, beta, rho_new;
+    int64_t i;
+    int32_t k = 0;
+    int status = -5;
+    memset(info, 0, sizeof(*info));
+    bb = mp_dot_vec(K, n, b, b);
+    tol2 = mp_mul_d(K, bb, rtol * rtol);
+    mpm_residual(&M, b, x, q, r);
+    memcpy(rt, r, vb);
+    mpm_precond(&M, minv, r, z);
+    memcpy(zt, z, vb);
+    memcpy(p, z, vb);
+    memcpy(pt, z, vb);
+    rho = mp_dot_vec(K, n, rt, z);
+    rr = mp_dot_vec(K, n, r, r);
+    if (hist) { hist[0] = rr.c[0]; hist[1] = rr.c[1]; }
+    for (;;) {
+        if (mp_le(K, rr, tol2)) {
+            mpm_residual(&M, b, x, q, r);
+            rr = mp_dot_vec(K, n, r, r);
+            if (mp_le(K, rr, tol2)) { status = 0; break; }
+            info->restarts++;
+            memcpy(rt, r, vb);
+            mpm_precond(&M, minv, r, z);
+            memcpy(zt, z, vb);
+            memcpy(p, z, vb);
+            memcpy(pt, z, vb);
+            rho = mp_dot_vec(K, n, rt, z);
+        }
+        if (k >= max_iter) break;
+        mpm_spmv(&M, p, q);
+        mpm_spmv(&Mt, pt, qt);
+        sigma = mp_dot_vec(K, n, pt, q);
+        if (sigma.c[0] == 0.0 || !isfinite(sigma.c[0])) { status = -6; break; }
+        alpha = mp_div(K, rho, sigma);
+        for (i = 0; i < n; ++i) {
+            stk(&M, x, i, mp_add(K, ldk(&M, x, i), mp_mul(K, alpha, ldk(&M, p, i))));
+            stk(&M, r, i, mp_add(K, ldk(&M, r, i), mp_neg(mp_mul(K, alpha, ldk(&M, q, i)))));
+            stk(&M, rt, i, mp_add(K, ldk(&M, rt, i), mp_neg(mp_mul(K, alpha, ldk(&M, qt, i)))));
+        }
+        mpm_precond(&M, minv, r, z);
+        mpm_precond(&M, minv, rt, zt);
+        rho_new = mp_dot_vec(K, n, rt, z);
+        rr = mp_dot_vec(K, n, r, r);
+        k++;
+        if (hist) { hist[2 * k] = rr.c[0]; hist[2 * k + 1] = rr.c[1]; }
+        if (!isfinite(rr.c[0]) || !isfinite(rho_new.c[0])) { status = -6; break; }
+        if (rho_new.c[0] == 0.0 && !mp_le(K, rr, tol2)) { status = -6; break; }
+        beta = mp_div(K, rho_new, rho);
+        rho = rho_new;
+        for (i = 0; i < n; ++i) {
+            stk(&M, p, i, mp_add(K, ldk(&M, z, i), mp_mul(K, beta, ldk(&M, p, i))));
+            stk(&M, pt, i, mp_add(K, ldk(&M, zt, i), mp_mul(K, beta, ldk(&M, pt, i))));
+        }
+    }
+    mpm_residual(&M, b, x, q, r);
+    rr = mp_dot_vec(K, n, r, r);
+    info->status = status;
+    info->iters = k;
+    info->rr_true[0] = rr.c[0]; info->rr_true[1] = rr.c[1];
+    info->bb[0] = bb.c[0]; info->bb[1] = bb.c[1];
+    free(r); free(z); free(p); free(q); free(rt); free(zt); free(pt); free(qt);
+    return status;
+}
+
+int oracle_bicg(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx, const uint8_t *log2w,
+                const double *a, const int32_t *row_ptr_t, const int32_t *col_idx_t, const uint8_t *log2w_t,
+                const double *a_t, const double *b, double *x, const double *minv, double rtol, int32_t max_iter,
+                oracle_solve_info *info, double *hist)
+{
+    return oracle_bicg_k(2, n, nnz, row_ptr, col_idx, log2w, a, row_ptr_t, col_idx_t, log2w_t, a_t, b, x, minv, rtol,
+                         max_iter, info, hist);
+}
+
+/*
+ * CGS in K-component arithmetic (DD: K = 2) (Sonneveld's conjugate gradient squared, Sec. 4.2's list), with right
+ * Jacobi preconditioning as oracle_bicgstab (solve A M y = b, x = M y, so r stays
+ * the true recurrence residual of A x = b).  Shadow r~ = r at the start and after
+ * each restart.  Step: rho = (r~, r) (breakdown when 0 or not finite); the first
+ * step after a (re)start takes u = p = r, later steps beta = rho / rho_old,
+ * u = r + beta q, p = u + beta (q + beta p); p^ = M p, v = A p^, sigma = (r~, v)
+ * (breakdown when 0 or not finite), alpha = rho / sigma, q = u - alpha v,
+ * u^ = M (u + q), x += alpha u^, r -= alpha A u^.  Stop test, confirmation and
+ * restarts as oracle_cg.
+ */
+int oracle_cgs_k(int K, int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx, const uint8_t *log2w,
+               const double *a, const double *b, double *x, const double *minv, double rtol, int32_t max_iter,
+               oracle_solve_info *info, double *hist)
+{
+    mp_mat M = {K, n, nnz, row_ptr, col_idx, log2w, a};
+    size_t vb = sizeof(double) * (size_t)K * (size_t)n;
+    double *r = (double *)malloc(vb), *rh = (double *)malloc(vb), *u = (double *)malloc(vb), *p = (double *)malloc(vb);
+    double *q = (double *)malloc(vb), *v = (double *)malloc(vb), *uh = (double *)malloc(vb), *t = (double *)malloc(vb);
+    double *ph = (double *)malloc(vb);
+    mpv rho, rho_old = {{1.0, 0.0, 0.0, 0.0}}, beta, sigma, alpha, rr, bb, tol2;
+    int64_t i;
+    int32_t k = 0;
+    int status = -5, fresh = 1;
+    memset(info, 0, sizeof(*info));
+    bb = mp_dot_vec(K, n, b, b);
+    tol2 = mp_mul_d(K, bb, rtol * rtol);
+    mpm_residual(&M, b, x, t, r);
+    memcpy(rh, r, vb);
+    memset(q, 0, vb);
+    memset(p, 0, vb);
+    rr = mp_dot_vec(K, n, r, r);
+    if (hist) { hist[0] = rr.c[0]; hist[1] = rr.c[1]; }
+    for (;;) {
+        if (mp_le(K, rr, tol2)) {
+            mpm_residual(&M, b, x, t, r);
+            rr = mp_dot_vec(K, n, r, r);
+            if (mp_le(K, rr, tol2)) { status = 0; break; }
+            info->restarts++;
+            memcpy(rh, r, vb);
+            fresh = 1;
+        }
+        if (k >= max_iter) break;
+        rho = mp_dot_vec(K, n, rh, r);
+        if (rho.c[0] == 0.0 || !isfinite(rho.c[0])) { status = -6; break; }
+        if (fresh) {
+            memcpy(u, r, vb);
+            memcpy(p, r, vb);
+            fresh = 0;
+        } else {
+            beta = mp_div(K, rho, rho_old);
+            for (i = 0; i < n; ++i) {
+                mpv ui = mp_add(K, ldk(&M, r, i), mp_mul(K, beta, ldk(&M, q, i)));
+                mpv w = mp_add(K, ldk(&M, q, i), mp_mul(K, beta, ldk(&M, p, i)));
+                stk(&M, u, i, ui);
+                stk(&M, p, i, mp_add(K, ui, mp_mul(K, beta, w)));
+            }
+        }
+        mpm_precond(&M, minv, p, ph);
+        mpm_spmv(&M, ph, v);
+        sigma = mp_dot_vec(K, n, rh, v);
+        if (sigma.c[0] == 0.0 || !isfinite(sigma.c[0])) { status = -6; break; }
+        alpha = mp_div(K, rho, sigma);
+        for (i = 0; i < n; ++i) {
+            mpv qi = mp_add(K, ldk(&M, u, i), mp_neg(mp_mul(K, alpha, ldk(&M, v, i))));
+            mpv s = mp_add(K, ldk(&M, u, i), qi);
+            stk(&M, q, i, qi);
+            stk(&M, uh, i, minv ? mp_mul_d(K, s, minv[i]) : s);
+        }
+        for (i = 0; i < n; ++i) stk(&M, x, i, mp_add(K, ldk(&M, x, i), mp_mul(K, alpha, ldk(&M, uh, i))));
+        mpm_spmv(&M, uh, t);
+        for (i = 0; i < n; ++i) stk(&M, r, i, mp_add(K, ldk(&M, r, i), mp_neg(mp_mul(K, alpha, ldk(&M, t, i)))));
+        rr = mp_dot_vec(K, n, r, r);
+        k++;
+        if (hist) { hist[2 * k] = rr.c[0]; hist[2 * k + 1] = rr.c[1]; }
+        if (!isfinite(rr.c[0])) { status = -6; break; }
+        rho_old = rho;
+    }
+    mpm_residual(&M, b, x, t, r);
+    rr = mp_dot_vec(K, n, r, r);
+    info->status = status;
+    info->iters = k;
+    info->rr_true[0] = rr.c[0]; info->rr_true[1] = rr.c[1];
+    info->bb[0] = bb.c[0]; info->bb[1] = bb.c[1];
+    free(r); free(rh); free(u); free(p); free(q); free(v); free(uh); free(t); free(ph);
+    return status;
+}
+
+int oracle_cgs(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx, const uint8_t *log2w,
+               const double *a, const double *b, double *x, const double *minv, double rtol, int32_t max_iter,
+               oracle_solve_info *info, double *hist)
+{
+    return oracle_cgs_k(2, n, nnz, row_ptr, col_idx, log2w, a, b, x, minv, rtol, max_iter, info, hist);
+}
+
+/*
+ * GPBiCG in K-component arithmetic (DD: K = 2) (Zhang's generalized product-type BiCG, Sec. 4.2's list), with right
+ * Jacobi preconditioning as oracle_bicgstab: every product with A is a product with
+ * A M, and x collects M times the y-space corrections.  Shadow r~ = r at the start and
+ * after each restart.  One step:
+ *   rho = (r~, r) (breakdown when 0 or not finite);
+ *   first step after a (re)start: p = r; later steps: beta = (alpha'/zeta')(rho/rho'),
+ *     p = r + beta (p - u), w = c' + beta q'  (primes: the previous step's values);
+ *   q = A M p; sigma = (r~, q) (breakdown when 0 or not finite); alpha = rho / sigma;
+ *   t = r - alpha q; later steps y = t' - t - alpha w;
+ *   half step: when (t, t) meets the tolerance, x += M (alpha p), r = t, and the
+ *     next step starts fresh (as BiCGSTAB's s test);
+ *   c = A M t;
+ *   first step: zeta = (c, t) / (c, c), eta = 0 (breakdown when (c, c) is 0);
+ *   later steps, with d = (c,c)(y,y) - (y,c)^2 (breakdown when 0):
+ *     zeta = ((y,y)(c,t) - (y,t)(y,c)) / d,  eta = ((c,c)(y,t) - (y,c)(c,t)) / d;
+ *   breakdown when zeta is 0 or zeta / eta are not finite;
+ *   u = zeta q + eta (t' - r + beta u)       [first step: u = zeta q]
+ *   z = zeta r + eta z - alpha u             [first step: z = zeta r - alpha u]
+ *   x += M (alpha p + z)
+ *   r = t - eta y - zeta c                   [first step: r = t - zeta c]
+ *   t' = t.
+ * Stop test, confirmation and restarts as oracle_cg; a step is counted when t is formed.
+ */
+int oracle_gpbicg_k(int K, int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx, const uint8_t *log2w,
+                  const double *a, const double *b, double *x, const double *minv, double rtol, int32_t max_iter,
+                  oracle_solve_info *info, double *hist)
+{
+    mp_mat M = {K, n, nnz, row_ptr, col_idx, log2w, a};
+    size_t vb = sizeof(double) * (size_t)K * (size_t)n;
+    double *r = (double *)malloc(vb), *rh = (double *)malloc(vb), *p = (double *)malloc(vb);
+    double *q = (double *)malloc(vb), *t = (double *)malloc(vb), *c = (double *)malloc(vb);
+    double *y = (double *)malloc(vb), *u = (double *)malloc(vb), *z = (double *)malloc(vb);
+    double *w = (double *)malloc(vb), *tp = (double *)malloc(vb), *tmp = (double *)malloc(vb);
+    mpv zero = {{0.0, 0.0, 0.0, 0.0}};
+    mpv rho, rho_old = zero, beta = zero, sigma, alpha = zero, zeta = zero, eta = zero;
+    mpv rr, tt, cc, ct, yy, yc, yt, den, bb, tol2;
+    int64_t i;
+    int32_t k = 0;
+    int status = -5, fresh = 1;
+    memset(info, 0, sizeof(*info));
+    bb = mp_dot_vec(K, n, b, b);
+    tol2 = mp_mul_d(K, bb, rtol * rtol);
+    mpm_residual(&M, b, x, tmp, r);
+    memcpy(rh, r, vb);
+    rr = mp_dot_vec(K, n, r, r);
+    if (hist) { hist[0] = rr.c[0]; hist[1] = rr.c[1]; }
+    for (;;) {
+        if (mp_le(K, rr, tol2)) {
+            mpm_residual(&M, b, x, tmp, r);
+            rr = mp_dot_vec(K, n, r, r);
+            if (mp_le(K, rr, tol2)) { status = 0; break; }
+            info->restarts++;
+            memcpy(rh, r, vb);
+            fresh = 1;
+        }
+        if (k >= max_iter) break;
+        rho = mp_dot_vec(K, n, rh, r);
+        if (rho.c[0] == 0.0 || !isfinite(rho.c[0])) { status = -6; break; }
+        if (fresh) {
+            memcpy(p, r, vb);
+        } else {
+            beta = mp_mul(K, mp_div(K, alpha, zeta), mp_div(K, rho, rho_old));
+            for (i = 0; i < n; ++i) {
+                mpv pu = mp_add(K, ldk(&M, p, i), mp_neg(ldk(&M, u, i)));
+                stk(&M, p, i, mp_add(K, ldk(&M, r, i), mp_mul(K, beta, pu)));
+                stk(&M, w, i, mp_add(K, ldk(&M, c, i), mp_mul(K, beta, ldk(&M, q, i))));
+            }
+        }
+        mpm_precond(&M, minv, p, tmp);
+        mpm_spmv(&M, tmp, q);
+        sigma = mp_dot_vec(K, n, rh, q);
+        if (sigma.c[0] == 0.0 || !isfinite(sigma.c[0])) { status = -6; break; }
+        alpha = mp_div(K, rho, sigma);
+        for (i = 0; i < n; ++i) {
+            mpv ti = mp_add(K, ldk(&M, r, i), mp_neg(mp_mul(K, alpha, ldk(&M, q, i))));
+            stk(&M, t, i, ti);
+            if (!fresh) {
+                mpv d = mp_add(K, ldk(&M, tp, i), mp_neg(ti));
+                stk(&M, y, i, mp_add(K, d, mp_neg(mp_mul(K, alpha, ldk(&M, w, i)))));
+            }
+        }
+        tt = mp_dot_vec(K, n, t, t);
+        k++;
+        if (mp_le(K, tt, tol2)) {
+            for (i = 0; i < n; ++i) {
+                mpv d = mp_mul(K, alpha, ldk(&M, p, i));
+                stk(&M, x, i, mp_add(K, ldk(&M, x, i), minv ? mp_mul_d(K, d, minv[i]) : d));
+            }
+            memcpy(r, t, vb);
+            rr = tt;
+            if (hist) { hist[2 * k] = rr.c[0]; hist[2 * k + 1] = rr.c[1]; }
+            rho_old = rho;
+            fresh = 1;
+            continue;
+        }
+        mpm_precond(&M, minv, t, tmp);
+        mpm_spmv(&M, tmp, c);
+        cc = mp_dot_vec(K, n, c, c);
+        ct = mp_dot_vec(K, n, c, t);
+        if (fresh) {
+            if (cc.c[0] == 0.0 || !isfinite(cc.c[0])) { status = -6; break; }
+            zeta = mp_div(K, ct, cc);
+            eta = zero;
+        } else {
+            yy = mp_dot_vec(K, n, y, y);
+            yc = mp_dot_vec(K, n, y, c);
+            yt = mp_dot_vec(K, n, y, t);
+            den = mp_add(K, mp_mul(K, cc, yy), mp_neg(mp_mul(K, yc, yc)));
+            if (den.c[0] == 0.0 || !isfinite(den.c[0])) { status = -6; break; }
+            zeta = mp_div(K, mp_add(K, mp_mul(K, yy, ct), mp_neg(mp_mul(K, yt, yc))), den);
+            eta = mp_div(K, mp_add(K, mp_mul(K, cc, yt), mp_neg(mp_mul(K, yc, ct))), den);
+        }
+        if (zeta.c[0] == 0.0 || !isfinite(zeta.c[0]) || !isfinite(eta.c[0])) { status = -6; break; }
+        for (i = 0; i < n; ++i) {
+            mpv ri = ldk(&M, r, i), ti = ldk(&M, t, i), ui, zi, d;
+            if (fresh) {
+                ui = mp_mul(K, zeta, ldk(&M, q, i));
+                zi = mp_add(K, mp_mul(K, zeta, ri), mp_neg(mp_mul(K, alpha, ui)));
+            } else {
+                mpv g = mp_add(K, mp_add(K, ldk(&M, tp, i), mp_neg(ri)), mp_mul(K, beta, ldk(&M, u, i)));
+                ui = mp_add(K, mp_mul(K, zeta, ldk(&M, q, i)), mp_mul(K, eta, g));
+                mpv zr = mp_add(K, mp_mul(K, zeta, ri), mp_mul(K, eta, ldk(&M, z, i)));
+                zi = mp_add(K, zr, mp_neg(mp_mul(K, alpha, ui)));
+            }
+            stk(&M, u, i, ui);
+            stk(&M, z, i, zi);
+            d = mp_add(K, mp_mul(K, alpha, ldk(&M, p, i)), zi);
+            stk(&M, x, i, mp_add(K, ldk(&M, x, i), minv ? mp_mul_d(K, d, minv[i]) : d));
+            if (fresh)
+                ri = mp_add(K, ti, mp_neg(mp_mul(K, zeta, ldk(&M, c, i))));
+            else {
+                mpv ty = mp_add(K, ti, mp_neg(mp_mul(K, eta, ldk(&M, y, i))));
+                ri = mp_add(K, ty, mp_neg(mp_mul(K, zeta, ldk(&M, c, i))));
+            }
+            stk(&M, r, i, ri);
+            stk(&M, tp, i, ti);
+        }
+        rr = mp_dot_vec(K, n, r, r);
+        if (hist) { hist[2 * k] = rr.c[0]; hist[2 * k + 1] = rr.c[1]; }
+        if (!isfinite(rr.c[0])) { status = -6; break; }
+        rho_old = rho;
+        fresh = 0;
+    }
+    mpm_residual(&M, b, x, tmp, r);
+    rr = mp_dot_vec(K, n, r, r);
+    info->status = status;
+    info->iters = k;
+    info->rr_true[0] = rr.c[0]; info->rr_true[1] = rr.c[1];
+    info->bb[0] = bb.c[0]; info->bb[1] = bb.c[1];
+    free(r); free(rh); free(p); free(q); free(t); free(c); free(y); free(u); free(z); free(w); free(tp); free(tmp);
+    return status;
+}
+
+int oracle_gpbicg(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx, const uint8_t *log2w,
+                  const double *a, const double *b, double *x, const double *minv, double rtol, int32_t max_iter,
+                  oracle_solve_info *info, double *hist)
+{
+    return oracle_gpbicg_k(2, n, nnz, row_ptr, col_idx, log2w, a, b, x, minv, rtol, max_iter, info, hist);
 }

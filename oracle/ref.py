@@ -209,10 +209,13 @@ def _krylov_sigs():
     L.oracle_bicg.argtypes = [i64, i64, P, P, P, P, P, P, P, P, P, P, P, ctypes.c_double, ctypes.c_int32,
                               ctypes.POINTER(SolveInfo), P]
     L.oracle_bicg.restype = ctypes.c_int
-    for f in (L.oracle_cg_k, L.oracle_bicgstab_k):
+    for f in (L.oracle_cg_k, L.oracle_bicgstab_k, L.oracle_cgs_k, L.oracle_gpbicg_k):
         f.argtypes = [ctypes.c_int, i64, i64, P, P, P, P, P, P, P, ctypes.c_double, ctypes.c_int32,
                       ctypes.POINTER(SolveInfo), P]
         f.restype = ctypes.c_int
+    L.oracle_bicg_k.argtypes = [ctypes.c_int, i64, i64, P, P, P, P, P, P, P, P, P, P, P, ctypes.c_double,
+                                ctypes.c_int32, ctypes.POINTER(SolveInfo), P]
+    L.oracle_bicg_k.restype = ctypes.c_int
     L.oracle_mp_div.argtypes = [ctypes.c_int, P, P, P]
     L.oracle_mp_dot.argtypes = [ctypes.c_int, i64, P, P, P]
     L.oracle_mp_le.argtypes = [ctypes.c_int, P, P]
@@ -323,6 +326,43 @@ def bicgstab_k(K, row_ptr, col_idx, a, b, x0=None, precond="jacobi", rtol=1e-28,
                history=False):
     """K-component BiCGSTAB (oracle; K = 2 is bicgstab).  a, b, x: (K, len)."""
     return _solve_k("oracle_bicgstab_k", K, row_ptr, col_idx, a, b, x0, precond, rtol, max_iter, log2w, history)
+
+
+def cgs_k(K, row_ptr, col_idx, a, b, x0=None, precond="jacobi", rtol=1e-28, max_iter=10000, log2w=None,
+          history=False):
+    """K-component CGS (oracle; K = 2 is cgs).  a, b, x: (K, len)."""
+    return _solve_k("oracle_cgs_k", K, row_ptr, col_idx, a, b, x0, precond, rtol, max_iter, log2w, history)
+
+
+def gpbicg_k(K, row_ptr, col_idx, a, b, x0=None, precond="jacobi", rtol=1e-28, max_iter=10000, log2w=None,
+             history=False):
+    """K-component GPBiCG (oracle; K = 2 is gpbicg).  a, b, x: (K, len)."""
+    return _solve_k("oracle_gpbicg_k", K, row_ptr, col_idx, a, b, x0, precond, rtol, max_iter, log2w, history)
+
+
+def bicg_k(K, row_ptr, col_idx, a, b, x0=None, precond="jacobi", rtol=1e-28, max_iter=10000, log2w=None,
+           log2w_t=None, history=False):
+    """K-component BiCG (oracle; K = 2 is bicg); A^T from the oracle's stable transpose."""
+    L = _krylov_sigs()
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
+    a, b = _f64(a), _f64(b)
+    n = row_ptr.size - 1
+    assert a.shape == (K, col_idx.size) and b.shape == (K, n)
+    rpt, cit, at = transpose(row_ptr, col_idx, a, n_cols=n)
+    x = np.array(x0, dtype=np.float64, order="C", copy=True) if x0 is not None else np.zeros((K, n))
+    minv = jacobi_minv(row_ptr, col_idx, a[0]) if precond == "jacobi" else None
+    lw = None if log2w is None else np.ascontiguousarray(log2w, dtype=np.uint8)
+    lwt = None if log2w_t is None else np.ascontiguousarray(log2w_t, dtype=np.uint8)
+    hist = np.zeros(2 * (max_iter + 1)) if history else None
+    info = SolveInfo()
+    L.oracle_bicg_k(K, n, col_idx.size, _p(row_ptr), _p(col_idx), _p(lw), _p(a), _p(rpt), _p(cit), _p(lwt), _p(at),
+                    _p(b), _p(x), _p(minv), float(rtol), int(max_iter), ctypes.byref(info), _p(hist))
+    out = {"status": info.status, "iters": info.iters, "restarts": info.restarts,
+           "rr_true": np.array(info.rr_true[:]), "bb": np.array(info.bb[:])}
+    if history:
+        out["history"] = hist[:2 * (info.iters + 1)].reshape(-1, 2)
+    return x, out
 
 
 def cg(row_ptr, col_idx, a, b, x0=None, precond="jacobi", rtol=1e-28, max_iter=10000, log2w=None,

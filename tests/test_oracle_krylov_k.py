@@ -13,6 +13,9 @@
   eigenvalues; TD / QD CG (SPD diffusion) and BiCGSTAB (non-symmetric band) reach
   relative residuals 1e-44 / 1e-60, beyond DD, certified by an exact rational residual
   of b = A sqrt(2)[1..n] with K-component data; NaN input and iteration limits report.
+* TD / QD BiCG equals TD / QD CG bit for bit on a symmetric matrix; CGS and GPBiCG
+  terminate within k steps on k distinct eigenvalues; all three certify 1e-44 / 1e-60
+  on the non-symmetric band; their K = 2 instances are the DD solvers.
 """
 import math
 from fractions import Fraction
@@ -156,3 +159,45 @@ def test_k_solver_failures(K):
         assert solve(K, rp, ci, a, bad, rtol=RTOL[K], max_iter=50)[1]["status"] == -6
         _, info = solve(K, rp, ci, a, b, rtol=RTOL[K], max_iter=3)
         assert info["status"] == -5 and info["iters"] == 3
+
+
+@pytest.mark.parametrize("K", [3, 4])
+def test_k_bicg_cgs_gpbicg(K):
+    """TD / QD BiCG, CGS and GPBiCG: BiCG equals CG bit for bit on an exactly symmetric
+    matrix; CGS and GPBiCG terminate within k steps on k distinct eigenvalues; all three
+    reach 1e-44 / 1e-60 on the non-symmetric band, certified by an exact residual; the
+    K = 2 instances are the DD solvers."""
+    rp, ci, a = diffusion3d_7pt(m=6, sigma=1.5, seed=8, K=K)
+    n = rp.size - 1
+    b = random_mp(n, K, np.random.default_rng(31))
+    for precond in ("none", "jacobi"):
+        xc, ic = ref.cg_k(K, rp, ci, a, b, precond=precond, rtol=RTOL[K], max_iter=5000, history=True)
+        xb, ib = ref.bicg_k(K, rp, ci, a, b, precond=precond, rtol=RTOL[K], max_iter=5000, history=True)
+        assert ic["status"] == 0 and (ib["status"], ib["iters"], ib["restarts"]) == (0, ic["iters"], ic["restarts"])
+        assert np.array_equal(xb, xc) and np.array_equal(ib["history"], ic["history"])
+    nd = 400
+    eig = np.array([1.0, 2.0, 3.0, 5.0, 8.0])
+    ad = np.zeros((K, nd))
+    ad[0] = eig[np.arange(nd) % eig.size]
+    bd = random_mp(nd, K, np.random.default_rng(32))
+    idx = np.arange(nd + 1, dtype=np.int32)
+    for solve in (ref.cgs_k, ref.gpbicg_k):
+        _, info = solve(K, idx, idx[:-1], ad, bd, precond="none", rtol=RTOL[K], max_iter=50)
+        assert info["status"] == 0 and info["iters"] <= eig.size, solve.__name__
+    rp, ci, a = banded_nonsymmetric(n=150, seed=5, K=K)
+    b = ref.spmv(K, rp, ci, a, sqrt2_vector(150, K))
+    for solve in (ref.bicg_k, ref.cgs_k, ref.gpbicg_k):
+        x, info = solve(K, rp, ci, a, b, precond="jacobi", rtol=RTOL[K], max_iter=20000)
+        assert info["status"] == 0, solve.__name__
+        ok, rel = _certified(rp, ci, a, b, x, RTOL[K])
+        assert ok, (solve.__name__, rel)
+
+
+def test_k2_instances_are_the_dd_solvers():
+    rp, ci, a = banded_nonsymmetric(n=200, seed=5)
+    b = random_mp(200, 2, np.random.default_rng(33))
+    for gen, dd in ((ref.bicg_k, ref.bicg), (ref.cgs_k, ref.cgs), (ref.gpbicg_k, ref.gpbicg)):
+        xk, ik = gen(2, rp, ci, a, b, rtol=1e-28, max_iter=20000, history=True)
+        xd, idd = dd(rp, ci, a, b, rtol=1e-28, max_iter=20000, history=True)
+        assert np.array_equal(xk, xd) and np.array_equal(ik["history"], idd["history"])
+        assert (ik["status"], ik["iters"]) == (idd["status"], idd["iters"])
