@@ -330,6 +330,25 @@ mp_status mpkrylov_bicgstab_qd(const mp_csr *A, const double *a, const double *b
                                const mp_solve_opts *opts, const mp_plan *plan, void *ws, size_t ws_bytes,
                                mp_solve_info *info, void *stream);
 
+/* CGS, GPBiCG and BiCG in TD / QD: the steps of mpkrylov_cgs, mpkrylov_gpbicg and
+ * mpkrylov_bicg with the K-component operations above (BiCG: At, at the K-component
+ * transpose, e.g. from mp_csr_transpose with ncomp = K, plan_t NULL or a K-component
+ * plan of At).  Arguments, workspace and results as mpkrylov_cg_td / _qd. */
+mp_status mpkrylov_cgs_td(const mp_csr *A, const double *a, const double *b, double *x, const mp_solve_opts *opts,
+                          const mp_plan *plan, void *ws, size_t ws_bytes, mp_solve_info *info, void *stream);
+mp_status mpkrylov_cgs_qd(const mp_csr *A, const double *a, const double *b, double *x, const mp_solve_opts *opts,
+                          const mp_plan *plan, void *ws, size_t ws_bytes, mp_solve_info *info, void *stream);
+mp_status mpkrylov_gpbicg_td(const mp_csr *A, const double *a, const double *b, double *x, const mp_solve_opts *opts,
+                             const mp_plan *plan, void *ws, size_t ws_bytes, mp_solve_info *info, void *stream);
+mp_status mpkrylov_gpbicg_qd(const mp_csr *A, const double *a, const double *b, double *x, const mp_solve_opts *opts,
+                             const mp_plan *plan, void *ws, size_t ws_bytes, mp_solve_info *info, void *stream);
+mp_status mpkrylov_bicg_td(const mp_csr *A, const double *a, const mp_csr *At, const double *at, const double *b,
+                           double *x, const mp_solve_opts *opts, const mp_plan *plan, const mp_plan *plan_t, void *ws,
+                           size_t ws_bytes, mp_solve_info *info, void *stream);
+mp_status mpkrylov_bicg_qd(const mp_csr *A, const double *a, const mp_csr *At, const double *at, const double *b,
+                           double *x, const mp_solve_opts *opts, const mp_plan *plan, const mp_plan *plan_t, void *ws,
+                           size_t ws_bytes, mp_solve_info *info, void *stream);
+
 /*
  * DD GPBiCG (Zhang's generalized product-type method based on BiCG; Sec. 4.2's list)
  * with right Jacobi preconditioning (opts.precond; every product with A is one with

@@ -85,8 +85,12 @@ for _name in ("mpkrylov_cg", "mpkrylov_bicgstab", "mpkrylov_cgs", "mpkrylov_gpbi
     _SIGS[_name] = ([_CSR, _P, _P, _P, ctypes.POINTER(mp_solve_opts), _P, _P, ctypes.c_size_t,
                      ctypes.POINTER(mp_solve_info), _P], ctypes.c_int)
 
-for _name in ("mpkrylov_cg_td", "mpkrylov_cg_qd", "mpkrylov_bicgstab_td", "mpkrylov_bicgstab_qd"):
+for _name in ("mpkrylov_cg_td", "mpkrylov_cg_qd", "mpkrylov_bicgstab_td", "mpkrylov_bicgstab_qd", "mpkrylov_cgs_td",
+              "mpkrylov_cgs_qd", "mpkrylov_gpbicg_td", "mpkrylov_gpbicg_qd"):
     _SIGS[_name] = ([_CSR, _P, _P, _P, ctypes.POINTER(mp_solve_opts), _P, _P, ctypes.c_size_t,
+                     ctypes.POINTER(mp_solve_info), _P], ctypes.c_int)
+for _name in ("mpkrylov_bicg_td", "mpkrylov_bicg_qd"):
+    _SIGS[_name] = ([_CSR, _P, _CSR, _P, _P, _P, ctypes.POINTER(mp_solve_opts), _P, _P, _P, ctypes.c_size_t,
                      ctypes.POINTER(mp_solve_info), _P], ctypes.c_int)
 _SIGS["mpkrylov_mp_workspace_bytes"] = ([_CSR, _I, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int)
 _SIGS["mpkrylov_bicg"] = ([_CSR, _P, _CSR, _P, _P, _P, ctypes.POINTER(mp_solve_opts), _P, _P, _P, ctypes.c_size_t,
@@ -421,15 +425,11 @@ def _solver_k(name, K):
     fn = getattr(_lib, name)
 
     def call(A, a, b, x, plan=None, ws=None, stream=None, raise_on_failure=False, **opts):
-        import torch
         _check_mp(a, K, A.nnz, "a")
         _check_mp(b, K, A.n_rows, "b")
         _check_mp(x, K, A.n_rows, "x")
         o = _opts(**opts)
-        nb = ctypes.c_size_t()
-        _check(_lib.mpkrylov_mp_workspace_bytes(ctypes.byref(A.c), K, ctypes.byref(nb)), "mpkrylov_mp_workspace_bytes")
-        if ws is None:
-            ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+        ws = _mp_workspace(A, K, ws)
         info = mp_solve_info()
         st = fn(ctypes.byref(A.c), _ptr(a), _ptr(b), _ptr(x), ctypes.byref(o), _plan_handle(plan), _ptr(ws),
                 ws.numel() * ws.element_size(), ctypes.byref(info), _stream_ptr(stream))
@@ -442,10 +442,46 @@ def _solver_k(name, K):
     return call
 
 
+def _mp_workspace(A, K, ws):
+    import torch
+    nb = ctypes.c_size_t()
+    _check(_lib.mpkrylov_mp_workspace_bytes(ctypes.byref(A.c), K, ctypes.byref(nb)), "mpkrylov_mp_workspace_bytes")
+    return torch.empty(nb.value, dtype=torch.uint8, device="cuda") if ws is None else ws
+
+
+def _bicg_k(name, K):
+    fn = getattr(_lib, name)
+
+    def call(A, a, At, at, b, x, plan=None, plan_t=None, ws=None, stream=None, raise_on_failure=False, **opts):
+        _check_mp(a, K, A.nnz, "a")
+        _check_mp(at, K, At.nnz, "at")
+        _check_mp(b, K, A.n_rows, "b")
+        _check_mp(x, K, A.n_rows, "x")
+        o = _opts(**opts)
+        ws = _mp_workspace(A, K, ws)
+        info = mp_solve_info()
+        st = fn(ctypes.byref(A.c), _ptr(a), ctypes.byref(At.c), _ptr(at), _ptr(b), _ptr(x), ctypes.byref(o),
+                _plan_handle(plan), _plan_handle(plan_t), _ptr(ws), ws.numel() * ws.element_size(), ctypes.byref(info),
+                _stream_ptr(stream))
+        if st not in (MP_OK, -5, -6) or (raise_on_failure and st != MP_OK):
+            _check(st, name)
+        return _info_dict(info)
+
+    call.__name__ = name
+    call.__doc__ = "%d-component BiCG (C ABI %s) with A^T given as (At, at); returns the info record." % (K, name)
+    return call
+
+
 mpkrylov_cg_td = _solver_k("mpkrylov_cg_td", 3)
 mpkrylov_cg_qd = _solver_k("mpkrylov_cg_qd", 4)
 mpkrylov_bicgstab_td = _solver_k("mpkrylov_bicgstab_td", 3)
 mpkrylov_bicgstab_qd = _solver_k("mpkrylov_bicgstab_qd", 4)
+mpkrylov_cgs_td = _solver_k("mpkrylov_cgs_td", 3)
+mpkrylov_cgs_qd = _solver_k("mpkrylov_cgs_qd", 4)
+mpkrylov_gpbicg_td = _solver_k("mpkrylov_gpbicg_td", 3)
+mpkrylov_gpbicg_qd = _solver_k("mpkrylov_gpbicg_qd", 4)
+mpkrylov_bicg_td = _bicg_k("mpkrylov_bicg_td", 3)
+mpkrylov_bicg_qd = _bicg_k("mpkrylov_bicg_qd", 4)
 mpkrylov_ir = _solver("mpkrylov_ir")
 
 

@@ -555,6 +555,410 @@ __global__ __launch_bounds__(256) void k_bi_rr(const mpn<K> *__restrict__ part, 
     }
 }
 
+// ---------------------------------------------------------------------------
+// BiCG (A^T explicit; the shadow system preconditioned by the same Jacobi M)
+// ---------------------------------------------------------------------------
+
+// sigma = (p~, q): breakdown when 0 or not finite; alpha = rho / sigma
+template <int K>
+__global__ __launch_bounds__(256) void k_bicg_alpha(const mpn<K> *__restrict__ ppq, int m, State<K> *__restrict__ st)
+{
+    __shared__ mpn<K> P[kMaxChunks];
+    if (st->done != RUN) return;
+    const mpn<K> pq = pair_tree(ppq, m, P);
+    if (threadIdx.x == 0) {
+        st->pq = pq;
+        if (pq.c[0] == 0.0 || !k_finite(pq))
+            st->done = BROKE_DOWN;
+        else
+            st->alpha = k_div(st->rho, pq);
+    }
+}
+
+// x += alpha p; r -= alpha q; r~ -= alpha q~; z = M^-1 r; z~ = M^-1 r~
+template <int K>
+__global__ __launch_bounds__(256) void k_bicg_update(int64_t n, double *__restrict__ x, double *__restrict__ r,
+                                                     double *__restrict__ z, const double *__restrict__ p,
+                                                     const double *__restrict__ q, double *__restrict__ rt,
+                                                     double *__restrict__ zt, const double *__restrict__ qt,
+                                                     const double *__restrict__ minv, const State<K> *__restrict__ st)
+{
+    if (st->done != RUN) return;
+    const mpn<K> alpha = st->alpha;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        stk<K>(x, n, i, mp_add(ldk<K>(x, n, i), mp_mul(alpha, ldk<K>(p, n, i))));
+        const mpn<K> ri = k_sub(ldk<K>(r, n, i), mp_mul(alpha, ldk<K>(q, n, i)));
+        const mpn<K> rti = k_sub(ldk<K>(rt, n, i), mp_mul(alpha, ldk<K>(qt, n, i)));
+        stk<K>(r, n, i, ri);
+        stk<K>(rt, n, i, rti);
+        stk<K>(z, n, i, minv ? mp_mul_d(ri, minv[i]) : ri);
+        stk<K>(zt, n, i, minv ? mp_mul_d(rti, minv[i]) : rti);
+    }
+}
+
+// rho' = (r~, z), rr = (r, r): one step counted; breakdown when not finite or when
+// rho' = 0 short of the tolerance; beta = rho' / rho; stop tests
+template <int K>
+__global__ __launch_bounds__(256) void k_bicg_beta(const mpn<K> *__restrict__ prz, const mpn<K> *__restrict__ prr,
+                                                   int m, State<K> *__restrict__ st)
+{
+    __shared__ mpn<K> P[kMaxChunks];
+    if (st->done != RUN) return;
+    const mpn<K> rz = pair_tree(prz, m, P);
+    const mpn<K> rr = pair_tree(prr, m, P);
+    if (threadIdx.x == 0) {
+        st->iters += 1;
+        st->rr = rr;
+        if (!k_finite(rr) || !k_finite(rz) || (rz.c[0] == 0.0 && !k_le(rr, st->tol2))) {
+            st->done = BROKE_DOWN;
+            return;
+        }
+        st->beta = k_div(rz, st->rho);
+        st->rho = rz;
+        if (k_le(rr, st->tol2))
+            st->done = RECURRENCE_MET;
+        else if (st->iters >= st->max_iter)
+            st->done = ITER_LIMIT;
+    }
+}
+
+// p = z + beta p; p~ = z~ + beta p~
+template <int K>
+__global__ __launch_bounds__(256) void k_bicg_p(int64_t n, const double *__restrict__ z, double *__restrict__ p,
+                                                const double *__restrict__ zt, double *__restrict__ pt,
+                                                const State<K> *__restrict__ st)
+{
+    if (st->done != RUN) return;
+    const mpn<K> beta = st->beta;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        stk<K>(p, n, i, mp_add(ldk<K>(z, n, i), mp_mul(beta, ldk<K>(p, n, i))));
+        stk<K>(pt, n, i, mp_add(ldk<K>(zt, n, i), mp_mul(beta, ldk<K>(pt, n, i))));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// CGS (right Jacobi preconditioning)
+// ---------------------------------------------------------------------------
+
+template <int K>
+__global__ __launch_bounds__(256) void k_cgs_rho(const mpn<K> *__restrict__ prho, int m, State<K> *__restrict__ st)
+{
+    __shared__ mpn<K> P[kMaxChunks];
+    if (st->done != RUN) return;
+    const mpn<K> rho = pair_tree(prho, m, P);
+    if (threadIdx.x == 0) {
+        if (rho.c[0] == 0.0 || !k_finite(rho)) {
+            st->done = BROKE_DOWN;
+            return;
+        }
+        st->rho = rho;
+        if (!st->fresh) st->beta = k_div(rho, st->rho_old);
+    }
+}
+
+// fresh: u = p = r; else u = r + beta q, p = u + beta (q + beta p); p^ = M^-1 p
+template <int K>
+__global__ __launch_bounds__(256) void k_cgs_up(int64_t n, const double *__restrict__ r, const double *__restrict__ q,
+                                                double *__restrict__ u, double *__restrict__ p,
+                                                double *__restrict__ ph, const double *__restrict__ minv,
+                                                const State<K> *__restrict__ st)
+{
+    if (st->done != RUN) return;
+    const bool fresh = st->fresh != 0;
+    const mpn<K> beta = st->beta;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const mpn<K> ri = ldk<K>(r, n, i);
+        mpn<K> pi;
+        if (fresh) {
+            stk<K>(u, n, i, ri);
+            pi = ri;
+        } else {
+            const mpn<K> qi = ldk<K>(q, n, i);
+            const mpn<K> ui = mp_add(ri, mp_mul(beta, qi));
+            const mpn<K> w = mp_add(qi, mp_mul(beta, ldk<K>(p, n, i)));
+            stk<K>(u, n, i, ui);
+            pi = mp_add(ui, mp_mul(beta, w));
+        }
+        stk<K>(p, n, i, pi);
+        stk<K>(ph, n, i, minv ? mp_mul_d(pi, minv[i]) : pi);
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_cgs_alpha(const mpn<K> *__restrict__ psig, int m, State<K> *__restrict__ st)
+{
+    __shared__ mpn<K> P[kMaxChunks];
+    if (st->done != RUN) return;
+    const mpn<K> sigma = pair_tree(psig, m, P);
+    if (threadIdx.x == 0) {
+        st->fresh = 0;
+        st->pq = sigma;
+        if (sigma.c[0] == 0.0 || !k_finite(sigma))
+            st->done = BROKE_DOWN;
+        else
+            st->alpha = k_div(st->rho, sigma);
+    }
+}
+
+// q = u - alpha v; u^ = M^-1 (u + q); x += alpha u^
+template <int K>
+__global__ __launch_bounds__(256) void k_cgs_q(int64_t n, const double *__restrict__ u, const double *__restrict__ v,
+                                               double *__restrict__ q, double *__restrict__ uh, double *__restrict__ x,
+                                               const double *__restrict__ minv, const State<K> *__restrict__ st)
+{
+    if (st->done != RUN) return;
+    const mpn<K> alpha = st->alpha;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const mpn<K> ui = ldk<K>(u, n, i);
+        const mpn<K> qi = k_sub(ui, mp_mul(alpha, ldk<K>(v, n, i)));
+        const mpn<K> sm = mp_add(ui, qi);
+        const mpn<K> uhi = minv ? mp_mul_d(sm, minv[i]) : sm;
+        stk<K>(q, n, i, qi);
+        stk<K>(uh, n, i, uhi);
+        stk<K>(x, n, i, mp_add(ldk<K>(x, n, i), mp_mul(alpha, uhi)));
+    }
+}
+
+// r -= alpha t
+template <int K>
+__global__ __launch_bounds__(256) void k_cgs_r(int64_t n, double *__restrict__ r, const double *__restrict__ t,
+                                               const State<K> *__restrict__ st)
+{
+    if (st->done != RUN) return;
+    const mpn<K> alpha = st->alpha;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        stk<K>(r, n, i, k_sub(ldk<K>(r, n, i), mp_mul(alpha, ldk<K>(t, n, i))));
+}
+
+// rr = (r, r): one step counted; breakdown when not finite; stop tests
+template <int K>
+__global__ __launch_bounds__(256) void k_cgs_rr(const mpn<K> *__restrict__ prr, int m, State<K> *__restrict__ st)
+{
+    __shared__ mpn<K> P[kMaxChunks];
+    if (st->done != RUN) return;
+    const mpn<K> rr = pair_tree(prr, m, P);
+    if (threadIdx.x == 0) {
+        st->iters += 1;
+        st->rr = rr;
+        if (!k_finite(rr)) {
+            st->done = BROKE_DOWN;
+            return;
+        }
+        st->rho_old = st->rho;
+        if (k_le(rr, st->tol2))
+            st->done = RECURRENCE_MET;
+        else if (st->iters >= st->max_iter)
+            st->done = ITER_LIMIT;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// GPBiCG (right Jacobi preconditioning)
+// ---------------------------------------------------------------------------
+
+template <int K>
+__global__ __launch_bounds__(256) void k_gp_rho(const mpn<K> *__restrict__ prho, int m, State<K> *__restrict__ st)
+{
+    __shared__ mpn<K> P[kMaxChunks];
+    if (st->done != RUN) return;
+    const mpn<K> rho = pair_tree(prho, m, P);
+    if (threadIdx.x == 0) {
+        if (rho.c[0] == 0.0 || !k_finite(rho)) {
+            st->done = BROKE_DOWN;
+            return;
+        }
+        st->rho = rho;
+        if (!st->fresh) st->beta = mp_mul(k_div(st->alpha, st->omega), k_div(rho, st->rho_old));
+    }
+}
+
+// fresh: p = r; else p = r + beta (p - u), w = c + beta q; tmp = M p
+template <int K>
+__global__ __launch_bounds__(256) void k_gp_p(int64_t n, const double *__restrict__ r, double *__restrict__ p,
+                                              const double *__restrict__ u, const double *__restrict__ c,
+                                              const double *__restrict__ q, double *__restrict__ w,
+                                              double *__restrict__ tmp, const double *__restrict__ minv,
+                                              const State<K> *__restrict__ st)
+{
+    if (st->done != RUN) return;
+    const bool fresh = st->fresh != 0;
+    const mpn<K> beta = st->beta;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const mpn<K> ri = ldk<K>(r, n, i);
+        mpn<K> pi;
+        if (fresh) {
+            pi = ri;
+        } else {
+            pi = mp_add(ri, mp_mul(beta, k_sub(ldk<K>(p, n, i), ldk<K>(u, n, i))));
+            stk<K>(w, n, i, mp_add(ldk<K>(c, n, i), mp_mul(beta, ldk<K>(q, n, i))));
+        }
+        stk<K>(p, n, i, pi);
+        stk<K>(tmp, n, i, minv ? mp_mul_d(pi, minv[i]) : pi);
+    }
+}
+
+// sigma = (r~, q): breakdown when 0 or not finite; alpha = rho / sigma (the step's
+// first-step flag stays set until the step ends)
+template <int K>
+__global__ __launch_bounds__(256) void k_gp_alpha(const mpn<K> *__restrict__ psig, int m, State<K> *__restrict__ st)
+{
+    __shared__ mpn<K> P[kMaxChunks];
+    if (st->done != RUN) return;
+    const mpn<K> sigma = pair_tree(psig, m, P);
+    if (threadIdx.x == 0) {
+        st->pq = sigma;
+        if (sigma.c[0] == 0.0 || !k_finite(sigma))
+            st->done = BROKE_DOWN;
+        else
+            st->alpha = k_div(st->rho, sigma);
+    }
+}
+
+// t = r - alpha q; later steps y = (t' - t) - alpha w; tmp = M t
+template <int K>
+__global__ __launch_bounds__(256) void k_gp_t(int64_t n, const double *__restrict__ r, const double *__restrict__ q,
+                                              const double *__restrict__ tp, const double *__restrict__ w,
+                                              double *__restrict__ t, double *__restrict__ y, double *__restrict__ tmp,
+                                              const double *__restrict__ minv, const State<K> *__restrict__ st)
+{
+    if (st->done != RUN) return;
+    const bool fresh = st->fresh != 0;
+    const mpn<K> alpha = st->alpha;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const mpn<K> ti = k_sub(ldk<K>(r, n, i), mp_mul(alpha, ldk<K>(q, n, i)));
+        stk<K>(t, n, i, ti);
+        if (!fresh) stk<K>(y, n, i, k_sub(k_sub(ldk<K>(tp, n, i), ti), mp_mul(alpha, ldk<K>(w, n, i))));
+        stk<K>(tmp, n, i, minv ? mp_mul_d(ti, minv[i]) : ti);
+    }
+}
+
+// half step met the tolerance: x += M (alpha p); r = t
+template <int K>
+__global__ __launch_bounds__(256) void k_gp_half(int64_t n, double *__restrict__ x, double *__restrict__ r,
+                                                 const double *__restrict__ p, const double *__restrict__ t,
+                                                 const double *__restrict__ minv, const State<K> *__restrict__ st)
+{
+    if (st->done != RUN || !st->half) return;
+    const mpn<K> alpha = st->alpha;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const mpn<K> d = mp_mul(alpha, ldk<K>(p, n, i));
+        stk<K>(x, n, i, mp_add(ldk<K>(x, n, i), minv ? mp_mul_d(d, minv[i]) : d));
+        stk<K>(r, n, i, ldk<K>(t, n, i));
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(64) void k_gp_half_final(State<K> *__restrict__ st)
+{
+    if (threadIdx.x != 0 || st->done != RUN || !st->half) return;
+    st->rr = st->ss;
+    st->rho_old = st->rho;
+    st->fresh = 1;
+    st->half = 0;
+    st->done = RECURRENCE_MET;
+}
+
+// zeta (kept in omega) and eta (kept in ts): first step zeta = (c,t)/(c,c), eta = 0;
+// later steps from d = (c,c)(y,y) - (y,c)^2
+template <int K>
+__global__ __launch_bounds__(256) void k_gp_zeta(const mpn<K> *__restrict__ pcc, const mpn<K> *__restrict__ pct,
+                                                 const mpn<K> *__restrict__ pyy, const mpn<K> *__restrict__ pyc,
+                                                 const mpn<K> *__restrict__ pyt, int m, State<K> *__restrict__ st)
+{
+    __shared__ mpn<K> P[kMaxChunks];
+    if (st->done != RUN) return;
+    const bool fresh = st->fresh != 0;
+    const mpn<K> cc = pair_tree(pcc, m, P);
+    const mpn<K> ct = pair_tree(pct, m, P);
+    mpn<K> yy = mp_zero<K>(), yc = mp_zero<K>(), yt = mp_zero<K>();
+    if (!fresh) {
+        yy = pair_tree(pyy, m, P);
+        yc = pair_tree(pyc, m, P);
+        yt = pair_tree(pyt, m, P);
+    }
+    if (threadIdx.x == 0) {
+        mpn<K> zeta, eta;
+        if (fresh) {
+            if (cc.c[0] == 0.0 || !k_finite(cc)) {
+                st->done = BROKE_DOWN;
+                return;
+            }
+            zeta = k_div(ct, cc);
+            eta = mp_zero<K>();
+        } else {
+            const mpn<K> den = k_sub(mp_mul(cc, yy), mp_mul(yc, yc));
+            if (den.c[0] == 0.0 || !k_finite(den)) {
+                st->done = BROKE_DOWN;
+                return;
+            }
+            zeta = k_div(k_sub(mp_mul(yy, ct), mp_mul(yt, yc)), den);
+            eta = k_div(k_sub(mp_mul(cc, yt), mp_mul(yc, ct)), den);
+        }
+        if (zeta.c[0] == 0.0 || !k_finite(zeta) || !k_finite(eta)) {
+            st->done = BROKE_DOWN;
+            return;
+        }
+        st->omega = zeta;
+        st->ts = eta;
+    }
+}
+
+// u, z, x, r and t' of a full step (see the header for the forms)
+template <int K>
+__global__ __launch_bounds__(256) void k_gp_update(int64_t n, double *__restrict__ x, double *__restrict__ r,
+                                                   const double *__restrict__ p, const double *__restrict__ q,
+                                                   const double *__restrict__ t, const double *__restrict__ cv,
+                                                   const double *__restrict__ y, double *__restrict__ u,
+                                                   double *__restrict__ z, double *__restrict__ tp,
+                                                   const double *__restrict__ minv, const State<K> *__restrict__ st)
+{
+    if (st->done != RUN) return;
+    const bool fresh = st->fresh != 0;
+    const mpn<K> alpha = st->alpha, beta = st->beta, zeta = st->omega, eta = st->ts;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const mpn<K> ri = ldk<K>(r, n, i), ti = ldk<K>(t, n, i), qi = ldk<K>(q, n, i), ci = ldk<K>(cv, n, i);
+        mpn<K> ui, zi, rn;
+        if (fresh) {
+            ui = mp_mul(zeta, qi);
+            zi = k_sub(mp_mul(zeta, ri), mp_mul(alpha, ui));
+            rn = k_sub(ti, mp_mul(zeta, ci));
+        } else {
+            const mpn<K> g = mp_add(k_sub(ldk<K>(tp, n, i), ri), mp_mul(beta, ldk<K>(u, n, i)));
+            ui = mp_add(mp_mul(zeta, qi), mp_mul(eta, g));
+            zi = k_sub(mp_add(mp_mul(zeta, ri), mp_mul(eta, ldk<K>(z, n, i))), mp_mul(alpha, ui));
+            rn = k_sub(k_sub(ti, mp_mul(eta, ldk<K>(y, n, i))), mp_mul(zeta, ci));
+        }
+        stk<K>(u, n, i, ui);
+        stk<K>(z, n, i, zi);
+        const mpn<K> d = mp_add(mp_mul(alpha, ldk<K>(p, n, i)), zi);
+        stk<K>(x, n, i, mp_add(ldk<K>(x, n, i), minv ? mp_mul_d(d, minv[i]) : d));
+        stk<K>(r, n, i, rn);
+        stk<K>(tp, n, i, ti);
+    }
+}
+
+// rr = (r, r): breakdown when not finite; the next step is not fresh; stop tests
+template <int K>
+__global__ __launch_bounds__(256) void k_gp_rr(const mpn<K> *__restrict__ prr, int m, State<K> *__restrict__ st)
+{
+    __shared__ mpn<K> P[kMaxChunks];
+    if (st->done != RUN) return;
+    const mpn<K> rr = pair_tree(prr, m, P);
+    if (threadIdx.x == 0) {
+        st->rr = rr;
+        if (!k_finite(rr)) {
+            st->done = BROKE_DOWN;
+            return;
+        }
+        st->rho_old = st->rho;
+        st->fresh = 0;
+        if (k_le(rr, st->tol2))
+            st->done = RECURRENCE_MET;
+        else if (st->iters >= st->max_iter)
+            st->done = ITER_LIMIT;
+    }
+}
+
 #undef KMP_FOR
 
 // ---------------------------------------------------------------------------
@@ -563,11 +967,14 @@ __global__ __launch_bounds__(256) void k_bi_rr(const mpn<K> *__restrict__ part, 
 
 inline size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+constexpr int kVecs = 12;   // K-component work vectors (GPBiCG uses all of them)
+constexpr int kParts = 6;   // chunk-sum arrays
+
 template <int K>
 size_t ws_bytes(int64_t n)
 {
     return 2 * al256(sizeof(State<K>)) + al256(sizeof(double) * (size_t)n) +
-           9 * al256(sizeof(double) * K * (size_t)n) + 3 * al256(sizeof(mpn<K>) * kMaxChunks);
+           kVecs * al256(sizeof(double) * K * (size_t)n) + kParts * al256(sizeof(mpn<K>) * kMaxChunks);
 }
 
 template <int K>
@@ -581,8 +988,8 @@ struct Solver {
     unsigned vb;
     State<K> *st;
     double *minv;
-    double *v[9];
-    mpn<K> *part[3];
+    double *v[kVecs];
+    mpn<K> *part[kParts];
 
     void carve(void *ws)
     {
@@ -591,11 +998,11 @@ struct Solver {
         p += 2 * al256(sizeof(State<K>));
         minv = reinterpret_cast<double *>(p);
         p += al256(sizeof(double) * (size_t)n);
-        for (int i = 0; i < 9; ++i) {
+        for (int i = 0; i < kVecs; ++i) {
             v[i] = reinterpret_cast<double *>(p);
             p += al256(sizeof(double) * K * (size_t)n);
         }
-        for (int i = 0; i < 3; ++i) {
+        for (int i = 0; i < kParts; ++i) {
             part[i] = reinterpret_cast<mpn<K> *>(p);
             p += al256(sizeof(mpn<K>) * kMaxChunks);
         }
@@ -811,11 +1218,229 @@ mp_status run_bicgstab(Solver<K> &S, const double *b, double *x, const mp_solve_
     return MP_OK;
 }
 
-// kind 0 CG, 1 BiCGSTAB
+
+template <int K>
+mp_status run_bicg(Solver<K> &S, const mp_csr *At, const double *at, const mp_plan *plan_t, const double *b,
+                   double *x, const mp_solve_opts *o, mp_solve_info *info, const char *name)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    const int64_t n = S.n;
+    const int m = S.m;
+    double *r = S.v[0], *z = S.v[1], *p = S.v[2], *q = S.v[3], *rt = S.v[4], *zt = S.v[5], *pt = S.v[6], *qt = S.v[7];
+    const double *minv = o->precond == MP_PRECOND_JACOBI ? S.minv : nullptr;
+    const int every = o->check_every > 0 ? o->check_every : 32;
+    const int64_t len = (int64_t)K * n;
+    mp_status st;
+    State<K> h;
+    std::memset(&h, 0, sizeof(h));
+    MP_HIP_TRY(hipMemsetAsync(S.st, 0, sizeof(State<K>), S.s));
+    if (minv && (st = S.jacobi()) != MP_OK) return st;
+    // shadow start r~ = r; z = M^-1 r; z~ = p = p~ = z
+    auto reset = [&]() -> mp_status {
+        hipLaunchKernelGGL(k_copy, dim3(S.vb), dim3(256), 0, S.s, len, r, rt);
+        hipLaunchKernelGGL(k_precond<K>, dim3(S.vb), dim3(256), 0, S.s, n, minv, r, z, nullptr);
+        hipLaunchKernelGGL(k_copy, dim3(S.vb), dim3(256), 0, S.s, len, z, zt);
+        hipLaunchKernelGGL(k_copy, dim3(S.vb), dim3(256), 0, S.s, len, z, p);
+        hipLaunchKernelGGL(k_copy, dim3(S.vb), dim3(256), 0, S.s, len, z, pt);
+        return S.launched();
+    };
+    if ((st = S.residual(b, x, q, r)) != MP_OK) return st;
+    if ((st = reset()) != MP_OK) return st;
+    if ((st = S.dot2(b, b, rt, z, S.part[0], S.part[1], nullptr)) != MP_OK) return st;
+    if ((st = S.dot2(r, r, nullptr, nullptr, S.part[2], nullptr, nullptr)) != MP_OK) return st;
+    hipLaunchKernelGGL(k_cg_init<K>, dim3(1), dim3(256), 0, S.s, S.part[0], S.part[1], S.part[2], m, o->rtol * o->rtol,
+                       o->max_iter, S.st);
+    if ((st = S.launched()) != MP_OK) return st;
+    for (;;) {
+        if ((st = S.read_state(&h)) != MP_OK) return st;
+        if (h.done == RUN) {
+            for (int it = 0; it < every; ++it) {
+                if ((st = S.spmv(p, q)) != MP_OK) return st;
+                if ((st = spmv_dispatch(K, false, At, at, nullptr, pt, nullptr, qt, nullptr, plan_t, S.s)) != MP_OK)
+                    return st;
+                if ((st = S.dot2(pt, q, nullptr, nullptr, S.part[0], nullptr, S.st)) != MP_OK) return st;
+                hipLaunchKernelGGL(k_bicg_alpha<K>, dim3(1), dim3(256), 0, S.s, S.part[0], m, S.st);
+                hipLaunchKernelGGL(k_bicg_update<K>, dim3(S.vb), dim3(256), 0, S.s, n, x, r, z, p, q, rt, zt, qt, minv,
+                                   S.st);
+                if ((st = S.launched()) != MP_OK) return st;
+                if ((st = S.dot2(rt, z, r, r, S.part[1], S.part[2], S.st)) != MP_OK) return st;
+                hipLaunchKernelGGL(k_bicg_beta<K>, dim3(1), dim3(256), 0, S.s, S.part[1], S.part[2], m, S.st);
+                hipLaunchKernelGGL(k_bicg_p<K>, dim3(S.vb), dim3(256), 0, S.s, n, z, p, zt, pt, S.st);
+                if ((st = S.launched()) != MP_OK) return st;
+            }
+            continue;
+        }
+        if (h.done == RECURRENCE_MET) {
+            if ((st = S.true_residual(b, x, q, r, true)) != MP_OK) return st;
+            continue;
+        }
+        if (h.done == RESTART) {
+            if ((st = reset()) != MP_OK) return st;
+            if ((st = S.dot2(rt, z, nullptr, nullptr, S.part[1], nullptr, nullptr)) != MP_OK) return st;
+            hipLaunchKernelGGL(k_cg_restart<K>, dim3(1), dim3(256), 0, S.s, S.part[1], m, S.st);
+            if ((st = S.launched()) != MP_OK) return st;
+            continue;
+        }
+        break;
+    }
+    const int status = finish_status(h);
+    if ((st = S.true_residual(b, x, q, r, false)) != MP_OK) return st;
+    if ((st = S.read_state(&h)) != MP_OK) return st;
+    fill(h, status, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(), info);
+    if (status == MP_ERR_NOT_CONVERGED) return fail(MP_ERR_NOT_CONVERGED, "%s: no convergence in %d iterations", name, h.iters);
+    if (status == MP_ERR_BREAKDOWN) return fail(MP_ERR_BREAKDOWN, "%s: breakdown at iteration %d", name, h.iters);
+    return MP_OK;
+}
+
+template <int K>
+mp_status run_cgs(Solver<K> &S, const double *b, double *x, const mp_solve_opts *o, mp_solve_info *info,
+                  const char *name)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    const int64_t n = S.n;
+    const int m = S.m;
+    double *r = S.v[0], *rh = S.v[1], *u = S.v[2], *p = S.v[3], *q = S.v[4], *v = S.v[5];
+    double *uh = S.v[6], *t = S.v[7], *ph = S.v[8];
+    const double *minv = o->precond == MP_PRECOND_JACOBI ? S.minv : nullptr;
+    const int every = o->check_every > 0 ? o->check_every : 32;
+    const int64_t len = (int64_t)K * n;
+    mp_status st;
+    State<K> h;
+    std::memset(&h, 0, sizeof(h));
+    MP_HIP_TRY(hipMemsetAsync(S.st, 0, sizeof(State<K>), S.s));
+    if (minv && (st = S.jacobi()) != MP_OK) return st;
+    if ((st = S.residual(b, x, t, r)) != MP_OK) return st;
+    hipLaunchKernelGGL(k_copy, dim3(S.vb), dim3(256), 0, S.s, len, r, rh);
+    if ((st = S.launched()) != MP_OK) return st;
+    if ((st = S.dot2(b, b, r, r, S.part[0], S.part[1], nullptr)) != MP_OK) return st;
+    hipLaunchKernelGGL(k_bi_init<K>, dim3(1), dim3(256), 0, S.s, S.part[0], S.part[1], m, o->rtol * o->rtol,
+                       o->max_iter, S.st);
+    if ((st = S.launched()) != MP_OK) return st;
+    for (;;) {
+        if ((st = S.read_state(&h)) != MP_OK) return st;
+        if (h.done == RUN) {
+            for (int it = 0; it < every; ++it) {
+                if ((st = S.dot2(rh, r, nullptr, nullptr, S.part[0], nullptr, S.st)) != MP_OK) return st;
+                hipLaunchKernelGGL(k_cgs_rho<K>, dim3(1), dim3(256), 0, S.s, S.part[0], m, S.st);
+                hipLaunchKernelGGL(k_cgs_up<K>, dim3(S.vb), dim3(256), 0, S.s, n, r, q, u, p, ph, minv, S.st);
+                if ((st = S.launched()) != MP_OK) return st;
+                if ((st = S.spmv(ph, v)) != MP_OK) return st;
+                if ((st = S.dot2(rh, v, nullptr, nullptr, S.part[1], nullptr, S.st)) != MP_OK) return st;
+                hipLaunchKernelGGL(k_cgs_alpha<K>, dim3(1), dim3(256), 0, S.s, S.part[1], m, S.st);
+                hipLaunchKernelGGL(k_cgs_q<K>, dim3(S.vb), dim3(256), 0, S.s, n, u, v, q, uh, x, minv, S.st);
+                if ((st = S.launched()) != MP_OK) return st;
+                if ((st = S.spmv(uh, t)) != MP_OK) return st;
+                hipLaunchKernelGGL(k_cgs_r<K>, dim3(S.vb), dim3(256), 0, S.s, n, r, t, S.st);
+                if ((st = S.launched()) != MP_OK) return st;
+                if ((st = S.dot2(r, r, nullptr, nullptr, S.part[2], nullptr, S.st)) != MP_OK) return st;
+                hipLaunchKernelGGL(k_cgs_rr<K>, dim3(1), dim3(256), 0, S.s, S.part[2], m, S.st);
+                if ((st = S.launched()) != MP_OK) return st;
+            }
+            continue;
+        }
+        if (h.done == RECURRENCE_MET) {
+            if ((st = S.true_residual(b, x, t, r, true)) != MP_OK) return st;
+            continue;
+        }
+        if (h.done == RESTART) {
+            hipLaunchKernelGGL(k_copy, dim3(S.vb), dim3(256), 0, S.s, len, r, rh);
+            hipLaunchKernelGGL(k_bi_restart<K>, dim3(1), dim3(64), 0, S.s, S.st);
+            if ((st = S.launched()) != MP_OK) return st;
+            continue;
+        }
+        break;
+    }
+    const int status = finish_status(h);
+    if ((st = S.true_residual(b, x, t, r, false)) != MP_OK) return st;
+    if ((st = S.read_state(&h)) != MP_OK) return st;
+    fill(h, status, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(), info);
+    if (status == MP_ERR_NOT_CONVERGED) return fail(MP_ERR_NOT_CONVERGED, "%s: no convergence in %d iterations", name, h.iters);
+    if (status == MP_ERR_BREAKDOWN) return fail(MP_ERR_BREAKDOWN, "%s: breakdown at iteration %d", name, h.iters);
+    return MP_OK;
+}
+
+template <int K>
+mp_status run_gpbicg(Solver<K> &S, const double *b, double *x, const mp_solve_opts *o, mp_solve_info *info,
+                     const char *name)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    const int64_t n = S.n;
+    const int m = S.m;
+    double *r = S.v[0], *rh = S.v[1], *p = S.v[2], *q = S.v[3], *t = S.v[4], *c = S.v[5];
+    double *y = S.v[6], *u = S.v[7], *z = S.v[8], *w = S.v[9], *tp = S.v[10], *tmp = S.v[11];
+    mpn<K> **P = S.part;
+    const double *minv = o->precond == MP_PRECOND_JACOBI ? S.minv : nullptr;
+    const int every = o->check_every > 0 ? o->check_every : 32;
+    const int64_t len = (int64_t)K * n;
+    mp_status st;
+    State<K> h;
+    std::memset(&h, 0, sizeof(h));
+    MP_HIP_TRY(hipMemsetAsync(S.st, 0, sizeof(State<K>), S.s));
+    if (minv && (st = S.jacobi()) != MP_OK) return st;
+    if ((st = S.residual(b, x, tmp, r)) != MP_OK) return st;
+    hipLaunchKernelGGL(k_copy, dim3(S.vb), dim3(256), 0, S.s, len, r, rh);
+    if ((st = S.launched()) != MP_OK) return st;
+    if ((st = S.dot2(b, b, r, r, P[0], P[1], nullptr)) != MP_OK) return st;
+    hipLaunchKernelGGL(k_bi_init<K>, dim3(1), dim3(256), 0, S.s, P[0], P[1], m, o->rtol * o->rtol, o->max_iter, S.st);
+    if ((st = S.launched()) != MP_OK) return st;
+    for (;;) {
+        if ((st = S.read_state(&h)) != MP_OK) return st;
+        if (h.done == RUN) {
+            for (int it = 0; it < every; ++it) {
+                if ((st = S.dot2(rh, r, nullptr, nullptr, P[0], nullptr, S.st)) != MP_OK) return st;
+                hipLaunchKernelGGL(k_gp_rho<K>, dim3(1), dim3(256), 0, S.s, P[0], m, S.st);
+                hipLaunchKernelGGL(k_gp_p<K>, dim3(S.vb), dim3(256), 0, S.s, n, r, p, u, c, q, w, tmp, minv, S.st);
+                if ((st = S.launched()) != MP_OK) return st;
+                if ((st = S.spmv(tmp, q)) != MP_OK) return st;
+                if ((st = S.dot2(rh, q, nullptr, nullptr, P[1], nullptr, S.st)) != MP_OK) return st;
+                hipLaunchKernelGGL(k_gp_alpha<K>, dim3(1), dim3(256), 0, S.s, P[1], m, S.st);
+                hipLaunchKernelGGL(k_gp_t<K>, dim3(S.vb), dim3(256), 0, S.s, n, r, q, tp, w, t, y, tmp, minv, S.st);
+                if ((st = S.launched()) != MP_OK) return st;
+                if ((st = S.dot2(t, t, nullptr, nullptr, P[2], nullptr, S.st)) != MP_OK) return st;
+                hipLaunchKernelGGL(k_bi_ss<K>, dim3(1), dim3(256), 0, S.s, P[2], m, S.st);
+                hipLaunchKernelGGL(k_gp_half<K>, dim3(S.vb), dim3(256), 0, S.s, n, x, r, p, t, minv, S.st);
+                hipLaunchKernelGGL(k_gp_half_final<K>, dim3(1), dim3(64), 0, S.s, S.st);
+                if ((st = S.launched()) != MP_OK) return st;
+                if ((st = S.spmv(tmp, c)) != MP_OK) return st;
+                if ((st = S.dot2(c, c, c, t, P[0], P[1], S.st)) != MP_OK) return st;
+                if ((st = S.dot2(y, y, y, c, P[2], P[3], S.st)) != MP_OK) return st;
+                if ((st = S.dot2(y, t, nullptr, nullptr, P[4], nullptr, S.st)) != MP_OK) return st;
+                hipLaunchKernelGGL(k_gp_zeta<K>, dim3(1), dim3(256), 0, S.s, P[0], P[1], P[2], P[3], P[4], m, S.st);
+                hipLaunchKernelGGL(k_gp_update<K>, dim3(S.vb), dim3(256), 0, S.s, n, x, r, p, q, t, c, y, u, z, tp, minv,
+                                   S.st);
+                if ((st = S.launched()) != MP_OK) return st;
+                if ((st = S.dot2(r, r, nullptr, nullptr, P[5], nullptr, S.st)) != MP_OK) return st;
+                hipLaunchKernelGGL(k_gp_rr<K>, dim3(1), dim3(256), 0, S.s, P[5], m, S.st);
+                if ((st = S.launched()) != MP_OK) return st;
+            }
+            continue;
+        }
+        if (h.done == RECURRENCE_MET) {
+            if ((st = S.true_residual(b, x, tmp, r, true)) != MP_OK) return st;
+            continue;
+        }
+        if (h.done == RESTART) {
+            hipLaunchKernelGGL(k_copy, dim3(S.vb), dim3(256), 0, S.s, len, r, rh);
+            hipLaunchKernelGGL(k_bi_restart<K>, dim3(1), dim3(64), 0, S.s, S.st);
+            if ((st = S.launched()) != MP_OK) return st;
+            continue;
+        }
+        break;
+    }
+    const int status = finish_status(h);
+    if ((st = S.true_residual(b, x, tmp, r, false)) != MP_OK) return st;
+    if ((st = S.read_state(&h)) != MP_OK) return st;
+    fill(h, status, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(), info);
+    if (status == MP_ERR_NOT_CONVERGED) return fail(MP_ERR_NOT_CONVERGED, "%s: no convergence in %d iterations", name, h.iters);
+    if (status == MP_ERR_BREAKDOWN) return fail(MP_ERR_BREAKDOWN, "%s: breakdown at iteration %d", name, h.iters);
+    return MP_OK;
+}
+
+// kind 0 CG, 1 BiCGSTAB, 2 CGS, 3 GPBiCG, 4 BiCG (with At, at and plan_t)
 template <int K>
 mp_status entry(const char *name, int kind, const mp_csr *A, const double *a, const double *b, double *x,
                 const mp_solve_opts *opts, const mp_plan *plan, void *ws, size_t wsb, mp_solve_info *info,
-                void *stream)
+                void *stream, const mp_csr *At = nullptr, const double *at = nullptr, const mp_plan *plan_t = nullptr)
 {
     clear_error();
     mp_status st = check_csr(A);
@@ -842,6 +1467,17 @@ mp_status entry(const char *name, int kind, const mp_csr *A, const double *a, co
         std::memset(info, 0, sizeof(*info));
         return MP_OK;
     }
+    if (kind == 4) {
+        if ((st = check_csr(At)) != MP_OK) return st;
+        if (At->n_rows != A->n_rows || At->n_cols != A->n_cols || At->nnz != A->nnz)
+            return fail(MP_ERR_INVALID_ARG, "%s: At is not %d x %d with %lld elements", name, A->n_rows, A->n_cols,
+                        (long long)A->nnz);
+        if (A->nnz > 0 && !at) return fail(MP_ERR_INVALID_ARG, "%s: at is NULL", name);
+        if (plan_t && (plan_t->ncomp != K || plan_t->cplx || plan_t->n_rows != At->n_rows || plan_t->nnz != At->nnz))
+            return fail(MP_ERR_INVALID_ARG, "%s: plan_t is not a %d-component real plan of At", name, K);
+        if (overlaps(x, vb, at, sizeof(double) * K * (size_t)A->nnz))
+            return fail(MP_ERR_ALIAS, "%s: x overlaps at", name);
+    }
     Solver<K> S;
     S.A = A;
     S.a = a;
@@ -852,7 +1488,13 @@ mp_status entry(const char *name, int kind, const mp_csr *A, const double *a, co
     const int64_t blocks = (S.n + 255) / 256;
     S.vb = (unsigned)(blocks < 8192 ? blocks : 8192);
     S.carve(ws);
-    return kind == 0 ? run_cg<K>(S, b, x, opts, info, name) : run_bicgstab<K>(S, b, x, opts, info, name);
+    switch (kind) {
+        case 0: return run_cg<K>(S, b, x, opts, info, name);
+        case 1: return run_bicgstab<K>(S, b, x, opts, info, name);
+        case 2: return run_cgs<K>(S, b, x, opts, info, name);
+        case 3: return run_gpbicg<K>(S, b, x, opts, info, name);
+        default: return run_bicg<K>(S, At, at, plan_t, b, x, opts, info, name);
+    }
 }
 
 }  // namespace kmp
@@ -895,6 +1537,48 @@ mp_status mpkrylov_bicgstab_qd(const mp_csr *A, const double *a, const double *b
                                mp_solve_info *info, void *stream)
 {
     return mpk::kmp::entry<4>("mpkrylov_bicgstab_qd", 1, A, a, b, x, opts, plan, ws, ws_bytes, info, stream);
+}
+
+}  // extern "C"
+
+extern "C" {
+
+mp_status mpkrylov_cgs_td(const mp_csr *A, const double *a, const double *b, double *x, const mp_solve_opts *opts,
+                          const mp_plan *plan, void *ws, size_t ws_bytes, mp_solve_info *info, void *stream)
+{
+    return mpk::kmp::entry<3>("mpkrylov_cgs_td", 2, A, a, b, x, opts, plan, ws, ws_bytes, info, stream);
+}
+
+mp_status mpkrylov_cgs_qd(const mp_csr *A, const double *a, const double *b, double *x, const mp_solve_opts *opts,
+                          const mp_plan *plan, void *ws, size_t ws_bytes, mp_solve_info *info, void *stream)
+{
+    return mpk::kmp::entry<4>("mpkrylov_cgs_qd", 2, A, a, b, x, opts, plan, ws, ws_bytes, info, stream);
+}
+
+mp_status mpkrylov_gpbicg_td(const mp_csr *A, const double *a, const double *b, double *x, const mp_solve_opts *opts,
+                             const mp_plan *plan, void *ws, size_t ws_bytes, mp_solve_info *info, void *stream)
+{
+    return mpk::kmp::entry<3>("mpkrylov_gpbicg_td", 3, A, a, b, x, opts, plan, ws, ws_bytes, info, stream);
+}
+
+mp_status mpkrylov_gpbicg_qd(const mp_csr *A, const double *a, const double *b, double *x, const mp_solve_opts *opts,
+                             const mp_plan *plan, void *ws, size_t ws_bytes, mp_solve_info *info, void *stream)
+{
+    return mpk::kmp::entry<4>("mpkrylov_gpbicg_qd", 3, A, a, b, x, opts, plan, ws, ws_bytes, info, stream);
+}
+
+mp_status mpkrylov_bicg_td(const mp_csr *A, const double *a, const mp_csr *At, const double *at, const double *b,
+                           double *x, const mp_solve_opts *opts, const mp_plan *plan, const mp_plan *plan_t, void *ws,
+                           size_t ws_bytes, mp_solve_info *info, void *stream)
+{
+    return mpk::kmp::entry<3>("mpkrylov_bicg_td", 4, A, a, b, x, opts, plan, ws, ws_bytes, info, stream, At, at, plan_t);
+}
+
+mp_status mpkrylov_bicg_qd(const mp_csr *A, const double *a, const mp_csr *At, const double *at, const double *b,
+                           double *x, const mp_solve_opts *opts, const mp_plan *plan, const mp_plan *plan_t, void *ws,
+                           size_t ws_bytes, mp_solve_info *info, void *stream)
+{
+    return mpk::kmp::entry<4>("mpkrylov_bicg_qd", 4, A, a, b, x, opts, plan, ws, ws_bytes, info, stream, At, at, plan_t);
 }
 
 }  // extern "C"

@@ -1,5 +1,5 @@
-"""GPU parity of the TD / QD Krylov solvers (C ABI mpkrylov_{cg,bicgstab}_{td,qd}) with the
-oracle's K-component CG / BiCGSTAB: same status, iteration count and restarts, bitwise
+"""GPU parity of the TD / QD Krylov solvers (C ABI mpkrylov_{cg,bicgstab,cgs,gpbicg,bicg}_{td,qd}) with the
+oracle's K-component solvers: same status, iteration count and restarts, bitwise
 identical x and identical leading components of the true residual, with and without
 Jacobi preconditioning and with a non-canonical plan, on an SPD 3D diffusion matrix
 (also over several 4096-row chunks), the non-symmetric band, a one-eigenvalue diagonal
@@ -107,3 +107,67 @@ def test_limits_half_step_breakdown_and_errors(mp, K):
     with pytest.raises(mp.MpError) as ei:
         gfn(A, dev(a), dev(b), x, ws=torch.empty(4096, dtype=torch.uint8, device="cuda"), rtol=RTOL[K])
     assert ei.value.status == -4
+
+
+@pytest.mark.parametrize("K", [3, 4])
+def test_cgs_gpbicg_bicg_match_oracle(mp, K):
+    """TD / QD CGS, GPBiCG and BiCG (with the device transpose) equal the oracle's
+    K-component solvers bit for bit on the non-symmetric band (with and without
+    Jacobi, with a plan), over several chunks of a diffusion matrix, at iteration
+    limits, and BiCG equals CG on a symmetric matrix."""
+    import torch
+    rp, ci, a = banded_nonsymmetric(n=300, seed=6, K=K)
+    n = 300
+    A = mp.Csr.from_numpy(rp, ci)
+    ad = dev(a)
+    b = random_mp(n, K, np.random.default_rng(40 + K))
+    At, at, _ = mp.mp_csr_transpose(A, ad)
+    cases = [("cgs", mp.mpkrylov_cgs_td if K == 3 else mp.mpkrylov_cgs_qd, ref.cgs_k),
+             ("gpbicg", mp.mpkrylov_gpbicg_td if K == 3 else mp.mpkrylov_gpbicg_qd, ref.gpbicg_k)]
+    bicg = mp.mpkrylov_bicg_td if K == 3 else mp.mpkrylov_bicg_qd
+    for precond in ("none", "jacobi"):
+        for plan in (None, mp.mp_plan_create(A, K, False, 1, 6)):
+            lw = None if plan is None else plan.row_log2w()
+            for name, gfn, ofn in cases:
+                x = torch.zeros((K, n), dtype=torch.float64, device="cuda")
+                ig = gfn(A, ad, dev(b), x, plan=plan, precond=precond, rtol=RTOL[K], max_iter=20000, check_every=8)
+                xo, io = ofn(K, rp, ci, a, b, precond=precond, rtol=RTOL[K], max_iter=20000, log2w=lw)
+                assert io["status"] == 0, name
+                assert (ig["status"], ig["iters"], ig["restarts"]) == (io["status"], io["iters"], io["restarts"]), name
+                assert_same_values(host(x), xo, "%s x" % name)
+                assert_same_values(ig["rr_true"], io["rr_true"], "%s rr" % name)
+            x = torch.zeros((K, n), dtype=torch.float64, device="cuda")
+            ig = bicg(A, ad, At, at, dev(b), x, plan=plan, precond=precond, rtol=RTOL[K], max_iter=20000,
+                      check_every=8)
+            xo, io = ref.bicg_k(K, rp, ci, a, b, precond=precond, rtol=RTOL[K], max_iter=20000, log2w=lw)
+            assert io["status"] == 0
+            assert (ig["status"], ig["iters"], ig["restarts"]) == (io["status"], io["iters"], io["restarts"])
+            assert_same_values(host(x), xo, "bicg x")
+    # iteration limits inside a check chunk
+    for name, gfn, ofn in cases:
+        for lim in (1, 5):
+            x = torch.zeros((K, n), dtype=torch.float64, device="cuda")
+            ig = gfn(A, ad, dev(b), x, precond="none", rtol=RTOL[K], max_iter=lim, check_every=4)
+            xo, io = ofn(K, rp, ci, a, b, precond="none", rtol=RTOL[K], max_iter=lim)
+            assert io["status"] == -5 and (ig["status"], ig["iters"]) == (io["status"], io["iters"]), name
+            assert_same_values(host(x), xo, "%s limit x" % name)
+    # several chunks of rows
+    rpd, cid, adf = diffusion3d_7pt(m=21, sigma=1.0, seed=12, K=K)
+    nd = rpd.size - 1
+    bd = random_mp(nd, K, np.random.default_rng(50 + K))
+    Ad = mp.Csr.from_numpy(rpd, cid)
+    for name, gfn, ofn in cases:
+        x = torch.zeros((K, nd), dtype=torch.float64, device="cuda")
+        ig = gfn(Ad, dev(adf), dev(bd), x, precond="jacobi", rtol=RTOL[K], max_iter=5000)
+        xo, io = ofn(K, rpd, cid, adf, bd, precond="jacobi", rtol=RTOL[K], max_iter=5000)
+        assert io["status"] == 0 and (ig["status"], ig["iters"], ig["restarts"]) == (0, io["iters"], io["restarts"])
+        assert_same_values(host(x), xo, "%s chunks x" % name)
+    # BiCG = CG on a symmetric matrix
+    Atd, atd, _ = mp.mp_csr_transpose(Ad, dev(adf))
+    xb = torch.zeros((K, nd), dtype=torch.float64, device="cuda")
+    xc = torch.zeros((K, nd), dtype=torch.float64, device="cuda")
+    ib = bicg(Ad, dev(adf), Atd, atd, dev(bd), xb, precond="jacobi", rtol=RTOL[K], max_iter=5000)
+    cg = mp.mpkrylov_cg_td if K == 3 else mp.mpkrylov_cg_qd
+    ic = cg(Ad, dev(adf), dev(bd), xc, precond="jacobi", rtol=RTOL[K], max_iter=5000)
+    assert ib["status"] == ic["status"] == 0 and ib["iters"] == ic["iters"]
+    assert_same_values(host(xb), host(xc), "bicg = cg")
