@@ -270,7 +270,7 @@ def nonsymmetric_section(mp, torch, repeats=3):
     BiCGSTAB, GPBiCG; x0 = 0, unpreconditioned) in DD on the tub1000-shaped synthetic band
     (n = 1000, 3,996 nonzeros), b = A sqrt(2)[1..n], to the paper's criterion
     ||r|| <= 1e-13 ||b|| and to the DD-accurate 1e-28.  BiCG's A^T comes from the device
-    transpose (formed once, outside the timed solve).  BiCGSTAB also runs in TD and QD
+    transpose (formed once, outside the timed solve).  All four also run in TD and QD
     (the paper compares iteration counts across precisions)."""
     from workloads import banded_nonsymmetric, sqrt2_vector
     rp, ci, a = banded_nonsymmetric(n=1000, seed=3)
@@ -305,29 +305,36 @@ def nonsymmetric_section(mp, torch, repeats=3):
             log("tub1000-like %-9s rtol %.0e: %.5f s  %d iters  relres %.3g  fwd err %.3g" % (
                 name, rtol, info["seconds"], info["iters"], info["relres"], rec[name]["forward_err"]))
         out["rtol_%.0e" % rtol] = rec
-    # BiCGSTAB in TD and QD on the same band (K-component data, same leading parts)
-    for K, fn in ((3, mp.mpkrylov_bicgstab_td), (4, mp.mpkrylov_bicgstab_qd)):
+    # the four methods in TD and QD on the same band (K-component data, same law)
+    for K, pre in ((3, "td"), (4, "qd")):
         rpk, cik, ak = banded_nonsymmetric(n=1000, seed=3, K=K)
         Ak = mp.Csr.from_numpy(rpk, cik)
         akd = torch.from_numpy(ak).cuda()
+        Akt, akt, _ = mp.mp_csr_transpose(Ak, akd)
         vk = sqrt2_vector(n, K)
         bk = torch.empty((K, n), dtype=torch.float64, device="cuda")
         mp.SPMV[(K, False)](Ak, akd, torch.from_numpy(vk).cuda(), bk)
+        fk = {"bicg": lambda x, fn=getattr(mp, "mpkrylov_bicg_" + pre), **kw: fn(Ak, akd, Akt, akt, bk, x, **kw),
+              "cgs": lambda x, fn=getattr(mp, "mpkrylov_cgs_" + pre), **kw: fn(Ak, akd, bk, x, **kw),
+              "bicgstab": lambda x, fn=getattr(mp, "mpkrylov_bicgstab_" + pre), **kw: fn(Ak, akd, bk, x, **kw),
+              "gpbicg": lambda x, fn=getattr(mp, "mpkrylov_gpbicg_" + pre), **kw: fn(Ak, akd, bk, x, **kw)}
         for rtol in (1e-13, 1e-28):
-            best = None
-            for _ in range(repeats):
-                x = torch.zeros((K, n), dtype=torch.float64, device="cuda")
-                info = fn(Ak, akd, bk, x, precond="none", rtol=rtol, max_iter=50000, check_every=16)
-                if best is None or info["seconds"] < best[1]["seconds"]:
-                    best = (x.cpu().numpy(), info)
-            xh, info = best
-            name = "bicgstab_%s" % ("td" if K == 3 else "qd")
-            out["rtol_%.0e" % rtol][name] = {"seconds": round(info["seconds"], 6), "status": info["status"],
-                                             "iters": info["iters"], "restarts": info["restarts"],
-                                             "relres": info["relres"], "forward_err": dd_rel_diff(xh[:2], vk[:2]),
-                                             "per_step": "2 SpMV"}
-            log("tub1000-like %-12s rtol %.0e: %.5f s  %d iters  relres %.3g" % (
-                name, rtol, info["seconds"], info["iters"], info["relres"]))
+            for meth, fn in fk.items():
+                best = None
+                for _ in range(repeats):
+                    x = torch.zeros((K, n), dtype=torch.float64, device="cuda")
+                    info = fn(x, precond="none", rtol=rtol, max_iter=50000, check_every=16)
+                    if best is None or info["seconds"] < best[1]["seconds"]:
+                        best = (x.cpu().numpy(), info)
+                xh, info = best
+                name = "%s_%s" % (meth, pre)
+                out["rtol_%.0e" % rtol][name] = {"seconds": round(info["seconds"], 6), "status": info["status"],
+                                                 "iters": info["iters"], "restarts": info["restarts"],
+                                                 "relres": info["relres"],
+                                                 "forward_err": dd_rel_diff(xh[:2], vk[:2]),
+                                                 "per_step": spmvs[meth]}
+                log("tub1000-like %-12s rtol %.0e: %.5f s  %d iters  relres %.3g" % (
+                    name, rtol, info["seconds"], info["iters"], info["relres"]))
     return out
 
 
