@@ -78,3 +78,19 @@ def test_learned_entry_points_host_checks(lib):
     assert lib.mpkrylov_ir_learned(None, None, None, None, None, None, None, None, ctypes.c_size_t(0), None,
                                    None) == -1
     assert lib.mp_graph_create(None, None, None, ctypes.byref(h)) == -1
+
+
+def test_traffic_record_is_usable_by_the_bench():
+    """The committed counter record carries what bench.py matches before it reports the
+    traffic figure: the kernel-source hash, the plan and the matrix size, and a
+    positive copy-calibrated byte count per call."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "profiles",
+                        "spmv_dd_powerlaw_traffic.json")
+    with open(path) as f:
+        rec = json.load(f)
+    for key in ("source_hash", "plan", "n", "nnz", "traffic_bytes", "commands"):
+        assert key in rec, key
+    assert set(rec["plan"]) == {"shift", "max_log2w", "tile_nnz"} and rec["n"] == 1_000_000
+    assert rec["traffic_bytes"] > 0 and len(rec["source_hash"]) == 16
