@@ -450,14 +450,18 @@ __device__ __forceinline__ void short_tile(const SpmvArgs &A, const uint8_t *__r
 
 // LONG tile: one row of len > C with W <= 256 lanes (lane l on thread l).
 //
-// Register form (DD real): lane l reads its own elements l, l+W, ... straight from
-// memory (consecutive lanes read consecutive elements, so every load is coalesced),
-// kLongBatch of them issued together, and adds their products in order in registers.
-// The fold steps whose partner lies in another wavefront (off >= 64) go through LDS,
-// the rest through cross-lane shuffles.  The wider TD / QD / complex values would
-// raise the register count of the whole kernel (and cut its occupancy), so they keep
-// the staged form below.
-constexpr int kLongBatch = 4;
+// Register form (DD, real and complex): lane l reads its own elements l, l+W, ...
+// straight from memory (consecutive lanes read consecutive elements, so every load is
+// coalesced), a batch of them issued together (four, two for complex), and adds their
+// products in order in registers.  The fold steps whose partner lies in another
+// wavefront (off >= 64) go through LDS, the rest through cross-lane shuffles.  The
+// wider TD / QD values would raise the register count of the whole kernel (and cut
+// its occupancy), so they keep the staged form below.
+template <bool CPLX>
+constexpr int long_batch()
+{
+    return CPLX ? 2 : 4;
+}
 
 template <int K, bool CPLX, int J, bool DM>
 __device__ __forceinline__ void long_tile_lanes(const SpmvArgs &A, const uint8_t *__restrict__ log2w,
@@ -467,6 +471,7 @@ __device__ __forceinline__ void long_tile_lanes(const SpmvArgs &A, const uint8_t
     const int row = T.row_start;
     const int32_t b0 = A.row_ptr[row], end = A.row_ptr[row + 1];
     const int W = 1 << log2w[row];
+    constexpr int kLongBatch = long_batch<CPLX>();
     Acc<K, CPLX> acc;
     acc_zero(acc);
     if (t < W) {
@@ -570,7 +575,7 @@ __global__ __launch_bounds__(256) void spmv_stream_kernel(SpmvArgs A, const mp_s
     const mp_stream_tile T = tiles[tile];
     if (((T.info >> 4) & 15) == 0)
         short_tile<K, CPLX, J, DM>(A, log2w, T, L);
-    else if constexpr (K == 2 && !CPLX)
+    else if constexpr (K == 2)
         long_tile_lanes<K, CPLX, J, DM>(A, log2w, T, L);
     else
         long_tile_staged<K, CPLX, J, DM>(A, log2w, T, L);
