@@ -450,17 +450,16 @@ __device__ __forceinline__ void short_tile(const SpmvArgs &A, const uint8_t *__r
 
 // LONG tile: one row of len > C with W <= 256 lanes (lane l on thread l).
 //
-// Register form (DD, real and complex): lane l reads its own elements l, l+W, ...
-// straight from memory (consecutive lanes read consecutive elements, so every load is
-// coalesced), a batch of them issued together (four, two for complex), and adds their
-// products in order in registers.  The fold steps whose partner lies in another
-// wavefront (off >= 64) go through LDS, the rest through cross-lane shuffles.  The
-// wider TD / QD values would raise the register count of the whole kernel (and cut
-// its occupancy), so they keep the staged form below.
-template <bool CPLX>
+// Register form: lane l reads its own elements l, l+W, ... straight from memory
+// (consecutive lanes read consecutive elements, so every load is coalesced), a batch
+// of them issued together (DD four, DD complex and TD / QD two, QD complex one: the
+// register budget of the short tiles), and adds their products in order in
+// registers.  The fold steps whose partner lies in another wavefront (off >= 64) go
+// through LDS, the rest through cross-lane shuffles.
+template <int K, bool CPLX>
 constexpr int long_batch()
 {
-    return CPLX ? 2 : 4;
+    return K == 2 ? (CPLX ? 2 : 4) : (CPLX ? 1 : 2);
 }
 
 template <int K, bool CPLX, int J, bool DM>
@@ -471,7 +470,7 @@ __device__ __forceinline__ void long_tile_lanes(const SpmvArgs &A, const uint8_t
     const int row = T.row_start;
     const int32_t b0 = A.row_ptr[row], end = A.row_ptr[row + 1];
     const int W = 1 << log2w[row];
-    constexpr int kLongBatch = long_batch<CPLX>();
+    constexpr int kLongBatch = long_batch<K, CPLX>();
     Acc<K, CPLX> acc;
     acc_zero(acc);
     if (t < W) {
@@ -514,8 +513,9 @@ __device__ __forceinline__ void long_tile_lanes(const SpmvArgs &A, const uint8_t
     if (t == 0) acc_store(A, row, acc, true);
 }
 
-// LONG tile, staged form (TD / QD / complex): the row's elements pass through LDS in
-// chunks of C products, lane l (thread l) carrying its running sum in registers.
+// LONG tile, staged form (rows whose lanes own many elements): the row's elements pass
+// through LDS in chunks of C products, lane l (thread l) carrying its running sum in
+// registers.
 template <int K, bool CPLX, int J, bool DM>
 __device__ __forceinline__ void long_tile_staged(const SpmvArgs &A, const uint8_t *__restrict__ log2w,
                                           const mp_stream_tile &T, StreamLds<K, CPLX, 256 * J> &L)
@@ -566,6 +566,24 @@ __device__ __forceinline__ void long_tile_staged(const SpmvArgs &A, const uint8_
     if (t == 0) acc_store(A, row, L.prod[0], true);
 }
 
+// A long row runs in register lanes when each lane owns at most kLaneElems elements
+// (its chain of dependent batches stays short), else in the staged form, whose chunks
+// keep all 256 threads loading.  Both sum in the same order.  TD complex keeps the
+// staged form only (measured: its lanes form costs more in occupancy than it saves).
+constexpr int kLaneElems = 16;
+
+template <int K, bool CPLX>
+constexpr bool lanes_form()
+{
+    return !(K == 3 && CPLX);
+}
+
+__device__ __forceinline__ bool long_in_lanes(const SpmvArgs &A, const uint8_t *__restrict__ log2w, int row)
+{
+    const int64_t len = (int64_t)A.row_ptr[row + 1] - A.row_ptr[row];
+    return len <= ((int64_t)kLaneElems << log2w[row]);
+}
+
 template <int K, bool CPLX, int J, bool DM>
 __global__ __launch_bounds__(256) void spmv_stream_kernel(SpmvArgs A, const mp_stream_tile *__restrict__ tiles,
                                                           const uint8_t *__restrict__ log2w)
@@ -575,7 +593,7 @@ __global__ __launch_bounds__(256) void spmv_stream_kernel(SpmvArgs A, const mp_s
     const mp_stream_tile T = tiles[tile];
     if (((T.info >> 4) & 15) == 0)
         short_tile<K, CPLX, J, DM>(A, log2w, T, L);
-    else if constexpr (K == 2)
+    else if (lanes_form<K, CPLX>() && long_in_lanes(A, log2w, T.row_start))
         long_tile_lanes<K, CPLX, J, DM>(A, log2w, T, L);
     else
         long_tile_staged<K, CPLX, J, DM>(A, log2w, T, L);
