@@ -445,7 +445,7 @@ def main():
         return
 
     from paper_2412_17510_amd import mp
-    from paper_2412_17510_amd.profiling import source_hash
+    from paper_2412_17510_amd.profiling import find_record, source_hash
     from workloads import powerlaw_pattern, random_mp, mp_from_leads
 
     if args.workload == "batched":
@@ -536,13 +536,11 @@ def main():
     rf = dict(rf)
     rf["kernels"] = "one mpspmv_csr_dd call = x staging kernel + tile kernel (timed together)"
     rf["traffic"] = None
-    tfile = os.path.join(ROOT, "profiles", "spmv_dd_powerlaw_traffic.json")
-    if os.path.exists(tfile):
-        with open(tfile) as f:
-            tr = json.load(f)
-        if tr.get("source_hash") == source_hash() and tr.get("plan") == pol and tr.get("n") == n:
-            rf["traffic"] = round(tr["traffic_bytes"])
-            rf["traffic_note"] = "FETCH_SIZE+WRITE_SIZE of the tile kernel per launch, copy-calibrated"
+    tr = find_record(os.path.join(ROOT, "profiles", "spmv_dd_powerlaw_traffic.json"), pol, n, source_hash())
+    if tr is not None:
+        rf["traffic"] = round(tr["traffic_bytes"])
+        rf["traffic_note"] = ("FETCH_SIZE+WRITE_SIZE of the staging and tile kernels per call, copy-calibrated, "
+                              "counters taken under this plan")
     rf["algorithmic_bytes"] = algo_bytes(n, nnz, 2, False)
     rf["measured_copy_GBs"] = round(copy_gbs, 1)
     out = {

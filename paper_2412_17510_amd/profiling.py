@@ -9,6 +9,9 @@
 kernel into bytes per launch, scaled by what the same counters read for a plain copy
 of known size (bytes moved / counter reading), and records the hash of the kernel
 sources so that a benchmark can tell whether the figure still describes the code.
+With --merge the output file holds a list of such records ({"records": [...]}), one per
+launch configuration (the "plan" given in --extra): a record of the same plan is
+replaced, and records taken from other kernel sources (another hash) are dropped.
 """
 import argparse
 import csv
@@ -88,6 +91,30 @@ def traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes, ma
             "fetch_bytes": fb, "write_bytes": wb, "traffic_bytes": fb + wb, "source_hash": source_hash()}
 
 
+def merge_record(path, rec):
+    """Records of `path` (if any) with `rec` added: same-plan records replaced, records of
+    other kernel sources dropped; ordered by plan."""
+    old = []
+    if os.path.exists(path):
+        with open(path) as f:
+            old = json.load(f).get("records", [])
+    keep = [r for r in old if r.get("source_hash") == rec["source_hash"] and r.get("plan") != rec.get("plan")]
+    keep.append(rec)
+    return sorted(keep, key=lambda r: json.dumps(r.get("plan"), sort_keys=True))
+
+
+def find_record(path, plan, n, hash_):
+    """The record of `path` measured on these kernel sources, plan and matrix size, or None."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        recs = json.load(f).get("records", [])
+    for r in recs:
+        if r.get("source_hash") == hash_ and r.get("plan") == plan and r.get("n") == n:
+            return r
+    return None
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -103,6 +130,7 @@ def main(argv=None):
     tr.add_argument("--copy-match", default="copy")
     tr.add_argument("--copy-bytes", type=float, required=True)
     tr.add_argument("--extra", default="{}", help="JSON object merged into the output (workload, plan)")
+    tr.add_argument("--merge", action="store_true", help="keep one record per plan in a {records: [...]} file")
     args = ap.parse_args(argv)
     if args.cmd == "stats":
         print("%-70s %6s %12s %12s %12s %7s" % ("kernel", "calls", "avg_us", "min_us", "max_us", "pct"))
@@ -116,8 +144,11 @@ def main(argv=None):
         res = traffic(args.fetch, args.write, args.copy_fetch, args.copy_write, args.copy_bytes, args.match,
                       args.copy_match)
         res.update(json.loads(args.extra))
+        out = res
+        if args.merge:
+            out = {"records": merge_record(args.out, res)}
         with open(args.out, "w") as f:
-            json.dump(res, f, indent=1)
+            json.dump(out, f, indent=1)
         print(json.dumps(res, indent=1))
     return 0
 

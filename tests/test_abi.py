@@ -81,16 +81,51 @@ def test_learned_entry_points_host_checks(lib):
 
 
 def test_traffic_record_is_usable_by_the_bench():
-    """The committed counter record carries what bench.py matches before it reports the
+    """Each committed counter record carries what bench.py matches before it reports the
     traffic figure: the kernel-source hash, the plan and the matrix size, and a
-    positive copy-calibrated byte count per call."""
+    positive copy-calibrated byte count per call; one record per plan, all taken on the
+    same kernel sources."""
     import json
     import os
     path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "profiles",
                         "spmv_dd_powerlaw_traffic.json")
     with open(path) as f:
-        rec = json.load(f)
-    for key in ("source_hash", "plan", "n", "nnz", "traffic_bytes", "commands"):
-        assert key in rec, key
-    assert set(rec["plan"]) == {"shift", "max_log2w", "tile_nnz"} and rec["n"] == 1_000_000
-    assert rec["traffic_bytes"] > 0 and len(rec["source_hash"]) == 16
+        recs = json.load(f)["records"]
+    assert recs
+    plans = [json.dumps(r["plan"], sort_keys=True) for r in recs]
+    assert len(set(plans)) == len(plans)
+    for rec in recs:
+        for key in ("source_hash", "plan", "n", "nnz", "traffic_bytes", "commands"):
+            assert key in rec, key
+        assert set(rec["plan"]) == {"shift", "max_log2w", "tile_nnz"} and rec["n"] == 1_000_000
+        assert rec["traffic_bytes"] > 0 and len(rec["source_hash"]) == 16
+        assert rec["source_hash"] == recs[0]["source_hash"]
+
+
+def test_traffic_records_merge_and_match(tmp_path):
+    """The per-plan merge keeps one record per plan, drops records of other kernel
+    sources, and the bench's lookup matches plan, size and source hash exactly."""
+    from paper_2412_17510_amd.profiling import find_record, merge_record
+    import json
+    p = str(tmp_path / "t.json")
+    pa = {"shift": 2, "max_log2w": 6, "tile_nnz": 512}
+    pb = {"shift": 2, "max_log2w": 8, "tile_nnz": 512}
+
+    def write(recs):
+        with open(p, "w") as f:
+            json.dump({"records": recs}, f)
+
+    write(merge_record(p, {"plan": pa, "n": 10, "source_hash": "h1", "traffic_bytes": 1}))
+    write(merge_record(p, {"plan": pb, "n": 10, "source_hash": "h1", "traffic_bytes": 2}))
+    r3 = {"plan": pa, "n": 10, "source_hash": "h1", "traffic_bytes": 3}
+    recs = merge_record(p, r3)
+    assert [r["traffic_bytes"] for r in recs] == [3, 2]
+    write(recs)
+    assert find_record(p, pa, 10, "h1")["traffic_bytes"] == 3
+    assert find_record(p, pb, 10, "h1")["traffic_bytes"] == 2
+    assert find_record(p, pa, 11, "h1") is None
+    assert find_record(p, pa, 10, "h2") is None
+    assert find_record(p, {"shift": 0, "max_log2w": 6, "tile_nnz": 512}, 10, "h1") is None
+    r4 = {"plan": pb, "n": 10, "source_hash": "h2", "traffic_bytes": 4}
+    assert [r["traffic_bytes"] for r in merge_record(p, r4)] == [4]
+    assert find_record(str(tmp_path / "missing.json"), pa, 10, "h1") is None
