@@ -76,7 +76,9 @@ inline int xstage_doubles(int K, bool cplx) { return K * (cplx ? 2 : 1); }
 // LDS bytes of a SHORT/LONG tile kernel staging C elements
 inline int64_t stream_lds_bytes(int K, bool cplx, int C)
 {
-    return (int64_t)C * (8 * prod_doubles(K, cplx) + 4 + 4 + 2) + 16;
+    // products, row starts, lane offsets, lane rows, scan scratch; TD adds the fold's
+    // row list and width counters
+    return (int64_t)C * (8 * prod_doubles(K, cplx) + 4 + 4 + 2) + 16 + (K == 3 ? 2 * (int64_t)C + 128 : 4 + 128);
 }
 
 // largest tile size (power of two in 256..2048) that fits 64 KiB of LDS
