@@ -73,6 +73,27 @@ def roofline(n, nnz, K, cplx, ms, dmat=False):
             "frac": round(tops / peak, 4)}
 
 
+def measured_ceilings(mp, results):
+    """Measured arithmetic ceilings (mp_measure_rate) and, for every variant with a
+    K-component matrix, its SpMV rate as a fraction of the rate at which this device
+    runs the multiply-then-add step alone (one step per nnz, four for complex)."""
+    fma = mp.mp_measure_rate(0)
+    step = {K: mp.mp_measure_rate(K) for K in (2, 3, 4)}
+    log("measured: binary64 FMA %.1f T lane-instr/s (%.0f %% of %.1f); multiply-add steps/s: DD %.3g, TD %.3g, "
+        "QD %.3g" % (fma / 1e12, 100 * fma / FP64_INSTR_PEAK, FP64_INSTR_PEAK / 1e12, step[2], step[3], step[4]))
+    for name, r in results.items():
+        if name.endswith("_d"):
+            continue
+        K = {"dd": 2, "td": 3, "qd": 4}[name.split("_")[0]]
+        ceil = step[K] / (4 if name.endswith("complex") else 1) / 1e9
+        r["arith_ceiling_gnnz_s"] = round(ceil, 2)
+        r["frac_of_arith_ceiling"] = round(r["gnnz_s"] / ceil, 4)
+    return {"fp64_fma_lane_instr_per_s": round(fma, -9), "fp64_fma_frac_of_spec": round(fma / FP64_INSTR_PEAK, 4),
+            "muladd_steps_per_s": {"dd": round(step[2], -6), "td": round(step[3], -6), "qd": round(step[4], -6)},
+            "note": "arith_ceiling_gnnz_s in each variant = measured multiply-add steps/s per nnz (complex: 4 steps "
+                    "per nnz); frac_of_arith_ceiling = achieved / that ceiling"}
+
+
 def time_loop(fn, steps, warmup, torch):
     for _ in range(warmup):
         fn()
@@ -532,6 +553,7 @@ def main():
 
     copy_gbs = copy_bandwidth(torch)
     log("device copy bandwidth %.0f GB/s" % copy_gbs)
+    measured = measured_ceilings(mp, results)
     ms, wall, rf, pol = headline
     rf = dict(rf)
     rf["kernels"] = "one mpspmv_csr_dd call = x staging kernel + tile kernel (timed together)"
@@ -561,6 +583,7 @@ def main():
                    "plan": pol, "parallelism": "single-gpu"},
         "roofline": rf,
         "variants": results,
+        "measured_ceilings": measured,
     }
     if not args.no_solves:
         out["solves"] = solves_section(mp, torch)

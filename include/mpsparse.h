@@ -547,6 +547,24 @@ mp_status mp_mpnn_loss_grad(mp_mpnn *net, mp_graph *g, const double *r, const do
 mp_status mp_mpnn_adam_step(mp_mpnn *net, float lr, float beta1, float beta2, float eps, float grad_scale,
                             int32_t step, void *stream);
 
+/* ------------------------------------------------------------------------- */
+/* Measured ceilings                                                          */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * Throughput of the arithmetic the kernels are made of, measured on the current
+ * device, so that roofline fractions can be stated against what the device delivers
+ * as well as against its specification.  kind 0: binary64 FMA instructions per second
+ * (per lane; eight independent chains per thread, 16 workgroups of 256 threads per
+ * compute unit).  kind K = 2, 3, 4: K-component "mul then add" steps per second, the
+ * inner step of the SpMV (Sec. 2 operations: Algs 1-2 for DD, the quad-double
+ * sequences for QD, TD as QD on zero-padded values), two independent accumulators per
+ * thread; each step also carries one binary64 multiply that keeps the product in the
+ * loop.  *per_second is a host double.  Allocates and frees 8 MiB of device memory and
+ * synchronises the stream.  MP_ERR_INVALID_ARG for another kind or a NULL output.
+ */
+mp_status mp_measure_rate(int32_t kind, double *per_second, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -56,6 +56,11 @@ INNER = {"fp64": 0, "fp32": 1}
 if not os.path.exists(LIB_PATH):
     raise ImportError("libmpsparse.so is not built (expected at %s); run __graft_entry__.build()" % LIB_PATH)
 
+# torch supplies device memory and streams, and ships its own HIP runtime under the
+# soname the library links against (libamdhip64.so.7): whichever copy loads first serves
+# the process.  Import torch first so that the library and torch share torch's runtime.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 _P = ctypes.c_void_p
 _I = ctypes.c_int32
@@ -65,6 +70,7 @@ _SIGS = {
     "mp_last_error": ([], ctypes.c_char_p),
     "mp_version": ([], ctypes.c_char_p),
     "mp_csr_validate": ([_CSR, _P], ctypes.c_int),
+    "mp_measure_rate": ([_I, ctypes.POINTER(ctypes.c_double), _P], ctypes.c_int),
     "mp_plan_create": ([_CSR, _I, _I, ctypes.POINTER(mp_plan_opts), _P, ctypes.POINTER(_P)], ctypes.c_int),
     "mp_plan_create_explicit": ([_CSR, _I, _I, _P, _I, _P, ctypes.POINTER(_P)], ctypes.c_int),
     "mp_plan_autotune": ([_CSR, _I, _I, _P, _P, _P, _P, _P, _P, _I, _P, ctypes.POINTER(_P),
@@ -220,6 +226,14 @@ def _plan_handle(plan):
 
 def mp_csr_validate(A, stream=None):
     _check(_lib.mp_csr_validate(ctypes.byref(A.c), _stream_ptr(stream)), "mp_csr_validate")
+
+
+def mp_measure_rate(kind, stream=None):
+    """Measured throughput (C ABI mp_measure_rate): kind 0 = binary64 FMA lane-instructions
+    per second, kind K = 2, 3, 4 = K-component multiply-then-add steps per second."""
+    v = ctypes.c_double()
+    _check(_lib.mp_measure_rate(int(kind), ctypes.byref(v), _stream_ptr(stream)), "mp_measure_rate")
+    return v.value
 
 
 def mp_plan_create(A, ncomp, is_complex=False, shift=0, max_log2w=6, tile_nnz=0, stream=None):

@@ -78,6 +78,10 @@ def test_learned_entry_points_host_checks(lib):
     assert lib.mpkrylov_ir_learned(None, None, None, None, None, None, None, None, ctypes.c_size_t(0), None,
                                    None) == -1
     assert lib.mp_graph_create(None, None, None, ctypes.byref(h)) == -1
+    d = ctypes.c_double()
+    assert lib.mp_measure_rate(1, ctypes.byref(d), None) == -1
+    assert lib.mp_measure_rate(5, ctypes.byref(d), None) == -1
+    assert lib.mp_measure_rate(0, None, None) == -1
 
 
 def test_traffic_record_is_usable_by_the_bench():
