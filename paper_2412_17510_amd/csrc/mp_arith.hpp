@@ -151,6 +151,14 @@ __device__ __forceinline__ void three_sum2(double a, double b, double c, double 
 // the final carry is the last component.  The all-non-zero case (the usual one for
 // data with full-length mantissas) takes a straight path; any lane with a zero error
 // takes the general select-based path, which gives the same values.
+//
+// KEEP = 3 (triple-double: only three components are read) widens the straight path.
+// With t1 and the second closing error e2 non-zero, the general path closes t0 and s2
+// and its third component is s3 when the third closing error e3 is non-zero, else the
+// QuickTwoSum sum fl(s3 + t4) (e3 = 0 carries s3 on to t4).  The straight path selects
+// between the two: the same three values, without the general path, which zero-padded
+// fourth components would otherwise send many lanes down.
+template <int KEEP = 4>
 __device__ __forceinline__ qd_t renorm5(double c0, double c1, double c2, double c3, double c4)
 {
     double s, t0, t1, t2, t3, t4;
@@ -163,12 +171,22 @@ __device__ __forceinline__ qd_t renorm5(double c0, double c1, double c2, double 
     double s2, e2, s3, e3;
     quick_two_sum(t1, t2, s2, e2);
     quick_two_sum(e2, t3, s3, e3);
-    if (__builtin_expect((t1 != 0.0) & (e2 != 0.0) & (e3 != 0.0), 1)) {
-        r.c[0] = t0;
-        r.c[1] = s2;
-        r.c[2] = s3;
-        r.c[3] = e3 + t4;
-        return r;
+    if constexpr (KEEP == 3) {
+        if (__builtin_expect((t1 != 0.0) & (e2 != 0.0), 1)) {
+            r.c[0] = t0;
+            r.c[1] = s2;
+            r.c[2] = (e3 != 0.0) ? s3 : s3 + t4;
+            r.c[3] = 0.0;
+            return r;
+        }
+    } else {
+        if (__builtin_expect((t1 != 0.0) & (e2 != 0.0) & (e3 != 0.0), 1)) {
+            r.c[0] = t0;
+            r.c[1] = s2;
+            r.c[2] = s3;
+            r.c[3] = e3 + t4;
+            return r;
+        }
     }
     // general path: carry s, k components closed so far
     double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0;
@@ -205,7 +223,8 @@ __device__ __forceinline__ qd_t renorm5(double c0, double c1, double c2, double 
     return r;
 }
 
-// QD sloppy addition
+// QD sloppy addition (KEEP = 3: only the first three components are meaningful)
+template <int KEEP = 4>
 __device__ __forceinline__ qd_t qd_add(const qd_t &x, const qd_t &y)
 {
     double s0, s1, s2, s3, e0, e1, e2, e3;
@@ -218,10 +237,11 @@ __device__ __forceinline__ qd_t qd_add(const qd_t &x, const qd_t &y)
     three_sum2(s3, e0, e2, s3, e0);         // order eps^3
     double t = e0 + e1;                     // order eps^4
     t = t + e3;
-    return renorm5(s0, s1, s2, s3, t);
+    return renorm5<KEEP>(s0, s1, s2, s3, t);
 }
 
-// QD sloppy multiplication
+// QD sloppy multiplication (KEEP = 3: only the first three components are meaningful)
+template <int KEEP = 4>
 __device__ __forceinline__ qd_t qd_mul(const qd_t &x, const qd_t &y)
 {
     double p0, q0, p1, q1, p2, q2, p3, q3, p4, q4, p5, q5;
@@ -251,7 +271,7 @@ __device__ __forceinline__ qd_t qd_mul(const qd_t &x, const qd_t &y)
     t = t + q4;
     t = t + q5;
     s1 = s1 + t;
-    return renorm5(p0, h1, s0, s1, s2);
+    return renorm5<KEEP>(p0, h1, s0, s1, s2);
 }
 
 // QD times binary64 (Alg. 4; its garbled steps read after Hida, Li and Bailey's
@@ -259,6 +279,7 @@ __device__ __forceinline__ qd_t qd_mul(const qd_t &x, const qd_t &y)
 // the fourth plain; the order-eps pair merged by TwoSum, the order-eps^2 terms by
 // ThreeSum, the first order-eps^2 error with the second product error and the
 // fourth product by ThreeSum2, the last two errors by one add; renormalised.
+template <int KEEP = 4>
 __device__ __forceinline__ qd_t qd_mul_d(const qd_t &x, double y)
 {
     double p0, q0, p1, q1, p2, q2;
@@ -272,7 +293,7 @@ __device__ __forceinline__ qd_t qd_mul_d(const qd_t &x, double y)
     three_sum(s2, q1, p2, t0, t1, t2);
     double u0, u1;
     three_sum2(t1, q2, p3, u0, u1);
-    return renorm5(p0, s1, t0, u0, u1 + t2);
+    return renorm5<KEEP>(p0, s1, t0, u0, u1 + t2);
 }
 
 // ---------------------------------------------------------------------------
@@ -283,7 +304,7 @@ __device__ __forceinline__ td_t td_add(const td_t &x, const td_t &y)
 {
     const qd_t a = {{x.c[0], x.c[1], x.c[2], 0.0}};
     const qd_t b = {{y.c[0], y.c[1], y.c[2], 0.0}};
-    const qd_t r = qd_add(a, b);
+    const qd_t r = qd_add<3>(a, b);
     return td_t{{r.c[0], r.c[1], r.c[2]}};
 }
 
@@ -291,7 +312,7 @@ __device__ __forceinline__ td_t td_mul(const td_t &x, const td_t &y)
 {
     const qd_t a = {{x.c[0], x.c[1], x.c[2], 0.0}};
     const qd_t b = {{y.c[0], y.c[1], y.c[2], 0.0}};
-    const qd_t r = qd_mul(a, b);
+    const qd_t r = qd_mul<3>(a, b);
     return td_t{{r.c[0], r.c[1], r.c[2]}};
 }
 
@@ -300,7 +321,7 @@ __device__ __forceinline__ td_t td_mul(const td_t &x, const td_t &y)
 __device__ __forceinline__ td_t td_mul_d(const td_t &x, double y)
 {
     const qd_t a = {{x.c[0], x.c[1], x.c[2], 0.0}};
-    const qd_t r = qd_mul_d(a, y);
+    const qd_t r = qd_mul_d<3>(a, y);
     return td_t{{r.c[0], r.c[1], r.c[2]}};
 }
 
