@@ -637,9 +637,22 @@ __device__ __forceinline__ bool long_in_lanes(const SpmvArgs &A, const uint8_t *
     return len <= ((int64_t)kLaneElems << log2w[row]);
 }
 
+// Workgroups per CU the register allocation must leave room for, where LDS admits one
+// more than the compiler's own register count would: TD complex with one element per
+// thread 5 (100 -> 96 registers, +10-12 %), TD real with two 8 (68 -> 64, +2-5 %), QD
+// real with two 7 (76 -> 70, +3-4 %).  Elsewhere the compiler's allocation stands.
+template <int K, bool CPLX, int J>
+constexpr int stream_min_blocks()
+{
+    if (K == 3 && CPLX && J == 1) return 5;
+    if (K == 3 && !CPLX && J == 2) return 8;
+    if (K == 4 && !CPLX && J == 2) return 7;
+    return 1;
+}
+
 template <int K, bool CPLX, int J, bool DM>
-__global__ __launch_bounds__(256) void spmv_stream_kernel(SpmvArgs A, const mp_stream_tile *__restrict__ tiles,
-                                                          const uint8_t *__restrict__ log2w)
+__global__ __launch_bounds__(256, (stream_min_blocks<K, CPLX, J>())) void spmv_stream_kernel(
+    SpmvArgs A, const mp_stream_tile *__restrict__ tiles, const uint8_t *__restrict__ log2w)
 {
     __shared__ StreamLds<K, CPLX, 256 * J> L;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
