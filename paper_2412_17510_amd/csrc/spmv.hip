@@ -637,14 +637,16 @@ __device__ __forceinline__ bool long_in_lanes(const SpmvArgs &A, const uint8_t *
     return len <= ((int64_t)kLaneElems << log2w[row]);
 }
 
-// Workgroups per CU the register allocation must leave room for, where LDS admits one
-// more than the compiler's own register count would: TD complex with one element per
-// thread 5 (100 -> 96 registers, +10-12 %), TD real with two 8 (68 -> 64, +2-5 %), QD
-// real with two 7 (76 -> 70, +3-4 %).  Elsewhere the compiler's allocation stands.
+// Workgroups per CU the register allocation must leave room for, where LDS admits more
+// than the compiler's own register count would: TD complex with one element per thread
+// 5 (100 -> 96 registers, +10-12 %), DD complex with one 8 (74 -> 64, +3-5 %), TD real
+// with two 8 (68 -> 64, +2-5 %), QD real with two 7 (76 -> 70, +3-4 %).  Elsewhere the
+// compiler's allocation stands.
 template <int K, bool CPLX, int J>
 constexpr int stream_min_blocks()
 {
     if (K == 3 && CPLX && J == 1) return 5;
+    if (K == 2 && CPLX && J == 1) return 8;
     if (K == 3 && !CPLX && J == 2) return 8;
     if (K == 4 && !CPLX && J == 2) return 7;
     return 1;
