@@ -470,10 +470,11 @@ __global__ __launch_bounds__(256) void k_bexit(const dd_t *__restrict__ prr, con
 // per-chunk update kernels
 // ---------------------------------------------------------------------------
 
-// x += alpha p; r -= alpha q; z = M^-1 r; chunk sums of (r, z), (r, r) -- running pairs
+// x += alpha p; r -= alpha q; chunk sums of (r, z), (r, r) with z = M^-1 r -- running
+// pairs.  z is not stored: k_bp forms it again from r by the same operation.
 template <int R>
 __global__ __launch_bounds__(BMap<R>::THREADS) void k_bupdate(int32_t n, double *__restrict__ X,
-                                                              double *__restrict__ Rv, double *__restrict__ Z,
+                                                              double *__restrict__ Rv,
                                                               const double *__restrict__ P,
                                                               const double *__restrict__ Q,
                                                               const double *__restrict__ minv,
@@ -517,7 +518,6 @@ __global__ __launch_bounds__(BMap<R>::THREADS) void k_bupdate(int32_t n, double 
             const dd_t rk = dd_add(rk0, mp_neg(dd_mul(alpha[i], qk)));
             bst(Rv, NR, k, R, r, rk);
             const dd_t zk = minv ? dd_mul_d(rk, mi) : rk;
-            bst(Z, NR, k, R, r, zk);
             const dd_t p1 = dd_mul(rk, zk), p2 = dd_mul(rk, rk);
             arz[i] = first ? p1 : dd_add(arz[i], p1);
             arr[i] = first ? p2 : dd_add(arr[i], p2);
@@ -528,10 +528,10 @@ __global__ __launch_bounds__(BMap<R>::THREADS) void k_bupdate(int32_t n, double 
     bfold<R>(arr, ch.used, lds, prr + (int64_t)c * R);
 }
 
-// p = z + beta p -- running pairs
+// p = z + beta p with z = M^-1 r (minv NULL: z = r) -- running pairs
 template <int R>
-__global__ __launch_bounds__(BMap<R>::THREADS) void k_bp(int32_t n, const double *__restrict__ Z,
-                                                         double *__restrict__ P,
+__global__ __launch_bounds__(BMap<R>::THREADS) void k_bp(int32_t n, const double *__restrict__ Rv,
+                                                         const double *__restrict__ minv, double *__restrict__ P,
                                                          const int32_t *__restrict__ chunk_row,
                                                          const int32_t *__restrict__ chunk_sys,
                                                          const int32_t *__restrict__ sys_ptr,
@@ -549,10 +549,15 @@ __global__ __launch_bounds__(BMap<R>::THREADS) void k_bp(int32_t n, const double
         beta[i] = st[ch.sys * R + M::rhs(i)].beta;
     }
     for (int64_t k = ch.row0 + M::lane(); k < ch.end; k += kBLanes) {
+        const double mi = minv ? minv[k] : 1.0;
 #pragma unroll
         for (int i = 0; i < M::RPT; ++i) {
             const int r = M::rhs(i);
-            if (run[i]) bst(P, NR, k, R, r, dd_add(bld(Z, NR, k, R, r), dd_mul(beta[i], bld(P, NR, k, R, r))));
+            if (run[i]) {
+                const dd_t rk = bld(Rv, NR, k, R, r);
+                const dd_t zk = minv ? dd_mul_d(rk, mi) : rk;
+                bst(P, NR, k, R, r, dd_add(zk, dd_mul(beta[i], bld(P, NR, k, R, r))));
+            }
         }
     }
 }
@@ -670,12 +675,11 @@ struct BatchCG {
         if (stt != MP_OK) return stt;
         dot2(P, Q, nullptr, nullptr, part[0], nullptr);
         hipLaunchKernelGGL(k_balpha<R>, dim3(p->nsys), dim3(256), 0, s, part[0], p->d_sys_chunk, st);
-        hipLaunchKernelGGL(k_bupdate<R>, dim3(p->n_chunks), dim3(BMap<R>::THREADS), 0, s, A->n_rows, X, Rv, Z, P, Q, minv,
-                           part[1],
-                           part[2], p->d_chunk_row, p->d_chunk_sys, p->d_sys_ptr, st);
+        hipLaunchKernelGGL(k_bupdate<R>, dim3(p->n_chunks), dim3(BMap<R>::THREADS), 0, s, A->n_rows, X, Rv, P, Q, minv,
+                           part[1], part[2], p->d_chunk_row, p->d_chunk_sys, p->d_sys_ptr, st);
         hipLaunchKernelGGL(k_bbeta<R>, dim3(p->nsys), dim3(256), 0, s, part[1], part[2], p->d_sys_chunk, max_iter, st);
-        hipLaunchKernelGGL(k_bp<R>, dim3(p->n_chunks), dim3(BMap<R>::THREADS), 0, s, A->n_rows, Z, P, p->d_chunk_row,
-                           p->d_chunk_sys, p->d_sys_ptr, st);
+        hipLaunchKernelGGL(k_bp<R>, dim3(p->n_chunks), dim3(BMap<R>::THREADS), 0, s, A->n_rows, Rv, minv, P,
+                           p->d_chunk_row, p->d_chunk_sys, p->d_sys_ptr, st);
         return launched();
     }
     mp_status true_residual(const double *B, const double *X, int want)
