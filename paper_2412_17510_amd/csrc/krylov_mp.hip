@@ -26,6 +26,10 @@ namespace kmp {
 constexpr int kLanes = 256;
 constexpr int kChunk = 4096;
 constexpr int kMaxChunks = 1024;   // n <= 4,194,304 (the chunk sums of a QD dot fit 32 KiB of LDS)
+// chunk workgroups: kGroups groups of kLanes lanes, kPerThread elements of a lane each
+constexpr int kGroups = 4;
+constexpr int kPerThread = kChunk / kLanes / kGroups;
+constexpr int kChunkThreads = kLanes * kGroups;
 
 enum : int32_t { RUN = 0, RECURRENCE_MET = 1, BROKE_DOWN = 2, ITER_LIMIT = 3, CONFIRMED = 4, RESTART = 5 };
 
@@ -108,32 +112,15 @@ __device__ __forceinline__ mpn<K> k_one()
     return r;
 }
 
-// lane sums of one chunk -> fold acc[l] += acc[l+off] (off = 128..1) over the lanes
-// that hold elements; returns lds[0] to every thread
-template <int K>
-__device__ __forceinline__ mpn<K> chunk_fold(const mpn<K> &v, int used, mpn<K> *lds)
-{
-    const int t = threadIdx.x;
-    lds[t] = v;
-    __syncthreads();
-    for (int off = kLanes / 2; off >= 1; off >>= 1) {
-        if (t < off && t + off < used) lds[t] = mp_add(lds[t], lds[t + off]);
-        __syncthreads();
-    }
-    const mpn<K> r = lds[0];
-    __syncthreads();
-    return r;
-}
-
-// pairwise tree over m chunk sums (one workgroup of 256 threads)
+// pairwise tree over m chunk sums (all threads of the workgroup take part)
 template <int K>
 __device__ __forceinline__ mpn<K> pair_tree(const mpn<K> *__restrict__ part, int m, mpn<K> *P)
 {
-    const int t = threadIdx.x;
-    for (int i = t; i < m; i += kLanes) P[i] = part[i];
+    const int t = threadIdx.x, nt = blockDim.x;
+    for (int i = t; i < m; i += nt) P[i] = part[i];
     __syncthreads();
     for (int s = 1; s < m; s <<= 1) {
-        for (int i = t; (int64_t)i * 2 * s + s < m; i += kLanes) P[i * 2 * s] = mp_add(P[i * 2 * s], P[i * 2 * s + s]);
+        for (int i = t; (int64_t)i * 2 * s + s < m; i += nt) P[i * 2 * s] = mp_add(P[i * 2 * s], P[i * 2 * s + s]);
         __syncthreads();
     }
     const mpn<K> r = m > 0 ? P[0] : mp_zero<K>();
@@ -147,37 +134,107 @@ __device__ __forceinline__ int chunk_used(int64_t n, int c)
     return left < kLanes ? (int)left : kLanes;
 }
 
+// Chunk workgroups of kChunkThreads threads: thread (g, t) = (tid / 256, tid % 256)
+// holds elements j = g*kPerThread .. g*kPerThread + kPerThread - 1 of lane t (element
+// c*4096 + t + 256 j).  Their loads and products run in parallel; each lane's sum is
+// then carried from group to group through LDS, so the lane still adds its products
+// one at a time in j order, starting from its first product -- the order of a single
+// 256-lane pass over the chunk.
+
+// valid elements of this thread in chunk c (a prefix of its kPerThread elements)
+__device__ __forceinline__ int thread_valid(int64_t n, int c)
+{
+    const int g = threadIdx.x / kLanes, t = threadIdx.x % kLanes;
+    const int64_t first = (int64_t)c * kChunk + t + (int64_t)g * kPerThread * kLanes;
+    if (first >= n) return 0;
+    const int64_t left = (n - 1 - first) / kLanes + 1;
+    return left < kPerThread ? (int)left : kPerThread;
+}
+
+__device__ __forceinline__ int64_t thread_elem(int c, int jj)
+{
+    const int g = threadIdx.x / kLanes, t = threadIdx.x % kLanes;
+    return (int64_t)c * kChunk + t + (int64_t)(g * kPerThread + jj) * kLanes;
+}
+
+// prod[q][jj]: product jj of sum q of this thread (valid for jj < nvalid); leaves lane
+// t's sum q in chain[q][t] for the lanes that hold at least one element
+template <int K, int NS>
+__device__ __forceinline__ void lane_chain(const mpn<K> (&prod)[NS][kPerThread], int nvalid, mpn<K> (*chain)[kLanes])
+{
+    const int g = threadIdx.x / kLanes, t = threadIdx.x % kLanes;
+    for (int st = 0; st < kGroups; ++st) {
+        if (g == st && nvalid > 0) {
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
+                mpn<K> a = st == 0 ? prod[q][0] : mp_add(chain[q][t], prod[q][0]);
+#pragma unroll
+                for (int jj = 1; jj < kPerThread; ++jj)
+                    if (jj < nvalid) a = mp_add(a, prod[q][jj]);
+                chain[q][t] = a;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// fold of the lane sums left by lane_chain: lds[l] += lds[l + off] for off = 128..1
+// where lane l + off holds a value; returns lds[0] to every thread
+template <int K>
+__device__ __forceinline__ mpn<K> chain_fold(mpn<K> *lds, int used)
+{
+    const int t = threadIdx.x;
+    for (int off = kLanes / 2; off >= 1; off >>= 1) {
+        if (t < off && t + off < used) lds[t] = mp_add(lds[t], lds[t + off]);
+        __syncthreads();
+    }
+    const mpn<K> r = lds[0];
+    __syncthreads();
+    return r;
+}
+
 // chunk sums of (x1, y1) and optionally (x2, y2): lane l of chunk c adds the products of
 // elements c*4096 + l + 256 j in j order, starting from its first product
 template <int K>
-__global__ __launch_bounds__(256) void k_dot2(int64_t n, const double *__restrict__ x1, const double *__restrict__ y1,
-                                              const double *__restrict__ x2, const double *__restrict__ y2,
-                                              mpn<K> *__restrict__ p1, mpn<K> *__restrict__ p2,
-                                              const State<K> *__restrict__ st)
+__global__ __launch_bounds__(kChunkThreads) void k_dot2(int64_t n, const double *__restrict__ x1,
+                                                        const double *__restrict__ y1, const double *__restrict__ x2,
+                                                        const double *__restrict__ y2, mpn<K> *__restrict__ p1,
+                                                        mpn<K> *__restrict__ p2, const State<K> *__restrict__ st)
 {
-    __shared__ mpn<K> lds[kLanes];
+    __shared__ mpn<K> chain[2][kLanes];
     if (st && st->done != RUN) return;
     const int c = blockIdx.x;
-    const int t = threadIdx.x;
-    const int64_t base = (int64_t)c * kChunk;
-    const int64_t end = (n - base) < kChunk ? n : base + kChunk;
-    mpn<K> a1 = mp_zero<K>(), a2 = mp_zero<K>();
-    bool first = true;
-    for (int64_t k = base + t; k < end; k += kLanes) {
-        const mpn<K> q1 = mp_mul(ldk<K>(x1, n, k), ldk<K>(y1, n, k));
-        a1 = first ? q1 : mp_add(a1, q1);
-        if (x2) {
-            const mpn<K> q2 = mp_mul(ldk<K>(x2, n, k), ldk<K>(y2, n, k));
-            a2 = first ? q2 : mp_add(a2, q2);
-        }
-        first = false;
-    }
+    const int nv = thread_valid(n, c);
     const int used = chunk_used(n, c);
-    const mpn<K> s1 = chunk_fold(a1, used, lds);
-    if (t == 0) p1[c] = s1;
     if (x2) {
-        const mpn<K> s2 = chunk_fold(a2, used, lds);
-        if (t == 0) p2[c] = s2;
+        mpn<K> pr[2][kPerThread];
+#pragma unroll
+        for (int jj = 0; jj < kPerThread; ++jj) {
+            if (jj < nv) {
+                const int64_t k = thread_elem(c, jj);
+                pr[0][jj] = mp_mul(ldk<K>(x1, n, k), ldk<K>(y1, n, k));
+                pr[1][jj] = mp_mul(ldk<K>(x2, n, k), ldk<K>(y2, n, k));
+            }
+        }
+        lane_chain<K, 2>(pr, nv, chain);
+        const mpn<K> s1 = chain_fold(chain[0], used);
+        const mpn<K> s2 = chain_fold(chain[1], used);
+        if (threadIdx.x == 0) {
+            p1[c] = s1;
+            p2[c] = s2;
+        }
+    } else {
+        mpn<K> pr[1][kPerThread];
+#pragma unroll
+        for (int jj = 0; jj < kPerThread; ++jj) {
+            if (jj < nv) {
+                const int64_t k = thread_elem(c, jj);
+                pr[0][jj] = mp_mul(ldk<K>(x1, n, k), ldk<K>(y1, n, k));
+            }
+        }
+        lane_chain<K, 1>(pr, nv, chain);
+        const mpn<K> s1 = chain_fold(chain[0], used);
+        if (threadIdx.x == 0) p1[c] = s1;
     }
 }
 
@@ -280,78 +337,124 @@ __global__ __launch_bounds__(256) void k_cg_restart(const mpn<K> *__restrict__ p
     }
 }
 
-// alpha = rho / (p, q); breakdown unless (p, q) > 0 and finite
+// One CG step after q = A p and the chunk sums of (p, q) is two kernels:
+//   k_cg_update: alpha = rho / (p, q) (breakdown unless (p, q) > 0 and finite), then
+//                x += alpha p; r -= alpha q; z = M^-1 r; chunk sums of (r, z), (r, r)
+//                (one workgroup per chunk, lane l over the chunk's elements l + 256 j
+//                in j order, as k_dot2)
+//   k_cg_pstep:  rho_new = (r, z), rr = (r, r); one step counted; breakdown when not
+//                finite; beta = rho_new / rho; stop tests; p = z + beta p unless the
+//                step broke down
+// Every workgroup reduces the chunk sums itself (the same tree, so the same values),
+// so no scalar kernel runs between them.  The state is double-buffered across the
+// p kernel: it reads `sr` and its first workgroup writes the next state to `sw`, so
+// no workgroup reads a field that another workgroup of the same kernel writes.
 template <int K>
-__global__ __launch_bounds__(256) void k_cg_alpha(const mpn<K> *__restrict__ ppq, int m, State<K> *__restrict__ st)
+__global__ __launch_bounds__(kChunkThreads) void k_cg_update(int64_t n, double *__restrict__ x, double *__restrict__ r,
+                                                             double *__restrict__ z, const double *__restrict__ p,
+                                                             const double *__restrict__ q,
+                                                             const double *__restrict__ minv,
+                                                             const mpn<K> *__restrict__ ppq, int m,
+                                                             mpn<K> *__restrict__ prz, mpn<K> *__restrict__ prr,
+                                                             State<K> *__restrict__ st)
 {
     __shared__ mpn<K> P[kMaxChunks];
-    if (st->done != RUN) return;
-    const mpn<K> pq = pair_tree(ppq, m, P);
+    __shared__ mpn<K> chain[2][kLanes];
+    __shared__ mpn<K> s_rho;
+    __shared__ int32_t s_done;
     if (threadIdx.x == 0) {
-        st->pq = pq;
-        if (!(pq.c[0] > 0.0) || !k_finite(pq))
+        s_done = st->done;
+        s_rho = st->rho;
+    }
+    __syncthreads();
+    if (s_done != RUN) return;   // uniform in the workgroup
+    const mpn<K> pq = pair_tree(ppq, m, P);
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (!(pq.c[0] > 0.0) || !k_finite(pq)) {
+        if (lead) {
+            st->pq = pq;
             st->done = BROKE_DOWN;
-        else
-            st->alpha = k_div(st->rho, pq);
+        }
+        return;
+    }
+    const mpn<K> alpha = k_div(s_rho, pq);
+    if (lead) {
+        st->pq = pq;
+        st->alpha = alpha;
+    }
+    const int c = blockIdx.x;
+    const int nv = thread_valid(n, c);
+    mpn<K> pr[2][kPerThread];
+#pragma unroll
+    for (int jj = 0; jj < kPerThread; ++jj) {
+        if (jj < nv) {
+            const int64_t k = thread_elem(c, jj);
+            stk<K>(x, n, k, mp_add(ldk<K>(x, n, k), mp_mul(alpha, ldk<K>(p, n, k))));
+            const mpn<K> rk = k_sub(ldk<K>(r, n, k), mp_mul(alpha, ldk<K>(q, n, k)));
+            stk<K>(r, n, k, rk);
+            const mpn<K> zk = minv ? mp_mul_d(rk, minv[k]) : rk;
+            stk<K>(z, n, k, zk);
+            pr[0][jj] = mp_mul(rk, zk);
+            pr[1][jj] = mp_mul(rk, rk);
+        }
+    }
+    lane_chain<K, 2>(pr, nv, chain);
+    const int used = chunk_used(n, c);
+    const mpn<K> s1 = chain_fold(chain[0], used);
+    const mpn<K> s2 = chain_fold(chain[1], used);
+    if (threadIdx.x == 0) {
+        prz[c] = s1;
+        prr[c] = s2;
     }
 }
 
-// x += alpha p; r -= alpha q
 template <int K>
-__global__ __launch_bounds__(256) void k_cg_xr(int64_t n, double *__restrict__ x, double *__restrict__ r,
-                                               const double *__restrict__ p, const double *__restrict__ q,
-                                               const State<K> *__restrict__ st)
-{
-    if (st->done != RUN) return;
-    const mpn<K> alpha = st->alpha;
-    KMP_FOR(i, n)
-    {
-        stk<K>(x, n, i, mp_add(ldk<K>(x, n, i), mp_mul(alpha, ldk<K>(p, n, i))));
-        stk<K>(r, n, i, k_sub(ldk<K>(r, n, i), mp_mul(alpha, ldk<K>(q, n, i))));
-    }
-}
-
-// rho_new = (r, z), rr = (r, r): one step counted; breakdown when not finite;
-// beta = rho_new / rho; stop tests
-template <int K>
-__global__ __launch_bounds__(256) void k_cg_beta(const mpn<K> *__restrict__ prz, const mpn<K> *__restrict__ prr, int m,
-                                                 State<K> *__restrict__ st)
+__global__ __launch_bounds__(256) void k_cg_pstep(int64_t n, const double *__restrict__ z, double *__restrict__ p,
+                                                  const mpn<K> *__restrict__ prz, const mpn<K> *__restrict__ prr,
+                                                  int m, const State<K> *__restrict__ sr, State<K> *__restrict__ sw)
 {
     __shared__ mpn<K> P[kMaxChunks];
-    if (st->done != RUN) return;
+    __shared__ mpn<K> s_rho, s_tol2;
+    __shared__ int32_t s_done, s_iters, s_max;
+    if (threadIdx.x == 0) {
+        s_done = sr->done;
+        s_rho = sr->rho;
+        s_tol2 = sr->tol2;
+        s_iters = sr->iters;
+        s_max = sr->max_iter;
+    }
+    __syncthreads();
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (s_done != RUN) {
+        if (lead) *sw = *sr;
+        return;
+    }
     const mpn<K> rz = pair_tree(prz, m, P);
     const mpn<K> rr = pair_tree(prr, m, P);
-    if (threadIdx.x == 0) {
-        st->iters += 1;
-        st->rr = rr;
-        if (!k_finite(rr) || !k_finite(rz)) {
-            st->done = BROKE_DOWN;
-            return;
-        }
-        st->beta = k_div(rz, st->rho);
-        st->rho = rz;
-        st->half = 1;   // p is to be updated
-        if (k_le(rr, st->tol2))
-            st->done = RECURRENCE_MET;
-        else if (st->iters >= st->max_iter)
-            st->done = ITER_LIMIT;
+    const int32_t iters = s_iters + 1;
+    int32_t done = RUN;
+    mpn<K> beta = mp_zero<K>();
+    if (!k_finite(rr) || !k_finite(rz)) {
+        done = BROKE_DOWN;
+    } else {
+        beta = k_div(rz, s_rho);
+        if (k_le(rr, s_tol2))
+            done = RECURRENCE_MET;
+        else if (iters >= s_max)
+            done = ITER_LIMIT;
     }
-}
-
-// p = z + beta p (after a completed step, whatever the stop tests decided)
-template <int K>
-__global__ __launch_bounds__(256) void k_cg_p(int64_t n, const double *__restrict__ z, double *__restrict__ p,
-                                              State<K> *__restrict__ st)
-{
-    if (!st->half) return;
-    const mpn<K> beta = st->beta;
+    if (lead) {
+        *sw = *sr;
+        sw->iters = iters;
+        sw->rr = rr;
+        if (done != BROKE_DOWN) {
+            sw->beta = beta;
+            sw->rho = rz;
+        }
+        sw->done = done;
+    }
+    if (done == BROKE_DOWN) return;
     KMP_FOR(i, n) stk<K>(p, n, i, mp_add(ldk<K>(z, n, i), mp_mul(beta, ldk<K>(p, n, i))));
-}
-
-template <int K>
-__global__ __launch_bounds__(64) void k_cg_p_done(State<K> *__restrict__ st)
-{
-    if (threadIdx.x == 0) st->half = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -987,6 +1090,7 @@ struct Solver {
     int m;
     unsigned vb;
     State<K> *st;
+    State<K> *st2;   // second slot of the double-buffered CG state
     double *minv;
     double *v[kVecs];
     mpn<K> *part[kParts];
@@ -995,6 +1099,7 @@ struct Solver {
     {
         char *p = static_cast<char *>(ws);
         st = reinterpret_cast<State<K> *>(p);
+        st2 = reinterpret_cast<State<K> *>(p + al256(sizeof(State<K>)));
         p += 2 * al256(sizeof(State<K>));
         minv = reinterpret_cast<double *>(p);
         p += al256(sizeof(double) * (size_t)n);
@@ -1019,7 +1124,7 @@ struct Solver {
     mp_status dot2(const double *x1, const double *y1, const double *x2, const double *y2, mpn<K> *p1, mpn<K> *p2,
                    const State<K> *guard)
     {
-        hipLaunchKernelGGL(k_dot2<K>, dim3(m), dim3(256), 0, s, n, x1, y1, x2, y2, p1, p2, guard);
+        hipLaunchKernelGGL(k_dot2<K>, dim3(m), dim3(kChunkThreads), 0, s, n, x1, y1, x2, y2, p1, p2, guard);
         return launched();
     }
     mp_status residual(const double *b, const double *x, double *q, double *r)
@@ -1099,20 +1204,22 @@ mp_status run_cg(Solver<K> &S, const double *b, double *x, const mp_solve_opts *
     hipLaunchKernelGGL(k_cg_init<K>, dim3(1), dim3(256), 0, S.s, S.part[0], S.part[1], S.part[2], m, o->rtol * o->rtol,
                        o->max_iter, S.st);
     if ((st = S.launched()) != MP_OK) return st;
+    // the step's state alternates between the two slots; a chunk of an even number of
+    // steps ends with it in S.st, where the rest of the driver reads it
+    State<K> *sb[2] = {S.st, S.st2};
+    const int steps = (every + 1) & ~1;
     for (;;) {
         if ((st = S.read_state(&h)) != MP_OK) return st;
         if (h.done == RUN) {
-            for (int it = 0; it < every; ++it) {
+            for (int it = 0; it < steps; ++it) {
+                State<K> *sr = sb[it & 1], *sw = sb[(it + 1) & 1];
                 if ((st = S.spmv(p, q)) != MP_OK) return st;
-                if ((st = S.dot2(p, q, nullptr, nullptr, S.part[0], nullptr, S.st)) != MP_OK) return st;
-                hipLaunchKernelGGL(k_cg_alpha<K>, dim3(1), dim3(256), 0, S.s, S.part[0], m, S.st);
-                hipLaunchKernelGGL(k_cg_xr<K>, dim3(S.vb), dim3(256), 0, S.s, n, x, r, p, q, S.st);
-                hipLaunchKernelGGL(k_precond<K>, dim3(S.vb), dim3(256), 0, S.s, n, minv, r, z, S.st);
-                if ((st = S.launched()) != MP_OK) return st;
-                if ((st = S.dot2(r, z, r, r, S.part[1], S.part[2], S.st)) != MP_OK) return st;
-                hipLaunchKernelGGL(k_cg_beta<K>, dim3(1), dim3(256), 0, S.s, S.part[1], S.part[2], m, S.st);
-                hipLaunchKernelGGL(k_cg_p<K>, dim3(S.vb), dim3(256), 0, S.s, n, z, p, S.st);
-                hipLaunchKernelGGL(k_cg_p_done<K>, dim3(1), dim3(64), 0, S.s, S.st);
+                if ((st = S.dot2(p, q, nullptr, nullptr, S.part[0], nullptr, sr)) != MP_OK) return st;
+                hipLaunchKernelGGL(k_cg_update<K>, dim3(m), dim3(kChunkThreads), 0, S.s, n, x, r, z, p, q, minv,
+                                   S.part[0], m,
+                                   S.part[1], S.part[2], sr);
+                hipLaunchKernelGGL(k_cg_pstep<K>, dim3(S.vb), dim3(256), 0, S.s, n, z, p, S.part[1], S.part[2], m, sr,
+                                   sw);
                 if ((st = S.launched()) != MP_OK) return st;
             }
             continue;
