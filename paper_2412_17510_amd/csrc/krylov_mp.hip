@@ -128,6 +128,38 @@ __device__ __forceinline__ mpn<K> pair_tree(const mpn<K> *__restrict__ part, int
     return r;
 }
 
+// the pairwise trees of two sets of m chunk sums, level by level together (the same
+// additions as two pair_tree calls, with half the dependent levels); falls back to two
+// passes when both sets do not fit P
+template <int K>
+__device__ __forceinline__ void pair_tree2(const mpn<K> *__restrict__ a, const mpn<K> *__restrict__ b, int m,
+                                           mpn<K> *P, mpn<K> &ra, mpn<K> &rb)
+{
+    if (2 * m > kMaxChunks) {
+        ra = pair_tree(a, m, P);
+        rb = pair_tree(b, m, P);
+        return;
+    }
+    const int t = threadIdx.x, nt = blockDim.x;
+    for (int i = t; i < m; i += nt) {
+        P[i] = a[i];
+        P[m + i] = b[i];
+    }
+    __syncthreads();
+    for (int s = 1; s < m; s <<= 1) {
+        const int cnt = (m - s + 2 * s - 1) / (2 * s);   // pairs per set at this level
+        for (int i = t; i < 2 * cnt; i += nt) {
+            const int base = i < cnt ? 0 : m;
+            const int j = (i < cnt ? i : i - cnt) * 2 * s;
+            P[base + j] = mp_add(P[base + j], P[base + j + s]);
+        }
+        __syncthreads();
+    }
+    ra = m > 0 ? P[0] : mp_zero<K>();
+    rb = m > 0 ? P[m] : mp_zero<K>();
+    __syncthreads();
+}
+
 __device__ __forceinline__ int chunk_used(int64_t n, int c)
 {
     const int64_t left = n - (int64_t)c * kChunk;
@@ -429,8 +461,8 @@ __global__ __launch_bounds__(256) void k_cg_pstep(int64_t n, const double *__res
         if (lead) *sw = *sr;
         return;
     }
-    const mpn<K> rz = pair_tree(prz, m, P);
-    const mpn<K> rr = pair_tree(prr, m, P);
+    mpn<K> rz, rr;
+    pair_tree2(prz, prr, m, P, rz, rr);
     const int32_t iters = s_iters + 1;
     int32_t done = RUN;
     mpn<K> beta = mp_zero<K>();
