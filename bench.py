@@ -449,8 +449,8 @@ def main():
                     help="only run a plain 1 GiB device copy 5 times (counter calibration for the traffic figure)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (multi-GPU sharding is a design note, not a "
-              "measured path); run with --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only (multi-GPU sharding is a design note, not a measured path); "
+              "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
