@@ -1050,6 +1050,60 @@ int oracle_spmv_dmat(int K, int64_t n_rows, int64_t n_cols, int64_t nnz, const i
     return bad ? -1 : 0;
 }
 
+/*
+ * Complex y = A x with a binary64 complex matrix (a_re, a_im: one value per element)
+ * and a K-component complex x: Eq. 3 with four accumulator sets in the summation
+ * order of oracle_spmv, each product mul_d(x_col, a_k) (Algs 3-5); y_re = rr - ii,
+ * y_im = ri + ir at the end of the row.
+ */
+int oracle_spmv_dmat_complex(int K, int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_t *row_ptr,
+                             const int32_t *col_idx, const uint8_t *log2w, const double *a_re, const double *a_im,
+                             const double *x_re, const double *x_im, double *y_re, double *y_im, int64_t nsel,
+                             const int64_t *rows, int nthreads)
+{
+    int64_t t, count = rows ? nsel : n_rows;
+    int bad = 0;
+    if (K < 2 || K > 4) return -1;
+    (void)nnz;
+#ifdef _OPENMP
+    const int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel num_threads(nt)
+    {
+        mpv *lanes = (mpv *)malloc(sizeof(mpv) * 1024);
+#pragma omp for schedule(dynamic, 256)
+        for (t = 0; t < count; ++t) {
+            int64_t i = rows ? rows[t] : t;
+            int64_t start = row_ptr[i], len = (int64_t)row_ptr[i + 1] - row_ptr[i];
+            int lw = log2w ? log2w[i] : oracle_canonical_log2w(len);
+            int W = 1 << lw;
+            mpv zero = {{0.0, 0.0, 0.0, 0.0}};
+            if (len == 0) {
+                store_mp(K, y_re, n_rows, i, zero);
+                store_mp(K, y_im, n_rows, i, zero);
+                continue;
+            }
+            if (lw > 10 || W > len) {
+#pragma omp atomic write
+                bad = 1;
+                continue;
+            }
+            {
+                mpv rr = row_sum_d(K, start, len, W, col_idx, a_re, x_re, n_cols, lanes);
+                mpv ii = row_sum_d(K, start, len, W, col_idx, a_im, x_im, n_cols, lanes);
+                mpv ri = row_sum_d(K, start, len, W, col_idx, a_re, x_im, n_cols, lanes);
+                mpv ir = row_sum_d(K, start, len, W, col_idx, a_im, x_re, n_cols, lanes);
+                store_mp(K, y_re, n_rows, i, mp_add(K, rr, mp_neg(ii)));
+                store_mp(K, y_im, n_rows, i, mp_add(K, ri, ir));
+            }
+        }
+        free(lanes);
+    }
+    return bad ? -1 : 0;
+}
+
 /* ------------------------------------------------------------------------- */
 /* Transpose (for A^T v, Sec. 3): a stable counting sort by column, so row j   */
 /* of A^T holds column j of A in increasing row order.  a: ncomp planar value  */

@@ -26,12 +26,14 @@ def lib():
         L.oracle_renorm5.argtypes = [i64, P, P]
         L.oracle_spmv.argtypes = [ctypes.c_int, i64, i64, i64, P, P, P, P, P, P, P, P, P, i64, P, ctypes.c_int]
         L.oracle_spmv_dmat.argtypes = [ctypes.c_int, i64, i64, i64, P, P, P, P, P, P, i64, P, ctypes.c_int]
+        L.oracle_spmv_dmat_complex.argtypes = [ctypes.c_int, i64, i64, i64, P, P, P, P, P, P, P, P, P, i64, P,
+                                               ctypes.c_int]
         L.oracle_transpose.argtypes = [i64, i64, i64, ctypes.c_int, P, P, P, P, P, P]
         L.oracle_coo_to_csr.argtypes = [i64, i64, i64, P, P, ctypes.c_int, P, P, P, P]
         L.oracle_canonical_log2w.argtypes = [i64]
         L.oracle_num_threads.argtypes = []
         for name in ("oracle_eft", "oracle_elementwise", "oracle_renorm5", "oracle_spmv", "oracle_spmv_dmat",
-                     "oracle_transpose", "oracle_coo_to_csr",
+                     "oracle_spmv_dmat_complex", "oracle_transpose", "oracle_coo_to_csr",
                      "oracle_canonical_log2w", "oracle_num_threads"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -135,6 +137,32 @@ def spmv_dmat(K, row_ptr, col_idx, a, x, log2w=None, n_cols=None, rows=None, nth
     if rc != 0:
         raise ValueError("oracle_spmv_dmat: invalid argument")
     return y
+
+
+def spmv_dmat_complex(K, row_ptr, col_idx, a_re, a_im, x_re, x_im, log2w=None, n_cols=None, rows=None,
+                      nthreads=0):
+    """Complex y = A x with a binary64 complex matrix (a_re, a_im: nnz values each) and a
+    K-component complex x (Eq. 3, products by Algs 3-5, the order of spmv).  Returns
+    (y_re, y_im), each (K, n); rows: optional subset (the other rows are NaN)."""
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
+    n = row_ptr.size - 1
+    nnz = col_idx.size
+    a_re, a_im, x_re, x_im = _f64(a_re), _f64(a_im), _f64(x_re), _f64(x_im)
+    if n_cols is None:
+        n_cols = x_re.shape[1]
+    assert a_re.shape == (nnz,) and a_im.shape == (nnz,)
+    assert x_re.shape == (K, n_cols) and x_im.shape == (K, n_cols)
+    y_re = np.full((K, n), np.nan)
+    y_im = np.full((K, n), np.nan)
+    lw = None if log2w is None else np.ascontiguousarray(log2w, dtype=np.uint8)
+    sel = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    rc = lib().oracle_spmv_dmat_complex(K, n, n_cols, nnz, _p(row_ptr), _p(col_idx), _p(lw), _p(a_re), _p(a_im),
+                                        _p(x_re), _p(x_im), _p(y_re), _p(y_im), 0 if sel is None else sel.size,
+                                        _p(sel), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle_spmv_dmat_complex: invalid argument")
+    return y_re, y_im
 
 
 def transpose(row_ptr, col_idx, a, n_cols=None):

@@ -13,6 +13,11 @@ K-component vector built on them.
 * The 5x5 example of Sec. 3 times sqrt(2)[1..5] is sqrt(2)[7,-14,15,-22,40] to the
   K-component precision; integer data give exact rows; the exact-rational row bound
   max(len,1) 2^-b sum|a||x| (b = 100/150/200) holds on ragged random matrices.
+* Complex (Eq. 3 with these products): a_im = x_im = 0 gives the real product and a
+  zero imaginary part; x -> i x gives y -> i y exactly; integer data are exact; the row
+  bound holds for both parts; the 5x5 example times sqrt(2+3i)[1..5] has the modulus
+  and phase of sqrt(2+3i) m.  (Swapping the matrix parts of one cross term, or the sign
+  of the imaginary combination, fails these.)
 """
 import json
 import math
@@ -123,3 +128,107 @@ def test_dmat_integer_rows_exact_and_bound(K):
             got = exact.fixed_mp(y[:, i])
             ratio = exact.error_ratio(got, ys[i], ss[i], int(lengths[i]), ROW_BITS[K])
             assert ratio <= 1.0, (K, i, ratio)
+
+
+# ---------------------------------------------------------------------------
+# complex matrix of binary64 values times a K-component complex vector (Eq. 3 with
+# the products of Algs 3-5)
+# ---------------------------------------------------------------------------
+
+def _complex_case(K, seed, n_rows=40, n_cols=300, maxlen=120):
+    rng = np.random.default_rng(seed)
+    lengths = np.concatenate([[0, 1, 2, 3, 64, 65], rng.integers(0, maxlen, n_rows - 6)])
+    row_ptr, col_idx, _, _ = random_csr(lengths.size, n_cols, lengths, K, rng)
+    a_re = rng.uniform(-1, 1, col_idx.size)
+    a_im = rng.uniform(-1, 1, col_idx.size)
+    x_re = random_mp(n_cols, K, rng)
+    x_im = random_mp(n_cols, K, rng)
+    return lengths, row_ptr, col_idx, a_re, a_im, x_re, x_im
+
+
+@pytest.mark.parametrize("K", [2, 3, 4])
+def test_dmat_complex_reduces_to_real(K):
+    """With a_im = 0 and x_im = 0 the real part is the real binary64-matrix product and
+    the imaginary part is zero, for every summation order."""
+    lengths, row_ptr, col_idx, a_re, _, x_re, _ = _complex_case(K, 340 + K)
+    zi_a = np.zeros_like(a_re)
+    zi_x = np.zeros_like(x_re)
+    for lw in (None, np.zeros(lengths.size, dtype=np.uint8)):
+        yr, yi = ref.spmv_dmat_complex(K, row_ptr, col_idx, a_re, zi_a, x_re, zi_x, log2w=lw)
+        assert np.array_equal(yr, ref.spmv_dmat(K, row_ptr, col_idx, a_re, x_re, log2w=lw))
+        assert np.all(yi == 0)
+
+
+@pytest.mark.parametrize("K", [2, 3, 4])
+def test_dmat_complex_times_i(K):
+    """x -> i x gives y -> i y exactly (negation commutes with every rounded step); a
+    swapped matrix part or sign in the cross terms breaks it."""
+    lengths, row_ptr, col_idx, a_re, a_im, x_re, x_im = _complex_case(K, 350 + K)
+    yr, yi = ref.spmv_dmat_complex(K, row_ptr, col_idx, a_re, a_im, x_re, x_im)
+    yr2, yi2 = ref.spmv_dmat_complex(K, row_ptr, col_idx, a_re, a_im, -x_im, x_re)
+    assert np.array_equal(yr2, -yi) and np.array_equal(yi2, yr)
+
+
+@pytest.mark.parametrize("K", [2, 3, 4])
+def test_dmat_complex_integers_exact_and_bound(K):
+    rng = np.random.default_rng(360 + K)
+    lengths = rng.integers(0, 200, 40)
+    row_ptr, col_idx, _, _ = random_csr(40, 300, lengths, K, rng)
+    a_re = rng.integers(-2 ** 20, 2 ** 20, col_idx.size).astype(np.float64)
+    a_im = rng.integers(-2 ** 20, 2 ** 20, col_idx.size).astype(np.float64)
+    x_re = np.zeros((K, 300))
+    x_im = np.zeros((K, 300))
+    x_re[0] = rng.integers(-2 ** 20, 2 ** 20, 300)
+    x_im[0] = rng.integers(-2 ** 20, 2 ** 20, 300)
+    rows = np.repeat(np.arange(40), np.diff(row_ptr))
+    wr = [0] * 40
+    wi = [0] * 40
+    for k in range(col_idx.size):
+        j = col_idx[k]
+        ar, ai, xr, xi = int(a_re[k]), int(a_im[k]), int(x_re[0, j]), int(x_im[0, j])
+        wr[rows[k]] += ar * xr - ai * xi
+        wi[rows[k]] += ar * xi + ai * xr
+    yr, yi = ref.spmv_dmat_complex(K, row_ptr, col_idx, a_re, a_im, x_re, x_im)
+    assert [int(v) for v in yr[0]] == wr and [int(v) for v in yi[0]] == wi
+    assert np.all(yr[1:] == 0) and np.all(yi[1:] == 0)
+    # random values, ragged rows: |y - exact| <= max(len,1) 2^-b sum of the absolute products
+    lengths, row_ptr, col_idx, a_re, a_im, x_re, x_im = _complex_case(K, 370 + K)
+    for lw in (None, np.zeros(lengths.size, dtype=np.uint8)):
+        yr, yi = ref.spmv_dmat_complex(K, row_ptr, col_idx, a_re, a_im, x_re, x_im, log2w=lw)
+        for i in range(lengths.size):
+            er = ei = sr = si = F(0)
+            for k in range(row_ptr[i], row_ptr[i + 1]):
+                j = col_idx[k]
+                ar, ai = F(float(a_re[k])), F(float(a_im[k]))
+                xr, xi = _exact(x_re, j), _exact(x_im, j)
+                er += ar * xr - ai * xi
+                ei += ar * xi + ai * xr
+                sr += abs(ar * xr) + abs(ai * xi)
+                si += abs(ar * xi) + abs(ai * xr)
+            L = max(1, int(lengths[i]))
+            assert abs(_exact(yr, i) - er) * 2 ** ROW_BITS[K] <= L * sr, (K, i)
+            assert abs(_exact(yi, i) - ei) * 2 ** ROW_BITS[K] <= L * si, (K, i)
+
+
+@pytest.mark.parametrize("K", [2, 3, 4])
+def test_dmat_complex_5x5_times_sqrt_2p3i(golden_dir, K):
+    """The 5x5 example of Sec. 3 as a complex matrix with zero imaginary part times
+    sqrt(2+3i)[1..5] (Eq. 4): y = sqrt(2+3i) m with m = A [1..5], so |y_j|^2 = sqrt(13) m_j^2
+    and y_im / y_re = tan(atan2(3, 2) / 2) to the K-component precision."""
+    from workloads import sqrt_2p3i_vector
+    with open(os.path.join(golden_dir, "csr_5x5.json")) as f:
+        g = json.load(f)
+    row_ptr = np.array(g["csr_indptr"], dtype=np.int32)
+    col_idx = np.array(g["csr_indices"], dtype=np.int32)
+    a = np.array(g["csr_data"], dtype=np.float64)
+    m = g["Av_over_sqrt2_for_v_eq_sqrt2_times_1_to_n"]
+    vre, vim = sqrt_2p3i_vector(5, K)
+    yr, yi = ref.spmv_dmat_complex(K, row_ptr, col_idx, a, np.zeros_like(a), vre, vim)
+    for i in range(5):
+        re, im = exact.mp_value(yr[:, i]), exact.mp_value(yi[:, i])
+        # (re^2 + im^2)^2 = 13 m^4 (|sqrt(2+3i)|^4 = 13)
+        lhs = (re * re + im * im) ** 2
+        rhs = 13 * F(m[i]) ** 4
+        assert abs(lhs - rhs) <= rhs * F(64, 2 ** (53 * K - 8)), (K, i)
+        # the phase: 2 re im / (re^2 - im^2) = tan(atan2(3, 2)) = 3/2
+        assert abs(2 * re * im * 2 - 3 * (re * re - im * im)) <= abs(re * re) * F(64, 2 ** (53 * K - 8)), (K, i)
