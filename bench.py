@@ -47,15 +47,13 @@ def log(*a):
 
 
 def ops_per_nnz(K, cplx, dmat=False):
-    if dmat:
-        return OPS_MUL_D[K] + OPS_ADD[K]
-    per = OPS_MUL[K] + OPS_ADD[K]
+    per = (OPS_MUL_D[K] if dmat else OPS_MUL[K]) + OPS_ADD[K]
     return per * (4 if cplx else 1)
 
 
 def algo_bytes(n, nnz, K, cplx, dmat=False):
     c = 2 if cplx else 1
-    per_nnz = 4 + (8 if dmat else 8 * K * c)
+    per_nnz = 4 + (8 * c if dmat else 8 * K * c)
     return 4 * (n + 1) + nnz * per_nnz + 2 * 8 * K * c * n
 
 
@@ -535,19 +533,24 @@ def main():
             name, pol, ms, nnz / (ms * 1e-3) / 1e9, rf["bound"], rf["achieved"], rf["unit"], 100 * rf["frac"]))
         if name == "dd":
             headline = (ms, wall, rf, pol)
-        if not cplx:
-            # binary64 matrix (its leading components) times the same K-component x, same plan
-            a64 = ad_re[0].contiguous()
+        # binary64 matrix (its leading components) times the same K-component x, same plan
+        a64 = ad_re[0].contiguous()
+        a64i = ad_im[0].contiguous() if cplx else None
+        if cplx:
+            fdc = mp.SPMV_D_COMPLEX[K]
+            msd, _ = time_loop(lambda: fdc(A, a64, a64i, xd_re, xd_im, y_re, y_im, plan=plan), args.steps,
+                               args.warmup, torch)
+        else:
             fd = mp.SPMV_D[K]
             msd, _ = time_loop(lambda: fd(A, a64, xd_re, y_re, plan=plan), args.steps, args.warmup, torch)
-            rfd = roofline(n, nnz, K, False, msd, dmat=True)
-            results[name + "_d"] = {"gnnz_s": round(nnz / (msd * 1e-3) / 1e9, 3), "ms": round(msd, 4),
-                                    "plan": pol, "roofline": rfd,
-                                    "matrix": "binary64 (Algs 3-5 products)"}
-            log("%-10s policy=%s %.4f ms  %.2f GNNZ/s  %s %.1f %s (%.1f%%)" % (
-                name + "_d", pol, msd, nnz / (msd * 1e-3) / 1e9, rfd["bound"], rfd["achieved"], rfd["unit"],
-                100 * rfd["frac"]))
-            del a64
+        rfd = roofline(n, nnz, K, cplx, msd, dmat=True)
+        results[name + "_d"] = {"gnnz_s": round(nnz / (msd * 1e-3) / 1e9, 3), "ms": round(msd, 4),
+                                "plan": pol, "roofline": rfd,
+                                "matrix": "binary64 (Algs 3-5 products)"}
+        log("%-10s policy=%s %.4f ms  %.2f GNNZ/s  %s %.1f %s (%.1f%%)" % (
+            name + "_d", pol, msd, nnz / (msd * 1e-3) / 1e9, rfd["bound"], rfd["achieved"], rfd["unit"],
+            100 * rfd["frac"]))
+        del a64, a64i
         del ad_re, ad_im, xd_re, xd_im, y_re, y_im, plan
         torch.cuda.empty_cache()
 

@@ -188,6 +188,25 @@ mp_status mpspmv_csr_qd_d(const mp_csr *A, const double *a, const double *x, dou
                           void *stream);
 
 /*
+ * Complex y = A x with a binary64 complex matrix and a K-component complex vector
+ * (Eq. 3 with the mixed products of Algs 3-5; the paper's complex SuiteSparse matrices
+ * are binary64 too).  a_re, a_im: nnz binary64 values each (element order of A);
+ * x_re, x_im, y_re, y_im: K-component planar arrays as in mpspmv_csr_dd_complex.
+ * Four accumulator sets in the plan's order, each product the x part times the matrix
+ * part: rr = sum mul_d(x_re, a_re), ii = sum mul_d(x_im, a_im), ri = sum mul_d(x_im,
+ * a_re), ir = sum mul_d(x_re, a_im); y_re = rr + (-ii), y_im = ri + ir at the end of
+ * the row.  A plan made for (K, complex) serves both this call and
+ * mpspmv_csr_{dd,td,qd}_complex.  Errors and aliasing rules as mpspmv_csr_dd_complex
+ * (a_re, a_im are nnz doubles each).
+ */
+mp_status mpspmv_csr_dd_d_complex(const mp_csr *A, const double *a_re, const double *a_im, const double *x_re,
+                                  const double *x_im, double *y_re, double *y_im, const mp_plan *plan, void *stream);
+mp_status mpspmv_csr_td_d_complex(const mp_csr *A, const double *a_re, const double *a_im, const double *x_re,
+                                  const double *x_im, double *y_re, double *y_im, const mp_plan *plan, void *stream);
+mp_status mpspmv_csr_qd_d_complex(const mp_csr *A, const double *a_re, const double *a_im, const double *x_re,
+                                  const double *x_im, double *y_re, double *y_im, const mp_plan *plan, void *stream);
+
+/*
  * A^T in CSR, for A^T v (Sec. 3's SpTMV, which the paper computes by splitting A
  * across threads and combining the partial results in a critical section, and
  * suggests transposing first).  Row j of A^T lists column j of A in increasing row

@@ -82,7 +82,8 @@ _SIGS = {
 for _name in ("mpspmv_csr_dd", "mpspmv_csr_td", "mpspmv_csr_qd", "mpspmv_csr_dd_d", "mpspmv_csr_td_d",
               "mpspmv_csr_qd_d"):
     _SIGS[_name] = ([_CSR, _P, _P, _P, _P, _P], ctypes.c_int)
-for _name in ("mpspmv_csr_dd_complex", "mpspmv_csr_td_complex", "mpspmv_csr_qd_complex"):
+for _name in ("mpspmv_csr_dd_complex", "mpspmv_csr_td_complex", "mpspmv_csr_qd_complex", "mpspmv_csr_dd_d_complex",
+              "mpspmv_csr_td_d_complex", "mpspmv_csr_qd_d_complex"):
     _SIGS[_name] = ([_CSR, _P, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int)
 
 _SIGS["mpkrylov_workspace_bytes"] = ([_CSR, ctypes.POINTER(mp_solve_opts), ctypes.POINTER(ctypes.c_size_t)],
@@ -367,10 +368,35 @@ mpspmv_csr_dd_complex = _spmv_complex("mpspmv_csr_dd_complex", 2)
 mpspmv_csr_td_complex = _spmv_complex("mpspmv_csr_td_complex", 3)
 mpspmv_csr_qd_complex = _spmv_complex("mpspmv_csr_qd_complex", 4)
 
+def _spmv_dmat_complex(name, K):
+    fn = getattr(_lib, name)
+
+    def call(A, a_re, a_im, x_re, x_im, y_re, y_im, plan=None, stream=None):
+        import torch
+        for t, nm in ((a_re, "a_re"), (a_im, "a_im")):
+            if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != A.nnz:
+                raise ValueError("%s must be a contiguous CUDA float64 tensor of %d binary64 values" % (nm, A.nnz))
+        for t, nm, L in ((x_re, "x_re", A.n_cols), (x_im, "x_im", A.n_cols), (y_re, "y_re", A.n_rows),
+                         (y_im, "y_im", A.n_rows)):
+            _check_mp(t, K, L, nm)
+        _check(fn(ctypes.byref(A.c), _ptr(a_re), _ptr(a_im), _ptr(x_re), _ptr(x_im), _ptr(y_re), _ptr(y_im),
+                  _plan_handle(plan), _stream_ptr(stream)), name)
+        return y_re, y_im
+
+    call.__name__ = name
+    call.__doc__ = ("complex y = A x with a binary64 complex matrix and a %d-component complex vector (C ABI %s)."
+                    % (K, name))
+    return call
+
+
 mpspmv_csr_dd_d = _spmv_dmat("mpspmv_csr_dd_d", 2)
 mpspmv_csr_td_d = _spmv_dmat("mpspmv_csr_td_d", 3)
 mpspmv_csr_qd_d = _spmv_dmat("mpspmv_csr_qd_d", 4)
 SPMV_D = {2: mpspmv_csr_dd_d, 3: mpspmv_csr_td_d, 4: mpspmv_csr_qd_d}
+mpspmv_csr_dd_d_complex = _spmv_dmat_complex("mpspmv_csr_dd_d_complex", 2)
+mpspmv_csr_td_d_complex = _spmv_dmat_complex("mpspmv_csr_td_d_complex", 3)
+mpspmv_csr_qd_d_complex = _spmv_dmat_complex("mpspmv_csr_qd_d_complex", 4)
+SPMV_D_COMPLEX = {2: mpspmv_csr_dd_d_complex, 3: mpspmv_csr_td_d_complex, 4: mpspmv_csr_qd_d_complex}
 
 SPMV = {(2, False): mpspmv_csr_dd, (3, False): mpspmv_csr_td, (4, False): mpspmv_csr_qd,
         (2, True): mpspmv_csr_dd_complex, (3, True): mpspmv_csr_td_complex, (4, True): mpspmv_csr_qd_complex}

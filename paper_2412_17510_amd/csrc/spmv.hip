@@ -122,28 +122,44 @@ __device__ __forceinline__ void add_product(const SpmvArgs &A, int64_t k, Acc<K,
     acc.v = mp_add(acc.v, elem_product<K, DM>(A, k));
 }
 
+// the four products of Eq. 3 for element k; DM: binary64 matrix parts, each product
+// the K-component x part times the matrix part (Algs 3-5)
+template <int K, bool DM>
+__device__ __forceinline__ Acc<K, true> elem_products_c(const SpmvArgs &A, int64_t k)
+{
+    const int32_t j = A.col[k];
+    const mpn<K> xr = load_mp<K>(A.x_re, A.n_cols, j), xi = load_mp<K>(A.x_im, A.n_cols, j);
+    Acc<K, true> p;
+    if constexpr (DM) {
+        const double ar = A.a_re[k], ai = A.a_im[k];
+        p.rr = mp_mul_d(xr, ar);
+        p.ii = mp_mul_d(xi, ai);
+        p.ri = mp_mul_d(xi, ar);
+        p.ir = mp_mul_d(xr, ai);
+    } else {
+        const mpn<K> ar = load_mp<K>(A.a_re, A.nnz, k), ai = load_mp<K>(A.a_im, A.nnz, k);
+        p.rr = mp_mul(ar, xr);
+        p.ii = mp_mul(ai, xi);
+        p.ri = mp_mul(ar, xi);
+        p.ir = mp_mul(ai, xr);
+    }
+    return p;
+}
+
 template <int K, bool DM>
 __device__ __forceinline__ void first_product(const SpmvArgs &A, int64_t k, Acc<K, true> &acc)
 {
-    const int32_t j = A.col[k];
-    const mpn<K> ar = load_mp<K>(A.a_re, A.nnz, k), ai = load_mp<K>(A.a_im, A.nnz, k);
-    const mpn<K> xr = load_mp<K>(A.x_re, A.n_cols, j), xi = load_mp<K>(A.x_im, A.n_cols, j);
-    acc.rr = mp_mul(ar, xr);
-    acc.ii = mp_mul(ai, xi);
-    acc.ri = mp_mul(ar, xi);
-    acc.ir = mp_mul(ai, xr);
+    acc = elem_products_c<K, DM>(A, k);
 }
 
 template <int K, bool DM>
 __device__ __forceinline__ void add_product(const SpmvArgs &A, int64_t k, Acc<K, true> &acc)
 {
-    const int32_t j = A.col[k];
-    const mpn<K> ar = load_mp<K>(A.a_re, A.nnz, k), ai = load_mp<K>(A.a_im, A.nnz, k);
-    const mpn<K> xr = load_mp<K>(A.x_re, A.n_cols, j), xi = load_mp<K>(A.x_im, A.n_cols, j);
-    acc.rr = mp_add(acc.rr, mp_mul(ar, xr));
-    acc.ii = mp_add(acc.ii, mp_mul(ai, xi));
-    acc.ri = mp_add(acc.ri, mp_mul(ar, xi));
-    acc.ir = mp_add(acc.ir, mp_mul(ai, xr));
+    const Acc<K, true> p = elem_products_c<K, DM>(A, k);
+    acc.rr = mp_add(acc.rr, p.rr);
+    acc.ii = mp_add(acc.ii, p.ii);
+    acc.ri = mp_add(acc.ri, p.ri);
+    acc.ir = mp_add(acc.ir, p.ir);
 }
 
 template <int K>
@@ -271,6 +287,7 @@ __device__ __forceinline__ void load_aelem(const SpmvArgs &A, int64_t k, AElem<K
     e.col = __builtin_nontemporal_load(A.col + k);
     if constexpr (DM) {
         e.re.c[0] = __builtin_nontemporal_load(A.a_re + k);
+        if constexpr (CPLX) e.im.c[0] = __builtin_nontemporal_load(A.a_im + k);
         return;
     }
 #pragma unroll
@@ -306,7 +323,12 @@ template <int K, bool CPLX, bool DM>
 __device__ __forceinline__ Acc<K, CPLX> elem_times_x(const AElem<K, CPLX> &e, const XVal<K, CPLX> &x)
 {
     Acc<K, CPLX> p;
-    if constexpr (CPLX) {
+    if constexpr (CPLX && DM) {
+        p.rr = mp_mul_d(x.re, e.re.c[0]);
+        p.ii = mp_mul_d(x.im, e.im.c[0]);
+        p.ri = mp_mul_d(x.im, e.re.c[0]);
+        p.ir = mp_mul_d(x.re, e.im.c[0]);
+    } else if constexpr (CPLX) {
         p.rr = mp_mul(e.re, x.re);
         p.ii = mp_mul(e.im, x.im);
         p.ri = mp_mul(e.re, x.im);
@@ -949,6 +971,27 @@ mp_status mpspmv_csr_qd_d(const mp_csr *A, const double *a, const double *x, dou
                           void *stream)
 {
     return mpk::spmv_entry<4, false, true>("mpspmv_csr_qd_d", A, a, nullptr, x, nullptr, y, nullptr, plan, stream);
+}
+
+mp_status mpspmv_csr_dd_d_complex(const mp_csr *A, const double *a_re, const double *a_im, const double *x_re,
+                                  const double *x_im, double *y_re, double *y_im, const mp_plan *plan, void *stream)
+{
+    return mpk::spmv_entry<2, true, true>("mpspmv_csr_dd_d_complex", A, a_re, a_im, x_re, x_im, y_re, y_im, plan,
+                                          stream);
+}
+
+mp_status mpspmv_csr_td_d_complex(const mp_csr *A, const double *a_re, const double *a_im, const double *x_re,
+                                  const double *x_im, double *y_re, double *y_im, const mp_plan *plan, void *stream)
+{
+    return mpk::spmv_entry<3, true, true>("mpspmv_csr_td_d_complex", A, a_re, a_im, x_re, x_im, y_re, y_im, plan,
+                                          stream);
+}
+
+mp_status mpspmv_csr_qd_d_complex(const mp_csr *A, const double *a_re, const double *a_im, const double *x_re,
+                                  const double *x_im, double *y_re, double *y_im, const mp_plan *plan, void *stream)
+{
+    return mpk::spmv_entry<4, true, true>("mpspmv_csr_qd_d_complex", A, a_re, a_im, x_re, x_im, y_re, y_im, plan,
+                                          stream);
 }
 
 }  // extern "C"

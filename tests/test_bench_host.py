@@ -20,6 +20,9 @@ def test_algorithmic_bytes_and_ops():
     assert bench.ops_per_nnz(2, False) == 20
     assert bench.ops_per_nnz(4, True) == 4 * (118 + 82)
     assert bench.ops_per_nnz(3, False, dmat=True) == 66 + 82
+    # complex with a binary64 matrix: two binary64 values per element, four mixed products
+    assert bench.algo_bytes(n, nnz, 4, True, dmat=True) == 4 * (n + 1) + nnz * (4 + 16) + 2 * 64 * n
+    assert bench.ops_per_nnz(4, True, dmat=True) == 4 * (66 + 82)
 
 
 def test_roofline_picks_the_binding_resource():
