@@ -157,6 +157,81 @@ __device__ __forceinline__ V chain_fold(V *lds, int used)
     return r;
 }
 
+// Lane shuffles within a wavefront (64 lanes): the value of lane l + d (own value past
+// the end), and lane 0's value.
+__device__ __forceinline__ double shfl_down_v(double v, int d) { return __shfl_down(v, d, 64); }
+__device__ __forceinline__ float shfl_down_v(float v, int d) { return __shfl_down(v, d, 64); }
+__device__ __forceinline__ dd_t shfl_down_v(const dd_t &v, int d)
+{
+    dd_t r;
+    r.c[0] = __shfl_down(v.c[0], d, 64);
+    r.c[1] = __shfl_down(v.c[1], d, 64);
+    return r;
+}
+__device__ __forceinline__ double shfl0_v(double v) { return __shfl(v, 0, 64); }
+__device__ __forceinline__ float shfl0_v(float v) { return __shfl(v, 0, 64); }
+__device__ __forceinline__ dd_t shfl0_v(const dd_t &v)
+{
+    dd_t r;
+    r.c[0] = __shfl(v.c[0], 0, 64);
+    r.c[1] = __shfl(v.c[1], 0, 64);
+    return r;
+}
+template <typename V>
+__device__ __forceinline__ V vzero()
+{
+    return V{};
+}
+
+// chain_fold of NS sums at once with the result in thread 0 only (the same additions in
+// the same order): the two levels that cross wavefronts (off = 128, 64) through LDS, the
+// levels off = 32..1 by lane shuffles in wavefront 0, which leaves no barrier after the
+// last LDS level.
+template <typename V, int NS>
+__device__ __forceinline__ void chain_fold_lead(V (*chain)[kDotLanes], int used, V (&out)[NS])
+{
+    const int t = threadIdx.x;
+    for (int off = kDotLanes / 2; off >= 64; off >>= 1) {
+        for (int k = t; k < NS * off; k += blockDim.x) {
+            const int q = k / off, l = k % off;
+            if (l + off < used) chain[q][l] = vadd(chain[q][l], chain[q][l + off]);
+        }
+        __syncthreads();
+    }
+    if (t < 64) {
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            V v = chain[q][t];
+            for (int off = 32; off >= 1; off >>= 1) {
+                const V o = shfl_down_v(v, off);
+                if (t < off && t + off < used) v = vadd(v, o);
+            }
+            out[q] = v;
+        }
+    }
+}
+
+// pair_tree for m <= 64 without LDS or barriers: every wavefront reduces all m chunk sums
+// itself (level s: lane l, a multiple of 2s, adds lane l + s when l + s < m), starting from
+// tree_pre, this lane's chunk sum, which a caller loads ahead of its other work.
+template <typename V>
+__device__ __forceinline__ V tree_pre(const V *__restrict__ part, int m)
+{
+    const int l = threadIdx.x & 63;
+    return l < m ? part[l] : vzero<V>();
+}
+
+template <typename V>
+__device__ __forceinline__ V tree_wave(V v, int m)
+{
+    const int l = threadIdx.x & 63;
+    for (int s = 1; s < 64; s <<= 1) {
+        const V o = shfl_down_v(v, s);
+        if ((l & (2 * s - 1)) == 0 && l + s < m) v = vadd(v, o);
+    }
+    return shfl0_v(v);
+}
+
 // valid elements of this thread in chunk c (a prefix of its kPerThread elements)
 __device__ __forceinline__ int thread_valid(int64_t n, int c)
 {
@@ -199,16 +274,17 @@ __global__ __launch_bounds__(kChunkThreads) void k_dot2(int64_t n, const double 
     const int used = chunk_used(n, c);
     if (x2) {
         lane_chain<dd_t, 2>(pr, nv, chain);
-        const dd_t s1 = chain_fold(chain[0], used);
-        const dd_t s2 = chain_fold(chain[1], used);
+        dd_t s[2];
+        chain_fold_lead<dd_t, 2>(chain, used, s);
         if (threadIdx.x == 0) {
-            part1[c] = s1;
-            part2[c] = s2;
+            part1[c] = s[0];
+            part2[c] = s[1];
         }
     } else {
         lane_chain<dd_t, 1>(reinterpret_cast<const dd_t(&)[1][kPerThread]>(pr[0]), nv, chain);
-        const dd_t s1 = chain_fold(chain[0], used);
-        if (threadIdx.x == 0) part1[c] = s1;
+        dd_t s[1];
+        chain_fold_lead<dd_t, 1>(chain, used, s);
+        if (threadIdx.x == 0) part1[c] = s[0];
     }
 }
 
@@ -356,9 +432,11 @@ __global__ __launch_bounds__(kChunkThreads) void k_cg_update(int64_t n, double *
             mv[jj] = minv ? minv[k] : 0.0;
         }
     }
+    const bool small = m <= 64;
+    const dd_t pq_pre = small ? tree_pre(ppq, m) : dd_zero();
     if (threadIdx.x == 0) s_rho = st->rho;
     if (block_state(st) != RUN) return;
-    const dd_t pq = pair_tree(ppq, m, P);
+    const dd_t pq = small ? tree_wave(pq_pre, m) : pair_tree(ppq, m, P);
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     if (!(pq.c[0] > 0.0) || !dd_finite(pq)) {
         if (lead) {
@@ -388,11 +466,11 @@ __global__ __launch_bounds__(kChunkThreads) void k_cg_update(int64_t n, double *
     }
     lane_chain<dd_t, 2>(pr, nv, chain);
     const int used = chunk_used(n, c);
-    const dd_t s1 = chain_fold(chain[0], used);
-    const dd_t s2 = chain_fold(chain[1], used);
+    dd_t s[2];
+    chain_fold_lead<dd_t, 2>(chain, used, s);
     if (threadIdx.x == 0) {
-        prz[c] = s1;
-        prr[c] = s2;
+        prz[c] = s[0];
+        prr[c] = s[1];
     }
 }
 
@@ -413,6 +491,9 @@ __global__ __launch_bounds__(256) void k_cg_p(int64_t n, const double *__restric
         z0 = ldd(z, n, i0);
         p0 = ldd(p, n, i0);
     }
+    const bool small = m <= 64;
+    const dd_t rz_pre = small ? tree_pre(prz, m) : dd_zero();
+    const dd_t rr_pre = small ? tree_pre(prr, m) : dd_zero();
     if (threadIdx.x == 0) {
         s_rho = sr->rho;
         s_tol2 = sr->tol2;
@@ -423,8 +504,8 @@ __global__ __launch_bounds__(256) void k_cg_p(int64_t n, const double *__restric
         if (lead) *sw = *sr;
         return;
     }
-    const dd_t rz = pair_tree(prz, m, P);
-    const dd_t rr = pair_tree(prr, m, P);
+    const dd_t rz = small ? tree_wave(rz_pre, m) : pair_tree(prz, m, P);
+    const dd_t rr = small ? tree_wave(rr_pre, m) : pair_tree(prr, m, P);
     const int32_t iters = s_iters + 1;
     int32_t done = RUN;
     dd_t beta = dd_zero();
@@ -1315,16 +1396,17 @@ __global__ __launch_bounds__(kChunkThreads) void k_in_dot2(int64_t n, const T *_
     const int used = chunk_used(n, c);
     if (x2) {
         lane_chain<T, 2>(pr, nv, chain);
-        const T s1 = chain_fold(chain[0], used);
-        const T s2 = chain_fold(chain[1], used);
+        T s[2];
+        chain_fold_lead<T, 2>(chain, used, s);
         if (threadIdx.x == 0) {
-            part1[c] = s1;
-            part2[c] = s2;
+            part1[c] = s[0];
+            part2[c] = s[1];
         }
     } else {
         lane_chain<T, 1>(reinterpret_cast<const T(&)[1][kPerThread]>(pr[0]), nv, chain);
-        const T s1 = chain_fold(chain[0], used);
-        if (threadIdx.x == 0) part1[c] = s1;
+        T s[1];
+        chain_fold_lead<T, 1>(chain, used, s);
+        if (threadIdx.x == 0) part1[c] = s[0];
     }
 }
 
@@ -1396,15 +1478,16 @@ __device__ __forceinline__ int32_t in_block_state(const InState<T> *st)
     return s_done;
 }
 
-// alpha = rho / (p, q) (breakdown unless (p, q) > 0 and finite); false when not running
+// alpha = rho / (p, q) (breakdown unless (p, q) > 0 and finite); false when not running.
+// pre: tree_pre(ppq, m) when m <= 64.
 template <typename T>
-__device__ __forceinline__ bool in_alpha(const T *__restrict__ ppq, int m, InState<T> *__restrict__ st, T *P,
-                                         T *alpha)
+__device__ __forceinline__ bool in_alpha(const T *__restrict__ ppq, int m, T pre, InState<T> *__restrict__ st,
+                                         T *P, T *alpha)
 {
     __shared__ T s_rho;
     if (threadIdx.x == 0) s_rho = st->rho;
     if (in_block_state(st) != RUN) return false;
-    const T pq = pair_tree_t(ppq, m, P);
+    const T pq = m <= 64 ? tree_wave(pre, m) : pair_tree_t(ppq, m, P);
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     if (!(pq > T(0)) || !isfinite((double)pq)) {
         if (lead) {
@@ -1447,8 +1530,9 @@ __global__ __launch_bounds__(kChunkThreads) void k_in_update(int64_t n, T *__res
             mv[jj] = minv ? minv[k] : T(0);
         }
     }
+    const T pq_pre = m <= 64 ? tree_pre(ppq, m) : T(0);
     T alpha;
-    if (!in_alpha(ppq, m, st, P, &alpha)) return;
+    if (!in_alpha(ppq, m, pq_pre, st, P, &alpha)) return;
     T pr[2][kPerThread];
 #pragma unroll
     for (int jj = 0; jj < kPerThread; ++jj) {
@@ -1470,11 +1554,11 @@ __global__ __launch_bounds__(kChunkThreads) void k_in_update(int64_t n, T *__res
     if (!z) return;
     lane_chain<T, 2>(pr, nv, chain);
     const int used = chunk_used(n, c);
-    const T s1 = chain_fold(chain[0], used);
-    const T s2 = chain_fold(chain[1], used);
+    T s[2];
+    chain_fold_lead<T, 2>(chain, used, s);
     if (threadIdx.x == 0) {
-        prz[c] = s1;
-        prr[c] = s2;
+        prz[c] = s[0];
+        prr[c] = s[1];
     }
 }
 
@@ -1494,6 +1578,9 @@ __global__ __launch_bounds__(256) void k_in_p(int64_t n, const T *__restrict__ z
         z0 = z[i0];
         p0 = p[i0];
     }
+    const bool small = m <= 64;
+    const T rz_pre = small ? tree_pre(prz, m) : T(0);
+    const T rr_pre = small ? tree_pre(prr, m) : T(0);
     if (threadIdx.x == 0) {
         s_rho = sr->rho;
         s_tol = sr->tol;
@@ -1504,8 +1591,8 @@ __global__ __launch_bounds__(256) void k_in_p(int64_t n, const T *__restrict__ z
         if (lead) *sw = *sr;
         return;
     }
-    const T rz = pair_tree_t(prz, m, P);
-    const T rr = pair_tree_t(prr, m, P);
+    const T rz = small ? tree_wave(rz_pre, m) : pair_tree_t(prz, m, P);
+    const T rr = small ? tree_wave(rr_pre, m) : pair_tree_t(prr, m, P);
     const int32_t iters = s_iters + 1;
     int32_t done = RUN;
     T beta = T(0);
