@@ -248,6 +248,18 @@ __device__ __forceinline__ int64_t thread_elem(int c, int jj)
     return (int64_t)c * kDotChunk + t + (int64_t)(g * kPerThread + jj) * kDotLanes;
 }
 
+// Workgroup index -> logical block such that each XCD (workgroups are dealt round-robin
+// to the 8 XCDs) takes one contiguous range of blocks, as the SpMV's tiles do, so the
+// vector kernels of a step touch on each XCD about the rows its SpMV work produced.
+__device__ __forceinline__ int xcd_block(int b, int nb)
+{
+    const int xcd = b & 7;
+    const int idx = b >> 3;
+    const int per = nb >> 3;
+    const int rem = nb & 7;
+    return xcd * per + (xcd < rem ? xcd : rem) + idx;
+}
+
 // ---------------------------------------------------------------------------
 // generic kernels
 // ---------------------------------------------------------------------------
@@ -260,7 +272,7 @@ __global__ __launch_bounds__(kChunkThreads) void k_dot2(int64_t n, const double 
 {
     __shared__ dd_t chain[2][kDotLanes];
     if (st && st->done != RUN) return;
-    const int c = blockIdx.x;
+    const int c = xcd_block(blockIdx.x, gridDim.x);
     const int nv = thread_valid(n, c);
     dd_t pr[2][kPerThread];
 #pragma unroll
@@ -417,7 +429,7 @@ __global__ __launch_bounds__(kChunkThreads) void k_cg_update(int64_t n, double *
     __shared__ dd_t P[kMaxChunks];
     __shared__ dd_t s_rho;
     // the element loads do not depend on the scalars: issue them first
-    const int c = blockIdx.x;
+    const int c = xcd_block(blockIdx.x, gridDim.x);
     const int nv = thread_valid(n, c);
     dd_t xv[kPerThread], pv[kPerThread], rv[kPerThread], qv[kPerThread];
     double mv[kPerThread];
@@ -485,7 +497,7 @@ __global__ __launch_bounds__(256) void k_cg_p(int64_t n, const double *__restric
     __shared__ int32_t s_iters, s_max;
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     // this thread's first element, loaded ahead of the scalars
-    const int64_t i0 = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t i0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
     dd_t z0 = dd_zero(), p0 = dd_zero();
     if (i0 < n) {
         z0 = ldd(z, n, i0);
@@ -1382,7 +1394,7 @@ __global__ __launch_bounds__(kChunkThreads) void k_in_dot2(int64_t n, const T *_
 {
     __shared__ T chain[2][kDotLanes];
     if (st && st->done != RUN) return;
-    const int c = blockIdx.x;
+    const int c = xcd_block(blockIdx.x, gridDim.x);
     const int nv = thread_valid(n, c);
     T pr[2][kPerThread];
 #pragma unroll
@@ -1438,7 +1450,8 @@ __global__ __launch_bounds__(256) void k_in_spmv(int64_t n, const int32_t *__res
                                                  const InState<T> *__restrict__ st)
 {
     if (st && st->done != RUN) return;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    for (int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * 256) {
         const int32_t b = rp[i], e = rp[i + 1];
         T s = T(0);
         for (int32_t k0 = b; k0 < e; k0 += 8) {
@@ -1516,7 +1529,7 @@ __global__ __launch_bounds__(kChunkThreads) void k_in_update(int64_t n, T *__res
 {
     __shared__ T chain[2][kDotLanes];
     __shared__ T P[kMaxChunks];
-    const int c = blockIdx.x;
+    const int c = xcd_block(blockIdx.x, gridDim.x);
     const int nv = thread_valid(n, c);
     T dv[kPerThread], rv[kPerThread], pv[kPerThread], qv[kPerThread], mv[kPerThread];
 #pragma unroll
@@ -1572,7 +1585,7 @@ __global__ __launch_bounds__(256) void k_in_p(int64_t n, const T *__restrict__ z
     __shared__ T s_rho, s_tol;
     __shared__ int32_t s_iters, s_max;
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
-    const int64_t i0 = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t i0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
     T z0 = T(0), p0 = T(0);
     if (i0 < n) {
         z0 = z[i0];
