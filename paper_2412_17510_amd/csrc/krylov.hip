@@ -399,9 +399,10 @@ __global__ __launch_bounds__(256) void k_cg_restart(const dd_t *__restrict__ prz
 
 // One CG step after q = A p and the chunk sums of (p, q) is two kernels:
 //   k_cg_update: alpha = rho / (p, q) (breakdown unless (p, q) > 0), then
-//                x += alpha p; r -= alpha q; z = M^-1 r; chunk sums of (r, z), (r, r)
-//   k_cg_p:      rho_new = (r, z), rr = (r, r); beta = rho_new / rho; stop tests;
-//                p = z + beta p (also into the SpMV's staged copy of x)
+//                r -= alpha q; z = M^-1 r; chunk sums of (r, z), (r, r)
+//   k_cg_p:      x += alpha p (with the p it loads anyway, on the whole grid rather than
+//                the chunk workgroups); rho_new = (r, z), rr = (r, r); beta = rho_new / rho;
+//                stop tests; p = z + beta p (also into the SpMV's staged copy of x)
 // Every workgroup reduces the chunk sums itself (the same tree, so the same values),
 // which needs no separate scalar kernel.  The state is double-buffered across the two
 // kernels of a step: k_cg_p reads state `sr` and workgroup 0 writes the next state to
@@ -416,10 +417,8 @@ __device__ __forceinline__ int32_t block_state(const KState *st)
     return s_done;
 }
 
-__global__ __launch_bounds__(kChunkThreads) void k_cg_update(int64_t n, double *__restrict__ x,
-                                                             double *__restrict__ r, double *__restrict__ z,
-                                                             const double *__restrict__ p,
-                                                             const double *__restrict__ q,
+__global__ __launch_bounds__(kChunkThreads) void k_cg_update(int64_t n, double *__restrict__ r,
+                                                             double *__restrict__ z, const double *__restrict__ q,
                                                              const double *__restrict__ minv,
                                                              const dd_t *__restrict__ ppq, int m,
                                                              dd_t *__restrict__ prz, dd_t *__restrict__ prr,
@@ -431,14 +430,12 @@ __global__ __launch_bounds__(kChunkThreads) void k_cg_update(int64_t n, double *
     // the element loads do not depend on the scalars: issue them first
     const int c = xcd_block(blockIdx.x, gridDim.x);
     const int nv = thread_valid(n, c);
-    dd_t xv[kPerThread], pv[kPerThread], rv[kPerThread], qv[kPerThread];
+    dd_t rv[kPerThread], qv[kPerThread];
     double mv[kPerThread];
 #pragma unroll
     for (int jj = 0; jj < kPerThread; ++jj) {
         if (jj < nv) {
             const int64_t k = thread_elem(c, jj);
-            xv[jj] = ldd(x, n, k);
-            pv[jj] = ldd(p, n, k);
             rv[jj] = ldd(r, n, k);
             qv[jj] = ldd(q, n, k);
             mv[jj] = minv ? minv[k] : 0.0;
@@ -467,7 +464,6 @@ __global__ __launch_bounds__(kChunkThreads) void k_cg_update(int64_t n, double *
     for (int jj = 0; jj < kPerThread; ++jj) {
         if (jj < nv) {
             const int64_t k = thread_elem(c, jj);
-            sdd(x, n, k, dd_add(xv[jj], dd_mul(alpha, pv[jj])));
             const dd_t rk = dd_sub(rv[jj], dd_mul(alpha, qv[jj]));
             sdd(r, n, k, rk);
             const dd_t zk = minv ? dd_mul_d(rk, mv[jj]) : rk;
@@ -487,13 +483,13 @@ __global__ __launch_bounds__(kChunkThreads) void k_cg_update(int64_t n, double *
 }
 
 // xs: NULL, or the plan's staged copy of x (interleaved hi, lo) that the next SpMV reads
-__global__ __launch_bounds__(256) void k_cg_p(int64_t n, const double *__restrict__ z, double *__restrict__ p,
-                                              double *__restrict__ xs, const dd_t *__restrict__ prz,
-                                              const dd_t *__restrict__ prr, int m, const KState *__restrict__ sr,
-                                              KState *__restrict__ sw)
+__global__ __launch_bounds__(256) void k_cg_p(int64_t n, double *__restrict__ x, const double *__restrict__ z,
+                                              double *__restrict__ p, double *__restrict__ xs,
+                                              const dd_t *__restrict__ prz, const dd_t *__restrict__ prr, int m,
+                                              const KState *__restrict__ sr, KState *__restrict__ sw)
 {
     __shared__ dd_t P[kMaxChunks];
-    __shared__ dd_t s_rho, s_tol2;
+    __shared__ dd_t s_rho, s_tol2, s_alpha;
     __shared__ int32_t s_iters, s_max;
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     // this thread's first element, loaded ahead of the scalars
@@ -509,6 +505,7 @@ __global__ __launch_bounds__(256) void k_cg_p(int64_t n, const double *__restric
     if (threadIdx.x == 0) {
         s_rho = sr->rho;
         s_tol2 = sr->tol2;
+        s_alpha = sr->alpha;
         s_iters = sr->iters;
         s_max = sr->max_iter;
     }
@@ -516,6 +513,9 @@ __global__ __launch_bounds__(256) void k_cg_p(int64_t n, const double *__restric
         if (lead) *sw = *sr;
         return;
     }
+    // the update kernel ran to the end with this alpha: x += alpha p (old p)
+    for (int64_t i = i0; i < n; i += (int64_t)gridDim.x * 256)
+        sdd(x, n, i, dd_add(ldd(x, n, i), dd_mul(s_alpha, i == i0 ? p0 : ldd(p, n, i))));
     const dd_t rz = small ? tree_wave(rz_pre, m) : pair_tree(prz, m, P);
     const dd_t rr = small ? tree_wave(rr_pre, m) : pair_tree(prr, m, P);
     const int32_t iters = s_iters + 1;
@@ -1517,12 +1517,11 @@ __device__ __forceinline__ bool in_alpha(const T *__restrict__ ppq, int m, T pre
     return true;
 }
 
-// d += alpha p; r -= alpha q; z = M^-1 r (Jacobi or none); chunk sums of (r, z), (r, r).
-// With z == NULL only d and r are updated (the learned preconditioner applies z = M r
-// in a kernel of its own) and no sums are written.
+// r -= alpha q; z = M^-1 r (Jacobi or none); chunk sums of (r, z), (r, r) (d += alpha p
+// follows in k_in_p).  With z == NULL only r is updated (the learned preconditioner
+// applies z = M r in a kernel of its own) and no sums are written.
 template <typename T>
-__global__ __launch_bounds__(kChunkThreads) void k_in_update(int64_t n, T *__restrict__ d, T *__restrict__ r,
-                                                             T *__restrict__ z, const T *__restrict__ p,
+__global__ __launch_bounds__(kChunkThreads) void k_in_update(int64_t n, T *__restrict__ r, T *__restrict__ z,
                                                              const T *__restrict__ q, const T *__restrict__ minv,
                                                              const T *__restrict__ ppq, int m, T *__restrict__ prz,
                                                              T *__restrict__ prr, InState<T> *__restrict__ st)
@@ -1531,14 +1530,12 @@ __global__ __launch_bounds__(kChunkThreads) void k_in_update(int64_t n, T *__res
     __shared__ T P[kMaxChunks];
     const int c = xcd_block(blockIdx.x, gridDim.x);
     const int nv = thread_valid(n, c);
-    T dv[kPerThread], rv[kPerThread], pv[kPerThread], qv[kPerThread], mv[kPerThread];
+    T rv[kPerThread], qv[kPerThread], mv[kPerThread];
 #pragma unroll
     for (int jj = 0; jj < kPerThread; ++jj) {
         if (jj < nv) {
             const int64_t k = thread_elem(c, jj);
-            dv[jj] = d[k];
             rv[jj] = r[k];
-            pv[jj] = p[k];
             qv[jj] = q[k];
             mv[jj] = minv ? minv[k] : T(0);
         }
@@ -1551,9 +1548,7 @@ __global__ __launch_bounds__(kChunkThreads) void k_in_update(int64_t n, T *__res
     for (int jj = 0; jj < kPerThread; ++jj) {
         if (jj < nv) {
             const int64_t k = thread_elem(c, jj);
-            const T ap = alpha * pv[jj];
             const T aq = alpha * qv[jj];
-            d[k] = dv[jj] + ap;
             const T rk = rv[jj] - aq;
             r[k] = rk;
             if (z) {
@@ -1575,14 +1570,15 @@ __global__ __launch_bounds__(kChunkThreads) void k_in_update(int64_t n, T *__res
     }
 }
 
-// rho_new = (r, z), rr = (r, r); beta = rho_new / rho; stop tests; p = z + beta p
+// d += alpha p (old p, on the whole grid); rho_new = (r, z), rr = (r, r);
+// beta = rho_new / rho; stop tests; p = z + beta p
 template <typename T>
-__global__ __launch_bounds__(256) void k_in_p(int64_t n, const T *__restrict__ z, T *__restrict__ p,
-                                              const T *__restrict__ prz, const T *__restrict__ prr, int m,
-                                              const InState<T> *__restrict__ sr, InState<T> *__restrict__ sw)
+__global__ __launch_bounds__(256) void k_in_p(int64_t n, T *__restrict__ d, const T *__restrict__ z,
+                                              T *__restrict__ p, const T *__restrict__ prz, const T *__restrict__ prr,
+                                              int m, const InState<T> *__restrict__ sr, InState<T> *__restrict__ sw)
 {
     __shared__ T P[kMaxChunks];
-    __shared__ T s_rho, s_tol;
+    __shared__ T s_rho, s_tol, s_alpha;
     __shared__ int32_t s_iters, s_max;
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     const int64_t i0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
@@ -1597,12 +1593,18 @@ __global__ __launch_bounds__(256) void k_in_p(int64_t n, const T *__restrict__ z
     if (threadIdx.x == 0) {
         s_rho = sr->rho;
         s_tol = sr->tol;
+        s_alpha = sr->alpha;
         s_iters = sr->iters;
         s_max = sr->max_iter;
     }
     if (in_block_state(sr) != RUN) {
         if (lead) *sw = *sr;
         return;
+    }
+    // the update kernel ran to the end with this alpha
+    for (int64_t i = i0; i < n; i += (int64_t)gridDim.x * 256) {
+        const T ap = s_alpha * (i == i0 ? p0 : p[i]);
+        d[i] = d[i] + ap;
     }
     const T rz = small ? tree_wave(rz_pre, m) : pair_tree_t(prz, m, P);
     const T rr = small ? tree_wave(rr_pre, m) : pair_tree_t(prr, m, P);
@@ -1942,10 +1944,10 @@ mp_status run_cg(Solver &S, const double *b, double *x, const mp_solve_opts *o, 
                 KState *sr = sb[it & 1], *sw = sb[(it + 1) & 1];
                 if ((st = spmv_dd_prestaged(S.A, S.a, p, q, S.plan, S.s)) != MP_OK) return st;
                 if ((st = S.dot2(p, q, nullptr, nullptr, S.w.part[0], nullptr, sr)) != MP_OK) return st;
-                hipLaunchKernelGGL(k_cg_update, dim3(m), dim3(kChunkThreads), 0, S.s, n, x, r, z, p, q, minv, S.w.part[0], m,
+                hipLaunchKernelGGL(k_cg_update, dim3(m), dim3(kChunkThreads), 0, S.s, n, r, z, q, minv, S.w.part[0], m,
                                    S.w.part[1], S.w.part[2], sr);
-                hipLaunchKernelGGL(k_cg_p, dim3(S.vblocks), dim3(256), 0, S.s, n, z, p, xs, S.w.part[1], S.w.part[2],
-                                   m, sr, sw);
+                hipLaunchKernelGGL(k_cg_p, dim3(S.vblocks), dim3(256), 0, S.s, n, x, z, p, xs, S.w.part[1],
+                                   S.w.part[2], m, sr, sw);
                 if ((st = S.launched()) != MP_OK) return st;
             }
             continue;
@@ -2312,16 +2314,16 @@ mp_status inner_solve(Solver &S, const double *r_dd, int e, const T *a_in, const
             hipLaunchKernelGGL(k_in_dot2<T>, dim3(m), dim3(kChunkThreads), 0, S.s, n, p, q, nullptr, nullptr, part0, nullptr,
                                sr);
             if (mv) {
-                hipLaunchKernelGGL(k_in_update<T>, dim3(m), dim3(kChunkThreads), 0, S.s, n, d, r, nullptr, p, q, nullptr, part0,
+                hipLaunchKernelGGL(k_in_update<T>, dim3(m), dim3(kChunkThreads), 0, S.s, n, r, nullptr, q, nullptr, part0,
                                    m, nullptr, nullptr, sr);
                 hipLaunchKernelGGL(k_in_mspmv<T>, dim3(S.vblocks), dim3(256), 0, S.s, n, S.A->row_ptr, S.A->col_idx,
                                    mv, r, z, nullptr, sr);
                 hipLaunchKernelGGL(k_in_dot2<T>, dim3(m), dim3(kChunkThreads), 0, S.s, n, r, z, r, r, part1, part2, sr);
             } else {
-                hipLaunchKernelGGL(k_in_update<T>, dim3(m), dim3(kChunkThreads), 0, S.s, n, d, r, z, p, q, minv, part0, m,
+                hipLaunchKernelGGL(k_in_update<T>, dim3(m), dim3(kChunkThreads), 0, S.s, n, r, z, q, minv, part0, m,
                                    part1, part2, sr);
             }
-            hipLaunchKernelGGL(k_in_p<T>, dim3(S.vblocks), dim3(256), 0, S.s, n, z, p, part1, part2, m, sr, sw);
+            hipLaunchKernelGGL(k_in_p<T>, dim3(S.vblocks), dim3(256), 0, S.s, n, d, z, p, part1, part2, m, sr, sw);
             if ((st = S.launched()) != MP_OK) return st;
         }
     }
