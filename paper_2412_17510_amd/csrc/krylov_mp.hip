@@ -371,10 +371,12 @@ __global__ __launch_bounds__(256) void k_cg_restart(const mpn<K> *__restrict__ p
 
 // One CG step after q = A p and the chunk sums of (p, q) is two kernels:
 //   k_cg_update: alpha = rho / (p, q) (breakdown unless (p, q) > 0 and finite), then
-//                x += alpha p; r -= alpha q; z = M^-1 r; chunk sums of (r, z), (r, r)
+//                r -= alpha q; z = M^-1 r; chunk sums of (r, z), (r, r)
 //                (one workgroup per chunk, lane l over the chunk's elements l + 256 j
 //                in j order, as k_dot2)
-//   k_cg_pstep:  rho_new = (r, z), rr = (r, r); one step counted; breakdown when not
+//   k_cg_pstep:  x += alpha p when the update kernel ran to the end (on the whole grid
+//                rather than the chunk workgroups); rho_new = (r, z), rr = (r, r); one
+//                step counted; breakdown when not
 //                finite; beta = rho_new / rho; stop tests; p = z + beta p unless the
 //                step broke down
 // Every workgroup reduces the chunk sums itself (the same tree, so the same values),
@@ -382,9 +384,8 @@ __global__ __launch_bounds__(256) void k_cg_restart(const mpn<K> *__restrict__ p
 // p kernel: it reads `sr` and its first workgroup writes the next state to `sw`, so
 // no workgroup reads a field that another workgroup of the same kernel writes.
 template <int K>
-__global__ __launch_bounds__(kChunkThreads) void k_cg_update(int64_t n, double *__restrict__ x, double *__restrict__ r,
-                                                             double *__restrict__ z, const double *__restrict__ p,
-                                                             const double *__restrict__ q,
+__global__ __launch_bounds__(kChunkThreads) void k_cg_update(int64_t n, double *__restrict__ r,
+                                                             double *__restrict__ z, const double *__restrict__ q,
                                                              const double *__restrict__ minv,
                                                              const mpn<K> *__restrict__ ppq, int m,
                                                              mpn<K> *__restrict__ prz, mpn<K> *__restrict__ prr,
@@ -421,7 +422,6 @@ __global__ __launch_bounds__(kChunkThreads) void k_cg_update(int64_t n, double *
     for (int jj = 0; jj < kPerThread; ++jj) {
         if (jj < nv) {
             const int64_t k = thread_elem(c, jj);
-            stk<K>(x, n, k, mp_add(ldk<K>(x, n, k), mp_mul(alpha, ldk<K>(p, n, k))));
             const mpn<K> rk = k_sub(ldk<K>(r, n, k), mp_mul(alpha, ldk<K>(q, n, k)));
             stk<K>(r, n, k, rk);
             const mpn<K> zk = minv ? mp_mul_d(rk, minv[k]) : rk;
@@ -441,17 +441,19 @@ __global__ __launch_bounds__(kChunkThreads) void k_cg_update(int64_t n, double *
 }
 
 template <int K>
-__global__ __launch_bounds__(256) void k_cg_pstep(int64_t n, const double *__restrict__ z, double *__restrict__ p,
-                                                  const mpn<K> *__restrict__ prz, const mpn<K> *__restrict__ prr,
-                                                  int m, const State<K> *__restrict__ sr, State<K> *__restrict__ sw)
+__global__ __launch_bounds__(256) void k_cg_pstep(int64_t n, double *__restrict__ x, const double *__restrict__ z,
+                                                  double *__restrict__ p, const mpn<K> *__restrict__ prz,
+                                                  const mpn<K> *__restrict__ prr, int m,
+                                                  const State<K> *__restrict__ sr, State<K> *__restrict__ sw)
 {
     __shared__ mpn<K> P[kMaxChunks];
-    __shared__ mpn<K> s_rho, s_tol2;
+    __shared__ mpn<K> s_rho, s_tol2, s_alpha;
     __shared__ int32_t s_done, s_iters, s_max;
     if (threadIdx.x == 0) {
         s_done = sr->done;
         s_rho = sr->rho;
         s_tol2 = sr->tol2;
+        s_alpha = sr->alpha;
         s_iters = sr->iters;
         s_max = sr->max_iter;
     }
@@ -461,6 +463,8 @@ __global__ __launch_bounds__(256) void k_cg_pstep(int64_t n, const double *__res
         if (lead) *sw = *sr;
         return;
     }
+    // the update kernel ran to the end with this alpha: x += alpha p (old p)
+    KMP_FOR(i, n) stk<K>(x, n, i, mp_add(ldk<K>(x, n, i), mp_mul(s_alpha, ldk<K>(p, n, i))));
     mpn<K> rz, rr;
     pair_tree2(prz, prr, m, P, rz, rr);
     const int32_t iters = s_iters + 1;
@@ -1247,11 +1251,10 @@ mp_status run_cg(Solver<K> &S, const double *b, double *x, const mp_solve_opts *
                 State<K> *sr = sb[it & 1], *sw = sb[(it + 1) & 1];
                 if ((st = S.spmv(p, q)) != MP_OK) return st;
                 if ((st = S.dot2(p, q, nullptr, nullptr, S.part[0], nullptr, sr)) != MP_OK) return st;
-                hipLaunchKernelGGL(k_cg_update<K>, dim3(m), dim3(kChunkThreads), 0, S.s, n, x, r, z, p, q, minv,
-                                   S.part[0], m,
-                                   S.part[1], S.part[2], sr);
-                hipLaunchKernelGGL(k_cg_pstep<K>, dim3(S.vb), dim3(256), 0, S.s, n, z, p, S.part[1], S.part[2], m, sr,
-                                   sw);
+                hipLaunchKernelGGL(k_cg_update<K>, dim3(m), dim3(kChunkThreads), 0, S.s, n, r, z, q, minv, S.part[0],
+                                   m, S.part[1], S.part[2], sr);
+                hipLaunchKernelGGL(k_cg_pstep<K>, dim3(S.vb), dim3(256), 0, S.s, n, x, z, p, S.part[1], S.part[2], m,
+                                   sr, sw);
                 if ((st = S.launched()) != MP_OK) return st;
             }
             continue;
