@@ -1518,8 +1518,7 @@ __device__ __forceinline__ bool in_alpha(const T *__restrict__ ppq, int m, T pre
 }
 
 // r -= alpha q; z = M^-1 r (Jacobi or none); chunk sums of (r, z), (r, r) (d += alpha p
-// follows in k_in_p).  With z == NULL only r is updated (the learned preconditioner
-// applies z = M r in a kernel of its own) and no sums are written.
+// follows in k_in_p).
 template <typename T>
 __global__ __launch_bounds__(kChunkThreads) void k_in_update(int64_t n, T *__restrict__ r, T *__restrict__ z,
                                                              const T *__restrict__ q, const T *__restrict__ minv,
@@ -1551,15 +1550,12 @@ __global__ __launch_bounds__(kChunkThreads) void k_in_update(int64_t n, T *__res
             const T aq = alpha * qv[jj];
             const T rk = rv[jj] - aq;
             r[k] = rk;
-            if (z) {
-                const T zk = minv ? rk * mv[jj] : rk;
-                z[k] = zk;
-                pr[0][jj] = rk * zk;
-                pr[1][jj] = rk * rk;
-            }
+            const T zk = minv ? rk * mv[jj] : rk;
+            z[k] = zk;
+            pr[0][jj] = rk * zk;
+            pr[1][jj] = rk * rk;
         }
     }
-    if (!z) return;
     lane_chain<T, 2>(pr, nv, chain);
     const int used = chunk_used(n, c);
     T s[2];
@@ -1635,6 +1631,57 @@ __global__ __launch_bounds__(256) void k_in_p(int64_t n, T *__restrict__ d, cons
     for (int64_t i = i0; i < n; i += (int64_t)gridDim.x * 256) {
         const T bp = beta * (i == i0 ? p0 : p[i]);
         p[i] = (i == i0 ? z0 : z[i]) + bp;
+    }
+}
+
+// An inner step with the learned preconditioner, after q = A p and the chunk sums of
+// (p, q): alpha = rho / (p, q) in every workgroup, then for each row i
+//   r_next[i] = r[i] - alpha q[i],   z[i] = sum_k M[i,k] (r[c_k] - alpha q[c_k]),
+// the neighbours' new residual recomputed from the old r and q with the same two
+// roundings, so z = M r_next without a grid-wide wait for r_next.  r and r_next are
+// two buffers that alternate from step to step.
+template <typename T>
+__global__ __launch_bounds__(256) void k_in_mupdate(int64_t n, const int32_t *__restrict__ rp,
+                                                    const int32_t *__restrict__ ci, const T *__restrict__ mv,
+                                                    const T *__restrict__ r, const T *__restrict__ q,
+                                                    T *__restrict__ r_next, T *__restrict__ z,
+                                                    const T *__restrict__ ppq, int m, InState<T> *__restrict__ st)
+{
+    __shared__ T P[kMaxChunks];
+    const T pq_pre = m <= 64 ? tree_pre(ppq, m) : T(0);
+    T alpha;
+    if (!in_alpha(ppq, m, pq_pre, st, P, &alpha)) return;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const int32_t b = rp[i], e = rp[i + 1];
+        const T aqi = alpha * q[i];
+        r_next[i] = r[i] - aqi;
+        T s = T(0);
+        for (int32_t k0 = b; k0 < e; k0 += 8) {
+            T av[8], rv[8], qv[8];
+            int32_t cv[8];
+            // branch-free loads and gathers (a slot past the row's end re-reads its first
+            // element), so every gather of the group is in flight at once
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int32_t k = k0 + j < e ? k0 + j : b;
+                av[j] = mv[k];
+                cv[j] = ci[k];
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                rv[j] = r[cv[j]];
+                qv[j] = q[cv[j]];
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (k0 + j < e) {
+                    const T aq = alpha * qv[j];
+                    const T rn = rv[j] - aq;
+                    const T prod = av[j] * rn;
+                    s = (k0 + j == b) ? prod : s + prod;
+                }
+        }
+        z[i] = s;
     }
 }
 
@@ -2314,11 +2361,12 @@ mp_status inner_solve(Solver &S, const double *r_dd, int e, const T *a_in, const
             hipLaunchKernelGGL(k_in_dot2<T>, dim3(m), dim3(kChunkThreads), 0, S.s, n, p, q, nullptr, nullptr, part0, nullptr,
                                sr);
             if (mv) {
-                hipLaunchKernelGGL(k_in_update<T>, dim3(m), dim3(kChunkThreads), 0, S.s, n, r, nullptr, q, nullptr, part0,
-                                   m, nullptr, nullptr, sr);
-                hipLaunchKernelGGL(k_in_mspmv<T>, dim3(S.vblocks), dim3(256), 0, S.s, n, S.A->row_ptr, S.A->col_idx,
-                                   mv, r, z, nullptr, sr);
-                hipLaunchKernelGGL(k_in_dot2<T>, dim3(m), dim3(kChunkThreads), 0, S.s, n, r, z, r, r, part1, part2, sr);
+                // the residual alternates between r and r0 (free after the start)
+                T *rc = (it & 1) ? r0 : r, *rn = (it & 1) ? r : r0;
+                hipLaunchKernelGGL(k_in_mupdate<T>, dim3(S.vblocks), dim3(256), 0, S.s, n, S.A->row_ptr,
+                                   S.A->col_idx, mv, rc, q, rn, z, part0, m, sr);
+                hipLaunchKernelGGL(k_in_dot2<T>, dim3(m), dim3(kChunkThreads), 0, S.s, n, rn, z, rn, rn, part1, part2,
+                                   sr);
             } else {
                 hipLaunchKernelGGL(k_in_update<T>, dim3(m), dim3(kChunkThreads), 0, S.s, n, r, z, q, minv, part0, m,
                                    part1, part2, sr);
