@@ -516,20 +516,43 @@ __global__ __launch_bounds__(256) void k_cg_p(int64_t n, double *__restrict__ x,
     // the update kernel ran to the end with this alpha: x += alpha p (old p)
     for (int64_t i = i0; i < n; i += (int64_t)gridDim.x * 256)
         sdd(x, n, i, dd_add(ldd(x, n, i), dd_mul(s_alpha, i == i0 ? p0 : ldd(p, n, i))));
-    const dd_t rz = small ? tree_wave(rz_pre, m) : pair_tree(prz, m, P);
-    const dd_t rr = small ? tree_wave(rr_pre, m) : pair_tree(prr, m, P);
-    const int32_t iters = s_iters + 1;
-    int32_t done = RUN;
-    dd_t beta = dd_zero();
-    if (!dd_finite(rr) || !dd_finite(rz)) {
-        done = BROKE_DOWN;
+    // wavefront 0 reduces the chunk sums (a single tree per workgroup) and thread 0 decides
+    // the step for the workgroup
+    __shared__ dd_t s_rz, s_rr, s_beta;
+    __shared__ int32_t s_next;
+    dd_t rz = dd_zero(), rr = dd_zero();
+    if (small) {
+        if (threadIdx.x < 64) {
+            rz = tree_wave(rz_pre, m);
+            rr = tree_wave(rr_pre, m);
+        }
     } else {
-        beta = dd_div(rz, s_rho);
-        if (dd_le(rr, s_tol2))
-            done = RECURRENCE_MET;
-        else if (iters >= s_max)
-            done = ITER_LIMIT;
+        rz = pair_tree(prz, m, P);
+        rr = pair_tree(prr, m, P);
     }
+    if (threadIdx.x == 0) {
+        int32_t d = RUN;
+        dd_t bt = dd_zero();
+        if (!dd_finite(rr) || !dd_finite(rz)) {
+            d = BROKE_DOWN;
+        } else {
+            bt = dd_div(rz, s_rho);
+            if (dd_le(rr, s_tol2))
+                d = RECURRENCE_MET;
+            else if (s_iters + 1 >= s_max)
+                d = ITER_LIMIT;
+        }
+        s_rz = rz;
+        s_rr = rr;
+        s_beta = bt;
+        s_next = d;
+    }
+    __syncthreads();
+    const int32_t iters = s_iters + 1;
+    const int32_t done = s_next;
+    const dd_t beta = s_beta;
+    rz = s_rz;
+    rr = s_rr;
     if (lead) {
         KState o = *sr;
         o.iters = iters;
@@ -1602,20 +1625,43 @@ __global__ __launch_bounds__(256) void k_in_p(int64_t n, T *__restrict__ d, cons
         const T ap = s_alpha * (i == i0 ? p0 : p[i]);
         d[i] = d[i] + ap;
     }
-    const T rz = small ? tree_wave(rz_pre, m) : pair_tree_t(prz, m, P);
-    const T rr = small ? tree_wave(rr_pre, m) : pair_tree_t(prr, m, P);
-    const int32_t iters = s_iters + 1;
-    int32_t done = RUN;
-    T beta = T(0);
-    if (!isfinite((double)rr) || !isfinite((double)rz)) {
-        done = BROKE_DOWN;
+    // wavefront 0 reduces the chunk sums (a single tree per workgroup) and thread 0 decides
+    // the step for the workgroup
+    __shared__ T s_rz, s_rr, s_beta;
+    __shared__ int32_t s_next;
+    T rz = T(0), rr = T(0);
+    if (small) {
+        if (threadIdx.x < 64) {
+            rz = tree_wave(rz_pre, m);
+            rr = tree_wave(rr_pre, m);
+        }
     } else {
-        beta = rz / s_rho;
-        if (rr <= s_tol)
-            done = CONFIRMED;
-        else if (iters >= s_max)
-            done = ITER_LIMIT;
+        rz = pair_tree_t(prz, m, P);
+        rr = pair_tree_t(prr, m, P);
     }
+    if (threadIdx.x == 0) {
+        int32_t d = RUN;
+        T bt = T(0);
+        if (!isfinite((double)rr) || !isfinite((double)rz)) {
+            d = BROKE_DOWN;
+        } else {
+            bt = rz / s_rho;
+            if (rr <= s_tol)
+                d = CONFIRMED;
+            else if (s_iters + 1 >= s_max)
+                d = ITER_LIMIT;
+        }
+        s_rz = rz;
+        s_rr = rr;
+        s_beta = bt;
+        s_next = d;
+    }
+    __syncthreads();
+    const int32_t iters = s_iters + 1;
+    const int32_t done = s_next;
+    const T beta = s_beta;
+    rz = s_rz;
+    rr = s_rr;
     if (lead) {
         InState<T> o = *sr;
         o.iters = iters;
