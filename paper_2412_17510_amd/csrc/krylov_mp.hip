@@ -468,17 +468,27 @@ __global__ __launch_bounds__(256) void k_cg_pstep(int64_t n, double *__restrict_
     mpn<K> rz, rr;
     pair_tree2(prz, prr, m, P, rz, rr);
     const int32_t iters = s_iters + 1;
-    int32_t done = RUN;
-    mpn<K> beta = mp_zero<K>();
-    if (!k_finite(rr) || !k_finite(rz)) {
-        done = BROKE_DOWN;
-    } else {
-        beta = k_div(rz, s_rho);
-        if (k_le(rr, s_tol2))
-            done = RECURRENCE_MET;
-        else if (iters >= s_max)
-            done = ITER_LIMIT;
+    // thread 0 forms beta (one K-component division per workgroup) and the stop decision
+    __shared__ mpn<K> s_beta;
+    __shared__ int32_t s_next;
+    if (threadIdx.x == 0) {
+        int32_t d = RUN;
+        mpn<K> bt = mp_zero<K>();
+        if (!k_finite(rr) || !k_finite(rz)) {
+            d = BROKE_DOWN;
+        } else {
+            bt = k_div(rz, s_rho);
+            if (k_le(rr, s_tol2))
+                d = RECURRENCE_MET;
+            else if (iters >= s_max)
+                d = ITER_LIMIT;
+        }
+        s_beta = bt;
+        s_next = d;
     }
+    __syncthreads();
+    const int32_t done = s_next;
+    const mpn<K> beta = s_beta;
     if (lead) {
         *sw = *sr;
         sw->iters = iters;
