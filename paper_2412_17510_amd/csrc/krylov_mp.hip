@@ -410,7 +410,11 @@ __global__ __launch_bounds__(kChunkThreads) void k_cg_update(int64_t n, double *
         }
         return;
     }
-    const mpn<K> alpha = k_div(s_rho, pq);
+    // thread 0 alone performs the K-component division
+    __shared__ mpn<K> s_alpha;
+    if (threadIdx.x == 0) s_alpha = k_div(s_rho, pq);
+    __syncthreads();
+    const mpn<K> alpha = s_alpha;
     if (lead) {
         st->pq = pq;
         st->alpha = alpha;
