@@ -416,13 +416,14 @@ def locality_section(mp, torch, args):
         xd = torch.from_numpy(random_mp(n, 2, rng)).cuda()
         yd = torch.empty((2, n), dtype=torch.float64, device="cuda")
         plan, pol = mp.mp_plan_autotune(A, 2, ad, xd, yd, reps=5)
-        ms, _ = time_loop(lambda: mp.mpspmv_csr_dd(A, ad, xd, yd, plan=plan), args.steps, args.warmup, torch)
+        ws = mp.spmv_workspace(plan)
+        ms, _ = time_loop(lambda: mp.mpspmv_csr_dd(A, ad, xd, yd, plan=plan, ws=ws), args.steps, args.warmup, torch)
         rf = roofline(n, nnz, 2, False, ms)
         out[name] = {"ms": round(ms, 4), "gnnz_s": round(nnz / (ms * 1e-3) / 1e9, 3), "plan": pol,
                      "roofline_frac": rf["frac"], "achieved_GBs": rf["achieved"]}
         log("%-34s %.4f ms  %.2f GNNZ/s  %.1f%% of 8 TB/s (algorithmic bytes)" % (
             name, ms, nnz / (ms * 1e-3) / 1e9, 100 * rf["frac"]))
-        del A, ad, xd, yd, plan
+        del A, ad, xd, yd, plan, ws
         torch.cuda.empty_cache()
     return out
 
@@ -530,10 +531,11 @@ def main():
             plan = mp.mp_plan_create(A, K, cplx, s, m, c)
             pol = {"shift": s, "max_log2w": m, "tile_nnz": plan.info()["tile_nnz"]}
         fn = mp.SPMV[(K, cplx)]
+        ws = mp.spmv_workspace(plan)
         if cplx:
-            step = lambda: fn(A, ad_re, ad_im, xd_re, xd_im, y_re, y_im, plan=plan)  # noqa: E731
+            step = lambda: fn(A, ad_re, ad_im, xd_re, xd_im, y_re, y_im, plan=plan, ws=ws)  # noqa: E731
         else:
-            step = lambda: fn(A, ad_re, xd_re, y_re, plan=plan)  # noqa: E731
+            step = lambda: fn(A, ad_re, xd_re, y_re, plan=plan, ws=ws)  # noqa: E731
         ms, wall = time_loop(step, args.steps, args.warmup, torch)
         rf = roofline(n, nnz, K, cplx, ms)
         results[name] = {"gnnz_s": round(nnz / (ms * 1e-3) / 1e9, 3), "ms": round(ms, 4),
@@ -547,11 +549,11 @@ def main():
         a64i = ad_im[0].contiguous() if cplx else None
         if cplx:
             fdc = mp.SPMV_D_COMPLEX[K]
-            msd, _ = time_loop(lambda: fdc(A, a64, a64i, xd_re, xd_im, y_re, y_im, plan=plan), args.steps,
+            msd, _ = time_loop(lambda: fdc(A, a64, a64i, xd_re, xd_im, y_re, y_im, plan=plan, ws=ws), args.steps,
                                args.warmup, torch)
         else:
             fd = mp.SPMV_D[K]
-            msd, _ = time_loop(lambda: fd(A, a64, xd_re, y_re, plan=plan), args.steps, args.warmup, torch)
+            msd, _ = time_loop(lambda: fd(A, a64, xd_re, y_re, plan=plan, ws=ws), args.steps, args.warmup, torch)
         rfd = roofline(n, nnz, K, cplx, msd, dmat=True)
         results[name + "_d"] = {"gnnz_s": round(nnz / (msd * 1e-3) / 1e9, 3), "ms": round(msd, 4),
                                 "plan": pol, "roofline": rfd,
@@ -560,7 +562,7 @@ def main():
             name + "_d", pol, msd, nnz / (msd * 1e-3) / 1e9, rfd["bound"], rfd["achieved"], rfd["unit"],
             100 * rfd["frac"]))
         del a64, a64i
-        del ad_re, ad_im, xd_re, xd_im, y_re, y_im, plan
+        del ad_re, ad_im, xd_re, xd_im, y_re, y_im, plan, ws
         torch.cuda.empty_cache()
 
     copy_gbs = copy_bandwidth(torch)

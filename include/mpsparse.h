@@ -69,13 +69,11 @@ typedef struct {
 } mp_csr;
 
 /* Opaque execution plan of one pattern for one variant (K components, real or
- * complex): the per-row lane widths (the summation order), the work decomposition
+ * complex): the per-row lane widths (the summation order) and the work decomposition
  * one SpMV launch walks -- contiguous row tiles of at most tile_nnz elements whose
- * products are staged in LDS, and single-row tiles for longer rows -- and a device
- * buffer into which every planned SpMV first copies x with its components side by
- * side (so that one gather fetches all of them).  Owned by the library.  Because of
- * that buffer, SpMV calls that use the same plan must not run concurrently: issue
- * them on one stream or order them with events. */
+ * products are staged in LDS, and single-row tiles for longer rows.  Owned by the
+ * library and read-only after creation: SpMV calls that share a plan may run
+ * concurrently on several streams (each with its own workspace). */
 typedef struct mp_plan mp_plan;
 
 /* Plan options.  Lane widths: log2w(len) = clamp(floor(log2(len)) - shift, 0,
@@ -134,38 +132,48 @@ mp_status mp_plan_row_log2w(const mp_plan *plan, uint8_t *log2w_host);
 mp_status mp_plan_info(const mp_plan *plan, int32_t *n_rows, int32_t *n_tiles, int32_t *tile_nnz,
                        int32_t *ncomp, int32_t *is_complex);
 
+/* Bytes of device workspace a planned SpMV with this plan needs (host size_t out):
+ * an interleaved copy of x (its K components -- complex: then the K imaginary ones --
+ * side by side per column, so one gather fetches every component), which the call
+ * writes before its tile kernel reads it.  0 for a NULL plan. */
+mp_status mpspmv_workspace_bytes(const mp_plan *plan, size_t *bytes);
+
 /*
  * Real SpMV y = A x (Sec. 3, Fig. 1) in DD (Algs 1-2), TD and QD (Sec. 2).
  *   a: K*nnz values, x: K*n_cols, y: K*n_rows (multi-component layout above).
  *   plan: NULL = canonical order with a one-row-per-wavefront kernel that needs no
  *   plan; otherwise the plan's order and tiles (the plan must have been made for
  *   this variant and for a pattern with the same n_rows and nnz).
- *   y must not overlap a or x (MP_ERR_ALIAS).  Enqueues on `stream` and returns.
+ *   ws: device workspace of ws_bytes >= mpspmv_workspace_bytes(plan) bytes, 256-byte
+ *   aligned (ignored when that is 0, e.g. plan NULL); overwritten by the call and in
+ *   use until it completes on `stream`, so concurrent calls need separate workspaces.
+ *   y must not overlap a or x, nor ws an operand (MP_ERR_ALIAS); a workspace that is
+ *   too small gives MP_ERR_NO_MEMORY.  Enqueues on `stream` and returns.
  */
 mp_status mpspmv_csr_dd(const mp_csr *A, const double *a, const double *x, double *y,
-                        const mp_plan *plan, void *stream);
+                        const mp_plan *plan, void *ws, size_t ws_bytes, void *stream);
 mp_status mpspmv_csr_td(const mp_csr *A, const double *a, const double *x, double *y,
-                        const mp_plan *plan, void *stream);
+                        const mp_plan *plan, void *ws, size_t ws_bytes, void *stream);
 mp_status mpspmv_csr_qd(const mp_csr *A, const double *a, const double *x, double *y,
-                        const mp_plan *plan, void *stream);
+                        const mp_plan *plan, void *ws, size_t ws_bytes, void *stream);
 
 /*
  * Complex SpMV (Sec. 3, Eq. 3): with A = A_re + i A_im and x = x_re + i x_im,
  *   y_re = A_re x_re - A_im x_im and y_im = A_re x_im + A_im x_re, formed as four
  *   accumulator sets in one pass over the pattern (each in the order above) and
  *   combined at the end of the row: y_re = add(rr, -ii), y_im = add(ri, ir).
- *   Same layouts and rules as the real calls; y_re / y_im must not overlap any input
- *   or each other.
+ *   Same layouts, workspace and rules as the real calls; y_re / y_im must not overlap
+ *   any input or each other.
  */
 mp_status mpspmv_csr_dd_complex(const mp_csr *A, const double *a_re, const double *a_im,
                                 const double *x_re, const double *x_im, double *y_re, double *y_im,
-                                const mp_plan *plan, void *stream);
+                                const mp_plan *plan, void *ws, size_t ws_bytes, void *stream);
 mp_status mpspmv_csr_td_complex(const mp_csr *A, const double *a_re, const double *a_im,
                                 const double *x_re, const double *x_im, double *y_re, double *y_im,
-                                const mp_plan *plan, void *stream);
+                                const mp_plan *plan, void *ws, size_t ws_bytes, void *stream);
 mp_status mpspmv_csr_qd_complex(const mp_csr *A, const double *a_re, const double *a_im,
                                 const double *x_re, const double *x_im, double *y_re, double *y_im,
-                                const mp_plan *plan, void *stream);
+                                const mp_plan *plan, void *ws, size_t ws_bytes, void *stream);
 
 /*
  * y = A x with a binary64 matrix and a K-component vector (Sec. 2: the SuiteSparse
@@ -177,15 +185,15 @@ mp_status mpspmv_csr_qd_complex(const mp_csr *A, const double *a_re, const doubl
  * product of the zero-padded value, three components kept (Alg. 5 per Sec. 2) --
  * and the row sums follow the plan's order exactly as in mpspmv_csr_dd, so a plan
  * made for (K, real) serves both.  For DD the result equals mpspmv_csr_dd on the
- * same matrix stored with zero trailing components.  Errors and aliasing rules as
- * mpspmv_csr_dd (a is nnz doubles).
+ * same matrix stored with zero trailing components.  Workspace, errors and aliasing
+ * rules as mpspmv_csr_dd (a is nnz doubles).
  */
 mp_status mpspmv_csr_dd_d(const mp_csr *A, const double *a, const double *x, double *y, const mp_plan *plan,
-                          void *stream);
+                          void *ws, size_t ws_bytes, void *stream);
 mp_status mpspmv_csr_td_d(const mp_csr *A, const double *a, const double *x, double *y, const mp_plan *plan,
-                          void *stream);
+                          void *ws, size_t ws_bytes, void *stream);
 mp_status mpspmv_csr_qd_d(const mp_csr *A, const double *a, const double *x, double *y, const mp_plan *plan,
-                          void *stream);
+                          void *ws, size_t ws_bytes, void *stream);
 
 /*
  * Complex y = A x with a binary64 complex matrix and a K-component complex vector
@@ -196,15 +204,18 @@ mp_status mpspmv_csr_qd_d(const mp_csr *A, const double *a, const double *x, dou
  * part: rr = sum mul_d(x_re, a_re), ii = sum mul_d(x_im, a_im), ri = sum mul_d(x_im,
  * a_re), ir = sum mul_d(x_re, a_im); y_re = rr + (-ii), y_im = ri + ir at the end of
  * the row.  A plan made for (K, complex) serves both this call and
- * mpspmv_csr_{dd,td,qd}_complex.  Errors and aliasing rules as mpspmv_csr_dd_complex
- * (a_re, a_im are nnz doubles each).
+ * mpspmv_csr_{dd,td,qd}_complex.  Workspace, errors and aliasing rules as
+ * mpspmv_csr_dd_complex (a_re, a_im are nnz doubles each).
  */
 mp_status mpspmv_csr_dd_d_complex(const mp_csr *A, const double *a_re, const double *a_im, const double *x_re,
-                                  const double *x_im, double *y_re, double *y_im, const mp_plan *plan, void *stream);
+                                  const double *x_im, double *y_re, double *y_im, const mp_plan *plan, void *ws,
+                                  size_t ws_bytes, void *stream);
 mp_status mpspmv_csr_td_d_complex(const mp_csr *A, const double *a_re, const double *a_im, const double *x_re,
-                                  const double *x_im, double *y_re, double *y_im, const mp_plan *plan, void *stream);
+                                  const double *x_im, double *y_re, double *y_im, const mp_plan *plan, void *ws,
+                                  size_t ws_bytes, void *stream);
 mp_status mpspmv_csr_qd_d_complex(const mp_csr *A, const double *a_re, const double *a_im, const double *x_re,
-                                  const double *x_im, double *y_re, double *y_im, const mp_plan *plan, void *stream);
+                                  const double *x_im, double *y_re, double *y_im, const mp_plan *plan, void *ws,
+                                  size_t ws_bytes, void *stream);
 
 /*
  * A^T in CSR, for A^T v (Sec. 3's SpTMV, which the paper computes by splitting A
@@ -284,7 +295,15 @@ typedef struct {
     int32_t reserved;
 } mp_solve_info;
 
-/* Bytes of device workspace a solver needs for A and opts (host size_t out). */
+/* z = x - y for n DD values (x, y, z: 2*n planar), each element by Alg. 1's addition
+ * of x_i and the negation of y_i (exact sign flips of both components), so the result
+ * keeps both components (e.g. the error x* - x_k of an iterate).  z may be x or y
+ * itself but must not overlap them otherwise (MP_ERR_ALIAS).  Enqueues and returns. */
+mp_status mpvec_dd_sub(int64_t n, const double *x, const double *y, double *z, void *stream);
+
+/* Bytes of device workspace a solver needs for A and opts (host size_t out).  It
+ * includes the staging buffer of the planned SpMV, so a solve only reads its plan and
+ * solves that share a plan may run concurrently with separate workspaces. */
 mp_status mpkrylov_workspace_bytes(const mp_csr *A, const mp_solve_opts *opts, size_t *bytes);
 
 /*

@@ -79,13 +79,15 @@ _SIGS = {
     "mp_plan_row_log2w": ([_P, _P], ctypes.c_int),
     "mp_plan_info": ([_P] + [ctypes.POINTER(_I)] * 5, ctypes.c_int),
 }
+_SIGS["mpspmv_workspace_bytes"] = ([_P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int)
 for _name in ("mpspmv_csr_dd", "mpspmv_csr_td", "mpspmv_csr_qd", "mpspmv_csr_dd_d", "mpspmv_csr_td_d",
               "mpspmv_csr_qd_d"):
-    _SIGS[_name] = ([_CSR, _P, _P, _P, _P, _P], ctypes.c_int)
+    _SIGS[_name] = ([_CSR, _P, _P, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int)
 for _name in ("mpspmv_csr_dd_complex", "mpspmv_csr_td_complex", "mpspmv_csr_qd_complex", "mpspmv_csr_dd_d_complex",
               "mpspmv_csr_td_d_complex", "mpspmv_csr_qd_d_complex"):
-    _SIGS[_name] = ([_CSR, _P, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int)
+    _SIGS[_name] = ([_CSR, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int)
 
+_SIGS["mpvec_dd_sub"] = ([ctypes.c_int64, _P, _P, _P, _P], ctypes.c_int)
 _SIGS["mpkrylov_workspace_bytes"] = ([_CSR, ctypes.POINTER(mp_solve_opts), ctypes.POINTER(ctypes.c_size_t)],
                                      ctypes.c_int)
 for _name in ("mpkrylov_cg", "mpkrylov_bicgstab", "mpkrylov_cgs", "mpkrylov_gpbicg", "mpkrylov_ir"):
@@ -225,6 +227,37 @@ def _plan_handle(plan):
     return None if plan is None else plan.handle
 
 
+def mpspmv_workspace_bytes(plan):
+    """Bytes of SpMV workspace the plan needs (C ABI mpspmv_workspace_bytes; 0 for None)."""
+    v = ctypes.c_size_t()
+    _check(_lib.mpspmv_workspace_bytes(_plan_handle(plan), ctypes.byref(v)), "mpspmv_workspace_bytes")
+    return v.value
+
+
+def spmv_workspace(plan, stream=None):
+    """A device tensor large enough for the plan's SpMV workspace (None if it needs none),
+    allocated on `stream` (torch's current stream by default)."""
+    import torch
+    nb = mpspmv_workspace_bytes(plan)
+    if nb == 0:
+        return None
+    with torch.cuda.stream(stream if stream is not None else torch.cuda.current_stream()):
+        return torch.empty((nb + 7) // 8, dtype=torch.float64, device="cuda")
+
+
+def _spmv_ws(plan, ws, stream):
+    """(workspace tensor or None, pointer, bytes) for one SpMV call: the caller's tensor,
+    or a fresh one on the call's stream (kept alive by the caching allocator's stream
+    order until the call completes)."""
+    if plan is None:
+        return None, None, 0
+    if ws is None:
+        ws = spmv_workspace(plan, stream)
+        if ws is None:
+            return None, None, 0
+    return ws, _ptr(ws), ws.numel() * ws.element_size()
+
+
 def mp_csr_validate(A, stream=None):
     _check(_lib.mp_csr_validate(ctypes.byref(A.c), _stream_ptr(stream)), "mp_csr_validate")
 
@@ -271,11 +304,13 @@ def mp_plan_autotune(A, ncomp, a_re, x_re, y_re, a_im=None, x_im=None, y_im=None
 def _spmv_real(name, K):
     fn = getattr(_lib, name)
 
-    def call(A, a, x, y, plan=None, stream=None):
+    def call(A, a, x, y, plan=None, stream=None, ws=None):
         _check_mp(a, K, A.nnz, "a")
         _check_mp(x, K, A.n_cols, "x")
         _check_mp(y, K, A.n_rows, "y")
-        _check(fn(ctypes.byref(A.c), _ptr(a), _ptr(x), _ptr(y), _plan_handle(plan), _stream_ptr(stream)), name)
+        _w, wp, wb = _spmv_ws(plan, ws, stream)
+        _check(fn(ctypes.byref(A.c), _ptr(a), _ptr(x), _ptr(y), _plan_handle(plan), wp, wb, _stream_ptr(stream)),
+               name)
         return y
 
     call.__name__ = name
@@ -331,13 +366,15 @@ def mp_coo_to_csr(n_rows, n_cols, row, col, v_re, v_im=None, stream=None):
 def _spmv_dmat(name, K):
     fn = getattr(_lib, name)
 
-    def call(A, a, x, y, plan=None, stream=None):
+    def call(A, a, x, y, plan=None, stream=None, ws=None):
         import torch
         if not a.is_cuda or a.dtype != torch.float64 or not a.is_contiguous() or a.numel() != A.nnz:
             raise ValueError("a must be a contiguous CUDA float64 tensor of %d binary64 values" % A.nnz)
         _check_mp(x, K, A.n_cols, "x")
         _check_mp(y, K, A.n_rows, "y")
-        _check(fn(ctypes.byref(A.c), _ptr(a), _ptr(x), _ptr(y), _plan_handle(plan), _stream_ptr(stream)), name)
+        _w, wp, wb = _spmv_ws(plan, ws, stream)
+        _check(fn(ctypes.byref(A.c), _ptr(a), _ptr(x), _ptr(y), _plan_handle(plan), wp, wb, _stream_ptr(stream)),
+               name)
         return y
 
     call.__name__ = name
@@ -348,12 +385,13 @@ def _spmv_dmat(name, K):
 def _spmv_complex(name, K):
     fn = getattr(_lib, name)
 
-    def call(A, a_re, a_im, x_re, x_im, y_re, y_im, plan=None, stream=None):
+    def call(A, a_re, a_im, x_re, x_im, y_re, y_im, plan=None, stream=None, ws=None):
         for t, nm, L in ((a_re, "a_re", A.nnz), (a_im, "a_im", A.nnz), (x_re, "x_re", A.n_cols),
                          (x_im, "x_im", A.n_cols), (y_re, "y_re", A.n_rows), (y_im, "y_im", A.n_rows)):
             _check_mp(t, K, L, nm)
+        _w, wp, wb = _spmv_ws(plan, ws, stream)
         _check(fn(ctypes.byref(A.c), _ptr(a_re), _ptr(a_im), _ptr(x_re), _ptr(x_im), _ptr(y_re), _ptr(y_im),
-                  _plan_handle(plan), _stream_ptr(stream)), name)
+                  _plan_handle(plan), wp, wb, _stream_ptr(stream)), name)
         return y_re, y_im
 
     call.__name__ = name
@@ -371,7 +409,7 @@ mpspmv_csr_qd_complex = _spmv_complex("mpspmv_csr_qd_complex", 4)
 def _spmv_dmat_complex(name, K):
     fn = getattr(_lib, name)
 
-    def call(A, a_re, a_im, x_re, x_im, y_re, y_im, plan=None, stream=None):
+    def call(A, a_re, a_im, x_re, x_im, y_re, y_im, plan=None, stream=None, ws=None):
         import torch
         for t, nm in ((a_re, "a_re"), (a_im, "a_im")):
             if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != A.nnz:
@@ -379,8 +417,9 @@ def _spmv_dmat_complex(name, K):
         for t, nm, L in ((x_re, "x_re", A.n_cols), (x_im, "x_im", A.n_cols), (y_re, "y_re", A.n_rows),
                          (y_im, "y_im", A.n_rows)):
             _check_mp(t, K, L, nm)
+        _w, wp, wb = _spmv_ws(plan, ws, stream)
         _check(fn(ctypes.byref(A.c), _ptr(a_re), _ptr(a_im), _ptr(x_re), _ptr(x_im), _ptr(y_re), _ptr(y_im),
-                  _plan_handle(plan), _stream_ptr(stream)), name)
+                  _plan_handle(plan), wp, wb, _stream_ptr(stream)), name)
         return y_re, y_im
 
     call.__name__ = name
@@ -405,6 +444,15 @@ SPMV = {(2, False): mpspmv_csr_dd, (3, False): mpspmv_csr_td, (4, False): mpspmv
 # ---------------------------------------------------------------------------------------
 # Krylov solvers
 # ---------------------------------------------------------------------------------------
+
+def mpvec_dd_sub(x, y, z, stream=None):
+    """z = x - y in DD (C ABI mpvec_dd_sub); (2, n) CUDA float64 tensors."""
+    n = x.shape[1] if x.dim() == 2 else 0
+    for t, nm in ((x, "x"), (y, "y"), (z, "z")):
+        _check_mp(t, 2, n, nm)
+    _check(_lib.mpvec_dd_sub(n, _ptr(x), _ptr(y), _ptr(z), _stream_ptr(stream)), "mpvec_dd_sub")
+    return z
+
 
 def _opts(precond="jacobi", rtol=1e-28, max_iter=10000, check_every=32, inner="fp64", inner_rtol=1e-8,
           inner_max_iter=0, max_outer=50):

@@ -1850,6 +1850,7 @@ struct Workspace {
     double *minv;
     double *v[kVecs];
     dd_t *part[kParts];
+    double *xs;    // interleaved copy of x that the planned SpMV gathers from
     void *inner;   // InState<T>
     float *a32;
 };
@@ -1862,6 +1863,7 @@ size_t workspace_bytes(int64_t n, int64_t nnz_f32 = 0)
     b += align256(sizeof(double) * (size_t)n);
     b += kVecs * align256(sizeof(double) * 2 * (size_t)n);
     b += kParts * align256(sizeof(dd_t) * kMaxChunks);
+    b += align256(sizeof(double) * 2 * (size_t)n);    // staged x of the planned SpMV
     b += 256;                                         // inner-solver state
     b += align256(sizeof(float) * (size_t)nnz_f32);   // binary32 copies of hi(A) (and of M)
     return b;
@@ -1885,6 +1887,8 @@ Workspace carve(void *ws, int64_t n)
         w.part[i] = reinterpret_cast<dd_t *>(p);
         p += align256(sizeof(dd_t) * kMaxChunks);
     }
+    w.xs = reinterpret_cast<double *>(p);
+    p += align256(sizeof(double) * 2 * (size_t)n);
     w.inner = p;
     p += 256;
     w.a32 = reinterpret_cast<float *>(p);
@@ -1895,7 +1899,7 @@ bool host_dd_le(const double *a, const double *b) { return (a[0] < b[0]) || (a[0
 
 mp_status spmv_dispatch(int K, bool cplx, const mp_csr *A, const double *a_re, const double *a_im,
                         const double *x_re, const double *x_im, double *y_re, double *y_im, const mp_plan *plan,
-                        hipStream_t s);
+                        double *xs, hipStream_t s);
 
 struct Solver {
     const mp_csr *A;
@@ -1909,7 +1913,7 @@ struct Solver {
 
     mp_status spmv(const double *xin, double *yout)
     {
-        return spmv_dispatch(2, false, A, a, nullptr, xin, nullptr, yout, nullptr, plan, s);
+        return spmv_dispatch(2, false, A, a, nullptr, xin, nullptr, yout, nullptr, plan, w.xs, s);
     }
     mp_status launched()
     {
@@ -2020,14 +2024,14 @@ mp_status run_cg(Solver &S, const double *b, double *x, const mp_solve_opts *o, 
     hipLaunchKernelGGL(k_precond, dim3(S.vblocks), dim3(256), 0, S.s, n, minv, r, z, nullptr);
     hipLaunchKernelGGL(k_copy, dim3(S.vblocks), dim3(256), 0, S.s, 2 * n, z, p);
     if ((st = S.launched()) != MP_OK) return st;
-    if ((st = spmv_stage_x(2, false, S.A, p, nullptr, S.plan, S.s)) != MP_OK) return st;
+    if ((st = spmv_stage_x(2, false, S.A, p, nullptr, S.plan, S.w.xs, S.s)) != MP_OK) return st;
     if ((st = S.dot2(b, b, r, z, S.w.part[0], S.w.part[1], nullptr)) != MP_OK) return st;
     if ((st = S.dot2(r, r, nullptr, nullptr, S.w.part[2], nullptr, nullptr)) != MP_OK) return st;
     hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(256), 0, S.s, S.w.part[0], S.w.part[1], S.w.part[2], m,
                        o->rtol * o->rtol, o->max_iter, S.w.st);
     if ((st = S.launched()) != MP_OK) return st;
     int status = MP_ERR_NOT_CONVERGED;
-    double *xs = plan_staged_x(S.plan);
+    double *xs = plan_stage_bytes(S.plan) ? S.w.xs : nullptr;   // k_cg_p stages the next p there
     KState *sb[2] = {S.w.st, S.w.st2};
     const int steps = (every + 1) & ~1;   // even: a chunk ends with the state in sb[0]
     for (;;) {
@@ -2035,7 +2039,7 @@ mp_status run_cg(Solver &S, const double *b, double *x, const mp_solve_opts *o, 
         if (h.done == RUN) {
             for (int it = 0; it < steps; ++it) {
                 KState *sr = sb[it & 1], *sw = sb[(it + 1) & 1];
-                if ((st = spmv_dd_prestaged(S.A, S.a, p, q, S.plan, S.s)) != MP_OK) return st;
+                if ((st = spmv_dd_prestaged(S.A, S.a, p, q, S.plan, S.w.xs, S.s)) != MP_OK) return st;
                 if ((st = S.dot2(p, q, nullptr, nullptr, S.w.part[0], nullptr, sr)) != MP_OK) return st;
                 hipLaunchKernelGGL(k_cg_update, dim3(m), dim3(kChunkThreads), 0, S.s, n, r, z, q, minv, S.w.part[0], m,
                                    S.w.part[1], S.w.part[2], sr);
@@ -2053,7 +2057,7 @@ mp_status run_cg(Solver &S, const double *b, double *x, const mp_solve_opts *o, 
             hipLaunchKernelGGL(k_precond, dim3(S.vblocks), dim3(256), 0, S.s, n, minv, r, z, nullptr);
             hipLaunchKernelGGL(k_copy, dim3(S.vblocks), dim3(256), 0, S.s, 2 * n, z, p);
             if ((st = S.launched()) != MP_OK) return st;
-            if ((st = spmv_stage_x(2, false, S.A, p, nullptr, S.plan, S.s)) != MP_OK) return st;
+            if ((st = spmv_stage_x(2, false, S.A, p, nullptr, S.plan, S.w.xs, S.s)) != MP_OK) return st;
             if ((st = S.dot2(r, z, nullptr, nullptr, S.w.part[1], nullptr, nullptr)) != MP_OK) return st;
             hipLaunchKernelGGL(k_cg_restart, dim3(1), dim3(256), 0, S.s, S.w.part[1], m, S.w.st);
             if ((st = S.launched()) != MP_OK) return st;
@@ -2113,7 +2117,7 @@ mp_status run_bicg(Solver &S, const mp_csr *At, const double *at, const mp_plan 
         if (h.done == RUN) {
             for (int it = 0; it < every; ++it) {
                 if ((st = S.spmv(p, q)) != MP_OK) return st;
-                if ((st = spmv_dispatch(2, false, At, at, nullptr, pt, nullptr, qt, nullptr, plan_t, S.s)) != MP_OK)
+                if ((st = spmv_dispatch(2, false, At, at, nullptr, pt, nullptr, qt, nullptr, plan_t, S.w.xs, S.s)) != MP_OK)
                     return st;
                 if ((st = S.dot2(pt, q, nullptr, nullptr, S.w.part[0], nullptr, S.w.st)) != MP_OK) return st;
                 hipLaunchKernelGGL(k_bicg_alpha, dim3(1), dim3(256), 0, S.s, S.w.part[0], m, S.w.st);
@@ -2594,6 +2598,22 @@ mp_status solve_entry(const char *name, int kind, const mp_csr *A, const double 
 }  // namespace mpk
 
 extern "C" {
+
+mp_status mpvec_dd_sub(int64_t n, const double *x, const double *y, double *z, void *stream)
+{
+    mpk::clear_error();
+    if (n < 0) return mpk::fail(MP_ERR_INVALID_ARG, "mpvec_dd_sub: n < 0");
+    if (n == 0) return MP_OK;
+    if (!x || !y || !z) return mpk::fail(MP_ERR_INVALID_ARG, "mpvec_dd_sub: NULL vector");
+    const size_t vb = sizeof(double) * 2 * (size_t)n;
+    if ((z != x && mpk::overlaps(z, vb, x, vb)) || (z != y && mpk::overlaps(z, vb, y, vb)))
+        return mpk::fail(MP_ERR_ALIAS, "mpvec_dd_sub: z overlaps x or y without being equal to it");
+    const int64_t nb = (n + 255) / 256;
+    hipLaunchKernelGGL(mpk::k_residual, dim3((unsigned)(nb < 65536 ? nb : 65536)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), n, x, y, z);
+    MP_HIP_TRY(hipGetLastError());
+    return MP_OK;
+}
 
 mp_status mpkrylov_workspace_bytes(const mp_csr *A, const mp_solve_opts *opts, size_t *bytes)
 {

@@ -1127,7 +1127,8 @@ template <int K>
 size_t ws_bytes(int64_t n)
 {
     return 2 * al256(sizeof(State<K>)) + al256(sizeof(double) * (size_t)n) +
-           kVecs * al256(sizeof(double) * K * (size_t)n) + kParts * al256(sizeof(mpn<K>) * kMaxChunks);
+           kVecs * al256(sizeof(double) * K * (size_t)n) + kParts * al256(sizeof(mpn<K>) * kMaxChunks) +
+           al256(sizeof(double) * K * (size_t)n);   // staged x of the planned SpMV
 }
 
 template <int K>
@@ -1144,6 +1145,7 @@ struct Solver {
     double *minv;
     double *v[kVecs];
     mpn<K> *part[kParts];
+    double *xs;   // interleaved copy of x that the planned SpMV gathers from
 
     void carve(void *ws)
     {
@@ -1161,6 +1163,7 @@ struct Solver {
             part[i] = reinterpret_cast<mpn<K> *>(p);
             p += al256(sizeof(mpn<K>) * kMaxChunks);
         }
+        xs = reinterpret_cast<double *>(p);
     }
     mp_status launched()
     {
@@ -1169,7 +1172,7 @@ struct Solver {
     }
     mp_status spmv(const double *x, double *y)
     {
-        return spmv_dispatch(K, false, A, a, nullptr, x, nullptr, y, nullptr, plan, s);
+        return spmv_dispatch(K, false, A, a, nullptr, x, nullptr, y, nullptr, plan, xs, s);
     }
     mp_status dot2(const double *x1, const double *y1, const double *x2, const double *y2, mpn<K> *p1, mpn<K> *p2,
                    const State<K> *guard)
@@ -1412,7 +1415,7 @@ mp_status run_bicg(Solver<K> &S, const mp_csr *At, const double *at, const mp_pl
         if (h.done == RUN) {
             for (int it = 0; it < every; ++it) {
                 if ((st = S.spmv(p, q)) != MP_OK) return st;
-                if ((st = spmv_dispatch(K, false, At, at, nullptr, pt, nullptr, qt, nullptr, plan_t, S.s)) != MP_OK)
+                if ((st = spmv_dispatch(K, false, At, at, nullptr, pt, nullptr, qt, nullptr, plan_t, S.xs, S.s)) != MP_OK)
                     return st;
                 if ((st = S.dot2(pt, q, nullptr, nullptr, S.part[0], nullptr, S.st)) != MP_OK) return st;
                 hipLaunchKernelGGL(k_bicg_alpha<K>, dim3(1), dim3(256), 0, S.s, S.part[0], m, S.st);

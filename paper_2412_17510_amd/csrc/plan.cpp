@@ -17,7 +17,6 @@ void plan_free(mp_plan *p)
 {
     if (!p) return;
     if (p->d_stream) (void)hipFree(p->d_stream);
-    if (p->d_xstage) (void)hipFree(p->d_xstage);
     if (p->d_log2w) (void)hipFree(p->d_log2w);
     if (p->d_wide_rows) (void)hipFree(p->d_wide_rows);
     if (p->d_wide) (void)hipFree(p->d_wide);
@@ -123,11 +122,6 @@ mp_status plan_build(const std::vector<int32_t> &rp, std::vector<uint8_t> &&log2
     if (st == MP_OK) st = upload(p->log2w, &p->d_log2w, s);
     if (st == MP_OK) st = upload(wide_rows, &p->d_wide_rows, s);
     if (st == MP_OK) st = upload(wide, &p->d_wide, s);
-    if (st == MP_OK && n_cols > 0) {
-        hipError_t e = hipMalloc(reinterpret_cast<void **>(&p->d_xstage),
-                                 sizeof(double) * (size_t)xstage_doubles(K, cplx) * (size_t)n_cols);
-        if (e != hipSuccess) st = hip_fail(e, "hipMalloc(x staging)");
-    }
     if (st == MP_OK) {
         hipError_t e = hipStreamSynchronize(s);
         if (e != hipSuccess) st = hip_fail(e, "hipStreamSynchronize");
@@ -268,9 +262,21 @@ mp_status mp_plan_autotune(const mp_csr *A, int32_t ncomp, int32_t is_complex, c
     std::vector<int32_t> rp;
     st = mpk::read_row_ptr(A, s, rp);
     if (st != MP_OK) return st;
+    // one staging buffer serves every trial plan (the calls run in order on s)
+    double *xs = nullptr;
+    if (A->n_cols > 0)
+        MP_HIP_TRY(hipMalloc(reinterpret_cast<void **>(&xs),
+                             sizeof(double) * (size_t)mpk::xstage_doubles(ncomp, cplx) * (size_t)A->n_cols));
     hipEvent_t e0, e1;
-    MP_HIP_TRY(hipEventCreate(&e0));
-    MP_HIP_TRY(hipEventCreate(&e1));
+    hipError_t ee = hipEventCreate(&e0);
+    if (ee == hipSuccess) {
+        ee = hipEventCreate(&e1);
+        if (ee != hipSuccess) (void)hipEventDestroy(e0);
+    }
+    if (ee != hipSuccess) {
+        if (xs) (void)hipFree(xs);
+        return mpk::hip_fail(ee, "hipEventCreate");
+    }
     mp_plan *best = nullptr;
     float best_ms = 0.f;
     mp_plan_opts best_o{0, 6, 0};
@@ -281,11 +287,11 @@ mp_status mp_plan_autotune(const mp_csr *A, int32_t ncomp, int32_t is_complex, c
         mp_plan *p = nullptr;
         t = mpk::create_with_opts(A, ncomp, cplx, o, C, s, rp, &p);
         if (t != MP_OK) return t;
-        t = mpk::spmv_dispatch(ncomp, cplx, A, a_re, a_im, x_re, x_im, y_re, y_im, p, s);
+        t = mpk::spmv_dispatch(ncomp, cplx, A, a_re, a_im, x_re, x_im, y_re, y_im, p, xs, s);
         hipError_t err = hipSuccess;
         if (t == MP_OK) err = hipEventRecord(e0, s);
         for (int r = 0; t == MP_OK && err == hipSuccess && r < reps; ++r)
-            t = mpk::spmv_dispatch(ncomp, cplx, A, a_re, a_im, x_re, x_im, y_re, y_im, p, s);
+            t = mpk::spmv_dispatch(ncomp, cplx, A, a_re, a_im, x_re, x_im, y_re, y_im, p, xs, s);
         if (t == MP_OK && err == hipSuccess) err = hipEventRecord(e1, s);
         if (t == MP_OK && err == hipSuccess) err = hipEventSynchronize(e1);
         float ms = 0.f;
@@ -317,6 +323,11 @@ mp_status mp_plan_autotune(const mp_csr *A, int32_t ncomp, int32_t is_complex, c
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (st == MP_OK) {
+        const hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = mpk::hip_fail(e, "hipStreamSynchronize");
+    }
+    if (xs) (void)hipFree(xs);
     if (st != MP_OK) {
         mpk::plan_free(best);
         return st;

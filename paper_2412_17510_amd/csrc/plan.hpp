@@ -11,9 +11,10 @@
 //              tile_nnz staged products, W lane accumulators carried in registers;
 //   * rows longer than tile_nnz with W >= 512 go to a separate list handled by the
 //     register-only wide-row kernel (one row per workgroup);
-//   * a staging buffer for an interleaved copy of x (the K components of x_j, and for
-//     complex data then the K imaginary ones, side by side), written at the start
-//     of every planned SpMV so that one gather fetches all components of x_j.
+// A planned SpMV first writes an interleaved copy of x (the K components of x_j, and
+// for complex data then the K imaginary ones, side by side) into caller workspace so
+// that one gather fetches all components of x_j; the plan itself holds no buffer that
+// an SpMV writes, so it is read-only after creation and may serve several streams.
 // Tiles are in ascending row order, so the XCD-aware block mapping hands each XCD a
 // contiguous range of rows (its L2 then holds the banded part of x those rows gather).
 #pragma once
@@ -52,7 +53,6 @@ struct mp_plan {
     int32_t n_stream = 0;
     int32_t n_wide = 0;
     mp_stream_tile *d_stream = nullptr;   // device, n_stream
-    double *d_xstage = nullptr;           // device, interleaved copy of x (K or 2K doubles per column)
     int32_t n_cols = 0;
     uint8_t *d_log2w = nullptr;           // device, n_rows
     int32_t *d_wide_rows = nullptr;       // device, n_wide
@@ -113,22 +113,28 @@ mp_status plan_build(const std::vector<int32_t> &row_ptr_host, std::vector<uint8
 
 void plan_free(mp_plan *p);
 
-// the plan's staged (interleaved) copy of x that its tile kernel gathers from, or NULL
-// when the plan has no tile kernel
-double *plan_staged_x(const mp_plan *plan);
+// bytes of the interleaved copy of x that a planned SpMV writes before its tile kernel
+// gathers from it (0 when the plan has no tile kernel, or for a NULL plan)
+size_t plan_stage_bytes(const mp_plan *plan);
 
-// write x into the plan's staged copy (no-op without one); DD real only
+// the O(1) argument checks of mpspmv_csr_dd (pattern, operands, plan, aliasing; not the
+// workspace)
+mp_status spmv_check_dd(const char *name, const mp_csr *A, const double *a, const double *x, const double *y,
+                        const mp_plan *plan);
+
+// write x into the interleaved copy xs (no-op when the plan needs none); DD real only
 mp_status spmv_stage_x(int K, bool cplx, const mp_csr *A, const double *x_re, const double *x_im,
-                       const mp_plan *plan, hipStream_t s);
+                       const mp_plan *plan, double *xs, hipStream_t s);
 
-// DD real SpMV whose x has already been staged into the plan's copy (same x planar:
-// the wide-row kernel reads it)
+// DD real SpMV whose x has already been staged into xs (same x planar: the wide-row
+// kernel reads it)
 mp_status spmv_dd_prestaged(const mp_csr *A, const double *a, const double *x, double *y, const mp_plan *plan,
-                            hipStream_t s);
+                            const double *xs, hipStream_t s);
 
-// launch one SpMV of variant (K, cplx) with an optional plan (used by the autotuner)
+// launch one SpMV of variant (K, cplx) with an optional plan; xs: staging buffer of at
+// least plan_stage_bytes(plan) bytes (may be NULL when that is 0)
 mp_status spmv_dispatch(int K, bool cplx, const mp_csr *A, const double *a_re, const double *a_im,
                         const double *x_re, const double *x_im, double *y_re, double *y_im, const mp_plan *plan,
-                        hipStream_t s);
+                        double *xs, hipStream_t s);
 
 }  // namespace mpk

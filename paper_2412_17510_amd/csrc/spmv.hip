@@ -786,11 +786,12 @@ mp_status launch_stream(const SpmvArgs &A, const mp_plan *plan, hipStream_t s)
     }
 }
 
-// stage = false: the caller has already written x into the plan's staged copy
+// xs: the interleaved copy of x the tile kernel gathers from (caller memory of at least
+// plan_stage_bytes(plan) bytes); stage = false: the caller has already written it
 template <int K, bool CPLX, bool DM = false>
 mp_status launch_spmv(const mp_csr *Acsr, const double *a_re, const double *a_im, const double *x_re,
-                      const double *x_im, double *y_re, double *y_im, const mp_plan *plan, hipStream_t s,
-                      bool stage = true)
+                      const double *x_im, double *y_re, double *y_im, const mp_plan *plan, const double *xs,
+                      hipStream_t s, bool stage = true)
 {
     SpmvArgs A;
     A.row_ptr = Acsr->row_ptr;
@@ -819,11 +820,12 @@ mp_status launch_spmv(const mp_csr *Acsr, const double *a_re, const double *a_im
     if (plan->n_stream > 0) {
         if (plan->n_cols != Acsr->n_cols)
             return fail(MP_ERR_INVALID_ARG, "plan was built for n_cols=%d, matrix has %d", plan->n_cols, Acsr->n_cols);
-        A.xs = plan->d_xstage;
+        if (Acsr->n_cols > 0 && !xs) return fail(MP_ERR_INVALID_ARG, "a planned SpMV needs its staging workspace");
+        A.xs = xs;
         if (stage && Acsr->n_cols > 0) {
             const int64_t sb = ((int64_t)Acsr->n_cols + 255) / 256;
             hipLaunchKernelGGL((k_stage_x<K, CPLX>), dim3((unsigned)(sb < 4096 ? sb : 4096)), dim3(256), 0, s, x_re,
-                               x_im, Acsr->n_cols, plan->d_xstage);
+                               x_im, Acsr->n_cols, const_cast<double *>(xs));
             MP_HIP_TRY(hipGetLastError());
         }
         mp_status st;
@@ -846,11 +848,18 @@ mp_status launch_spmv(const mp_csr *Acsr, const double *a_re, const double *a_im
     return MP_OK;
 }
 
-template <int K, bool CPLX, bool DM = false>
-mp_status spmv_entry(const char *name, const mp_csr *A, const double *a_re, const double *a_im, const double *x_re,
-                     const double *x_im, double *y_re, double *y_im, const mp_plan *plan, void *stream)
+size_t plan_stage_bytes(const mp_plan *plan)
 {
-    clear_error();
+    if (!plan || plan->n_stream == 0 || plan->n_cols <= 0) return 0;
+    return sizeof(double) * (size_t)xstage_doubles(plan->ncomp, plan->cplx != 0) * (size_t)plan->n_cols;
+}
+
+// the O(1) argument checks every SpMV entry point runs (the workspace is checked by
+// the caller)
+template <int K, bool CPLX, bool DM>
+mp_status spmv_check(const char *name, const mp_csr *A, const double *a_re, const double *a_im, const double *x_re,
+                     const double *x_im, const double *y_re, const double *y_im, const mp_plan *plan)
+{
     mp_status st = check_csr(A);
     if (st != MP_OK) return st;
     if (A->n_rows > 0 && (!y_re || (CPLX && !y_im))) return fail(MP_ERR_INVALID_ARG, "%s: y is NULL", name);
@@ -862,55 +871,97 @@ mp_status spmv_entry(const char *name, const mp_csr *A, const double *a_re, cons
     if (plan && (plan->ncomp != K || plan->cplx != (CPLX ? 1 : 0)))
         return fail(MP_ERR_INVALID_ARG, "%s: plan was built for ncomp=%d is_complex=%d", name, plan->ncomp,
                     plan->cplx);
+    if (plan && plan->n_stream > 0 && plan->n_cols != A->n_cols)
+        return fail(MP_ERR_INVALID_ARG, "%s: plan was built for n_cols=%d, matrix has %d", name, plan->n_cols,
+                    A->n_cols);
     const size_t yb = sizeof(double) * K * (size_t)A->n_rows;
     const size_t ab = sizeof(double) * (DM ? 1 : K) * (size_t)A->nnz;
     const size_t xb = sizeof(double) * K * (size_t)A->n_cols;
     const double *ins[4] = {a_re, a_im, x_re, x_im};
     const size_t insz[4] = {ab, CPLX ? ab : 0, xb, CPLX ? xb : 0};
-    double *outs[2] = {y_re, CPLX ? y_im : nullptr};
+    const double *outs[2] = {y_re, CPLX ? y_im : nullptr};
     for (int o = 0; o < 2; ++o) {
         for (int i = 0; i < 4; ++i)
             if (overlaps(outs[o], outs[o] ? yb : 0, ins[i], insz[i]))
                 return fail(MP_ERR_ALIAS, "%s: an output overlaps an input", name);
     }
     if (CPLX && overlaps(y_re, yb, y_im, yb)) return fail(MP_ERR_ALIAS, "%s: y_re overlaps y_im", name);
-    return launch_spmv<K, CPLX, DM>(A, a_re, a_im, x_re, x_im, y_re, y_im, plan, static_cast<hipStream_t>(stream));
+    return MP_OK;
 }
 
-double *plan_staged_x(const mp_plan *plan)
+// the staging workspace must not overlap an operand (it is written before the
+// operands are read)
+template <int K, bool CPLX, bool DM>
+bool ws_overlaps(const mp_csr *A, const double *a_re, const double *a_im, const double *x_re, const double *x_im,
+                 const double *y_re, const double *y_im, const void *ws, size_t wb)
 {
-    return (plan && plan->n_stream > 0 && plan->n_cols > 0) ? plan->d_xstage : nullptr;
+    const size_t yb = sizeof(double) * K * (size_t)A->n_rows;
+    const size_t ab = sizeof(double) * (DM ? 1 : K) * (size_t)A->nnz;
+    const size_t xb = sizeof(double) * K * (size_t)A->n_cols;
+    return overlaps(ws, wb, a_re, ab) || (CPLX && overlaps(ws, wb, a_im, ab)) || overlaps(ws, wb, x_re, xb) ||
+           (CPLX && overlaps(ws, wb, x_im, xb)) || overlaps(ws, wb, y_re, yb) || (CPLX && overlaps(ws, wb, y_im, yb)) ||
+           overlaps(ws, wb, A->row_ptr, sizeof(int32_t) * ((size_t)A->n_rows + 1)) ||
+           overlaps(ws, wb, A->col_idx, sizeof(int32_t) * (size_t)A->nnz);
+}
+
+template <int K, bool CPLX, bool DM = false>
+mp_status spmv_entry(const char *name, const mp_csr *A, const double *a_re, const double *a_im, const double *x_re,
+                     const double *x_im, double *y_re, double *y_im, const mp_plan *plan, void *ws, size_t ws_bytes,
+                     void *stream)
+{
+    clear_error();
+    mp_status st = spmv_check<K, CPLX, DM>(name, A, a_re, a_im, x_re, x_im, y_re, y_im, plan);
+    if (st != MP_OK) return st;
+    const size_t need = plan_stage_bytes(plan);
+    if (need > 0) {
+        if (!ws) return fail(MP_ERR_INVALID_ARG, "%s: the plan needs %zu bytes of workspace and ws is NULL", name, need);
+        if (ws_bytes < need)
+            return fail(MP_ERR_NO_MEMORY, "%s: workspace of %zu bytes, %zu needed", name, ws_bytes, need);
+        if (reinterpret_cast<uintptr_t>(ws) & 255)
+            return fail(MP_ERR_INVALID_ARG, "%s: workspace must be 256-byte aligned", name);
+        if (ws_overlaps<K, CPLX, DM>(A, a_re, a_im, x_re, x_im, y_re, y_im, ws, need))
+            return fail(MP_ERR_ALIAS, "%s: the workspace overlaps an operand", name);
+    }
+    return launch_spmv<K, CPLX, DM>(A, a_re, a_im, x_re, x_im, y_re, y_im, plan, static_cast<double *>(ws),
+                                    static_cast<hipStream_t>(stream));
+}
+
+mp_status spmv_check_dd(const char *name, const mp_csr *A, const double *a, const double *x, const double *y,
+                        const mp_plan *plan)
+{
+    return spmv_check<2, false, false>(name, A, a, nullptr, x, nullptr, y, nullptr, plan);
 }
 
 mp_status spmv_stage_x(int K, bool cplx, const mp_csr *A, const double *x_re, const double *x_im,
-                       const mp_plan *plan, hipStream_t s)
+                       const mp_plan *plan, double *xs, hipStream_t s)
 {
-    if (!plan_staged_x(plan)) return MP_OK;
+    if (plan_stage_bytes(plan) == 0) return MP_OK;
     if (K != 2 || cplx) return fail(MP_ERR_UNSUPPORTED, "staging is only exported for the DD real variant");
+    if (!xs) return fail(MP_ERR_INVALID_ARG, "staging workspace is NULL");
     const int64_t sb = ((int64_t)A->n_cols + 255) / 256;
     hipLaunchKernelGGL((k_stage_x<2, false>), dim3((unsigned)(sb < 4096 ? sb : 4096)), dim3(256), 0, s, x_re, x_im,
-                       A->n_cols, plan->d_xstage);
+                       A->n_cols, xs);
     MP_HIP_TRY(hipGetLastError());
     return MP_OK;
 }
 
 mp_status spmv_dd_prestaged(const mp_csr *A, const double *a, const double *x, double *y, const mp_plan *plan,
-                            hipStream_t s)
+                            const double *xs, hipStream_t s)
 {
-    return launch_spmv<2, false>(A, a, nullptr, x, nullptr, y, nullptr, plan, s, false);
+    return launch_spmv<2, false>(A, a, nullptr, x, nullptr, y, nullptr, plan, xs, s, false);
 }
 
 mp_status spmv_dispatch(int K, bool cplx, const mp_csr *A, const double *a_re, const double *a_im,
                         const double *x_re, const double *x_im, double *y_re, double *y_im, const mp_plan *plan,
-                        hipStream_t s)
+                        double *xs, hipStream_t s)
 {
     switch (K * 2 + (cplx ? 1 : 0)) {
-        case 4: return launch_spmv<2, false>(A, a_re, a_im, x_re, x_im, y_re, y_im, plan, s);
-        case 5: return launch_spmv<2, true>(A, a_re, a_im, x_re, x_im, y_re, y_im, plan, s);
-        case 6: return launch_spmv<3, false>(A, a_re, a_im, x_re, x_im, y_re, y_im, plan, s);
-        case 7: return launch_spmv<3, true>(A, a_re, a_im, x_re, x_im, y_re, y_im, plan, s);
-        case 8: return launch_spmv<4, false>(A, a_re, a_im, x_re, x_im, y_re, y_im, plan, s);
-        case 9: return launch_spmv<4, true>(A, a_re, a_im, x_re, x_im, y_re, y_im, plan, s);
+        case 4: return launch_spmv<2, false>(A, a_re, a_im, x_re, x_im, y_re, y_im, plan, xs, s);
+        case 5: return launch_spmv<2, true>(A, a_re, a_im, x_re, x_im, y_re, y_im, plan, xs, s);
+        case 6: return launch_spmv<3, false>(A, a_re, a_im, x_re, x_im, y_re, y_im, plan, xs, s);
+        case 7: return launch_spmv<3, true>(A, a_re, a_im, x_re, x_im, y_re, y_im, plan, xs, s);
+        case 8: return launch_spmv<4, false>(A, a_re, a_im, x_re, x_im, y_re, y_im, plan, xs, s);
+        case 9: return launch_spmv<4, true>(A, a_re, a_im, x_re, x_im, y_re, y_im, plan, xs, s);
         default: return fail(MP_ERR_INVALID_ARG, "ncomp must be 2, 3 or 4 (got %d)", K);
     }
 }
@@ -919,79 +970,96 @@ mp_status spmv_dispatch(int K, bool cplx, const mp_csr *A, const double *a_re, c
 
 extern "C" {
 
-mp_status mpspmv_csr_dd(const mp_csr *A, const double *a, const double *x, double *y, const mp_plan *plan,
-                        void *stream)
+mp_status mpspmv_workspace_bytes(const mp_plan *plan, size_t *bytes)
 {
-    return mpk::spmv_entry<2, false>("mpspmv_csr_dd", A, a, nullptr, x, nullptr, y, nullptr, plan, stream);
+    mpk::clear_error();
+    if (!bytes) return mpk::fail(MP_ERR_INVALID_ARG, "bytes is NULL");
+    *bytes = mpk::plan_stage_bytes(plan);
+    return MP_OK;
 }
 
-mp_status mpspmv_csr_td(const mp_csr *A, const double *a, const double *x, double *y, const mp_plan *plan,
-                        void *stream)
+mp_status mpspmv_csr_dd(const mp_csr *A, const double *a, const double *x, double *y, const mp_plan *plan, void *ws,
+        size_t ws_bytes, void *stream)
 {
-    return mpk::spmv_entry<3, false>("mpspmv_csr_td", A, a, nullptr, x, nullptr, y, nullptr, plan, stream);
+    return mpk::spmv_entry<2, false>("mpspmv_csr_dd", A, a, nullptr, x, nullptr, y, nullptr, plan, ws, ws_bytes, stream);
 }
 
-mp_status mpspmv_csr_qd(const mp_csr *A, const double *a, const double *x, double *y, const mp_plan *plan,
-                        void *stream)
+mp_status mpspmv_csr_td(const mp_csr *A, const double *a, const double *x, double *y, const mp_plan *plan, void *ws,
+        size_t ws_bytes, void *stream)
 {
-    return mpk::spmv_entry<4, false>("mpspmv_csr_qd", A, a, nullptr, x, nullptr, y, nullptr, plan, stream);
+    return mpk::spmv_entry<3, false>("mpspmv_csr_td", A, a, nullptr, x, nullptr, y, nullptr, plan, ws, ws_bytes, stream);
+}
+
+mp_status mpspmv_csr_qd(const mp_csr *A, const double *a, const double *x, double *y, const mp_plan *plan, void *ws,
+        size_t ws_bytes, void *stream)
+{
+    return mpk::spmv_entry<4, false>("mpspmv_csr_qd", A, a, nullptr, x, nullptr, y, nullptr, plan, ws, ws_bytes, stream);
 }
 
 mp_status mpspmv_csr_dd_complex(const mp_csr *A, const double *a_re, const double *a_im, const double *x_re,
-                                const double *x_im, double *y_re, double *y_im, const mp_plan *plan, void *stream)
+        const double *x_im, double *y_re, double *y_im, const mp_plan *plan, void *ws, size_t ws_bytes,
+        void *stream)
 {
-    return mpk::spmv_entry<2, true>("mpspmv_csr_dd_complex", A, a_re, a_im, x_re, x_im, y_re, y_im, plan, stream);
+    return mpk::spmv_entry<2, true>("mpspmv_csr_dd_complex", A, a_re, a_im, x_re, x_im, y_re, y_im, plan, ws, ws_bytes,
+        stream);
 }
 
 mp_status mpspmv_csr_td_complex(const mp_csr *A, const double *a_re, const double *a_im, const double *x_re,
-                                const double *x_im, double *y_re, double *y_im, const mp_plan *plan, void *stream)
+        const double *x_im, double *y_re, double *y_im, const mp_plan *plan, void *ws, size_t ws_bytes,
+        void *stream)
 {
-    return mpk::spmv_entry<3, true>("mpspmv_csr_td_complex", A, a_re, a_im, x_re, x_im, y_re, y_im, plan, stream);
+    return mpk::spmv_entry<3, true>("mpspmv_csr_td_complex", A, a_re, a_im, x_re, x_im, y_re, y_im, plan, ws, ws_bytes,
+        stream);
 }
 
 mp_status mpspmv_csr_qd_complex(const mp_csr *A, const double *a_re, const double *a_im, const double *x_re,
-                                const double *x_im, double *y_re, double *y_im, const mp_plan *plan, void *stream)
+        const double *x_im, double *y_re, double *y_im, const mp_plan *plan, void *ws, size_t ws_bytes,
+        void *stream)
 {
-    return mpk::spmv_entry<4, true>("mpspmv_csr_qd_complex", A, a_re, a_im, x_re, x_im, y_re, y_im, plan, stream);
+    return mpk::spmv_entry<4, true>("mpspmv_csr_qd_complex", A, a_re, a_im, x_re, x_im, y_re, y_im, plan, ws, ws_bytes,
+        stream);
 }
 
-mp_status mpspmv_csr_dd_d(const mp_csr *A, const double *a, const double *x, double *y, const mp_plan *plan,
-                          void *stream)
+mp_status mpspmv_csr_dd_d(const mp_csr *A, const double *a, const double *x, double *y, const mp_plan *plan, void *ws,
+        size_t ws_bytes, void *stream)
 {
-    return mpk::spmv_entry<2, false, true>("mpspmv_csr_dd_d", A, a, nullptr, x, nullptr, y, nullptr, plan, stream);
+    return mpk::spmv_entry<2, false, true>("mpspmv_csr_dd_d", A, a, nullptr, x, nullptr, y, nullptr, plan, ws, ws_bytes, stream);
 }
 
-mp_status mpspmv_csr_td_d(const mp_csr *A, const double *a, const double *x, double *y, const mp_plan *plan,
-                          void *stream)
+mp_status mpspmv_csr_td_d(const mp_csr *A, const double *a, const double *x, double *y, const mp_plan *plan, void *ws,
+        size_t ws_bytes, void *stream)
 {
-    return mpk::spmv_entry<3, false, true>("mpspmv_csr_td_d", A, a, nullptr, x, nullptr, y, nullptr, plan, stream);
+    return mpk::spmv_entry<3, false, true>("mpspmv_csr_td_d", A, a, nullptr, x, nullptr, y, nullptr, plan, ws, ws_bytes, stream);
 }
 
-mp_status mpspmv_csr_qd_d(const mp_csr *A, const double *a, const double *x, double *y, const mp_plan *plan,
-                          void *stream)
+mp_status mpspmv_csr_qd_d(const mp_csr *A, const double *a, const double *x, double *y, const mp_plan *plan, void *ws,
+        size_t ws_bytes, void *stream)
 {
-    return mpk::spmv_entry<4, false, true>("mpspmv_csr_qd_d", A, a, nullptr, x, nullptr, y, nullptr, plan, stream);
+    return mpk::spmv_entry<4, false, true>("mpspmv_csr_qd_d", A, a, nullptr, x, nullptr, y, nullptr, plan, ws, ws_bytes, stream);
 }
 
 mp_status mpspmv_csr_dd_d_complex(const mp_csr *A, const double *a_re, const double *a_im, const double *x_re,
-                                  const double *x_im, double *y_re, double *y_im, const mp_plan *plan, void *stream)
+        const double *x_im, double *y_re, double *y_im, const mp_plan *plan, void *ws, size_t ws_bytes,
+        void *stream)
 {
-    return mpk::spmv_entry<2, true, true>("mpspmv_csr_dd_d_complex", A, a_re, a_im, x_re, x_im, y_re, y_im, plan,
-                                          stream);
+    return mpk::spmv_entry<2, true, true>("mpspmv_csr_dd_d_complex", A, a_re, a_im, x_re, x_im, y_re, y_im, plan, ws, ws_bytes,
+        stream);
 }
 
 mp_status mpspmv_csr_td_d_complex(const mp_csr *A, const double *a_re, const double *a_im, const double *x_re,
-                                  const double *x_im, double *y_re, double *y_im, const mp_plan *plan, void *stream)
+        const double *x_im, double *y_re, double *y_im, const mp_plan *plan, void *ws, size_t ws_bytes,
+        void *stream)
 {
-    return mpk::spmv_entry<3, true, true>("mpspmv_csr_td_d_complex", A, a_re, a_im, x_re, x_im, y_re, y_im, plan,
-                                          stream);
+    return mpk::spmv_entry<3, true, true>("mpspmv_csr_td_d_complex", A, a_re, a_im, x_re, x_im, y_re, y_im, plan, ws, ws_bytes,
+        stream);
 }
 
 mp_status mpspmv_csr_qd_d_complex(const mp_csr *A, const double *a_re, const double *a_im, const double *x_re,
-                                  const double *x_im, double *y_re, double *y_im, const mp_plan *plan, void *stream)
+        const double *x_im, double *y_re, double *y_im, const mp_plan *plan, void *ws, size_t ws_bytes,
+        void *stream)
 {
-    return mpk::spmv_entry<4, true, true>("mpspmv_csr_qd_d_complex", A, a_re, a_im, x_re, x_im, y_re, y_im, plan,
-                                          stream);
+    return mpk::spmv_entry<4, true, true>("mpspmv_csr_qd_d_complex", A, a_re, a_im, x_re, x_im, y_re, y_im, plan, ws, ws_bytes,
+        stream);
 }
 
 }  // extern "C"

@@ -39,13 +39,13 @@ def cg_pairs(A, a, x_true, snapshots=SNAPSHOTS, plan=None):
     mp.mpspmv_csr_dd(A, a, x_true, b, plan=plan)
     E = torch.empty((len(snapshots), n), dtype=torch.float64, device="cuda")
     R = torch.empty_like(E)
-    ev = torch.zeros((2, n), dtype=torch.float64, device="cuda")
+    ev = torch.empty((2, n), dtype=torch.float64, device="cuda")
     rv = torch.empty((2, n), dtype=torch.float64, device="cuda")
     ws = mp._workspace(A, None)
     for i, k in enumerate(snapshots):
         x = torch.zeros((2, n), dtype=torch.float64, device="cuda")
         mp.mpkrylov_cg(A, a, b, x, plan=plan, ws=ws, precond="jacobi", rtol=0.0, max_iter=k, check_every=k)
-        ev[0].copy_(x_true[0] - x[0])
+        mp.mpvec_dd_sub(x_true, x, ev)
         mp.mpspmv_csr_dd(A, a, ev, rv, plan=plan)
         E[i].copy_(ev[0])
         R[i].copy_(rv[0])

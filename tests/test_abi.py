@@ -61,8 +61,14 @@ def test_null_arguments_rejected_without_gpu(lib):
     """O(1) host checks fire before any HIP call."""
     lib.mpspmv_csr_dd.restype = ctypes.c_int
     lib.mp_last_error.restype = ctypes.c_char_p
-    assert lib.mpspmv_csr_dd(None, None, None, None, None, None) == -1
+    assert lib.mpspmv_csr_dd(None, None, None, None, None, None, ctypes.c_size_t(0), None) == -1
     assert b"NULL" in lib.mp_last_error()
+    nb = ctypes.c_size_t(123)
+    assert lib.mpspmv_workspace_bytes(None, ctypes.byref(nb)) == 0 and nb.value == 0
+    assert lib.mpspmv_workspace_bytes(None, None) == -1
+    assert lib.mpvec_dd_sub(ctypes.c_int64(-1), None, None, None, None) == -1
+    assert lib.mpvec_dd_sub(ctypes.c_int64(0), None, None, None, None) == 0
+    assert lib.mpvec_dd_sub(ctypes.c_int64(4), None, None, None, None) == -1
 
 
 def test_learned_entry_points_host_checks(lib):

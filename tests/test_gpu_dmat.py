@@ -2,7 +2,7 @@
 oracle: bitwise equality of every component under the plan's exported order, on
 ragged random matrices spanning several tiles and every lane width 1..1024 (plan-free
 kernel, canonical plans of every tile size, width policies, explicit orders), the
-paper's 5x5 example, and sampled rows of the full n = 1e6 power-law workload; for DD
+paper's 5x5 example, and every row of the full n = 1e6 power-law workload; for DD
 the result equals the DD SpMV of the zero-tail matrix on the GPU too; argument
 checks."""
 import numpy as np
@@ -83,8 +83,9 @@ def test_paper_5x5(mp, K):
     check(mp, K, row_ptr, col_idx, vals, v, A, plan=mp.mp_plan_create(A, K), what="5x5 canonical")
 
 
-@pytest.mark.parametrize("K", [2, 4])
-def test_powerlaw_full_size_sampled(mp, K):
+@pytest.mark.parametrize("K", [2, 3, 4])
+def test_powerlaw_full_size(mp, K):
+    """Every one of the 1e6 rows, under an autotuned-style plan and the plan-free kernel."""
     import torch
     row_ptr, col_idx = powerlaw_pattern(n=1_000_000, seed=1)
     n = row_ptr.size - 1
@@ -93,13 +94,13 @@ def test_powerlaw_full_size_sampled(mp, K):
     x = random_mp(n, K, rng)
     A = mp.Csr.from_numpy(row_ptr, col_idx)
     y = torch.empty((K, n), dtype=torch.float64, device="cuda")
-    plan = mp.mp_plan_create(A, K, False, 2, 8, 512)
-    mp.SPMV_D[K](A, dev(a), dev(x), y, plan=plan)
-    torch.cuda.synchronize()
-    lengths = np.diff(row_ptr)
-    rows = np.unique(np.concatenate([rng.choice(n, 3000, replace=False), np.nonzero(lengths >= 2048)[0], [0, n - 1]]))
-    want = ref.spmv_dmat(K, row_ptr, col_idx, a, x, log2w=plan.row_log2w(), rows=rows)
-    assert_same_values(host(y)[:, rows], want[:, rows], "powerlaw dmat K=%d" % K)
+    ad, xd = dev(a), dev(x)
+    for plan in (mp.mp_plan_create(A, K, False, 2, 8, 512), None):
+        y.fill_(float("nan"))
+        mp.SPMV_D[K](A, ad, xd, y, plan=plan)
+        torch.cuda.synchronize()
+        want = ref.spmv_dmat(K, row_ptr, col_idx, a, x, log2w=None if plan is None else plan.row_log2w())
+        assert_same_values(host(y), want, "powerlaw dmat K=%d plan %s" % (K, plan is not None))
 
 
 def test_argument_checks(mp):
@@ -173,8 +174,9 @@ def test_complex_ragged_random_every_width(mp, K):
     assert_same_values(gr, run(mp, K, A, a_re, x_re, plan_r), "complex with zero imaginary parts vs real")
 
 
-@pytest.mark.parametrize("K", [2, 4])
-def test_complex_powerlaw_full_size_sampled(mp, K):
+@pytest.mark.parametrize("K", [2, 3, 4])
+def test_complex_powerlaw_full_size(mp, K):
+    """Every one of the 1e6 rows of the binary64 complex matrix product."""
     import torch
     row_ptr, col_idx = powerlaw_pattern(n=1_000_000, seed=1)
     n = row_ptr.size - 1
@@ -189,11 +191,9 @@ def test_complex_powerlaw_full_size_sampled(mp, K):
     plan = mp.mp_plan_create(A, K, True, 2, 8, 256)
     mp.SPMV_D_COMPLEX[K](A, dev(a_re), dev(a_im), dev(x_re), dev(x_im), y_re, y_im, plan=plan)
     torch.cuda.synchronize()
-    lengths = np.diff(row_ptr)
-    rows = np.unique(np.concatenate([rng.choice(n, 2000, replace=False), np.nonzero(lengths >= 2048)[0], [0, n - 1]]))
-    wr, wi = ref.spmv_dmat_complex(K, row_ptr, col_idx, a_re, a_im, x_re, x_im, log2w=plan.row_log2w(), rows=rows)
-    assert_same_values(host(y_re)[:, rows], wr[:, rows], "powerlaw complex dmat re K=%d" % K)
-    assert_same_values(host(y_im)[:, rows], wi[:, rows], "powerlaw complex dmat im K=%d" % K)
+    wr, wi = ref.spmv_dmat_complex(K, row_ptr, col_idx, a_re, a_im, x_re, x_im, log2w=plan.row_log2w())
+    assert_same_values(host(y_re), wr, "powerlaw complex dmat re K=%d" % K)
+    assert_same_values(host(y_im), wi, "powerlaw complex dmat im K=%d" % K)
 
 
 def test_complex_argument_checks(mp):

@@ -249,3 +249,32 @@ def test_gpbicg_limits_half_step_and_breakdown(mp):
     with pytest.raises(mp.MpError) as ei:
         mp.mpkrylov_gpbicg(A, ad, dev(bad), x, rtol=1e-28, max_iter=50, raise_on_failure=True)
     assert ei.value.status == -6
+
+
+def test_dd_sub_keeps_both_components(mp):
+    """mpvec_dd_sub equals the oracle's DD addition of x and -y (negation is exact), also
+    in place; the result carries the trailing component that a leading-only difference
+    would drop."""
+    import torch
+    rng = np.random.default_rng(21)
+    n = 100_003
+    x = random_mp(n, 2, rng)
+    y = x.copy()
+    y[1] = random_mp(n, 2, rng)[1] * 1e-3   # same leading parts, different tails
+    y[0, ::7] = random_mp(n, 2, rng)[0, ::7]
+    want = ref.elementwise(2, "add", x, -y)
+    xd, yd = dev(x), dev(y)
+    z = torch.full((2, n), float("nan"), dtype=torch.float64, device="cuda")
+    mp.mpvec_dd_sub(xd, yd, z)
+    torch.cuda.synchronize()
+    assert_same_values(host(z), want, "dd_sub")
+    mp.mpvec_dd_sub(xd, yd, xd)
+    torch.cuda.synchronize()
+    assert_same_values(host(xd), want, "dd_sub in place")
+    same_lead = np.ones(n, dtype=bool)
+    same_lead[::7] = False
+    assert np.all(want[0][same_lead] == x[1][same_lead] - y[1][same_lead])
+    buf = torch.zeros(2 * n + 1, dtype=torch.float64, device="cuda")
+    with pytest.raises(mp.MpError) as ei:
+        mp.mpvec_dd_sub(buf[:2 * n].view(2, n), yd, buf[1:].view(2, n))
+    assert ei.value.status == -2

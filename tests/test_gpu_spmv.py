@@ -6,8 +6,8 @@ oracle.  Cases: the 2D 5-point workload (n = 10,000, 49,600 nnz), ragged random
 matrices spanning several tiles and every lane width 1..1024, the paper's 5x5
 example, empty rows / empty matrices / a single 5,000-element row, every plan kind
 (plan-free kernel, canonical plan, width policies, explicit orders, autotuned), run
-to run determinism, argument errors, and the full n = 1e6 power-law workload on
-sampled rows (including every 4,096-element row).
+to run determinism, argument errors, concurrent calls that share one plan on two
+streams, and the full n = 1e6 power-law workload compared on every row.
 """
 import numpy as np
 import pytest
@@ -238,7 +238,9 @@ def powerlaw():
 
 
 @pytest.mark.parametrize("K,cplx", VARIANTS)
-def test_powerlaw_full_size_sampled(mp, powerlaw, K, cplx):
+def test_powerlaw_full_size(mp, powerlaw, K, cplx):
+    """Every one of the 1e6 rows, under the autotuned plan (the launch configuration the
+    benchmark times) and the plan-free kernel."""
     import torch
     row_ptr, col_idx = powerlaw
     n = row_ptr.size - 1
@@ -256,22 +258,91 @@ def test_powerlaw_full_size_sampled(mp, powerlaw, K, cplx):
     y_im = torch.empty((K, n), dtype=torch.float64, device="cuda") if cplx else None
     args = (ad_re, ad_im, xd_re, xd_im, y_re, y_im) if cplx else (ad_re, xd_re, y_re)
     plan, pol = mp.mp_plan_autotune(A, K, ad_re, xd_re, y_re, ad_im, xd_im, y_im, reps=2)
-    lengths = np.diff(row_ptr)
-    rows = np.unique(np.concatenate([rng.choice(n, 3000, replace=False), np.nonzero(lengths >= 2048)[0],
-                                     [0, n - 1]]))
+    ws = mp.spmv_workspace(plan)
     for p in (plan, None):
         if cplx:
             y_im.fill_(float("nan"))
         y_re.fill_(float("nan"))
-        mp.SPMV[(K, cplx)](A, *args, plan=p)
+        mp.SPMV[(K, cplx)](A, *args, plan=p, ws=ws if p is not None else None)
         torch.cuda.synchronize()
         lw = None if p is None else p.row_log2w()
-        want = ref.spmv(K, row_ptr, col_idx, a_re, x_re, a_im=a_im, x_im=x_im, log2w=lw, rows=rows)
-        got_re = host(y_re)
+        want = ref.spmv(K, row_ptr, col_idx, a_re, x_re, a_im=a_im, x_im=x_im, log2w=lw)
         if cplx:
-            assert_same_values(got_re[:, rows], want[0][:, rows], "powerlaw re %s" % (pol,))
-            assert_same_values(host(y_im)[:, rows], want[1][:, rows], "powerlaw im %s" % (pol,))
+            assert_same_values(host(y_re), want[0], "powerlaw re %s" % (pol,))
+            assert_same_values(host(y_im), want[1], "powerlaw im %s" % (pol,))
         else:
-            assert_same_values(got_re[:, rows], want[:, rows], "powerlaw %s" % (pol,))
-        assert not np.isnan(got_re).any()
+            assert_same_values(host(y_re), want, "powerlaw %s" % (pol,))
     assert plan.info()["tile_nnz"] == pol["tile_nnz"]
+
+
+@pytest.mark.parametrize("K,cplx", [(2, False), (3, True)])
+def test_shared_plan_concurrent_streams(mp, K, cplx):
+    """A plan is read-only: two SpMVs that share it, each with its own workspace, run
+    concurrently on two streams (different x, different y) and both equal the oracle
+    bit for bit; repeated with the calls interleaved many times."""
+    import torch
+    rng = np.random.default_rng([11, K, int(cplx)])
+    n_cols = 60000
+    lengths = np.concatenate([rng.integers(0, 60, 40000), rng.integers(200, 3000, 40)])
+    row_ptr, col_idx, a_re, a_im = random_csr(lengths.size, n_cols, lengths, K, rng, cplx)
+    A = mp.Csr.from_numpy(row_ptr, col_idx, n_cols=n_cols)
+    plan = mp.mp_plan_create(A, K, cplx, 1, 6)
+    xs = [(random_mp(n_cols, K, rng), random_mp(n_cols, K, rng) if cplx else None) for _ in range(2)]
+    wants = [ref.spmv(K, row_ptr, col_idx, a_re, xr, a_im=a_im, x_im=xi, log2w=plan.row_log2w()) for xr, xi in xs]
+    ad_re = dev(a_re)
+    ad_im = dev(a_im) if cplx else None
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    torch.cuda.synchronize()
+    ins, outs, wss = [], [], []
+    for j, st in enumerate(streams):
+        with torch.cuda.stream(st):
+            xr, xi = xs[j]
+            ins.append((dev(xr), dev(xi) if cplx else None))
+            outs.append((torch.empty((K, A.n_rows), dtype=torch.float64, device="cuda"),
+                         torch.empty((K, A.n_rows), dtype=torch.float64, device="cuda") if cplx else None))
+            wss.append(mp.spmv_workspace(plan, st))
+    torch.cuda.synchronize()
+    for _ in range(20):
+        for j, st in enumerate(streams):
+            (xr, xi), (yr, yi) = ins[j], outs[j]
+            if cplx:
+                mp.SPMV[(K, True)](A, ad_re, ad_im, xr, xi, yr, yi, plan=plan, stream=st, ws=wss[j])
+            else:
+                mp.SPMV[(K, False)](A, ad_re, xr, yr, plan=plan, stream=st, ws=wss[j])
+    torch.cuda.synchronize()
+    for j in range(2):
+        yr, yi = outs[j]
+        if cplx:
+            assert_same_values(host(yr), wants[j][0], "stream %d re" % j)
+            assert_same_values(host(yi), wants[j][1], "stream %d im" % j)
+        else:
+            assert_same_values(host(yr), wants[j], "stream %d" % j)
+
+
+def test_workspace_errors(mp):
+    """A planned SpMV refuses a workspace that is too small, misaligned or overlapping an
+    operand; the plan-free call needs none."""
+    import torch
+    rng = np.random.default_rng(12)
+    lengths = rng.integers(1, 50, 3000)
+    row_ptr, col_idx, a, _ = random_csr(3000, 3000, lengths, 2, rng)
+    x = random_mp(3000, 2, rng)
+    A = mp.Csr.from_numpy(row_ptr, col_idx, n_cols=3000)
+    plan = mp.mp_plan_create(A, 2)
+    need = mp.mpspmv_workspace_bytes(plan)
+    assert need == 16 * 3000 and mp.mpspmv_workspace_bytes(None) == 0
+    ad, xd = dev(a), dev(x)
+    y = torch.empty((2, 3000), dtype=torch.float64, device="cuda")
+    with pytest.raises(mp.MpError) as ei:
+        mp.mpspmv_csr_dd(A, ad, xd, y, plan=plan, ws=torch.empty(need // 8 - 1, dtype=torch.float64, device="cuda"))
+    assert ei.value.status == -4
+    big = torch.empty(need // 8 + 64, dtype=torch.float64, device="cuda")
+    with pytest.raises(mp.MpError) as ei:
+        mp.mpspmv_csr_dd(A, ad, xd, y, plan=plan, ws=big[1:])
+    assert ei.value.status == -1
+    with pytest.raises(mp.MpError) as ei:
+        mp.mpspmv_csr_dd(A, ad, xd, y, plan=plan, ws=y.view(-1))
+    assert ei.value.status == -2
+    mp.mpspmv_csr_dd(A, ad, xd, y, plan=plan, ws=big)
+    torch.cuda.synchronize()
+    assert_same_values(host(y), ref.spmv(2, row_ptr, col_idx, a, x, log2w=plan.row_log2w()), "workspace")
