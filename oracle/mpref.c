@@ -525,12 +525,15 @@ static mpv dot_tree(int K, int64_t n, const double *x, const double *y)
 {
     int64_t nch = (n + DOT_CHUNK - 1) / DOT_CHUNK, c, m;
     mpv zero = {{0.0, 0.0, 0.0, 0.0}};
-    mpv *P, lanes[DOT_LANES], out;
+    mpv *P, out;
     if (n == 0) return zero;
     P = (mpv *)malloc(sizeof(mpv) * (size_t)nch);
+    /* chunks are independent (each thread sums whole chunks in the order above) */
+#pragma omp parallel for schedule(static) if (nch >= 8)
     for (c = 0; c < nch; ++c) {
         int64_t base = c * DOT_CHUNK, cnt = n - base < DOT_CHUNK ? n - base : DOT_CHUNK;
         int l, off, used = cnt < DOT_LANES ? (int)cnt : DOT_LANES;
+        mpv lanes[DOT_LANES];
         for (l = 0; l < used; ++l) {
             int64_t k = base + l;
             lanes[l] = mp_mul(K, load_mp(K, x, n, k), load_mp(K, y, n, k));
@@ -601,6 +604,7 @@ static void dd_residual(const dd_mat *M, const double *b, const double *x, doubl
 {
     int64_t i, n = M->n;
     dd_spmv(M, x, q);
+#pragma omp parallel for schedule(static) if (n >= 32768)
     for (i = 0; i < n; ++i) st2(r, n, i, dd_add(ld2(b, n, i), mp_neg(ld2(q, n, i))));
 }
 
@@ -608,6 +612,7 @@ static void dd_residual(const dd_mat *M, const double *b, const double *x, doubl
 static void dd_precond(int64_t n, const double *minv, const double *r, double *z)
 {
     int64_t i;
+#pragma omp parallel for schedule(static) if (n >= 32768)
     for (i = 0; i < n; ++i) st2(z, n, i, minv ? dd_mul_d(ld2(r, n, i), minv[i]) : ld2(r, n, i));
 }
 
@@ -670,6 +675,7 @@ int oracle_cg(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col
         pq = dd_dot_vec(n, p, q);
         if (!(pq.c[0] > 0.0) || !isfinite(pq.c[0])) { status = -6; break; }
         alpha = dd_div(rho, pq);
+#pragma omp parallel for schedule(static) if (n >= 32768)
         for (i = 0; i < n; ++i) {
             st2(x, n, i, dd_add(ld2(x, n, i), dd_mul(alpha, ld2(p, n, i))));
             st2(r, n, i, dd_add(ld2(r, n, i), mp_neg(dd_mul(alpha, ld2(q, n, i)))));
@@ -682,6 +688,7 @@ int oracle_cg(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col
         if (!isfinite(rr.c[0]) || !isfinite(rho_new.c[0])) { status = -6; break; }
         beta = dd_div(rho_new, rho);
         rho = rho_new;
+#pragma omp parallel for schedule(static) if (n >= 32768)
         for (i = 0; i < n; ++i) st2(p, n, i, dd_add(ld2(z, n, i), dd_mul(beta, ld2(p, n, i))));
     }
     /* exit record: the true residual of the returned x */
@@ -808,12 +815,14 @@ int oracle_bicgstab(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_
     static T dot_##SUF(int64_t n, const T *x, const T *y)                                          \
     {                                                                                              \
         int64_t nch = (n + DOT_CHUNK - 1) / DOT_CHUNK, c, m;                                       \
-        T *P, lanes[DOT_LANES], out;                                                               \
+        T *P, out;                                                                                 \
         if (n == 0) return (T)0;                                                                   \
         P = (T *)malloc(sizeof(T) * (size_t)nch);                                                  \
+        _Pragma("omp parallel for schedule(static) if (nch >= 8)")                                 \
         for (c = 0; c < nch; ++c) {                                                                \
             int64_t base = c * DOT_CHUNK, cnt = n - base < DOT_CHUNK ? n - base : DOT_CHUNK;      \
             int l, off, used = cnt < DOT_LANES ? (int)cnt : DOT_LANES;                             \
+            T lanes[DOT_LANES];                                                                    \
             for (l = 0; l < used; ++l) {                                                           \
                 int64_t k = base + l;                                                              \
                 T prod = x[k] * y[k];                                                              \
@@ -879,6 +888,7 @@ int oracle_bicgstab(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_
             pq = dot_##SUF(n, p, q);                                                               \
             if (!(pq > (T)0) || !isfinite((double)pq)) { *status = -6; break; }                   \
             alpha = rho / pq;                                                                      \
+            _Pragma("omp parallel for schedule(static) if (n >= 32768)")                           \
             for (i = 0; i < n; ++i) {                                                              \
                 T ap = alpha * p[i], aq = alpha * q[i];                                            \
                 d[i] = d[i] + ap;                                                                  \
@@ -893,6 +903,7 @@ int oracle_bicgstab(int64_t n, int64_t nnz, const int32_t *row_ptr, const int32_
             beta = rho_new / rho;                                                                  \
             rho = rho_new;                                                                         \
             if (rr <= tol) { *status = 0; break; }                                                 \
+            _Pragma("omp parallel for schedule(static) if (n >= 32768)")                           \
             for (i = 0; i < n; ++i) {                                                              \
                 T bp = beta * p[i];                                                                \
                 p[i] = z[i] + bp;                                                                  \
@@ -1248,12 +1259,14 @@ static void mpm_residual(const mp_mat *M, const double *b, const double *x, doub
 {
     int64_t i;
     mpm_spmv(M, x, q);
+#pragma omp parallel for schedule(static) if (M->n >= 32768)
     for (i = 0; i < M->n; ++i) stk(M, r, i, mp_add(M->K, ldk(M, b, i), mp_neg(ldk(M, q, i))));
 }
 
 static void mpm_precond(const mp_mat *M, const double *minv, const double *r, double *z)
 {
     int64_t i;
+#pragma omp parallel for schedule(static) if (M->n >= 32768)
     for (i = 0; i < M->n; ++i) stk(M, z, i, minv ? mp_mul_d(M->K, ldk(M, r, i), minv[i]) : ldk(M, r, i));
 }
 
@@ -1307,6 +1320,7 @@ int oracle_cg_k(int K, int64_t n, int64_t nnz, const int32_t *row_ptr, const int
         pq = mp_dot_vec(K, n, p, q);
         if (!(pq.c[0] > 0.0) || !isfinite(pq.c[0])) { status = -6; break; }
         alpha = mp_div(K, rho, pq);
+#pragma omp parallel for schedule(static) if (n >= 32768)
         for (i = 0; i < n; ++i) {
             stk(&M, x, i, mp_add(K, ldk(&M, x, i), mp_mul(K, alpha, ldk(&M, p, i))));
             stk(&M, r, i, mp_add(K, ldk(&M, r, i), mp_neg(mp_mul(K, alpha, ldk(&M, q, i)))));
@@ -1319,6 +1333,7 @@ int oracle_cg_k(int K, int64_t n, int64_t nnz, const int32_t *row_ptr, const int
         if (!isfinite(rr.c[0]) || !isfinite(rho_new.c[0])) { status = -6; break; }
         beta = mp_div(K, rho_new, rho);
         rho = rho_new;
+#pragma omp parallel for schedule(static) if (n >= 32768)
         for (i = 0; i < n; ++i) stk(&M, p, i, mp_add(K, ldk(&M, z, i), mp_mul(K, beta, ldk(&M, p, i))));
     }
     mpm_residual(&M, b, x, q, r);

@@ -32,6 +32,8 @@ def lib():
         L.oracle_coo_to_csr.argtypes = [i64, i64, i64, P, P, ctypes.c_int, P, P, P, P]
         L.oracle_canonical_log2w.argtypes = [i64]
         L.oracle_num_threads.argtypes = []
+        L.oracle_exact_residual.argtypes = [ctypes.c_int, ctypes.c_int, i64, i64, P, P, P, P, P, P, P]
+        L.oracle_exact_residual.restype = ctypes.c_int
         for name in ("oracle_eft", "oracle_elementwise", "oracle_renorm5", "oracle_spmv", "oracle_spmv_dmat",
                      "oracle_spmv_dmat_complex", "oracle_transpose", "oracle_coo_to_csr",
                      "oracle_canonical_log2w", "oracle_num_threads"):
@@ -203,6 +205,32 @@ def coo_to_csr(n_rows, n_cols, row, col, v):
         raise ValueError("coordinate outside the %d x %d matrix" % (n_rows, n_cols))
     assert st == 0
     return rp, ci, a.reshape(v.shape)
+
+
+def exact_residual(row_ptr, col_idx, a, b, x, want_vector=False):
+    """Exact residual of A x = b (oracle_exact_residual): a (Ka, nnz) or (nnz,), b and x
+    (Kx, n), every value the exact sum of its stored components.  Returns a dict with
+    rr_upper >= ||b - A x||^2, bb_lower <= ||b||^2, relres_upper = sqrt of their ratio
+    (rounded up), the informational rr / bb, and r (the exact residual rounded to
+    binary64) when want_vector."""
+    a = _f64(a)
+    a2 = a.reshape(1, -1) if a.ndim == 1 else a
+    b, x = _f64(b), _f64(x)
+    n = b.shape[1]
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    norms = np.zeros(4)
+    r = np.zeros(n) if want_vector else None
+    st = lib().oracle_exact_residual(a2.shape[0], b.shape[0], n, ci.size, _p(rp), _p(ci), _p(a2), _p(b), _p(x),
+                                     _p(r), _p(norms))
+    if st != 0:
+        raise ValueError("oracle_exact_residual failed (%d)" % st)
+    ratio = norms[0] / norms[1] if norms[1] > 0 else (0.0 if norms[0] == 0 else np.inf)
+    out = {"rr_upper": float(norms[0]), "bb_lower": float(norms[1]),
+           "relres_upper": float(np.sqrt(ratio) * (1.0 + 2.0 ** -50)), "rr": float(norms[2]), "bb": float(norms[3])}
+    if want_vector:
+        out["r"] = r
+    return out
 
 
 def num_threads():
