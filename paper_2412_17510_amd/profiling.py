@@ -5,10 +5,17 @@
     python -m paper_2412_17510_amd.profiling traffic --fetch F.csv --write W.csv \
             --copy-fetch CF.csv --copy-write CW.csv --copy-bytes B --match NAME --out T.json
 
-`traffic` turns the per-dispatch FETCH_SIZE / WRITE_SIZE counters (KiB) of the named
-kernel into bytes per launch, scaled by what the same counters read for a plain copy
-of known size (bytes moved / counter reading), and records the hash of the kernel
-sources so that a benchmark can tell whether the figure still describes the code.
+`traffic` turns the per-dispatch L2-to-memory request counters of the named kernels
+into bytes per launch, each request counted at its own size:
+    read  = 32 TCC_EA0_RDREQ_32B + 64 TCC_EA0_RDREQ_64B + 128 TCC_EA0_RDREQ_128B
+    write = 32 (TCC_EA0_WRREQ - TCC_EA0_WRREQ_64B) + 64 TCC_EA0_WRREQ_64B
+(one rocprofv3 --pmc run for the read counters, one for the write counters), and
+checks them against a plain copy of known size, whose bytes moved divided by the
+counted bytes give the scale factors applied (about 1: the request sizes account
+for the copy's traffic exactly).  The derived FETCH_SIZE counter of this device
+counts a 128-byte request as 64 bytes, which is why it is not used.  The record
+carries the hash of the kernel sources so that a benchmark can tell whether the
+figure still describes the code.
 With --merge the output file holds a list of such records ({"records": [...]}), one per
 launch configuration (the "plan" given in --extra): a record of the same plan is
 replaced, and records taken from other kernel sources (another hash) are dropped.
@@ -62,33 +69,47 @@ def counter_values(path, counter, match):
     return vals
 
 
-def traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes, match, copy_match):
-    """Copy-calibrated bytes per launch; `match` may name several kernels ("a|b"), whose
-    per-launch means are added (one library call launching several kernels)."""
+READ_COUNTERS = ("TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum", "TCC_EA0_RDREQ_128B_sum", "TCC_EA0_RDREQ_sum")
+WRITE_COUNTERS = ("TCC_EA0_WRREQ_sum", "TCC_EA0_WRREQ_64B_sum", "TCC_EA0_RDREQ_DRAM_sum")
+
+
+def request_bytes(read_csv, write_csv, match):
+    """Mean bytes per dispatch read and written by kernels whose name contains `match`,
+    from the request-size-resolved counters; also the requests of no resolved size."""
     mean = lambda v: sum(v) / len(v)  # noqa: E731
-    cf = counter_values(copy_fetch_csv, "FETCH_SIZE", copy_match)
-    cw = counter_values(copy_write_csv, "WRITE_SIZE", copy_match)
-    if not (cf and cw):
-        raise SystemExit("traffic: no copy-kernel counter rows matching %r" % copy_match)
-    # the copy reads and writes copy_bytes each: scale factors in bytes per KiB of reading
-    kf = copy_bytes / mean(cf)
-    kw = copy_bytes / mean(cw)
+    c = {}
+    for path, names in ((read_csv, READ_COUNTERS), (write_csv, WRITE_COUNTERS)):
+        for name in names:
+            v = counter_values(path, name, match)
+            if not v:
+                raise SystemExit("traffic: no %s rows for kernel %r in %s" % (name, match, path))
+            c[name] = mean(v)
+    n32, n64, n128, nall = (c[k] for k in READ_COUNTERS)
+    wr, wr64 = c["TCC_EA0_WRREQ_sum"], c["TCC_EA0_WRREQ_64B_sum"]
+    return {"read_bytes": 32 * n32 + 64 * n64 + 128 * n128, "write_bytes": 32 * (wr - wr64) + 64 * wr64,
+            "read_requests": {"32B": n32, "64B": n64, "128B": n128, "all": nall,
+                              "unresolved": nall - (n32 + n64 + n128)},
+            "write_requests": {"all": wr, "64B": wr64}, "dram_read_requests": c["TCC_EA0_RDREQ_DRAM_sum"],
+            "launches": len(counter_values(read_csv, READ_COUNTERS[0], match))}
+
+
+def traffic(read_csv, write_csv, copy_read_csv, copy_write_csv, copy_bytes, match, copy_match):
+    """Bytes per library call (the named kernels' per-dispatch means added: one call may
+    launch several kernels), scaled by the copy's bytes moved per counted byte."""
+    cp = request_bytes(copy_read_csv, copy_write_csv, copy_match)
+    kr = copy_bytes / cp["read_bytes"]
+    kw = copy_bytes / cp["write_bytes"]
     per = {}
-    fkib = wkib = 0.0
+    rb = wb = 0.0
     for m in match.split("|"):
-        f = counter_values(fetch_csv, "FETCH_SIZE", m)
-        w = counter_values(write_csv, "WRITE_SIZE", m)
-        if not (f and w):
-            raise SystemExit("traffic: missing counter rows for kernel %r" % m)
-        per[m] = {"fetch_kib": mean(f), "write_kib": mean(w), "launches": len(f)}
-        fkib += mean(f)
-        wkib += mean(w)
-    fb = fkib * kf
-    wb = wkib * kw
-    return {"kernels": per, "fetch_kib_per_call": fkib, "write_kib_per_call": wkib,
-            "copy_fetch_kib": mean(cf), "copy_write_kib": mean(cw), "copy_bytes": copy_bytes,
-            "fetch_scale_bytes_per_kib": kf, "write_scale_bytes_per_kib": kw,
-            "fetch_bytes": fb, "write_bytes": wb, "traffic_bytes": fb + wb, "source_hash": source_hash()}
+        r = request_bytes(read_csv, write_csv, m)
+        per[m] = r
+        rb += r["read_bytes"]
+        wb += r["write_bytes"]
+    return {"kernels": per, "copy": cp, "copy_bytes": copy_bytes, "read_scale": kr, "write_scale": kw,
+            "read_bytes": rb * kr, "write_bytes": wb * kw, "traffic_bytes": rb * kr + wb * kw,
+            "counters": {"read": list(READ_COUNTERS), "write": list(WRITE_COUNTERS)},
+            "source_hash": source_hash()}
 
 
 def merge_record(path, rec):

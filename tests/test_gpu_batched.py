@@ -7,6 +7,10 @@ mpkrylov_cg_batched).
   same order (status, iterations, restarts, bitwise x and true residual); the hipGraph
   replay path equals the eager path bitwise; a pair equals the GPU's own single-system
   mpkrylov_cg with a W = 1 plan.
+* Systems of several 4096-row dot chunks (grid edges 12..33, 1,728..35,937 rows, 8
+  right-hand sides): every pair after a capped number of iterations, and every pair of
+  two multi-chunk systems solved to 1e-28, equal to separate oracle solves, in the
+  graph and the eager path.
 * A matrix with an entry outside its system's block is refused.
 """
 import numpy as np
@@ -100,6 +104,58 @@ def test_batched_cg_matches_single_solves(mp, precond):
     mp.mpkrylov_cg(As, dev(np.ascontiguousarray(a[:, rp[r0]:rp[r1]])), dev(np.ascontiguousarray(B[:, r0:r1, r])),
                    xs, plan=p1, precond=precond, rtol=1e-28, max_iter=3000)
     assert_same_values(host(xs), Xg[:, r0:r1, r], "batched vs single GPU solve")
+
+
+def compare_pairs(mp, edges, R, seed, max_iter, precond="jacobi", converged=False):
+    import torch
+    rp, ci, a, sp = batched_diffusion(edges, sigma=2.5, seed=seed)
+    N = rp.size - 1
+    rng = np.random.default_rng(seed)
+    B = multi(rng, N, R)
+    A = mp.Csr.from_numpy(rp, ci)
+    plan = mp.mp_batch_plan_create(A, sp, R, 2)
+    results = {}
+    for use_graph in (True, False):
+        print("batched edges=%s R=%d max_iter=%d graph=%s" % (edges, R, max_iter, use_graph), flush=True)
+        X = torch.zeros((2, N, R), dtype=torch.float64, device="cuda")
+        infos = mp.mpkrylov_cg_batched(A, dev(a), dev(B), X, R, plan, use_graph=use_graph, precond=precond,
+                                       rtol=1e-28, max_iter=max_iter, check_every=8)
+        results[use_graph] = (host(X), infos)
+    assert_same_values(results[True][0], results[False][0], "graph vs eager")
+    for g in (True, False):
+        assert [i["iters"] for i in results[True][1]] == [i["iters"] for i in results[g][1]]
+    Xg, infos = results[True]
+    for s in range(len(edges)):
+        r0, r1 = sp[s], sp[s + 1]
+        rps = (rp[r0:r1 + 1] - rp[r0]).astype(np.int32)
+        cis = (ci[rp[r0]:rp[r1]] - r0).astype(np.int32)
+        a_s = np.ascontiguousarray(a[:, rp[r0]:rp[r1]])
+        for r in range(R):
+            b_s = np.ascontiguousarray(B[:, r0:r1, r])
+            xo, io = ref.cg(rps, cis, a_s, b_s, precond=precond, rtol=1e-28, max_iter=max_iter,
+                            log2w=np.zeros(r1 - r0, np.uint8))
+            ig = infos[s * R + r]
+            assert (ig["status"], ig["iters"], ig["restarts"]) == (io["status"], io["iters"], io["restarts"]), (s, r)
+            assert_same_values(Xg[:, r0:r1, r], xo, "pair (%d, %d) x" % (s, r))
+            assert_same_values(ig["rr_true"], io["rr_true"], "pair (%d, %d) rr" % (s, r))
+            assert_same_values(ig["bb"], io["bb"], "pair (%d, %d) bb" % (s, r))
+            if converged:
+                assert ig["status"] == 0
+    return infos
+
+
+def test_batched_cg_multi_chunk_capped(mp):
+    """Five systems of 1..9 dot chunks, 8 right-hand sides each, 40 iterations: every
+    pair's iterate equals the oracle's (the per-system chunk boundaries and the
+    multi-chunk reduction trees of every scalar)."""
+    infos = compare_pairs(mp, [12, 17, 20, 24, 33], 8, 44, 40)
+    assert all(i["status"] == -5 and i["iters"] == 40 for i in infos)
+
+
+def test_batched_cg_multi_chunk_converged(mp):
+    """Two multi-chunk systems (4,913 and 8,000 rows), 8 right-hand sides, solved to
+    1e-28: every pair equals the oracle's solve, status and iteration count included."""
+    compare_pairs(mp, [17, 20], 8, 45, 20000, converged=True)
 
 
 def test_batched_rejects_off_block_entries(mp):
