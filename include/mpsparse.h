@@ -158,6 +158,19 @@ mp_status mpspmv_csr_qd(const mp_csr *A, const double *a, const double *x, doubl
                         const mp_plan *plan, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * mpspmv_csr_dd without workspace, for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid allocation).
+ * Same arguments, order, results and errors as mpspmv_csr_dd, but the interleaved
+ * copy of x is staged in a fixed 16 MiB device array of the library (one per GPU,
+ * held from module load until the process ends), so n_cols <= 1,048,576 when plan is
+ * non-NULL (larger: MP_ERR_NO_MEMORY before anything is launched).  Calls no
+ * allocating routine.  Calls that overlap on one GPU share that array and race:
+ * order them on one stream or with events.  Enqueues on `stream` and returns.
+ */
+mp_status mpspmv_csr_dd_noalloc(const mp_csr *A, const double *a, const double *x, double *y,
+                                const mp_plan *plan, void *stream);
+
+/*
  * Complex SpMV (Sec. 3, Eq. 3): with A = A_re + i A_im and x = x_re + i x_im,
  *   y_re = A_re x_re - A_im x_im and y_im = A_re x_im + A_im x_re, formed as four
  *   accumulator sets in one pass over the pattern (each in the order above) and

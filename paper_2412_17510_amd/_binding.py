@@ -87,6 +87,7 @@ for _name in ("mpspmv_csr_dd_complex", "mpspmv_csr_td_complex", "mpspmv_csr_qd_c
               "mpspmv_csr_td_d_complex", "mpspmv_csr_qd_d_complex"):
     _SIGS[_name] = ([_CSR, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int)
 
+_SIGS["mpspmv_csr_dd_noalloc"] = ([_CSR, _P, _P, _P, _P, _P], ctypes.c_int)
 _SIGS["mpvec_dd_sub"] = ([ctypes.c_int64, _P, _P, _P, _P], ctypes.c_int)
 _SIGS["mpkrylov_workspace_bytes"] = ([_CSR, ctypes.POINTER(mp_solve_opts), ctypes.POINTER(ctypes.c_size_t)],
                                      ctypes.c_int)
@@ -436,6 +437,17 @@ mpspmv_csr_dd_d_complex = _spmv_dmat_complex("mpspmv_csr_dd_d_complex", 2)
 mpspmv_csr_td_d_complex = _spmv_dmat_complex("mpspmv_csr_td_d_complex", 3)
 mpspmv_csr_qd_d_complex = _spmv_dmat_complex("mpspmv_csr_qd_d_complex", 4)
 SPMV_D_COMPLEX = {2: mpspmv_csr_dd_d_complex, 3: mpspmv_csr_td_d_complex, 4: mpspmv_csr_qd_d_complex}
+
+def mpspmv_csr_dd_noalloc(A, a, x, y, plan=None, stream=None):
+    """DD y = A x without workspace (C ABI mpspmv_csr_dd_noalloc: x is staged in the
+    library's fixed device array, n_cols <= 1,048,576; overlapping calls race)."""
+    _check_mp(a, 2, A.nnz, "a")
+    _check_mp(x, 2, A.n_cols, "x")
+    _check_mp(y, 2, A.n_rows, "y")
+    _check(_lib.mpspmv_csr_dd_noalloc(ctypes.byref(A.c), _ptr(a), _ptr(x), _ptr(y), _plan_handle(plan),
+                                      _stream_ptr(stream)), "mpspmv_csr_dd_noalloc")
+    return y
+
 
 SPMV = {(2, False): mpspmv_csr_dd, (3, False): mpspmv_csr_td, (4, False): mpspmv_csr_qd,
         (2, True): mpspmv_csr_dd_complex, (3, True): mpspmv_csr_td_complex, (4, True): mpspmv_csr_qd_complex}

@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmpsparse.so")
 
 SOURCES = ["common.cpp", "plan.cpp", "spmv.hip", "krylov.hip", "krylov_mp.hip", "batched.hip", "learned.hip",
-           "transpose.hip", "measure.hip"]
+           "transpose.hip", "measure.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
