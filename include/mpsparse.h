@@ -500,11 +500,26 @@ typedef struct mp_batch_plan mp_batch_plan;
 mp_status mp_batch_plan_create(const mp_csr *A, const int32_t *sys_ptr_host, int32_t nsys, int32_t nrhs,
                                int32_t threads_per_row, void *stream, mp_batch_plan **out);
 
-/* Time the SpMM for every threads-per-row choice on the caller's operands (X read,
- * Y overwritten) and keep the fastest in the plan (*threads_per_row, host, may be
- * NULL).  Synchronises. */
+/* Autotune the batch schedule on the caller's operands (X read, Y overwritten): the
+ * persistent SpMM of the CG step is timed for every threads-per-row choice (each
+ * thread computes nrhs/threads_per_row right-hand sides of one row) and every tile of
+ * (256 / threads_per_row) * {1, 2, 4} rows, and the dot-chunk kernels for the two item
+ * orders (chunks in row order, or the chunks of the largest systems first); the
+ * fastest choices are kept in the plan.  *threads_per_row (host, may be NULL) receives
+ * the chosen mapping.  Allocates temporaries and synchronises. */
 mp_status mp_batch_plan_autotune(mp_batch_plan *plan, const mp_csr *A, const double *a, const double *X, double *Y,
                                  int32_t reps, void *stream, int32_t *threads_per_row);
+
+/* The plan's schedule (host ints, any may be NULL): threads per row, rows per SpMM
+ * tile of the CG step, and the chunk order (0 row order, 1 largest systems first). */
+mp_status mp_batch_plan_schedule(const mp_batch_plan *plan, int32_t *threads_per_row, int32_t *rows_per_tile,
+                                 int32_t *chunk_order);
+
+/* Set the schedule explicitly (instead of autotuning): threads_per_row a power of two
+ * <= nrhs, SpMM tiles of (256 / threads_per_row) * rows_mult rows with rows_mult in
+ * {1, 2, 4}, chunk_order 0 or 1.  Results do not depend on the schedule. */
+mp_status mp_batch_plan_set_schedule(mp_batch_plan *plan, int32_t threads_per_row, int32_t rows_mult,
+                                     int32_t chunk_order);
 
 mp_status mp_batch_plan_destroy(mp_batch_plan *plan);
 
@@ -520,12 +535,18 @@ mp_status mpkrylov_batched_workspace_bytes(const mp_batch_plan *plan, size_t *by
  * DD Jacobi-PCG (opts.precond) for every (system, right-hand side) pair at once.
  * B: right-hand sides, X: in = starting vectors, out = solutions (2*N*nrhs each).
  * Each pair keeps its own DD scalars, stop test (rtol), true-residual confirmation,
- * restarts and iteration limit, exactly as mpkrylov_cg.  One step runs six kernels
- * over all pairs; with use_graph = 1 a chunk of opts.check_every steps is captured
- * once into a hipGraph and replayed (on a private stream ordered after `stream`)
- * until every pair has finished.  info: host array of nsys*nrhs records, pair (s, r)
- * at index s*nrhs + r.  Synchronises `stream`.  Returns MP_OK when every pair
- * converged, else the worst pair status.
+ * restarts and iteration limit, exactly as mpkrylov_cg.  One step is four persistent
+ * kernels over all pairs (the SpMM over row tiles; the (p, q) chunk sums; alpha and the
+ * update of x and r with the (r, z), (r, r) chunk sums; beta, the stop tests and p),
+ * each sized to the device's resident occupancy, its workgroups taking tiles or dot
+ * chunks in the plan's order from one work queue per XCD (a vector-memory atomic
+ * counter each; a workgroup that finds its queue empty takes from the others; no
+ * workgroup ever waits for another).  Every item of a system forms that system's
+ * scalars itself from the chunk sums (the per-system trees).  With use_graph = 1 a
+ * chunk of opts.check_every steps is captured once into a hipGraph and replayed (on a
+ * private stream ordered after `stream`) until every pair has finished.  info: host
+ * array of nsys*nrhs records, pair (s, r) at index s*nrhs + r.  Synchronises `stream`.
+ * Returns MP_OK when every pair converged, else the worst pair status.
  */
 mp_status mpkrylov_cg_batched(const mp_csr *A, const double *a, const double *B, double *X, int32_t nrhs,
                               const mp_solve_opts *opts, const mp_batch_plan *plan, int32_t use_graph, void *ws,

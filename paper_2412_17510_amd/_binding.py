@@ -123,6 +123,8 @@ _SIGS["mp_mpnn_adam_step"] = ([_P, ctypes.c_float, ctypes.c_float, ctypes.c_floa
 _SIGS["mp_batch_plan_create"] = ([_CSR, _P, _I, _I, _I, _P, ctypes.POINTER(_P)], ctypes.c_int)
 _SIGS["mp_batch_plan_autotune"] = ([_P, _CSR, _P, _P, _P, _I, _P, ctypes.POINTER(_I)], ctypes.c_int)
 _SIGS["mp_batch_plan_destroy"] = ([_P], ctypes.c_int)
+_SIGS["mp_batch_plan_set_schedule"] = ([_P, _I, _I, _I], ctypes.c_int)
+_SIGS["mp_batch_plan_schedule"] = ([_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)], ctypes.c_int)
 _SIGS["mpspmm_csr_dd_batched"] = ([_CSR, _P, _P, _P, _I, _P, _P], ctypes.c_int)
 _SIGS["mpkrylov_batched_workspace_bytes"] = ([_P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int)
 _SIGS["mpkrylov_cg_batched"] = ([_CSR, _P, _P, _P, _I, ctypes.POINTER(mp_solve_opts), _P, _I, _P, ctypes.c_size_t,
@@ -786,6 +788,19 @@ def mp_batch_plan_autotune(plan, A, a, X, Y, reps=3, stream=None):
     _check(_lib.mp_batch_plan_autotune(plan.handle, ctypes.byref(A.c), _ptr(a), _ptr(X), _ptr(Y), reps,
                                        _stream_ptr(stream), ctypes.byref(tpr)), "mp_batch_plan_autotune")
     return tpr.value
+
+
+def mp_batch_plan_schedule(plan):
+    """{"threads_per_row", "rows_per_tile", "chunk_order"} of a batch plan (C ABI mp_batch_plan_schedule)."""
+    v = [ctypes.c_int32() for _ in range(3)]
+    _check(_lib.mp_batch_plan_schedule(plan.handle, *[ctypes.byref(x) for x in v]), "mp_batch_plan_schedule")
+    return dict(zip(("threads_per_row", "rows_per_tile", "chunk_order"), (x.value for x in v)))
+
+
+def mp_batch_plan_set_schedule(plan, threads_per_row, rows_mult, chunk_order):
+    """Explicit batch schedule (C ABI mp_batch_plan_set_schedule)."""
+    _check(_lib.mp_batch_plan_set_schedule(plan.handle, int(threads_per_row), int(rows_mult), int(chunk_order)),
+           "mp_batch_plan_set_schedule")
 
 
 def mpspmm_csr_dd_batched(A, a, X, Y, nrhs, plan=None, stream=None):

@@ -16,7 +16,8 @@
 // chunk tree), every pair has its own DD scalars and state, and a pair whose state is
 // not "running" is left untouched by the update kernels -- so each pair's iterates
 // equal those of a separate mpkrylov_cg call with a W = 1 plan, bit for bit.  One
-// step is six kernels over all pairs; a chunk of steps is captured once into a
+// step is four persistent kernels over all pairs, fed by per-XCD work queues (see
+// "persistent step kernels" below); a chunk of steps is captured once into a
 // hipGraph and replayed, the host reading the pair states between replays to
 // confirm converged pairs with their true residuals (and restart those that fail).
 #include <hip/hip_runtime.h>
@@ -46,12 +47,15 @@ struct mp_batch_plan {
     int32_t nsys = 0;
     int32_t nrhs = 0;
     int32_t tpr = 1;          // SpMM threads per row
+    int32_t rows_mult = 1;    // persistent SpMM: tiles of (256 / tpr) * rows_mult rows
+    int32_t chunk_order = 0;  // 0: dot chunks in row order; 1: largest systems first
     int32_t n_chunks = 0;     // dot chunks (<= 4096 rows of one system)
     int32_t max_sys_chunks = 0;
     int32_t *d_sys_ptr = nullptr;
     int32_t *d_sys_chunk = nullptr;   // nsys + 1: first chunk of each system
     int32_t *d_chunk_row = nullptr;   // n_chunks: first row of each chunk
     int32_t *d_chunk_sys = nullptr;   // n_chunks: system of each chunk
+    int32_t *d_chunk_big = nullptr;   // n_chunks: the chunks, largest systems first
     std::vector<int32_t> sys_ptr;
 };
 
@@ -103,16 +107,13 @@ __device__ __forceinline__ int bxcd_block(int b, int nblocks)
 // SpMM
 // ---------------------------------------------------------------------------
 
+// one row of Y = A X for right-hand sides r0 .. r0 + R/TPR - 1
 template <int R, int TPR>
-__global__ __launch_bounds__(256) void k_bspmm(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                               const double *__restrict__ a, int64_t nnz, const double *__restrict__ X,
-                                               double *__restrict__ Y)
+__device__ __forceinline__ void bspmm_row(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                          const double *__restrict__ a, int64_t nnz, const double *__restrict__ X,
+                                          double *__restrict__ Y, int64_t row, int r0)
 {
     constexpr int RPT = R / TPR;
-    const int64_t g = (int64_t)bxcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
-    const int64_t row = g / TPR;
-    if (row >= n) return;
-    const int r0 = (int)(g % TPR) * RPT;
     const int64_t NR = (int64_t)n * R;
     const int32_t b = rp[row], e = rp[row + 1];
     dd_t acc[RPT];
@@ -152,6 +153,17 @@ __global__ __launch_bounds__(256) void k_bspmm(int32_t n, const int32_t *__restr
     }
 #pragma unroll
     for (int q = 0; q < RPT; ++q) bst(Y, NR, row, R, r0 + q, acc[q]);
+}
+
+template <int R, int TPR>
+__global__ __launch_bounds__(256) void k_bspmm(int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                               const double *__restrict__ a, int64_t nnz, const double *__restrict__ X,
+                                               double *__restrict__ Y)
+{
+    const int64_t g = (int64_t)bxcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+    const int64_t row = g / TPR;
+    if (row >= n) return;
+    bspmm_row<R, TPR>(n, rp, ci, a, nnz, X, Y, row, (int)(g % TPR) * (R / TPR));
 }
 
 // ---------------------------------------------------------------------------
@@ -212,20 +224,16 @@ __device__ __forceinline__ ChunkInfo chunk_info(int c, const int32_t *__restrict
     return ch;
 }
 
-// chunk sums of (X1, Y1) and optionally (X2, Y2), every right-hand side
+// chunk sums of (X1, Y1) and optionally (X2, Y2) of chunk c, every right-hand side
 template <int R>
-__global__ __launch_bounds__(BMap<R>::THREADS) void k_bdot2(int32_t n, const double *__restrict__ X1,
-                                                            const double *__restrict__ Y1,
-                                                            const double *__restrict__ X2,
-                                                            const double *__restrict__ Y2, dd_t *__restrict__ part1,
-                                                            dd_t *__restrict__ part2,
-                                                            const int32_t *__restrict__ chunk_row,
-                                                            const int32_t *__restrict__ chunk_sys,
-                                                            const int32_t *__restrict__ sys_ptr)
+__device__ __forceinline__ void bdot_chunk(int32_t n, const double *__restrict__ X1, const double *__restrict__ Y1,
+                                           const double *__restrict__ X2, const double *__restrict__ Y2,
+                                           dd_t *__restrict__ part1, dd_t *__restrict__ part2, int c,
+                                           const int32_t *__restrict__ chunk_row,
+                                           const int32_t *__restrict__ chunk_sys, const int32_t *__restrict__ sys_ptr,
+                                           dd_t (*lds)[R])
 {
     using M = BMap<R>;
-    __shared__ dd_t lds[kBLanes][R];
-    const int c = blockIdx.x;
     const ChunkInfo ch = chunk_info(c, chunk_row, chunk_sys, sys_ptr);
     const int64_t NR = (int64_t)n * R;
     dd_t a1[M::RPT], a2[M::RPT];
@@ -247,6 +255,20 @@ __global__ __launch_bounds__(BMap<R>::THREADS) void k_bdot2(int32_t n, const dou
     }
     bfold<R>(a1, ch.used, lds, part1 + (int64_t)c * R);
     if (X2) bfold<R>(a2, ch.used, lds, part2 + (int64_t)c * R);
+}
+
+template <int R>
+__global__ __launch_bounds__(BMap<R>::THREADS) void k_bdot2(int32_t n, const double *__restrict__ X1,
+                                                            const double *__restrict__ Y1,
+                                                            const double *__restrict__ X2,
+                                                            const double *__restrict__ Y2, dd_t *__restrict__ part1,
+                                                            dd_t *__restrict__ part2,
+                                                            const int32_t *__restrict__ chunk_row,
+                                                            const int32_t *__restrict__ chunk_sys,
+                                                            const int32_t *__restrict__ sys_ptr)
+{
+    __shared__ dd_t lds[kBLanes][R];
+    bdot_chunk<R>(n, X1, Y1, X2, Y2, part1, part2, blockIdx.x, chunk_row, chunk_sys, sys_ptr, lds);
 }
 
 // pairwise tree over the chunk sums [c0, c0+m) of right-hand side r (single workgroup)
@@ -357,59 +379,6 @@ __global__ __launch_bounds__(256) void k_binit(const dd_t *__restrict__ pbb, con
 }
 
 template <int R>
-__global__ __launch_bounds__(256) void k_balpha(const dd_t *__restrict__ ppq, const int32_t *__restrict__ sys_chunk,
-                                                BState *__restrict__ st)
-{
-    __shared__ dd_t P[kBMaxSysChunks];
-    const int s = blockIdx.x;
-    const int c0 = sys_chunk[s], m = sys_chunk[s + 1] - c0;
-    for (int r = 0; r < R; ++r) {
-        if (st[s * R + r].done != B_RUN) continue;   // uniform in the workgroup
-        const dd_t pq = bpair_tree<R>(ppq, c0, m, r, P);
-        if (threadIdx.x == 0) {
-            BState &q = st[s * R + r];
-            q.pq = pq;
-            if (!(pq.c[0] > 0.0) || !isfinite(pq.c[0]))
-                q.done = B_BROKE_DOWN;
-            else
-                q.alpha = dd_div(q.rho, pq);
-        }
-        __syncthreads();
-    }
-}
-
-template <int R>
-__global__ __launch_bounds__(256) void k_bbeta(const dd_t *__restrict__ prz, const dd_t *__restrict__ prr,
-                                               const int32_t *__restrict__ sys_chunk, int32_t max_iter,
-                                               BState *__restrict__ st)
-{
-    __shared__ dd_t P[kBMaxSysChunks];
-    const int s = blockIdx.x;
-    const int c0 = sys_chunk[s], m = sys_chunk[s + 1] - c0;
-    for (int r = 0; r < R; ++r) {
-        if (st[s * R + r].done != B_RUN) continue;
-        const dd_t rz = bpair_tree<R>(prz, c0, m, r, P);
-        const dd_t rr = bpair_tree<R>(prr, c0, m, r, P);
-        if (threadIdx.x == 0) {
-            BState &q = st[s * R + r];
-            q.iters += 1;
-            q.rr = rr;
-            if (!isfinite(rr.c[0]) || !isfinite(rz.c[0])) {
-                q.done = B_BROKE_DOWN;
-            } else {
-                q.beta = dd_div(rz, q.rho);
-                q.rho = rz;
-                if (dd_le(rr, q.tol2))
-                    q.done = B_RECURRENCE_MET;
-                else if (q.iters >= max_iter)
-                    q.done = B_ITER_LIMIT;
-            }
-        }
-        __syncthreads();
-    }
-}
-
-template <int R>
 __global__ __launch_bounds__(256) void k_bconfirm(const dd_t *__restrict__ prr, const int32_t *__restrict__ sys_chunk,
                                                   BState *__restrict__ st)
 {
@@ -470,95 +439,324 @@ __global__ __launch_bounds__(256) void k_bexit(const dd_t *__restrict__ prr, con
 // per-chunk update kernels
 // ---------------------------------------------------------------------------
 
-// x += alpha p; r -= alpha q; chunk sums of (r, z), (r, r) with z = M^-1 r -- running
-// pairs.  z is not stored: k_bp forms it again from r by the same operation.
+// ---------------------------------------------------------------------------
+// persistent step kernels
+//
+// One CG step is four launches: the SpMM over row tiles, the (p, q) chunk sums, the
+// update (alpha, x, r and the (r, z), (r, r) chunk sums) and the p step (beta, stop
+// tests, p).  Each is a persistent kernel sized to the device's resident occupancy
+// whose workgroups take work items -- row tiles, or dot chunks in the plan's order --
+// from 8 queues, one per XCD: queue x holds the contiguous range
+// [x floor(n/8) + min(x, n mod 8), ...) of the item order, and a workgroup launched on
+// XCD x (block index mod 8) takes items from queue x through a vector-memory atomic
+// counter, then from the other queues in turn.  No workgroup waits for another, every
+// item is taken exactly once, and a workgroup exits after one failed take per queue.
+// The per-system scalars (alpha from the (p, q) sums; beta, ||r||^2 and the stop tests
+// from the (r, z), (r, r) sums) are formed by every item of the system (the same
+// pairwise trees over the system's chunk sums, so the same values), and the system's first chunk
+// writes the pair states, double-buffered between the update kernel (reads sa, writes
+// sb) and the p kernel (reads sb, writes sa).  Each kernel clears the counters of the
+// kernel that follows it in the step (which cannot start before this one ends).
+// ---------------------------------------------------------------------------
+
+constexpr int kQueues = 8;
+
+struct BQueue {
+    int32_t *cnt;            // this kernel's kQueues counters
+    int32_t *cnt_next;       // the next kernel's counters, cleared by this kernel
+    const int32_t *order;    // item order (NULL: natural)
+    int32_t n_items;
+};
+
+__device__ __forceinline__ int32_t bq_begin(int32_t n, int x)
+{
+    return x * (n / kQueues) + (x < n % kQueues ? x : n % kQueues);
+}
+
+// thread 0 only: the next item for this workgroup, or -1; probe = queues exhausted
+__device__ __forceinline__ int32_t bq_next(const BQueue &Q, int &probe)
+{
+    const int home = blockIdx.x & (kQueues - 1);
+    while (probe < kQueues) {
+        const int qx = (home + probe) & (kQueues - 1);
+        const int32_t b = bq_begin(Q.n_items, qx), e = bq_begin(Q.n_items, qx + 1);
+        const int32_t k = atomicAdd(&Q.cnt[qx], 1);
+        if (b + k < e) return Q.order ? Q.order[b + k] : b + k;
+        ++probe;
+    }
+    return -1;
+}
+
+// every thread: the workgroup's next item (-1 when none is left)
+__device__ __forceinline__ int32_t bq_take(const BQueue &Q, int &probe, int32_t *s_item)
+{
+    if (threadIdx.x == 0) *s_item = bq_next(Q, probe);
+    __syncthreads();
+    const int32_t it = *s_item;
+    __syncthreads();
+    return it;
+}
+
+__device__ __forceinline__ void bq_clear_next(const BQueue &Q)
+{
+    if (blockIdx.x == 0 && threadIdx.x < kQueues) Q.cnt_next[threadIdx.x] = 0;
+}
+
+__global__ __launch_bounds__(64) void k_bfill_i32(int32_t *__restrict__ v, int n, int32_t val)
+{
+    for (int i = threadIdx.x; i < n; i += 64) v[i] = val;
+}
+
+__device__ __forceinline__ dd_t bshfl_down(const dd_t &v, int d)
+{
+    dd_t r;
+    r.c[0] = __shfl_down(v.c[0], d, 64);
+    r.c[1] = __shfl_down(v.c[1], d, 64);
+    return r;
+}
+
+// out[r] = the pairwise tree of part[(c0 + i) * R + r], i < m (bpair_tree's order), for
+// every r with want[r]; all threads return after a barrier.  m <= 64: wavefront r alone,
+// by lane shuffles (level s: lane l, a multiple of 2s, adds lane l + s when l + s < m);
+// otherwise through LDS, one right-hand side after the other.
 template <int R>
-__global__ __launch_bounds__(BMap<R>::THREADS) void k_bupdate(int32_t n, double *__restrict__ X,
-                                                              double *__restrict__ Rv,
-                                                              const double *__restrict__ P,
-                                                              const double *__restrict__ Q,
-                                                              const double *__restrict__ minv,
-                                                              dd_t *__restrict__ prz, dd_t *__restrict__ prr,
-                                                              const int32_t *__restrict__ chunk_row,
-                                                              const int32_t *__restrict__ chunk_sys,
-                                                              const int32_t *__restrict__ sys_ptr,
-                                                              const BState *__restrict__ st)
+__device__ __forceinline__ void bq_trees(const dd_t *__restrict__ part, int c0, int m, const int *want, dd_t *out,
+                                         dd_t *P)
+{
+    const int t = threadIdx.x;
+    if (m <= 64) {
+        const int w = t >> 6, l = t & 63;
+        if (w < R && want[w]) {
+            dd_t v = l < m ? part[(int64_t)(c0 + l) * R + w] : bz();
+            for (int s = 1; s < m; s <<= 1) {
+                const dd_t o = bshfl_down(v, s);
+                if ((l & (2 * s - 1)) == 0 && l + s < m) v = dd_add(v, o);
+            }
+            if (l == 0) out[w] = v;
+        }
+        __syncthreads();
+        return;
+    }
+    for (int r = 0; r < R; ++r) {
+        if (!want[r]) continue;   // uniform: want is in LDS
+        for (int i = t; i < m; i += blockDim.x) P[i] = part[(int64_t)(c0 + i) * R + r];
+        __syncthreads();
+        for (int s = 1; s < m; s <<= 1) {
+            for (int i = t; (int64_t)i * 2 * s + s < m; i += blockDim.x) P[i * 2 * s] = dd_add(P[i * 2 * s], P[i * 2 * s + s]);
+            __syncthreads();
+        }
+        if (t == 0) out[r] = P[0];
+        __syncthreads();
+    }
+}
+
+// Y = A X over row tiles of (256 / TPR) * U rows
+template <int R, int TPR, int U>
+__global__ __launch_bounds__(256) void k_bq_spmm(int32_t n, const int32_t *__restrict__ rp,
+                                                 const int32_t *__restrict__ ci, const double *__restrict__ a,
+                                                 int64_t nnz, const double *__restrict__ X, double *__restrict__ Y,
+                                                 BQueue Q)
+{
+    constexpr int RW = 256 / TPR;   // rows of one pass of the workgroup
+    __shared__ int32_t s_item;
+    bq_clear_next(Q);
+    int probe = 0;
+    for (;;) {
+        const int32_t item = bq_take(Q, probe, &s_item);
+        if (item < 0) break;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t row = (int64_t)item * (RW * U) + u * RW + threadIdx.x / TPR;
+            if (row < n) bspmm_row<R, TPR>(n, rp, ci, a, nnz, X, Y, row, (int)(threadIdx.x % TPR) * (R / TPR));
+        }
+    }
+}
+
+// chunk sums of (P, Q) over dot chunks
+template <int R>
+__global__ __launch_bounds__(BMap<R>::THREADS) void k_bq_pq(int32_t n, const double *__restrict__ P,
+                                                            const double *__restrict__ Qv, dd_t *__restrict__ ppq,
+                                                            const int32_t *__restrict__ chunk_row,
+                                                            const int32_t *__restrict__ chunk_sys,
+                                                            const int32_t *__restrict__ sys_ptr, BQueue Q)
+{
+    __shared__ dd_t lds[kBLanes][R];
+    __shared__ int32_t s_item;
+    bq_clear_next(Q);
+    int probe = 0;
+    for (;;) {
+        const int32_t c = bq_take(Q, probe, &s_item);
+        if (c < 0) break;
+        bdot_chunk<R>(n, P, Qv, nullptr, nullptr, ppq, nullptr, c, chunk_row, chunk_sys, sys_ptr, lds);
+    }
+}
+
+// alpha = rho / (p, q) per running pair (breakdown unless (p, q) > 0 and finite), then
+// x += alpha p, r -= alpha q and the chunk sums of (r, z), (r, r) with z = M^-1 r (z is
+// not stored: k_bq_p forms it again from r by the same operation), per dot chunk
+template <int R>
+__global__ __launch_bounds__(BMap<R>::THREADS) void k_bq_upd(int32_t n, double *__restrict__ X,
+                                                             double *__restrict__ Rv, const double *__restrict__ P,
+                                                             const double *__restrict__ Qv,
+                                                             const double *__restrict__ minv,
+                                                             const dd_t *__restrict__ ppq, dd_t *__restrict__ prz,
+                                                             dd_t *__restrict__ prr,
+                                                             const int32_t *__restrict__ chunk_row,
+                                                             const int32_t *__restrict__ chunk_sys,
+                                                             const int32_t *__restrict__ sys_ptr,
+                                                             const int32_t *__restrict__ sys_chunk,
+                                                             const BState *__restrict__ sa, BState *__restrict__ sb,
+                                                             BQueue Q)
 {
     using M = BMap<R>;
     __shared__ dd_t lds[kBLanes][R];
-    __shared__ int s_any;
-    const int c = blockIdx.x;
-    const ChunkInfo ch = chunk_info(c, chunk_row, chunk_sys, sys_ptr);
+    __shared__ dd_t P_[kBMaxSysChunks];
+    __shared__ dd_t s_pq[R], s_alpha[R];
+    __shared__ int s_want[R], s_run[R];
+    __shared__ int32_t s_item;
+    bq_clear_next(Q);
+    int probe = 0;
     const int64_t NR = (int64_t)n * R;
-    if (threadIdx.x == 0) {
+    for (;;) {
+        const int32_t c = bq_take(Q, probe, &s_item);
+        if (c < 0) break;
+        const ChunkInfo ch = chunk_info(c, chunk_row, chunk_sys, sys_ptr);
+        const int c0 = sys_chunk[ch.sys], m = sys_chunk[ch.sys + 1] - c0;
+        if (threadIdx.x < R) s_want[threadIdx.x] = sa[ch.sys * R + threadIdx.x].done == B_RUN;
+        __syncthreads();
+        bq_trees<R>(ppq, c0, m, s_want, s_pq, P_);
+        if (threadIdx.x < R) {
+            const int r = threadIdx.x;
+            BState q = sa[ch.sys * R + r];
+            int run = 0;
+            if (q.done == B_RUN) {
+                const dd_t pq = s_pq[r];
+                q.pq = pq;
+                if (!(pq.c[0] > 0.0) || !isfinite(pq.c[0])) {
+                    q.done = B_BROKE_DOWN;
+                } else {
+                    q.alpha = dd_div(q.rho, pq);
+                    run = 1;
+                }
+            }
+            s_run[r] = run;
+            s_alpha[r] = q.alpha;
+            if (c == c0) sb[ch.sys * R + r] = q;
+        }
+        __syncthreads();
         int any = 0;
-        for (int r = 0; r < R; ++r) any |= st[ch.sys * R + r].done == B_RUN;
-        s_any = any;
-    }
-    __syncthreads();
-    if (!s_any) return;   // uniform in the workgroup
-    bool run[M::RPT];
-    dd_t alpha[M::RPT], arz[M::RPT], arr[M::RPT];
 #pragma unroll
-    for (int i = 0; i < M::RPT; ++i) {
-        run[i] = st[ch.sys * R + M::rhs(i)].done == B_RUN;
-        alpha[i] = st[ch.sys * R + M::rhs(i)].alpha;
-        arz[i] = arr[i] = bz();
-    }
-    bool first = true;
-    for (int64_t k = ch.row0 + M::lane(); k < ch.end; k += kBLanes) {
-        const double mi = minv ? minv[k] : 1.0;
+        for (int r = 0; r < R; ++r) any |= s_run[r];
+        if (!any) continue;   // uniform in the workgroup
+        bool run[M::RPT];
+        dd_t alpha[M::RPT], arz[M::RPT], arr[M::RPT];
 #pragma unroll
         for (int i = 0; i < M::RPT; ++i) {
-            if (!run[i]) continue;
-            const int r = M::rhs(i);
-            const dd_t xk = bld(X, NR, k, R, r), pk = bld(P, NR, k, R, r);
-            const dd_t rk0 = bld(Rv, NR, k, R, r), qk = bld(Q, NR, k, R, r);
-            bst(X, NR, k, R, r, dd_add(xk, dd_mul(alpha[i], pk)));
-            const dd_t rk = dd_add(rk0, mp_neg(dd_mul(alpha[i], qk)));
-            bst(Rv, NR, k, R, r, rk);
-            const dd_t zk = minv ? dd_mul_d(rk, mi) : rk;
-            const dd_t p1 = dd_mul(rk, zk), p2 = dd_mul(rk, rk);
-            arz[i] = first ? p1 : dd_add(arz[i], p1);
-            arr[i] = first ? p2 : dd_add(arr[i], p2);
+            run[i] = s_run[M::rhs(i)] != 0;
+            alpha[i] = s_alpha[M::rhs(i)];
+            arz[i] = arr[i] = bz();
         }
-        first = false;
+        bool first = true;
+        for (int64_t k = ch.row0 + M::lane(); k < ch.end; k += kBLanes) {
+            const double mi = minv ? minv[k] : 1.0;
+#pragma unroll
+            for (int i = 0; i < M::RPT; ++i) {
+                if (!run[i]) continue;
+                const int r = M::rhs(i);
+                const dd_t xk = bld(X, NR, k, R, r), pk = bld(P, NR, k, R, r);
+                const dd_t rk0 = bld(Rv, NR, k, R, r), qk = bld(Qv, NR, k, R, r);
+                bst(X, NR, k, R, r, dd_add(xk, dd_mul(alpha[i], pk)));
+                const dd_t rk = dd_add(rk0, mp_neg(dd_mul(alpha[i], qk)));
+                bst(Rv, NR, k, R, r, rk);
+                const dd_t zk = minv ? dd_mul_d(rk, mi) : rk;
+                const dd_t p1 = dd_mul(rk, zk), p2 = dd_mul(rk, rk);
+                arz[i] = first ? p1 : dd_add(arz[i], p1);
+                arr[i] = first ? p2 : dd_add(arr[i], p2);
+            }
+            first = false;
+        }
+        bfold<R>(arz, ch.used, lds, prz + (int64_t)c * R);
+        bfold<R>(arr, ch.used, lds, prr + (int64_t)c * R);
     }
-    bfold<R>(arz, ch.used, lds, prz + (int64_t)c * R);
-    bfold<R>(arr, ch.used, lds, prr + (int64_t)c * R);
 }
 
-// p = z + beta p with z = M^-1 r (minv NULL: z = r) -- running pairs
+// iterations + 1, ||r||^2, beta = (r, z) / rho and the stop tests per running pair,
+// then p = z + beta p for the pairs still running, per dot chunk
 template <int R>
-__global__ __launch_bounds__(BMap<R>::THREADS) void k_bp(int32_t n, const double *__restrict__ Rv,
-                                                         const double *__restrict__ minv, double *__restrict__ P,
-                                                         const int32_t *__restrict__ chunk_row,
-                                                         const int32_t *__restrict__ chunk_sys,
-                                                         const int32_t *__restrict__ sys_ptr,
-                                                         const BState *__restrict__ st)
+__global__ __launch_bounds__(BMap<R>::THREADS) void k_bq_p(int32_t n, const double *__restrict__ Rv,
+                                                           const double *__restrict__ minv, double *__restrict__ P,
+                                                           const dd_t *__restrict__ prz, const dd_t *__restrict__ prr,
+                                                           const int32_t *__restrict__ chunk_row,
+                                                           const int32_t *__restrict__ chunk_sys,
+                                                           const int32_t *__restrict__ sys_ptr,
+                                                           const int32_t *__restrict__ sys_chunk, int32_t max_iter,
+                                                           const BState *__restrict__ sb, BState *__restrict__ sa,
+                                                           BQueue Q)
 {
     using M = BMap<R>;
-    const int c = blockIdx.x;
-    const ChunkInfo ch = chunk_info(c, chunk_row, chunk_sys, sys_ptr);
+    __shared__ dd_t P_[kBMaxSysChunks];
+    __shared__ dd_t s_rz[R], s_rr[R], s_beta[R];
+    __shared__ int s_want[R], s_run[R];
+    __shared__ int32_t s_item;
+    bq_clear_next(Q);
+    int probe = 0;
     const int64_t NR = (int64_t)n * R;
-    bool run[M::RPT];
-    dd_t beta[M::RPT];
+    for (;;) {
+        const int32_t c = bq_take(Q, probe, &s_item);
+        if (c < 0) break;
+        const ChunkInfo ch = chunk_info(c, chunk_row, chunk_sys, sys_ptr);
+        const int c0 = sys_chunk[ch.sys], m = sys_chunk[ch.sys + 1] - c0;
+        if (threadIdx.x < R) s_want[threadIdx.x] = sb[ch.sys * R + threadIdx.x].done == B_RUN;
+        __syncthreads();
+        bq_trees<R>(prz, c0, m, s_want, s_rz, P_);
+        bq_trees<R>(prr, c0, m, s_want, s_rr, P_);
+        if (threadIdx.x < R) {
+            const int r = threadIdx.x;
+            BState q = sb[ch.sys * R + r];
+            if (q.done == B_RUN) {
+                const dd_t rz = s_rz[r], rr = s_rr[r];
+                q.iters += 1;
+                q.rr = rr;
+                if (!isfinite(rr.c[0]) || !isfinite(rz.c[0])) {
+                    q.done = B_BROKE_DOWN;
+                } else {
+                    q.beta = dd_div(rz, q.rho);
+                    q.rho = rz;
+                    if (dd_le(rr, q.tol2))
+                        q.done = B_RECURRENCE_MET;
+                    else if (q.iters >= max_iter)
+                        q.done = B_ITER_LIMIT;
+                }
+            }
+            s_run[r] = q.done == B_RUN;
+            s_beta[r] = q.beta;
+            if (c == c0) sa[ch.sys * R + r] = q;
+        }
+        __syncthreads();
+        int any = 0;
 #pragma unroll
-    for (int i = 0; i < M::RPT; ++i) {
-        run[i] = st[ch.sys * R + M::rhs(i)].done == B_RUN;
-        beta[i] = st[ch.sys * R + M::rhs(i)].beta;
-    }
-    for (int64_t k = ch.row0 + M::lane(); k < ch.end; k += kBLanes) {
-        const double mi = minv ? minv[k] : 1.0;
+        for (int r = 0; r < R; ++r) any |= s_run[r];
+        if (!any) continue;   // uniform in the workgroup
+        bool run[M::RPT];
+        dd_t beta[M::RPT];
 #pragma unroll
         for (int i = 0; i < M::RPT; ++i) {
-            const int r = M::rhs(i);
-            if (run[i]) {
-                const dd_t rk = bld(Rv, NR, k, R, r);
-                const dd_t zk = minv ? dd_mul_d(rk, mi) : rk;
-                bst(P, NR, k, R, r, dd_add(zk, dd_mul(beta[i], bld(P, NR, k, R, r))));
+            run[i] = s_run[M::rhs(i)] != 0;
+            beta[i] = s_beta[M::rhs(i)];
+        }
+        for (int64_t k = ch.row0 + M::lane(); k < ch.end; k += kBLanes) {
+            const double mi = minv ? minv[k] : 1.0;
+#pragma unroll
+            for (int i = 0; i < M::RPT; ++i) {
+                const int r = M::rhs(i);
+                if (run[i]) {
+                    const dd_t rk = bld(Rv, NR, k, R, r);
+                    const dd_t zk = minv ? dd_mul_d(rk, mi) : rk;
+                    bst(P, NR, k, R, r, dd_add(zk, dd_mul(beta[i], bld(P, NR, k, R, r))));
+                }
             }
         }
+        __syncthreads();   // s_run / s_beta are rewritten by the next item
     }
 }
 
@@ -620,6 +818,7 @@ void bplan_free(mp_batch_plan *p)
     if (p->d_sys_chunk) (void)hipFree(p->d_sys_chunk);
     if (p->d_chunk_row) (void)hipFree(p->d_chunk_row);
     if (p->d_chunk_sys) (void)hipFree(p->d_chunk_sys);
+    if (p->d_chunk_big) (void)hipFree(p->d_chunk_big);
     delete p;
 }
 
@@ -639,8 +838,85 @@ size_t batch_ws_bytes(const mp_batch_plan *p)
     size_t b = 4 * bal(vec);                                          // R, Z, P, Q
     b += bal(sizeof(double) * (size_t)p->n_rows);                     // minv
     b += 3 * bal(sizeof(dd_t) * (size_t)p->n_chunks * p->nrhs);       // chunk sums
-    b += bal(sizeof(BState) * (size_t)p->nsys * p->nrhs);             // pair states
+    b += 2 * bal(sizeof(BState) * (size_t)p->nsys * p->nrhs);         // pair states (double-buffered)
+    b += bal(sizeof(int32_t) * 4 * kQueues);                          // queue counters of the step kernels
     return b;
+}
+
+// resident workgroups of a kernel on the current device (at least one per compute unit)
+template <typename F>
+int resident_grid(F kernel, int threads)
+{
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess || per < 1) per = 1;
+    return cus * per;
+}
+
+// grid <= 0: the kernel's resident workgroups (an occupancy query: not under capture)
+template <int R, int TPR, int U>
+mp_status launch_bq_spmm_t(const mp_csr *A, const double *a, const double *X, double *Y, int32_t *cnt,
+                           int32_t *cnt_next, int grid, hipStream_t s)
+{
+    const int rows = (256 / TPR) * U;
+    BQueue Q{cnt, cnt_next, nullptr, (int32_t)(((int64_t)A->n_rows + rows - 1) / rows)};
+    if (Q.n_items == 0) return MP_OK;
+    if (grid <= 0) grid = resident_grid(k_bq_spmm<R, TPR, U>, 256);
+    if (grid > Q.n_items) grid = Q.n_items;
+    hipLaunchKernelGGL((k_bq_spmm<R, TPR, U>), dim3(grid), dim3(256), 0, s, A->n_rows, A->row_ptr, A->col_idx, a,
+                       A->nnz, X, Y, Q);
+    MP_HIP_TRY(hipGetLastError());
+    return MP_OK;
+}
+
+template <int R, int TPR>
+mp_status launch_bq_spmm_u(int U, const mp_csr *A, const double *a, const double *X, double *Y, int32_t *cnt,
+                           int32_t *cnt_next, int grid, hipStream_t s)
+{
+    switch (U) {
+        case 1: return launch_bq_spmm_t<R, TPR, 1>(A, a, X, Y, cnt, cnt_next, grid, s);
+        case 2: return launch_bq_spmm_t<R, TPR, 2>(A, a, X, Y, cnt, cnt_next, grid, s);
+        case 4: return launch_bq_spmm_t<R, TPR, 4>(A, a, X, Y, cnt, cnt_next, grid, s);
+        default: return fail(MP_ERR_INVALID_ARG, "rows multiple must be 1, 2 or 4 (got %d)", U);
+    }
+}
+
+// persistent SpMM of the CG step: tiles of (256 / tpr) * U rows from the queues
+template <int R>
+mp_status launch_bq_spmm(int tpr, int U, const mp_csr *A, const double *a, const double *X, double *Y, int32_t *cnt,
+                         int32_t *cnt_next, hipStream_t s, int grid = 0)
+{
+    if (tpr == 1) return launch_bq_spmm_u<R, 1>(U, A, a, X, Y, cnt, cnt_next, grid, s);
+    if (tpr == 2 && R >= 2) return launch_bq_spmm_u<R, (R >= 2 ? 2 : 1)>(U, A, a, X, Y, cnt, cnt_next, grid, s);
+    if (tpr == 4 && R >= 4) return launch_bq_spmm_u<R, (R >= 4 ? 4 : 1)>(U, A, a, X, Y, cnt, cnt_next, grid, s);
+    if (tpr == 8 && R >= 8) return launch_bq_spmm_u<R, (R >= 8 ? 8 : 1)>(U, A, a, X, Y, cnt, cnt_next, grid, s);
+    return fail(MP_ERR_INVALID_ARG, "invalid threads-per-row %d for %d right-hand sides", tpr, R);
+}
+
+template <int R, int TPR>
+int bq_spmm_grid_u(int U)
+{
+    switch (U) {
+        case 1: return resident_grid(k_bq_spmm<R, TPR, 1>, 256);
+        case 2: return resident_grid(k_bq_spmm<R, TPR, 2>, 256);
+        default: return resident_grid(k_bq_spmm<R, TPR, 4>, 256);
+    }
+}
+
+template <int R>
+int bq_spmm_grid(int tpr, int U)
+{
+    if (tpr == 2 && R >= 2) return bq_spmm_grid_u<R, (R >= 2 ? 2 : 1)>(U);
+    if (tpr == 4 && R >= 4) return bq_spmm_grid_u<R, (R >= 4 ? 4 : 1)>(U);
+    if (tpr == 8 && R >= 8) return bq_spmm_grid_u<R, (R >= 8 ? 8 : 1)>(U);
+    return bq_spmm_grid_u<R, 1>(U);
+}
+
+template <int R>
+BQueue chunk_queue(const mp_batch_plan *p, int32_t *cnt, int32_t *cnt_next)
+{
+    return BQueue{cnt, cnt_next, p->chunk_order ? p->d_chunk_big : nullptr, p->n_chunks};
 }
 
 // Batched CG driver: one instance per call.
@@ -654,7 +930,11 @@ struct BatchCG {
     double *Rv, *Z, *P, *Q, *minv;
     dd_t *part[3];
     BState *st;
+    BState *st2;     // the second buffer of the pair states inside a step
+    int32_t *cnt;    // queue counters: SpMM, (p, q) sums, update, p step
     unsigned vblocks;
+    int grid_c;      // resident workgroups of the chunk kernels
+    int grid_s;      // resident workgroups of the plan's SpMM kernel
 
     mp_status launched()
     {
@@ -668,18 +948,21 @@ struct BatchCG {
                            p2,
                            p->d_chunk_row, p->d_chunk_sys, p->d_sys_ptr);
     }
-    // one CG step for every running pair
+    // one CG step for every running pair: four persistent kernels
     mp_status step(double *X, int max_iter)
     {
-        mp_status stt = spmm(P, Q);
+        int32_t *c0 = cnt, *c1 = cnt + kQueues, *c2 = cnt + 2 * kQueues, *c3 = cnt + 3 * kQueues;
+        mp_status stt = launch_bq_spmm<R>(p->tpr, p->rows_mult, A, a, P, Q, c0, c1, s, grid_s);
         if (stt != MP_OK) return stt;
-        dot2(P, Q, nullptr, nullptr, part[0], nullptr);
-        hipLaunchKernelGGL(k_balpha<R>, dim3(p->nsys), dim3(256), 0, s, part[0], p->d_sys_chunk, st);
-        hipLaunchKernelGGL(k_bupdate<R>, dim3(p->n_chunks), dim3(BMap<R>::THREADS), 0, s, A->n_rows, X, Rv, P, Q, minv,
-                           part[1], part[2], p->d_chunk_row, p->d_chunk_sys, p->d_sys_ptr, st);
-        hipLaunchKernelGGL(k_bbeta<R>, dim3(p->nsys), dim3(256), 0, s, part[1], part[2], p->d_sys_chunk, max_iter, st);
-        hipLaunchKernelGGL(k_bp<R>, dim3(p->n_chunks), dim3(BMap<R>::THREADS), 0, s, A->n_rows, Rv, minv, P,
-                           p->d_chunk_row, p->d_chunk_sys, p->d_sys_ptr, st);
+        const int g = grid_c < p->n_chunks ? grid_c : p->n_chunks;
+        hipLaunchKernelGGL(k_bq_pq<R>, dim3(g), dim3(BMap<R>::THREADS), 0, s, A->n_rows, P, Q, part[0],
+                           p->d_chunk_row, p->d_chunk_sys, p->d_sys_ptr, chunk_queue<R>(p, c1, c2));
+        hipLaunchKernelGGL(k_bq_upd<R>, dim3(g), dim3(BMap<R>::THREADS), 0, s, A->n_rows, X, Rv, P, Q, minv, part[0],
+                           part[1], part[2], p->d_chunk_row, p->d_chunk_sys, p->d_sys_ptr, p->d_sys_chunk, st, st2,
+                           chunk_queue<R>(p, c2, c3));
+        hipLaunchKernelGGL(k_bq_p<R>, dim3(g), dim3(BMap<R>::THREADS), 0, s, A->n_rows, Rv, minv, P, part[1], part[2],
+                           p->d_chunk_row, p->d_chunk_sys, p->d_sys_ptr, p->d_sys_chunk, max_iter, st2, st,
+                           chunk_queue<R>(p, c3, c0));
         return launched();
     }
     mp_status true_residual(const double *B, const double *X, int want)
@@ -719,6 +1002,14 @@ mp_status run_batched(const mp_csr *A, const double *a, const double *B, double 
         w += bal(sizeof(dd_t) * (size_t)p->n_chunks * R);
     }
     S.st = reinterpret_cast<BState *>(w);
+    w += bal(sizeof(BState) * (size_t)p->nsys * R);
+    S.st2 = reinterpret_cast<BState *>(w);
+    w += bal(sizeof(BState) * (size_t)p->nsys * R);
+    S.cnt = reinterpret_cast<int32_t *>(w);
+    S.grid_c = std::min(resident_grid(k_bq_upd<R>, BMap<R>::THREADS),
+                        std::min(resident_grid(k_bq_p<R>, BMap<R>::THREADS),
+                                 resident_grid(k_bq_pq<R>, BMap<R>::THREADS)));
+    S.grid_s = bq_spmm_grid<R>(p->tpr, p->rows_mult);
     const int npairs = p->nsys * R;
     const bool jacobi = o->precond == MP_PRECOND_JACOBI;
 
@@ -763,6 +1054,8 @@ mp_status run_batched(const mp_csr *A, const double *a, const double *B, double 
     }
     const double *minv = jacobi ? S.minv : nullptr;
     S.minv = const_cast<double *>(minv);
+    hipLaunchKernelGGL(k_bfill_i32, dim3(1), dim3(64), 0, s, S.cnt, 4 * kQueues, 0);
+    BST(S.launched());
     BST(S.true_residual(B, X, -1));
     hipLaunchKernelGGL(k_bprecond_copy<R>, dim3(S.vblocks), dim3(256), 0, s, A->n_rows, minv, S.Rv, S.Z, S.P,
                        p->d_sys_ptr, p->nsys, S.st, -1);
@@ -897,11 +1190,22 @@ mp_status mp_batch_plan_create(const mp_csr *A, const int32_t *sys_ptr_host, int
     }
     sys_chunk[nsys] = (int32_t)chunk_row.size();
     p->n_chunks = (int32_t)chunk_row.size();
+    // the alternative item order of the chunk kernels: systems by decreasing chunk count
+    // (ties by index), each system's chunks in row order
+    std::vector<int32_t> by_size((size_t)nsys), chunk_big;
+    for (int32_t q = 0; q < nsys; ++q) by_size[q] = q;
+    std::stable_sort(by_size.begin(), by_size.end(), [&](int32_t x, int32_t y) {
+        return sys_chunk[x + 1] - sys_chunk[x] > sys_chunk[y + 1] - sys_chunk[y];
+    });
+    chunk_big.reserve(chunk_row.size());
+    for (int32_t q : by_size)
+        for (int32_t c = sys_chunk[q]; c < sys_chunk[q + 1]; ++c) chunk_big.push_back(c);
     hipStream_t s = static_cast<hipStream_t>(stream);
     st = bupload(p->sys_ptr, &p->d_sys_ptr, s);
     if (st == MP_OK) st = bupload(sys_chunk, &p->d_sys_chunk, s);
     if (st == MP_OK) st = bupload(chunk_row, &p->d_chunk_row, s);
     if (st == MP_OK) st = bupload(chunk_sys, &p->d_chunk_sys, s);
+    if (st == MP_OK) st = bupload(chunk_big, &p->d_chunk_big, s);
     int32_t *d_bad = nullptr;
     int32_t h_bad = INT32_MAX;
     if (st == MP_OK) {
@@ -941,33 +1245,137 @@ mp_status mp_batch_plan_autotune(mp_batch_plan *plan, const mp_csr *A, const dou
     clear_error();
     if (!plan || !A || (A->nnz > 0 && (!a || !X || !Y))) return fail(MP_ERR_INVALID_ARG, "NULL argument");
     if (plan->n_rows != A->n_rows || plan->nnz != A->nnz) return fail(MP_ERR_INVALID_ARG, "plan does not match A");
+    if (reps < 1) reps = 3;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipEvent_t e0, e1;
-    MP_HIP_TRY(hipEventCreate(&e0));
-    MP_HIP_TRY(hipEventCreate(&e1));
+    // two counter sets, used alternately (each launch clears the other)
+    int32_t *cnt = nullptr;
+    dd_t *part = nullptr;
+    MP_HIP_TRY(hipMalloc(reinterpret_cast<void **>(&cnt), sizeof(int32_t) * 2 * kQueues));
+    hipError_t he = hipMalloc(reinterpret_cast<void **>(&part), sizeof(dd_t) * (size_t)plan->n_chunks * plan->nrhs);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (he == hipSuccess) he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    mp_status st = he == hipSuccess ? MP_OK : hip_fail(he, "batched autotune set-up");
+    int flip = 0;
+    auto timed = [&](auto launch, float *ms) -> mp_status {
+        hipLaunchKernelGGL(k_bfill_i32, dim3(1), dim3(64), 0, s, cnt, 2 * kQueues, 0);
+        flip = 0;
+        mp_status t = launch();   // warm-up
+        hipError_t e = hipEventRecord(e0, s);
+        for (int r = 0; t == MP_OK && e == hipSuccess && r < reps; ++r) t = launch();
+        if (t == MP_OK && e == hipSuccess) e = hipEventRecord(e1, s);
+        if (t == MP_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+        if (t == MP_OK && e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+        if (t == MP_OK && e != hipSuccess) t = hip_fail(e, "batched autotune timing");
+        return t;
+    };
+    // the persistent SpMM: threads per row x rows per tile
     float best = -1.f;
-    int best_tpr = plan->tpr;
-    mp_status st = MP_OK;
+    int best_tpr = plan->tpr, best_u = plan->rows_mult;
     for (int tpr = 1; tpr <= plan->nrhs && st == MP_OK; tpr <<= 1) {
-        st = launch_bspmm(plan->nrhs, tpr, A, a, X, Y, s);
-        if (st != MP_OK) break;
-        (void)hipEventRecord(e0, s);
-        for (int r = 0; r < (reps > 0 ? reps : 3) && st == MP_OK; ++r) st = launch_bspmm(plan->nrhs, tpr, A, a, X, Y, s);
-        (void)hipEventRecord(e1, s);
-        hipError_t e = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e != hipSuccess) st = hip_fail(e, "batched autotune timing");
-        if (st == MP_OK && (best < 0.f || ms < best)) {
-            best = ms;
-            best_tpr = tpr;
+        for (int U = 1; U <= 4 && st == MP_OK; U <<= 1) {
+            float ms = 0.f;
+            auto launch = [&]() -> mp_status {
+                int32_t *c0 = cnt + flip * kQueues, *c1 = cnt + (1 - flip) * kQueues;
+                flip = 1 - flip;
+                switch (plan->nrhs) {
+                    case 1: return launch_bq_spmm<1>(tpr, U, A, a, X, Y, c0, c1, s);
+                    case 2: return launch_bq_spmm<2>(tpr, U, A, a, X, Y, c0, c1, s);
+                    case 4: return launch_bq_spmm<4>(tpr, U, A, a, X, Y, c0, c1, s);
+                    default: return launch_bq_spmm<8>(tpr, U, A, a, X, Y, c0, c1, s);
+                }
+            };
+            st = timed(launch, &ms);
+            if (st == MP_OK && (best < 0.f || ms < best)) {
+                best = ms;
+                best_tpr = tpr;
+                best_u = U;
+            }
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    // the chunk kernels' item order, timed on the (p, q) sums of (X, Y)
+    int best_order = plan->chunk_order;
+    float best_c = -1.f;
+    for (int order = 0; order < 2 && st == MP_OK; ++order) {
+        plan->chunk_order = order;
+        float ms = 0.f;
+        auto launch = [&]() -> mp_status {
+            int32_t *c0 = cnt + flip * kQueues, *c1 = cnt + (1 - flip) * kQueues;
+            flip = 1 - flip;
+            switch (plan->nrhs) {
+                case 1: {
+                    const int g = std::min(resident_grid(k_bq_pq<1>, BMap<1>::THREADS), plan->n_chunks);
+                    hipLaunchKernelGGL(k_bq_pq<1>, dim3(g), dim3(BMap<1>::THREADS), 0, s, A->n_rows, X, Y, part,
+                                       plan->d_chunk_row, plan->d_chunk_sys, plan->d_sys_ptr, chunk_queue<1>(plan, c0, c1));
+                    break;
+                }
+                case 2: {
+                    const int g = std::min(resident_grid(k_bq_pq<2>, BMap<2>::THREADS), plan->n_chunks);
+                    hipLaunchKernelGGL(k_bq_pq<2>, dim3(g), dim3(BMap<2>::THREADS), 0, s, A->n_rows, X, Y, part,
+                                       plan->d_chunk_row, plan->d_chunk_sys, plan->d_sys_ptr, chunk_queue<2>(plan, c0, c1));
+                    break;
+                }
+                case 4: {
+                    const int g = std::min(resident_grid(k_bq_pq<4>, BMap<4>::THREADS), plan->n_chunks);
+                    hipLaunchKernelGGL(k_bq_pq<4>, dim3(g), dim3(BMap<4>::THREADS), 0, s, A->n_rows, X, Y, part,
+                                       plan->d_chunk_row, plan->d_chunk_sys, plan->d_sys_ptr, chunk_queue<4>(plan, c0, c1));
+                    break;
+                }
+                default: {
+                    const int g = std::min(resident_grid(k_bq_pq<8>, BMap<8>::THREADS), plan->n_chunks);
+                    hipLaunchKernelGGL(k_bq_pq<8>, dim3(g), dim3(BMap<8>::THREADS), 0, s, A->n_rows, X, Y, part,
+                                       plan->d_chunk_row, plan->d_chunk_sys, plan->d_sys_ptr, chunk_queue<8>(plan, c0, c1));
+                }
+            }
+            MP_HIP_TRY(hipGetLastError());
+            return MP_OK;
+        };
+        st = timed(launch, &ms);
+        if (st == MP_OK && (best_c < 0.f || ms < best_c)) {
+            best_c = ms;
+            best_order = order;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st == MP_OK) {
+        const hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = hip_fail(e, "hipStreamSynchronize");
+    }
+    if (part) (void)hipFree(part);
+    (void)hipFree(cnt);
     if (st != MP_OK) return st;
     plan->tpr = best_tpr;
+    plan->rows_mult = best_u;
+    plan->chunk_order = best_order;
     if (threads_per_row) *threads_per_row = best_tpr;
+    return MP_OK;
+}
+
+mp_status mp_batch_plan_set_schedule(mp_batch_plan *plan, int32_t threads_per_row, int32_t rows_mult,
+                                     int32_t chunk_order)
+{
+    mpk::clear_error();
+    if (!plan) return mpk::fail(MP_ERR_INVALID_ARG, "plan is NULL");
+    if (threads_per_row < 1 || threads_per_row > plan->nrhs || (threads_per_row & (threads_per_row - 1)))
+        return mpk::fail(MP_ERR_INVALID_ARG, "threads_per_row must be a power of two <= nrhs");
+    if (rows_mult != 1 && rows_mult != 2 && rows_mult != 4)
+        return mpk::fail(MP_ERR_INVALID_ARG, "rows_mult must be 1, 2 or 4");
+    if (chunk_order != 0 && chunk_order != 1) return mpk::fail(MP_ERR_INVALID_ARG, "chunk_order must be 0 or 1");
+    plan->tpr = threads_per_row;
+    plan->rows_mult = rows_mult;
+    plan->chunk_order = chunk_order;
+    return MP_OK;
+}
+
+mp_status mp_batch_plan_schedule(const mp_batch_plan *plan, int32_t *threads_per_row, int32_t *rows_per_tile,
+                                 int32_t *chunk_order)
+{
+    mpk::clear_error();
+    if (!plan) return mpk::fail(MP_ERR_INVALID_ARG, "plan is NULL");
+    if (threads_per_row) *threads_per_row = plan->tpr;
+    if (rows_per_tile) *rows_per_tile = (256 / plan->tpr) * plan->rows_mult;
+    if (chunk_order) *chunk_order = plan->chunk_order;
     return MP_OK;
 }
 

@@ -211,6 +211,59 @@ __device__ __forceinline__ void acc_store(const SpmvArgs &A, int32_t row, const 
     store_mp<K>(A.y_im, A.n_rows, row, yi);
 }
 
+// Complex products in two passes (H = 1, 2), each with two of Eq. 3's accumulator
+// sets: pass 1 sums rr and ii and stores y_re = rr + (-ii), pass 2 sums ri and ir and
+// stores y_im = ri + ir.  Every set is summed in the same order as in the one-pass form
+// (H = 0), so the results are the same bits; a pass stages half the products in LDS.
+template <int K>
+struct Acc2 {
+    mpn<K> s0, s1;
+};
+
+template <int K, bool CPLX, int H>
+struct AccSel {
+    using type = Acc<K, CPLX>;
+};
+template <int K, bool CPLX>
+struct AccSel<K, CPLX, 1> {
+    using type = Acc2<K>;
+};
+template <int K, bool CPLX>
+struct AccSel<K, CPLX, 2> {
+    using type = Acc2<K>;
+};
+template <int K, bool CPLX, int H>
+using AccT = typename AccSel<K, CPLX, H>::type;
+
+template <int K>
+__device__ __forceinline__ void acc_zero(Acc2<K> &a) { a.s0 = a.s1 = mp_zero<K>(); }
+template <int K>
+__device__ __forceinline__ void acc_fold_xor(Acc2<K> &a, int mask)
+{
+    a.s0 = mp_add(a.s0, shfl_xor_mp(a.s0, mask));
+    a.s1 = mp_add(a.s1, shfl_xor_mp(a.s1, mask));
+}
+template <int K>
+__device__ __forceinline__ void acc_add(Acc2<K> &a, const Acc2<K> &b)
+{
+    a.s0 = mp_add(a.s0, b.s0);
+    a.s1 = mp_add(a.s1, b.s1);
+}
+
+template <int H, int K, bool CPLX>
+__device__ __forceinline__ void acc_store_h(const SpmvArgs &A, int32_t row, const Acc<K, CPLX> &a, bool nonempty)
+{
+    acc_store(A, row, a, nonempty);
+}
+template <int H, int K>
+__device__ __forceinline__ void acc_store_h(const SpmvArgs &A, int32_t row, const Acc2<K> &a, bool nonempty)
+{
+    if constexpr (H == 1)
+        store_mp<K>(A.y_re, A.n_rows, row, nonempty ? mp_add(a.s0, mp_neg(a.s1)) : mp_zero<K>());
+    else
+        store_mp<K>(A.y_im, A.n_rows, row, nonempty ? mp_add(a.s0, a.s1) : mp_zero<K>());
+}
+
 // Fold the W lane sums of each W-lane group of a wavefront (W <= 64).  Lanes
 // l < off receive their partner l + off (= l ^ off inside the group); the other
 // lanes' results are never read again.
@@ -347,6 +400,31 @@ __device__ __forceinline__ Acc<K, CPLX> staged_product(const SpmvArgs &A, const 
     return elem_times_x<K, CPLX, DM>(e, load_x<K, CPLX>(A, e.col));
 }
 
+// the product(s) one pass stages: H = 0 all sets; H = 1 (rr, ii); H = 2 (ri, ir)
+template <int K, bool CPLX, bool DM, int H>
+__device__ __forceinline__ AccT<K, CPLX, H> elem_times_x_h(const AElem<K, CPLX> &e, const XVal<K, CPLX> &x)
+{
+    if constexpr (H == 0) {
+        return elem_times_x<K, CPLX, DM>(e, x);
+    } else {
+        Acc2<K> p;
+        if constexpr (DM) {
+            p.s0 = H == 1 ? mp_mul_d(x.re, e.re.c[0]) : mp_mul_d(x.im, e.re.c[0]);
+            p.s1 = H == 1 ? mp_mul_d(x.im, e.im.c[0]) : mp_mul_d(x.re, e.im.c[0]);
+        } else {
+            p.s0 = H == 1 ? mp_mul(e.re, x.re) : mp_mul(e.re, x.im);
+            p.s1 = H == 1 ? mp_mul(e.im, x.im) : mp_mul(e.im, x.re);
+        }
+        return p;
+    }
+}
+
+template <int K, bool CPLX, bool DM, int H>
+__device__ __forceinline__ AccT<K, CPLX, H> staged_product_h(const SpmvArgs &A, const AElem<K, CPLX> &e)
+{
+    return elem_times_x_h<K, CPLX, DM, H>(e, load_x<K, CPLX>(A, e.col));
+}
+
 // The fold of the short tiles runs over a compact list of (row, lane) pairs for TD
 // (fewer wave-wide TD additions with idle lanes; measured +4-5 % real and complex),
 // and lane by lane for DD and QD, where the list's bookkeeping costs what it saves.
@@ -357,10 +435,10 @@ constexpr bool compact_fold()
 }
 
 // LDS of one stream-tile workgroup staging C elements
-template <int K, bool CPLX, int C>
+template <int K, bool CPLX, int C, int H = 0>
 struct StreamLds {
     static constexpr int kFoldRows = compact_fold<K>() ? C : 1;
-    Acc<K, CPLX> prod[C];      // staged products, later lane sums
+    AccT<K, CPLX, H> prod[C];  // staged products, later lane sums
     int32_t beg[C + 1];        // row starts relative to the tile's first element
     int32_t off[C + 1];        // first lane of each row
     uint16_t lane_row[C];      // row of each lane
@@ -376,9 +454,9 @@ struct StreamLds {
 // product is formed, and the products go to LDS.  Loads and gathers are branch-free
 // (a thread past the tile's end re-reads the tile's first element and discards it),
 // so a thread keeps all of its gathers in flight at once.
-template <int K, bool CPLX, int J, bool DM>
+template <int K, bool CPLX, int J, bool DM, int H>
 __device__ __forceinline__ void short_tile(const SpmvArgs &A, const uint8_t *__restrict__ log2w,
-                                           const mp_stream_tile &T, StreamLds<K, CPLX, 256 * J> &L)
+                                           const mp_stream_tile &T, StreamLds<K, CPLX, 256 * J, H> &L)
 {
     const int t = threadIdx.x;
     const int r0 = T.row_start;
@@ -419,7 +497,7 @@ __device__ __forceinline__ void short_tile(const SpmvArgs &A, const uint8_t *__r
 #pragma unroll
         for (int j = 0; j < J; ++j) {
             const int p = t + 256 * j;
-            if (p < ne) L.prod[p] = elem_times_x<K, CPLX, DM>(el[j], xv[j]);
+            if (p < ne) L.prod[p] = elem_times_x_h<K, CPLX, DM, H>(el[j], xv[j]);
         }
     }
     int run = block_exclusive_scan(sum, L.wave_tmp);
@@ -480,7 +558,7 @@ __device__ __forceinline__ void short_tile(const SpmvArgs &A, const uint8_t *__r
             lw[q] = L.off[i + 1] - o;
             lb[q] = L.beg[i];
             const int e = L.beg[i + 1];
-            Acc<K, CPLX> acc = L.prod[lb[q] + ll[q]];
+            AccT<K, CPLX, H> acc = L.prod[lb[q] + ll[q]];
             for (int p = lb[q] + ll[q] + lw[q]; p < e; p += lw[q]) acc_add(acc, L.prod[p]);
             L.prod[lb[q] + ll[q]] = acc;
         }
@@ -494,7 +572,7 @@ __device__ __forceinline__ void short_tile(const SpmvArgs &A, const uint8_t *__r
             const int pairs = L.wstart[k] << k;
             for (int p = t; p < pairs; p += 256) {
                 const int b = L.beg[L.rows_by_w[p >> k]] + (p & ((1 << k) - 1));
-                Acc<K, CPLX> v = L.prod[b];
+                AccT<K, CPLX, H> v = L.prod[b];
                 acc_add(v, L.prod[b + (1 << k)]);
                 L.prod[b] = v;
             }
@@ -505,7 +583,7 @@ __device__ __forceinline__ void short_tile(const SpmvArgs &A, const uint8_t *__r
 #pragma unroll
             for (int q = 0; q < J; ++q) {
                 if (li[q] >= 0 && ll[q] < off && off < lw[q]) {
-                    Acc<K, CPLX> v = L.prod[lb[q] + ll[q]];
+                    AccT<K, CPLX, H> v = L.prod[lb[q] + ll[q]];
                     acc_add(v, L.prod[lb[q] + ll[q] + off]);
                     L.prod[lb[q] + ll[q]] = v;
                 }
@@ -516,10 +594,10 @@ __device__ __forceinline__ void short_tile(const SpmvArgs &A, const uint8_t *__r
     for (int i = t; i < nr; i += 256) {
         const int b = L.beg[i];
         const bool nonempty = L.beg[i + 1] > b;
-        Acc<K, CPLX> v;
+        AccT<K, CPLX, H> v;
         if (nonempty) v = L.prod[b];
         else acc_zero(v);
-        acc_store(A, r0 + i, v, nonempty);
+        acc_store_h<H>(A, r0 + i, v, nonempty);
     }
 }
 
@@ -537,16 +615,16 @@ constexpr int long_batch()
     return K == 2 ? (CPLX ? 2 : 4) : (CPLX ? 1 : 2);
 }
 
-template <int K, bool CPLX, int J, bool DM>
+template <int K, bool CPLX, int J, bool DM, int H>
 __device__ __forceinline__ void long_tile_lanes(const SpmvArgs &A, const uint8_t *__restrict__ log2w,
-                                                const mp_stream_tile &T, StreamLds<K, CPLX, 256 * J> &L)
+                                                const mp_stream_tile &T, StreamLds<K, CPLX, 256 * J, H> &L)
 {
     const int t = threadIdx.x;
     const int row = T.row_start;
     const int32_t b0 = A.row_ptr[row], end = A.row_ptr[row + 1];
     const int W = 1 << log2w[row];
     constexpr int kLongBatch = long_batch<K, CPLX>();
-    Acc<K, CPLX> acc;
+    AccT<K, CPLX, H> acc;
     acc_zero(acc);
     if (t < W) {
         // W <= len, so every lane owns at least one element and starts from its first product
@@ -565,7 +643,7 @@ __device__ __forceinline__ void long_tile_lanes(const SpmvArgs &A, const uint8_t
 #pragma unroll
             for (int q = 0; q < kLongBatch; ++q) {
                 if (k0 + (int64_t)q * W < end) {
-                    const Acc<K, CPLX> p = elem_times_x<K, CPLX, DM>(el[q], xv[q]);
+                    const AccT<K, CPLX, H> p = elem_times_x_h<K, CPLX, DM, H>(el[q], xv[q]);
                     if (first)
                         acc = p;
                     else
@@ -585,22 +663,22 @@ __device__ __forceinline__ void long_tile_lanes(const SpmvArgs &A, const uint8_t
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1)
         if (off < W) acc_fold_xor(acc, off);
-    if (t == 0) acc_store(A, row, acc, true);
+    if (t == 0) acc_store_h<H>(A, row, acc, true);
 }
 
 // LONG tile, staged form (rows whose lanes own many elements): the row's elements pass
 // through LDS in chunks of C products, lane l (thread l) carrying its running sum in
 // registers.
-template <int K, bool CPLX, int J, bool DM>
+template <int K, bool CPLX, int J, bool DM, int H>
 __device__ __forceinline__ void long_tile_staged(const SpmvArgs &A, const uint8_t *__restrict__ log2w,
-                                          const mp_stream_tile &T, StreamLds<K, CPLX, 256 * J> &L)
+                                          const mp_stream_tile &T, StreamLds<K, CPLX, 256 * J, H> &L)
 {
     constexpr int C = 256 * J;
     const int t = threadIdx.x;
     const int row = T.row_start;
     const int32_t b0 = A.row_ptr[row], end = A.row_ptr[row + 1];
     const int W = 1 << log2w[row];
-    Acc<K, CPLX> acc;
+    AccT<K, CPLX, H> acc;
     acc_zero(acc);
     for (int32_t c0 = b0; c0 < end; c0 += C) {
         const int cl = (end - c0) < C ? (end - c0) : C;
@@ -613,7 +691,7 @@ __device__ __forceinline__ void long_tile_staged(const SpmvArgs &A, const uint8_
 #pragma unroll
         for (int j = 0; j < J; ++j) {
             const int p = t + 256 * j;
-            if (p < cl) L.prod[p] = staged_product<K, CPLX, DM>(A, el[j]);
+            if (p < cl) L.prod[p] = staged_product_h<K, CPLX, DM, H>(A, el[j]);
         }
         __syncthreads();
         if (t < W) {
@@ -632,13 +710,29 @@ __device__ __forceinline__ void long_tile_staged(const SpmvArgs &A, const uint8_
     __syncthreads();
     for (int off = W >> 1; off >= 1; off >>= 1) {
         if (t < off) {
-            Acc<K, CPLX> v = L.prod[t];
+            AccT<K, CPLX, H> v = L.prod[t];
             acc_add(v, L.prod[t + off]);
             L.prod[t] = v;
         }
         __syncthreads();
     }
-    if (t == 0) acc_store(A, row, L.prod[0], true);
+    if (t == 0) acc_store_h<H>(A, row, L.prod[0], true);
+}
+
+// Complex variants whose tiles run as two passes of two accumulator sets (H = 1, 2):
+// QD, whose four staged sets of a 256-element tile fill 32 KiB of LDS and leave room
+// for four workgroups per CU; each pass stages half of that.
+template <int K, bool CPLX, bool DM>
+constexpr bool two_pass()
+{
+    return CPLX && K == 4 && !DM;
+}
+
+// workgroups per CU asked of a two-pass tile kernel
+template <int K, int J>
+constexpr int two_pass_min_blocks()
+{
+    return J == 1 ? 6 : 1;
 }
 
 // A long row runs in register lanes when each lane owns at most kLaneElems elements
@@ -664,9 +758,10 @@ __device__ __forceinline__ bool long_in_lanes(const SpmvArgs &A, const uint8_t *
 // 5 (100 -> 96 registers, +10-12 %), DD complex with one 8 (74 -> 64, +3-5 %), TD real
 // with two 8 (68 -> 64, +2-5 %), QD real with two 7 (76 -> 70, +3-4 %).  Elsewhere the
 // compiler's allocation stands.
-template <int K, bool CPLX, int J>
+template <int K, bool CPLX, int J, int H = 0>
 constexpr int stream_min_blocks()
 {
+    if (H != 0) return two_pass_min_blocks<K, J>();
     if (K == 3 && CPLX && J == 1) return 5;
     if (K == 2 && CPLX && J == 1) return 8;
     if (K == 3 && !CPLX && J == 2) return 8;
@@ -674,19 +769,19 @@ constexpr int stream_min_blocks()
     return 1;
 }
 
-template <int K, bool CPLX, int J, bool DM>
-__global__ __launch_bounds__(256, (stream_min_blocks<K, CPLX, J>())) void spmv_stream_kernel(
+template <int K, bool CPLX, int J, bool DM, int H = 0>
+__global__ __launch_bounds__(256, (stream_min_blocks<K, CPLX, J, H>())) void spmv_stream_kernel(
     SpmvArgs A, const mp_stream_tile *__restrict__ tiles, const uint8_t *__restrict__ log2w)
 {
-    __shared__ StreamLds<K, CPLX, 256 * J> L;
+    __shared__ StreamLds<K, CPLX, 256 * J, H> L;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const mp_stream_tile T = tiles[tile];
     if (((T.info >> 4) & 15) == 0)
-        short_tile<K, CPLX, J, DM>(A, log2w, T, L);
+        short_tile<K, CPLX, J, DM, H>(A, log2w, T, L);
     else if (lanes_form<K, CPLX>() && long_in_lanes(A, log2w, T.row_start))
-        long_tile_lanes<K, CPLX, J, DM>(A, log2w, T, L);
+        long_tile_lanes<K, CPLX, J, DM, H>(A, log2w, T, L);
     else
-        long_tile_staged<K, CPLX, J, DM>(A, log2w, T, L);
+        long_tile_staged<K, CPLX, J, DM, H>(A, log2w, T, L);
 }
 
 // ---------------------------------------------------------------------------
@@ -778,6 +873,13 @@ mp_status launch_stream(const SpmvArgs &A, const mp_plan *plan, hipStream_t s)
 {
     if constexpr (sizeof(StreamLds<K, CPLX, 256 * J>) > 65536) {
         return fail(MP_ERR_UNSUPPORTED, "tile size %d exceeds the LDS budget of this variant", 256 * J);
+    } else if constexpr (two_pass<K, CPLX, DM>()) {
+        hipLaunchKernelGGL((spmv_stream_kernel<K, CPLX, J, DM, 1>), dim3(plan->n_stream), dim3(256), 0, s, A,
+                           plan->d_stream, plan->d_log2w);
+        hipLaunchKernelGGL((spmv_stream_kernel<K, CPLX, J, DM, 2>), dim3(plan->n_stream), dim3(256), 0, s, A,
+                           plan->d_stream, plan->d_log2w);
+        MP_HIP_TRY(hipGetLastError());
+        return MP_OK;
     } else {
         hipLaunchKernelGGL((spmv_stream_kernel<K, CPLX, J, DM>), dim3(plan->n_stream), dim3(256), 0, s, A,
                            plan->d_stream, plan->d_log2w);

@@ -158,6 +158,41 @@ def test_batched_cg_multi_chunk_converged(mp):
     compare_pairs(mp, [17, 20], 8, 45, 20000, converged=True)
 
 
+def test_batched_schedules_give_the_same_solves(mp):
+    """Every schedule of the persistent step (threads per row, SpMM tile rows, chunk
+    order) and the autotuned one give the same pairs bit for bit (graph path), on
+    systems of several dot chunks; the schedule setter refuses bad values."""
+    import torch
+    rp, ci, a, sp = batched_diffusion([20, 12, 17, 9], sigma=2.5, seed=46)
+    N = rp.size - 1
+    R = 8
+    B = multi(np.random.default_rng(46), N, R)
+    A = mp.Csr.from_numpy(rp, ci)
+    ad, Bd = dev(a), dev(B)
+    plan = mp.mp_batch_plan_create(A, sp, R, 1)
+    ref_x, ref_it = None, None
+    for sched in ((1, 1, 0), (2, 4, 1), (8, 2, 1), (4, 1, 0), None):
+        if sched is None:
+            mp.mp_batch_plan_autotune(plan, A, ad, Bd, torch.empty((2, N, R), dtype=torch.float64, device="cuda"))
+        else:
+            mp.mp_batch_plan_set_schedule(plan, *sched)
+        got = mp.mp_batch_plan_schedule(plan)
+        print("schedule", got, flush=True)
+        X = torch.zeros((2, N, R), dtype=torch.float64, device="cuda")
+        infos = mp.mpkrylov_cg_batched(A, ad, Bd, X, R, plan, use_graph=True, precond="jacobi", rtol=1e-28,
+                                       max_iter=300, check_every=16)
+        xh = host(X)
+        its = [i["iters"] for i in infos]
+        if ref_x is None:
+            ref_x, ref_it = xh, its
+        else:
+            assert_same_values(xh, ref_x, "schedule %s" % (got,))
+            assert its == ref_it
+    for bad in ((3, 1, 0), (16, 1, 0), (1, 3, 0), (1, 1, 2)):
+        with pytest.raises(mp.MpError):
+            mp.mp_batch_plan_set_schedule(plan, *bad)
+
+
 def test_batched_rejects_off_block_entries(mp):
     rp, ci, a, sp = batched_diffusion([4, 4], sigma=1.0, seed=43)
     bad = ci.copy()
