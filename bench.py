@@ -119,21 +119,52 @@ def copy_bandwidth(torch):
     return 2 * n * 8 / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(row_ptr, col_idx, a, x, min_seconds):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(row_ptr, col_idx, a, x, min_seconds, solves=None, kept=None):
+    """The oracle (plain scalar C, OpenMP over rows) on the host: the DD SpMV of the
+    full power-law matrix on every core and on one core, and -- when the 64^3 solves ran
+    -- the oracle's DD CG solve of each system, which also certifies every GPU solve."""
     from oracle import ref
-    reps = 0
-    t0 = time.perf_counter()
-    while True:
-        ref.spmv(2, row_ptr, col_idx, a, x)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= min_seconds:
-            break
     nnz = col_idx.size
-    return {"value": round(reps * nnz / el / 1e9, 4), "unit": "GNNZ/s", "cores": ref.num_threads(),
-            "kind": "oracle",
-            "sample": "DD real y=Ax on the full n=1e6 power-law matrix (%d nnz), %d repetitions in %.1f s"
-                      % (nnz, reps, el)}
+
+    def rate(threads, seconds):
+        reps = 0
+        t0 = time.perf_counter()
+        while True:
+            ref.spmv(2, row_ptr, col_idx, a, x, nthreads=threads)
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= seconds:
+                return reps, el
+
+    reps, el = rate(0, min_seconds)
+    reps1, el1 = rate(1, min_seconds / 2)
+    cores = ref.num_threads()
+    out = {"value": round(reps * nnz / el / 1e9, 4), "unit": "GNNZ/s", "cores": cores, "kind": "oracle",
+           "cpu_model": cpu_model(),
+           "sample": "DD real y=Ax on the full n=1e6 power-law matrix (%d nnz), %d repetitions in %.1f s on %d "
+                     "threads" % (nnz, reps, el, cores),
+           "one_thread": {"value": round(reps1 * nnz / el1 / 1e9, 4), "unit": "GNNZ/s",
+                          "sample": "%d repetitions in %.1f s" % (reps1, el1)}}
+    if solves is not None and kept:
+        out["solves"] = certify_solves(solves, kept, cores)
+        first = next(iter(out["solves"].values()))
+        out["learned_eval_extrapolated"] = {
+            "seconds": round(200 * first["seconds"], 1),
+            "note": "plain DD Jacobi-CG on the 200 held-out 64^3 systems, extrapolated as 200 x the oracle's "
+                    "solve of the first 64^3 system above (same size; the held-out systems vary sigma in "
+                    "[1.5, 3.0], so their iteration counts differ)"}
+    return out
 
 
 def dd_rel_diff(x, ref):
@@ -142,90 +173,150 @@ def dd_rel_diff(x, ref):
     return float(np.max(np.abs(d)) / np.max(np.abs(ref[0])))
 
 
-def solves_section(mp, torch, repeats=2):
-    """DD-accurate solves of the 64^3 sigma = 2.5 diffusion system (relative residual 1e-28):
-    plain DD Jacobi-CG against mixed-precision refinement with binary64 / binary32 inner CG,
-    preconditioned by Jacobi or by the trained network (when its checkpoint is present)."""
+def dd_rel_err2(x, ref):
+    """||x - ref||_2 / ||ref||_2 for DD vectors (2, n): the difference of the leading
+    parts is exact where they are close (Sterbenz), the trailing parts are added to it."""
+    d = (x[0] - ref[0]) + (x[1] - ref[1])
+    return float(np.linalg.norm(d) / np.linalg.norm(ref[0] + ref[1]))
+
+
+def solver_systems():
+    """The 64^3 solver systems of the calibrated law (workloads/c2_law.json): the
+    configured sigma = 2.5 at the anisotropy factor of largest condition number, and the
+    sigma at which the measured condition number is 1e10."""
+    from workloads.condition import load_law
+    return load_law()["systems"]
+
+
+def solves_section(mp, torch, repeats=2, keep=None):
+    """DD-accurate solves (relative residual 1e-28) of the 64^3 diffusion systems:
+    plain DD Jacobi-CG against mixed-precision refinement with binary64 / binary32 inner
+    CG, preconditioned by Jacobi or by the trained network (when its checkpoint is
+    present).  keep: dict that receives, per system, the generated matrix and right-hand
+    side and every solver's x (host arrays) for the CPU leg's certification."""
     from workloads import diffusion3d_7pt, random_mp
-    t0 = time.perf_counter()
-    rp, ci, a = diffusion3d_7pt(m=64, sigma=2.5, seed=2)
-    n = rp.size - 1
-    b = random_mp(n, 2, np.random.default_rng(2))
-    log("solve system 64^3 n=%d nnz=%d generated in %.1f s" % (n, ci.size, time.perf_counter() - t0))
-    A = mp.Csr.from_numpy(rp, ci)
-    ad = torch.from_numpy(a).cuda()
-    bd = torch.from_numpy(b).cuda()
-    ytmp = torch.empty((2, n), dtype=torch.float64, device="cuda")
-    plan, pol = mp.mp_plan_autotune(A, 2, ad, bd, ytmp, reps=5)
-    runs = {"plain_dd_cg": dict(fn=mp.mpkrylov_cg, kw=dict(precond="jacobi", rtol=1e-28, max_iter=100000)),
-            "ir_fp64_inner": dict(fn=mp.mpkrylov_ir, kw=dict(precond="jacobi", rtol=1e-28, inner="fp64",
-                                                            inner_rtol=1e-8, inner_max_iter=50000, max_outer=60,
-                                                            max_iter=100000)),
-            "ir_fp32_inner": dict(fn=mp.mpkrylov_ir, kw=dict(precond="jacobi", rtol=1e-28, inner="fp32",
-                                                            inner_rtol=1e-5, inner_max_iter=50000, max_outer=60,
-                                                            max_iter=100000))}
-    out = {"workload": "3D 7-point diffusion 64^3, lognormal sigma 2.5 (seed 2), random DD b, x0 = 0",
-           "plan": pol, "target_relres": 1e-28}
-    # learned preconditioner: M from the trained network (forward pass timed and added)
+    out = {"target_relres": 1e-28}
     ckpt = os.path.join(ROOT, "paper_2412_17510_amd", "data", "mpnn_diffusion.npz")
-    t_fwd = None
+    net, meta = None, None
     if os.path.exists(ckpt):
-        from paper_2412_17510_amd import learned
         net = mp.Mpnn()
         with np.load(ckpt, allow_pickle=False) as f:
             net.set_params(f["theta"])
-            meta = {k: f[k].item() for k in f.files if k != "theta"}
-        fwd = []
-        for _ in range(3):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            g = mp.Graph(A, ad)
-            M = mp.mp_mpnn_forward(net, g)
-            torch.cuda.synchronize()
-            fwd.append(time.perf_counter() - t0)
-            g.destroy()
-        t_fwd = min(fwd)
-        out["learned"] = {"checkpoint": os.path.relpath(ckpt, ROOT), "trained_on": meta,
-                          "forward_s": round(t_fwd, 5),
-                          "note": "M = network forward pass on this matrix (graph set-up + 5 dense layers + "
-                                  "readouts); its time is added to the learned solves"}
-        for inn, irt in (("fp64", 1e-8), ("fp32", 1e-5)):
-            runs["ir_%s_learned" % inn] = dict(
-                fn=lambda A_, a_, b_, x_, M=M, **kw: mp.mpkrylov_ir_learned(A_, a_, M, b_, x_, **kw),
-                kw=dict(rtol=1e-28, inner=inn, inner_rtol=irt, inner_max_iter=50000, max_outer=60, max_iter=100000),
-                extra=t_fwd)
-    ref = None
-    for name, r in runs.items():
-        best = None
-        for _ in range(repeats):
-            x = torch.zeros((2, n), dtype=torch.float64, device="cuda")
-            info = r["fn"](A, ad, bd, x, plan=plan, check_every=32, **r["kw"])
-            info["seconds"] += r.get("extra", 0.0)
-            if best is None or info["seconds"] < best[1]["seconds"]:
-                best = (x.cpu().numpy(), info)
-        xh, info = best
-        if ref is None:
-            ref = xh
-        rec = {"seconds": round(info["seconds"], 5), "solves_per_s": round(1.0 / info["seconds"], 3),
-               "status": info["status"], "iters": info["iters"], "outer_iters": info["outer_iters"],
-               "fell_back": info["fell_back"], "relres": info["relres"],
-               "rel_diff_vs_plain_dd_cg": dd_rel_diff(xh, ref)}
-        out[name] = rec
-        log("%-14s %.4f s (%.2f solves/s) status %d iters %d outer %d relres %.3g" % (
-            name, info["seconds"], 1.0 / info["seconds"], info["status"], info["iters"], info["outer_iters"],
-            info["relres"]))
+            meta = {k: (f[k].item() if f[k].size == 1 else f[k].tolist()) for k in f.files if k != "theta"}
+    for sysrec in solver_systems():
+        t0 = time.perf_counter()
+        rp, ci, a = diffusion3d_7pt(m=sysrec["m"], sigma=sysrec["sigma"], az=sysrec["az"], seed=sysrec["seed"])
+        n = rp.size - 1
+        b = random_mp(n, 2, np.random.default_rng(sysrec["seed"]))
+        log("solve system %s: %d^3 sigma %g az %g cond %.3g, n=%d nnz=%d generated in %.1f s" % (
+            sysrec["name"], sysrec["m"], sysrec["sigma"], sysrec["az"], sysrec["cond"], n, ci.size,
+            time.perf_counter() - t0))
+        A = mp.Csr.from_numpy(rp, ci)
+        ad = torch.from_numpy(a).cuda()
+        bd = torch.from_numpy(b).cuda()
+        ytmp = torch.empty((2, n), dtype=torch.float64, device="cuda")
+        plan, pol = mp.mp_plan_autotune(A, 2, ad, bd, ytmp, reps=5)
+        runs = {"plain_dd_cg": dict(fn=mp.mpkrylov_cg, kw=dict(precond="jacobi", rtol=1e-28, max_iter=100000)),
+                "ir_fp64_inner": dict(fn=mp.mpkrylov_ir, kw=dict(precond="jacobi", rtol=1e-28, inner="fp64",
+                                                                inner_rtol=1e-8, inner_max_iter=50000, max_outer=60,
+                                                                max_iter=100000)),
+                "ir_fp32_inner": dict(fn=mp.mpkrylov_ir, kw=dict(precond="jacobi", rtol=1e-28, inner="fp32",
+                                                                inner_rtol=1e-5, inner_max_iter=50000, max_outer=60,
+                                                                max_iter=100000))}
+        rec_sys = {"workload": "3D 7-point diffusion %d^3, lognormal sigma %g, axis factors (1, 1, %g), seed %d, "
+                               "random DD b, x0 = 0" % (sysrec["m"], sysrec["sigma"], sysrec["az"], sysrec["seed"]),
+                   "cond": sysrec["cond"], "lambda_max": sysrec["lambda_max"], "lambda_min": sysrec["lambda_min"],
+                   "plan": pol}
+        if net is not None:
+            fwd = []
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                g = mp.Graph(A, ad)
+                M = mp.mp_mpnn_forward(net, g)
+                torch.cuda.synchronize()
+                fwd.append(time.perf_counter() - t0)
+                g.destroy()
+            t_fwd = min(fwd)
+            rec_sys["learned"] = {"checkpoint": os.path.relpath(ckpt, ROOT), "trained_on": meta,
+                                  "forward_s": round(t_fwd, 5),
+                                  "note": "M = network forward pass on this matrix (graph set-up + 5 dense layers + "
+                                          "readouts); its time is added to the learned solves"}
+            for inn, irt in (("fp64", 1e-8), ("fp32", 1e-5)):
+                runs["ir_%s_learned" % inn] = dict(
+                    fn=lambda A_, a_, b_, x_, M=M, **kw: mp.mpkrylov_ir_learned(A_, a_, M, b_, x_, **kw),
+                    kw=dict(rtol=1e-28, inner=inn, inner_rtol=irt, inner_max_iter=50000, max_outer=60,
+                            max_iter=100000),
+                    extra=t_fwd)
+        xs = {}
+        for name, r in runs.items():
+            best = None
+            for _ in range(repeats):
+                x = torch.zeros((2, n), dtype=torch.float64, device="cuda")
+                kw = dict(r["kw"])
+                info = r["fn"](A, ad, bd, x, plan=plan, check_every=32, **kw)
+                info["seconds"] += r.get("extra", 0.0)
+                if best is None or info["seconds"] < best[1]["seconds"]:
+                    best = (x.cpu().numpy(), info)
+            xh, info = best
+            xs[name] = xh
+            rec_sys[name] = {"seconds": round(info["seconds"], 5), "solves_per_s": round(1.0 / info["seconds"], 3),
+                             "status": info["status"], "iters": info["iters"], "outer_iters": info["outer_iters"],
+                             "fell_back": info["fell_back"], "relres_dd": info["relres"],
+                             "rel_diff_vs_plain_dd_cg": dd_rel_diff(xh, xs["plain_dd_cg"]),
+                             "exact_relres_upper": None, "rel_err_vs_oracle": None}
+            log("%-10s %-14s %.4f s (%.2f solves/s) status %d iters %d outer %d fell_back %d relres %.3g" % (
+                sysrec["name"], name, info["seconds"], 1.0 / info["seconds"], info["status"], info["iters"],
+                info["outer_iters"], info["fell_back"], info["relres"]))
+        out[sysrec["name"]] = rec_sys
+        if keep is not None:
+            keep[sysrec["name"]] = dict(row_ptr=rp, col_idx=ci, a=a, b=b, x=xs, plan_log2w=plan.row_log2w())
+        del A, ad, bd, ytmp, plan
+        torch.cuda.empty_cache()
     return out
 
 
+def certify_solves(solves, kept, threads_note):
+    """CPU leg (oracle): for each 64^3 system, the oracle's plain DD Jacobi-CG solve
+    (timed on the host's cores) and, for every GPU solve, the certified exact relative
+    residual (long accumulator, oracle_exact_residual) and ||x - x_oracle|| / ||x_oracle||."""
+    from oracle import ref
+    timing = {}
+    for name, k in kept.items():
+        rp, ci, a, b = k["row_ptr"], k["col_idx"], k["a"], k["b"]
+        t0 = time.perf_counter()
+        xo, io = ref.cg(rp, ci, a, b, precond="jacobi", rtol=1e-28, max_iter=100000, log2w=k["plan_log2w"])
+        secs = time.perf_counter() - t0
+        ex_o = ref.exact_residual(rp, ci, a, b, xo)
+        timing[name] = {"seconds": round(secs, 2), "iters": io["iters"], "status": io["status"],
+                        "exact_relres_upper": ex_o["relres_upper"], "threads": threads_note,
+                        "solver": "oracle DD Jacobi-CG (the plain method), same plan order as the GPU's"}
+        log("oracle DD CG %s: %.1f s, %d iterations, certified relres <= %.3g" % (
+            name, secs, io["iters"], ex_o["relres_upper"]))
+        for sname, xg in k["x"].items():
+            rec = solves[name][sname]
+            ex = ref.exact_residual(rp, ci, a, b, xg)
+            rec["exact_relres_upper"] = ex["relres_upper"]
+            rec["rel_err_vs_oracle"] = dd_rel_err2(xg, xo)
+            rec["bitwise_equal_to_oracle"] = bool(np.array_equal(xg, xo))
+            log("  %-14s certified relres <= %.3g, ||x - x_oracle|| / ||x_oracle|| = %.3g" % (
+                sname, ex["relres_upper"], rec["rel_err_vs_oracle"]))
+    return timing
+
+
 def batched_section(mp, torch, args):
-    """256 block-diagonal diffusion systems (edges U{12..60}, sigma 2.5) x 8 random DD
-    right-hand sides: autotuned batched SpMM throughput, one batched CG solve to 1e-28
-    (hipGraph replay), and a per-system loop of single solves on a labelled subset."""
+    """256 block-diagonal diffusion systems (edges U{12..60}, sigma 2.5 and the anisotropy
+    factor of the calibrated 64^3 law) x 8 random DD right-hand sides: the SpMM
+    throughput, one batched CG solve to 1e-28 (persistent step kernels, hipGraph replay)
+    under the autotuned schedule, and single-system solves of a size-stratified subset
+    (one system per size stratum) extrapolated to every pair; the oracle's solves of
+    the same subset give the CPU figure."""
     from workloads import batched_diffusion, random_mp
+    az = solver_systems()[0]["az"]
     t0 = time.perf_counter()
     rng = np.random.default_rng(3)
     edges = rng.integers(12, 61, args.nsys)
-    rp, ci, a, sp = batched_diffusion(edges, sigma=2.5, seed=3)
+    rp, ci, a, sp = batched_diffusion(edges, sigma=2.5, seed=3, az=az)
     N = rp.size - 1
     nnz = ci.size
     R = 8
@@ -236,15 +327,17 @@ def batched_section(mp, torch, args):
     Bd = torch.from_numpy(np.ascontiguousarray(B)).cuda()
     Y = torch.empty((2, N, R), dtype=torch.float64, device="cuda")
     plan = mp.mp_batch_plan_create(A, sp, R, 1)
-    tpr = mp.mp_batch_plan_autotune(plan, A, ad, Bd, Y, reps=5)
+    mp.mp_batch_plan_autotune(plan, A, ad, Bd, Y, reps=5)
+    sched = mp.mp_batch_plan_schedule(plan)
+    tpr = sched["threads_per_row"]
     ms, _ = time_loop(lambda: mp.mpspmm_csr_dd_batched(A, ad, Bd, Y, R, plan=plan), args.steps, args.warmup, torch)
     bytes_ = 4 * (N + 1) + nnz * 20 + 2 * 16 * N * R
     spmm = {"ms": round(ms, 4), "gnnz_rhs_per_s": round(nnz * R / (ms * 1e-3) / 1e9, 2),
             "threads_per_row": tpr,
             "roofline": {"bound": "hbm", "achieved": round(bytes_ / (ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(bytes_ / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
-    log("batched SpMM: %.3f ms, %.1f GNNZ*RHS/s, %.0f GB/s, tpr %d" % (ms, nnz * R / (ms * 1e-3) / 1e9,
-                                                                      bytes_ / (ms * 1e-3) / 1e9, tpr))
+    log("batched SpMM: %.3f ms, %.1f GNNZ*RHS/s, %.0f GB/s, schedule %s" % (
+        ms, nnz * R / (ms * 1e-3) / 1e9, bytes_ / (ms * 1e-3) / 1e9, sched))
     del Y
     X = torch.zeros((2, N, R), dtype=torch.float64, device="cuda")
     infos = mp.mpkrylov_cg_batched(A, ad, Bd, X, R, plan, use_graph=True, precond="jacobi", rtol=1e-28,
@@ -253,10 +346,15 @@ def batched_section(mp, torch, args):
     conv = sum(1 for i in infos if i["status"] == 0)
     log("batched CG: %.2f s, %d/%d pairs converged, max iters %d" % (bsec, conv, len(infos),
                                                                    max(i["iters"] for i in infos)))
-    # per-system loop on a subset: systems 0..k-1, right-hand side 0, single GPU solves (W = 1 plan)
+    # size-stratified subset: the systems at the middle of args.loop_systems equal size strata
+    sizes = np.diff(sp)
+    by_size = np.argsort(sizes, kind="stable")
+    k = min(args.loop_systems, args.nsys)
+    subset = [int(by_size[int((j + 0.5) * args.nsys / k)]) for j in range(k)]
+    Xh = X.cpu().numpy()
     loop = []
-    for s in range(min(args.loop_systems, args.nsys)):
-        r0, r1 = int(sp[s]), int(sp[s + 1])
+    for s_ in subset:
+        r0, r1 = int(sp[s_]), int(sp[s_ + 1])
         rps = (rp[r0:r1 + 1] - rp[r0]).astype(np.int32)
         cis = (ci[rp[r0]:rp[r1]] - r0).astype(np.int32)
         As = mp.Csr.from_numpy(rps, cis)
@@ -266,22 +364,48 @@ def batched_section(mp, torch, args):
         xs = torch.zeros((2, r1 - r0), dtype=torch.float64, device="cuda")
         info = mp.mpkrylov_cg(As, a_s, b_s, xs, plan=p1, precond="jacobi", rtol=1e-28, max_iter=100000,
                               check_every=32)
-        same = bool(np.array_equal(xs.cpu().numpy(), X[:, r0:r1, 0].cpu().numpy()))
-        loop.append({"system": s, "n": r1 - r0, "seconds": info["seconds"], "iters": info["iters"],
+        same = bool(np.array_equal(xs.cpu().numpy(), Xh[:, r0:r1, 0]))
+        loop.append({"system": s_, "n": r1 - r0, "seconds": info["seconds"], "iters": info["iters"],
                      "bitwise_equal_to_batched": same})
     per_pair = sum(l["seconds"] for l in loop) / len(loop)
     pairs = len(infos)
-    return {"workload": "%d block-diagonal 3D diffusion systems, edges U{12..60} (seed 3), sigma 2.5, 8 random DD "
-                        "right-hand sides; N=%d nnz=%d" % (args.nsys, N, nnz),
-            "spmm": spmm,
-            "cg": {"seconds": round(bsec, 3), "pairs": pairs, "converged": conv,
-                   "max_iters": max(i["iters"] for i in infos), "solves_per_s": round(pairs / bsec, 2),
-                   "max_relres": max(i["relres"] for i in infos), "hipgraph": True},
-            "per_system_loop": {"subset": loop, "mean_seconds_per_solve": round(per_pair, 4),
-                                "extrapolated_seconds_all_pairs": round(per_pair * pairs, 2),
-                                "note": "single mpkrylov_cg calls on systems 0..%d, rhs 0, extrapolated by the "
-                                        "mean time per solve" % (len(loop) - 1)},
-            "speedup_vs_loop": round(per_pair * pairs / bsec, 2)}
+    out = {"workload": "%d block-diagonal 3D diffusion systems, edges U{12..60} (seed 3), sigma 2.5, axis factors "
+                       "(1, 1, %g), 8 random DD right-hand sides; N=%d nnz=%d" % (args.nsys, az, N, nnz),
+           "schedule": sched,
+           "spmm": spmm,
+           "cg": {"seconds": round(bsec, 3), "pairs": pairs, "converged": conv,
+                  "max_iters": max(i["iters"] for i in infos), "solves_per_s": round(pairs / bsec, 2),
+                  "max_relres": max(i["relres"] for i in infos), "hipgraph": True,
+                  "step": "four persistent kernels (SpMM tiles, (p, q) sums, update, p step) fed by per-XCD work "
+                          "queues"},
+           "per_system_loop": {"subset": loop, "mean_seconds_per_solve": round(per_pair, 4),
+                               "extrapolated_seconds_all_pairs": round(per_pair * pairs, 2),
+                               "note": "single mpkrylov_cg calls (right-hand side 0) on one system from each of %d "
+                                       "equal size strata (systems sorted by size), extrapolated as the subset's mean "
+                                       "time per solve times the %d pairs" % (k, pairs)},
+           "speedup_vs_loop": round(per_pair * pairs / bsec, 2)}
+    if not args.no_cpu_baseline:
+        from oracle import ref
+        t_or = []
+        for s_ in subset[:: max(1, len(subset) // 4)]:
+            r0, r1 = int(sp[s_]), int(sp[s_ + 1])
+            rps = (rp[r0:r1 + 1] - rp[r0]).astype(np.int32)
+            cis = (ci[rp[r0]:rp[r1]] - r0).astype(np.int32)
+            t1 = time.perf_counter()
+            xo, io = ref.cg(rps, cis, np.ascontiguousarray(a[:, rp[r0]:rp[r1]]),
+                            np.ascontiguousarray(B[:, r0:r1, 0]), precond="jacobi", rtol=1e-28, max_iter=100000,
+                            log2w=np.zeros(r1 - r0, np.uint8))
+            t_or.append({"system": s_, "n": r1 - r0, "seconds": round(time.perf_counter() - t1, 3),
+                         "iters": io["iters"], "bitwise_equal_to_batched": bool(np.array_equal(xo, Xh[:, r0:r1, 0]))})
+            log("oracle CG system %d (n=%d): %.2f s" % (s_, r1 - r0, t_or[-1]["seconds"]))
+        mean_o = sum(t["seconds"] for t in t_or) / len(t_or)
+        out["cpu_baseline"] = {"kind": "oracle", "cores": ref.num_threads(), "cpu_model": cpu_model(),
+                               "subset": t_or, "extrapolated_seconds_all_pairs": round(mean_o * pairs, 1),
+                               "value": round(pairs / (mean_o * pairs), 4), "unit": "solves/s",
+                               "sample": "oracle DD Jacobi-CG (the plain method, W = 1 order) on every other "
+                                         "system of the GPU's size-stratified subset, right-hand side 0; "
+                                         "extrapolated as their mean time per solve times the %d pairs" % pairs}
+    return out
 
 
 def nonsymmetric_section(mp, torch, repeats=3):
@@ -443,7 +567,7 @@ def main():
                          "locality (the DD SpMV on three column laws with the same row lengths) or solves (only "
                          "the 64^3 DD-accurate solves, one run each, e.g. under a kernel trace)")
     ap.add_argument("--nsys", type=int, default=256)
-    ap.add_argument("--loop-systems", type=int, default=6)
+    ap.add_argument("--loop-systems", type=int, default=8)
     ap.add_argument("--no-solves", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (counter calibration for the traffic figure)")
@@ -479,10 +603,12 @@ def main():
 
     if args.workload == "solves":
         res = solves_section(mp, torch, repeats=1)
-        best = max(v["solves_per_s"] for v in res.values() if isinstance(v, dict) and "solves_per_s" in v)
+        first = next(v for v in res.values() if isinstance(v, dict))
+        best = max(v["solves_per_s"] for v in first.values() if isinstance(v, dict) and "solves_per_s" in v)
         print(json.dumps({"metric": "DD-accurate solves/s on the 64^3 diffusion system (best solver)",
                           "value": best, "unit": "solves/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64",
-                          "data": "synthetic", "config": {"workload": res["workload"]}, "solves": res}), flush=True)
+                          "data": "synthetic", "config": {"workload": first["workload"]}, "solves": res}),
+              flush=True)
         return
 
     if args.workload == "locality":
@@ -574,9 +700,17 @@ def main():
     rf["traffic"] = None
     tr = find_record(os.path.join(ROOT, "profiles", "spmv_dd_powerlaw_traffic.json"), pol, n, source_hash())
     if tr is not None:
-        rf["traffic"] = round(tr["traffic_bytes"])
-        rf["traffic_note"] = ("FETCH_SIZE+WRITE_SIZE of the staging and tile kernels per call, copy-calibrated, "
-                              "counters taken under this plan")
+        implied = tr["traffic_bytes"] / (ms * 1e-3) / 1e9
+        if implied <= copy_gbs:
+            rf["traffic"] = round(tr["traffic_bytes"])
+            rf["traffic_note"] = ("L2-to-memory bytes per call (staging + tile kernel), each read request counted "
+                                  "at its size (TCC_EA0_RDREQ_32B/64B/128B, TCC_EA0_WRREQ/_64B), scaled by a plain "
+                                  "copy's bytes per counted byte (read %.3f, write %.3f); counters taken under this "
+                                  "plan on these kernel sources" % (tr["read_scale"], tr["write_scale"]))
+            rf["traffic_implied_GBs"] = round(implied, 1)
+        else:
+            rf["traffic_note"] = ("recorded traffic %.0f B would imply %.0f GB/s, above the measured copy bandwidth "
+                                  "%.0f GB/s: not reported" % (tr["traffic_bytes"], implied, copy_gbs))
     rf["algorithmic_bytes"] = algo_bytes(n, nnz, 2, False)
     rf["measured_copy_GBs"] = round(copy_gbs, 1)
     out = {
@@ -599,13 +733,15 @@ def main():
         "variants": results,
         "measured_ceilings": measured,
     }
+    kept = {}
     if not args.no_solves:
-        out["solves"] = solves_section(mp, torch)
+        out["solves"] = solves_section(mp, torch, keep=kept)
         out["nonsymmetric_solves"] = nonsymmetric_section(mp, torch)
         out["precision_solves"] = precision_section(mp, torch)
     if not args.no_cpu_baseline and host_dd is not None:
         log("timing the CPU oracle ...")
-        out["cpu_baseline"] = cpu_baseline(row_ptr, col_idx, host_dd[0], host_dd[1], args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(row_ptr, col_idx, host_dd[0], host_dd[1], args.cpu_seconds,
+                                           solves=out.get("solves"), kept=kept)
     print(json.dumps(out), flush=True)
 
 

@@ -69,6 +69,33 @@ def test_cg_full_size_100_iterations(mp):
     assert info["status"] == -5 and info["iters"] == 100
 
 
+@pytest.mark.parametrize("which", [0, 1])
+def test_cg_64cubed_converged_parity(mp, which):
+    """The benchmark's 64^3 solver systems (the calibrated law: sigma 2.5 at the
+    anisotropy of largest condition number, and the sigma of condition number 1e10),
+    solved to 1e-28 by Jacobi DD CG under the plan the benchmark autotunes for them: the
+    GPU's whole solve equals the oracle's (status, iterations, restarts, every component
+    of x, the DD true residual), and the exact residual certifies 1e-28."""
+    import torch
+    from workloads.condition import load_law
+    law = load_law()["systems"][which]
+    print("64^3 system %s sigma %g az %g" % (law["name"], law["sigma"], law["az"]), flush=True)
+    row_ptr, col_idx, a = diffusion3d_7pt(m=law["m"], sigma=law["sigma"], az=law["az"], seed=law["seed"])
+    n = row_ptr.size - 1
+    b = random_mp(n, 2, np.random.default_rng(law["seed"]))
+    A = mp.Csr.from_numpy(row_ptr, col_idx)
+    ad, bd = dev(a), dev(b)
+    plan, _ = mp.mp_plan_autotune(A, 2, ad, bd, torch.empty((2, n), dtype=torch.float64, device="cuda"), reps=3)
+    x = torch.zeros((2, n), dtype=torch.float64, device="cuda")
+    ig = mp.mpkrylov_cg(A, ad, bd, x, plan=plan, precond="jacobi", rtol=1e-28, max_iter=100000, check_every=32)
+    xo, io = ref.cg(row_ptr, col_idx, a, b, precond="jacobi", rtol=1e-28, max_iter=100000, log2w=plan.row_log2w())
+    assert (ig["status"], ig["iters"], ig["restarts"]) == (io["status"], io["iters"], io["restarts"])
+    assert_same_values(host(x), xo, "64^3 x")
+    assert_same_values(ig["rr_true"], io["rr_true"], "64^3 rr_true")
+    assert ig["status"] == 0
+    assert ref.exact_residual(row_ptr, col_idx, a, b, xo)["relres_upper"] <= 1e-28
+
+
 @pytest.mark.parametrize("precond", ["none", "jacobi"])
 def test_bicgstab_parity(mp, precond):
     row_ptr, col_idx, a = banded_nonsymmetric(n=1000, seed=3)
