@@ -1681,74 +1681,53 @@ __global__ __launch_bounds__(256) void k_in_p(int64_t n, T *__restrict__ d, cons
 }
 
 // An inner step with the learned preconditioner, after q = A p and the chunk sums of
-// (p, q), in the chunk workgroups of the dot products: alpha = rho / (p, q) in every
-// workgroup, then for each row i of the chunk (thread_elem's rows of each thread)
+// (p, q): alpha = rho / (p, q) in every workgroup, then for each row i
 //   r_next[i] = r[i] - alpha q[i],   z[i] = sum_k M[i,k] (r[c_k] - alpha q[c_k]),
 // the neighbours' new residual recomputed from the old r and q with the same two
-// roundings, so z = M r_next without a grid-wide wait for r_next; and from them the
-// chunk sums of (r_next, z) and (r_next, r_next) in the order of k_in_dot2.  r and
-// r_next are two buffers that alternate from step to step.
+// roundings, so z = M r_next without a grid-wide wait for r_next.  r and r_next are
+// two buffers that alternate from step to step.
 template <typename T>
-__global__ __launch_bounds__(kChunkThreads) void k_in_mupdate_c(int64_t n, const int32_t *__restrict__ rp,
-                                                                const int32_t *__restrict__ ci,
-                                                                const T *__restrict__ mv, const T *__restrict__ r,
-                                                                const T *__restrict__ q, T *__restrict__ r_next,
-                                                                T *__restrict__ z, const T *__restrict__ ppq, int m,
-                                                                T *__restrict__ prz, T *__restrict__ prr,
-                                                                InState<T> *__restrict__ st)
+__global__ __launch_bounds__(256) void k_in_mupdate(int64_t n, const int32_t *__restrict__ rp,
+                                                    const int32_t *__restrict__ ci, const T *__restrict__ mv,
+                                                    const T *__restrict__ r, const T *__restrict__ q,
+                                                    T *__restrict__ r_next, T *__restrict__ z,
+                                                    const T *__restrict__ ppq, int m, InState<T> *__restrict__ st)
 {
-    constexpr int G = 8;   // elements per row loaded at once (the 7-point rows in one round)
-    __shared__ T chain[2][kDotLanes];
     __shared__ T P[kMaxChunks];
-    const int c = xcd_block(blockIdx.x, gridDim.x);
-    const int nv = thread_valid(n, c);
     const T pq_pre = m <= 64 ? tree_pre(ppq, m) : T(0);
     T alpha;
     if (!in_alpha(ppq, m, pq_pre, st, P, &alpha)) return;
-    T pr[2][kPerThread];
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const int32_t b = rp[i], e = rp[i + 1];
+        const T aqi = alpha * q[i];
+        r_next[i] = r[i] - aqi;
+        T s = T(0);
+        for (int32_t k0 = b; k0 < e; k0 += 8) {
+            T av[8], rv[8], qv[8];
+            int32_t cv[8];
+            // branch-free loads and gathers (a slot past the row's end re-reads its first
+            // element), so every gather of the group is in flight at once
 #pragma unroll
-    for (int jj = 0; jj < kPerThread; ++jj) {
-        if (jj < nv) {
-            const int64_t i = thread_elem(c, jj);
-            const int32_t b = rp[i], e = rp[i + 1];
-            const T rn = r[i] - alpha * q[i];
-            r_next[i] = rn;
-            T s = T(0);
-            for (int32_t k0 = b; k0 < e; k0 += G) {
-                T av[G], rv[G], qv[G];
-                int32_t cv[G];
-#pragma unroll
-                for (int j = 0; j < G; ++j) {
-                    const int32_t k = k0 + j < e ? k0 + j : b;
-                    av[j] = mv[k];
-                    cv[j] = ci[k];
-                }
-#pragma unroll
-                for (int j = 0; j < G; ++j) {
-                    rv[j] = r[cv[j]];
-                    qv[j] = q[cv[j]];
-                }
-#pragma unroll
-                for (int j = 0; j < G; ++j)
-                    if (k0 + j < e) {
-                        const T aq = alpha * qv[j];
-                        const T rj = rv[j] - aq;
-                        const T prod = av[j] * rj;
-                        s = (k0 + j == b) ? prod : s + prod;
-                    }
+            for (int j = 0; j < 8; ++j) {
+                const int32_t k = k0 + j < e ? k0 + j : b;
+                av[j] = mv[k];
+                cv[j] = ci[k];
             }
-            z[i] = s;
-            pr[0][jj] = rn * s;
-            pr[1][jj] = rn * rn;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                rv[j] = r[cv[j]];
+                qv[j] = q[cv[j]];
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (k0 + j < e) {
+                    const T aq = alpha * qv[j];
+                    const T rn = rv[j] - aq;
+                    const T prod = av[j] * rn;
+                    s = (k0 + j == b) ? prod : s + prod;
+                }
         }
-    }
-    lane_chain<T, 2>(pr, nv, chain);
-    const int used = chunk_used(n, c);
-    T sums[2];
-    chain_fold_lead<T, 2>(chain, used, sums);
-    if (threadIdx.x == 0) {
-        prz[c] = sums[0];
-        prr[c] = sums[1];
+        z[i] = s;
     }
 }
 
@@ -2434,8 +2413,10 @@ mp_status inner_solve(Solver &S, const double *r_dd, int e, const T *a_in, const
             if (mv) {
                 // the residual alternates between r and r0 (free after the start)
                 T *rc = (it & 1) ? r0 : r, *rn = (it & 1) ? r : r0;
-                hipLaunchKernelGGL(k_in_mupdate_c<T>, dim3(m), dim3(kChunkThreads), 0, S.s, n, S.A->row_ptr,
-                                   S.A->col_idx, mv, rc, q, rn, z, part0, m, part1, part2, sr);
+                hipLaunchKernelGGL(k_in_mupdate<T>, dim3(S.vblocks), dim3(256), 0, S.s, n, S.A->row_ptr,
+                                   S.A->col_idx, mv, rc, q, rn, z, part0, m, sr);
+                hipLaunchKernelGGL(k_in_dot2<T>, dim3(m), dim3(kChunkThreads), 0, S.s, n, rn, z, rn, rn, part1, part2,
+                                   sr);
             } else {
                 hipLaunchKernelGGL(k_in_update<T>, dim3(m), dim3(kChunkThreads), 0, S.s, n, r, z, q, minv, part0, m,
                                    part1, part2, sr);
