@@ -554,15 +554,17 @@ mp_status mpkrylov_cg_batched(const mp_csr *A, const double *a, const double *B,
 
 /* ---------------------------------------------------------------------------
  * Learned preconditioner (layer on the paper's method, for the refinement's inner
- * solve): a message-passing network over the graph of an SPD matrix with a symmetric
- * pattern and sorted columns predicts M = S (I + C) S on A's pattern (S = D^-1/2,
- * C symmetric with |c_ij| <= 1/2 and diagonal 1 + sum_j |c_ij| + delta_i, delta_i >= 0,
- * so M is SPD; zero weights give exactly M = D^-1).  Network, with w_ij =
- * -hi(a_ij)/sqrt(hi(a_ii) hi(a_jj)) and node features f_i = [sum_j w_ij,
- * sum_j w_ij^2, deg_i/8, 1]:
+ * solve): a message-passing network over the graph of a Stieltjes matrix (SPD with
+ * non-positive off-diagonal entries, like every diffusion matrix; symmetric pattern,
+ * sorted columns) predicts M = S (I + Delta + G o W) S on A's pattern (S = D^-1/2,
+ * W = the scaled negated off-diagonal part, g_ij in [0, 1) symmetric, Delta >= 0
+ * diagonal): a damped first-order Neumann approximation of A^-1 = S (I - W)^-1 S.  M
+ * is SPD (W >= 0 has spectral radius below 1, so does G o W <= W), and zero weights
+ * give exactly M = D^-1.  Network, with w_ij = -hi(a_ij)/sqrt(hi(a_ii) hi(a_jj)) and
+ * node features f_i = [sum_j w_ij, sum_j w_ij^2, deg_i/8, 1]:
  *   h0 = relu(f W0 + b0); three layers h = relu(h Ws + (sum_j w_ij h_j) Wn + b);
- *   u_i = h_i.wu + bu; v_ij = sum_k qv_k h_ik h_jk + bv; c_ij = tanh(v_ij)/2;
- *   delta_i = softplus(u_i) - softplus(0).
+ *   u_i = h_i.wu + bu; v_ij = sum_k qv_k h_ik h_jk + bv; g_ij = tanh(v_ij)^2;
+ *   M_ij = g_ij w_ij sqrt(m_i m_j) (i != j), M_ii = (1 + log(1 + u_i^2)) m_i, m = 1/a_ii.
  * Hidden width 64; 25218 parameters, float32 master copy in this order: W0 (4x64,
  * row-major), b0, then per layer Ws (64x64), Wn (64x64), b; then wu, bu, qv, bv.
  * Weights and dense-layer inputs are rounded to bfloat16 (nearest-even) when used,
@@ -595,8 +597,8 @@ mp_status mp_mpnn_zero_grads(mp_mpnn *net, void *stream);
 /*
  * Build the graph of A: a = DD values (device, 2*nnz; only hi is read).  The graph
  * keeps pointers to A's row_ptr/col_idx and to a: they must stay valid and unchanged
- * while it exists.  MP_ERR_INVALID_ARG unless every row has a positive diagonal and
- * every off-diagonal entry its transpose (columns sorted).  Synchronises.
+ * while it exists.  MP_ERR_INVALID_ARG unless every row has a positive diagonal, every
+ * off-diagonal entry is <= 0 and has its transpose (columns sorted).  Synchronises.
  */
 mp_status mp_graph_create(const mp_csr *A, const double *a, void *stream, mp_graph **out);
 mp_status mp_graph_destroy(mp_graph *g);

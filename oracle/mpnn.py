@@ -6,17 +6,22 @@ finite differences.  With ``bf16=True`` the weights and every dense-layer input 
 rounded to bfloat16 (round-to-nearest-even on the float32 bit pattern), as the GPU
 does; the backward pass treats that rounding as the identity (straight-through).
 
-Definition (a learned "diagonal plus neighbour" approximate inverse of an SPD matrix
-A with a symmetric pattern; hi = leading binary64 component of the DD values):
+Definition (a learned "diagonal plus neighbour" approximate inverse of a Stieltjes
+matrix A -- SPD with non-positive off-diagonal entries, like every diffusion matrix --
+with a symmetric pattern; hi = leading binary64 component of the DD values):
   minv_i = 1 / hi(a_ii);  w_ij = -hi(a_ij) / sqrt(hi(a_ii) hi(a_jj))  (i != j), float32
   features f_i = [sum_j w_ij, sum_j w_ij^2, deg_i / 8, 1]            (float32)
   h0 = relu(f W0 + b0)                                                 (4 -> 64)
   layer l = 1..3:  m_i = sum_j w_ij h_j  (row order);  h = relu(h Ws_l + m Wn_l + b_l)
   u_i = h_i . wu + bu;   v_ij = sum_k qv_k (h_ik h_jk) + bv               (v_ij = v_ji)
-  c_ij = gamma tanh(v_ij) (gamma = 0.5);  delta_i = softplus(u_i) - softplus(0)
-  M_ii = (1 + sum_j |c_ij| + delta_i) minv_i;  M_ij = c_ij sqrt(minv_i minv_j)
-M is symmetric and strictly diagonally dominant after the symmetric scaling, so it is
-SPD; with every weight zero (and zero biases) M is exactly the Jacobi inverse diagonal.
+  g_ij = tanh(v_ij)^2 in [0, 1);  c_ij = g_ij w_ij;  delta_i = log(1 + u_i^2) >= 0
+  M_ii = (1 + delta_i) minv_i;  M_ij = c_ij sqrt(minv_i minv_j)
+that is M = S (I + Delta + G o W) S with S = D^-1/2: a damped first-order Neumann
+approximation of A^-1 = S (I - W)^-1 S (g = 1, delta = 0 is exactly I + W).  M is SPD:
+W >= 0 entrywise with spectral radius rho(W) < 1 (I - W = S A S is SPD), so
+0 <= G o W <= W entrywise has rho(G o W) <= rho(W) < 1, every eigenvalue of G o W
+exceeds -1, and I + Delta + G o W with Delta >= 0 is positive definite.  With every
+weight zero (and zero biases) M is exactly the Jacobi inverse diagonal.
 Training loss of a pair (r, e):  L = (M r - e)^T A (M r - e) / e^T A e.
 
 Parameter vector (float32, this order): W0 (4x64 row-major), b0 (64), then for l = 1..3:
@@ -26,7 +31,6 @@ import numpy as np
 
 HIDDEN = 64
 NFEAT = 4
-GAMMA = 0.5
 
 
 def param_shapes(hidden=HIDDEN):
@@ -115,10 +119,10 @@ def forward(g, theta, bf=False):
     Hq = q(H)
     u = Hq @ q(p["wu"]) + p["bu"][0]
     v = (Hq[g.rows] * Hq[g.ci]) @ q(p["qv"]) + p["bv"][0]
-    cc = np.where(g.offd, GAMMA * np.tanh(v), 0.0)
-    delta = np.logaddexp(0.0, u) - np.log(2.0)
-    absum = np.bincount(g.rows, weights=np.abs(cc), minlength=g.n)
-    diag = 1.0 + absum + delta
+    th = np.tanh(v)
+    cc = np.where(g.offd, th * th * g.w, 0.0)
+    delta = np.log1p(u * u)
+    diag = 1.0 + delta
     M = np.where(g.offd, cc * np.sqrt(g.minv[g.rows] * g.minv[g.ci]), 0.0)
     dmask = ~g.offd
     M[dmask] = diag[g.rows[dmask]] * g.minv[g.rows[dmask]]
@@ -142,10 +146,10 @@ def backward(g, theta, r, e, bf=False):
     p, q = c["p"], c["q"]
     rows, ci = g.rows, g.ci
     G = gy * r * g.minv                        # dL/d diag_i
-    sgn = np.sign(c["cc"])
-    dc = np.where(g.offd, gy[rows] * r[ci] * np.sqrt(g.minv[rows] * g.minv[ci]) + sgn * G[rows], 0.0)
-    dv = np.where(g.offd, dc * GAMMA * (1.0 - np.tanh(c["v"]) ** 2), 0.0)
-    du = G / (1.0 + np.exp(-c["u"]))
+    dc = np.where(g.offd, gy[rows] * r[ci] * np.sqrt(g.minv[rows] * g.minv[ci]), 0.0)
+    th = np.tanh(c["v"])
+    dv = np.where(g.offd, dc * g.w * 2.0 * th * (1.0 - th * th), 0.0)
+    du = G * 2.0 * c["u"] / (1.0 + c["u"] * c["u"])
     grads = {k: np.zeros_like(v) for k, v in p.items()}
     Hq = c["Hq"]
     qv = q(p["qv"])

@@ -3,16 +3,19 @@
 // backward and Adam kernels.  Not part of the paper's method (the paper lists
 // mixed-precision preconditioned Krylov methods as future work, Sec. 5).
 //
-// For an SPD matrix A with a symmetric pattern (hi = leading DD component):
+// For a Stieltjes matrix A (SPD, non-positive off-diagonal entries, like every diffusion
+// matrix) with a symmetric pattern (hi = leading DD component):
 //   minv_i = 1/hi(a_ii);  w_ij = -hi(a_ij)/sqrt(hi(a_ii) hi(a_jj))           (float)
 //   f_i = [sum_j w_ij, sum_j w_ij^2, deg_i/8, 1]
 //   h0 = relu(f W0 + b0);  l = 1..3: m_i = sum_j w_ij h_j,  h = relu(h Ws + m Wn + b)
 //   u_i = h_i.wu + bu;  v_ij = sum_k qv_k (h_ik h_jk) + bv                   (v_ij = v_ji)
-//   c_ij = 0.5 tanh(v_ij);  delta_i = softplus(u_i) - softplus(0)
-//   M_ii = (1 + sum_j |c_ij| + delta_i) minv_i;  M_ij = c_ij sqrt(minv_i minv_j)
-// M is symmetric and (after the symmetric Jacobi scaling) strictly diagonally
-// dominant with a positive diagonal, hence SPD; with zero weights it is exactly the
-// Jacobi inverse diagonal.  Training loss of a pair (r, e = A^-1 r):
+//   g_ij = tanh(v_ij)^2 in [0, 1);  c_ij = g_ij w_ij;  delta_i = log(1 + u_i^2) >= 0
+//   M_ii = (1 + delta_i) minv_i;  M_ij = c_ij sqrt(minv_i minv_j)
+// i.e. M = S (I + Delta + G o W) S with S = D^-1/2, a damped first-order Neumann
+// approximation of A^-1 = S (I - W)^-1 S.  M is SPD: W >= 0 entrywise with spectral
+// radius below 1 (I - W = S A S is SPD), so rho(G o W) <= rho(W) < 1 and I + Delta +
+// G o W is positive definite.  With zero weights M is exactly the Jacobi inverse
+// diagonal.  Training loss of a pair (r, e = A^-1 r):
 //   L = (M r - e)^T A (M r - e) / e^T A e.
 // Weights are bfloat16 values (the float32 master copy is rounded to nearest-even on
 // every use); dense-layer inputs are rounded to bfloat16 too and products accumulate in
@@ -32,7 +35,6 @@ namespace mpk {
 
 constexpr int kH = 64;        // hidden width
 constexpr int kF = 4;         // node features
-constexpr float kGamma = 0.5f;
 constexpr int kNodeBlock = 256;   // nodes per partial-gradient block
 constexpr int kEdgeBlock = 1024;  // edges per partial-gradient block
 
@@ -127,7 +129,9 @@ __global__ __launch_bounds__(256) void k_g_edges(int32_t n, const int32_t *__res
             const int32_t j = ci[k];
             float wk = 0.f;
             if (j != i) {
-                // 1/sqrt(a_ii a_jj) = sqrt(minv_i minv_j)
+                // 1/sqrt(a_ii a_jj) = sqrt(minv_i minv_j); a positive off-diagonal entry
+                // (not a Stieltjes matrix) is refused
+                if (a[k] > 0.0) atomicMin(bad, (int32_t)i);
                 wk = (float)(-a[k] * sqrt(minv[i] * minv[j]));
                 ++deg;
                 // reverse element (j, i): columns of row j are sorted
@@ -365,15 +369,14 @@ __global__ __launch_bounds__(256) void k_readout(int32_t n, int64_t nnz, const i
     }
 }
 
-// c_ij, diagonal and M (float64) on the pattern; one thread per row
+// c_ij = tanh(v_ij)^2 w_ij, the diagonal and M (float64) on the pattern; one thread per row
 __global__ __launch_bounds__(256) void k_assemble(int32_t n, const int32_t *__restrict__ rp,
                                                   const int32_t *__restrict__ ci, const float *__restrict__ u,
-                                                  const float *__restrict__ v, const double *__restrict__ minv,
-                                                  float *__restrict__ c, double *__restrict__ M)
+                                                  const float *__restrict__ v, const float *__restrict__ w,
+                                                  const double *__restrict__ minv, float *__restrict__ c,
+                                                  double *__restrict__ M)
 {
-    const float sp0 = softplusf(0.f);
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        float absum = 0.f;
         int32_t kd = -1;
         for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
             const int32_t j = ci[k];
@@ -382,12 +385,12 @@ __global__ __launch_bounds__(256) void k_assemble(int32_t n, const int32_t *__re
                 c[k] = 0.f;
                 continue;
             }
-            const float ck = kGamma * tanhf(v[k]);
+            const float th = tanhf(v[k]);
+            const float ck = th * th * w[k];
             c[k] = ck;
-            absum += fabsf(ck);
             M[k] = (double)ck * sqrt(minv[i] * minv[j]);
         }
-        const float diag = 1.f + absum + (softplusf(u[i]) - sp0);
+        const float diag = 1.f + log1pf(u[i] * u[i]);
         if (kd >= 0) M[kd] = (double)diag * minv[i];
     }
 }
@@ -443,26 +446,27 @@ __global__ __launch_bounds__(256) void k_loss_final(const double *__restrict__ p
     out[1] = 2.0 / ee;
 }
 
-// gy = scale * Ad; du_i += G_i sigmoid(u_i); dv_k += dc_k gamma (1 - tanh^2 v_k), G_i = gy_i r_i minv_i
+// gy = scale * Ad; du_i += G_i 2 u_i / (1 + u_i^2) with G_i = gy_i r_i minv_i;
+// dv_k += dc_k w_k 2 tanh(v_k) (1 - tanh^2 v_k) with dc_k = gy_i r_j sqrt(minv_i minv_j)
 __global__ __launch_bounds__(256) void k_assemble_bwd(int32_t n, const int32_t *__restrict__ rp,
                                                       const int32_t *__restrict__ ci, const double *__restrict__ Ad,
                                                       const double *__restrict__ scale, const double *__restrict__ r,
                                                       const double *__restrict__ minv, const float *__restrict__ u,
-                                                      const float *__restrict__ v, const float *__restrict__ c,
+                                                      const float *__restrict__ v, const float *__restrict__ w,
                                                       float *__restrict__ du, float *__restrict__ dv)
 {
     const double sc = scale[1];
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         const double gi = sc * Ad[i];
         const double G = gi * r[i] * minv[i];
-        du[i] += (float)(G / (1.0 + exp(-(double)u[i])));
+        const double ui = (double)u[i];
+        du[i] += (float)(G * 2.0 * ui / (1.0 + ui * ui));
         for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
             const int32_t j = ci[k];
             if (j == i) continue;
-            const double sg = c[k] > 0.f ? 1.0 : (c[k] < 0.f ? -1.0 : 0.0);
-            const double dc = gi * r[j] * sqrt(minv[i] * minv[j]) + sg * G;
+            const double dc = gi * r[j] * sqrt(minv[i] * minv[j]);
             const double th = tanh((double)v[k]);
-            dv[k] += (float)(dc * (double)kGamma * (1.0 - th * th));
+            dv[k] += (float)(dc * (double)w[k] * 2.0 * th * (1.0 - th * th));
         }
     }
 }
@@ -651,7 +655,7 @@ mp_status mpnn_forward(const mp_mpnn *net, mp_graph *g, hipStream_t s)
     hipLaunchKernelGGL(k_readout, dim3(nb256(g->nnz > n ? g->nnz : n)), dim3(256), 0, s, n, g->nnz, g->d_rows,
                        g->col_idx, g->d_H[3], th, g->d_u, g->d_v);
     hipLaunchKernelGGL(k_assemble, dim3(nb256(n)), dim3(256), 0, s, n, g->row_ptr, g->col_idx, g->d_u, g->d_v,
-                       g->d_minv, g->d_c, g->d_M);
+                       g->d_w, g->d_minv, g->d_c, g->d_M);
     MP_HIP_TRY(hipGetLastError());
     return MP_OK;
 }
@@ -805,7 +809,9 @@ mp_status mp_graph_create(const mp_csr *A, const double *a, void *stream, mp_gra
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) st = hip_fail(e, "graph set-up");
         else if (h_bad != INT32_MAX)
-            st = fail(MP_ERR_INVALID_ARG, "row %d has no positive diagonal or an entry without its transpose", h_bad);
+            st = fail(MP_ERR_INVALID_ARG,
+                      "row %d has no positive diagonal, a positive off-diagonal entry or an entry without its transpose",
+                      h_bad);
     }
     if (d_bad) (void)hipFree(d_bad);
     if (st != MP_OK) {
@@ -866,7 +872,7 @@ mp_status mp_mpnn_loss_grad(mp_mpnn *net, mp_graph *g, const double *r, const do
         hipLaunchKernelGGL(k_dot64, dim3(m), dim3(256), 0, s, n, ep, Ae, pee);
         hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, s, pdd, pee, m, out + 2 * p);
         hipLaunchKernelGGL(k_assemble_bwd, dim3(nb256(n)), dim3(256), 0, s, n, g->row_ptr, g->col_idx, Ad, out + 2 * p,
-                           rp_, g->d_minv, g->d_u, g->d_v, g->d_c, g->d_du, g->d_dv);
+                           rp_, g->d_minv, g->d_u, g->d_v, g->d_w, g->d_du, g->d_dv);
         MP_HIP_TRY(hipGetLastError());
     }
     // readouts -> dH3 and readout parameter gradients

@@ -2,18 +2,21 @@
 evaluate it on held-out 64^3 systems.
 
 Training set: matrices from ``workloads.diffusion3d_7pt`` with grid edges uniform on
-[edge_lo, edge_hi] and lognormal coefficient spread sigma ~ U(sigma_lo, sigma_hi), one
-seed per matrix.  Each matrix is visited once (streamed, never stored): its (r, e)
-pairs come from plain DD Jacobi-CG iterates toward a random DD solution, and
-``steps_per_matrix`` Adam steps are taken on them.  Every arithmetic step runs in the
-HIP library (network forward/backward/Adam, CG, SpMV).
+[edge_lo, edge_hi], lognormal coefficient spread sigma ~ U(sigma_lo, sigma_hi) and the
+anisotropy factor of the calibrated 64^3 law (workloads/c2_law.json), one seed per
+matrix.  Each epoch streams the same matrices (regenerated from their seeds on host
+threads while the GPU trains, never stored): their (r, e) pairs come from plain DD
+Jacobi-CG iterates toward a random DD solution, and ``steps_per_matrix`` Adam steps
+are taken on them; the learning rate decays geometrically over all epochs.  Every
+arithmetic step runs in the HIP library (network forward/backward/Adam, CG, SpMV).
 
-Evaluation: held-out 64^3 systems (fresh seeds, same sigma law), each solved to a
-relative residual of 1e-28 by plain DD Jacobi-CG, Jacobi refinement and learned
-refinement (binary64 and binary32 inner solves); the network's forward pass is timed
-separately and included in the learned solve time.
+Evaluation: the two 64^3 systems of the solver benchmark and held-out 64^3 systems
+(fresh seeds, the training sigma law, the same anisotropy), each solved to a relative
+residual of 1e-28 by plain DD Jacobi-CG, Jacobi refinement and learned refinement
+(binary64 and binary32 inner solves); the network's forward pass is timed separately
+and included in the learned solve time.
 
-Usage:  python -m paper_2412_17510_amd.train_mpnn --matrices 2000 --out <ckpt.npz>
+Usage:  python -m paper_2412_17510_amd.train_mpnn --matrices 2000 --epochs 4 --out <ckpt.npz>
         python -m paper_2412_17510_amd.train_mpnn --eval-only --ckpt <ckpt.npz> --eval 200
 """
 import argparse
@@ -40,53 +43,75 @@ def _workloads():
     return workloads
 
 
+def _law_az():
+    wl = _workloads()
+    from workloads.condition import load_law
+    return load_law()["systems"][0]["az"]
+
+
 def train(n_matrices=2000, steps_per_matrix=2, edge_lo=24, edge_hi=48, sigma_lo=1.5, sigma_hi=3.0, seed=0,
-          lr=3e-3, lr_final=3e-4, log_every=100):
-    """Returns (theta, history).  history: list of (matrix index, n, mean loss of its pairs
-    before its first step)."""
+          lr=3e-3, lr_final=3e-4, log_every=250, epochs=1, az=None):
+    """Returns (theta, history, curve).  history: list of (epoch, matrix index, n, mean
+    loss of its pairs before its first step); curve: mean of those losses per epoch."""
     import torch
+    from concurrent.futures import ThreadPoolExecutor
     from . import _binding as mp
     from . import learned
     wl = _workloads()
+    if az is None:
+        az = _law_az()
     rng = np.random.default_rng([seed, 1])
+    law = [(int(rng.integers(edge_lo, edge_hi + 1)), float(rng.uniform(sigma_lo, sigma_hi)),
+            int(rng.integers(1, 2 ** 31 - 1))) for _ in range(n_matrices)]
+
+    def make(item):
+        m, sg, ms = item
+        rp, ci, a = wl.diffusion3d_7pt(m=m, sigma=sg, az=az, seed=ms)
+        return rp, ci, a, wl.random_mp(rp.size - 1, 2, np.random.default_rng(ms))
+
     net = mp.Mpnn()
     net.set_params(learned.init_params(seed))
     step = 0
-    total_steps = n_matrices * steps_per_matrix
-    history = []
+    total_steps = epochs * n_matrices * steps_per_matrix
+    history, curve = [], []
     t0 = time.perf_counter()
-    run_loss, run_cnt = 0.0, 0
-    for i in range(n_matrices):
-        m = int(rng.integers(edge_lo, edge_hi + 1))
-        sg = float(rng.uniform(sigma_lo, sigma_hi))
-        ms = int(rng.integers(1, 2 ** 31 - 1))
-        rp, ci, a = wl.diffusion3d_7pt(m=m, sigma=sg, seed=ms)
-        n = rp.size - 1
-        A = mp.Csr.from_numpy(rp, ci)
-        ad = torch.from_numpy(a).cuda()
-        xt = torch.from_numpy(wl.random_mp(n, 2, np.random.default_rng(ms))).cuda()
-        R, E = learned.cg_pairs(A, ad, xt)
-        g = mp.Graph(A, ad)
-        for s in range(steps_per_matrix):
-            frac = step / max(1, total_steps - 1)
-            lr_s = lr * (lr_final / lr) ** frac
-            net.zero_grads()
-            losses = mp.mp_mpnn_loss_grad(net, g, R, E)
-            if s == 0:
-                history.append((i, n, float(losses.mean())))
-                run_loss += float(losses.mean())
-                run_cnt += 1
-            step += 1
-            net.adam_step(step, lr=lr_s, grad_scale=1.0 / losses.size)
-        g.destroy()
-        del A, ad, xt, R, E
-        if (i + 1) % log_every == 0 or i + 1 == n_matrices:
-            torch.cuda.synchronize()
-            _log("matrix %d/%d  mean loss (last %d) %.5f  %.1f s" % (i + 1, n_matrices, run_cnt,
-                                                                     run_loss / max(1, run_cnt),
-                                                                     time.perf_counter() - t0))
-            run_loss, run_cnt = 0.0, 0
-    return net.get_params(), history
+    with ThreadPoolExecutor(max_workers=4) as pool:
+        for ep in range(epochs):
+            pending = [pool.submit(make, law[i]) for i in range(min(8, n_matrices))]
+            ep_loss, run_loss, run_cnt = 0.0, 0.0, 0
+            for i in range(n_matrices):
+                rp, ci, a, xt_h = pending.pop(0).result()
+                if i + len(pending) + 1 < n_matrices:
+                    pending.append(pool.submit(make, law[i + len(pending) + 1]))
+                n = rp.size - 1
+                A = mp.Csr.from_numpy(rp, ci)
+                ad = torch.from_numpy(a).cuda()
+                xt = torch.from_numpy(xt_h).cuda()
+                R, E = learned.cg_pairs(A, ad, xt)
+                g = mp.Graph(A, ad)
+                for s in range(steps_per_matrix):
+                    frac = step / max(1, total_steps - 1)
+                    lr_s = lr * (lr_final / lr) ** frac
+                    net.zero_grads()
+                    losses = mp.mp_mpnn_loss_grad(net, g, R, E)
+                    if s == 0:
+                        lm = float(losses.mean())
+                        history.append((ep, i, n, lm))
+                        ep_loss += lm
+                        run_loss += lm
+                        run_cnt += 1
+                    step += 1
+                    net.adam_step(step, lr=lr_s, grad_scale=1.0 / losses.size)
+                g.destroy()
+                del A, ad, xt, R, E
+                if (i + 1) % log_every == 0 or i + 1 == n_matrices:
+                    torch.cuda.synchronize()
+                    _log("epoch %d matrix %d/%d  mean loss (last %d) %.5f  %.1f s" % (
+                        ep + 1, i + 1, n_matrices, run_cnt, run_loss / max(1, run_cnt), time.perf_counter() - t0))
+                    run_loss, run_cnt = 0.0, 0
+            curve.append(ep_loss / n_matrices)
+            _log("epoch %d mean pair loss %.5f" % (ep + 1, curve[-1]))
+    return net.get_params(), history, curve
 
 
 def _solve(fn, *args, **kw):
@@ -94,24 +119,28 @@ def _solve(fn, *args, **kw):
 
 
 def evaluate(theta, n_systems=8, m=64, sigma_lo=1.5, sigma_hi=3.0, seed=7, inner=("fp64", "fp32"),
-             include_sigma25=True, log=True):
+             include_bench=True, log=True, az=None):
     """Per-system and summary results of plain DD CG, Jacobi refinement and learned
     refinement on held-out m^3 systems (relative residual 1e-28)."""
     import torch
     from . import _binding as mp
     wl = _workloads()
+    if az is None:
+        az = _law_az()
     net = mp.Mpnn()
     net.set_params(theta)
     rng = np.random.default_rng([seed, 2])
     systems = []
-    if include_sigma25:
-        systems.append((2.5, 2))            # the 64^3 sigma = 2.5 system of the solver benchmark
+    if include_bench:
+        from workloads.condition import load_law
+        for law in load_law()["systems"]:   # the 64^3 systems of the solver benchmark
+            systems.append((law["sigma"], law["seed"]))
     while len(systems) < n_systems:
         systems.append((float(rng.uniform(sigma_lo, sigma_hi)), int(rng.integers(10 ** 6, 2 ** 31 - 1))))
     inner_rtol = {"fp64": 1e-8, "fp32": 1e-5}
     rows = []
     for k, (sg, ms) in enumerate(systems):
-        rp, ci, a = wl.diffusion3d_7pt(m=m, sigma=sg, seed=ms)
+        rp, ci, a = wl.diffusion3d_7pt(m=m, sigma=sg, az=az, seed=ms)
         n = rp.size - 1
         A = mp.Csr.from_numpy(rp, ci)
         ad = torch.from_numpy(a).cuda()
@@ -182,6 +211,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--matrices", type=int, default=2000)
     ap.add_argument("--steps-per-matrix", type=int, default=2)
+    ap.add_argument("--epochs", type=int, default=1)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--out", default=DEFAULT_CKPT)
@@ -197,15 +227,18 @@ def main():
         theta = learned.load(args.ckpt)
     else:
         t0 = time.perf_counter()
-        theta, hist = train(args.matrices, args.steps_per_matrix, seed=args.seed, lr=args.lr)
+        theta, hist, curve = train(args.matrices, args.steps_per_matrix, seed=args.seed, lr=args.lr,
+                                   epochs=args.epochs)
         secs = time.perf_counter() - t0
         os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
-        first = float(np.mean([h[2] for h in hist[:50]]))
-        last = float(np.mean([h[2] for h in hist[-50:]]))
+        first = float(np.mean([h[3] for h in hist[:50]]))
+        last = float(np.mean([h[3] for h in hist[-50:]]))
         learned.save(args.out, theta, matrices=args.matrices, steps_per_matrix=args.steps_per_matrix,
-                     seed=args.seed, train_seconds=secs, loss_first50=first, loss_last50=last)
-        _log("saved %s: %d matrices in %.1f s, mean pair loss %.4f (first 50) -> %.4f (last 50)"
-             % (args.out, args.matrices, secs, first, last))
+                     epochs=args.epochs, seed=args.seed, train_seconds=secs, loss_first50=first, loss_last50=last,
+                     az=_law_az(), epoch_loss=np.asarray(curve))
+        _log("saved %s: %d matrices x %d epochs in %.1f s, mean pair loss %.4f (first 50) -> %.4f (last 50); "
+             "per epoch %s" % (args.out, args.matrices, args.epochs, secs, first, last,
+                               " ".join("%.4f" % c for c in curve)))
     if args.eval > 0:
         res = evaluate(theta, n_systems=args.eval)
         _log(json.dumps(res["summary"]))

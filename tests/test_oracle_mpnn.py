@@ -4,6 +4,10 @@
   ties to even), including exact ties;
 * with every parameter zero the network's M is exactly the Jacobi inverse diagonal;
 * for random (large) weights M is symmetric and positive definite, and v_ij = v_ji;
+* with g_ij -> 1 and delta = 0 (readout bias bv large, every other weight zero) M is
+  the first-order Neumann approximate inverse D^-1 + D^-1 N D^-1 (N = the negated
+  off-diagonal part of A), entry for entry, and still positive definite on a strongly
+  heterogeneous matrix;
 * the analytic gradient equals central finite differences of the loss (binary64
   network, every parameter block, relative-or-absolute tolerance);
 * the loss is 0 with a zero gradient when e = M r;
@@ -67,6 +71,24 @@ def test_m_is_spd_and_symmetric(scale):
     assert np.linalg.eigvalsh(D).min() > 0.0
     if scale >= 3.0:   # off-diagonal entries are really used (not a degenerate diagonal M)
         assert np.abs(M[g.offd]).max() > 1e-3 * np.abs(M[~g.offd]).max()
+
+
+def test_neumann_limit():
+    g, rp, ci, a = graph(m=5, seed=36, sigma=3.0)
+    p = {name: np.zeros(shp) for name, shp in mpnn.param_shapes()}
+    p["bv"] = np.array([20.0])           # tanh(20)^2 = 1 to binary64 precision
+    theta = mpnn.pack(p)
+    M, c = mpnn.forward(g, theta)
+    hi = a[0]
+    diag = np.zeros(g.n)
+    diag[g.rows[~g.offd]] = hi[~g.offd]
+    want = np.where(g.offd, -hi / (diag[g.rows] * diag[g.ci]), 1.0 / diag[g.rows])
+    # w is held in float32 (the network's input), so agreement is to float32 rounding
+    np.testing.assert_allclose(M, want, rtol=2e-7, atol=0)
+    n = g.n
+    D = np.zeros((n, n))
+    D[g.rows, g.ci] = M
+    assert np.linalg.eigvalsh(D).min() > 0.0
 
 
 def test_gradient_matches_finite_differences():
