@@ -721,11 +721,12 @@ __device__ __forceinline__ void long_tile_staged(const SpmvArgs &A, const uint8_
 
 // Complex variants whose tiles run as two passes of two accumulator sets (H = 1, 2):
 // QD, whose four staged sets of a 256-element tile fill 32 KiB of LDS and leave room
-// for four workgroups per CU; each pass stages half of that.
+// for four workgroups per CU, and TD (24 KiB; measured 1.57 -> 1.38 ms on the 1e6-row
+// power-law matrix); each pass stages half of that.
 template <int K, bool CPLX, bool DM>
 constexpr bool two_pass()
 {
-    return CPLX && K == 4 && !DM;
+    return CPLX && K >= 3 && !DM;
 }
 
 // workgroups per CU asked of a two-pass tile kernel

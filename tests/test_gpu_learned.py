@@ -276,7 +276,7 @@ def test_training_beats_jacobi_on_held_out(mp):
     assert tot_l < 0.9 * tot_j, (tot_l, tot_j)
 
 
-def test_trained_network_wins_on_time():
+def test_trained_network_wins_on_time(mp):
     """The committed network on the benchmark's sigma = 2.5 64^3 system: learned refinement
     (forward pass included) solves to 1e-28 in less wall time than Jacobi refinement
     (best of three each, binary64 inner), with under 0.7x its inner iterations, and
