@@ -561,7 +561,8 @@ def main():
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=6.0)
-    ap.add_argument("--plan", default="autotune", help="autotune | canonical | shift,max_log2w,tile_nnz")
+    ap.add_argument("--plan", default="autotune",
+                    help="autotune | canonical | shift,max_log2w,tile_nnz[,row_groups]")
     ap.add_argument("--workload", default="spmv", choices=["spmv", "batched", "locality", "solves"],
                     help="spmv (default: power-law SpMV line plus the 64^3 solves), batched (256 systems x 8 rhs), "
                          "locality (the DD SpMV on three column laws with the same row lengths) or solves (only "
@@ -651,11 +652,13 @@ def main():
             plan, pol = mp.mp_plan_autotune(A, K, ad_re, xd_re, y_re, ad_im, xd_im, y_im, reps=5)
         elif args.plan == "canonical":
             plan = mp.mp_plan_create(A, K, cplx)
-            pol = {"shift": 0, "max_log2w": 6, "tile_nnz": plan.info()["tile_nnz"]}
+            pol = {"shift": 0, "max_log2w": 6, "tile_nnz": plan.info()["tile_nnz"], "row_groups": 0}
         else:
-            s, m, c = (int(v) for v in args.plan.split(","))
-            plan = mp.mp_plan_create(A, K, cplx, s, m, c)
-            pol = {"shift": s, "max_log2w": m, "tile_nnz": plan.info()["tile_nnz"]}
+            v = [int(t) for t in args.plan.split(",")]
+            s, m, c = v[:3]
+            rg = v[3] if len(v) > 3 else 0
+            plan = mp.mp_plan_create(A, K, cplx, s, m, c, rg)
+            pol = {"shift": s, "max_log2w": m, "tile_nnz": plan.info()["tile_nnz"], "row_groups": rg}
         fn = mp.SPMV[(K, cplx)]
         ws = mp.spmv_workspace(plan)
         if cplx:

@@ -71,7 +71,8 @@ typedef struct {
 /* Opaque execution plan of one pattern for one variant (K components, real or
  * complex): the per-row lane widths (the summation order) and the work decomposition
  * one SpMV launch walks -- contiguous row tiles of at most tile_nnz elements whose
- * products are staged in LDS, and single-row tiles for longer rows.  Owned by the
+ * products are staged in LDS, single-row tiles for longer rows, and (row_groups)
+ * wavefronts that each sum up to 64 / W rows of one lane width W in registers.  Owned by the
  * library and read-only after creation: SpMV calls that share a plan may run
  * concurrently on several streams (each with its own workspace). */
 typedef struct mp_plan mp_plan;
@@ -86,6 +87,8 @@ typedef struct {
     int32_t shift;      /* 0..12: aim at >= 2^shift elements per lane */
     int32_t max_log2w;  /* 0..10: widest lane group (1024 lanes) */
     int32_t tile_nnz;   /* 0 or 256..2048 (power of two) */
+    int32_t row_groups; /* 0: every row in tiles; 1: rows with W <= 64 and at most 16
+                           elements per lane summed in wavefront lane groups (same order) */
 } mp_plan_opts;
 
 /* Last error message of the calling thread ("" if none).  Static storage. */

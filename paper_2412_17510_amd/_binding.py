@@ -34,7 +34,8 @@ class mp_csr(ctypes.Structure):
 
 
 class mp_plan_opts(ctypes.Structure):
-    _fields_ = [("shift", ctypes.c_int32), ("max_log2w", ctypes.c_int32), ("tile_nnz", ctypes.c_int32)]
+    _fields_ = [("shift", ctypes.c_int32), ("max_log2w", ctypes.c_int32), ("tile_nnz", ctypes.c_int32),
+                ("row_groups", ctypes.c_int32)]
 
 
 class mp_solve_opts(ctypes.Structure):
@@ -273,10 +274,10 @@ def mp_measure_rate(kind, stream=None):
     return v.value
 
 
-def mp_plan_create(A, ncomp, is_complex=False, shift=0, max_log2w=6, tile_nnz=0, stream=None):
+def mp_plan_create(A, ncomp, is_complex=False, shift=0, max_log2w=6, tile_nnz=0, row_groups=0, stream=None):
     """Plan for pattern A and variant (ncomp, is_complex); canonical order by default."""
     h = ctypes.c_void_p()
-    opts = mp_plan_opts(shift, max_log2w, tile_nnz)
+    opts = mp_plan_opts(shift, max_log2w, tile_nnz, int(row_groups))
     _check(_lib.mp_plan_create(ctypes.byref(A.c), ncomp, int(bool(is_complex)), ctypes.byref(opts),
                                _stream_ptr(stream), ctypes.byref(h)), "mp_plan_create")
     return Plan(h.value, A.n_rows)
@@ -294,14 +295,15 @@ def mp_plan_create_explicit(A, ncomp, is_complex, log2w, tile_nnz=0, stream=None
 
 
 def mp_plan_autotune(A, ncomp, a_re, x_re, y_re, a_im=None, x_im=None, y_im=None, reps=3, stream=None):
-    """Autotuned plan; returns (Plan, {"shift", "max_log2w", "tile_nnz"})."""
+    """Autotuned plan; returns (Plan, {"shift", "max_log2w", "tile_nnz", "row_groups"})."""
     cplx = a_im is not None
     h = ctypes.c_void_p()
     opts = mp_plan_opts()
     _check(_lib.mp_plan_autotune(ctypes.byref(A.c), ncomp, int(cplx), _ptr(a_re), _ptr(a_im), _ptr(x_re),
                                  _ptr(x_im), _ptr(y_re), _ptr(y_im), reps, _stream_ptr(stream), ctypes.byref(h),
                                  ctypes.byref(opts)), "mp_plan_autotune")
-    return Plan(h.value, A.n_rows), {"shift": opts.shift, "max_log2w": opts.max_log2w, "tile_nnz": opts.tile_nnz}
+    return Plan(h.value, A.n_rows), {"shift": opts.shift, "max_log2w": opts.max_log2w, "tile_nnz": opts.tile_nnz,
+                                     "row_groups": opts.row_groups}
 
 
 def _spmv_real(name, K):

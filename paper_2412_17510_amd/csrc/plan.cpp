@@ -20,6 +20,8 @@ void plan_free(mp_plan *p)
     if (p->d_log2w) (void)hipFree(p->d_log2w);
     if (p->d_wide_rows) (void)hipFree(p->d_wide_rows);
     if (p->d_wide) (void)hipFree(p->d_wide);
+    if (p->d_rg) (void)hipFree(p->d_rg);
+    if (p->d_rg_rows) (void)hipFree(p->d_rg_rows);
     delete p;
 }
 
@@ -72,7 +74,7 @@ mp_status resolve_tile(int32_t ncomp, int32_t is_complex, int32_t requested, int
 }  // namespace
 
 mp_status plan_build(const std::vector<int32_t> &rp, std::vector<uint8_t> &&log2w, int64_t nnz, int32_t n_cols,
-                     int K, bool cplx, int C, hipStream_t s, mp_plan **out)
+                     int K, bool cplx, int C, bool row_groups, hipStream_t s, mp_plan **out)
 {
     const int32_t n = (int32_t)rp.size() - 1;
     mp_plan *p = new (std::nothrow) mp_plan;
@@ -88,7 +90,41 @@ mp_status plan_build(const std::vector<int32_t> &rp, std::vector<uint8_t> &&log2
     std::vector<int32_t> wide_rows;
     std::vector<mp_tile> wide;
     tiles.reserve((size_t)(nnz / C + 16));
-    int32_t i = 0;
+    std::vector<mp_rg_wave> rg;
+    std::vector<int32_t> rg_rows;
+    if (row_groups) {
+        // rows with W <= 64 and at most kRgLaneElems elements per lane, block by block of
+        // kRgBlockRows rows (so that a stretch of wavefronts covers neighbouring rows),
+        // grouped by W inside a block, in row order inside a group; every other row is a
+        // LONG tile (W <= 256) or a wide row
+        std::vector<int32_t> by_w[kRgMaxLog2W + 1];
+        for (int32_t b0 = 0; b0 < n; b0 += kRgBlockRows) {
+            const int32_t b1 = n - b0 < kRgBlockRows ? n : b0 + kRgBlockRows;
+            for (auto &v : by_w) v.clear();
+            for (int32_t r = b0; r < b1; ++r) {
+                const int64_t len = (int64_t)rp[r + 1] - rp[r];
+                const int lw = p->log2w[r];
+                if (lw <= kRgMaxLog2W && len <= ((int64_t)kRgLaneElems << lw)) {
+                    by_w[lw].push_back(r);
+                } else if (lw > kMaxLongLog2W) {
+                    wide.push_back(mp_tile{(int32_t)wide_rows.size(), (int32_t)((lw << 16) | 1)});
+                    wide_rows.push_back(r);
+                } else {
+                    tiles.push_back(mp_stream_tile{r, 1, rp[r], tile_info(lw, 1, 0)});
+                }
+            }
+            for (int lw = 0; lw <= kRgMaxLog2W; ++lw) {
+                const int per = 64 >> lw;
+                const std::vector<int32_t> &v = by_w[lw];
+                for (size_t k = 0; k < v.size(); k += (size_t)per) {
+                    const int cnt = v.size() - k < (size_t)per ? (int)(v.size() - k) : per;
+                    rg.push_back(mp_rg_wave{(int32_t)rg_rows.size(), lw | (cnt << 8)});
+                    rg_rows.insert(rg_rows.end(), v.begin() + (long)k, v.begin() + (long)k + cnt);
+                }
+            }
+        }
+    }
+    int32_t i = row_groups ? n : 0;
     while (i < n) {
         const int64_t len = (int64_t)rp[i + 1] - rp[i];
         if (len > C) {
@@ -118,7 +154,10 @@ mp_status plan_build(const std::vector<int32_t> &rp, std::vector<uint8_t> &&log2
     }
     p->n_stream = (int32_t)tiles.size();
     p->n_wide = (int32_t)wide.size();
+    p->n_rg = (int32_t)rg.size();
     mp_status st = upload(tiles, &p->d_stream, s);
+    if (st == MP_OK) st = upload(rg, &p->d_rg, s);
+    if (st == MP_OK) st = upload(rg_rows, &p->d_rg_rows, s);
     if (st == MP_OK) st = upload(p->log2w, &p->d_log2w, s);
     if (st == MP_OK) st = upload(wide_rows, &p->d_wide_rows, s);
     if (st == MP_OK) st = upload(wide, &p->d_wide, s);
@@ -142,7 +181,7 @@ mp_status create_with_opts(const mp_csr *A, int K, bool cplx, const mp_plan_opts
     std::vector<uint8_t> lw((size_t)A->n_rows);
     for (int32_t i = 0; i < A->n_rows; ++i)
         lw[i] = (uint8_t)policy_log2w((int64_t)rp[i + 1] - rp[i], o.shift, o.max_log2w);
-    mp_status st = plan_build(rp, std::move(lw), A->nnz, A->n_cols, K, cplx, C, s, out);
+    mp_status st = plan_build(rp, std::move(lw), A->nnz, A->n_cols, K, cplx, C, o.row_groups != 0, s, out);
     if (st == MP_OK) {
         (*out)->opts = o;
         (*out)->opts.tile_nnz = C;
@@ -153,8 +192,10 @@ mp_status create_with_opts(const mp_csr *A, int K, bool cplx, const mp_plan_opts
 
 mp_status check_opts(const mp_plan_opts &o)
 {
-    if (o.shift < 0 || o.shift > 12 || o.max_log2w < 0 || o.max_log2w > kMaxLog2W)
-        return fail(MP_ERR_INVALID_ARG, "plan options out of range (shift=%d max_log2w=%d)", o.shift, o.max_log2w);
+    if (o.shift < 0 || o.shift > 12 || o.max_log2w < 0 || o.max_log2w > kMaxLog2W || o.row_groups < 0 ||
+        o.row_groups > 1)
+        return fail(MP_ERR_INVALID_ARG, "plan options out of range (shift=%d max_log2w=%d row_groups=%d)", o.shift,
+                    o.max_log2w, o.row_groups);
     return MP_OK;
 }
 
@@ -173,7 +214,7 @@ mp_status mp_plan_create(const mp_csr *A, int32_t ncomp, int32_t is_complex, con
     mp_status st = mpk::check_csr(A);
     if (st == MP_OK) st = mpk::check_variant(ncomp, is_complex);
     if (st != MP_OK) return st;
-    const mp_plan_opts o = opts ? *opts : mp_plan_opts{0, 6, 0};
+    const mp_plan_opts o = opts ? *opts : mp_plan_opts{0, 6, 0, 0};
     st = mpk::check_opts(o);
     int C = 0;
     if (st == MP_OK) st = mpk::resolve_tile(ncomp, is_complex, o.tile_nnz, &C);
@@ -208,7 +249,7 @@ mp_status mp_plan_create_explicit(const mp_csr *A, int32_t ncomp, int32_t is_com
             return mpk::fail(MP_ERR_INVALID_ARG, "log2w[%d] = %d is not valid for a row of %lld elements", i,
                              (int)lw[i], (long long)len);
     }
-    st = mpk::plan_build(rp, std::move(lw), A->nnz, A->n_cols, ncomp, is_complex != 0, C, s, out);
+    st = mpk::plan_build(rp, std::move(lw), A->nnz, A->n_cols, ncomp, is_complex != 0, C, false, s, out);
     if (st == MP_OK) {
         (*out)->explicit_order = true;
         (*out)->opts.tile_nnz = C;
@@ -237,7 +278,7 @@ mp_status mp_plan_info(const mp_plan *plan, int32_t *n_rows, int32_t *n_tiles, i
     mpk::clear_error();
     if (!plan) return mpk::fail(MP_ERR_INVALID_ARG, "plan is NULL");
     if (n_rows) *n_rows = plan->n_rows;
-    if (n_tiles) *n_tiles = plan->n_stream + plan->n_wide;
+    if (n_tiles) *n_tiles = plan->n_stream + plan->n_wide + plan->n_rg;
     if (tile_nnz) *tile_nnz = plan->tile_nnz;
     if (ncomp) *ncomp = plan->ncomp;
     if (is_complex) *is_complex = plan->cplx;
@@ -279,7 +320,7 @@ mp_status mp_plan_autotune(const mp_csr *A, int32_t ncomp, int32_t is_complex, c
     }
     mp_plan *best = nullptr;
     float best_ms = 0.f;
-    mp_plan_opts best_o{0, 6, 0};
+    mp_plan_opts best_o{0, 6, 0, 0};
     auto trial = [&](const mp_plan_opts &o) -> mp_status {
         int C = 0;
         mp_status t = mpk::resolve_tile(ncomp, is_complex, o.tile_nnz, &C);
@@ -311,15 +352,20 @@ mp_status mp_plan_autotune(const mp_csr *A, int32_t ncomp, int32_t is_complex, c
         }
         return MP_OK;
     };
-    // stage 1: tile sizes under a middle-of-the-road order; stage 2: lane-width policies
+    // stage 1: tile sizes under a middle-of-the-road order; stage 2: lane-width policies;
+    // stage 3: the same policies with row groups (W <= 64 only)
     const int mx = mpk::max_tile_nnz(ncomp, cplx);
-    for (int C = 256; st == MP_OK && C <= mx; C <<= 1) st = trial(mp_plan_opts{1, 6, C});
+    for (int C = 256; st == MP_OK && C <= mx; C <<= 1) st = trial(mp_plan_opts{1, 6, C, 0});
     const int bestC = best ? best->tile_nnz : mpk::default_tile_nnz(ncomp, cplx);
-    static const int pols[][2] = {{0, 6}, {2, 6}, {3, 6}, {0, 5}, {1, 5}, {2, 5}, {0, 4}, {1, 4},
+    static const int pols[][2] = {{0, 6}, {1, 6}, {2, 6}, {3, 6}, {0, 5}, {1, 5}, {2, 5}, {0, 4}, {1, 4},
                                   {2, 4}, {1, 3}, {0, 8}, {1, 8}, {2, 8}};
     for (const auto &pp : pols) {
         if (st != MP_OK) break;
-        st = trial(mp_plan_opts{pp[0], pp[1], bestC});
+        if (pp[0] != 1 || pp[1] != 6) st = trial(mp_plan_opts{pp[0], pp[1], bestC, 0});
+    }
+    for (const auto &pp : pols) {
+        if (st != MP_OK) break;
+        if (pp[1] <= mpk::kRgMaxLog2W) st = trial(mp_plan_opts{pp[0], pp[1], bestC, 1});
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

@@ -38,6 +38,13 @@ inline int32_t tile_info(int max_log2w, int kind, int elem_count)
     return max_log2w | (kind << 4) | (elem_count << 8);
 }
 
+// row-group wavefront: up to 64 / W rows of one lane width W = 2^(info & 15), listed at
+// rows[first ..], (info >> 8) of them
+struct mp_rg_wave {
+    int32_t first;
+    int32_t info;
+};
+
 // wide-row tile: position in the wide-row permutation and (log2w << 16) | row count
 struct mp_tile {
     int32_t first;
@@ -57,8 +64,11 @@ struct mp_plan {
     uint8_t *d_log2w = nullptr;           // device, n_rows
     int32_t *d_wide_rows = nullptr;       // device, n_wide
     mp_tile *d_wide = nullptr;            // device, n_wide
+    int32_t n_rg = 0;                     // row-group wavefronts
+    mp_rg_wave *d_rg = nullptr;           // device, n_rg
+    int32_t *d_rg_rows = nullptr;         // device: the rows of the row groups, wavefront by wavefront
     std::vector<uint8_t> log2w;           // host copy of the order
-    mp_plan_opts opts{0, 6, 0};
+    mp_plan_opts opts{0, 6, 0, 0};
     bool explicit_order = false;
 };
 
@@ -66,6 +76,9 @@ namespace mpk {
 
 constexpr int kMaxLog2W = 10;
 constexpr int kMaxLongLog2W = 8;   // LONG tiles: W <= 256
+constexpr int kRgMaxLog2W = 6;     // row groups: W <= 64 (one wavefront)
+constexpr int kRgLaneElems = 16;   // row groups: at most this many elements per lane
+constexpr int kRgBlockRows = 2048; // row groups are formed inside blocks of this many rows
 
 // doubles per staged product: K, times 4 accumulator sets for complex
 inline int prod_doubles(int K, bool cplx) { return K * (cplx ? 4 : 1); }
@@ -109,7 +122,8 @@ inline int policy_log2w(int64_t len, int shift, int max_log2w)
 
 // Build a plan from host row_ptr and per-row log2w (validated by the caller).
 mp_status plan_build(const std::vector<int32_t> &row_ptr_host, std::vector<uint8_t> &&log2w, int64_t nnz,
-                     int32_t n_cols, int K, bool cplx, int tile_nnz, hipStream_t stream, mp_plan **out);
+                     int32_t n_cols, int K, bool cplx, int tile_nnz, bool row_groups, hipStream_t stream,
+                     mp_plan **out);
 
 void plan_free(mp_plan *p);
 

@@ -786,6 +786,68 @@ __global__ __launch_bounds__(256, (stream_min_blocks<K, CPLX, J, H>())) void spm
 }
 
 // ---------------------------------------------------------------------------
+// row groups (plans built with row_groups): rows with W <= 64
+// ---------------------------------------------------------------------------
+
+// One wavefront per row group: up to 64 / W rows of one lane width W, row r of the group
+// on lanes r*W .. r*W + W - 1.  Lane l reads elements l, l+W, ... of its row straight
+// from memory (a batch at a time, branch-free), adds their products in order in
+// registers starting from its first product, and the W lane sums fold acc[l] +=
+// acc[l + off], off = W/2 .. 1, by shuffles inside the lane group: the tile kernels'
+// order, with no LDS and no barrier.  Consecutive workgroups of an XCD take consecutive
+// groups (a block of neighbouring rows).
+template <int K, bool CPLX, bool DM>
+__global__ __launch_bounds__(256) void spmv_rowgroup_kernel(SpmvArgs A, const mp_rg_wave *__restrict__ groups,
+                                                            const int32_t *__restrict__ rows, int32_t n_groups)
+{
+    const int g = xcd_tile(blockIdx.x, gridDim.x) * 4 + (int)(threadIdx.x >> 6);
+    if (g >= n_groups) return;   // uniform per wavefront
+    const mp_rg_wave G = groups[g];
+    const int lw = G.info & 15;
+    const int nr = G.info >> 8;
+    const int W = 1 << lw;
+    const int lane = threadIdx.x & 63;
+    const int r = lane >> lw;
+    const int l = lane & (W - 1);
+    constexpr int kBatch = long_batch<K, CPLX>();
+    Acc<K, CPLX> acc;
+    acc_zero(acc);
+    int32_t row = 0;
+    bool nonempty = false;
+    if (r < nr) {
+        row = rows[G.first + r];
+        const int32_t beg = A.row_ptr[row], end = A.row_ptr[row + 1];
+        nonempty = end > beg;
+        // W <= len for a non-empty row, so every lane owns at least one element
+        bool first = true;
+        for (int64_t k0 = (int64_t)beg + l; k0 < end; k0 += (int64_t)kBatch * W) {
+            AElem<K, CPLX> el[kBatch];
+#pragma unroll
+            for (int q = 0; q < kBatch; ++q) {
+                const int64_t k = k0 + (int64_t)q * W;
+                load_aelem<K, CPLX, DM>(A, k < end ? k : k0, el[q]);
+            }
+            XVal<K, CPLX> xv[kBatch];
+#pragma unroll
+            for (int q = 0; q < kBatch; ++q) xv[q] = load_x<K, CPLX>(A, el[q].col);
+#pragma unroll
+            for (int q = 0; q < kBatch; ++q) {
+                if (k0 + (int64_t)q * W < end) {
+                    const Acc<K, CPLX> p = elem_times_x<K, CPLX, DM>(el[q], xv[q]);
+                    if (first)
+                        acc = p;
+                    else
+                        acc_add(acc, p);
+                    first = false;
+                }
+            }
+        }
+    }
+    for (int off = W >> 1; off >= 1; off >>= 1) acc_fold_xor(acc, off);
+    if (r < nr && l == 0) acc_store(A, row, acc, nonempty);
+}
+
+// ---------------------------------------------------------------------------
 // wide rows: W = 512 or 1024 (one row per workgroup, lanes in registers)
 // ---------------------------------------------------------------------------
 
@@ -920,7 +982,7 @@ mp_status launch_spmv(const mp_csr *Acsr, const double *a_re, const double *a_im
         MP_HIP_TRY(hipGetLastError());
         return MP_OK;
     }
-    if (plan->n_stream > 0) {
+    if (plan->n_stream > 0 || plan->n_rg > 0) {
         if (plan->n_cols != Acsr->n_cols)
             return fail(MP_ERR_INVALID_ARG, "plan was built for n_cols=%d, matrix has %d", plan->n_cols, Acsr->n_cols);
         if (Acsr->n_cols > 0 && !xs) return fail(MP_ERR_INVALID_ARG, "a planned SpMV needs its staging workspace");
@@ -931,6 +993,14 @@ mp_status launch_spmv(const mp_csr *Acsr, const double *a_re, const double *a_im
                                x_im, Acsr->n_cols, const_cast<double *>(xs));
             MP_HIP_TRY(hipGetLastError());
         }
+    }
+    if (plan->n_rg > 0) {
+        const int64_t blocks = ((int64_t)plan->n_rg + 3) / 4;
+        hipLaunchKernelGGL((spmv_rowgroup_kernel<K, CPLX, DM>), dim3((unsigned)blocks), dim3(256), 0, s, A,
+                           plan->d_rg, plan->d_rg_rows, plan->n_rg);
+        MP_HIP_TRY(hipGetLastError());
+    }
+    if (plan->n_stream > 0) {
         mp_status st;
         switch (plan->tile_nnz) {
             case 256: st = launch_stream<K, CPLX, 1, DM>(A, plan, s); break;
@@ -953,7 +1023,7 @@ mp_status launch_spmv(const mp_csr *Acsr, const double *a_re, const double *a_im
 
 size_t plan_stage_bytes(const mp_plan *plan)
 {
-    if (!plan || plan->n_stream == 0 || plan->n_cols <= 0) return 0;
+    if (!plan || (plan->n_stream == 0 && plan->n_rg == 0) || plan->n_cols <= 0) return 0;
     return sizeof(double) * (size_t)xstage_doubles(plan->ncomp, plan->cplx != 0) * (size_t)plan->n_cols;
 }
 
@@ -974,7 +1044,7 @@ mp_status spmv_check(const char *name, const mp_csr *A, const double *a_re, cons
     if (plan && (plan->ncomp != K || plan->cplx != (CPLX ? 1 : 0)))
         return fail(MP_ERR_INVALID_ARG, "%s: plan was built for ncomp=%d is_complex=%d", name, plan->ncomp,
                     plan->cplx);
-    if (plan && plan->n_stream > 0 && plan->n_cols != A->n_cols)
+    if (plan && (plan->n_stream > 0 || plan->n_rg > 0) && plan->n_cols != A->n_cols)
         return fail(MP_ERR_INVALID_ARG, "%s: plan was built for n_cols=%d, matrix has %d", name, plan->n_cols,
                     A->n_cols);
     const size_t yb = sizeof(double) * K * (size_t)A->n_rows;

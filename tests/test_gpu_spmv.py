@@ -5,7 +5,7 @@ lane widths (the summation order, exported with mp_plan_row_log2w) are given to 
 oracle.  Cases: the 2D 5-point workload (n = 10,000, 49,600 nnz), ragged random
 matrices spanning several tiles and every lane width 1..1024, the paper's 5x5
 example, empty rows / empty matrices / a single 5,000-element row, every plan kind
-(plan-free kernel, canonical plan, width policies, explicit orders, autotuned), run
+(plan-free kernel, canonical plan, width policies, row groups, explicit orders, autotuned), run
 to run determinism, argument errors, concurrent calls that share one plan on two
 streams, and the full n = 1e6 power-law workload compared on every row.
 """
@@ -76,6 +76,8 @@ def test_laplace2d_dd_all_plans(mp):
     for shift, mx in ((0, 1), (2, 6), (1, 0)):
         check(mp, 2, False, row_ptr, col_idx, a, x, plan=mp.mp_plan_create(A, 2, False, shift, mx), A=A,
               what="policy %d,%d" % (shift, mx))
+        check(mp, 2, False, row_ptr, col_idx, a, x, plan=mp.mp_plan_create(A, 2, False, shift, mx, 0, 1), A=A,
+              what="row groups %d,%d" % (shift, mx))
     for tile in (256, 512, 1024, 2048):
         check(mp, 2, False, row_ptr, col_idx, a, x, plan=mp.mp_plan_create(A, 2, False, 0, 6, tile), A=A,
               what="tile %d" % tile)
@@ -100,6 +102,11 @@ def test_ragged_random_every_width(mp, K, cplx):
           what="policy 2,4")
     check(mp, K, cplx, row_ptr, col_idx, a_re, x_re, a_im, x_im, plan=mp.mp_plan_create(A, K, cplx, 0, 8), A=A,
           what="policy 0,8")
+    # row groups (rows with W <= 64 and at most 16 elements per lane; the rest LONG or wide)
+    for shift, mx in ((0, 6), (2, 6), (2, 4), (1, 3), (0, 0), (0, 10)):
+        plan = mp.mp_plan_create(A, K, cplx, shift, mx, 0, row_groups=1)
+        check(mp, K, cplx, row_ptr, col_idx, a_re, x_re, a_im, x_im, plan=plan, A=A,
+              what="row groups %d,%d" % (shift, mx))
     # explicit random orders, including every wide (multi-wavefront) width
     fl = np.array([0 if L == 0 else int(np.floor(np.log2(L))) for L in lengths])
     lw = np.array([rng.integers(0, min(10, f) + 1) for f in fl], dtype=np.uint8)
@@ -140,6 +147,8 @@ def test_edge_cases(mp, K, cplx):
     A = mp.Csr.from_numpy(row_ptr, col_idx, n_cols=4)
     check(mp, K, cplx, row_ptr, col_idx, a, x, a if cplx else None, xi, plan=mp.mp_plan_create(A, K, cplx), A=A,
           what="all empty, plan")
+    check(mp, K, cplx, row_ptr, col_idx, a, x, a if cplx else None, xi,
+          plan=mp.mp_plan_create(A, K, cplx, row_groups=1), A=A, what="all empty, row groups")
     # no rows at all
     A0 = mp.Csr.from_numpy(np.zeros(1, dtype=np.int32), col_idx, n_cols=4)
     y0 = torch.zeros((K, 0), dtype=torch.float64, device="cuda")
@@ -157,7 +166,9 @@ def test_edge_cases(mp, K, cplx):
     for plan in (None, mp.mp_plan_create(A, K, cplx), mp.mp_plan_create(A, K, cplx, 0, 10),
                  mp.mp_plan_create(A, K, cplx, 0, 8), mp.mp_plan_create(A, K, cplx, 3, 4),
                  mp.mp_plan_create_explicit(A, K, cplx, np.array([10, 0], dtype=np.uint8)),
-                 mp.mp_plan_create_explicit(A, K, cplx, np.array([9, 0], dtype=np.uint8))):
+                 mp.mp_plan_create_explicit(A, K, cplx, np.array([9, 0], dtype=np.uint8)),
+                 mp.mp_plan_create(A, K, cplx, 0, 6, 0, 1), mp.mp_plan_create(A, K, cplx, 0, 10, 0, 1),
+                 mp.mp_plan_create(A, K, cplx, 7, 6, 0, 1)):
         check(mp, K, cplx, row_ptr, col_idx, a_re, x, a_im, xi, plan=plan, A=A, what="long row")
 
 
@@ -259,11 +270,13 @@ def test_powerlaw_full_size(mp, powerlaw, K, cplx):
     args = (ad_re, ad_im, xd_re, xd_im, y_re, y_im) if cplx else (ad_re, xd_re, y_re)
     plan, pol = mp.mp_plan_autotune(A, K, ad_re, xd_re, y_re, ad_im, xd_im, y_im, reps=2)
     ws = mp.spmv_workspace(plan)
-    for p in (plan, None):
+    # the autotuned plan, the other plan kind under the same order, and the plan-free kernel
+    other = mp.mp_plan_create(A, K, cplx, pol["shift"], pol["max_log2w"], pol["tile_nnz"], 1 - pol["row_groups"])
+    for p in (plan, other, None):
         if cplx:
             y_im.fill_(float("nan"))
         y_re.fill_(float("nan"))
-        mp.SPMV[(K, cplx)](A, *args, plan=p, ws=ws if p is not None else None)
+        mp.SPMV[(K, cplx)](A, *args, plan=p, ws=ws if p is plan else None)
         torch.cuda.synchronize()
         lw = None if p is None else p.row_log2w()
         want = ref.spmv(K, row_ptr, col_idx, a_re, x_re, a_im=a_im, x_im=x_im, log2w=lw)
