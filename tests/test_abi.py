@@ -107,9 +107,13 @@ def test_traffic_record_is_usable_by_the_bench():
     for rec in recs:
         for key in ("source_hash", "plan", "n", "nnz", "traffic_bytes", "commands"):
             assert key in rec, key
-        assert set(rec["plan"]) == {"shift", "max_log2w", "tile_nnz"} and rec["n"] == 1_000_000
+        assert set(rec["plan"]) == {"shift", "max_log2w", "tile_nnz", "row_groups"} and rec["n"] == 1_000_000
         assert rec["traffic_bytes"] > 0 and len(rec["source_hash"]) == 16
         assert rec["source_hash"] == recs[0]["source_hash"]
+        # read bytes are the counted requests at their sizes, scaled by a plain copy
+        for k in rec["kernels"].values():
+            q = k["read_requests"]
+            assert k["read_bytes"] == 32 * q["32B"] + 64 * q["64B"] + 128 * q["128B"]
 
 
 def test_traffic_records_merge_and_match(tmp_path):

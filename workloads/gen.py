@@ -208,7 +208,7 @@ def powerlaw_xmin(mean=27.0, alpha=1.1, maxlen=4096):
     return 0.5 * (lo + hi)
 
 
-def powerlaw_pattern(n=1_000_000, mean=27.0, alpha=1.1, maxlen=4096, band=2000, p_band=0.7, seed=1):
+def powerlaw_pattern(n=1_000_000, mean=27.0, alpha=1.1, maxlen=4096, band=2000, p_band=0.7, seed=1, n_cols=None):
     """Power-law CSR pattern (row lengths with density ~ L^-(1+alpha), clipped at maxlen).
 
     Row length L_i = min(maxlen, n, floor(x_min * U^(-1/alpha))).  Each entry of row i is
@@ -218,8 +218,10 @@ def powerlaw_pattern(n=1_000_000, mean=27.0, alpha=1.1, maxlen=4096, band=2000, 
     window keeps the first |window| of them and turns the rest into uniform draws;
     duplicates are redrawn from their own law until none is left (rows that need more
     than half of their window are drawn as a random subset of the window directly).
+    n_cols (default n): uniform entries are drawn from [0, n_cols) instead.
     Returns (row_ptr int32, col_idx int32).
     """
+    nc = n if n_cols is None else int(n_cols)
     rng = np.random.default_rng(seed)
     xmin = powerlaw_xmin(mean, alpha, maxlen)
     u = 1.0 - rng.random(n)  # (0, 1]
@@ -244,7 +246,7 @@ def powerlaw_pattern(n=1_000_000, mean=27.0, alpha=1.1, maxlen=4096, band=2000, 
     cols = np.empty(nnz, dtype=np.int64)
     r_u = rng.random(nnz)
     cols[is_band] = w_lo[row_of[is_band]] + np.floor(r_u[is_band] * w_size[row_of[is_band]]).astype(np.int64)
-    cols[~is_band] = np.floor(r_u[~is_band] * n).astype(np.int64)
+    cols[~is_band] = np.floor(r_u[~is_band] * nc).astype(np.int64)
     # rows needing more than a quarter of their window: a random subset of the window
     for i in dense_rows:
         sel = np.nonzero(is_band[row_ptr[i]:row_ptr[i + 1]])[0] + row_ptr[i]
@@ -254,7 +256,7 @@ def powerlaw_pattern(n=1_000_000, mean=27.0, alpha=1.1, maxlen=4096, band=2000, 
     # After the first pass only the entries of rows that still hold duplicates are revisited.
     ent = np.arange(nnz, dtype=np.int64)
     for _ in range(200):
-        key = row_of[ent] * n + cols[ent]
+        key = row_of[ent] * nc + cols[ent]
         order = np.argsort(key * 2 + (~is_band[ent]), kind="stable")
         ks = key[order]
         dup_sorted = np.zeros(ent.size, dtype=bool)
@@ -265,14 +267,14 @@ def powerlaw_pattern(n=1_000_000, mean=27.0, alpha=1.1, maxlen=4096, band=2000, 
         r = rng.random(dup.size)
         b = is_band[dup]
         cols[dup[b]] = w_lo[row_of[dup[b]]] + np.floor(r[b] * w_size[row_of[dup[b]]]).astype(np.int64)
-        cols[dup[~b]] = np.floor(r[~b] * n).astype(np.int64)
+        cols[dup[~b]] = np.floor(r[~b] * nc).astype(np.int64)
         rows_left = np.unique(row_of[dup])
         ent = np.concatenate([np.arange(row_ptr[i], row_ptr[i + 1]) for i in rows_left])
     else:
         raise RuntimeError("powerlaw_pattern: duplicate columns did not resolve")
     # sort columns within rows
-    key = row_of * n + cols
-    cols = (np.sort(key) - row_of * n).astype(np.int32)
+    key = row_of * nc + cols
+    cols = (np.sort(key) - row_of * nc).astype(np.int32)
     return row_ptr.astype(np.int32), cols
 
 
