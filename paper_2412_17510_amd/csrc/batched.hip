@@ -592,11 +592,11 @@ __global__ __launch_bounds__(BMap<R>::THREADS) void k_bq_pq(int32_t n, const dou
 }
 
 // alpha = rho / (p, q) per running pair (breakdown unless (p, q) > 0 and finite), then
-// x += alpha p, r -= alpha q and the chunk sums of (r, z), (r, r) with z = M^-1 r (z is
-// not stored: k_bq_p forms it again from r by the same operation), per dot chunk
+// r -= alpha q and the chunk sums of (r, z), (r, r) with z = M^-1 r (z is not stored:
+// k_bq_p forms it again from r by the same operation), per dot chunk.  x += alpha p is
+// left to k_bq_p, which loads p anyway.
 template <int R>
-__global__ __launch_bounds__(BMap<R>::THREADS) void k_bq_upd(int32_t n, double *__restrict__ X,
-                                                             double *__restrict__ Rv, const double *__restrict__ P,
+__global__ __launch_bounds__(BMap<R>::THREADS) void k_bq_upd(int32_t n, double *__restrict__ Rv,
                                                              const double *__restrict__ Qv,
                                                              const double *__restrict__ minv,
                                                              const dd_t *__restrict__ ppq, dd_t *__restrict__ prz,
@@ -663,9 +663,7 @@ __global__ __launch_bounds__(BMap<R>::THREADS) void k_bq_upd(int32_t n, double *
             for (int i = 0; i < M::RPT; ++i) {
                 if (!run[i]) continue;
                 const int r = M::rhs(i);
-                const dd_t xk = bld(X, NR, k, R, r), pk = bld(P, NR, k, R, r);
                 const dd_t rk0 = bld(Rv, NR, k, R, r), qk = bld(Qv, NR, k, R, r);
-                bst(X, NR, k, R, r, dd_add(xk, dd_mul(alpha[i], pk)));
                 const dd_t rk = dd_add(rk0, mp_neg(dd_mul(alpha[i], qk)));
                 bst(Rv, NR, k, R, r, rk);
                 const dd_t zk = minv ? dd_mul_d(rk, mi) : rk;
@@ -680,10 +678,12 @@ __global__ __launch_bounds__(BMap<R>::THREADS) void k_bq_upd(int32_t n, double *
     }
 }
 
+// x += alpha p for the pairs k_bq_upd stepped (with the p this kernel loads anyway);
 // iterations + 1, ||r||^2, beta = (r, z) / rho and the stop tests per running pair,
 // then p = z + beta p for the pairs still running, per dot chunk
 template <int R>
-__global__ __launch_bounds__(BMap<R>::THREADS) void k_bq_p(int32_t n, const double *__restrict__ Rv,
+__global__ __launch_bounds__(BMap<R>::THREADS) void k_bq_p(int32_t n, double *__restrict__ X,
+                                                           const double *__restrict__ Rv,
                                                            const double *__restrict__ minv, double *__restrict__ P,
                                                            const dd_t *__restrict__ prz, const dd_t *__restrict__ prr,
                                                            const int32_t *__restrict__ chunk_row,
@@ -695,8 +695,8 @@ __global__ __launch_bounds__(BMap<R>::THREADS) void k_bq_p(int32_t n, const doub
 {
     using M = BMap<R>;
     __shared__ dd_t P_[kBMaxSysChunks];
-    __shared__ dd_t s_rz[R], s_rr[R], s_beta[R];
-    __shared__ int s_want[R], s_run[R];
+    __shared__ dd_t s_rz[R], s_rr[R], s_beta[R], s_alpha[R];
+    __shared__ int s_want[R], s_run[R], s_xrun[R];
     __shared__ int32_t s_item;
     bq_clear_next(Q);
     int probe = 0;
@@ -713,6 +713,8 @@ __global__ __launch_bounds__(BMap<R>::THREADS) void k_bq_p(int32_t n, const doub
         if (threadIdx.x < R) {
             const int r = threadIdx.x;
             BState q = sb[ch.sys * R + r];
+            s_xrun[r] = q.done == B_RUN;   // k_bq_upd stepped r with this alpha
+            s_alpha[r] = q.alpha;
             if (q.done == B_RUN) {
                 const dd_t rz = s_rz[r], rr = s_rr[r];
                 q.iters += 1;
@@ -735,28 +737,37 @@ __global__ __launch_bounds__(BMap<R>::THREADS) void k_bq_p(int32_t n, const doub
         __syncthreads();
         int any = 0;
 #pragma unroll
-        for (int r = 0; r < R; ++r) any |= s_run[r];
-        if (!any) continue;   // uniform in the workgroup
-        bool run[M::RPT];
-        dd_t beta[M::RPT];
+        for (int r = 0; r < R; ++r) any |= s_xrun[r];
+        if (!any) {
+            __syncthreads();   // s_xrun / s_run / s_alpha / s_beta are rewritten by the next item
+            continue;          // uniform in the workgroup
+        }
+        bool run[M::RPT], xrun[M::RPT];
+        dd_t beta[M::RPT], alpha[M::RPT];
 #pragma unroll
         for (int i = 0; i < M::RPT; ++i) {
             run[i] = s_run[M::rhs(i)] != 0;
+            xrun[i] = s_xrun[M::rhs(i)] != 0;
             beta[i] = s_beta[M::rhs(i)];
+            alpha[i] = s_alpha[M::rhs(i)];
         }
         for (int64_t k = ch.row0 + M::lane(); k < ch.end; k += kBLanes) {
             const double mi = minv ? minv[k] : 1.0;
 #pragma unroll
             for (int i = 0; i < M::RPT; ++i) {
                 const int r = M::rhs(i);
-                if (run[i]) {
-                    const dd_t rk = bld(Rv, NR, k, R, r);
-                    const dd_t zk = minv ? dd_mul_d(rk, mi) : rk;
-                    bst(P, NR, k, R, r, dd_add(zk, dd_mul(beta[i], bld(P, NR, k, R, r))));
+                if (xrun[i]) {
+                    const dd_t pk = bld(P, NR, k, R, r);
+                    bst(X, NR, k, R, r, dd_add(bld(X, NR, k, R, r), dd_mul(alpha[i], pk)));
+                    if (run[i]) {
+                        const dd_t rk = bld(Rv, NR, k, R, r);
+                        const dd_t zk = minv ? dd_mul_d(rk, mi) : rk;
+                        bst(P, NR, k, R, r, dd_add(zk, dd_mul(beta[i], pk)));
+                    }
                 }
             }
         }
-        __syncthreads();   // s_run / s_beta are rewritten by the next item
+        __syncthreads();   // s_xrun / s_run / s_alpha / s_beta are rewritten by the next item
     }
 }
 
@@ -957,10 +968,11 @@ struct BatchCG {
         const int g = grid_c < p->n_chunks ? grid_c : p->n_chunks;
         hipLaunchKernelGGL(k_bq_pq<R>, dim3(g), dim3(BMap<R>::THREADS), 0, s, A->n_rows, P, Q, part[0],
                            p->d_chunk_row, p->d_chunk_sys, p->d_sys_ptr, chunk_queue<R>(p, c1, c2));
-        hipLaunchKernelGGL(k_bq_upd<R>, dim3(g), dim3(BMap<R>::THREADS), 0, s, A->n_rows, X, Rv, P, Q, minv, part[0],
+        hipLaunchKernelGGL(k_bq_upd<R>, dim3(g), dim3(BMap<R>::THREADS), 0, s, A->n_rows, Rv, Q, minv, part[0],
                            part[1], part[2], p->d_chunk_row, p->d_chunk_sys, p->d_sys_ptr, p->d_sys_chunk, st, st2,
                            chunk_queue<R>(p, c2, c3));
-        hipLaunchKernelGGL(k_bq_p<R>, dim3(g), dim3(BMap<R>::THREADS), 0, s, A->n_rows, Rv, minv, P, part[1], part[2],
+        hipLaunchKernelGGL(k_bq_p<R>, dim3(g), dim3(BMap<R>::THREADS), 0, s, A->n_rows, X, Rv, minv, P, part[1],
+                           part[2],
                            p->d_chunk_row, p->d_chunk_sys, p->d_sys_ptr, p->d_sys_chunk, max_iter, st2, st,
                            chunk_queue<R>(p, c3, c0));
         return launched();
