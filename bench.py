@@ -679,15 +679,16 @@ def main():
         if name == "dd":
             headline = (ms, wall, rf, pol)
         # binary64 matrix (its leading components) times the same K-component x, under the same
-        # order: the variant's plan, and the same order at the smallest tile size when that
-        # differs (the binary64-matrix kernels stage fewer bytes per product); the faster one
+        # order: the variant's plan, the same order at the smallest tile size, and the same
+        # order in the other plan kind (the autotuner times the K-component matrix; the
+        # binary64-matrix kernels stage fewer bytes per product); the fastest one
         a64 = ad_re[0].contiguous()
         a64i = ad_im[0].contiguous() if cplx else None
         plans_d = [(plan, pol)]
-        if pol["tile_nnz"] != 256:
-            pol2 = dict(pol, tile_nnz=256)
-            plans_d.append((mp.mp_plan_create(A, K, cplx, pol["shift"], pol["max_log2w"], 256, pol["row_groups"]),
-                            pol2))
+        for tile, rg in ((256, pol["row_groups"]), (256, 1 - pol["row_groups"])):
+            if (tile, rg) != (pol["tile_nnz"], pol["row_groups"]):
+                plans_d.append((mp.mp_plan_create(A, K, cplx, pol["shift"], pol["max_log2w"], tile, rg),
+                                dict(pol, tile_nnz=tile, row_groups=rg)))
         msd, pold = None, None
         for pl, pp in plans_d:
             if cplx:
