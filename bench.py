@@ -567,7 +567,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=6.0)
     ap.add_argument("--plan", default="autotune",
-                    help="autotune | canonical | shift,max_log2w,tile_nnz[,row_groups]")
+                    help="autotune | canonical | shift,max_log2w,tile_nnz[,row_groups 0|1|2]")
     ap.add_argument("--workload", default="spmv", choices=["spmv", "batched", "locality", "solves"],
                     help="spmv (default: power-law SpMV line plus the 64^3 solves), batched (256 systems x 8 rhs), "
                          "locality (the DD SpMV on three column laws with the same row lengths) or solves (only "
@@ -685,7 +685,7 @@ def main():
         a64 = ad_re[0].contiguous()
         a64i = ad_im[0].contiguous() if cplx else None
         plans_d = [(plan, pol)]
-        for tile, rg in ((256, pol["row_groups"]), (256, 1 - pol["row_groups"])):
+        for tile, rg in ((256, 0), (256, 1), (256, 2)):
             if (tile, rg) != (pol["tile_nnz"], pol["row_groups"]):
                 plans_d.append((mp.mp_plan_create(A, K, cplx, pol["shift"], pol["max_log2w"], tile, rg),
                                 dict(pol, tile_nnz=tile, row_groups=rg)))

@@ -87,8 +87,9 @@ typedef struct {
     int32_t shift;      /* 0..12: aim at >= 2^shift elements per lane */
     int32_t max_log2w;  /* 0..10: widest lane group (1024 lanes) */
     int32_t tile_nnz;   /* 0 or 256..2048 (power of two) */
-    int32_t row_groups; /* 0: every row in tiles; 1: rows with W <= 64 and at most 16
-                           elements per lane summed in wavefront lane groups (same order) */
+    int32_t row_groups; /* 0: every row in tiles; rows with W <= 64 summed in wavefront lane
+                           groups (same order): 1 those with at most 16 elements per lane,
+                           2 all of them */
 } mp_plan_opts;
 
 /* Last error message of the calling thread ("" if none).  Static storage. */

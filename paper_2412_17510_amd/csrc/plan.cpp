@@ -74,7 +74,7 @@ mp_status resolve_tile(int32_t ncomp, int32_t is_complex, int32_t requested, int
 }  // namespace
 
 mp_status plan_build(const std::vector<int32_t> &rp, std::vector<uint8_t> &&log2w, int64_t nnz, int32_t n_cols,
-                     int K, bool cplx, int C, bool row_groups, hipStream_t s, mp_plan **out)
+                     int K, bool cplx, int C, int row_groups, hipStream_t s, mp_plan **out)
 {
     const int32_t n = (int32_t)rp.size() - 1;
     mp_plan *p = new (std::nothrow) mp_plan;
@@ -93,10 +93,10 @@ mp_status plan_build(const std::vector<int32_t> &rp, std::vector<uint8_t> &&log2
     std::vector<mp_rg_wave> rg;
     std::vector<int32_t> rg_rows;
     if (row_groups) {
-        // rows with W <= 64 and at most kRgLaneElems elements per lane, block by block of
-        // kRgBlockRows rows (so that a stretch of wavefronts covers neighbouring rows),
-        // grouped by W inside a block, in row order inside a group; every other row is a
-        // LONG tile (W <= 256) or a wide row
+        // rows with W <= 64 (and, for row_groups = 1, at most kRgLaneElems elements per
+        // lane), block by block of kRgBlockRows rows (so that a stretch of wavefronts covers
+        // neighbouring rows), grouped by W inside a block, in row order inside a group; every
+        // other row is a LONG tile (W <= 256) or a wide row
         std::vector<int32_t> by_w[kRgMaxLog2W + 1];
         for (int32_t b0 = 0; b0 < n; b0 += kRgBlockRows) {
             const int32_t b1 = n - b0 < kRgBlockRows ? n : b0 + kRgBlockRows;
@@ -104,7 +104,7 @@ mp_status plan_build(const std::vector<int32_t> &rp, std::vector<uint8_t> &&log2
             for (int32_t r = b0; r < b1; ++r) {
                 const int64_t len = (int64_t)rp[r + 1] - rp[r];
                 const int lw = p->log2w[r];
-                if (lw <= kRgMaxLog2W && len <= ((int64_t)kRgLaneElems << lw)) {
+                if (lw <= kRgMaxLog2W && (row_groups == 2 || len <= ((int64_t)kRgLaneElems << lw))) {
                     by_w[lw].push_back(r);
                 } else if (lw > kMaxLongLog2W) {
                     wide.push_back(mp_tile{(int32_t)wide_rows.size(), (int32_t)((lw << 16) | 1)});
@@ -181,7 +181,7 @@ mp_status create_with_opts(const mp_csr *A, int K, bool cplx, const mp_plan_opts
     std::vector<uint8_t> lw((size_t)A->n_rows);
     for (int32_t i = 0; i < A->n_rows; ++i)
         lw[i] = (uint8_t)policy_log2w((int64_t)rp[i + 1] - rp[i], o.shift, o.max_log2w);
-    mp_status st = plan_build(rp, std::move(lw), A->nnz, A->n_cols, K, cplx, C, o.row_groups != 0, s, out);
+    mp_status st = plan_build(rp, std::move(lw), A->nnz, A->n_cols, K, cplx, C, o.row_groups, s, out);
     if (st == MP_OK) {
         (*out)->opts = o;
         (*out)->opts.tile_nnz = C;
@@ -193,7 +193,7 @@ mp_status create_with_opts(const mp_csr *A, int K, bool cplx, const mp_plan_opts
 mp_status check_opts(const mp_plan_opts &o)
 {
     if (o.shift < 0 || o.shift > 12 || o.max_log2w < 0 || o.max_log2w > kMaxLog2W || o.row_groups < 0 ||
-        o.row_groups > 1)
+        o.row_groups > 2)
         return fail(MP_ERR_INVALID_ARG, "plan options out of range (shift=%d max_log2w=%d row_groups=%d)", o.shift,
                     o.max_log2w, o.row_groups);
     return MP_OK;
@@ -249,7 +249,7 @@ mp_status mp_plan_create_explicit(const mp_csr *A, int32_t ncomp, int32_t is_com
             return mpk::fail(MP_ERR_INVALID_ARG, "log2w[%d] = %d is not valid for a row of %lld elements", i,
                              (int)lw[i], (long long)len);
     }
-    st = mpk::plan_build(rp, std::move(lw), A->nnz, A->n_cols, ncomp, is_complex != 0, C, false, s, out);
+    st = mpk::plan_build(rp, std::move(lw), A->nnz, A->n_cols, ncomp, is_complex != 0, C, 0, s, out);
     if (st == MP_OK) {
         (*out)->explicit_order = true;
         (*out)->opts.tile_nnz = C;
@@ -353,7 +353,7 @@ mp_status mp_plan_autotune(const mp_csr *A, int32_t ncomp, int32_t is_complex, c
         return MP_OK;
     };
     // stage 1: tile sizes under a middle-of-the-road order; stage 2: lane-width policies;
-    // stage 3: the same policies with row groups (W <= 64 only)
+    // stage 3: the same policies (W <= 64 only) with row groups, short rows or every row
     const int mx = mpk::max_tile_nnz(ncomp, cplx);
     for (int C = 256; st == MP_OK && C <= mx; C <<= 1) st = trial(mp_plan_opts{1, 6, C, 0});
     const int bestC = best ? best->tile_nnz : mpk::default_tile_nnz(ncomp, cplx);
@@ -363,9 +363,11 @@ mp_status mp_plan_autotune(const mp_csr *A, int32_t ncomp, int32_t is_complex, c
         if (st != MP_OK) break;
         if (pp[0] != 1 || pp[1] != 6) st = trial(mp_plan_opts{pp[0], pp[1], bestC, 0});
     }
-    for (const auto &pp : pols) {
-        if (st != MP_OK) break;
-        if (pp[1] <= mpk::kRgMaxLog2W) st = trial(mp_plan_opts{pp[0], pp[1], bestC, 1});
+    for (int rg = 1; rg <= 2; ++rg) {
+        for (const auto &pp : pols) {
+            if (st != MP_OK) break;
+            if (pp[1] <= mpk::kRgMaxLog2W) st = trial(mp_plan_opts{pp[0], pp[1], bestC, rg});
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

@@ -77,7 +77,7 @@ namespace mpk {
 constexpr int kMaxLog2W = 10;
 constexpr int kMaxLongLog2W = 8;   // LONG tiles: W <= 256
 constexpr int kRgMaxLog2W = 6;     // row groups: W <= 64 (one wavefront)
-constexpr int kRgLaneElems = 16;   // row groups: at most this many elements per lane
+constexpr int kRgLaneElems = 16;   // row_groups = 1: at most this many elements per lane
 constexpr int kRgBlockRows = 2048; // row groups are formed inside blocks of this many rows
 
 // doubles per staged product: K, times 4 accumulator sets for complex
@@ -122,7 +122,7 @@ inline int policy_log2w(int64_t len, int shift, int max_log2w)
 
 // Build a plan from host row_ptr and per-row log2w (validated by the caller).
 mp_status plan_build(const std::vector<int32_t> &row_ptr_host, std::vector<uint8_t> &&log2w, int64_t nnz,
-                     int32_t n_cols, int K, bool cplx, int tile_nnz, bool row_groups, hipStream_t stream,
+                     int32_t n_cols, int K, bool cplx, int tile_nnz, int row_groups, hipStream_t stream,
                      mp_plan **out);
 
 void plan_free(mp_plan *p);

@@ -103,10 +103,11 @@ def test_ragged_random_every_width(mp, K, cplx):
     check(mp, K, cplx, row_ptr, col_idx, a_re, x_re, a_im, x_im, plan=mp.mp_plan_create(A, K, cplx, 0, 8), A=A,
           what="policy 0,8")
     # row groups (rows with W <= 64 and at most 16 elements per lane; the rest LONG or wide)
-    for shift, mx in ((0, 6), (2, 6), (2, 4), (1, 3), (0, 0), (0, 10)):
-        plan = mp.mp_plan_create(A, K, cplx, shift, mx, 0, row_groups=1)
-        check(mp, K, cplx, row_ptr, col_idx, a_re, x_re, a_im, x_im, plan=plan, A=A,
-              what="row groups %d,%d" % (shift, mx))
+    for rg in (1, 2):
+        for shift, mx in ((0, 6), (2, 6), (2, 4), (1, 3), (0, 0), (0, 10)):
+            plan = mp.mp_plan_create(A, K, cplx, shift, mx, 0, row_groups=rg)
+            check(mp, K, cplx, row_ptr, col_idx, a_re, x_re, a_im, x_im, plan=plan, A=A,
+                  what="row groups %d: %d,%d" % (rg, shift, mx))
     # explicit random orders, including every wide (multi-wavefront) width
     fl = np.array([0 if L == 0 else int(np.floor(np.log2(L))) for L in lengths])
     lw = np.array([rng.integers(0, min(10, f) + 1) for f in fl], dtype=np.uint8)
@@ -168,7 +169,8 @@ def test_edge_cases(mp, K, cplx):
                  mp.mp_plan_create_explicit(A, K, cplx, np.array([10, 0], dtype=np.uint8)),
                  mp.mp_plan_create_explicit(A, K, cplx, np.array([9, 0], dtype=np.uint8)),
                  mp.mp_plan_create(A, K, cplx, 0, 6, 0, 1), mp.mp_plan_create(A, K, cplx, 0, 10, 0, 1),
-                 mp.mp_plan_create(A, K, cplx, 7, 6, 0, 1)):
+                 mp.mp_plan_create(A, K, cplx, 7, 6, 0, 1), mp.mp_plan_create(A, K, cplx, 0, 6, 0, 2),
+                 mp.mp_plan_create(A, K, cplx, 0, 10, 0, 2)):
         check(mp, K, cplx, row_ptr, col_idx, a_re, x, a_im, xi, plan=plan, A=A, what="long row")
 
 
@@ -271,8 +273,9 @@ def test_powerlaw_full_size(mp, powerlaw, K, cplx):
     plan, pol = mp.mp_plan_autotune(A, K, ad_re, xd_re, y_re, ad_im, xd_im, y_im, reps=2)
     ws = mp.spmv_workspace(plan)
     # the autotuned plan, the other plan kind under the same order, and the plan-free kernel
-    other = mp.mp_plan_create(A, K, cplx, pol["shift"], pol["max_log2w"], pol["tile_nnz"], 1 - pol["row_groups"])
-    for p in (plan, other, None):
+    others = [mp.mp_plan_create(A, K, cplx, pol["shift"], pol["max_log2w"], pol["tile_nnz"], rg)
+              for rg in (0, 1, 2) if rg != pol["row_groups"]]
+    for p in (plan, *others, None):
         if cplx:
             y_im.fill_(float("nan"))
         y_re.fill_(float("nan"))
