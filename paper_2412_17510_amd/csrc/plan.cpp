@@ -95,8 +95,8 @@ mp_status plan_build(const std::vector<int32_t> &rp, std::vector<uint8_t> &&log2
     if (row_groups) {
         // rows with W <= 64 (and, for row_groups = 1, at most kRgLaneElems elements per
         // lane), block by block of kRgBlockRows rows (so that a stretch of wavefronts covers
-        // neighbouring rows), grouped by W inside a block, in row order inside a group; every
-        // other row is a LONG tile (W <= 256) or a wide row
+        // neighbouring rows), grouped by W inside a block, by decreasing length inside a
+        // group; every other row is a LONG tile (W <= 256) or a wide row
         std::vector<int32_t> by_w[kRgMaxLog2W + 1];
         for (int32_t b0 = 0; b0 < n; b0 += kRgBlockRows) {
             const int32_t b1 = n - b0 < kRgBlockRows ? n : b0 + kRgBlockRows;
@@ -115,7 +115,12 @@ mp_status plan_build(const std::vector<int32_t> &rp, std::vector<uint8_t> &&log2
             }
             for (int lw = 0; lw <= kRgMaxLog2W; ++lw) {
                 const int per = 64 >> lw;
-                const std::vector<int32_t> &v = by_w[lw];
+                // longest rows first inside a width class: the rows of one wavefront then
+                // have similar lengths, so its lanes finish together
+                std::vector<int32_t> &v = by_w[lw];
+                std::stable_sort(v.begin(), v.end(), [&rp](int32_t x, int32_t y) {
+                    return rp[x + 1] - rp[x] > rp[y + 1] - rp[y];
+                });
                 for (size_t k = 0; k < v.size(); k += (size_t)per) {
                     const int cnt = v.size() - k < (size_t)per ? (int)(v.size() - k) : per;
                     rg.push_back(mp_rg_wave{(int32_t)rg_rows.size(), lw | (cnt << 8)});
@@ -318,9 +323,22 @@ mp_status mp_plan_autotune(const mp_csr *A, int32_t ncomp, int32_t is_complex, c
         if (xs) (void)hipFree(xs);
         return mpk::hip_fail(ee, "hipEventCreate");
     }
-    mp_plan *best = nullptr;
-    float best_ms = 0.f;
-    mp_plan_opts best_o{0, 6, 0, 0};
+    // the three fastest plans so far (by their trial time), fastest first
+    constexpr int kTop = 3;
+    mp_plan *top[kTop] = {nullptr, nullptr, nullptr};
+    float top_ms[kTop] = {0.f, 0.f, 0.f};
+    auto time_plan = [&](mp_plan *p, float *ms) -> mp_status {
+        mp_status t = mpk::spmv_dispatch(ncomp, cplx, A, a_re, a_im, x_re, x_im, y_re, y_im, p, xs, s);
+        hipError_t err = hipSuccess;
+        if (t == MP_OK) err = hipEventRecord(e0, s);
+        for (int r = 0; t == MP_OK && err == hipSuccess && r < reps; ++r)
+            t = mpk::spmv_dispatch(ncomp, cplx, A, a_re, a_im, x_re, x_im, y_re, y_im, p, xs, s);
+        if (t == MP_OK && err == hipSuccess) err = hipEventRecord(e1, s);
+        if (t == MP_OK && err == hipSuccess) err = hipEventSynchronize(e1);
+        if (t == MP_OK && err == hipSuccess) err = hipEventElapsedTime(ms, e0, e1);
+        if (t == MP_OK && err != hipSuccess) t = mpk::hip_fail(err, "autotune timing");
+        return t;
+    };
     auto trial = [&](const mp_plan_opts &o) -> mp_status {
         int C = 0;
         mp_status t = mpk::resolve_tile(ncomp, is_complex, o.tile_nnz, &C);
@@ -328,35 +346,32 @@ mp_status mp_plan_autotune(const mp_csr *A, int32_t ncomp, int32_t is_complex, c
         mp_plan *p = nullptr;
         t = mpk::create_with_opts(A, ncomp, cplx, o, C, s, rp, &p);
         if (t != MP_OK) return t;
-        t = mpk::spmv_dispatch(ncomp, cplx, A, a_re, a_im, x_re, x_im, y_re, y_im, p, xs, s);
-        hipError_t err = hipSuccess;
-        if (t == MP_OK) err = hipEventRecord(e0, s);
-        for (int r = 0; t == MP_OK && err == hipSuccess && r < reps; ++r)
-            t = mpk::spmv_dispatch(ncomp, cplx, A, a_re, a_im, x_re, x_im, y_re, y_im, p, xs, s);
-        if (t == MP_OK && err == hipSuccess) err = hipEventRecord(e1, s);
-        if (t == MP_OK && err == hipSuccess) err = hipEventSynchronize(e1);
         float ms = 0.f;
-        if (t == MP_OK && err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-        if (t == MP_OK && err != hipSuccess) t = mpk::hip_fail(err, "autotune timing");
+        t = time_plan(p, &ms);
         if (t != MP_OK) {
             mpk::plan_free(p);
             return t;
         }
-        if (!best || ms < best_ms) {
-            mpk::plan_free(best);
-            best = p;
-            best_ms = ms;
-            best_o = p->opts;
-        } else {
+        int k = kTop;
+        while (k > 0 && (!top[k - 1] || ms < top_ms[k - 1])) --k;
+        if (k == kTop) {
             mpk::plan_free(p);
+            return MP_OK;
         }
+        mpk::plan_free(top[kTop - 1]);
+        for (int j = kTop - 1; j > k; --j) {
+            top[j] = top[j - 1];
+            top_ms[j] = top_ms[j - 1];
+        }
+        top[k] = p;
+        top_ms[k] = ms;
         return MP_OK;
     };
     // stage 1: tile sizes under a middle-of-the-road order; stage 2: lane-width policies;
     // stage 3: the same policies (W <= 64 only) with row groups, short rows or every row
     const int mx = mpk::max_tile_nnz(ncomp, cplx);
     for (int C = 256; st == MP_OK && C <= mx; C <<= 1) st = trial(mp_plan_opts{1, 6, C, 0});
-    const int bestC = best ? best->tile_nnz : mpk::default_tile_nnz(ncomp, cplx);
+    const int bestC = top[0] ? top[0]->tile_nnz : mpk::default_tile_nnz(ncomp, cplx);
     static const int pols[][2] = {{0, 6}, {1, 6}, {2, 6}, {3, 6}, {0, 5}, {1, 5}, {2, 5}, {0, 4}, {1, 4},
                                   {2, 4}, {1, 3}, {0, 8}, {1, 8}, {2, 8}};
     for (const auto &pp : pols) {
@@ -369,6 +384,24 @@ mp_status mp_plan_autotune(const mp_csr *A, int32_t ncomp, int32_t is_complex, c
             if (pp[1] <= mpk::kRgMaxLog2W) st = trial(mp_plan_opts{pp[0], pp[1], bestC, rg});
         }
     }
+    // runoff: the three fastest re-timed twice more, in turn; the lowest total wins
+    // (one trial's timing alone can rank near-ties by noise)
+    float total[kTop] = {0.f, 0.f, 0.f};
+    for (int round = 0; st == MP_OK && round < 2; ++round) {
+        for (int k = 0; st == MP_OK && k < kTop; ++k) {
+            if (!top[k]) continue;
+            float ms = 0.f;
+            st = time_plan(top[k], &ms);
+            total[k] += ms;
+        }
+    }
+    int win = 0;
+    for (int k = 1; k < kTop; ++k)
+        if (top[k] && total[k] < total[win]) win = k;
+    mp_plan *best = top[win];
+    for (int k = 0; k < kTop; ++k)
+        if (k != win) mpk::plan_free(top[k]);
+    const mp_plan_opts best_o = best ? best->opts : mp_plan_opts{0, 6, 0, 0};
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st == MP_OK) {
