@@ -54,11 +54,15 @@ def test_cg_diffusion_converged_parity(mp, precond):
     assert info["status"] == 0 and info["relres"] <= 1.01e-28
 
 
-def test_cg_with_plan_order(mp):
+@pytest.mark.parametrize("row_groups", [0, 1, 2])
+def test_cg_with_plan_order(mp, row_groups):
+    """CG under a plan's order, its SpMV in tiles or in row groups (the step stages p for
+    either kernel)."""
     row_ptr, col_idx, a = diffusion3d_7pt(m=12, sigma=1.5, seed=12)
     rng = np.random.default_rng(12)
     b = random_mp(row_ptr.size - 1, 2, rng)
-    compare(mp, "cg", row_ptr, col_idx, a, b, "jacobi", 1e-28, 5000, plan_opts=(1, 2, 256), what="cg plan")
+    compare(mp, "cg", row_ptr, col_idx, a, b, "jacobi", 1e-28, 5000, plan_opts=(1, 2, 256, row_groups),
+            what="cg plan, row groups %d" % row_groups)
 
 
 def test_cg_full_size_100_iterations(mp):
