@@ -117,9 +117,10 @@ mp_status mp_plan_create_explicit(const mp_csr *A, int32_t ncomp, int32_t is_com
 
 /* Autotuned plan (Sec. 4.1 observes that SpMV speed depends on the matrix size and
  * structure): times the K-component kernel (complex if is_complex) on the caller's
- * operands (only read; y is overwritten) for a fixed list of tile sizes and then of
- * width policies, and keeps the fastest.  The winning options are returned in
- * *chosen (may be NULL).  Synchronises `stream`. */
+ * operands (only read; y is overwritten) for a fixed list of tile sizes, then of width
+ * policies, then of those policies (W <= 64) with row groups of both kinds; re-times
+ * the three fastest twice more and keeps the lowest total.  The winning options are
+ * returned in *chosen (may be NULL).  Synchronises `stream`. */
 mp_status mp_plan_autotune(const mp_csr *A, int32_t ncomp, int32_t is_complex,
                            const double *a_re, const double *a_im, const double *x_re, const double *x_im,
                            double *y_re, double *y_im, int32_t reps, void *stream,
