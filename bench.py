@@ -109,6 +109,23 @@ def time_loop(fn, steps, warmup, torch):
     return e0.elapsed_time(e1) / steps, wall
 
 
+def per_call_ms(fn, calls, torch):
+    """Duration of each of `calls` back-to-back calls (HIP events between the calls on the
+    stream they run on): p10, median and p90 in ms."""
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(calls + 1)]
+    fn()
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for i in range(calls):
+        fn()
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    t = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(calls))
+    q = lambda f: round(t[int(round(f * (calls - 1)))], 4)  # noqa: E731
+    return {"calls": calls, "p10": q(0.1), "median": q(0.5), "p90": q(0.9)}
+
+
 def copy_bandwidth(torch):
     """Achievable HBM bandwidth of a plain device copy (1 GiB read + 1 GiB write)."""
     n = (1 << 30) // 8
@@ -165,6 +182,25 @@ def cpu_baseline(row_ptr, col_idx, a, x, min_seconds, solves=None, kept=None):
                     "solve of the first 64^3 system above (same size; the held-out systems vary sigma in "
                     "[1.5, 3.0], so their iteration counts differ)"}
     return out
+
+
+def oracle_variant_rate(K, row_ptr, col_idx, a_re, a_im, x_re, x_im, stride=8, seconds=0.5):
+    """CPU leg: the oracle's y = A x of one variant on every stride-th row of the matrix
+    (all threads), repeated for at least `seconds` (and twice); GNNZ/s of the fastest call
+    over the sampled rows' elements."""
+    from oracle import ref
+    rows = np.arange(0, row_ptr.size - 1, stride, dtype=np.int64)
+    sampled = int(np.sum(row_ptr[rows + 1] - row_ptr[rows]))
+    best, reps, t_all = None, 0, time.perf_counter()
+    while reps < 2 or time.perf_counter() - t_all < seconds:
+        t0 = time.perf_counter()
+        ref.spmv(K, row_ptr, col_idx, a_re, x_re, a_im=a_im, x_im=x_im, rows=rows)
+        el = time.perf_counter() - t0
+        best = el if best is None or el < best else best
+        reps += 1
+    return {"value": round(sampled / best / 1e9, 4), "unit": "GNNZ/s", "cores": ref.num_threads(),
+            "sample": "every %d-th row (%d rows, %d nnz), fastest of %d calls: %.4f s" % (
+                stride, rows.size, sampled, reps, best)}
 
 
 def dd_rel_diff(x, ref):
@@ -265,6 +301,15 @@ def solves_section(mp, torch, repeats=2, keep=None):
                              "fell_back": info["fell_back"], "relres_dd": info["relres"],
                              "rel_diff_vs_plain_dd_cg": dd_rel_diff(xh, xs["plain_dd_cg"]),
                              "exact_relres_upper": None, "rel_err_vs_oracle": None}
+            if name == "plain_dd_cg" and info["iters"] > 0:
+                # bytes per CG step: A once, plus 14 passes over DD vectors (16 n bytes each) made by
+                # the step's kernels: SpMV p in, q out; (p, q) sums p, q; update r, q, the Jacobi
+                # diagonal (8 n) in, r out; p step x, p, r, the diagonal in, x, p, staged p out
+                step_b = 4 * (n + 1) + 20 * ci.size + 14 * 16 * n
+                t_it = info["seconds"] / info["iters"]
+                rec_sys[name]["ms_per_iter"] = round(1e3 * t_it, 5)
+                rec_sys[name]["iter_GBs"] = round(step_b / t_it / 1e9, 1)
+                rec_sys[name]["iter_bytes"] = step_b
             log("%-10s %-14s %.4f s (%.2f solves/s) status %d iters %d outer %d fell_back %d relres %.3g" % (
                 sysrec["name"], name, info["seconds"], 1.0 / info["seconds"], info["status"], info["iters"],
                 info["outer_iters"], info["fell_back"], info["relres"]))
@@ -638,6 +683,7 @@ def main():
         raise SystemExit("the headline variant dd must be included")
 
     results = {}
+    cpu_variants = {}
     headline = None
     host_dd = None
     for K, cplx, name in wanted:
@@ -652,6 +698,9 @@ def main():
         y_im = torch.empty((K, n), dtype=torch.float64, device="cuda") if cplx else None
         if name == "dd":
             host_dd = (a_re, x_re)
+        if not args.no_cpu_baseline:
+            cpu_variants[name] = oracle_variant_rate(K, row_ptr, col_idx, a_re, a_im, x_re, x_im)
+            log("oracle %-10s %.4f GNNZ/s (%s)" % (name, cpu_variants[name]["value"], cpu_variants[name]["sample"]))
         del a_re, a_im, x_re, x_im
         if args.plan == "autotune":
             plan, pol = mp.mp_plan_autotune(A, K, ad_re, xd_re, y_re, ad_im, xd_im, y_im, reps=5)
@@ -673,7 +722,7 @@ def main():
         ms, wall = time_loop(step, args.steps, args.warmup, torch)
         rf = roofline(n, nnz, K, cplx, ms)
         results[name] = {"gnnz_s": round(nnz / (ms * 1e-3) / 1e9, 3), "ms": round(ms, 4),
-                         "plan": pol, "roofline": rf}
+                         "plan": pol, "roofline": rf, "per_call_ms": per_call_ms(step, 50, torch)}
         log("%-10s policy=%s %.4f ms  %.2f GNNZ/s  %s %.1f %s (%.1f%%)" % (
             name, pol, ms, nnz / (ms * 1e-3) / 1e9, rf["bound"], rf["achieved"], rf["unit"], 100 * rf["frac"]))
         if name == "dd":
@@ -764,6 +813,7 @@ def main():
         log("timing the CPU oracle ...")
         out["cpu_baseline"] = cpu_baseline(row_ptr, col_idx, host_dd[0], host_dd[1], args.cpu_seconds,
                                            solves=out.get("solves"), kept=kept)
+        out["cpu_baseline"]["variants"] = cpu_variants
     print(json.dumps(out), flush=True)
 
 
