@@ -383,6 +383,10 @@ def batched_section(mp, torch, args):
                          "unit": "GB/s", "frac": round(bytes_ / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
     log("batched SpMM: %.3f ms, %.1f GNNZ*RHS/s, %.0f GB/s, schedule %s" % (
         ms, nnz * R / (ms * 1e-3) / 1e9, bytes_ / (ms * 1e-3) / 1e9, sched))
+    workload = ("%d block-diagonal 3D diffusion systems, edges U{12..60} (seed 3), sigma 2.5, axis factors "
+                "(1, 1, %g), 8 random DD right-hand sides; N=%d nnz=%d" % (args.nsys, az, N, nnz))
+    if args.spmm_only:
+        return {"workload": workload, "schedule": sched, "spmm": spmm}
     del Y
     X = torch.zeros((2, N, R), dtype=torch.float64, device="cuda")
     infos = mp.mpkrylov_cg_batched(A, ad, Bd, X, R, plan, use_graph=True, precond="jacobi", rtol=1e-28,
@@ -414,8 +418,7 @@ def batched_section(mp, torch, args):
                      "bitwise_equal_to_batched": same})
     per_pair = sum(l["seconds"] for l in loop) / len(loop)
     pairs = len(infos)
-    out = {"workload": "%d block-diagonal 3D diffusion systems, edges U{12..60} (seed 3), sigma 2.5, axis factors "
-                       "(1, 1, %g), 8 random DD right-hand sides; N=%d nnz=%d" % (args.nsys, az, N, nnz),
+    out = {"workload": workload,
            "schedule": sched,
            "spmm": spmm,
            "cg": {"seconds": round(bsec, 3), "pairs": pairs, "converged": conv,
@@ -619,6 +622,8 @@ def main():
                          "the 64^3 DD-accurate solves, one run each, e.g. under a kernel trace)")
     ap.add_argument("--nsys", type=int, default=256)
     ap.add_argument("--loop-systems", type=int, default=8)
+    ap.add_argument("--spmm-only", action="store_true",
+                    help="with --workload batched: only the batched SpMM under the autotuned schedule (for counters)")
     ap.add_argument("--no-solves", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (counter calibration for the traffic figure)")
@@ -643,6 +648,15 @@ def main():
     from paper_2412_17510_amd import mp
     from paper_2412_17510_amd.profiling import find_record, source_hash
     from workloads import powerlaw_pattern, random_mp, mp_from_leads
+
+    if args.workload == "batched" and args.spmm_only:
+        res = batched_section(mp, torch, args)
+        print(json.dumps({"metric": "batched DD SpMM GNNZ*RHS/s (256 systems x 8 rhs)",
+                          "value": res["spmm"]["gnnz_rhs_per_s"], "unit": "GNNZ*RHS/s", "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["spmm"]["ms"],
+                          "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+                          "config": {"workload": res["workload"]}, "batched": res}), flush=True)
+        return
 
     if args.workload == "batched":
         res = batched_section(mp, torch, args)
