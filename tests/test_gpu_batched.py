@@ -2,7 +2,8 @@
 mpkrylov_cg_batched).
 
 * SpMM: every right-hand side equals the oracle's single-vector SpMV with W = 1 order,
-  bitwise, for every threads-per-row mapping (the autotuner's search space).
+  bitwise, for every threads-per-row mapping (the autotuner's search space), and at the
+  benchmark's full size (256 systems, 17.7 M rows, 8 right-hand sides) in every row.
 * Batched CG: every (system, rhs) pair equals a separate oracle DD CG solve with the
   same order (status, iterations, restarts, bitwise x and true residual); the hipGraph
   replay path equals the eager path bitwise; a pair equals the GPU's own single-system
@@ -58,6 +59,38 @@ def test_batched_spmm_matches_single_spmv(mp, R):
     Y = torch.empty((2, N, R), dtype=torch.float64, device="cuda")
     tpr = mp.mp_batch_plan_autotune(plan, A, dev(a), dev(X), Y)
     assert tpr in (1, 2, 4, 8) and tpr <= R
+
+
+def test_batched_spmm_full_size(mp):
+    """The benchmark's 256 systems (edges U{12..60}, 17.7 M rows, 122 M nnz) x 8
+    right-hand sides: every row of every right-hand side equal to the oracle's W = 1
+    SpMV, under the autotuned schedule and under one and eight threads per row."""
+    import torch
+    from workloads.condition import load_law
+    az = load_law()["systems"][0]["az"]
+    edges = np.random.default_rng(3).integers(12, 61, 256)
+    rp, ci, a, sp = batched_diffusion(edges, sigma=2.5, seed=3, az=az)
+    N, R = rp.size - 1, 8
+    print("batched full size: N=%d nnz=%d" % (N, ci.size), flush=True)
+    X = multi(np.random.default_rng(4), N, R)
+    A = mp.Csr.from_numpy(rp, ci)
+    ad, Xd = dev(a), dev(X)
+    Y = torch.empty((2, N, R), dtype=torch.float64, device="cuda")
+    plan = mp.mp_batch_plan_create(A, sp, R, 1)
+    tuned = mp.mp_batch_plan_autotune(plan, A, ad, Xd, Y)
+    got = {}
+    for tpr in sorted({tuned, 1, 8}):
+        pl = mp.mp_batch_plan_create(A, sp, R, tpr)
+        Y.fill_(float("nan"))
+        mp.mpspmm_csr_dd_batched(A, ad, Xd, Y, R, plan=pl)
+        torch.cuda.synchronize()
+        got[tpr] = host(Y)
+    del Y, Xd, ad
+    zero = np.zeros(N, np.uint8)
+    for r in range(R):
+        want = ref.spmv(2, rp, ci, a, np.ascontiguousarray(X[:, :, r]), log2w=zero)
+        for tpr, Yh in got.items():
+            assert_same_values(Yh[:, :, r], want, "full-size spmm tpr=%d rhs %d" % (tpr, r))
 
 
 @pytest.mark.parametrize("precond", ["jacobi", "none"])
