@@ -32,6 +32,25 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 FP64_INSTR_PEAK = 256 * 64 * 2.4e9      # 39.3e12 FP64 VALU instructions / s
+
+# The paper's CPU figures (context, not a target): it reports no absolute rates, only the
+# speedup of its 32-thread AVX2 SpMV over one thread on an AMD EPYC 9354P (32 cores), as the
+# share of SuiteSparse matrices with a speedup above 1 and the mean speedup, per size band
+# and mode (P: matrix in the K-component format; M: binary64 matrix).  Tables I (real) and
+# IV (complex); the 1001-5000 P row repeats the 101-1000 P means as printed.
+PAPER_CPU = {
+    "cpu": "AMD EPYC 9354P, 3.7 GHz, 32 cores (the paper's test machine)",
+    "kind": "speedup of 32 threads with AVX2 over 1 thread: [share of matrices above 1, mean]",
+    "real": {
+        "n101-1000": {"P": {"dd": [0.511, 29.09], "td": [0.626, 5.23], "qd": [0.644, 5.44]},
+                      "M": {"dd": [0.525, 28.06], "td": [0.566, 4.87], "qd": [0.648, 5.44]}},
+        "n1001-5000": {"P": {"dd": [0.612, 29.09], "td": [1.0, 5.23], "qd": [1.0, 5.44]},
+                       "M": {"dd": [0.984, 6.62], "td": [0.997, 7.63], "qd": [1.0, 11.37]}},
+        "n5001-10000": {"P": {"dd": [1.0, 16.89], "td": [1.0, 9.44], "qd": [1.0, 11.31]},
+                        "M": {"dd": [1.0, 7.45], "td": [1.0, 10.84], "qd": [1.0, 14.32]}}},
+    "complex": {"P": {"dd": [1.0, 7.88], "td": [1.0, 8.30], "qd": [1.0, 10.99]},
+                "M": {"dd": [0.941, 3.64], "td": [1.0, 9.74], "qd": [1.0, 14.15]}},
+}
 # FP64 instructions per nnz of the element operations (one mul + one add per nnz; the
 # counts follow the operation sequences of the library's arithmetic header)
 OPS_MUL = {2: 9, 3: 118, 4: 118}
@@ -828,6 +847,14 @@ def main():
         out["cpu_baseline"] = cpu_baseline(row_ptr, col_idx, host_dd[0], host_dd[1], args.cpu_seconds,
                                            solves=out.get("solves"), kept=kept)
         out["cpu_baseline"]["variants"] = cpu_variants
+        cb = out["cpu_baseline"]
+        out["paper_cpu"] = dict(PAPER_CPU, this_run={
+            "oracle_threads_over_one_thread_dd": round(cb["value"] / cb["one_thread"]["value"], 2),
+            "oracle_threads": cb["cores"],
+            "gpu_over_oracle_threads_dd": round(out["value"] / cb["value"], 1),
+            "gpu_over_oracle_one_thread_dd": round(out["value"] / cb["one_thread"]["value"], 1),
+            "note": "the same kind of ratio on this run's host (the plain scalar oracle, not an AVX2 code) and "
+                    "the GPU's DD rate over it; the paper's matrices have n <= 10000, this workload n = 1e6"})
     print(json.dumps(out), flush=True)
 
 
