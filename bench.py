@@ -375,16 +375,15 @@ def batched_section(mp, torch, args):
     under the autotuned schedule, and single-system solves of a size-stratified subset
     (one system per size stratum) extrapolated to every pair; the oracle's solves of
     the same subset give the CPU figure."""
-    from workloads import batched_diffusion, random_mp
+    from workloads import configs
     az = solver_systems()[0]["az"]
     t0 = time.perf_counter()
-    rng = np.random.default_rng(3)
-    edges = rng.integers(12, 61, args.nsys)
-    rp, ci, a, sp = batched_diffusion(edges, sigma=2.5, seed=3, az=az)
+    edges = configs.c3_edges(args.nsys)
+    rp, ci, a, sp = configs.c3_systems(az, args.nsys)
     N = rp.size - 1
     nnz = ci.size
-    R = 8
-    B = random_mp(N * R, 2, np.random.default_rng(4)).reshape(2, N, R)
+    R = configs.load("c3")["nrhs"]
+    B = configs.c3_rhs(N)
     log("batched: %d systems, N=%d nnz=%d, generated in %.1f s" % (args.nsys, N, nnz, time.perf_counter() - t0))
     A = mp.Csr.from_numpy(rp, ci)
     ad = torch.from_numpy(a).cuda()
@@ -584,7 +583,7 @@ def locality_section(mp, torch, args):
     and every column uniform over 64 n columns (x: 1 GiB, far beyond it).  The matrix
     streams are identical across the five; the algorithmic bytes are counted with n
     columns of x throughout."""
-    from workloads import powerlaw_pattern, random_mp, mp_from_leads
+    from workloads import configs, random_mp, mp_from_leads
     out = {}
     base = None
     for name, kw in (("workload 70% band / 30% uniform", {}), ("all within the band", {"p_band": 1.0}),
@@ -599,7 +598,7 @@ def locality_section(mp, torch, args):
             row_of = np.repeat(np.arange(n, dtype=np.int64), lens)
             ci = (start[row_of] + (np.arange(rp[-1], dtype=np.int64) - rp[:-1].astype(np.int64)[row_of])).astype(np.int32)
         else:
-            rp, ci = powerlaw_pattern(n=args.n, seed=1, **kw)
+            rp, ci = configs.c1_pattern(n=args.n, **kw)
             if base is None:
                 base = (rp, ci)
         n = rp.size - 1
@@ -630,7 +629,7 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--variants", default="all", help="comma list of dd,td,qd,dd_complex,... or all")
-    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--n", type=int, default=None, help="rows of the power-law matrix (default: the configured n)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=6.0)
     ap.add_argument("--plan", default="autotune",
@@ -639,7 +638,7 @@ def main():
                     help="spmv (default: power-law SpMV line plus the 64^3 solves), batched (256 systems x 8 rhs), "
                          "locality (the DD SpMV on three column laws with the same row lengths) or solves (only "
                          "the 64^3 DD-accurate solves, one run each, e.g. under a kernel trace)")
-    ap.add_argument("--nsys", type=int, default=256)
+    ap.add_argument("--nsys", type=int, default=None, help="batched systems (default: the configured count)")
     ap.add_argument("--loop-systems", type=int, default=8)
     ap.add_argument("--spmm-only", action="store_true",
                     help="with --workload batched: only the batched SpMM under the autotuned schedule (for counters)")
@@ -647,6 +646,11 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (counter calibration for the traffic figure)")
     args = ap.parse_args()
+    from workloads import configs
+    if args.n is None:
+        args.n = configs.load("c1")["n"]
+    if args.nsys is None:
+        args.nsys = configs.load("c3")["systems"]
     if args.gpus != 1:
         print("bench.py runs on one GPU only (multi-GPU sharding is a design note, not a measured path); "
               "run with --gpus 1", file=sys.stderr)
@@ -666,7 +670,7 @@ def main():
 
     from paper_2412_17510_amd import mp
     from paper_2412_17510_amd.profiling import find_record, source_hash
-    from workloads import powerlaw_pattern, random_mp, mp_from_leads
+    from workloads import configs
 
     if args.workload == "batched" and args.spmm_only:
         res = batched_section(mp, torch, args)
@@ -706,7 +710,7 @@ def main():
         return
 
     t0 = time.perf_counter()
-    row_ptr, col_idx = powerlaw_pattern(n=args.n, seed=1)
+    row_ptr, col_idx = configs.c1_pattern(n=args.n)
     n = row_ptr.size - 1
     nnz = col_idx.size
     log("pattern n=%d nnz=%d in %.1f s" % (n, nnz, time.perf_counter() - t0))
@@ -720,11 +724,7 @@ def main():
     headline = None
     host_dd = None
     for K, cplx, name in wanted:
-        rng = np.random.default_rng([1, K, int(cplx)])
-        a_re = mp_from_leads(rng.uniform(-1, 1, nnz), K, rng)
-        a_im = mp_from_leads(rng.uniform(-1, 1, nnz), K, rng) if cplx else None
-        x_re = random_mp(n, K, rng)
-        x_im = random_mp(n, K, rng) if cplx else None
+        a_re, a_im, x_re, x_im = configs.c1_operands(K, cplx, nnz, n)
         d = lambda v: None if v is None else torch.from_numpy(v).cuda()  # noqa: E731
         ad_re, ad_im, xd_re, xd_im = d(a_re), d(a_im), d(x_re), d(x_im)
         y_re = torch.empty((K, n), dtype=torch.float64, device="cuda")

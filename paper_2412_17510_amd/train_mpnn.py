@@ -208,11 +208,14 @@ def summarize(rows):
 
 
 def main():
+    _workloads()
+    from workloads import configs
+    c4 = configs.load("c4")
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--matrices", type=int, default=2000)
+    ap.add_argument("--matrices", type=int, default=c4["train_matrices"])
     ap.add_argument("--steps-per-matrix", type=int, default=2)
     ap.add_argument("--epochs", type=int, default=1)
-    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--seed", type=int, default=c4["train_seed"])
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--out", default=DEFAULT_CKPT)
     ap.add_argument("--eval", type=int, default=0, help="held-out 64^3 systems to evaluate after training")
@@ -227,8 +230,9 @@ def main():
         theta = learned.load(args.ckpt)
     else:
         t0 = time.perf_counter()
-        theta, hist, curve = train(args.matrices, args.steps_per_matrix, seed=args.seed, lr=args.lr,
-                                   epochs=args.epochs)
+        theta, hist, curve = train(args.matrices, args.steps_per_matrix, edge_lo=c4["train_edge_lo"],
+                                   edge_hi=c4["train_edge_hi"], sigma_lo=c4["train_sigma_lo"],
+                                   sigma_hi=c4["train_sigma_hi"], seed=args.seed, lr=args.lr, epochs=args.epochs)
         secs = time.perf_counter() - t0
         os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
         first = float(np.mean([h[3] for h in hist[:50]]))
@@ -240,7 +244,8 @@ def main():
              "per epoch %s" % (args.out, args.matrices, args.epochs, secs, first, last,
                                " ".join("%.4f" % c for c in curve)))
     if args.eval > 0:
-        res = evaluate(theta, n_systems=args.eval)
+        res = evaluate(theta, n_systems=args.eval, m=c4["eval_m"], sigma_lo=c4["eval_sigma_lo"],
+                       sigma_hi=c4["eval_sigma_hi"], seed=c4["eval_seed"])
         _log(json.dumps(res["summary"]))
         if args.eval_out:
             with open(args.eval_out, "w") as f:

@@ -66,13 +66,13 @@ def test_batched_spmm_full_size(mp):
     right-hand sides: every row of every right-hand side equal to the oracle's W = 1
     SpMV, under the autotuned schedule and under one and eight threads per row."""
     import torch
+    from workloads import configs
     from workloads.condition import load_law
     az = load_law()["systems"][0]["az"]
-    edges = np.random.default_rng(3).integers(12, 61, 256)
-    rp, ci, a, sp = batched_diffusion(edges, sigma=2.5, seed=3, az=az)
-    N, R = rp.size - 1, 8
+    rp, ci, a, sp = configs.c3_systems(az)
+    N, R = rp.size - 1, configs.load("c3")["nrhs"]
     print("batched full size: N=%d nnz=%d" % (N, ci.size), flush=True)
-    X = multi(np.random.default_rng(4), N, R)
+    X = configs.c3_rhs(N)
     A = mp.Csr.from_numpy(rp, ci)
     ad, Xd = dev(a), dev(X)
     Y = torch.empty((2, N, R), dtype=torch.float64, device="cuda")

@@ -10,7 +10,8 @@ import pytest
 
 from oracle import ref
 from tests.helpers import assert_same_values, dev, host
-from workloads import (random_csr, random_mp, sqrt2_vector, csr_from_dense, paper_example_5x5, powerlaw_pattern)
+from workloads import configs
+from workloads import (random_csr, random_mp, sqrt2_vector, csr_from_dense, paper_example_5x5)
 
 pytestmark = pytest.mark.gpu
 
@@ -87,7 +88,7 @@ def test_paper_5x5(mp, K):
 def test_powerlaw_full_size(mp, K):
     """Every one of the 1e6 rows, under an autotuned-style plan and the plan-free kernel."""
     import torch
-    row_ptr, col_idx = powerlaw_pattern(n=1_000_000, seed=1)
+    row_ptr, col_idx = configs.c1_pattern()
     n = row_ptr.size - 1
     rng = np.random.default_rng([7, K])
     a = rng.uniform(-1, 1, col_idx.size)
@@ -178,7 +179,7 @@ def test_complex_ragged_random_every_width(mp, K):
 def test_complex_powerlaw_full_size(mp, K):
     """Every one of the 1e6 rows of the binary64 complex matrix product."""
     import torch
-    row_ptr, col_idx = powerlaw_pattern(n=1_000_000, seed=1)
+    row_ptr, col_idx = configs.c1_pattern()
     n = row_ptr.size - 1
     rng = np.random.default_rng([8, K])
     a_re = rng.uniform(-1, 1, col_idx.size)

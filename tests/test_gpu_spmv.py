@@ -14,8 +14,9 @@ import pytest
 
 from oracle import ref
 from tests.helpers import assert_same_values, dev, host
+from workloads import configs
 from workloads import (laplace2d_5pt, random_csr, random_mp, sqrt2_vector, csr_from_dense,
-                       paper_example_5x5, powerlaw_pattern, mp_from_leads)
+                       paper_example_5x5, mp_from_leads)
 
 pytestmark = pytest.mark.gpu
 
@@ -246,7 +247,7 @@ def test_determinism_and_errors(mp):
 
 @pytest.fixture(scope="module")
 def powerlaw():
-    row_ptr, col_idx = powerlaw_pattern(n=1_000_000, seed=1)
+    row_ptr, col_idx = configs.c1_pattern()
     return row_ptr, col_idx
 
 

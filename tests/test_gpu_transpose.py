@@ -16,7 +16,8 @@ import pytest
 
 from oracle import ref
 from tests.helpers import assert_same_values, dev, host
-from workloads import random_csr, random_mp, sqrt2_vector, csr_from_dense, paper_example_5x5, powerlaw_pattern
+from workloads import configs
+from workloads import random_csr, random_mp, sqrt2_vector, csr_from_dense, paper_example_5x5
 
 pytestmark = pytest.mark.gpu
 
@@ -58,7 +59,7 @@ def test_transpose_empty_and_powerlaw(mp):
                n_cols=6)
     At, at, _ = mp.mp_csr_transpose(A, torch.zeros(0, dtype=torch.float64, device="cuda"))
     assert np.array_equal(host(At.row_ptr), np.zeros(7, np.int32))
-    row_ptr, col_idx = powerlaw_pattern(n=1_000_000, seed=1)
+    row_ptr, col_idx = configs.c1_pattern()
     a = np.random.default_rng(3).uniform(-1, 1, col_idx.size)
     same_transpose(mp, row_ptr, col_idx, a, row_ptr.size - 1, what="power-law")
 
