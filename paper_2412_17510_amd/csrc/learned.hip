@@ -497,15 +497,24 @@ __global__ __launch_bounds__(256) void k_readout_bwd(int32_t n, const int32_t *_
 }
 
 // per block of 256 nodes: partial dW[k][o] = sum_i bf(X_ik) dZ_io (dZ = dH o [Hout > 0]),
-// and (row K of the partial) db[o] = sum_i dZ_io.  Thread (q, o) = (tid / 64, tid % 64)
-// holds the sums of k = q, q + 4, ...; every sum runs over the block's nodes in order.
+// and (row K of the partial) db[o] = sum_i dZ_io.  Every sum runs over the block's nodes in
+// order.  The nodes pass through LDS 64 at a time (their X rows rounded to bfloat16 and
+// their dZ rows, each loaded once by coalesced reads); thread (q, o) = (tid / 64, tid % 64)
+// then holds the sums of k = q*NK .. q*NK + NK - 1, reading the X entries as wavefront-wide
+// broadcasts.
+constexpr int kGradChunk = 64;   // nodes staged in LDS at a time
+
 template <int K>
 __global__ __launch_bounds__(256) void k_wgrad_part(int32_t n, const float *__restrict__ X, const float *__restrict__ dH,
                                                     const float *__restrict__ Hout, float *__restrict__ part)
 {
-    constexpr int NK = (K + 3) / 4;
-    const int o = threadIdx.x & 63;
-    const int q = threadIdx.x >> 6;
+    static_assert(K % 4 == 0, "four thread groups of K / 4 rows each");
+    constexpr int NK = K / 4;
+    __shared__ float sX[kGradChunk * K];
+    __shared__ float sZ[kGradChunk * kH];
+    const int t = threadIdx.x;
+    const int o = t & 63;
+    const int q = t >> 6;
     const int64_t i0 = (int64_t)blockIdx.x * kNodeBlock;
     const int64_t i1 = (i0 + kNodeBlock) < n ? i0 + kNodeBlock : n;
     float *out = part + (int64_t)blockIdx.x * (K + 1) * kH;
@@ -513,21 +522,57 @@ __global__ __launch_bounds__(256) void k_wgrad_part(int32_t n, const float *__re
 #pragma unroll
     for (int m = 0; m < NK; ++m) acc[m] = 0.f;
     float db = 0.f;
-    for (int64_t i = i0; i < i1; ++i) {
-        const float dz = Hout[i * kH + o] > 0.f ? dH[i * kH + o] : 0.f;
-        db += dz;
+    for (int64_t c0 = i0; c0 < i1; c0 += kGradChunk) {
+        const int cn = (int)((i1 - c0) < kGradChunk ? (i1 - c0) : kGradChunk);
+        if (cn == kGradChunk) {
 #pragma unroll
-        for (int m = 0; m < NK; ++m) {
-            const int k = q + 4 * m;
-            if (k < K) acc[m] = fmaf(bfr(X[i * K + k]), dz, acc[m]);
+            for (int v = 0; v < (kGradChunk * K + 255) / 256; ++v) {
+                const int u = t + 256 * v;
+                if (u < kGradChunk * K) sX[u] = bfr(X[c0 * K + u]);
+            }
+#pragma unroll
+            for (int v = 0; v < kGradChunk * kH / 256; ++v) {
+                const int u = t + 256 * v;
+                const int64_t gi = c0 * kH + u;
+                const float h = Hout[gi], d = dH[gi];
+                sZ[u] = h > 0.f ? d : 0.f;
+            }
+        } else {
+            for (int u = t; u < cn * K; u += 256) sX[u] = bfr(X[c0 * K + u]);
+            for (int u = t; u < cn * kH; u += 256) {
+                const int64_t gi = c0 * kH + u;
+                sZ[u] = Hout[gi] > 0.f ? dH[gi] : 0.f;
+            }
         }
+        __syncthreads();
+        for (int r = 0; r < cn; ++r) {
+            const float dz = sZ[r * kH + o];
+            db += dz;
+            const float *xr = sX + r * K + q * NK;
+#pragma unroll
+            for (int m = 0; m < NK; ++m) acc[m] = fmaf(xr[m], dz, acc[m]);
+        }
+        __syncthreads();
     }
     if (q == 0) out[K * kH + o] = db;
 #pragma unroll
-    for (int m = 0; m < NK; ++m) {
-        const int k = q + 4 * m;
-        if (k < K) out[k * kH + o] = acc[m];
+    for (int m = 0; m < NK; ++m) out[(q * NK + m) * kH + o] = acc[m];
+}
+
+// sum of nb partials in block order, the loads issued eight at a time
+__device__ __forceinline__ float sum_parts(const float *__restrict__ part, int nb, int64_t stride, int64_t g)
+{
+    float acc = 0.f;
+    int b = 0;
+    for (; b + 8 <= nb; b += 8) {
+        float v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = part[(int64_t)(b + j) * stride + g];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc += v[j];
     }
+    for (; b < nb; ++b) acc += part[(int64_t)b * stride + g];
+    return acc;
 }
 
 // grad[off_w + k*64 + o] += sum_blocks part[b][k][o] (block order); grad[off_b + o] likewise
@@ -537,14 +582,14 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(int nb, const float *__res
 {
     const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (g >= (int64_t)(K + 1) * kH) return;
-    float acc = 0.f;
-    for (int b = 0; b < nb; ++b) acc += part[(int64_t)b * (K + 1) * kH + g];
+    const float acc = sum_parts(part, nb, (int64_t)(K + 1) * kH, g);
     if (g < (int64_t)K * kH) grad[off_w + g] += acc;
     else if (off_b >= 0) grad[off_b + (g - K * kH)] += acc;
 }
 
 // readout parameter gradients: per node block, dwu[f] = sum du_i bf(h_if), dbu = sum du_i;
-// per edge block, dqv[f] = sum dv_k bf(h_if) bf(h_jf), dbv = sum dv_k
+// per edge block, dqv[f] = sum dv_k bf(h_if) bf(h_jf), dbv = sum dv_k.  Each sum in node
+// (edge) order; the operands of eight nodes (edges) are loaded ahead of their arithmetic.
 __global__ __launch_bounds__(64) void k_readout_grad_part(int32_t n, int64_t nnz, const int32_t *__restrict__ rows,
                                                           const int32_t *__restrict__ ci, const float *__restrict__ H,
                                                           const float *__restrict__ du, const float *__restrict__ dv,
@@ -556,7 +601,21 @@ __global__ __launch_bounds__(64) void k_readout_grad_part(int32_t n, int64_t nnz
         const int64_t i0 = (int64_t)blockIdx.x * kNodeBlock;
         const int64_t i1 = (i0 + kNodeBlock) < n ? i0 + kNodeBlock : n;
         float a = 0.f, b = 0.f;
-        for (int64_t i = i0; i < i1; ++i) {
+        int64_t i = i0;
+        for (; i + 8 <= i1; i += 8) {
+            float d[8], h[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                d[j] = du[i + j];
+                h[j] = H[(i + j) * kH + f];
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                a = fmaf(d[j], bfr(h[j]), a);
+                b += d[j];
+            }
+        }
+        for (; i < i1; ++i) {
             a = fmaf(du[i], bfr(H[i * kH + f]), a);
             b += du[i];
         }
@@ -568,7 +627,29 @@ __global__ __launch_bounds__(64) void k_readout_grad_part(int32_t n, int64_t nnz
         const int64_t e0 = (int64_t)(blockIdx.x - nblk) * kEdgeBlock;
         const int64_t e1 = (e0 + kEdgeBlock) < nnz ? e0 + kEdgeBlock : nnz;
         float a = 0.f, b = 0.f;
-        for (int64_t e = e0; e < e1; ++e) {
+        int64_t e = e0;
+        for (; e + 8 <= e1; e += 8) {
+            int32_t ri[8], cj[8];
+            float d[8], hi[8], hj[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                ri[j] = rows[e + j];
+                cj[j] = ci[e + j];
+                d[j] = dv[e + j];
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                hi[j] = H[(int64_t)ri[j] * kH + f];
+                hj[j] = H[(int64_t)cj[j] * kH + f];
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (ri[j] == cj[j]) continue;
+                a = fmaf(d[j], bfr(hi[j]) * bfr(hj[j]), a);
+                b += d[j];
+            }
+        }
+        for (; e < e1; ++e) {
             const int64_t i = rows[e], j = ci[e];
             if (i == j) continue;
             a = fmaf(dv[e], bfr(H[i * kH + f]) * bfr(H[j * kH + f]), a);
@@ -586,8 +667,7 @@ __global__ __launch_bounds__(256) void k_readout_grad_reduce(int nparts, const f
 {
     const int g = threadIdx.x;
     if (g >= 2 * (kH + 1)) return;
-    float acc = 0.f;
-    for (int b = 0; b < nparts; ++b) acc += part[(int64_t)b * 2 * (kH + 1) + g];
+    const float acc = sum_parts(part, nparts, 2 * (kH + 1), g);
     // layout of a part: [wu(64), bu, qv(64), bv]
     if (g < kH) grad[OFF_WU + g] += acc;
     else if (g == kH) grad[OFF_BU] += acc;

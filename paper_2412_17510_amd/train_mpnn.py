@@ -87,7 +87,9 @@ def train(n_matrices=2000, steps_per_matrix=2, edge_lo=24, edge_hi=48, sigma_lo=
                 A = mp.Csr.from_numpy(rp, ci)
                 ad = torch.from_numpy(a).cuda()
                 xt = torch.from_numpy(xt_h).cuda()
-                R, E = learned.cg_pairs(A, ad, xt)
+                # the pairs' DD CG runs under a tile plan (rows summed sequentially) rather than
+                # the plan-free one-row-per-wavefront kernel
+                R, E = learned.cg_pairs(A, ad, xt, plan=mp.mp_plan_create(A, 2, False, 2, 6, 512))
                 g = mp.Graph(A, ad)
                 for s in range(steps_per_matrix):
                     frac = step / max(1, total_steps - 1)
