@@ -7,8 +7,9 @@ sources with the host half of every translation unit instrumented and links them
 kinds, SpMV variants, argument and workspace checks, transpose, COO -> CSR, the DD and
 K-component solvers, refinement, the batched layer, the network, the allocation-free
 SpMV) and checks status codes and exact identities.  The run must end with "ok" and no
-sanitizer report.  The HSA runtime's own allocations that live until exit are
-suppressed for the leak check (every frame of those stacks is in that library).
+sanitizer report.  Allocations made inside the HIP and HSA runtimes that live until exit
+are suppressed for the leak check (stacks through libamdhip64 or libhsa-runtime64); the
+library's own host allocations are checked.
 """
 import os
 import subprocess
@@ -25,7 +26,7 @@ def test_host_code_under_sanitizers(tmp_path):
     if not os.path.exists(EXE):
         pytest.skip("sanitizer driver not built (python tests/host_asan_build.py)")
     supp = tmp_path / "lsan.supp"
-    supp.write_text("leak:libhsa-runtime64.so\n")
+    supp.write_text("leak:libhsa-runtime64.so\nleak:libamdhip64.so\n")
     env = dict(os.environ)
     env["ASAN_OPTIONS"] = "detect_leaks=1"
     env["LSAN_OPTIONS"] = "suppressions=%s" % supp
