@@ -642,7 +642,10 @@ def main():
     ap.add_argument("--loop-systems", type=int, default=8)
     ap.add_argument("--spmm-only", action="store_true",
                     help="with --workload batched: only the batched SpMM under the autotuned schedule (for counters)")
-    ap.add_argument("--no-solves", action="store_true")
+    ap.add_argument("--no-solves", action="store_true",
+                    help="leave out every solver section (64^3 solves, band solves, TD/QD CG, batched systems)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="leave out the batched systems (SpMM, batched CG, per-system loop) of the default run")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (counter calibration for the traffic figure)")
     args = ap.parse_args()
@@ -842,6 +845,13 @@ def main():
         out["solves"] = solves_section(mp, torch, keep=kept)
         out["nonsymmetric_solves"] = nonsymmetric_section(mp, torch)
         out["precision_solves"] = precision_section(mp, torch)
+    if not args.no_solves and not args.no_batched:
+        torch.cuda.empty_cache()
+        saved = (args.steps, args.warmup)
+        args.steps, args.warmup = min(args.steps, 20), min(args.warmup, 3)
+        out["batched"] = batched_section(mp, torch, args)
+        args.steps, args.warmup = saved
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline and host_dd is not None:
         log("timing the CPU oracle ...")
         out["cpu_baseline"] = cpu_baseline(row_ptr, col_idx, host_dd[0], host_dd[1], args.cpu_seconds,
