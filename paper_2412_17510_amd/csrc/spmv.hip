@@ -25,7 +25,9 @@
 //   spmv_wide_kernel    rows longer than C with W = 512 or 1024: lanes strided over
 //                       the row in registers, folded in-thread, through LDS, then by
 //                       shuffles.
-//   spmv_rowwave_kernel no plan: one row per wavefront, canonical W chosen in-kernel.
+//   spmv_rowpack_kernel no plan: eight rows per wavefront, canonical W chosen in-kernel;
+//                       rows with W <= 8 on their own group of eight lanes, wider
+//                       rows afterwards with the whole wavefront.
 // Block indices are remapped so that consecutive tiles land on the same XCD.
 #include <hip/hip_runtime.h>
 
@@ -901,30 +903,81 @@ __global__ __launch_bounds__(256) void spmv_wide_kernel(SpmvArgs A)
 }
 
 // ---------------------------------------------------------------------------
-// no plan: one row per wavefront, canonical W = largest power of two <= min(len, 64)
+// no plan: canonical W = largest power of two <= min(len, 64)
 // ---------------------------------------------------------------------------
 
-template <int K, bool CPLX, bool DM>
-__global__ __launch_bounds__(256) void spmv_rowwave_kernel(SpmvArgs A)
+template <int K>
+__device__ __forceinline__ void acc_fold_xor_if(Acc<K, false> &a, int mask, bool apply)
 {
-    const int64_t wave = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
-    const int lane = threadIdx.x & 63;
-    if (wave >= A.n_rows) return;   // uniform per wavefront
-    const int32_t row = (int32_t)wave;
-    const int32_t beg = A.row_ptr[row], end = A.row_ptr[row + 1];
-    const int32_t len = end - beg;
+    const mpn<K> o = shfl_xor_mp(a.v, mask);
+    if (apply) a.v = mp_add(a.v, o);
+}
+template <int K>
+__device__ __forceinline__ void acc_fold_xor_if(Acc<K, true> &a, int mask, bool apply)
+{
+    const mpn<K> orr = shfl_xor_mp(a.rr, mask), oii = shfl_xor_mp(a.ii, mask);
+    const mpn<K> ori = shfl_xor_mp(a.ri, mask), oir = shfl_xor_mp(a.ir, mask);
+    if (apply) {
+        a.rr = mp_add(a.rr, orr);
+        a.ii = mp_add(a.ii, oii);
+        a.ri = mp_add(a.ri, ori);
+        a.ir = mp_add(a.ir, oir);
+    }
+}
+
+__device__ __forceinline__ int canonical_w(int32_t len)
+{
     int W = 1;
     while (W < 64 && 2 * W <= len) W *= 2;
+    return W;
+}
+
+// Eight consecutive rows per wavefront.  A row with W <= 8 runs on its own group of
+// eight lanes (lane l of the group: elements l, l+W, ...; folds by shuffles inside the
+// group, steps off < W only), so short rows fill the wavefront; the rows with W > 8 then
+// run one at a time on the whole wavefront.  The order of every row is the canonical one.
+template <int K, bool CPLX, bool DM>
+__global__ __launch_bounds__(256) void spmv_rowpack_kernel(SpmvArgs A)
+{
+    constexpr int kRows = 8;
+    const int64_t r0 = (((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6) * kRows;
+    const int lane = threadIdx.x & 63;
+    if (r0 >= A.n_rows) return;   // uniform per wavefront
+    const int64_t row = r0 + (lane >> 3);
+    const int l = lane & 7;
+    int32_t beg = 0, len = 0;
+    if (row < A.n_rows) {
+        beg = A.row_ptr[row];
+        len = A.row_ptr[row + 1] - beg;
+    }
+    const int W = canonical_w(len);
+    const bool packed = row < A.n_rows && W <= 8;
     Acc<K, CPLX> acc;
     acc_zero(acc);
-    if (lane < W && lane < len) {
-        first_product<K, DM>(A, beg + lane, acc);
-        for (int64_t k = (int64_t)beg + lane + W; k < end; k += W) add_product<K, DM>(A, k, acc);
+    if (packed && l < W && l < len) {
+        first_product<K, DM>(A, beg + l, acc);
+        for (int64_t k = (int64_t)beg + l + W; k < beg + len; k += W) add_product<K, DM>(A, k, acc);
     }
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1)
-        if (off < W) acc_fold_xor(acc, off);
-    if (lane == 0) acc_store(A, row, acc, len > 0);
+    for (int off = 4; off >= 1; off >>= 1) acc_fold_xor_if(acc, off, off < W);
+    if (packed && l == 0) acc_store(A, (int32_t)row, acc, len > 0);
+    // rows with W > 8: the whole wavefront, one row at a time
+    for (int j = 0; j < kRows && r0 + j < A.n_rows; ++j) {
+        const int32_t rj = (int32_t)(r0 + j);
+        const int32_t b = A.row_ptr[rj], e = A.row_ptr[rj + 1];
+        const int Wj = canonical_w(e - b);
+        if (Wj <= 8) continue;   // uniform per wavefront
+        Acc<K, CPLX> a;
+        acc_zero(a);
+        if (lane < Wj) {
+            first_product<K, DM>(A, b + lane, a);
+            for (int64_t k = (int64_t)b + lane + Wj; k < e; k += Wj) add_product<K, DM>(A, k, a);
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1)
+            if (off < Wj) acc_fold_xor(a, off);
+        if (lane == 0) acc_store(A, rj, a, true);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -976,9 +1029,8 @@ mp_status launch_spmv(const mp_csr *Acsr, const double *a_re, const double *a_im
     A.xs = nullptr;
     if (Acsr->n_rows == 0) return MP_OK;
     if (!plan) {
-        const int64_t blocks = ((int64_t)Acsr->n_rows + 3) / 4;
-        if (blocks > INT32_MAX) return fail(MP_ERR_INVALID_ARG, "too many rows for the plan-free kernel");
-        hipLaunchKernelGGL((spmv_rowwave_kernel<K, CPLX, DM>), dim3((unsigned)blocks), dim3(256), 0, s, A);
+        const int64_t blocks = ((int64_t)Acsr->n_rows + 31) / 32;   // 8 rows per wavefront, 4 per workgroup
+        hipLaunchKernelGGL((spmv_rowpack_kernel<K, CPLX, DM>), dim3((unsigned)blocks), dim3(256), 0, s, A);
         MP_HIP_TRY(hipGetLastError());
         return MP_OK;
     }
