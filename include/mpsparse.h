@@ -146,8 +146,9 @@ mp_status mpspmv_workspace_bytes(const mp_plan *plan, size_t *bytes);
 /*
  * Real SpMV y = A x (Sec. 3, Fig. 1) in DD (Algs 1-2), TD and QD (Sec. 2).
  *   a: K*nnz values, x: K*n_cols, y: K*n_rows (multi-component layout above).
- *   plan: NULL = canonical order with a one-row-per-wavefront kernel that needs no
- *   plan; otherwise the plan's order and tiles (the plan must have been made for
+ *   plan: NULL = canonical order with a kernel that needs no plan (eight rows per
+ *   wavefront: rows with W <= 8 on groups of eight lanes, wider rows on the whole
+ *   wavefront); otherwise the plan's order and tiles (the plan must have been made for
  *   this variant and for a pattern with the same n_rows and nnz).
  *   ws: device workspace of ws_bytes >= mpspmv_workspace_bytes(plan) bytes, 256-byte
  *   aligned (ignored when that is 0, e.g. plan NULL); overwritten by the call and in
