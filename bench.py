@@ -547,10 +547,11 @@ def nonsymmetric_section(mp, torch, repeats=3):
     return out
 
 
-def precision_section(mp, torch):
+def precision_section(mp, torch, keep=None):
     """CG on the 64^3 sigma = 2.5 system in TD and QD (Jacobi, x0 = 0) to relative
     residuals DD cannot reach (1e-44 and 1e-60), with K-component matrix and right-hand
-    side of the same law."""
+    side of the same law.  keep: dict that receives each solve's matrix, right-hand side
+    and x (host arrays) for the CPU leg's exact residual."""
     from workloads import diffusion3d_7pt, random_mp
     out = {}
     for K, fn, rtol in ((3, mp.mpkrylov_cg_td, 1e-44), (4, mp.mpkrylov_cg_qd, 1e-60)):
@@ -558,7 +559,8 @@ def precision_section(mp, torch):
         n = rp.size - 1
         A = mp.Csr.from_numpy(rp, ci)
         ad = torch.from_numpy(a).cuda()
-        bd = torch.from_numpy(random_mp(n, K, np.random.default_rng(2))).cuda()
+        b = random_mp(n, K, np.random.default_rng(2))
+        bd = torch.from_numpy(b).cuda()
         ytmp = torch.empty((K, n), dtype=torch.float64, device="cuda")
         plan, pol = mp.mp_plan_autotune(A, K, ad, bd, ytmp, reps=3)
         x = torch.zeros((K, n), dtype=torch.float64, device="cuda")
@@ -569,6 +571,8 @@ def precision_section(mp, torch):
                      "target_relres": rtol, "relres": info["relres"], "plan": pol}
         log("%-8s 64^3 to %.0e: %.4f s  status %d  iters %d  relres %.3g" % (
             name, rtol, info["seconds"], info["status"], info["iters"], info["relres"]))
+        if keep is not None:
+            keep[name] = (rp, ci, a, b, x.cpu().numpy())
         del A, ad, bd, x, ytmp, plan
         torch.cuda.empty_cache()
     return out
@@ -841,10 +845,11 @@ def main():
         "measured_ceilings": measured,
     }
     kept = {}
+    kept_prec = {}
     if not args.no_solves:
         out["solves"] = solves_section(mp, torch, keep=kept)
         out["nonsymmetric_solves"] = nonsymmetric_section(mp, torch)
-        out["precision_solves"] = precision_section(mp, torch)
+        out["precision_solves"] = precision_section(mp, torch, keep=kept_prec)
     if not args.no_solves and not args.no_batched:
         torch.cuda.empty_cache()
         saved = (args.steps, args.warmup)
@@ -857,6 +862,12 @@ def main():
         out["cpu_baseline"] = cpu_baseline(row_ptr, col_idx, host_dd[0], host_dd[1], args.cpu_seconds,
                                            solves=out.get("solves"), kept=kept)
         out["cpu_baseline"]["variants"] = cpu_variants
+        from oracle import ref
+        for name, (rp_, ci_, a_, b_, x_) in kept_prec.items():
+            # certified with the exact long accumulator: an upper bound on ||b - A x|| / ||b||
+            ex = ref.exact_residual(rp_, ci_, a_, b_, x_)
+            out["precision_solves"][name]["exact_relres_upper"] = ex["relres_upper"]
+            log("  %-8s certified relres <= %.3g" % (name, ex["relres_upper"]))
         cb = out["cpu_baseline"]
         out["paper_cpu"] = dict(PAPER_CPU, this_run={
             "oracle_threads_over_one_thread_dd": round(cb["value"] / cb["one_thread"]["value"], 2),
