@@ -88,7 +88,10 @@ def test_laplace2d_dd_all_plans(mp):
 def test_ragged_random_every_width(mp, K, cplx):
     rng = np.random.default_rng(1000 + 10 * K + cplx)
     # every length class: empty, short, around wavefront and tile sizes, long
-    lengths = np.concatenate([[0, 1, 2, 3, 5, 63, 64, 65, 127, 128, 255, 256, 511, 512, 1023, 1024, 2049, 0],
+    # (7, 8, 15, 16, 17: the plan-free kernel's boundary between rows on eight-lane groups and
+    # rows on the whole wavefront)
+    lengths = np.concatenate([[0, 1, 2, 3, 5, 7, 8, 15, 16, 17, 63, 64, 65, 127, 128, 255, 256, 511, 512, 1023, 1024,
+                               2049, 0],
                               rng.integers(0, 40, 700), rng.integers(40, 300, 60)])
     n_cols = 3000
     row_ptr, col_idx, a_re, a_im = random_csr(lengths.size, n_cols, lengths, K, rng, cplx)
