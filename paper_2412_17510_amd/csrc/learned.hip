@@ -92,6 +92,8 @@ struct mp_graph {
     double *d_vec = nullptr;             // 5 x n doubles of scratch for the loss
     double *d_dpart = nullptr;           // dot partials
     double *d_M = nullptr;               // assembled M values (nnz)
+    int32_t *d_bad = nullptr;            // set-up check result (1 value)
+    void *d_arena = nullptr;             // one device allocation holding every buffer above
     int32_t nblk = 0, eblk = 0;
 };
 
@@ -703,19 +705,51 @@ inline unsigned nb256(int64_t n)
 void graph_free(mp_graph *g)
 {
     if (!g) return;
-    void *ps[] = {g->d_rows, g->d_rev, g->d_w, g->d_f, g->d_minv, g->d_H[0], g->d_H[1], g->d_H[2], g->d_H[3],
-                  g->d_Mg[1], g->d_Mg[2], g->d_Mg[3], g->d_u, g->d_v, g->d_c, g->d_du, g->d_dv, g->d_dH, g->d_dH2,
-                  g->d_dMg, g->d_wpart, g->d_vec, g->d_dpart, g->d_M};
-    for (void *p : ps)
-        if (p) (void)hipFree(p);
+    if (g->d_arena) (void)hipFree(g->d_arena);
     delete g;
 }
 
-template <typename T>
-mp_status galloc(T **p, size_t count)
+// The graph's buffers, carved from one allocation (one hipMalloc / hipFree per graph
+// instead of one per buffer): a first pass with base == nullptr sizes the arena, a
+// second assigns each buffer its 256-byte aligned offset.
+struct Carver {
+    char *base;
+    size_t off;
+    template <typename T>
+    void take(T **p, size_t count)
+    {
+        off = (off + 255) & ~(size_t)255;
+        if (base) *p = reinterpret_cast<T *>(base + off);
+        off += sizeof(T) * (count > 0 ? count : 1);
+    }
+};
+
+void graph_layout(mp_graph *g, Carver &c)
 {
-    MP_HIP_TRY(hipMalloc(reinterpret_cast<void **>(p), sizeof(T) * (count > 0 ? count : 1)));
-    return MP_OK;
+    const size_t n = (size_t)g->n, nnz = (size_t)g->nnz;
+    const size_t nh = n * kH;
+    const size_t wpart = (size_t)(g->nblk > 0 ? g->nblk : 1) * (kH + 1) * kH;
+    const size_t rpart = (size_t)(g->nblk + g->eblk) * 2 * (kH + 1);
+    c.take(&g->d_rows, nnz);
+    c.take(&g->d_rev, nnz);
+    c.take(&g->d_w, nnz);
+    c.take(&g->d_f, n * kF);
+    c.take(&g->d_minv, n);
+    for (int l = 0; l < 4; ++l) c.take(&g->d_H[l], nh);
+    for (int l = 1; l < 4; ++l) c.take(&g->d_Mg[l], nh);
+    c.take(&g->d_u, n);
+    c.take(&g->d_v, nnz);
+    c.take(&g->d_c, nnz);
+    c.take(&g->d_du, n);
+    c.take(&g->d_dv, nnz);
+    c.take(&g->d_dH, nh);
+    c.take(&g->d_dH2, nh);
+    c.take(&g->d_dMg, nh);
+    c.take(&g->d_wpart, wpart > rpart ? wpart : rpart);
+    c.take(&g->d_vec, (size_t)5 * n);
+    c.take(&g->d_dpart, (size_t)2 * ((n + 4095) / 4096) + 2);
+    c.take(&g->d_M, nnz);
+    c.take(&g->d_bad, 1);
 }
 
 // forward pass of graph g: activations, readouts, c and M (in g->d_M)
@@ -850,32 +884,21 @@ mp_status mp_graph_create(const mp_csr *A, const double *a, void *stream, mp_gra
     g->a = a;
     g->nblk = (int32_t)((n + kNodeBlock - 1) / kNodeBlock);
     g->eblk = (int32_t)((nnz + kEdgeBlock - 1) / kEdgeBlock);
-    const size_t nh = (size_t)n * kH;
-    const size_t wpart = (size_t)(g->nblk > 0 ? g->nblk : 1) * (kH + 1) * kH;
-    const size_t rpart = (size_t)(g->nblk + g->eblk) * 2 * (kH + 1);
-    if (st == MP_OK) st = galloc(&g->d_rows, nnz);
-    if (st == MP_OK) st = galloc(&g->d_rev, nnz);
-    if (st == MP_OK) st = galloc(&g->d_w, nnz);
-    if (st == MP_OK) st = galloc(&g->d_f, (size_t)n * kF);
-    if (st == MP_OK) st = galloc(&g->d_minv, n);
-    for (int l = 0; l < 4 && st == MP_OK; ++l) st = galloc(&g->d_H[l], nh);
-    for (int l = 1; l < 4 && st == MP_OK; ++l) st = galloc(&g->d_Mg[l], nh);
-    if (st == MP_OK) st = galloc(&g->d_u, n);
-    if (st == MP_OK) st = galloc(&g->d_v, nnz);
-    if (st == MP_OK) st = galloc(&g->d_c, nnz);
-    if (st == MP_OK) st = galloc(&g->d_du, n);
-    if (st == MP_OK) st = galloc(&g->d_dv, nnz);
-    if (st == MP_OK) st = galloc(&g->d_dH, nh);
-    if (st == MP_OK) st = galloc(&g->d_dH2, nh);
-    if (st == MP_OK) st = galloc(&g->d_dMg, nh);
-    if (st == MP_OK) st = galloc(&g->d_wpart, wpart > rpart ? wpart : rpart);
-    if (st == MP_OK) st = galloc(&g->d_vec, (size_t)5 * n);
-    if (st == MP_OK) st = galloc(&g->d_dpart, (size_t)2 * ((n + 4095) / 4096) + 2);
-    if (st == MP_OK) st = galloc(&g->d_M, nnz);
-    int32_t *d_bad = nullptr;
+    Carver sizer{nullptr, 0};
+    graph_layout(g, sizer);
+    {
+        const hipError_t e = hipMalloc(&g->d_arena, sizer.off);
+        if (e != hipSuccess) {
+            g->d_arena = nullptr;
+            graph_free(g);
+            return hip_fail(e, "hipMalloc");
+        }
+    }
+    Carver carver{static_cast<char *>(g->d_arena), 0};
+    graph_layout(g, carver);
+    int32_t *d_bad = g->d_bad;
     int32_t h_bad = INT32_MAX;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (st == MP_OK) st = galloc(&d_bad, 1);
     if (st == MP_OK) {
         hipError_t e = hipMemcpyAsync(d_bad, &h_bad, sizeof(int32_t), hipMemcpyHostToDevice, s);
         if (e == hipSuccess && n > 0) {
@@ -893,7 +916,6 @@ mp_status mp_graph_create(const mp_csr *A, const double *a, void *stream, mp_gra
                       "row %d has no positive diagonal, a positive off-diagonal entry or an entry without its transpose",
                       h_bad);
     }
-    if (d_bad) (void)hipFree(d_bad);
     if (st != MP_OK) {
         graph_free(g);
         return st;
